@@ -1,0 +1,320 @@
+"""FP64 CPU oracle for the DART-Ray ray-march (test infrastructure).
+
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may import this package.  The product path never does: it runs on the GPU
+library alone.  The C source is ``dartray_oracle.c``; ``build()`` compiles it
+with gcc into ``liboracle.so`` next to it.
+
+Python-side helpers here only marshal arrays and chain passes in the order of
+the paper's algorithm (Sect. 2: step 1, direct light, scattering iterations).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dartray_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+STEP1, DIRECT, SCATTER = 0, 1, 2
+T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
+C_CROSS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (plain C, FP64, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("nroot", C.c_int32 * 3),
+        ("lo", C.c_double * 3),
+        ("root_size", C.c_double),
+        ("n_leaves", C.c_int64),
+        ("level", C.POINTER(C.c_int32)),
+        ("ijk", C.POINTER(C.c_int64)),
+        ("rho", C.POINTER(C.c_double)),
+        ("emis", C.POINTER(C.c_double)),
+        ("n_lambda", C.c_int32),
+        ("kappa", C.POINTER(C.c_double)),
+        ("albedo", C.POINTER(C.c_double)),
+        ("g", C.POINTER(C.c_double)),
+        ("nside_sca", C.POINTER(C.c_int32)),
+        ("n_fwhm", C.c_double),
+        ("k_max", C.c_int32),
+        ("c_light", C.c_double),
+    ]
+
+
+class PassOpts(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32),
+        ("adaptive", C.c_int32),
+        ("nside", C.c_int32),
+        ("nside_max", C.c_int32),
+        ("n_rays_min", C.c_double),
+        ("f_U", C.c_double),
+        ("r_pre", C.c_double),
+        ("frame", C.c_double * 9),
+        ("source_mask", C.POINTER(C.c_uint8)),
+        ("max_steps", C.c_int64),
+        ("n_threads", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build()
+        L = C.CDLL(path)
+        L.orc_healpix_vec.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_double)]
+        L.orc_hg.argtypes = [C.c_double, C.c_double]
+        L.orc_hg.restype = C.c_double
+        L.orc_hg_fwhm.argtypes = [C.c_double]
+        L.orc_hg_fwhm.restype = C.c_double
+        L.orc_k_hp_real.argtypes = [C.c_double, C.c_double]
+        L.orc_k_hp_real.restype = C.c_double
+        L.orc_k_hp.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.orc_k_hp.restype = C.c_int
+        L.orc_hg_weights.argtypes = [C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+        L.orc_model_create.argtypes = [C.POINTER(GridDesc), C.POINTER(C.c_void_p)]
+        L.orc_model_create.restype = C.c_int
+        L.orc_model_destroy.argtypes = [C.c_void_p]
+        L.orc_model_s_size.argtypes = [C.c_void_p]
+        L.orc_model_s_size.restype = C.c_int64
+        L.orc_model_nside_sca.argtypes = [C.c_void_p, C.c_int]
+        L.orc_model_nside_sca.restype = C.c_int32
+        L.orc_model_s_offset.argtypes = [C.c_void_p, C.c_int]
+        L.orc_model_s_offset.restype = C.c_int64
+        L.orc_locate.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_locate.restype = C.c_int64
+        L.orc_trace_cells.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                      C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
+        L.orc_trace_cells.restype = C.c_int64
+        L.orc_run_pass.argtypes = [C.c_void_p, C.POINTER(PassOpts), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.orc_run_pass.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _dvec(v):
+    return (C.c_double * 3)(*[float(x) for x in v])
+
+
+# ---------------------------------------------------------------------------
+# Geometry helpers
+# ---------------------------------------------------------------------------
+
+
+def healpix_vec(nside: int, pix: int) -> np.ndarray:
+    out = (C.c_double * 3)()
+    lib().orc_healpix_vec(nside, pix, out)
+    return np.array(out[:])
+
+
+def healpix_vecs(nside: int) -> np.ndarray:
+    return np.array([healpix_vec(nside, p) for p in range(12 * nside * nside)])
+
+
+def hg(g: float, mu: float) -> float:
+    return lib().orc_hg(g, mu)
+
+
+def hg_fwhm(g: float) -> float:
+    return lib().orc_hg_fwhm(g)
+
+
+def k_hp_real(g: float, n_fwhm: float = 5.0) -> float:
+    return lib().orc_k_hp_real(g, n_fwhm)
+
+
+def k_hp(g: float, n_fwhm: float = 5.0, k_max: int = 2) -> int:
+    return lib().orc_k_hp(g, n_fwhm, k_max)
+
+
+def hg_weights(nside_sca: int, g: float, n, frame=None) -> np.ndarray:
+    frame = np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)
+    w = np.zeros(12 * nside_sca * nside_sca)
+    fr = np.ascontiguousarray(frame, dtype=np.float64).ravel()
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    lib().orc_hg_weights(nside_sca, g, _p(nn, C.c_double), _p(fr, C.c_double), _p(w, C.c_double))
+    return w
+
+
+class Model:
+    """Oracle view of a workload grid (keeps the numpy arrays alive)."""
+
+    def __init__(self, grid):
+        self.grid = grid
+        self._keep = dict(
+            level=np.ascontiguousarray(grid.level, dtype=np.int32),
+            ijk=np.ascontiguousarray(grid.ijk, dtype=np.int64),
+            rho=np.ascontiguousarray(grid.rho, dtype=np.float64),
+            emis=np.ascontiguousarray(grid.emis, dtype=np.float64),
+            kappa=np.ascontiguousarray(grid.kappa, dtype=np.float64),
+            albedo=np.ascontiguousarray(grid.albedo, dtype=np.float64),
+            g=np.ascontiguousarray(grid.g, dtype=np.float64),
+            nside_sca=np.ascontiguousarray(grid.nside_sca, dtype=np.int32),
+        )
+        k = self._keep
+        d = GridDesc()
+        d.nroot = (C.c_int32 * 3)(*[int(x) for x in grid.nroot])
+        d.lo = (C.c_double * 3)(*[float(x) for x in grid.lo])
+        d.root_size = float(grid.root_size)
+        d.n_leaves = grid.n
+        d.level = _p(k["level"], C.c_int32)
+        d.ijk = _p(k["ijk"], C.c_int64)
+        d.rho = _p(k["rho"], C.c_double)
+        d.emis = _p(k["emis"], C.c_double)
+        d.n_lambda = grid.n_lambda
+        d.kappa = _p(k["kappa"], C.c_double)
+        d.albedo = _p(k["albedo"], C.c_double)
+        d.g = _p(k["g"], C.c_double)
+        d.nside_sca = _p(k["nside_sca"], C.c_int32)
+        d.n_fwhm = float(grid.n_fwhm)
+        d.k_max = int(grid.k_max)
+        d.c_light = float(grid.c_light)
+        self._desc = d
+        h = C.c_void_p()
+        rc = lib().orc_model_create(C.byref(d), C.byref(h))
+        if rc != 0:
+            raise ValueError(f"oracle rejected the grid (status {rc})")
+        self.h = h
+        self.n = grid.n
+        self.nl = grid.n_lambda
+        self.s_size = lib().orc_model_s_size(h)
+        self.nside_sca = [lib().orc_model_nside_sca(h, l) for l in range(self.nl)]
+        self.s_offset = [lib().orc_model_s_offset(h, l) for l in range(self.nl + 1)]
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.orc_model_destroy(self.h)
+            self.h = None
+
+    def npix(self, l):
+        return 12 * self.nside_sca[l] ** 2
+
+    def s_block(self, S, l):
+        """View of wavelength block l of an S array as [n, npix]."""
+        return S[self.s_offset[l]:self.s_offset[l + 1]].reshape(self.n, self.npix(l))
+
+    def locate(self, p, d):
+        return int(lib().orc_locate(self.h, _dvec(p), _dvec(d)))
+
+    def trace_cells(self, o, d, t0=0.0, max_cross=100000):
+        cells = np.zeros(max_cross, dtype=np.int64)
+        lens = np.zeros(max_cross)
+        tin = np.zeros(max_cross)
+        n = lib().orc_trace_cells(self.h, _dvec(o), _dvec(d), float(t0), max_cross,
+                                  _p(cells, C.c_int64), _p(lens, C.c_double), _p(tin, C.c_double))
+        return cells[:n], lens[:n], tin[:n]
+
+    def run_pass(self, mode, policy, S_pending=None, U_LL=None, frame=None, source_mask=None,
+                 max_steps=0, n_threads=0):
+        o = PassOpts()
+        o.mode = mode
+        o.adaptive = 1 if policy.adaptive else 0
+        o.nside = int(policy.nside)
+        o.nside_max = int(policy.nside_max)
+        o.n_rays_min = float(policy.n_rays_min)
+        o.f_U = float(policy.f_U)
+        o.r_pre = float(policy.r_pre)
+        fr = np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)
+        o.frame = (C.c_double * 9)(*fr.ravel().tolist())
+        mask = None
+        if source_mask is not None:
+            mask = np.ascontiguousarray(source_mask, dtype=np.uint8)
+            o.source_mask = _p(mask, C.c_uint8)
+        o.max_steps = int(max_steps)
+        o.n_threads = int(n_threads)
+        U_k = np.zeros(self.nl * self.n)
+        S_next = np.zeros(max(self.s_size, 1))
+        tally = np.zeros(self.nl * 8)
+        counters = np.zeros(8, dtype=np.int64)
+        Sp = None if S_pending is None else np.ascontiguousarray(S_pending, dtype=np.float64)
+        ULL = None if U_LL is None else np.ascontiguousarray(U_LL, dtype=np.float64).ravel()
+        rc = lib().orc_run_pass(self.h, C.byref(o),
+                                None if Sp is None else _p(Sp, C.c_double),
+                                None if ULL is None else _p(ULL, C.c_double),
+                                _p(U_k, C.c_double), _p(S_next, C.c_double), _p(tally, C.c_double),
+                                _p(counters, C.c_int64))
+        if rc != 0:
+            raise ValueError(f"oracle pass failed (status {rc})")
+        return PassResult(U_k.reshape(self.nl, self.n), S_next[:self.s_size], tally.reshape(self.nl, 8), counters)
+
+
+@dataclass
+class PassResult:
+    U: np.ndarray          # [nl, n]
+    S: np.ndarray          # [S size]
+    tally: np.ndarray      # [nl, 8]
+    counters: np.ndarray   # [8]
+
+
+@dataclass
+class RunResult:
+    U: np.ndarray          # total RFED [nl, n]
+    U_LL: Optional[np.ndarray]
+    S_total: np.ndarray    # all scattering orders, S_1 .. S_{K+1}
+    S_pending: np.ndarray  # last, unprocessed order
+    passes: list           # PassResult per pass (step 1 first when present)
+
+
+def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_init=None,
+        passes=None) -> RunResult:
+    """Step 1 (optional), the direct pass and the scattering iterations (Sect. 2).
+
+    U_LL is the step-1 result, then the running U after every pass (the
+    footnote of Sect. 2).  ``U_LL_init`` replaces step 1 by a given U_LL.
+    ``passes`` limits the number of passes after step 1 (direct counts as 1).
+    """
+    results = []
+    U_LL = None
+    if policy.adaptive:
+        if U_LL_init is not None:
+            U_LL = np.array(U_LL_init, dtype=np.float64).reshape(model.nl, model.n)
+        elif policy.step1:
+            r = model.run_pass(STEP1, policy, frame=frame, source_mask=source_mask, n_threads=n_threads)
+            results.append(r)
+            U_LL = r.U.copy()
+        else:
+            U_LL = np.zeros((model.nl, model.n))
+    n_pass = 1 + policy.n_scatter if passes is None else passes
+    U = np.zeros((model.nl, model.n))
+    S_total = np.zeros(model.s_size)
+    S_pending = None
+    for k in range(n_pass):
+        mode = DIRECT if k == 0 else SCATTER
+        r = model.run_pass(mode, policy, S_pending=S_pending, U_LL=U_LL, frame=frame,
+                           source_mask=source_mask if k == 0 else None, n_threads=n_threads)
+        results.append(r)
+        U += r.U
+        S_total += r.S
+        S_pending = r.S
+        if policy.adaptive:
+            U_LL = U.copy()
+    return RunResult(U=U, U_LL=U_LL, S_total=S_total, S_pending=S_pending, passes=results)

@@ -1,0 +1,710 @@
+/*
+ * FP64 reference ("oracle") for the ray-march of DART-Ray V2
+ * (Natale et al. 2017, "Ray-tracing 3D dust radiative transfer with DART-Ray:
+ * code upgrade and public release", arXiv:1709.03802).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or constant with the GPU library, and is deliberately plain:
+ * one ray at a time, one crossing at a time, every deposit written out, in
+ * double precision.
+ *
+ * What it computes (paper Sect. 2): for every radiation source (an emitting
+ * cell, or a dusty cell holding scattered luminosity) rays are cast along the
+ * HEALPix directions (Sect. 3.1.1, Gorski et al. 2005) from the cell centre.
+ * Each ray-cell crossing attenuates the ray, adds to the radiation-field
+ * energy density U of the crossed cell and adds the scattered part of the
+ * extinguished luminosity to that cell's angular scattered-luminosity array
+ * through the Henyey-Greenstein phase function (Eq. 4).  Rays may be split
+ * when the beam is too large (Eq. 2) and blocked when their contribution is
+ * negligible (Eq. 1, with the source-contribution estimate of Eq. 8); during
+ * step 1 the block test is replaced by the fixed extent R_pre (caption of the
+ * ray-density flowchart figure).  Multi-wavelength rays are blocked only when
+ * negligible at every wavelength and skip deposits at negligible wavelengths
+ * (Sect. 3.2).  Ray merging (Eq. 3) is not part of this oracle.
+ *
+ * Readings where the paper is silent (each one also listed in the design
+ * notes of the repository):
+ *  - rays start at the source-cell centre and the source cell is crossed from
+ *    the centre to its exit like any other cell;
+ *  - the per-ray luminosity is L_s / N_ray (direct) and, for scattered light,
+ *    the luminosity held in the j_sca pixel that contains the ray direction,
+ *    shared evenly among the rays inside that pixel;
+ *  - the energy-density deposit of one crossing is ext / (alpha V c), where
+ *    ext = L_in (1 - exp(-tau)), which equals the per-ray expression
+ *    <I> A_EM Omega_HP dL / (V c) of Sect. 3.5 with <I> the path-averaged
+ *    intensity;
+ *  - the scattered luminosity of a crossing is albedo * ext, spread over the
+ *    j_sca pixels with weights Phi(n_p . n) / sum_q Phi(n_q . n);
+ *  - the estimate of Eq. 8 becomes <L> / (Omega_HP d^2 c), with d the
+ *    distance from the source to the crossed cell centre and
+ *    Omega_INT = L_c^2 / d^2 (infinite in the source's own cell);
+ *  - a wavelength is significant when its path-averaged luminosity is > 0 and
+ *    that estimate is >= f_U * U_LL;
+ *  - a ray is split (4 children, each with a quarter of its luminosity,
+ *    starting at the entry distance of the triggering crossing) when the beam
+ *    is too large and the ray is significant at some wavelength, blocked when
+ *    the beam is too large and no wavelength is significant, and otherwise
+ *    deposits the significant wavelengths and carries on;
+ *  - traversal: the exit face is the axis with the smallest exit distance
+ *    (exact ties resolved x before y before z) and the next leaf is the face
+ *    neighbour across it that contains the exit point (points on a face
+ *    belong to the side the direction points to, the upper side when the
+ *    component is zero); a ray through an edge or corner therefore crosses
+ *    zero-length segments, which deposit nothing.
+ */
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_E_INVALID (-1)
+#define ORC_E_OOM (-2)
+
+enum { ORC_STEP1 = 0, ORC_DIRECT = 1, ORC_SCATTER = 2 };
+enum { T_EMITTED = 0, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED, N_TALLY = 8 };
+enum { C_CROSS = 0, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, N_COUNT = 8 };
+
+typedef struct {
+    int32_t nroot[3];
+    double lo[3];
+    double root_size;
+    int64_t n_leaves;
+    const int32_t *level;   /* [n] */
+    const int64_t *ijk;     /* [n][3] cell coordinates at the leaf's level */
+    const double *rho;      /* [n] */
+    const double *emis;     /* [n_lambda][n] */
+    int32_t n_lambda;
+    const double *kappa;    /* [n_lambda] */
+    const double *albedo;   /* [n_lambda] */
+    const double *g;        /* [n_lambda] */
+    const int32_t *nside_sca; /* [n_lambda], 0 selects Eq. 5 */
+    double n_fwhm;
+    int32_t k_max;
+    double c_light;
+} orc_grid_desc;
+
+typedef struct {
+    orc_grid_desc d;
+    int max_level;
+    int64_t fine[3];        /* finest-level cells along each axis */
+    double h_fine;
+    int32_t *fine_map;      /* finest-level cell -> leaf */
+    double *centre;         /* [n][3] */
+    double *side;           /* [n] */
+    int32_t *nside_sca;     /* [n_lambda] effective */
+    int64_t *s_offset;      /* [n_lambda + 1] start of each wavelength block of S */
+} orc_model;
+
+typedef struct {
+    int32_t mode;           /* ORC_STEP1, ORC_DIRECT, ORC_SCATTER */
+    int32_t adaptive;       /* 0: fixed Nside, 1: split/block rays */
+    int32_t nside;          /* fixed Nside, or the initial Nside */
+    int32_t nside_max;
+    double n_rays_min;      /* N_rays of Eq. 2 */
+    double f_U;             /* Eq. 1 */
+    double r_pre;           /* step-1 extent */
+    double frame[9];        /* rotation applied to every HEALPix direction */
+    const uint8_t *source_mask; /* [n] or NULL */
+    int64_t max_steps;      /* per ray; <= 0 means unlimited */
+    int32_t n_threads;
+} orc_pass_opts;
+
+/* ------------------------------------------------------------------------ */
+/* HEALPix, nested scheme (Gorski et al. 2005, Sect. 4-5 of that paper).      */
+/* ------------------------------------------------------------------------ */
+
+/* Base-pixel layout: ring index of the base pixel's southern-most corner
+ * row (in units of Nside) and its longitude offset, for faces 0..11. */
+static const int orc_face_ring[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+static const int orc_face_phi[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+
+static void orc_deinterleave(int64_t v, int64_t *x, int64_t *y)
+{
+    int64_t a = 0, b = 0;
+    for (int bit = 0; bit < 31; ++bit) {
+        a |= ((v >> (2 * bit)) & 1) << bit;
+        b |= ((v >> (2 * bit + 1)) & 1) << bit;
+    }
+    *x = a;
+    *y = b;
+}
+
+/* Unit vector of the centre of nested pixel `pix` at resolution `nside`. */
+void orc_healpix_vec(int64_t nside, int64_t pix, double v[3])
+{
+    int64_t npface = nside * nside;
+    int face = (int)(pix / npface);
+    int64_t ix, iy;
+    orc_deinterleave(pix % npface, &ix, &iy);
+    /* ring number counted from the north pole, 1 .. 4 nside - 1 */
+    int64_t ring = (int64_t)orc_face_ring[face] * nside - ix - iy - 1;
+    int64_t nr;           /* pixels in a quarter of this ring */
+    double z;
+    int shifted;          /* ring whose first pixel centre is offset by half a pixel less */
+    if (ring < nside) {                       /* north polar cap */
+        nr = ring;
+        z = 1.0 - (double)(nr * nr) / (3.0 * (double)npface);
+        shifted = 0;
+    } else if (ring > 3 * nside) {            /* south polar cap */
+        nr = 4 * nside - ring;
+        z = -(1.0 - (double)(nr * nr) / (3.0 * (double)npface));
+        shifted = 0;
+    } else {                                  /* equatorial belt */
+        nr = nside;
+        z = (double)(2 * nside - ring) * 2.0 / (3.0 * (double)nside);
+        shifted = (int)((ring - nside) & 1);
+    }
+    int64_t jp = ((int64_t)orc_face_phi[face] * nr + ix - iy + 1 + shifted) / 2;
+    if (jp > 4 * nr) jp -= 4 * nr;
+    if (jp < 1) jp += 4 * nr;
+    double phi = ((double)jp - 0.5 * (double)(1 + shifted)) * (M_PI / 2.0) / (double)nr;
+    double st = sqrt((1.0 - z) * (1.0 + z));
+    v[0] = st * cos(phi);
+    v[1] = st * sin(phi);
+    v[2] = z;
+}
+
+static void orc_rotate(const double R[9], const double a[3], double b[3])
+{
+    b[0] = R[0] * a[0] + R[1] * a[1] + R[2] * a[2];
+    b[1] = R[3] * a[0] + R[4] * a[1] + R[5] * a[2];
+    b[2] = R[6] * a[0] + R[7] * a[1] + R[8] * a[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Henyey-Greenstein phase function (Eq. 4) and the j_sca resolution rule     */
+/* (Eq. 5 with theta_min = FWHM[Phi - Phi(pi)] / n_FWHM).                    */
+/* ------------------------------------------------------------------------ */
+
+double orc_hg(double g, double cos_theta)
+{
+    double den = 1.0 + g * g - 2.0 * g * cos_theta;
+    return (1.0 - g * g) / (4.0 * M_PI * den * sqrt(den));
+}
+
+/* Full width at half maximum of Phi(theta) - Phi(pi), in radians.
+ * Zero when the profile has no forward peak (g <= 0). */
+double orc_hg_fwhm(double g)
+{
+    if (g <= 0.0) return 0.0;
+    double top = orc_hg(g, 1.0) - orc_hg(g, -1.0);
+    double a = 0.0, b = M_PI;   /* Phi is decreasing in theta for g > 0 */
+    for (int it = 0; it < 200; ++it) {
+        double m = 0.5 * (a + b);
+        double f = orc_hg(g, cos(m)) - orc_hg(g, -1.0) - 0.5 * top;
+        if (f > 0.0) a = m; else b = m;
+    }
+    return 2.0 * 0.5 * (a + b);
+}
+
+/* Real-valued k of Eq. 5 (before taking the integer part). */
+double orc_k_hp_real(double g, double n_fwhm)
+{
+    double fwhm = orc_hg_fwhm(g);
+    if (fwhm <= 0.0) return 0.0;
+    double tmin = fwhm / n_fwhm;
+    return 0.5 * log2(4.0 * M_PI / (12.0 * tmin * tmin));
+}
+
+/* Integer k of Eq. 5: integer part, clamped to [0, k_max]. */
+int orc_k_hp(double g, double n_fwhm, int k_max)
+{
+    double k = floor(orc_k_hp_real(g, n_fwhm));
+    if (k < 0.0) k = 0.0;
+    if (k > (double)k_max) k = (double)k_max;
+    return (int)k;
+}
+
+/* Weights w(p | n) = Phi(n_p . n) / sum_q Phi(n_q . n) over the j_sca pixels
+ * at `nside_sca`, with the pixel centres rotated by `frame`. */
+void orc_hg_weights(int nside_sca, double g, const double n[3], const double frame[9], double *w)
+{
+    int64_t npix = 12 * (int64_t)nside_sca * nside_sca;
+    double sum = 0.0;
+    for (int64_t p = 0; p < npix; ++p) {
+        double v0[3], v[3];
+        orc_healpix_vec(nside_sca, p, v0);
+        orc_rotate(frame, v0, v);
+        w[p] = orc_hg(g, v[0] * n[0] + v[1] * n[1] + v[2] * n[2]);
+        sum += w[p];
+    }
+    for (int64_t p = 0; p < npix; ++p) w[p] /= sum;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid model                                                                */
+/* ------------------------------------------------------------------------ */
+
+void orc_model_destroy(orc_model *m)
+{
+    if (!m) return;
+    free(m->fine_map);
+    free(m->centre);
+    free(m->side);
+    free(m->nside_sca);
+    free(m->s_offset);
+    free(m);
+}
+
+static int is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int orc_model_create(const orc_grid_desc *d, orc_model **out)
+{
+    *out = NULL;
+    if (d->n_leaves <= 0 || d->n_lambda <= 0 || d->root_size <= 0.0 || d->c_light <= 0.0) return ORC_E_INVALID;
+    for (int a = 0; a < 3; ++a) if (d->nroot[a] <= 0) return ORC_E_INVALID;
+    orc_model *m = (orc_model *)calloc(1, sizeof(orc_model));
+    if (!m) return ORC_E_OOM;
+    m->d = *d;
+    int lmax = 0;
+    for (int64_t i = 0; i < d->n_leaves; ++i) {
+        if (d->level[i] < 0 || d->level[i] > 20) { orc_model_destroy(m); return ORC_E_INVALID; }
+        if (d->level[i] > lmax) lmax = d->level[i];
+    }
+    m->max_level = lmax;
+    for (int a = 0; a < 3; ++a) m->fine[a] = (int64_t)d->nroot[a] << lmax;
+    m->h_fine = d->root_size / (double)((int64_t)1 << lmax);
+    int64_t nfine = m->fine[0] * m->fine[1] * m->fine[2];
+    m->fine_map = (int32_t *)malloc(sizeof(int32_t) * (size_t)nfine);
+    m->centre = (double *)malloc(sizeof(double) * 3 * (size_t)d->n_leaves);
+    m->side = (double *)malloc(sizeof(double) * (size_t)d->n_leaves);
+    m->nside_sca = (int32_t *)malloc(sizeof(int32_t) * (size_t)d->n_lambda);
+    m->s_offset = (int64_t *)malloc(sizeof(int64_t) * (size_t)(d->n_lambda + 1));
+    if (!m->fine_map || !m->centre || !m->side || !m->nside_sca || !m->s_offset) { orc_model_destroy(m); return ORC_E_OOM; }
+    for (int64_t f = 0; f < nfine; ++f) m->fine_map[f] = -1;
+    /* every finest-level cell must belong to exactly one leaf */
+    for (int64_t i = 0; i < d->n_leaves; ++i) {
+        int lv = d->level[i];
+        int64_t span = (int64_t)1 << (lmax - lv);
+        double side = d->root_size / (double)((int64_t)1 << lv);
+        m->side[i] = side;
+        for (int a = 0; a < 3; ++a) {
+            int64_t c = d->ijk[3 * i + a];
+            if (c < 0 || (c + 1) * span > m->fine[a]) { orc_model_destroy(m); return ORC_E_INVALID; }
+            m->centre[3 * i + a] = d->lo[a] + ((double)c + 0.5) * side;
+        }
+        if (!(d->rho[i] >= 0.0) || !isfinite(d->rho[i])) { orc_model_destroy(m); return ORC_E_INVALID; }
+        for (int l = 0; l < d->n_lambda; ++l) {
+            double e = d->emis[(int64_t)l * d->n_leaves + i];
+            if (!(e >= 0.0) || !isfinite(e)) { orc_model_destroy(m); return ORC_E_INVALID; }
+        }
+        int64_t x0 = d->ijk[3 * i] * span, y0 = d->ijk[3 * i + 1] * span, z0 = d->ijk[3 * i + 2] * span;
+        for (int64_t z = z0; z < z0 + span; ++z)
+            for (int64_t y = y0; y < y0 + span; ++y)
+                for (int64_t x = x0; x < x0 + span; ++x) {
+                    int64_t f = (z * m->fine[1] + y) * m->fine[0] + x;
+                    if (m->fine_map[f] != -1) { orc_model_destroy(m); return ORC_E_INVALID; }
+                    m->fine_map[f] = (int32_t)i;
+                }
+    }
+    for (int64_t f = 0; f < nfine; ++f)
+        if (m->fine_map[f] < 0) { orc_model_destroy(m); return ORC_E_INVALID; }
+    m->s_offset[0] = 0;
+    for (int l = 0; l < d->n_lambda; ++l) {
+        int ns = d->nside_sca[l];
+        if (ns == 0) ns = 1 << orc_k_hp(d->g[l], d->n_fwhm, d->k_max);
+        if (!is_pow2(ns) || !(d->kappa[l] >= 0.0) || !(d->albedo[l] >= 0.0 && d->albedo[l] <= 1.0) ||
+            !(d->g[l] > -1.0 && d->g[l] < 1.0)) { orc_model_destroy(m); return ORC_E_INVALID; }
+        m->nside_sca[l] = ns;
+        m->s_offset[l + 1] = m->s_offset[l] + d->n_leaves * 12 * (int64_t)ns * ns;
+    }
+    *out = m;
+    return ORC_OK;
+}
+
+int64_t orc_model_s_size(const orc_model *m) { return m->s_offset[m->d.n_lambda]; }
+int32_t orc_model_nside_sca(const orc_model *m, int l) { return m->nside_sca[l]; }
+int64_t orc_model_s_offset(const orc_model *m, int l) { return m->s_offset[l]; }
+
+/* Finest-level cell index of point p along each axis; a point on a cell face
+ * belongs to the cell that the direction d points into (upper cell when the
+ * component is zero).  Returns 0 outside the root block. */
+static int orc_fine_index(const orc_model *m, const double p[3], const double d[3], int64_t f[3])
+{
+    int inside = 1;
+    for (int a = 0; a < 3; ++a) {
+        double u = (p[a] - m->d.lo[a]) / m->h_fine;
+        double fl = floor(u);
+        int64_t i = (fl < -1.0) ? -1 : (fl > (double)m->fine[a]) ? m->fine[a] : (int64_t)fl;
+        if (u == fl && d[a] < 0.0) i -= 1;
+        if (i < 0 || i >= m->fine[a]) inside = 0;
+        f[a] = i;
+    }
+    return inside;
+}
+
+static int64_t orc_leaf_at(const orc_model *m, const int64_t f[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (f[a] < 0 || f[a] >= m->fine[a]) return -1;
+    return m->fine_map[(f[2] * m->fine[1] + f[1]) * m->fine[0] + f[0]];
+}
+
+/* Leaf containing point p (tie rule above); -1 outside the root block. */
+int64_t orc_locate(const orc_model *m, const double p[3], const double d[3])
+{
+    int64_t f[3];
+    if (!orc_fine_index(m, p, d, f)) return -1;
+    return orc_leaf_at(m, f);
+}
+
+/* Exit of leaf c along o + t d: exit distance and next leaf (-1 when the ray
+ * leaves the root block).  The next leaf is the face neighbour across the
+ * exit face that contains the exit point: on the exit axis its index follows
+ * from the leaf's integer coordinates, on the other axes the exit point is
+ * located and kept within the leaf's own extent. */
+static int64_t orc_step(const orc_model *m, int64_t c, const double o[3], const double d[3], double *t_exit)
+{
+    double lo[3], hi[3];
+    int64_t span = (int64_t)1 << (m->max_level - m->d.level[c]);
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = m->centre[3 * c + a] - 0.5 * m->side[c];
+        hi[a] = m->centre[3 * c + a] + 0.5 * m->side[c];
+    }
+    double best = INFINITY;
+    int axis = -1;
+    for (int a = 0; a < 3; ++a) {
+        double t;
+        if (d[a] > 0.0) t = (hi[a] - o[a]) / d[a];
+        else if (d[a] < 0.0) t = (lo[a] - o[a]) / d[a];
+        else continue;
+        if (t < best) { best = t; axis = a; }
+    }
+    *t_exit = best;
+    double p[3];
+    int64_t f[3];
+    for (int a = 0; a < 3; ++a) p[a] = o[a] + best * d[a];
+    orc_fine_index(m, p, d, f);
+    for (int a = 0; a < 3; ++a) {
+        int64_t first = m->d.ijk[3 * c + a] * span, last = first + span - 1;
+        if (a == axis) f[a] = d[a] > 0.0 ? last + 1 : first - 1;
+        else if (f[a] < first) f[a] = first;
+        else if (f[a] > last) f[a] = last;
+    }
+    return orc_leaf_at(m, f);
+}
+
+/* Cells crossed by the ray o + t d from t = t0: leaf ids, path lengths and
+ * entry distances (zero-length segments included).  Returns the count, at
+ * most max_cross. */
+int64_t orc_trace_cells(const orc_model *m, const double o[3], const double d[3], double t0,
+                        int64_t max_cross, int64_t *cells, double *lengths, double *t_in)
+{
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = o[a] + t0 * d[a];
+    int64_t c = orc_locate(m, p, d);
+    double t = t0;
+    int64_t n = 0;
+    while (c >= 0 && n < max_cross) {
+        double te;
+        int64_t nx = orc_step(m, c, o, d, &te);
+        cells[n] = c;
+        lengths[n] = te > t ? te - t : 0.0;
+        t_in[n] = t;
+        ++n;
+        if (te > t) t = te;
+        c = nx;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One radiative-transfer pass                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t level;      /* HEALPix level relative to the initial Nside */
+    int64_t pix;        /* nested pixel at Nside = nside0 << level */
+    double t_start;     /* distance already crossed from the source */
+    double *L;          /* [n_lambda] luminosity carried */
+} orc_ray;
+
+typedef struct {
+    double *U;          /* private or shared accumulators */
+    double *S;
+    int atomic;
+    double tally[64 * N_TALLY];
+    int64_t count[N_COUNT];
+    double *w;          /* [sum npix] weights of the current ray */
+    orc_ray *stack;
+    double *lbuf;
+    int64_t cap;
+} orc_thread;
+
+static inline void orc_add(double *p, double v, int atomic)
+{
+    if (atomic) {
+#pragma omp atomic
+        *p += v;
+    } else {
+        *p += v;
+    }
+}
+
+/* Luminosity launched along ray pixel `pix` at `nside_ray` from source s at
+ * wavelength l, for the direct pass or from the pending scattered light. */
+static double orc_launch(const orc_model *m, const orc_pass_opts *o, const double *S_pending,
+                         int64_t s, int l, int64_t nside_ray, int64_t pix)
+{
+    const orc_grid_desc *d = &m->d;
+    double nray = 12.0 * (double)nside_ray * (double)nside_ray;
+    if (o->mode != ORC_SCATTER)
+        return 4.0 * M_PI * d->emis[(int64_t)l * d->n_leaves + s] * m->side[s] * m->side[s] * m->side[s] / nray;
+    int64_t ns = m->nside_sca[l];
+    int64_t npix = 12 * ns * ns;
+    const double *row = S_pending + m->s_offset[l] + s * npix;
+    if (nside_ray >= ns) {
+        int64_t shift = 0;
+        while ((ns << shift) < nside_ray) ++shift;
+        return row[pix >> (2 * shift)] * (double)npix / nray;
+    }
+    int64_t shift = 0;
+    while ((nside_ray << shift) < ns) ++shift;
+    int64_t nchild = (int64_t)1 << (2 * shift);
+    double sum = 0.0;
+    for (int64_t q = pix * nchild; q < (pix + 1) * nchild; ++q) sum += row[q];
+    return sum;
+}
+
+static void orc_ray_dir(const orc_pass_opts *o, int64_t nside, int64_t pix, double n[3])
+{
+    double v[3];
+    orc_healpix_vec(nside, pix, v);
+    orc_rotate(o->frame, v, n);
+}
+
+/* Follow one ray until it escapes, is blocked or is split. */
+static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double *U_LL,
+                       int64_t s, orc_ray *ray, orc_thread *th, int64_t *stack_n)
+{
+    const orc_grid_desc *d = &m->d;
+    const int nl = d->n_lambda;
+    const double cl = d->c_light;
+    int64_t nside = (int64_t)o->nside << ray->level;
+    double omega_hp = 4.0 * M_PI / (12.0 * (double)nside * (double)nside);
+    double n[3];
+    orc_ray_dir(o, nside, ray->pix, n);
+    const double *xs = &m->centre[3 * s];
+    if (o->mode != ORC_STEP1) {
+        for (int l = 0; l < nl; ++l)
+            orc_hg_weights(m->nside_sca[l], d->g[l], n, o->frame, th->w + m->s_offset[l] / d->n_leaves);
+    }
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = xs[a] + ray->t_start * n[a];
+    int64_t c = orc_locate(m, p, n);
+    double t = ray->t_start;
+    double *L = ray->L;
+    double tau[64], ext[64];
+    int sig[64];
+    int64_t steps = 0;
+    while (c >= 0) {
+        if (o->max_steps > 0 && steps >= o->max_steps) { th->count[C_MAXSTEP]++; return; }
+        ++steps;
+        double te;
+        int64_t next = orc_step(m, c, xs, n, &te);
+        double len = te > t ? te - t : 0.0;
+        if (len > 0.0) {
+            double t_in = t;
+            double dc2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double q = m->centre[3 * c + a] - xs[a];
+                dc2 += q * q;
+            }
+            double vol = m->side[c] * m->side[c] * m->side[c];
+            int any_sig = 0;
+            for (int l = 0; l < nl; ++l) {
+                double alpha = d->kappa[l] * d->rho[c];
+                tau[l] = alpha * len;
+                ext[l] = L[l] * (-expm1(-tau[l]));
+                if (!o->adaptive || o->mode == ORC_STEP1) {
+                    sig[l] = 1;
+                } else {
+                    double lavg = tau[l] > 0.0 ? ext[l] / tau[l] : L[l];
+                    if (!(lavg > 0.0)) sig[l] = 0;
+                    else if (dc2 == 0.0) sig[l] = 1;
+                    else sig[l] = lavg / (omega_hp * dc2 * cl) >= o->f_U * U_LL[(int64_t)l * d->n_leaves + c];
+                }
+                any_sig |= sig[l];
+            }
+            if (o->adaptive) {
+                if (o->mode == ORC_STEP1 && t_in >= o->r_pre) {
+                    for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_CUT] += L[l];
+                    th->count[C_CUTS]++;
+                    return;
+                }
+                int too_large = dc2 > 0.0 &&
+                    omega_hp > (m->side[c] * m->side[c] / dc2) / o->n_rays_min;
+                if (too_large) {
+                    if (any_sig && nside < o->nside_max) {
+                        th->count[C_SPLITS]++;
+                        for (int k = 0; k < 4; ++k) {
+                            if (*stack_n >= th->cap) abort();
+                            orc_ray *ch = &th->stack[*stack_n];
+                            ch->level = ray->level + 1;
+                            ch->pix = 4 * ray->pix + k;
+                            ch->t_start = t_in;
+                            for (int l = 0; l < nl; ++l) ch->L[l] = 0.25 * L[l];
+                            ++*stack_n;
+                        }
+                        return;
+                    }
+                    if (!any_sig) {
+                        for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_CUT] += L[l];
+                        th->count[C_CUTS]++;
+                        return;
+                    }
+                }
+            }
+            th->count[C_CROSS]++;
+            for (int l = 0; l < nl; ++l) {
+                double alpha = d->kappa[l] * d->rho[c];
+                if (sig[l]) {
+                    double du = alpha > 0.0 ? ext[l] / (alpha * vol * cl) : L[l] * len / (vol * cl);
+                    orc_add(&th->U[(int64_t)l * d->n_leaves + c], du, th->atomic);
+                    double om = d->albedo[l];
+                    th->tally[l * N_TALLY + T_ABSORBED] += (1.0 - om) * ext[l];
+                    th->tally[l * N_TALLY + T_SCATTERED] += om * ext[l];
+                    th->count[C_DEPOSITS]++;
+                    if (o->mode != ORC_STEP1 && om * ext[l] != 0.0) {
+                        int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
+                        const double *w = th->w + m->s_offset[l] / d->n_leaves;
+                        double *row = th->S + m->s_offset[l] + c * npix;
+                        double ds = om * ext[l];
+                        for (int64_t q = 0; q < npix; ++q) orc_add(&row[q], ds * w[q], th->atomic);
+                    }
+                } else {
+                    th->tally[l * N_TALLY + T_SKIPPED] += ext[l];
+                    th->count[C_SKIPS]++;
+                }
+                L[l] *= exp(-tau[l]);
+            }
+            t = te;
+        }
+        c = next;
+    }
+    for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_ESCAPED] += L[l];
+    th->count[C_ESCAPES]++;
+}
+
+/* Run one pass.  Outputs (overwritten): U_k [n_lambda][n], S_next [S size]
+ * (untouched in step 1), tally [n_lambda][8], counters [8].  Inputs: S_pending
+ * (scatter pass), U_LL (adaptive direct/scatter passes). */
+int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pending, const double *U_LL,
+                 double *U_k, double *S_next, double *tally, int64_t *counters)
+{
+    const orc_grid_desc *d = &m->d;
+    const int nl = d->n_lambda;
+    const int64_t n = d->n_leaves;
+    if (nl > 64 || o->nside <= 0 || !is_pow2(o->nside)) return ORC_E_INVALID;
+    if (o->adaptive && (o->nside_max < o->nside || !is_pow2(o->nside_max) || !(o->n_rays_min > 0.0))) return ORC_E_INVALID;
+    if (o->mode == ORC_SCATTER && !S_pending) return ORC_E_INVALID;
+    if (o->adaptive && o->mode != ORC_STEP1 && !U_LL) return ORC_E_INVALID;
+    int64_t ssize = m->s_offset[nl];
+    int64_t wsize = ssize / n;
+    int nthreads = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
+    /* private accumulators when they fit comfortably, shared atomics otherwise */
+    double per_thread = 8.0 * ((double)nl * n + (o->mode == ORC_STEP1 ? 0.0 : (double)ssize));
+    int atomic = per_thread * nthreads > 6.0e9;
+    memset(U_k, 0, sizeof(double) * (size_t)(nl * n));
+    if (o->mode != ORC_STEP1) memset(S_next, 0, sizeof(double) * (size_t)ssize);
+    memset(tally, 0, sizeof(double) * (size_t)(nl * N_TALLY));
+    memset(counters, 0, sizeof(int64_t) * N_COUNT);
+    int levels = 0;
+    if (o->adaptive) while (((int64_t)o->nside << levels) < o->nside_max) ++levels;
+    int64_t nray0 = 12 * (int64_t)o->nside * o->nside;
+    int failed = 0;
+
+#pragma omp parallel num_threads(nthreads)
+    {
+        orc_thread th;
+        memset(&th, 0, sizeof(th));
+        th.atomic = atomic;
+        if (atomic) {
+            th.U = U_k;
+            th.S = S_next;
+        } else {
+            th.U = (double *)calloc((size_t)(nl * n), sizeof(double));
+            th.S = o->mode == ORC_STEP1 ? NULL : (double *)calloc((size_t)ssize, sizeof(double));
+        }
+        th.w = (double *)malloc(sizeof(double) * (size_t)(wsize > 0 ? wsize : 1));
+        th.cap = 3 * (int64_t)levels + 8;
+        th.stack = (orc_ray *)malloc(sizeof(orc_ray) * (size_t)th.cap);
+        th.lbuf = (double *)malloc(sizeof(double) * (size_t)(th.cap * nl));
+        int ok = th.w && th.stack && th.lbuf && th.U && (o->mode == ORC_STEP1 || th.S);
+        if (!ok) {
+#pragma omp atomic write
+            failed = 1;
+        }
+        if (ok) {
+            for (int64_t k = 0; k < th.cap; ++k) th.stack[k].L = th.lbuf + k * nl;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t s = 0; s < n; ++s) {
+                if (o->source_mask && !o->source_mask[s]) continue;
+                if (o->mode == ORC_STEP1 && o->adaptive == 0) { /* step 1 only makes sense with R_pre */ }
+                /* emitted luminosity of this source */
+                double emitted_any = 0.0;
+                for (int l = 0; l < nl; ++l) {
+                    double e;
+                    if (o->mode != ORC_SCATTER) {
+                        e = 4.0 * M_PI * d->emis[(int64_t)l * n + s] * m->side[s] * m->side[s] * m->side[s];
+                    } else {
+                        int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
+                        e = 0.0;
+                        for (int64_t q = 0; q < npix; ++q) e += S_pending[m->s_offset[l] + s * npix + q];
+                    }
+                    th.tally[l * N_TALLY + T_EMITTED] += e;
+                    emitted_any += e;
+                }
+                if (!(emitted_any > 0.0)) continue;
+                for (int64_t r = 0; r < nray0; ++r) {
+                    int64_t sn = 0;
+                    orc_ray *top = &th.stack[sn++];
+                    top->level = 0;
+                    top->pix = r;
+                    top->t_start = 0.0;
+                    double lsum = 0.0;
+                    for (int l = 0; l < nl; ++l) {
+                        top->L[l] = orc_launch(m, o, S_pending, s, l, o->nside, r);
+                        lsum += top->L[l];
+                    }
+                    if (!(lsum > 0.0)) continue;
+                    th.count[C_RAYS]++;
+                    while (sn > 0) {
+                        /* pop the last ray; copy its state since children overwrite the slot */
+                        orc_ray cur;
+                        double lcur[64];
+                        orc_ray *src = &th.stack[--sn];
+                        cur.level = src->level;
+                        cur.pix = src->pix;
+                        cur.t_start = src->t_start;
+                        for (int l = 0; l < nl; ++l) lcur[l] = src->L[l];
+                        cur.L = lcur;
+                        orc_follow(m, o, U_LL, s, &cur, &th, &sn);
+                    }
+                }
+            }
+#pragma omp critical
+            {
+                if (!atomic) {
+                    for (int64_t i = 0; i < nl * n; ++i) U_k[i] += th.U[i];
+                    if (o->mode != ORC_STEP1)
+                        for (int64_t i = 0; i < ssize; ++i) S_next[i] += th.S[i];
+                }
+                for (int i = 0; i < nl * N_TALLY; ++i) tally[i] += th.tally[i];
+                for (int i = 0; i < N_COUNT; ++i) counters[i] += th.count[i];
+            }
+        }
+        if (!atomic) {
+            free(th.U);
+            free(th.S);
+        }
+        free(th.w);
+        free(th.stack);
+        free(th.lbuf);
+    }
+    return failed ? ORC_E_OOM : ORC_OK;
+}
