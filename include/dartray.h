@@ -1,0 +1,255 @@
+/*
+ * dartray.h -- C ABI of the MI355X (gfx950) ray-march library for the
+ * purely ray-tracing dust radiative-transfer method of DART-Ray V2
+ * (Natale et al. 2017, arXiv:1709.03802).
+ *
+ * The method (paper Sect. 2): every radiation source of an adaptive Cartesian
+ * grid casts rays along HEALPix directions; each ray-cell crossing attenuates
+ * the ray and adds to the crossed cell's radiation-field energy density U and
+ * to its angular scattered-luminosity array (Henyey-Greenstein phase function,
+ * Eq. 4, and the albedo).  A run is step 1 (lower-limit U, adaptive rays only),
+ * the direct-light pass and a number of scattering iterations, each of which
+ * re-emits the scattered luminosity left by the previous pass.
+ *
+ * Conventions for every entry point:
+ *  - Return value: DARTRAY_OK or a negative status; the message of the last
+ *    failure on the calling thread is returned by dartray_last_error().
+ *  - Argument errors are detected before any output is written.
+ *  - All device buffers in dartray_fields are owned by the caller; the library
+ *    never frees them.  The library owns only what dartray_grid_create
+ *    allocates (geometry, tables, work arrays) and frees it in
+ *    dartray_grid_destroy.  No entry point other than dartray_grid_create
+ *    allocates device memory.
+ *  - Work is queued on the stream given to dartray_grid_create and is
+ *    asynchronous, except where a host output is returned (dartray_scatter_iter's
+ *    r_k, dartray_debug_ray_cells): those synchronise that stream.
+ *  - One grid handle must not be used by two threads or streams at once.
+ *  - Precision: geometry and deposits in FP32; the luminosity tallies and the
+ *    convergence ratio are FP64 reductions.
+ */
+#ifndef DARTRAY_H
+#define DARTRAY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DARTRAY_OK 0
+#define DARTRAY_E_INVALID (-1)      /* bad argument or grid description */
+#define DARTRAY_E_OOM (-2)          /* device allocation failed (create only) */
+#define DARTRAY_E_DEVICE (-3)       /* HIP runtime error; message has the HIP string */
+#define DARTRAY_E_STATE (-4)        /* call out of sequence (e.g. scatter before direct) */
+#define DARTRAY_E_UNSUPPORTED (-5)  /* valid request this build does not handle */
+#define DARTRAY_E_NUMERIC (-6)      /* non-finite value produced by a pass */
+
+/* pass modes */
+#define DARTRAY_MODE_STEP1 0        /* lower-limit U within r_pre (Sect. 2, step 1) */
+#define DARTRAY_MODE_DIRECT 1       /* direct light from the emitting cells (step 2) */
+
+/* option flags */
+#define DARTRAY_FLAG_COUNTERS 1u    /* fill fields->counters */
+
+/* tally slots, per wavelength, FP64, in luminosity units */
+#define DARTRAY_T_EMITTED 0         /* luminosity launched by the pass's sources */
+#define DARTRAY_T_ABSORBED 1        /* (1 - albedo) * extinguished, deposited crossings */
+#define DARTRAY_T_SCATTERED 2       /* albedo * extinguished, deposited crossings */
+#define DARTRAY_T_ESCAPED 3         /* left the root block */
+#define DARTRAY_T_CUT 4             /* carried by rays blocked by Eq. 1 / beyond r_pre */
+#define DARTRAY_T_SKIPPED 5         /* extinguished at crossings skipped at that wavelength */
+#define DARTRAY_N_TALLY 8
+
+/* counter slots (uint64) */
+#define DARTRAY_C_CROSSINGS 0       /* traversed ray-cell crossings longer than 1e-6 of the cell side */
+#define DARTRAY_C_RAYS 1            /* rays launched from sources */
+#define DARTRAY_C_SPLITS 2          /* rays replaced by 4 children (Eq. 2) */
+#define DARTRAY_C_CUTS 3            /* rays blocked */
+#define DARTRAY_C_ESCAPES 4         /* rays that left the root block */
+#define DARTRAY_C_DEPOSITS 5        /* crossing x wavelength deposits */
+#define DARTRAY_C_SKIPS 6           /* crossing x wavelength skipped (Sect. 3.2) */
+#define DARTRAY_C_MAXSTEP 7         /* rays stopped by max_steps */
+#define DARTRAY_N_COUNT 8
+
+typedef struct dartray_grid dartray_grid;   /* opaque handle */
+
+/*
+ * Grid description (host memory; read during dartray_grid_create only).
+ *
+ * The model is a block of nroot[0] x nroot[1] x nroot[2] cubic root cells of
+ * edge root_size with lower corner lo; each root cell is an octree.  Leaf i
+ * sits at refinement level leaf_level[i] (0 = root cell) with integer
+ * coordinates leaf_ijk[3i..3i+2] counted in level-sized cells over the whole
+ * block, so it spans lo + ijk * root_size / 2^level ... + root_size / 2^level.
+ * The leaves must tile the block exactly (no gap, no overlap).  This is the
+ * adaptive 3D Cartesian grid of Sect. 2.
+ *
+ * Per leaf: dust density rho (so that kappa[l] * rho is the optical depth per
+ * unit length, Sect. 2) and stellar volume emissivity emis[l * n + i]
+ * (luminosity per unit volume and solid angle).  Per wavelength: kappa,
+ * albedo, g (Henyey-Greenstein, Eq. 4) and nside_sca, the HEALPix Nside of
+ * the scattered source function at that wavelength (a power of two, or 0 to
+ * apply the resolution rule of Eq. 5-6 with n_fwhm and the cap k_max).
+ * Values must be finite, rho and emis >= 0, 0 <= albedo <= 1, |g| < 1.
+ */
+typedef struct {
+    int32_t nroot[3];
+    double lo[3];
+    double root_size;
+    int64_t n_leaves;
+    const int32_t *leaf_level;   /* [n] */
+    const int64_t *leaf_ijk;     /* [n][3] */
+    const float *rho;            /* [n] */
+    const float *emis;           /* [n_lambda][n] */
+    int32_t n_lambda;
+    const float *kappa;          /* [n_lambda] */
+    const float *albedo;         /* [n_lambda] */
+    const float *g;              /* [n_lambda] */
+    const int32_t *nside_sca;    /* [n_lambda] */
+    double n_fwhm;               /* Eq. 6; the paper uses 5 */
+    int32_t k_max;               /* cap on k of Eq. 5 (the paper suggests 2-3) */
+    double c_light;              /* speed of light in the grid's units */
+} dartray_grid_desc;
+
+/*
+ * Ray policy and pass options (Sect. 3.1.1, 3.5).
+ *
+ * adaptive = 0: every source casts the 12 nside^2 HEALPix rays, no cutoff.
+ * adaptive = 1: sources start with 12 nside^2 rays; a ray is split into its 4
+ *   nested children (nside doubled, up to nside_max) when its beam is larger
+ *   than the solid angle of the crossed cell over n_rays_min (Eq. 2) and it
+ *   still matters; it is blocked when the beam is too large and its estimated
+ *   contribution (Eq. 8) is below f_U times U_LL at every wavelength (Eq. 1);
+ *   wavelengths below the threshold skip their deposits (Sect. 3.2).  In step
+ *   1 the significance test is "entry distance < r_pre" and rays are cut at
+ *   r_pre.  f_U < 0 selects f_U = 4 a_RT / N_s (Eq. 11) with N_s the number
+ *   of sources of the pass.
+ * frame: row-major rotation applied to every HEALPix direction (rays and
+ *   scattered-light pixels alike); identity when all zero.
+ * source_mask: optional device uint8[n]; sources with 0 are skipped (direct
+ *   pass and step 1 only).  Used for source-subset runs.
+ * max_steps: per-ray crossing limit (0 = unlimited); rays hitting it stop and
+ *   are counted in DARTRAY_C_MAXSTEP.
+ */
+typedef struct {
+    int32_t mode;                /* DARTRAY_MODE_*, for dartray_trace_direct */
+    int32_t adaptive;
+    int32_t nside;
+    int32_t nside_max;
+    float n_rays_min;
+    float f_U;
+    float a_RT;
+    float r_pre;
+    double frame[9];
+    const uint8_t *source_mask;  /* device, nullable */
+    uint32_t flags;              /* DARTRAY_FLAG_* */
+    int64_t max_steps;
+} dartray_trace_opts;
+
+/*
+ * Field buffers (device memory, caller-owned, FP32 unless stated).
+ *  U         [n_lambda][n]  total energy density; each pass adds its U_k
+ *  U_LL      [n_lambda][n]  lower limit used by the block test (adaptive);
+ *                           step 1 writes it, every later pass sets it to U
+ *  U_pass    [n_lambda][n]  nullable; receives this pass's U_k
+ *  S_total   [s_size]       total scattered luminosity, all orders (Sect. 3.1.2)
+ *  S_pending [s_size]       scattered luminosity waiting for the next iteration
+ *  S_next    [s_size]       work array of the pass (overwritten)
+ *  tally     [n_lambda][8]  FP64, overwritten by each pass (DARTRAY_T_*)
+ *  counters  [8]            uint64, overwritten when DARTRAY_FLAG_COUNTERS
+ * S arrays hold one block per wavelength, block l starting at
+ * dartray_s_offset(grid, l), laid out [n][12 nside_sca(l)^2] with the HEALPix
+ * nested pixel index fastest.  S[l][c][p] is the luminosity scattered by cell
+ * c into pixel p; j_sca = S / (V_c * 4 pi / N_pix).
+ */
+typedef struct {
+    float *U;
+    float *U_LL;
+    float *U_pass;
+    float *S_total;
+    float *S_pending;
+    float *S_next;
+    double *tally;
+    uint64_t *counters;
+} dartray_fields;
+
+/* Build the device-side grid: validate, copy to the GPU, build the leaf
+ * locator and the direction / phase-function tables.  `stream` is a
+ * hipStream_t (NULL = default stream); all later work of the handle runs on
+ * it.  On failure *out is NULL. */
+int dartray_grid_create(const dartray_grid_desc *desc, void *stream, dartray_grid **out);
+
+/* Release everything dartray_grid_create allocated.  Accepts NULL. */
+int dartray_grid_destroy(dartray_grid *grid);
+
+/* Size queries. */
+int dartray_grid_info(const dartray_grid *grid, int64_t *n_leaves, int32_t *n_lambda, int64_t *s_size);
+int dartray_nside_sca(const dartray_grid *grid, int32_t l, int32_t *nside);
+int64_t dartray_s_offset(const dartray_grid *grid, int32_t l);
+
+/* Replace the dust density (device float[n]); used by gradient-based fits. */
+int dartray_grid_set_rho(dartray_grid *grid, const float *rho_device);
+
+/*
+ * Step 1 or the direct-light pass (Sect. 2, steps 1-2), by opts->mode.
+ * STEP1: U_LL <- U_k of rays traced within r_pre (adaptive only).
+ * DIRECT: zeroes S_total, then U <- U + U_k, S_total <- S_next,
+ *   S_pending <- S_next; U_LL <- U when adaptive.  Records sum(S_next) as the
+ *   reference of the convergence ratio.
+ */
+int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields);
+
+/*
+ * One scattering iteration (Sect. 2, step 3): the luminosity in S_pending is
+ * re-emitted from each dusty cell along the ray directions (the ray inside
+ * j_sca pixel p carries S_pending[p] * N_pix / N_ray), then U <- U + U_k,
+ * S_total <- S_total + S_next, S_pending <- S_next, U_LL <- U when adaptive.
+ * *r_k (host) receives sum(S_next) / sum(S after the direct pass), the ratio
+ * tested against f_L; this synchronises the stream.  Requires a prior DIRECT.
+ */
+int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields, double *r_k);
+
+/*
+ * Gradient of a loss of U with respect to rho, by an adjoint march that
+ * recomputes every ray in reverse (no ray storage).  fwd holds the forward
+ * run's fields; dJ_dU [n_lambda][n] (device) is dLoss/dU; dJ_drho [n] (device)
+ * is overwritten.  Not available in this build: returns DARTRAY_E_UNSUPPORTED.
+ */
+int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, const dartray_fields *fwd,
+                          const float *dJ_dU, const float *dJ_dj, const float *dJ_desc, float *dJ_drho);
+
+/*
+ * Test helper: the cells crossed by n_rays rays (host arrays: origin[3i],
+ * dir[3i], in grid coordinates), computed by the device traversal.  Up to
+ * max_cross crossings per ray are written to cells[i * max_cross + m] (leaf id)
+ * and lengths[...] (path length, 0 for zero-length segments); counts[i] gets
+ * the number written.  Synchronises the stream.
+ */
+int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *origin, const double *dir,
+                            int32_t max_cross, int64_t *cells, float *lengths, int32_t *counts);
+
+/* Timing of the ray-march kernels with HIP events recorded on the grid's
+ * stream around every march launch.  enable != 0 clears earlier records and
+ * starts recording; 0 stops. */
+int dartray_profile_enable(dartray_grid *grid, int32_t enable);
+
+/* Sum of the recorded march-kernel durations (ms) and the number of launches
+ * since recording started; synchronises the stream. */
+int dartray_profile_read(dartray_grid *grid, double *march_ms, int64_t *launches);
+
+/* Bytes of device work memory the handle holds. */
+int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *dartray_last_error(void);
+
+/* Library version string. */
+const char *dartray_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DARTRAY_H */

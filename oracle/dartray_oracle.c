@@ -559,7 +559,9 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
                     }
                 }
             }
-            th->count[C_CROSS]++;
+            /* a crossing counts as work when it is longer than 1e-6 of the
+             * cell; shorter ones are edge or corner grazes at near-ties */
+            if (len > 1e-6 * m->side[c]) th->count[C_CROSS]++;
             for (int l = 0; l < nl; ++l) {
                 double alpha = d->kappa[l] * d->rho[c];
                 if (sig[l]) {

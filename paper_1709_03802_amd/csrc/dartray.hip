@@ -1,0 +1,1267 @@
+// gfx950 ray-march library for the DART-Ray V2 radiative-transfer method
+// (Natale et al. 2017, arXiv:1709.03802): host API and kernels.
+//
+// Data layout on the device:
+//  * leaves: int4 box (lower corner in finest-level cell units, span) plus
+//    rho and 1/(V c) in structure-of-arrays form; positions along rays are in
+//    finest-level cell units so that cell faces and source-cell centres are
+//    exact in FP32;
+//  * locator: one code per root cell and 8 codes per internal octree node;
+//    code >= 0 is an internal node, code < 0 is leaf -code-1;
+//  * S arrays: one block per wavelength, [cell][HEALPix nested pixel].
+//
+// Fixed-Nside passes bin the energy-density deposits by ray direction
+// (ubar[l][r][c]); because every ray of direction r shares the phase-function
+// row w(.|r), the scattered source function follows exactly from
+// S[l][c][p] = albedo c alpha V * sum_r ubar[l][r][c] w_l(p|r), computed by a
+// flush kernel after each batch of directions.  One accumulate per crossing
+// and wavelength replaces the N_pix accumulates of a direct deposit.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "dr_internal.h"
+
+#define DR_VERSION "dartray-gfx950 0.1"
+
+namespace dr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return DARTRAY_E_DEVICE;
+}
+
+#define DR_HIP(call)                                        \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+    } while (0)
+
+#define DR_LAUNCH_CHECK(what)                               \
+    do {                                                    \
+        hipError_t e_ = hipGetLastError();                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what);    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T *p, size_t n, T v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+static int fill(Grid &g, T *p, size_t n, T v)
+{
+    if (n == 0) return DARTRAY_OK;
+    unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, g.stream, p, n, v);
+    DR_LAUNCH_CHECK("fill");
+    return DARTRAY_OK;
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// block-wide FP64 sum (blockDim.x multiple of 64, <= 1024); result valid in thread 0
+__device__ inline double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline void atomic_add_f32(float *p, float v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+__device__ inline void atomic_add_f64(double *p, double v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+// ---------------------------------------------------------------------------
+// Direction and phase tables (FP64 on the device, rounded to FP32)
+// ---------------------------------------------------------------------------
+
+struct Frame {
+    double R[9];
+};
+
+__global__ void k_dirs(float4 *dirs, int nside, int64_t nray, Frame f)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nray) return;
+    double v[3];
+    dr_pix_vec(nside, r, f.R, v);
+    dirs[r] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);
+}
+
+__device__ inline double hg_phase(double g, double mu)
+{
+    const double den = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (4.0 * kPi * den * sqrt(den));
+}
+
+// w_l(p | n_r) = Phi_l(n_p . n_r) / sum_q Phi_l(n_q . n_r), one thread per (r, l)
+__global__ void k_wtab(float *wtab, const LambdaTable *lt, int nside_ray, int64_t nray, int w_row, Frame f)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int nl = lt->n_lambda;
+    if (idx >= nray * nl) return;
+    const int64_t r = idx / nl;
+    const int l = (int)(idx - r * nl);
+    double n[3];
+    dr_pix_vec(nside_ray, r, f.R, n);
+    const int ns = lt->nside_sca[l];
+    const int npix = lt->npix[l];
+    const double g = lt->g[l];
+    double sum = 0.0;
+    for (int p = 0; p < npix; ++p) {
+        double v[3];
+        dr_pix_vec(ns, p, f.R, v);
+        sum += hg_phase(g, v[0] * n[0] + v[1] * n[1] + v[2] * n[2]);
+    }
+    float *row = wtab + r * (int64_t)w_row + lt->w_off[l];
+    for (int p = 0; p < npix; ++p) {
+        double v[3];
+        dr_pix_vec(ns, p, f.R, v);
+        row[p] = (float)(hg_phase(g, v[0] * n[0] + v[1] * n[1] + v[2] * n[2]) / sum);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Source selection: flags in Morton order, emitted luminosity (FP64), and a
+// stable compaction into src_list.
+// ---------------------------------------------------------------------------
+
+__global__ void k_source_flags(int32_t *flags, const int32_t *morton, int64_t n, const LambdaTable *lt,
+                               const float *emis_lum, const float *S_pending, const uint8_t *mask, int scatter,
+                               double *tally)
+{
+    __shared__ double sh[16];
+    const int nl = lt->n_lambda;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c = i < n ? morton[i] : -1;
+    bool any = false;
+    const bool allowed = c >= 0 && (scatter || mask == nullptr || mask[c] != 0);
+    for (int l = 0; l < nl; ++l) {
+        double e = 0.0;
+        if (allowed) {
+            if (!scatter) {
+                e = emis_lum[(int64_t)l * n + c];
+            } else {
+                const float *row = S_pending + lt->s_off[l] + c * (int64_t)lt->npix[l];
+                for (int p = 0; p < lt->npix[l]; ++p) e += row[p];
+            }
+        }
+        any |= e > 0.0;
+        const double b = block_sum(e, sh);
+        if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_EMITTED], b);
+    }
+    if (i < n) flags[i] = any ? 1 : 0;
+}
+
+constexpr int kScanBlock = 1024;
+
+__global__ void k_scan_count(const int32_t *flags, int64_t n, int32_t *block_counts)
+{
+    __shared__ int32_t sh[kScanBlock / 64];
+    const int64_t i = blockIdx.x * (int64_t)kScanBlock + threadIdx.x;
+    int v = i < n ? flags[i] : 0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kScanBlock / 64; ++w) s += sh[w];
+        block_counts[blockIdx.x] = s;
+    }
+}
+
+// exclusive scan of block counts (single block, sequential over chunks)
+__global__ void k_scan_blocks(int32_t *block_counts, int64_t nblocks, int32_t *total)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t run = 0;
+    for (int64_t b = 0; b < nblocks; ++b) {
+        const int32_t v = block_counts[b];
+        block_counts[b] = run;
+        run += v;
+    }
+    *total = run;
+}
+
+__global__ void k_scan_scatter(const int32_t *flags, const int32_t *morton, int64_t n, const int32_t *block_offs,
+                               int32_t *src_list)
+{
+    __shared__ int32_t sh[kScanBlock / 64];
+    const int64_t i = blockIdx.x * (int64_t)kScanBlock + threadIdx.x;
+    const int f = i < n ? flags[i] : 0;
+    const int lane = threadIdx.x & 63;
+    const uint64_t ballot = __ballot(f);
+    const int before = __popcll(ballot & ((1ull << lane) - 1ull));
+    if (lane == 0) sh[threadIdx.x >> 6] = __popcll(ballot);
+    __syncthreads();
+    int wave_off = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wave_off += sh[w];
+    if (f) src_list[block_offs[blockIdx.x] + wave_off + before] = morton[i];
+}
+
+// ---------------------------------------------------------------------------
+// Traversal
+// ---------------------------------------------------------------------------
+
+struct Geo {
+    const int4 *leaf_box;
+    const int32_t *root_tab;
+    const int32_t *nodes;
+    int32_t fine[3];
+    int32_t nroot[3];
+    int32_t max_level;
+};
+
+__device__ inline int32_t locate_fine(const Geo &g, int fx, int fy, int fz)
+{
+    if ((unsigned)fx >= (unsigned)g.fine[0] || (unsigned)fy >= (unsigned)g.fine[1] ||
+        (unsigned)fz >= (unsigned)g.fine[2])
+        return -1;
+    const int L = g.max_level;
+    int32_t v = g.root_tab[((fz >> L) * g.nroot[1] + (fy >> L)) * g.nroot[0] + (fx >> L)];
+    int bit = L - 1;
+    while (v >= 0) {
+        const int oct = ((fx >> bit) & 1) | (((fy >> bit) & 1) << 1) | (((fz >> bit) & 1) << 2);
+        v = g.nodes[v * 8 + oct];
+        --bit;
+    }
+    return -v - 1;
+}
+
+// fine-level cell coordinate of position p along an axis with direction
+// component d: on a face, the side d points to (upper side for d == 0)
+__device__ inline int fine_coord(float p, float d)
+{
+    const float fl = floorf(p);
+    int i = (int)fl;
+    if (p == fl && d < 0.f) i -= 1;
+    return i;
+}
+
+struct Ray {
+    float o[3];       // origin (source-cell centre), fine units
+    float n[3];       // unit direction
+    float inv[3];     // 1/n (unused for zero components)
+};
+
+// exit distance from the leaf with box b along ray R, and the exit axis
+__device__ inline float exit_t(const Ray &R, const int4 b, int &axis)
+{
+    const float INF = __builtin_huge_valf();
+    const int lo[3] = {b.x, b.y, b.z};
+    float best = INF;
+    axis = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float t = INF;
+        if (R.n[a] > 0.f) t = ((float)(lo[a] + b.w) - R.o[a]) * R.inv[a];
+        else if (R.n[a] < 0.f) t = ((float)lo[a] - R.o[a]) * R.inv[a];
+        if (t < best) {
+            best = t;
+            axis = a;
+        }
+    }
+    return best;
+}
+
+// the face neighbour across the exit face that contains the exit point
+template <bool UNIFORM>
+__device__ inline int32_t next_leaf(const Geo &g, const Ray &R, const int4 b, int axis, float te)
+{
+    const int lo[3] = {b.x, b.y, b.z};
+    int f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a == axis) {
+            f[a] = R.n[a] > 0.f ? lo[a] + b.w : lo[a] - 1;
+        } else if (UNIFORM) {
+            f[a] = lo[a];
+        } else {
+            int q = fine_coord(fmaf(te, R.n[a], R.o[a]), R.n[a]);
+            q = q < lo[a] ? lo[a] : q;
+            q = q > lo[a] + b.w - 1 ? lo[a] + b.w - 1 : q;
+            f[a] = q;
+        }
+    }
+    return locate_fine(g, f[0], f[1], f[2]);
+}
+
+__global__ void k_debug_cells(Geo g, int nrays, const double *origin, const double *dir, int max_cross,
+                              int64_t *cells, float *lengths, int32_t *counts)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrays) return;
+    Ray R;
+    float p[3];
+    for (int a = 0; a < 3; ++a) {
+        R.o[a] = (float)origin[3 * i + a];
+        R.n[a] = (float)dir[3 * i + a];
+        R.inv[a] = 1.0f / R.n[a];
+        p[a] = R.o[a];
+    }
+    int32_t c = locate_fine(g, fine_coord(p[0], R.n[0]), fine_coord(p[1], R.n[1]), fine_coord(p[2], R.n[2]));
+    float t = 0.f;
+    int m = 0;
+    while (c >= 0 && m < max_cross) {
+        const int4 b = g.leaf_box[c];
+        int axis;
+        const float te = exit_t(R, b, axis);
+        cells[(int64_t)i * max_cross + m] = c;
+        lengths[(int64_t)i * max_cross + m] = te > t ? te - t : 0.f;
+        ++m;
+        if (te > t) t = te;
+        c = next_leaf<false>(g, R, b, axis, te);
+    }
+    counts[i] = m;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-Nside march: lanes are 64 Morton-consecutive sources, one direction
+// per wave.  Deposits go to ubar[l][r - r0][c].
+// ---------------------------------------------------------------------------
+
+struct FixedArgs {
+    Geo geo;
+    const int32_t *src_list;
+    const int32_t *n_src;
+    const float4 *dirs;
+    const float *rho;
+    const float *inv_vc;
+    const float *emis_lum;       // direct pass
+    const float *S_pending;      // scatter pass
+    const LambdaTable *lt;
+    float *ubar;
+    double *tally;
+    uint64_t *counters;
+    int64_t n;
+    int32_t scatter;
+    int32_t r0;
+    int32_t nb;
+    int32_t nside_ray;
+    int32_t log2_nside_ray;
+    float inv_nray;
+    float h_fine;
+    int64_t max_steps;           // caller's per-ray limit (0 = none)
+    int64_t hard_cap;            // bound no straight ray can exceed; ends any loop
+};
+
+template <int NL, bool UNIFORM>
+__global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
+{
+    const LambdaTable *lt = A.lt;
+    const int nl = lt->n_lambda;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int nsrc = *A.n_src;
+    const int64_t ntiles = (nsrc + 63) >> 6;
+    const int64_t nitems = ntiles * A.nb;
+
+    float esc[NL], kap[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        esc[l] = 0.f;
+        kap[l] = l < nl ? lt->kappa[l] : 0.f;
+    }
+    uint32_t ncross = 0, nrays = 0, nmax = 0;
+
+    for (int64_t it = wid; it < nitems; it += nw) {
+        const int64_t tile = it / A.nb;
+        const int rl = (int)(it - tile * A.nb);
+        const int r = A.r0 + rl;
+        const int64_t si = tile * 64 + lane;
+        if (si >= nsrc) continue;
+        const int32_t s = A.src_list[si];
+        const float4 nd = A.dirs[r];
+        Ray R;
+        R.n[0] = nd.x;
+        R.n[1] = nd.y;
+        R.n[2] = nd.z;
+        int4 b = A.geo.leaf_box[s];
+        const float half = 0.5f * (float)b.w;
+        R.o[0] = (float)b.x + half;
+        R.o[1] = (float)b.y + half;
+        R.o[2] = (float)b.z + half;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
+
+        // launch luminosity
+        float L[NL];
+        float lsum = 0.f;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            float v = 0.f;
+            if (l < nl) {
+                if (!A.scatter) {
+                    v = A.emis_lum[(int64_t)l * A.n + s] * A.inv_nray;
+                } else {
+                    const int npix = lt->npix[l];
+                    const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
+                    const int ls = 31 - __clz(lt->nside_sca[l]);
+                    if (A.log2_nside_ray >= ls) {
+                        v = row[r >> (2 * (A.log2_nside_ray - ls))] * ((float)npix * A.inv_nray);
+                    } else {
+                        const int sh = 2 * (ls - A.log2_nside_ray);
+                        for (int q = r << sh; q < ((r + 1) << sh); ++q) v += row[q];
+                    }
+                }
+            }
+            L[l] = v;
+            lsum += v;
+        }
+        if (!(lsum > 0.f)) continue;
+        ++nrays;
+
+        int32_t c = s;
+        float t = 0.f;
+        int64_t steps = 0;
+        while (true) {
+            int axis;
+            const float te = exit_t(R, b, axis);
+            const float len = te - t;
+            if (len > 0.f) {
+                const float rho = A.rho[c];
+                const float ivc = A.inv_vc[c];
+                const float lp = len * A.h_fine;
+                float *ub = A.ubar + (size_t)rl * A.n + c;
+                const size_t lstride = (size_t)A.nb * A.n;
+#pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    if (l < nl) {
+                        const float alpha = kap[l] * rho;
+                        const float tau = alpha * lp;
+                        const float em1 = expm1f(-tau);          // exp(-tau) - 1
+                        const float ext = -L[l] * em1;
+                        const float du = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
+                        atomic_add_f32(ub + l * lstride, du);
+                        L[l] = fmaf(L[l], em1, L[l]);
+                    }
+                }
+                ncross += len > 1e-6f * (float)b.w;   // edge and corner grazes are not counted
+                t = te;
+            }
+            const int32_t nx = next_leaf<UNIFORM>(A.geo, R, b, axis, te);
+            if (nx < 0) break;
+            ++steps;
+            if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
+                ++nmax;
+                break;
+            }
+            c = nx;
+            b = A.geo.leaf_box[c];
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l) esc[l] += L[l];
+    }
+    // wave-level FP64 reductions of the tallies
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        if (l < nl) {
+            const double v = wave_sum((double)esc[l]);
+            if (lane == 0 && v != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
+        }
+    }
+    const uint64_t wc = wave_sum_u64(ncross), wr = wave_sum_u64(nrays), wm = wave_sum_u64(nmax);
+    if (lane == 0 && A.counters) {
+        if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_CROSSINGS], (unsigned long long)wc);
+        if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_RAYS], (unsigned long long)wr);
+        if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_ESCAPES], (unsigned long long)(wr - wm));
+        if (wm) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_MAXSTEP], (unsigned long long)wm);
+        if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_DEPOSITS], (unsigned long long)(wc * nl));
+        // deposits count the counted crossings times the wavelengths carried
+    }
+}
+
+// U_k[l][c] += sum_r ubar[l][r][c];  S[l][c][p] += albedo c alpha V sum_r ubar[l][r][c] w_l(p|r)
+// grid: x = cell tiles of 256, y = pixel chunks of PCH, z = wavelength
+template <int PCH>
+__global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const float *wtab, const LambdaTable *lt,
+                                                      const float *rho, const float *inv_vc, int64_t n, int r0,
+                                                      int nb, int w_row, float *U_k, float *S_next)
+{
+    __shared__ float ws[64][PCH];
+    const int l = blockIdx.z;
+    const int npix = lt->npix[l];
+    const int p0 = blockIdx.y * PCH;
+    if (p0 >= npix) return;
+    const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
+    const bool ok = c < n;
+    float acc[PCH];
+#pragma unroll
+    for (int j = 0; j < PCH; ++j) acc[j] = 0.f;
+    float accU = 0.f;
+    const float *ub = ubar + (size_t)l * nb * n + (ok ? c : 0);
+    for (int rb = 0; rb < nb; rb += 64) {
+        const int cnt = min(64, nb - rb);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * PCH; e += 256) {
+            const int i = e / PCH, j = e - (e / PCH) * PCH;
+            ws[i][j] = wtab[(int64_t)(r0 + rb + i) * w_row + lt->w_off[l] + p0 + j];
+        }
+        __syncthreads();
+        if (ok) {
+            for (int i = 0; i < cnt; ++i) {
+                const float u = ub[(size_t)(rb + i) * n];
+                accU += u;
+#pragma unroll
+                for (int j = 0; j < PCH; ++j) acc[j] = fmaf(u, ws[i][j], acc[j]);
+            }
+        }
+    }
+    if (!ok) return;
+    const float f = lt->albedo[l] * lt->kappa[l] * rho[c] / inv_vc[c];
+    float *srow = S_next + lt->s_off[l] + c * (int64_t)npix + p0;
+#pragma unroll
+    for (int j = 0; j < PCH; ++j) srow[j] += f * acc[j];
+    if (blockIdx.y == 0) U_k[(int64_t)l * n + c] += accU;
+}
+
+// U += U_k (and U_pass = U_k), absorbed / scattered tallies from U_k in FP64,
+// U_LL <- U when requested.  grid.y = wavelength
+__global__ void k_finish_u(const float *U_k, float *U, float *U_pass, float *U_LL, int set_ull, int ull_only,
+                           const LambdaTable *lt, const float *rho, const float *inv_vc, int64_t n, double *tally)
+{
+    __shared__ double sh[16];
+    const int l = blockIdx.y;
+    double ext = 0.0;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = (int64_t)l * n + c;
+        const float uk = U_k[i];
+        if (ull_only) {
+            U_LL[i] = uk;
+        } else {
+            const float u = U[i] + uk;
+            U[i] = u;
+            if (U_pass) U_pass[i] = uk;
+            if (set_ull) U_LL[i] = u;
+        }
+        ext += (double)lt->kappa[l] * (double)rho[c] / (double)inv_vc[c] * (double)uk;
+    }
+    const double b = block_sum(ext, sh);
+    if (threadIdx.x == 0 && b != 0.0) {
+        const double om = lt->albedo[l];
+        atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_ABSORBED], (1.0 - om) * b);
+        atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_SCATTERED], om * b);
+    }
+}
+
+// S_total (=|+=) S_next, S_pending = S_next, per-wavelength FP64 sums of S_next
+__global__ void k_finish_s(const float *S_next, float *S_total, float *S_pending, int accumulate,
+                           const LambdaTable *lt, int64_t s_size, double *ssum)
+{
+    __shared__ double sh[16];
+    const int l = blockIdx.y;
+    const int64_t lo = lt->s_off[l], hi = lt->s_off[l + 1];
+    double acc = 0.0;
+    for (int64_t i = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = S_next[i];
+        S_total[i] = accumulate ? S_total[i] + v : v;
+        S_pending[i] = v;
+        acc += v;
+    }
+    const double b = block_sum(acc, sh);
+    if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&ssum[l], b);
+}
+
+__global__ void k_check_finite(const float *a, int64_t n, int32_t *bad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(a[i])) *bad = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static double hg_fwhm_closed(double g)
+{
+    if (g <= 0.0) return 0.0;
+    const double f0 = std::pow(1.0 + g * g - 2.0 * g, -1.5);
+    const double fpi = std::pow(1.0 + g * g + 2.0 * g, -1.5);
+    const double half = fpi + 0.5 * (f0 - fpi);
+    const double c = (1.0 + g * g - std::pow(half, -2.0 / 3.0)) / (2.0 * g);
+    return 2.0 * std::acos(std::max(-1.0, std::min(1.0, c)));
+}
+
+// Eq. 5-6: k = 0.5 log2(4 pi / (12 theta_min^2)), theta_min = FWHM / n_fwhm,
+// integer part, clamped to [0, k_max]
+static int nside_from_rule(double g, double n_fwhm, int k_max)
+{
+    const double fwhm = hg_fwhm_closed(g);
+    if (fwhm <= 0.0) return 1;
+    const double tmin = fwhm / n_fwhm;
+    double k = std::floor(0.5 * std::log2(4.0 * kPi / (12.0 * tmin * tmin)));
+    k = std::max(0.0, std::min((double)k_max, k));
+    return 1 << (int)k;
+}
+
+static uint64_t spread3(uint64_t x)
+{
+    x &= 0x1FFFFF;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+template <typename T>
+static int dalloc(Grid &g, T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(DARTRAY_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    g.bytes += sizeof(T) * count;
+    return DARTRAY_OK;
+}
+
+static void free_grid(Grid &g)
+{
+    for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
+    g.ev_pool.clear();
+    void *ptrs[] = {g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
+                    g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dirs, g.wtab};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+static int validate_desc(const dartray_grid_desc *d)
+{
+    if (!d) return fail(DARTRAY_E_INVALID, "null grid description");
+    if (d->n_leaves <= 0 || d->n_leaves > (int64_t)INT32_MAX) return fail(DARTRAY_E_INVALID, "n_leaves out of range");
+    if (d->n_lambda <= 0 || d->n_lambda > kMaxLambda) return fail(DARTRAY_E_INVALID, "n_lambda must be 1..64");
+    if (!(d->root_size > 0.0) || !std::isfinite(d->root_size)) return fail(DARTRAY_E_INVALID, "root_size must be > 0");
+    if (!(d->c_light > 0.0)) return fail(DARTRAY_E_INVALID, "c_light must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (d->nroot[a] <= 0 || !std::isfinite(d->lo[a])) return fail(DARTRAY_E_INVALID, "bad root block");
+    if (!d->leaf_level || !d->leaf_ijk || !d->rho || !d->emis || !d->kappa || !d->albedo || !d->g || !d->nside_sca)
+        return fail(DARTRAY_E_INVALID, "null array in grid description");
+    for (int l = 0; l < d->n_lambda; ++l) {
+        if (!(d->kappa[l] >= 0.f) || !std::isfinite(d->kappa[l])) return fail(DARTRAY_E_INVALID, "kappa must be finite and >= 0");
+        if (!(d->albedo[l] >= 0.f && d->albedo[l] <= 1.f)) return fail(DARTRAY_E_INVALID, "albedo must lie in [0, 1]");
+        if (!(d->g[l] > -1.f && d->g[l] < 1.f)) return fail(DARTRAY_E_INVALID, "g must lie in (-1, 1)");
+        const int ns = d->nside_sca[l];
+        if (ns < 0 || (ns > 0 && (ns & (ns - 1))) || ns > 64) return fail(DARTRAY_E_INVALID, "nside_sca must be 0 or a power of two <= 64");
+    }
+    if (!(d->n_fwhm > 0.0)) {
+        for (int l = 0; l < d->n_lambda; ++l)
+            if (d->nside_sca[l] == 0) return fail(DARTRAY_E_INVALID, "n_fwhm must be > 0 with nside_sca = 0");
+    }
+    return DARTRAY_OK;
+}
+
+}  // namespace dr
+
+using namespace dr;
+
+extern "C" {
+
+const char *dartray_last_error(void) { return g_last_error.c_str(); }
+
+const char *dartray_version(void) { return DR_VERSION; }
+
+int dartray_grid_destroy(dartray_grid *grid)
+{
+    if (!grid) return DARTRAY_OK;
+    if (grid->g.stream) (void)hipStreamSynchronize(grid->g.stream);
+    else (void)hipDeviceSynchronize();
+    free_grid(grid->g);
+    delete grid;
+    return DARTRAY_OK;
+}
+
+int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid **out)
+{
+    if (!out) return fail(DARTRAY_E_INVALID, "null output handle");
+    *out = nullptr;
+    int rc = validate_desc(d);
+    if (rc) return rc;
+    const int64_t n = d->n_leaves;
+    const int nl = d->n_lambda;
+
+    // --- host-side checks and the locator -------------------------------
+    int lmax = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int lv = d->leaf_level[i];
+        if (lv < 0 || lv > 20) return fail(DARTRAY_E_INVALID, "leaf level out of range 0..20");
+        lmax = std::max(lmax, lv);
+    }
+    int64_t fine[3];
+    for (int a = 0; a < 3; ++a) {
+        fine[a] = (int64_t)d->nroot[a] << lmax;
+        if (fine[a] > (1 << 21)) return fail(DARTRAY_E_INVALID, "more than 2^21 finest-level cells along an axis");
+    }
+    const int64_t nroot = (int64_t)d->nroot[0] * d->nroot[1] * d->nroot[2];
+    // codes: >= 0 internal node, < 0 leaf; root table starts "unset"
+    const int32_t kUnset = INT32_MIN;
+    std::vector<int32_t> root_tab((size_t)nroot, kUnset);
+    std::vector<int32_t> nodes;
+    std::vector<int4> boxes((size_t)n);
+    std::vector<float> inv_vc((size_t)n);
+    std::vector<uint64_t> keys((size_t)n);
+    int64_t covered = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int lv = d->leaf_level[i];
+        const int64_t span = (int64_t)1 << (lmax - lv);
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = d->leaf_ijk[3 * i + a];
+            if (c[a] < 0 || (c[a] + 1) * span > fine[a])
+                return fail(DARTRAY_E_INVALID, "leaf outside the root block");
+        }
+        if (!(d->rho[i] >= 0.f) || !std::isfinite(d->rho[i])) return fail(DARTRAY_E_INVALID, "rho must be finite and >= 0");
+        for (int l = 0; l < nl; ++l) {
+            const float e = d->emis[(int64_t)l * n + i];
+            if (!(e >= 0.f) || !std::isfinite(e)) return fail(DARTRAY_E_INVALID, "emis must be finite and >= 0");
+        }
+        boxes[i] = make_int4((int)(c[0] * span), (int)(c[1] * span), (int)(c[2] * span), (int)span);
+        const double side = d->root_size / (double)((int64_t)1 << lv);
+        inv_vc[i] = (float)(1.0 / (side * side * side * d->c_light));
+        keys[i] = spread3((uint64_t)(c[0] * span)) | (spread3((uint64_t)(c[1] * span)) << 1) |
+                  (spread3((uint64_t)(c[2] * span)) << 2);
+        covered += span * span * span;
+        // insert into the locator; a slot is an index into root_tab (in_nodes
+        // false) or into nodes (true), so it survives reallocation of nodes
+        const int64_t root = ((c[2] >> lv) * d->nroot[1] + (c[1] >> lv)) * d->nroot[0] + (c[0] >> lv);
+        bool in_nodes = false;
+        size_t slot = (size_t)root;
+        auto at = [&](void) -> int32_t & { return in_nodes ? nodes[slot] : root_tab[slot]; };
+        for (int lev = 0; lev < lv; ++lev) {
+            int32_t code = at();
+            if (code == kUnset) {
+                code = (int32_t)(nodes.size() / 8);
+                at() = code;
+                nodes.resize(nodes.size() + 8, kUnset);
+            } else if (code < 0) {
+                return fail(DARTRAY_E_INVALID, "leaves overlap");
+            }
+            const int bit = lv - lev - 1;
+            const int oct = (int)(((c[0] >> bit) & 1) | (((c[1] >> bit) & 1) << 1) | (((c[2] >> bit) & 1) << 2));
+            in_nodes = true;
+            slot = (size_t)code * 8 + oct;
+        }
+        if (at() != kUnset) return fail(DARTRAY_E_INVALID, "leaves overlap");
+        at() = -(int32_t)i - 1;
+    }
+    if (covered != fine[0] * fine[1] * fine[2]) return fail(DARTRAY_E_INVALID, "leaves do not tile the root block");
+    for (int32_t v : root_tab)
+        if (v == kUnset) return fail(DARTRAY_E_INVALID, "leaves do not tile the root block");
+    for (int32_t v : nodes)
+        if (v == kUnset) return fail(DARTRAY_E_INVALID, "leaves do not tile the root block");
+
+    std::vector<int32_t> morton((size_t)n);
+    for (int64_t i = 0; i < n; ++i) morton[i] = (int32_t)i;
+    std::stable_sort(morton.begin(), morton.end(), [&](int32_t a, int32_t b) { return keys[a] < keys[b]; });
+
+    LambdaTable lt{};
+    lt.n_lambda = nl;
+    lt.s_off[0] = 0;
+    lt.w_off[0] = 0;
+    for (int l = 0; l < nl; ++l) {
+        lt.kappa[l] = d->kappa[l];
+        lt.albedo[l] = d->albedo[l];
+        lt.g[l] = d->g[l];
+        int ns = d->nside_sca[l];
+        if (ns == 0) ns = nside_from_rule(d->g[l], d->n_fwhm, d->k_max);
+        lt.nside_sca[l] = ns;
+        lt.npix[l] = 12 * ns * ns;
+        lt.s_off[l + 1] = lt.s_off[l] + n * (int64_t)lt.npix[l];
+        lt.w_off[l + 1] = lt.w_off[l] + lt.npix[l];
+    }
+
+    std::vector<float> emis_lum((size_t)(nl * n));
+    for (int l = 0; l < nl; ++l)
+        for (int64_t i = 0; i < n; ++i) {
+            const double side = d->root_size / (double)((int64_t)1 << d->leaf_level[i]);
+            emis_lum[(size_t)(l * n + i)] = (float)(4.0 * kPi * (double)d->emis[(int64_t)l * n + i] * side * side * side);
+        }
+
+    // --- device side ------------------------------------------------------
+    dartray_grid *h = new dartray_grid();
+    Grid &g = h->g;
+    g.n = n;
+    g.n_lambda = nl;
+    for (int a = 0; a < 3; ++a) {
+        g.nroot[a] = d->nroot[a];
+        g.fine[a] = (int32_t)fine[a];
+        g.lo[a] = d->lo[a];
+    }
+    g.max_level = lmax;
+    g.root_size = d->root_size;
+    g.h_fine = d->root_size / (double)((int64_t)1 << lmax);
+    g.c_light = d->c_light;
+    g.uniform = (lmax == 0);
+    g.n_internal = (int64_t)(nodes.size() / 8);
+    g.lt = lt;
+    g.s_size = lt.s_off[nl];
+    g.w_row = lt.w_off[nl];
+    g.stream = (hipStream_t)stream;
+
+    const size_t nray_fixed = 12 * (size_t)kMaxNsideFixed * kMaxNsideFixed;
+    const size_t nray_w = 12 * (size_t)kMaxNsideWTable * kMaxNsideWTable;
+    // direction-binned work array: all 768 Nside-8 directions when they fit
+    // in 8 GiB, else as many as fit
+    const size_t per_dir = (size_t)nl * (size_t)n;
+    size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, ((size_t)8 << 30) / (4 * per_dir)));
+    int rcs[] = {
+        dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
+        dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
+        dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.d_lt, 1),
+        dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
+        dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
+        dalloc(g, &g.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
+        dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dirs, nray_fixed),
+        dalloc(g, &g.wtab, nray_w * (size_t)g.w_row),
+    };
+    for (int r : rcs)
+        if (r) {
+            std::string msg = g_last_error;
+            free_grid(g);
+            delete h;
+            return fail(DARTRAY_E_OOM, msg);
+        }
+    g.ubar_floats = nb_cap * per_dir;
+    hipStream_t s = g.stream;
+    hipError_t e = hipSuccess;
+    std::vector<float> rho_f(d->rho, d->rho + n);
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    cp(g.leaf_box, boxes.data(), sizeof(int4) * n);
+    cp(g.rho, rho_f.data(), sizeof(float) * n);
+    cp(g.inv_vc, inv_vc.data(), sizeof(float) * n);
+    cp(g.emis_lum, emis_lum.data(), sizeof(float) * nl * n);
+    cp(g.root_tab, root_tab.data(), sizeof(int32_t) * nroot);
+    cp(g.nodes, nodes.data(), sizeof(int32_t) * nodes.size());
+    cp(g.morton, morton.data(), sizeof(int32_t) * n);
+    cp(g.d_lt, &lt, sizeof(LambdaTable));
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors go out of scope
+    if (e != hipSuccess) {
+        int r = hip_fail(e, "grid upload");
+        free_grid(g);
+        delete h;
+        return r;
+    }
+    *out = h;
+    return DARTRAY_OK;
+}
+
+int dartray_grid_info(const dartray_grid *grid, int64_t *n_leaves, int32_t *n_lambda, int64_t *s_size)
+{
+    if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
+    if (n_leaves) *n_leaves = grid->g.n;
+    if (n_lambda) *n_lambda = grid->g.n_lambda;
+    if (s_size) *s_size = grid->g.s_size;
+    return DARTRAY_OK;
+}
+
+int dartray_nside_sca(const dartray_grid *grid, int32_t l, int32_t *nside)
+{
+    if (!grid || !nside) return fail(DARTRAY_E_INVALID, "null argument");
+    if (l < 0 || l >= grid->g.n_lambda) return fail(DARTRAY_E_INVALID, "wavelength index out of range");
+    *nside = grid->g.lt.nside_sca[l];
+    return DARTRAY_OK;
+}
+
+int64_t dartray_s_offset(const dartray_grid *grid, int32_t l)
+{
+    if (!grid || l < 0 || l > grid->g.n_lambda) return -1;
+    return grid->g.lt.s_off[l];
+}
+
+int dartray_profile_enable(dartray_grid *grid, int32_t enable)
+{
+    if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
+    grid->g.prof = enable != 0;
+    grid->g.ev_used = 0;
+    return DARTRAY_OK;
+}
+
+int dartray_profile_read(dartray_grid *grid, double *march_ms, int64_t *launches)
+{
+    if (!grid || !march_ms || !launches) return fail(DARTRAY_E_INVALID, "null argument");
+    Grid &g = grid->g;
+    DR_HIP(hipStreamSynchronize(g.stream));
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < g.ev_used; i += 2) {
+        float ms = 0.f;
+        DR_HIP(hipEventElapsedTime(&ms, g.ev_pool[i], g.ev_pool[i + 1]));
+        total += ms;
+    }
+    *march_ms = total;
+    *launches = (int64_t)(g.ev_used / 2);
+    return DARTRAY_OK;
+}
+
+int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes)
+{
+    if (!grid || !bytes) return fail(DARTRAY_E_INVALID, "null argument");
+    *bytes = grid->g.bytes;
+    return DARTRAY_OK;
+}
+
+int dartray_grid_set_rho(dartray_grid *grid, const float *rho_device)
+{
+    if (!grid || !rho_device) return fail(DARTRAY_E_INVALID, "null argument");
+    Grid &g = grid->g;
+    DR_HIP(hipMemcpyAsync(g.rho, rho_device, sizeof(float) * g.n, hipMemcpyDeviceToDevice, g.stream));
+    return DARTRAY_OK;
+}
+
+int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *origin, const double *dir,
+                            int32_t max_cross, int64_t *cells, float *lengths, int32_t *counts)
+{
+    if (!grid || !origin || !dir || !cells || !lengths || !counts || n_rays <= 0 || max_cross <= 0)
+        return fail(DARTRAY_E_INVALID, "bad argument");
+    Grid &g = grid->g;
+    // origins and directions in fine-cell units
+    std::vector<double> o((size_t)3 * n_rays), dd((size_t)3 * n_rays);
+    for (int i = 0; i < n_rays; ++i) {
+        double nrm = 0.0;
+        for (int a = 0; a < 3; ++a) nrm += dir[3 * i + a] * dir[3 * i + a];
+        if (!(nrm > 0.0)) return fail(DARTRAY_E_INVALID, "zero direction");
+        for (int a = 0; a < 3; ++a) {
+            o[3 * i + a] = (origin[3 * i + a] - g.lo[a]) / g.h_fine;
+            dd[3 * i + a] = dir[3 * i + a] / std::sqrt(nrm);
+        }
+    }
+    double *d_o = nullptr, *d_d = nullptr;
+    int64_t *d_c = nullptr;
+    float *d_l = nullptr;
+    int32_t *d_n = nullptr;
+    const size_t tot = (size_t)n_rays * max_cross;
+    hipError_t e = hipMalloc((void **)&d_o, sizeof(double) * 3 * n_rays);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_d, sizeof(double) * 3 * n_rays);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_c, sizeof(int64_t) * tot);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_l, sizeof(float) * tot);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_n, sizeof(int32_t) * n_rays);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_o, o.data(), sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice, g.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_d, dd.data(), sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice, g.stream);
+    if (e == hipSuccess) {
+        Geo geo{g.leaf_box, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]},
+                {g.nroot[0], g.nroot[1], g.nroot[2]}, g.max_level};
+        hipLaunchKernelGGL(k_debug_cells, dim3((n_rays + 63) / 64), dim3(64), 0, g.stream, geo, n_rays, d_o, d_d,
+                           max_cross, d_c, d_l, d_n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(cells, d_c, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, g.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(lengths, d_l, sizeof(float) * tot, hipMemcpyDeviceToHost, g.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(counts, d_n, sizeof(int32_t) * n_rays, hipMemcpyDeviceToHost, g.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
+    (void)hipFree(d_o);
+    (void)hipFree(d_d);
+    (void)hipFree(d_c);
+    (void)hipFree(d_l);
+    (void)hipFree(d_n);
+    if (e != hipSuccess) return hip_fail(e, "debug_ray_cells");
+    for (size_t i = 0; i < tot; ++i) lengths[i] = (float)(lengths[i] * g.h_fine);
+    return DARTRAY_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Pass driver
+// ---------------------------------------------------------------------------
+
+namespace dr {
+
+static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_fields *f, bool scatter)
+{
+    if (!o || !f) return fail(DARTRAY_E_INVALID, "null opts or fields");
+    if (o->nside <= 0 || (o->nside & (o->nside - 1))) return fail(DARTRAY_E_INVALID, "nside must be a power of two");
+    if (!scatter && o->mode != DARTRAY_MODE_STEP1 && o->mode != DARTRAY_MODE_DIRECT)
+        return fail(DARTRAY_E_INVALID, "unknown mode");
+    if (o->max_steps < 0) return fail(DARTRAY_E_INVALID, "max_steps must be >= 0");
+    if (!f->tally) return fail(DARTRAY_E_INVALID, "tally buffer required");
+    const bool step1 = !scatter && o->mode == DARTRAY_MODE_STEP1;
+    if (step1) {
+        if (!o->adaptive) return fail(DARTRAY_E_INVALID, "step 1 needs adaptive rays");
+        if (!f->U_LL) return fail(DARTRAY_E_INVALID, "step 1 writes U_LL");
+    } else {
+        if (!f->U || !f->S_total || !f->S_pending || !f->S_next) return fail(DARTRAY_E_INVALID, "U and S buffers required");
+        if (o->adaptive && !f->U_LL) return fail(DARTRAY_E_INVALID, "adaptive passes need U_LL");
+    }
+    if (o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays are not available in this build");
+    if (o->nside > kMaxNsideFixed) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 64");
+    if ((f->counters == nullptr) && (o->flags & DARTRAY_FLAG_COUNTERS))
+        return fail(DARTRAY_E_INVALID, "counters buffer required by DARTRAY_FLAG_COUNTERS");
+    if (scatter && !g.have_s1) return fail(DARTRAY_E_STATE, "scatter_iter needs a prior direct pass");
+    return DARTRAY_OK;
+}
+
+static void frame_of(const dartray_trace_opts *o, Frame &f)
+{
+    bool zero = true;
+    for (int i = 0; i < 9; ++i) {
+        f.R[i] = o->frame[i];
+        zero &= o->frame[i] == 0.0;
+    }
+    if (zero)
+        for (int i = 0; i < 9; ++i) f.R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+}
+
+static int ensure_tables(Grid &g, int nside, const Frame &f, bool need_w)
+{
+    const bool same_frame = std::memcmp(g.dirs_frame, f.R, sizeof(f.R)) == 0;
+    const int64_t nray = 12 * (int64_t)nside * nside;
+    if (!(g.dirs_valid && g.dirs_nside == nside && same_frame)) {
+        hipLaunchKernelGGL(k_dirs, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, g.stream, g.dirs, nside, nray, f);
+        DR_LAUNCH_CHECK("k_dirs");
+        g.dirs_valid = true;
+        g.dirs_nside = nside;
+        g.wtab_valid = false;
+        std::memcpy(g.dirs_frame, f.R, sizeof(f.R));
+    }
+    if (need_w && !(g.wtab_valid && g.wtab_nside == nside)) {
+        if (nside > kMaxNsideWTable) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 16 with scattering");
+        const int64_t tot = nray * g.n_lambda;
+        hipLaunchKernelGGL(k_wtab, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, g.stream, g.wtab, g.d_lt, nside,
+                           nray, g.w_row, f);
+        DR_LAUNCH_CHECK("k_wtab");
+        g.wtab_valid = true;
+        g.wtab_nside = nside;
+    }
+    return DARTRAY_OK;
+}
+
+static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fields *f, bool scatter)
+{
+    const int64_t n = g.n;
+    const unsigned nblk = (unsigned)((n + kScanBlock - 1) / kScanBlock);
+    hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, g.morton,
+                       n, g.d_lt, g.emis_lum, scatter ? f->S_pending : nullptr, scatter ? nullptr : o->source_mask,
+                       scatter ? 1 : 0, f->tally);
+    DR_LAUNCH_CHECK("k_source_flags");
+    hipLaunchKernelGGL(k_scan_count, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, n, g.scan_blocks);
+    DR_LAUNCH_CHECK("k_scan_count");
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, g.stream, g.scan_blocks, (int64_t)nblk, g.n_src);
+    DR_LAUNCH_CHECK("k_scan_blocks");
+    hipLaunchKernelGGL(k_scan_scatter, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, g.morton, n,
+                       g.scan_blocks, g.src_list);
+    DR_LAUNCH_CHECK("k_scan_scatter");
+    return DARTRAY_OK;
+}
+
+// record a timing event on the grid's stream (profiling only)
+static int prof_mark(Grid &g)
+{
+    if (!g.prof) return DARTRAY_OK;
+    if (g.ev_used == g.ev_pool.size()) {
+        hipEvent_t e;
+        DR_HIP(hipEventCreate(&e));
+        g.ev_pool.push_back(e);
+    }
+    DR_HIP(hipEventRecord(g.ev_pool[g.ev_used++], g.stream));
+    return DARTRAY_OK;
+}
+
+template <int NL>
+static void launch_fixed(const FixedArgs &A, bool uniform, hipStream_t s, unsigned blocks)
+{
+    if (uniform) hipLaunchKernelGGL((k_march_fixed<NL, true>), dim3(blocks), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL((k_march_fixed<NL, false>), dim3(blocks), dim3(256), 0, s, A);
+}
+
+static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+{
+    const int nl = g.n_lambda;
+    const int64_t n = g.n;
+    Frame fr;
+    frame_of(o, fr);
+    int rc = ensure_tables(g, o->nside, fr, true);
+    if (rc) return rc;
+    const int64_t nray = 12 * (int64_t)o->nside * o->nside;
+    int log2n = 0;
+    while ((1 << log2n) < o->nside) ++log2n;
+
+    if ((rc = fill<float>(g, g.U_k, (size_t)nl * n, 0.f))) return rc;
+    if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
+    if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
+    if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
+    if ((rc = select_sources(g, o, f, scatter))) return rc;
+
+    const size_t per_dir = (size_t)nl * n;
+    const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
+    FixedArgs A{};
+    A.geo = Geo{g.leaf_box, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
+                g.max_level};
+    A.src_list = g.src_list;
+    A.n_src = g.n_src;
+    A.dirs = g.dirs;
+    A.rho = g.rho;
+    A.inv_vc = g.inv_vc;
+    A.emis_lum = g.emis_lum;
+    A.S_pending = f->S_pending;
+    A.lt = g.d_lt;
+    A.ubar = g.ubar;
+    A.tally = f->tally;
+    A.counters = (o->flags & DARTRAY_FLAG_COUNTERS) ? f->counters : nullptr;
+    A.n = n;
+    A.scatter = scatter ? 1 : 0;
+    A.nside_ray = o->nside;
+    A.log2_nside_ray = log2n;
+    A.inv_nray = (float)(1.0 / (double)nray);
+    A.h_fine = (float)g.h_fine;
+    A.max_steps = o->max_steps;
+    A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
+    const unsigned march_blocks = 2048;
+    for (int64_t r0 = 0; r0 < nray; r0 += nb_max) {
+        const int nb = (int)std::min<int64_t>(nb_max, nray - r0);
+        A.r0 = (int)r0;
+        A.nb = nb;
+        if ((rc = fill<float>(g, g.ubar, (size_t)nb * per_dir, 0.f))) return rc;
+        if ((rc = prof_mark(g))) return rc;
+        if (nl <= 1) launch_fixed<1>(A, g.uniform, g.stream, march_blocks);
+        else if (nl <= 4) launch_fixed<4>(A, g.uniform, g.stream, march_blocks);
+        else if (nl <= 8) launch_fixed<8>(A, g.uniform, g.stream, march_blocks);
+        else if (nl <= 16) launch_fixed<16>(A, g.uniform, g.stream, march_blocks);
+        else if (nl <= 32) launch_fixed<32>(A, g.uniform, g.stream, march_blocks);
+        else launch_fixed<64>(A, g.uniform, g.stream, march_blocks);
+        DR_LAUNCH_CHECK("k_march_fixed");
+        if ((rc = prof_mark(g))) return rc;
+        // flush: pixel chunks of 12 or 48
+        int min_npix = 1 << 30;
+        for (int l = 0; l < nl; ++l) min_npix = std::min(min_npix, g.lt.npix[l]);
+        int max_npix = 0;
+        for (int l = 0; l < nl; ++l) max_npix = std::max(max_npix, g.lt.npix[l]);
+        const unsigned cx = (unsigned)((n + 255) / 256);
+        if (min_npix % 48 == 0) {
+            hipLaunchKernelGGL(k_flush_fixed<48>, dim3(cx, max_npix / 48, nl), dim3(256), 0, g.stream, g.ubar, g.wtab,
+                               g.d_lt, g.rho, g.inv_vc, n, (int)r0, nb, g.w_row, g.U_k, f->S_next);
+        } else {
+            hipLaunchKernelGGL(k_flush_fixed<12>, dim3(cx, max_npix / 12, nl), dim3(256), 0, g.stream, g.ubar, g.wtab,
+                               g.d_lt, g.rho, g.inv_vc, n, (int)r0, nb, g.w_row, g.U_k, f->S_next);
+        }
+        DR_LAUNCH_CHECK("k_flush_fixed");
+    }
+    return DARTRAY_OK;
+}
+
+static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+{
+    const int nl = g.n_lambda;
+    const int64_t n = g.n;
+    const bool step1 = !scatter && o->mode == DARTRAY_MODE_STEP1;
+    hipLaunchKernelGGL(k_finish_u, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024), nl), dim3(256), 0,
+                       g.stream, g.U_k, f->U, f->U_pass, f->U_LL, o->adaptive ? 1 : 0, step1 ? 1 : 0, g.d_lt, g.rho,
+                       g.inv_vc, n, f->tally);
+    DR_LAUNCH_CHECK("k_finish_u");
+    if (step1) return DARTRAY_OK;
+    int rc;
+    double *ssum = g.dsum;
+    if ((rc = fill<double>(g, ssum, (size_t)nl, 0.0))) return rc;
+    hipLaunchKernelGGL(k_finish_s, dim3(1024, nl), dim3(256), 0, g.stream, f->S_next, f->S_total, f->S_pending,
+                       scatter ? 1 : 0, g.d_lt, g.s_size, ssum);
+    DR_LAUNCH_CHECK("k_finish_s");
+    if (!scatter) {
+        DR_HIP(hipMemcpyAsync(g.s1_sum, ssum, sizeof(double) * nl, hipMemcpyDeviceToDevice, g.stream));
+        g.have_s1 = true;
+    }
+    return DARTRAY_OK;
+}
+
+}  // namespace dr
+
+extern "C" {
+
+int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields)
+{
+    if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
+    Grid &g = grid->g;
+    int rc = check_opts(g, opts, fields, false);
+    if (rc) return rc;
+    if ((rc = run_fixed_pass(g, opts, fields, false))) return rc;
+    return finish_pass(g, opts, fields, false);
+}
+
+int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields, double *r_k)
+{
+    if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
+    Grid &g = grid->g;
+    int rc = check_opts(g, opts, fields, true);
+    if (rc) return rc;
+    if ((rc = run_fixed_pass(g, opts, fields, true))) return rc;
+    if ((rc = finish_pass(g, opts, fields, true))) return rc;
+    if (r_k) {
+        const int nl = g.n_lambda;
+        double a[kMaxLambda], b[kMaxLambda];
+        DR_HIP(hipMemcpyAsync(a, g.dsum, sizeof(double) * nl, hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipMemcpyAsync(b, g.s1_sum, sizeof(double) * nl, hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipStreamSynchronize(g.stream));
+        double sa = 0.0, sb = 0.0;
+        for (int l = 0; l < nl; ++l) {
+            sa += a[l];
+            sb += b[l];
+        }
+        *r_k = sb > 0.0 ? sa / sb : 0.0;
+    }
+    return DARTRAY_OK;
+}
+
+int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, const dartray_fields *fwd,
+                          const float *dJ_dU, const float *dJ_dj, const float *dJ_desc, float *dJ_drho)
+{
+    (void)opts;
+    (void)fwd;
+    (void)dJ_dU;
+    (void)dJ_dj;
+    (void)dJ_desc;
+    (void)dJ_drho;
+    if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
+    return fail(DARTRAY_E_UNSUPPORTED, "the adjoint march is not available in this build");
+}
+
+}  // extern "C"

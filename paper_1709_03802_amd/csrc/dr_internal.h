@@ -1,0 +1,164 @@
+// Internal declarations of the gfx950 ray-march library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "dartray.h"
+
+namespace dr {
+
+constexpr int kWave = 64;                 // CDNA wavefront width
+constexpr int kMaxLambda = 64;            // wavelengths per grid
+constexpr int kMaxNsideFixed = 64;        // fixed-mode ray Nside with tabulated directions
+constexpr int kMaxNsideWTable = 16;       // fixed-mode ray Nside with a tabulated phase table
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-wavelength constants used by every kernel (constant memory image).
+struct LambdaTable {
+    int32_t n_lambda;
+    int32_t pad;
+    float kappa[kMaxLambda];
+    float albedo[kMaxLambda];
+    float g[kMaxLambda];
+    int32_t nside_sca[kMaxLambda];
+    int32_t npix[kMaxLambda];
+    int64_t s_off[kMaxLambda + 1];        // start of wavelength block l in S
+    int32_t w_off[kMaxLambda + 1];        // start of wavelength l in a per-direction weight row
+};
+
+struct Grid {
+    // geometry
+    int64_t n = 0;
+    int32_t n_lambda = 0;
+    int32_t nroot[3] = {0, 0, 0};
+    int32_t max_level = 0;
+    int32_t fine[3] = {0, 0, 0};          // finest-level cells per axis
+    double lo[3] = {0, 0, 0};
+    double root_size = 0;
+    double h_fine = 0;                    // physical edge of a finest-level cell
+    double c_light = 1;
+    bool uniform = true;                  // no refinement anywhere
+    int64_t n_internal = 0;
+    LambdaTable lt{};
+    int64_t s_size = 0;
+    int32_t w_row = 0;                    // sum over wavelengths of npix
+
+    hipStream_t stream = nullptr;
+
+    // device arrays owned by the handle
+    int4 *leaf_box = nullptr;             // lower corner in fine units + span
+    float *rho = nullptr;
+    float *inv_vc = nullptr;              // 1 / (V c)
+    float *emis_lum = nullptr;            // [nl][n] 4 pi j V
+    int32_t *root_tab = nullptr;          // root cell -> node code
+    int32_t *nodes = nullptr;             // [8 * n_internal] child codes
+    int32_t *morton = nullptr;            // leaves in Morton order
+    LambdaTable *d_lt = nullptr;
+
+    // work arrays
+    float *U_k = nullptr;                 // [nl][n]
+    int32_t *flags = nullptr;             // [n] source flags, then scan
+    int32_t *src_list = nullptr;          // [n] compacted sources
+    int32_t *scan_blocks = nullptr;       // block sums
+    int32_t *n_src = nullptr;             // [1]
+    double *dsum = nullptr;               // [4 * kMaxLambda] FP64 scratch sums
+    double *s1_sum = nullptr;             // [kMaxLambda] sum of S after the direct pass
+    bool have_s1 = false;
+    float *ubar = nullptr;                // direction-binned energy density (fixed mode)
+    size_t ubar_floats = 0;
+    float4 *dirs = nullptr;               // fixed-mode direction table
+    float *wtab = nullptr;                // fixed-mode phase weights [r][w_row]
+    int32_t dirs_nside = 0;
+    double dirs_frame[9] = {0};
+    bool dirs_valid = false;
+    int32_t wtab_nside = 0;
+    bool wtab_valid = false;
+
+    size_t bytes = 0;
+
+    // march-kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+};
+
+// error handling
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+}  // namespace dr
+
+struct dartray_grid {
+    dr::Grid g;
+};
+
+// ---------------------------------------------------------------------------
+// HEALPix nested pixel centres (Gorski et al. 2005), device and host.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline uint32_t dr_compact_bits(uint64_t v)
+{
+    // gather the even bits of v into the low half
+    v &= 0x5555555555555555ull;
+    v = (v | (v >> 1)) & 0x3333333333333333ull;
+    v = (v | (v >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v >> 4)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v >> 8)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)v;
+}
+
+// Centre of nested pixel `pix` at resolution `nside`, as (z, phi).
+__host__ __device__ inline void dr_pix_zphi(int64_t nside, int64_t pix, double *z_out, double *phi_out)
+{
+    // base pixels are numbered 0..11: four around the north pole, four on
+    // the equator, four around the south pole
+    const int64_t npf = nside * nside;
+    const int face = (int)(pix / npf);
+    const uint64_t in_face = (uint64_t)(pix - (int64_t)face * npf);
+    const int64_t x = dr_compact_bits(in_face);
+    const int64_t y = dr_compact_bits(in_face >> 1);
+    const int row = face >> 2;                       // 0 north, 1 equator, 2 south
+    const int col = face & 3;
+    // ring index counted from the north pole: the face's south vertex lies on
+    // ring (row + 2) * nside
+    const int64_t ring = (int64_t)(row + 2) * nside - x - y - 1;
+    int64_t q;                                       // pixels per quarter ring
+    double z;
+    int64_t half_shift;                              // 1 when the ring starts half a pixel later
+    if (ring < nside) {
+        q = ring;
+        z = 1.0 - (double)(q * q) / (3.0 * (double)npf);
+        half_shift = 0;
+    } else if (ring > 3 * nside) {
+        q = 4 * nside - ring;
+        z = (double)(q * q) / (3.0 * (double)npf) - 1.0;
+        half_shift = 0;
+    } else {
+        q = nside;
+        z = 2.0 * (double)(2 * nside - ring) / (3.0 * (double)nside);
+        half_shift = (ring - nside) & 1;
+    }
+    // longitude of the face centre in units of half a quarter-ring pixel
+    const int64_t face_phi = (row == 1) ? 2 * col : 2 * col + 1;
+    int64_t j = (face_phi * q + x - y + 1 + half_shift) / 2;   // 1-based position in the ring
+    if (j > 4 * q) j -= 4 * q;
+    if (j < 1) j += 4 * q;
+    *z_out = z;
+    *phi_out = ((double)j - 0.5 * (double)(1 + half_shift)) * (0.5 * dr::kPi) / (double)q;
+}
+
+__host__ __device__ inline void dr_pix_vec(int64_t nside, int64_t pix, const double *R, double v[3])
+{
+    double z, phi;
+    dr_pix_zphi(nside, pix, &z, &phi);
+    const double st = sqrt((1.0 - z) * (1.0 + z));
+    const double a[3] = {st * cos(phi), st * sin(phi), z};
+    for (int i = 0; i < 3; ++i) v[i] = R[3 * i] * a[0] + R[3 * i + 1] * a[1] + R[3 * i + 2] * a[2];
+}

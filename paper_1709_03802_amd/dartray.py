@@ -1,0 +1,341 @@
+"""Python binding of the gfx950 ray-march library (``libdartray.so``).
+
+Argument marshalling only: every step of a pass runs in the library's HIP
+kernels.  torch provides device memory and the stream.  Entry points mirror the
+C ABI declared in ``include/dartray.h``:
+
+    Grid(...)                 -> dartray_grid_create / dartray_grid_destroy
+    trace_direct(...)         -> dartray_trace_direct
+    scatter_iter(...)         -> dartray_scatter_iter
+    trace_adjoint(...)        -> dartray_trace_adjoint
+    debug_ray_cells(...)      -> dartray_debug_ray_cells
+
+``run()`` chains the passes in the order of the paper's algorithm (Sect. 2):
+optional step 1, the direct-light pass, then the scattering iterations.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdartray.so")
+
+OK, E_INVALID, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+MODE_STEP1, MODE_DIRECT = 0, 1
+FLAG_COUNTERS = 1
+T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
+C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)
+
+EXPORTS = [
+    "dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
+    "dartray_s_offset", "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter",
+    "dartray_trace_adjoint", "dartray_debug_ray_cells", "dartray_workspace_bytes",
+    "dartray_last_error", "dartray_version", "dartray_profile_enable", "dartray_profile_read",
+]
+
+
+class DartRayError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dartray status {code}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("nroot", C.c_int32 * 3),
+        ("lo", C.c_double * 3),
+        ("root_size", C.c_double),
+        ("n_leaves", C.c_int64),
+        ("leaf_level", C.POINTER(C.c_int32)),
+        ("leaf_ijk", C.POINTER(C.c_int64)),
+        ("rho", C.POINTER(C.c_float)),
+        ("emis", C.POINTER(C.c_float)),
+        ("n_lambda", C.c_int32),
+        ("kappa", C.POINTER(C.c_float)),
+        ("albedo", C.POINTER(C.c_float)),
+        ("g", C.POINTER(C.c_float)),
+        ("nside_sca", C.POINTER(C.c_int32)),
+        ("n_fwhm", C.c_double),
+        ("k_max", C.c_int32),
+        ("c_light", C.c_double),
+    ]
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32),
+        ("adaptive", C.c_int32),
+        ("nside", C.c_int32),
+        ("nside_max", C.c_int32),
+        ("n_rays_min", C.c_float),
+        ("f_U", C.c_float),
+        ("a_RT", C.c_float),
+        ("r_pre", C.c_float),
+        ("frame", C.c_double * 9),
+        ("source_mask", C.c_void_p),
+        ("flags", C.c_uint32),
+        ("max_steps", C.c_int64),
+    ]
+
+
+class FieldsC(C.Structure):
+    _fields_ = [
+        ("U", C.c_void_p),
+        ("U_LL", C.c_void_p),
+        ("U_pass", C.c_void_p),
+        ("S_total", C.c_void_p),
+        ("S_pending", C.c_void_p),
+        ("S_next", C.c_void_p),
+        ("tally", C.c_void_p),
+        ("counters", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libdartray.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1709_03802_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    L.dartray_grid_create.argtypes = [C.POINTER(GridDesc), C.c_void_p, C.POINTER(C.c_void_p)]
+    L.dartray_grid_destroy.argtypes = [C.c_void_p]
+    L.dartray_grid_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+    L.dartray_nside_sca.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+    L.dartray_s_offset.argtypes = [C.c_void_p, C.c_int32]
+    L.dartray_s_offset.restype = C.c_int64
+    L.dartray_grid_set_rho.argtypes = [C.c_void_p, C.c_void_p]
+    L.dartray_trace_direct.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC)]
+    L.dartray_scatter_iter.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.POINTER(C.c_double)]
+    L.dartray_trace_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
+    L.dartray_debug_ray_cells.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_float),
+                                          C.POINTER(C.c_int32)]
+    L.dartray_workspace_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    L.dartray_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+    L.dartray_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.dartray_last_error.restype = C.c_char_p
+    L.dartray_version.restype = C.c_char_p
+    for name in ("dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
+                 "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter", "dartray_trace_adjoint",
+                 "dartray_debug_ray_cells", "dartray_workspace_bytes", "dartray_profile_enable",
+                 "dartray_profile_read"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        msg = load_library().dartray_last_error().decode(errors="replace")
+        raise DartRayError(rc, msg)
+
+
+def version() -> str:
+    return load_library().dartray_version().decode()
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Grid:
+    """Device-side grid built from a ``workloads.Grid``."""
+
+    def __init__(self, grid, stream=None):
+        import torch
+        L = load_library()
+        self.src = grid
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        keep = dict(
+            level=np.ascontiguousarray(grid.level, dtype=np.int32),
+            ijk=np.ascontiguousarray(grid.ijk, dtype=np.int64),
+            rho=np.ascontiguousarray(grid.rho, dtype=np.float32),
+            emis=np.ascontiguousarray(grid.emis, dtype=np.float32),
+            kappa=np.ascontiguousarray(grid.kappa, dtype=np.float32),
+            albedo=np.ascontiguousarray(grid.albedo, dtype=np.float32),
+            g=np.ascontiguousarray(grid.g, dtype=np.float32),
+            nside_sca=np.ascontiguousarray(grid.nside_sca, dtype=np.int32),
+        )
+        d = GridDesc()
+        d.nroot = (C.c_int32 * 3)(*[int(x) for x in grid.nroot])
+        d.lo = (C.c_double * 3)(*[float(x) for x in grid.lo])
+        d.root_size = float(grid.root_size)
+        d.n_leaves = int(grid.n)
+        d.leaf_level = _ptr(keep["level"], C.c_int32)
+        d.leaf_ijk = _ptr(keep["ijk"], C.c_int64)
+        d.rho = _ptr(keep["rho"], C.c_float)
+        d.emis = _ptr(keep["emis"], C.c_float)
+        d.n_lambda = int(grid.n_lambda)
+        d.kappa = _ptr(keep["kappa"], C.c_float)
+        d.albedo = _ptr(keep["albedo"], C.c_float)
+        d.g = _ptr(keep["g"], C.c_float)
+        d.nside_sca = _ptr(keep["nside_sca"], C.c_int32)
+        d.n_fwhm = float(grid.n_fwhm)
+        d.k_max = int(grid.k_max)
+        d.c_light = float(grid.c_light)
+        h = C.c_void_p()
+        _check(L.dartray_grid_create(C.byref(d), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        n = C.c_int64()
+        nl = C.c_int32()
+        ss = C.c_int64()
+        _check(L.dartray_grid_info(h, C.byref(n), C.byref(nl), C.byref(ss)))
+        self.n, self.nl, self.s_size = n.value, nl.value, ss.value
+        self.nside_sca = []
+        for l in range(self.nl):
+            v = C.c_int32()
+            _check(L.dartray_nside_sca(h, l, C.byref(v)))
+            self.nside_sca.append(v.value)
+        self.s_offset = [int(L.dartray_s_offset(h, l)) for l in range(self.nl + 1)]
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.dartray_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def npix(self, l):
+        return 12 * self.nside_sca[l] ** 2
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(load_library().dartray_workspace_bytes(self.h, C.byref(b)))
+        return b.value
+
+    def profile(self, enable=True):
+        _check(load_library().dartray_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(load_library().dartray_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def set_rho(self, rho_dev):
+        _check(load_library().dartray_grid_set_rho(self.h, C.c_void_p(rho_dev.data_ptr())))
+
+
+class Fields:
+    """Caller-owned device buffers (torch tensors) of one run."""
+
+    def __init__(self, grid: Grid, keep_pass_u=False):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.U = torch.zeros((grid.nl, grid.n), **f32)
+        self.U_LL = torch.zeros((grid.nl, grid.n), **f32)
+        self.U_pass = torch.zeros((grid.nl, grid.n), **f32) if keep_pass_u else None
+        self.S_total = torch.zeros(max(grid.s_size, 1), **f32)
+        self.S_pending = torch.zeros(max(grid.s_size, 1), **f32)
+        self.S_next = torch.zeros(max(grid.s_size, 1), **f32)
+        self.tally = torch.zeros((grid.nl, 8), dtype=torch.float64, device=dev)
+        self.counters = torch.zeros(8, dtype=torch.int64, device=dev)
+
+    def c(self) -> FieldsC:
+        f = FieldsC()
+        for name in ("U", "U_LL", "U_pass", "S_total", "S_pending", "S_next", "tally", "counters"):
+            t = getattr(self, name)
+            setattr(f, name, None if t is None else t.data_ptr())
+        return f
+
+
+def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=True, max_steps=0) -> TraceOpts:
+    o = TraceOpts()
+    o.mode = mode
+    o.adaptive = 1 if policy.adaptive else 0
+    o.nside = int(policy.nside)
+    o.nside_max = int(policy.nside_max)
+    o.n_rays_min = float(policy.n_rays_min)
+    o.f_U = float(policy.f_U)
+    o.a_RT = 0.0
+    o.r_pre = float(policy.r_pre)
+    fr = np.zeros(9) if frame is None else np.asarray(frame, dtype=np.float64).ravel()
+    o.frame = (C.c_double * 9)(*fr.tolist())
+    o.source_mask = None if source_mask is None else source_mask.data_ptr()
+    o.flags = FLAG_COUNTERS if counters else 0
+    o.max_steps = int(max_steps)
+    return o
+
+
+def trace_direct(grid: Grid, opts: TraceOpts, fields: Fields):
+    fc = fields.c()
+    _check(load_library().dartray_trace_direct(grid.h, C.byref(opts), C.byref(fc)))
+
+
+def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields) -> float:
+    fc = fields.c()
+    rk = C.c_double()
+    _check(load_library().dartray_scatter_iter(grid.h, C.byref(opts), C.byref(fc), C.byref(rk)))
+    return rk.value
+
+
+def trace_adjoint(grid: Grid, opts: TraceOpts, fields: Fields, dJ_dU, dJ_drho, dJ_dj=None, dJ_desc=None):
+    fc = fields.c()
+    _check(load_library().dartray_trace_adjoint(
+        grid.h, C.byref(opts), C.byref(fc), C.c_void_p(dJ_dU.data_ptr()),
+        None if dJ_dj is None else C.c_void_p(dJ_dj.data_ptr()),
+        None if dJ_desc is None else C.c_void_p(dJ_desc.data_ptr()), C.c_void_p(dJ_drho.data_ptr())))
+
+
+def debug_ray_cells(grid: Grid, origins, dirs, max_cross=4096):
+    o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    nr = o.shape[0]
+    cells = np.zeros((nr, max_cross), dtype=np.int64)
+    lens = np.zeros((nr, max_cross), dtype=np.float32)
+    counts = np.zeros(nr, dtype=np.int32)
+    _check(load_library().dartray_debug_ray_cells(grid.h, nr, _ptr(o, C.c_double), _ptr(d, C.c_double), max_cross,
+                                                  _ptr(cells, C.c_int64), _ptr(lens, C.c_float),
+                                                  _ptr(counts, C.c_int32)))
+    return [(cells[i, :counts[i]], lens[i, :counts[i]]) for i in range(nr)]
+
+
+@dataclass
+class RunOutput:
+    fields: Fields
+    tallies: list            # per pass, numpy [nl, 8]
+    counters: list           # per pass, numpy [8]
+    r_k: list
+
+
+def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Fields] = None,
+        collect=True, passes=None) -> RunOutput:
+    """Step 1 (adaptive + step1), direct pass, scattering iterations."""
+    f = Fields(grid) if fields is None else fields
+    tallies, counters, rks = [], [], []
+    if policy.adaptive and policy.step1:
+        trace_direct(grid, make_opts(policy, MODE_STEP1, frame, source_mask), f)
+        if collect:
+            tallies.append(f.tally.cpu().numpy().copy())
+            counters.append(f.counters.cpu().numpy().copy())
+    n_pass = 1 + policy.n_scatter if passes is None else passes
+    for k in range(n_pass):
+        if k == 0:
+            trace_direct(grid, make_opts(policy, MODE_DIRECT, frame, source_mask), f)
+        else:
+            rks.append(scatter_iter(grid, make_opts(policy, MODE_DIRECT, frame), f))
+        if collect:
+            tallies.append(f.tally.cpu().numpy().copy())
+            counters.append(f.counters.cpu().numpy().copy())
+    return RunOutput(f, tallies, counters, rks)

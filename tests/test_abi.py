@@ -1,0 +1,146 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, its structs have the layout the binding assumes, and
+malformed grid descriptions are rejected before any device work."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dartray.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1709_03802_amd import dartray
+    if not os.path.exists(dartray.LIB_PATH):
+        from paper_1709_03802_amd import build
+        build.build()
+    return dartray.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|int64_t|char|const char)\s*\*?\s*(dartray_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1709_03802_amd import dartray
+    assert sorted(dartray.EXPORTS) == names
+
+
+def test_version(lib):
+    from paper_1709_03802_amd import dartray
+    assert dartray.version().startswith("dartray-gfx950")
+
+
+def test_struct_layout_matches_header(tmp_path):
+    from paper_1709_03802_amd import dartray
+    src = tmp_path / "probe.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "dartray.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(dartray_grid_desc), sizeof(dartray_trace_opts), sizeof(dartray_fields));
+  printf("%zu %zu %zu %zu\\n", offsetof(dartray_grid_desc, c_light), offsetof(dartray_trace_opts, frame),
+         offsetof(dartray_trace_opts, max_steps), offsetof(dartray_fields, counters));
+  return 0;
+}
+""")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    got = [int(x) for x in out]
+    want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC),
+            dartray.GridDesc.c_light.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
+            dartray.FieldsC.counters.offset]
+    assert got == want
+
+
+def _desc(grid):
+    from paper_1709_03802_amd import dartray
+    keep = dict(
+        level=np.ascontiguousarray(grid.level, dtype=np.int32),
+        ijk=np.ascontiguousarray(grid.ijk, dtype=np.int64),
+        rho=np.ascontiguousarray(grid.rho, dtype=np.float32),
+        emis=np.ascontiguousarray(grid.emis, dtype=np.float32),
+        kappa=np.ascontiguousarray(grid.kappa, dtype=np.float32),
+        albedo=np.ascontiguousarray(grid.albedo, dtype=np.float32),
+        g=np.ascontiguousarray(grid.g, dtype=np.float32),
+        nside_sca=np.ascontiguousarray(grid.nside_sca, dtype=np.int32),
+    )
+    d = dartray.GridDesc()
+    d.nroot = (C.c_int32 * 3)(*grid.nroot)
+    d.lo = (C.c_double * 3)(*grid.lo)
+    d.root_size = grid.root_size
+    d.n_leaves = grid.n
+    p = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+    d.leaf_level = p(keep["level"], C.c_int32)
+    d.leaf_ijk = p(keep["ijk"], C.c_int64)
+    d.rho = p(keep["rho"], C.c_float)
+    d.emis = p(keep["emis"], C.c_float)
+    d.n_lambda = grid.n_lambda
+    d.kappa = p(keep["kappa"], C.c_float)
+    d.albedo = p(keep["albedo"], C.c_float)
+    d.g = p(keep["g"], C.c_float)
+    d.nside_sca = p(keep["nside_sca"], C.c_int32)
+    d.n_fwhm = 5.0
+    d.k_max = 2
+    d.c_light = 1.0
+    return d, keep
+
+
+@pytest.mark.parametrize("breakage", ["overlap", "gap", "nan_rho", "neg_emis", "nside3", "albedo", "g1",
+                                      "zero_n", "outside", "c_light"])
+def test_malformed_descriptions_rejected_before_device_work(lib, breakage):
+    from paper_1709_03802_amd import workloads as W
+    from paper_1709_03802_amd import dartray
+    grid = W.random_octree(seed=5)
+    if breakage == "overlap":
+        grid.ijk[1] = grid.ijk[0]
+        grid.level[1] = grid.level[0]
+    elif breakage == "gap":
+        grid = grid.copy()
+        grid.level = grid.level[1:]
+        grid.ijk = grid.ijk[1:]
+        grid.rho = grid.rho[1:]
+        grid.emis = grid.emis[:, 1:]
+    elif breakage == "nan_rho":
+        grid.rho[2] = np.nan
+    elif breakage == "neg_emis":
+        grid.emis[0, 3] = -1.0
+    elif breakage == "nside3":
+        grid.nside_sca[0] = 3
+    elif breakage == "albedo":
+        grid.albedo[0] = 1.5
+    elif breakage == "g1":
+        grid.g[0] = 1.0
+    elif breakage == "outside":
+        grid.ijk[0, 0] = 10 ** 6
+    d, keep = _desc(grid)
+    if breakage == "zero_n":
+        d.n_leaves = 0
+    if breakage == "c_light":
+        d.c_light = 0.0
+    h = C.c_void_p()
+    rc = lib.dartray_grid_create(C.byref(d), None, C.byref(h))
+    assert rc == dartray.E_INVALID
+    assert h.value is None
+    assert len(lib.dartray_last_error()) > 0
+
+
+def test_null_arguments(lib):
+    from paper_1709_03802_amd import dartray
+    assert lib.dartray_grid_create(None, None, None) == dartray.E_INVALID
+    assert lib.dartray_trace_direct(None, None, None) == dartray.E_INVALID
+    assert lib.dartray_scatter_iter(None, None, None, None) == dartray.E_INVALID
+    assert lib.dartray_grid_destroy(None) == dartray.OK

@@ -1,0 +1,189 @@
+"""GPU parity of the fixed-Nside path against the FP64 oracle.
+
+Traversal: the device's cell sequences equal the oracle's, index by index, for
+rays in general position (no exact ties), on uniform grids and octrees.
+Fields: U and the scattered luminosity S after the direct pass and the
+scattering iterations match the oracle within 1e-4 relative (per element, max);
+the FP64 tallies balance within 1e-6.  Inputs are rounded to FP32 before both
+sides see them, so only arithmetic differs.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_1709_03802_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1709_03802_amd import dartray
+    dartray.load_library()
+    return dartray
+
+
+def as_f32(grid):
+    g = grid.copy()
+    for name in ("rho", "emis", "kappa", "albedo", "g"):
+        setattr(g, name, getattr(g, name).astype(np.float32).astype(np.float64))
+    return g
+
+
+def rel_err(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.abs(x - ref) / np.maximum(np.abs(ref), 1e-30)
+
+
+def compare_run(dr, orc, grid, policy, frame=None, source_mask=None, passes=None, tol=TOL, label=""):
+    import torch
+    g32 = as_f32(grid)
+    m = orc.Model(g32)
+    ref = orc.run(m, policy, frame=frame, source_mask=source_mask, passes=passes)
+    G = dr.Grid(g32)
+    mask_t = None if source_mask is None else torch.as_tensor(source_mask.astype(np.uint8)).cuda()
+    out = dr.run(G, policy, frame=frame, source_mask=mask_t, passes=passes)
+    torch.cuda.synchronize()
+    U = out.fields.U.cpu().numpy().astype(np.float64)
+    S = out.fields.S_total.cpu().numpy()[:G.s_size].astype(np.float64)
+    assert G.s_offset == m.s_offset and G.nside_sca == m.nside_sca
+    eu = rel_err(U, ref.U)
+    es = rel_err(S, ref.S_total)
+    print(f"{label}: U max rel {eu.max():.3g} p99.9 {np.quantile(eu, 0.999):.3g}; "
+          f"S max rel {es.max():.3g} p99.9 {np.quantile(es, 0.999):.3g}", flush=True)
+    assert eu.max() <= tol, f"U rel err {eu.max()}"
+    assert es.max() <= tol, f"S rel err {es.max()}"
+    for k, (t_gpu, r) in enumerate(zip(out.tallies, ref.passes)):
+        t_ref = r.tally
+        em = t_gpu[:, 0]
+        np.testing.assert_allclose(em, t_ref[:, 0], rtol=1e-6)
+        for col in (1, 2, 3):
+            np.testing.assert_allclose(t_gpu[:, col], t_ref[:, col], rtol=TOL, atol=1e-12 * em.max())
+        resid = t_gpu[:, 1:6].sum(axis=1) - em
+        assert np.all(np.abs(resid) <= 1e-6 * np.abs(em) + 1e-300), f"pass {k} balance {resid / em}"
+        c_gpu = out.counters[k]
+        # crossings longer than 1e-6 of the cell; FP32/FP64 may disagree only
+        # for lengths at that threshold
+        assert abs(int(c_gpu[dr.C_CROSSINGS]) - int(r.counters[orc.C_CROSS])) <= 1e-4 * r.counters[orc.C_CROSS]
+        assert c_gpu[dr.C_RAYS] == r.counters[orc.C_RAYS]
+    return out, ref
+
+
+def test_traversal_index_sequences(dr, orc):
+    grids = [W.plain16(n=16).grid, W.plain16(n=5).grid, W.random_octree(seed=1),
+             W.random_octree(nroot=(3, 2, 1), root_size=1.0, max_level=3, p_split=0.5, seed=2, lo=(-1.5, -1.0, -0.5)),
+             W.disk_small().grid]
+    rng = np.random.default_rng(11)
+    for gi, grid in enumerate(grids):
+        G = dr.Grid(grid)
+        m = orc.Model(grid)
+        blo, bhi = grid.box()
+        n_rays = 200
+        o = blo + rng.random((n_rays, 3)) * (bhi - blo)
+        d = rng.standard_normal((n_rays, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        got = dr.debug_ray_cells(G, o, d)
+        h = float(np.min(grid.side()))
+        checked = 0
+        for i in range(n_rays):
+            cells, lens, tin = m.trace_cells(o[i], d[i])
+            # tie-free: successive face distances differ by more than 1e-5 of a cell
+            if np.any((lens > 0) & (lens < 1e-5 * h)):
+                continue
+            want = cells[lens > 0]
+            gc, gl = got[i]
+            have = gc[gl > 1e-6 * h]
+            assert list(have) == list(want), f"grid {gi} ray {i}"
+            # FP32 face distances carry an absolute error of a few ulp of the
+            # distance travelled, so short segments are compared absolutely
+            ext = float(np.max(bhi - blo))
+            np.testing.assert_allclose(gl[gl > 1e-6 * h], lens[lens > 0], rtol=1e-5, atol=1e-6 * ext)
+            checked += 1
+        assert checked > 0.9 * n_rays
+        G.close()
+
+
+def test_plain16_direct_and_two_scattering_iterations(dr, orc):
+    wl = W.plain16()
+    compare_run(dr, orc, wl.grid, wl.policy, label="plain16")
+
+
+def test_plain16_rotated_frame(dr, orc):
+    wl = W.plain16()
+    compare_run(dr, orc, wl.grid, wl.policy, frame=W.rotation(4), passes=2, label="plain16 rotated")
+
+
+@pytest.mark.parametrize("n,nside", [(5, 4), (7, 2), (9, 8)])
+def test_ragged_uniform_grids(dr, orc, n, nside):
+    # cell counts that are not multiples of the 64-lane source tiles
+    wl = W.plain16(n=n, nside=nside)
+    compare_run(dr, orc, wl.grid, wl.policy, label=f"uniform {n}^3 nside {nside}")
+
+
+def test_four_wavelengths(dr, orc):
+    wl = W.plain16(n=8, nside=4, lambdas=np.array([0.15, 0.30, 0.55, 2.2]))
+    compare_run(dr, orc, wl.grid, wl.policy, label="8^3 x 4 lambda")
+
+
+def test_octree_fixed_rays(dr, orc):
+    grid = W.random_octree(nroot=(2, 2, 1), root_size=0.5, max_level=3, p_split=0.35, seed=9, n_lambda=3)
+    pol = W.RayPolicy(adaptive=False, nside=4, nside_max=4, n_scatter=1)
+    compare_run(dr, orc, grid, pol, label="octree fixed")
+
+
+def test_source_subset_additivity(dr, orc):
+    wl = W.plain16(n=8, nside=4)
+    rng = np.random.default_rng(2)
+    mask = (rng.random(wl.grid.n) < 0.3).astype(np.uint8)
+    compare_run(dr, orc, wl.grid, wl.policy, source_mask=mask, label="subset")
+
+
+def test_sparse_sources_and_empty_cells(dr, orc):
+    # few emitting cells and dust-free cells (alpha = 0 deposits)
+    wl = W.plain16(n=8, nside=4)
+    g = wl.grid.copy()
+    rng = np.random.default_rng(3)
+    g.emis[:, rng.random(g.n) < 0.9] = 0.0
+    g.rho[rng.random(g.n) < 0.2] = 0.0
+    compare_run(dr, orc, g, wl.policy, label="sparse")
+
+
+def test_no_sources(dr, orc):
+    import torch
+    wl = W.plain16(n=4, nside=2)
+    g = wl.grid.copy()
+    g.emis[:] = 0.0
+    G = dr.Grid(g)
+    out = dr.run(G, wl.policy)
+    torch.cuda.synchronize()
+    assert float(out.fields.U.abs().max()) == 0.0
+    assert float(out.fields.S_total.abs().max()) == 0.0
+    assert out.r_k == [0.0, 0.0]
+
+
+def test_scatter_requires_direct(dr):
+    wl = W.plain16(n=4, nside=2)
+    G = dr.Grid(wl.grid)
+    f = dr.Fields(G)
+    with pytest.raises(dr.DartRayError) as e:
+        dr.scatter_iter(G, dr.make_opts(wl.policy), f)
+    assert e.value.code == dr.E_STATE
+
+
+def test_max_steps_guard(dr):
+    import torch
+    wl = W.plain16(n=8, nside=2)
+    G = dr.Grid(wl.grid)
+    f = dr.Fields(G)
+    dr.trace_direct(G, dr.make_opts(wl.policy, max_steps=2), f)
+    torch.cuda.synchronize()
+    c = f.counters.cpu().numpy()
+    assert c[dr.C_MAXSTEP] > 0
+    assert c[dr.C_MAXSTEP] + c[dr.C_ESCAPES] == c[dr.C_RAYS]
