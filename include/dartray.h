@@ -63,7 +63,7 @@ extern "C" {
 #define DARTRAY_N_TALLY 8
 
 /* counter slots (uint64) */
-#define DARTRAY_C_CROSSINGS 0       /* traversed ray-cell crossings longer than 1e-6 of the cell side */
+#define DARTRAY_C_CROSSINGS 0       /* traversed crossings longer than 1e-6 (cell side + distance) */
 #define DARTRAY_C_RAYS 1            /* rays launched from sources */
 #define DARTRAY_C_SPLITS 2          /* rays replaced by 4 children (Eq. 2) */
 #define DARTRAY_C_CUTS 3            /* rays blocked */
@@ -92,7 +92,8 @@ typedef struct dartray_grid dartray_grid;   /* opaque handle */
  * albedo, g (Henyey-Greenstein, Eq. 4) and nside_sca, the HEALPix Nside of
  * the scattered source function at that wavelength (a power of two, or 0 to
  * apply the resolution rule of Eq. 5-6 with n_fwhm and the cap k_max).
- * Values must be finite, rho and emis >= 0, 0 <= albedo <= 1, |g| < 1.
+ * Values must be finite, rho and emis >= 0, 0 <= albedo <= 1, |g| < 1,
+ * nside_sca <= 8.
  */
 typedef struct {
     int32_t nroot[3];
@@ -111,6 +112,11 @@ typedef struct {
     double n_fwhm;               /* Eq. 6; the paper uses 5 */
     int32_t k_max;               /* cap on k of Eq. 5 (the paper suggests 2-3) */
     double c_light;              /* speed of light in the grid's units */
+    int32_t nside_max;           /* largest ray Nside any trace on this handle uses
+                                    (power of two, <= 1024; 0 means 64); sizes the
+                                    direction table (16 * 4 nside_max^2 bytes) and,
+                                    for adaptive rays, the phase-normalisation
+                                    table (4 * n_lambda * 4 nside_max^2 bytes) */
 } dartray_grid_desc;
 
 /*

@@ -51,7 +51,11 @@
  *    neighbour across it that contains the exit point (points on a face
  *    belong to the side the direction points to, the upper side when the
  *    component is zero); a ray through an edge or corner therefore crosses
- *    zero-length segments, which deposit nothing.
+ *    zero-length segments;
+ *  - a segment shorter than 1e-6 (cell side + exit distance) is a graze: it
+ *    deposits nothing, counts as no crossing and takes no split or block
+ *    decision (at an exact tie its length is zero; the threshold keeps the
+ *    rounding of near-ties in any precision out of the result).
  */
 
 #include <math.h>
@@ -219,20 +223,38 @@ int orc_k_hp(double g, double n_fwhm, int k_max)
     return (int)k;
 }
 
-/* Weights w(p | n) = Phi(n_p . n) / sum_q Phi(n_q . n) over the j_sca pixels
- * at `nside_sca`, with the pixel centres rotated by `frame`. */
-void orc_hg_weights(int nside_sca, double g, const double n[3], const double frame[9], double *w)
+/* Weights w(p | n) = Phi(n_p . n) / sum_q Phi(n_q . n) over `npix` j_sca
+ * pixels whose (rotated) centre vectors are pv[3p..3p+2]. */
+static void orc_hg_weights_tab(int64_t npix, const double *pv, double g, const double n[3], double *w)
 {
-    int64_t npix = 12 * (int64_t)nside_sca * nside_sca;
     double sum = 0.0;
     for (int64_t p = 0; p < npix; ++p) {
-        double v0[3], v[3];
-        orc_healpix_vec(nside_sca, p, v0);
-        orc_rotate(frame, v0, v);
-        w[p] = orc_hg(g, v[0] * n[0] + v[1] * n[1] + v[2] * n[2]);
+        w[p] = orc_hg(g, pv[3 * p] * n[0] + pv[3 * p + 1] * n[1] + pv[3 * p + 2] * n[2]);
         sum += w[p];
     }
     for (int64_t p = 0; p < npix; ++p) w[p] /= sum;
+}
+
+/* Rotated centre vectors of the nested pixels at `nside`: out[3p..3p+2]. */
+static void orc_pixel_table(int64_t nside, const double frame[9], double *out)
+{
+    for (int64_t p = 0; p < 12 * nside * nside; ++p) {
+        double v0[3];
+        orc_healpix_vec(nside, p, v0);
+        orc_rotate(frame, v0, out + 3 * p);
+    }
+}
+
+/* Weights w(p | n) over the j_sca pixels at `nside_sca`, pixel centres
+ * rotated by `frame`. */
+void orc_hg_weights(int nside_sca, double g, const double n[3], const double frame[9], double *w)
+{
+    int64_t npix = 12 * (int64_t)nside_sca * nside_sca;
+    double *pv = (double *)malloc(sizeof(double) * 3 * (size_t)npix);
+    if (!pv) return;
+    orc_pixel_table(nside_sca, frame, pv);
+    orc_hg_weights_tab(npix, pv, g, n, w);
+    free(pv);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -430,6 +452,7 @@ typedef struct {
     double tally[64 * N_TALLY];
     int64_t count[N_COUNT];
     double *w;          /* [sum npix] weights of the current ray */
+    const double *pv;   /* [sum npix][3] j_sca pixel vectors of each wavelength's block */
     orc_ray *stack;
     double *lbuf;
     int64_t cap;
@@ -490,8 +513,11 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
     orc_ray_dir(o, nside, ray->pix, n);
     const double *xs = &m->centre[3 * s];
     if (o->mode != ORC_STEP1) {
-        for (int l = 0; l < nl; ++l)
-            orc_hg_weights(m->nside_sca[l], d->g[l], n, o->frame, th->w + m->s_offset[l] / d->n_leaves);
+        for (int l = 0; l < nl; ++l) {
+            int64_t woff = m->s_offset[l] / d->n_leaves;
+            orc_hg_weights_tab(12 * (int64_t)m->nside_sca[l] * m->nside_sca[l], th->pv + 3 * woff, d->g[l], n,
+                               th->w + woff);
+        }
     }
     double p[3];
     for (int a = 0; a < 3; ++a) p[a] = xs[a] + ray->t_start * n[a];
@@ -507,7 +533,9 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
         double te;
         int64_t next = orc_step(m, c, xs, n, &te);
         double len = te > t ? te - t : 0.0;
-        if (len > 0.0) {
+        /* a segment shorter than 1e-6 (cell side + exit distance) is a graze of
+         * an edge or corner: nothing is deposited and no decision is taken */
+        if (len > 1e-6 * (m->side[c] + te)) {
             double t_in = t;
             double dc2 = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -559,9 +587,7 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
                     }
                 }
             }
-            /* a crossing counts as work when it is longer than 1e-6 of the
-             * cell; shorter ones are edge or corner grazes at near-ties */
-            if (len > 1e-6 * m->side[c]) th->count[C_CROSS]++;
+            th->count[C_CROSS]++;
             for (int l = 0; l < nl; ++l) {
                 double alpha = d->kappa[l] * d->rho[c];
                 if (sig[l]) {
@@ -619,12 +645,17 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     if (o->adaptive) while (((int64_t)o->nside << levels) < o->nside_max) ++levels;
     int64_t nray0 = 12 * (int64_t)o->nside * o->nside;
     int failed = 0;
+    /* j_sca pixel centre vectors, one block per wavelength (rotated frame) */
+    double *pv = (double *)malloc(sizeof(double) * 3 * (size_t)(wsize > 0 ? wsize : 1));
+    if (!pv) return ORC_E_OOM;
+    for (int l = 0; l < nl; ++l) orc_pixel_table(m->nside_sca[l], o->frame, pv + 3 * (m->s_offset[l] / n));
 
 #pragma omp parallel num_threads(nthreads)
     {
         orc_thread th;
         memset(&th, 0, sizeof(th));
         th.atomic = atomic;
+        th.pv = pv;
         if (atomic) {
             th.U = U_k;
             th.S = S_next;
@@ -708,5 +739,6 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
         free(th.stack);
         free(th.lbuf);
     }
+    free(pv);
     return failed ? ORC_E_OOM : ORC_OK;
 }

@@ -126,13 +126,32 @@ struct Frame {
     double R[9];
 };
 
-__global__ void k_dirs(float4 *dirs, int nside, int64_t nray, Frame f)
+// Nside of table entry e (entry 4 (N^2 - 1) + pix): the largest N with 4 (N^2 - 1) <= e
+__host__ __device__ inline int64_t entry_nside(int64_t e)
 {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= nray) return;
+    int64_t N = 1;
+    while (4 * (4 * N * N - 1) <= e) N *= 2;
+    return N;
+}
+
+__host__ __device__ inline int64_t entry_of(int64_t nside, int64_t pix) { return 4 * (nside * nside - 1) + pix; }
+
+__global__ void k_dir_all(float4 *dirs, int64_t total, Frame f)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t N = entry_nside(e);
     double v[3];
-    dr_pix_vec(nside, r, f.R, v);
-    dirs[r] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);
+    dr_pix_vec(N, e - entry_of(N, 0), f.R, v);
+    dirs[e] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);
+}
+
+__global__ void k_sca64(double *out, Frame f)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kScaDirs) return;
+    const int64_t N = entry_nside(e);
+    dr_pix_vec(N, e - entry_of(N, 0), f.R, out + 3 * e);
 }
 
 __device__ inline double hg_phase(double g, double mu)
@@ -142,7 +161,8 @@ __device__ inline double hg_phase(double g, double mu)
 }
 
 // w_l(p | n_r) = Phi_l(n_p . n_r) / sum_q Phi_l(n_q . n_r), one thread per (r, l)
-__global__ void k_wtab(float *wtab, const LambdaTable *lt, int nside_ray, int64_t nray, int w_row, Frame f)
+__global__ void k_wtab(float *wtab, const LambdaTable *lt, const double *sca64, int nside_ray, int64_t nray,
+                       int w_row, Frame f)
 {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int nl = lt->n_lambda;
@@ -154,17 +174,30 @@ __global__ void k_wtab(float *wtab, const LambdaTable *lt, int nside_ray, int64_
     const int ns = lt->nside_sca[l];
     const int npix = lt->npix[l];
     const double g = lt->g[l];
+    const double *v = sca64 + 3 * entry_of(ns, 0);
     double sum = 0.0;
-    for (int p = 0; p < npix; ++p) {
-        double v[3];
-        dr_pix_vec(ns, p, f.R, v);
-        sum += hg_phase(g, v[0] * n[0] + v[1] * n[1] + v[2] * n[2]);
-    }
+    for (int p = 0; p < npix; ++p) sum += hg_phase(g, v[3 * p] * n[0] + v[3 * p + 1] * n[1] + v[3 * p + 2] * n[2]);
     float *row = wtab + r * (int64_t)w_row + lt->w_off[l];
-    for (int p = 0; p < npix; ++p) {
-        double v[3];
-        dr_pix_vec(ns, p, f.R, v);
-        row[p] = (float)(hg_phase(g, v[0] * n[0] + v[1] * n[1] + v[2] * n[2]) / sum);
+    for (int p = 0; p < npix; ++p)
+        row[p] = (float)(hg_phase(g, v[3 * p] * n[0] + v[3 * p + 1] * n[1] + v[3 * p + 2] * n[2]) / sum);
+}
+
+// 1 / sum_p Phi_l(n_p . n_e) for every table entry e from e0 on, in FP64
+__global__ void k_invz(float *invz, const LambdaTable *lt, const double *sca64, int64_t e0, int64_t total, Frame f)
+{
+    const int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t N = entry_nside(e);
+    double n[3];
+    dr_pix_vec(N, e - entry_of(N, 0), f.R, n);
+    const int nl = lt->n_lambda;
+    for (int l = 0; l < nl; ++l) {
+        const double *v = sca64 + 3 * entry_of(lt->nside_sca[l], 0);
+        const double g = lt->g[l];
+        double sum = 0.0;
+        for (int p = 0; p < lt->npix[l]; ++p)
+            sum += hg_phase(g, v[3 * p] * n[0] + v[3 * p + 1] * n[1] + v[3 * p + 2] * n[2]);
+        invz[e * nl + l] = (float)(1.0 / sum);
     }
 }
 
@@ -466,7 +499,7 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
             int axis;
             const float te = exit_t(R, b, axis);
             const float len = te - t;
-            if (len > 0.f) {
+            if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
                 const float rho = A.rho[c];
                 const float ivc = A.inv_vc[c];
                 const float lp = len * A.h_fine;
@@ -484,7 +517,7 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
                         L[l] = fmaf(L[l], em1, L[l]);
                     }
                 }
-                ncross += len > 1e-6f * (float)b.w;   // edge and corner grazes are not counted
+                ++ncross;
                 t = te;
             }
             const int32_t nx = next_leaf<UNIFORM>(A.geo, R, b, axis, te);
@@ -563,6 +596,400 @@ __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const fl
     if (blockIdx.y == 0) U_k[(int64_t)l * n + c] += accU;
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive march (ray splitting and blocking, Sect. 3.1.1 / 3.2 / 3.5).
+//
+// A persistent kernel: each lane takes work items (top-level pixel r0,
+// source) from a device counter, 64 at a time per wave, items ordered so that
+// a wave starts on 64 Morton-consecutive sources with the same direction.  A
+// lane walks the ray tree of its item depth first: a split replaces the ray
+// by its four nested children (Nside doubled) that restart at the entry
+// distance of the triggering crossing with a quarter of its luminosity.  The
+// stack keeps one (distance, luminosity / 4) entry per level; the pixel of
+// the next sibling is pix + 1 and the parent is pix >> 2.
+//
+// Every loop iteration advances each lane with a ray by one crossing; the
+// energy density is deposited lane by lane, the scattered luminosity
+// cooperatively: for each depositing lane the whole wave adds that crossing's
+// phase-weighted luminosity to the cell's HEALPix row, 64 pixels per
+// instruction.
+// ---------------------------------------------------------------------------
+
+struct AdaptArgs {
+    Geo geo;
+    const int32_t *src_list;
+    const int32_t *n_src;
+    const float4 *dirs;          // all-level direction table
+    const float *invz;           // [entry][n_lambda]
+    const float *rho;
+    const float *inv_vc;
+    const float *emis_lum;
+    const float *S_pending;
+    const float *U_LL;
+    const uint8_t *mask;
+    const LambdaTable *lt;
+    float *U_k;
+    float *S_next;
+    double *tally;
+    uint64_t *counters;
+    unsigned long long *queue;
+    int64_t n;
+    int32_t mode;                // 0 step 1, 1 direct, 2 scatter
+    int32_t nside0;
+    int32_t log2_nside0;
+    int32_t max_depth;           // levels above nside0 a ray may reach
+    float n_rays;                // N_rays of Eq. 2
+    float f_U;                   // < 0: 4 a_RT / N_s
+    float a_RT;
+    float r_pre_fine;            // step-1 extent in fine units
+    float h_fine;
+    float c_light;
+    int64_t max_steps;
+    int64_t hard_cap;
+};
+
+__device__ inline float readlane_f(float v, int j)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+__device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+
+template <int NL, int MODE>
+__global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
+{
+    constexpr bool STEP1 = MODE == 0;
+    __shared__ float4 sca[kScaDirs];
+    for (int i = threadIdx.x; i < kScaDirs; i += blockDim.x) sca[i] = A.dirs[i];
+    __syncthreads();
+
+    const LambdaTable *lt = A.lt;
+    const int nl = lt->n_lambda;
+    const int lane = threadIdx.x & 63;
+    const int nsrc = *A.n_src;
+    const uint64_t nitems = (uint64_t)nsrc * (uint64_t)(12 * A.nside0 * A.nside0);
+    const float f_U = A.f_U >= 0.f ? A.f_U : (nsrc > 0 ? 4.f * A.a_RT / (float)nsrc : 0.f);
+
+    float kap[NL], hgA[NL], hgB[NL], hgC[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const float g = l < nl ? lt->g[l] : 0.f;
+        kap[l] = l < nl ? lt->kappa[l] : 0.f;
+        hgA[l] = (1.f - g * g) / (4.f * 3.14159265358979f);   // HG prefactor
+        hgB[l] = 1.f + g * g;
+        hgC[l] = -2.f * g;
+    }
+
+    // tallies and counters of this lane
+    float esc[NL], cut[NL], skp[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) esc[l] = cut[l] = skp[l] = 0.f;
+    uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_skip = 0, n_max = 0;
+
+    // ray state
+    bool has_ray = false;
+    bool has_item = false;
+    bool done = false;            // the work counter is exhausted for this lane
+    int32_t s = 0;
+    float o[3] = {0.f, 0.f, 0.f};
+    int depth = 0;
+    int pix = 0;
+    float t = 0.f;
+    int32_t c = -1;
+    int4 b = make_int4(0, 0, 0, 1);
+    Ray R;
+    float L[NL], iz[NL];
+    float st_t[kMaxDepthAdaptive + 1];
+    float st_L[kMaxDepthAdaptive + 1][NL];
+    int64_t steps = 0;
+    float omega_hp = 0.f;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) L[l] = iz[l] = 0.f;
+
+    // set up the ray (depth, pix) from distance t: direction, 1/Z, first cell
+    auto start_ray = [&]() {
+        const int64_t N = (int64_t)A.nside0 << depth;
+        const int64_t e = entry_of(N, pix);
+        const float4 nd = A.dirs[e];
+        R.n[0] = nd.x;
+        R.n[1] = nd.y;
+        R.n[2] = nd.z;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R.o[a] = o[a];
+            R.inv[a] = 1.0f / R.n[a];
+        }
+        if (!STEP1) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) iz[l] = l < nl ? A.invz[e * nl + l] : 0.f;
+        }
+        omega_hp = 3.14159265358979f / (3.f * (float)N * (float)N);   // 4 pi / (12 N^2)
+        steps = 0;
+        if (t == 0.f) {
+            c = s;
+        } else {
+            c = locate_fine(A.geo, fine_coord(fmaf(t, R.n[0], o[0]), R.n[0]),
+                            fine_coord(fmaf(t, R.n[1], o[1]), R.n[1]), fine_coord(fmaf(t, R.n[2], o[2]), R.n[2]));
+        }
+        if (c >= 0) {
+            b = A.geo.leaf_box[c];
+            has_ray = true;
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) esc[l] += L[l];
+            ++n_esc;
+            has_ray = false;
+        }
+    };
+
+    while (true) {
+        // ---- lanes without a ray: next sibling, or a new item
+        if (!has_ray && has_item) {
+            while (depth > 0 && (pix & 3) == 3) {
+                --depth;
+                pix >>= 2;
+            }
+            if (depth > 0) {
+                ++pix;
+                t = st_t[depth];
+#pragma unroll
+                for (int l = 0; l < NL; ++l) L[l] = st_L[depth][l];
+                start_ray();
+            } else {
+                has_item = false;
+            }
+        }
+        const uint64_t need = __ballot(!has_ray && !has_item && !done);
+        if (need) {
+            const int k = __popcll(need);
+            unsigned long long base = 0;
+            if (lane == __ffsll((unsigned long long)need) - 1) base = atomicAdd(A.queue, (unsigned long long)k);
+            base = __shfl(base, __ffsll((unsigned long long)need) - 1, 64);
+            if (!has_ray && !has_item && !done) {
+                const uint64_t it = base + __popcll(need & ((1ull << lane) - 1ull));
+                if (it >= nitems) done = true;
+                if (it < nitems) {
+                    const int r0 = (int)(it / (uint64_t)nsrc);
+                    s = A.src_list[it - (uint64_t)r0 * nsrc];
+                    const int4 sb = A.geo.leaf_box[s];
+                    const float half = 0.5f * (float)sb.w;
+                    o[0] = (float)sb.x + half;
+                    o[1] = (float)sb.y + half;
+                    o[2] = (float)sb.z + half;
+                    float lsum = 0.f;
+                    const float inv_nray0 = 1.f / (float)(12 * A.nside0 * A.nside0);
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        float v = 0.f;
+                        if (l < nl) {
+                            if (MODE != 2) {
+                                v = A.emis_lum[(int64_t)l * A.n + s] * inv_nray0;
+                            } else {
+                                const int npix = lt->npix[l];
+                                const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
+                                const int ls = 31 - __clz(lt->nside_sca[l]);
+                                if (A.log2_nside0 >= ls) {
+                                    v = row[r0 >> (2 * (A.log2_nside0 - ls))] * ((float)npix * inv_nray0);
+                                } else {
+                                    const int sh = 2 * (ls - A.log2_nside0);
+                                    for (int q = r0 << sh; q < ((r0 + 1) << sh); ++q) v += row[q];
+                                }
+                            }
+                        }
+                        L[l] = v;
+                        lsum += v;
+                    }
+                    has_item = true;
+                    if (lsum > 0.f) {
+                        ++n_rays;
+                        depth = 0;
+                        pix = r0;
+                        t = 0.f;
+                        start_ray();
+                    } else {
+                        depth = 0;
+                        pix = 3;   // nothing to trace; the item ends at the next refill
+                    }
+                }
+            }
+        }
+        if (__ballot(has_ray) == 0) {
+            if (__ballot(has_item) == 0) break;
+            continue;
+        }
+        (void)done;
+
+        // ---- one crossing per lane with a ray
+        bool deposit = false;
+        float F[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) F[l] = 0.f;
+        int32_t cdep = 0;
+        if (has_ray) {
+            int axis;
+            const float te = exit_t(R, b, axis);
+            const float len = te - t;
+            int action = 0;   // 0 continue, 1 split, 2 cut
+            if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes: no deposit, no decision
+                const float t_in = t;
+                const float dx = ((float)b.x + 0.5f * (float)b.w - o[0]);
+                const float dy = ((float)b.y + 0.5f * (float)b.w - o[1]);
+                const float dz = ((float)b.z + 0.5f * (float)b.w - o[2]);
+                const float h = A.h_fine;
+                const float d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
+                const float side = (float)b.w * h;
+                const float lp = len * h;
+                const float rho_c = A.rho[c];
+                float ext[NL], em1[NL];
+                bool sig[NL];
+                bool any_sig = false;
+                const float thr = f_U * omega_hp * d2 * A.c_light;
+#pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    sig[l] = false;
+                    ext[l] = 0.f;
+                    em1[l] = 0.f;
+                    if (l < nl) {
+                        const float tau = kap[l] * rho_c * lp;
+                        em1[l] = expm1f(-tau);
+                        ext[l] = -L[l] * em1[l];
+                        if (STEP1) {
+                            sig[l] = true;
+                        } else {
+                            const float lavg = tau > 0.f ? ext[l] / tau : L[l];
+                            sig[l] = lavg > 0.f && (d2 == 0.f || lavg >= thr * A.U_LL[(int64_t)l * A.n + c]);
+                        }
+                        any_sig |= sig[l];
+                    }
+                }
+                if (STEP1 && t_in >= A.r_pre_fine) {
+                    action = 2;
+                } else if (d2 > 0.f && omega_hp * A.n_rays * d2 > side * side) {   // Eq. 2
+                    if (any_sig && depth < A.max_depth) action = 1;
+                    else if (!any_sig) action = 2;
+                }
+                if (action == 1) {
+                    ++n_split;
+                    ++depth;
+                    st_t[depth] = t_in;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        L[l] *= 0.25f;
+                        st_L[depth][l] = L[l];
+                    }
+                    pix = 4 * pix;
+                    t = t_in;
+                    start_ray();
+                } else if (action == 2) {
+                    ++n_cut;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) cut[l] += L[l];
+                    has_ray = false;
+                } else {
+                    const float ivc = A.inv_vc[c];
+                    ++n_cross;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        if (l < nl) {
+                            if (sig[l]) {
+                                const float alpha = kap[l] * rho_c;
+                                const float du = alpha > 0.f ? ext[l] * (ivc / alpha) : L[l] * lp * ivc;
+                                atomic_add_f32(A.U_k + (int64_t)l * A.n + c, du);
+                                ++n_dep;
+                                if (!STEP1) F[l] = lt->albedo[l] * ext[l] * iz[l] * hgA[l];
+                            } else {
+                                skp[l] += ext[l];
+                                ++n_skip;
+                            }
+                            L[l] = fmaf(L[l], em1[l], L[l]);
+                        }
+                    }
+                    if (!STEP1) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) deposit |= F[l] != 0.f;
+                    }
+                    cdep = c;
+                    t = te;
+                }
+            }
+            if (has_ray && action == 0) {
+                const int32_t nx = next_leaf<false>(A.geo, R, b, axis, te);
+                ++steps;
+                if (nx < 0) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) esc[l] += L[l];
+                    ++n_esc;
+                    has_ray = false;
+                } else if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
+                    ++n_max;
+                    has_ray = false;
+                } else {
+                    c = nx;
+                    b = A.geo.leaf_box[c];
+                }
+            }
+        }
+
+        // ---- cooperative scattered-light deposit
+        if (!STEP1) {
+            uint64_t m = __ballot(deposit);
+            while (m) {
+                const int j = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const int cj = readlane_i(cdep, j);
+                const float nx = readlane_f(R.n[0], j), ny = readlane_f(R.n[1], j), nz = readlane_f(R.n[2], j);
+                for (int l = 0; l < nl; ++l) {
+                    float Fl = 0.f;
+#pragma unroll
+                    for (int q = 0; q < NL; ++q)
+                        if (q == l) Fl = F[q];
+                    const float Fj = readlane_f(Fl, j);
+                    if (Fj == 0.f) continue;
+                    const int npix = lt->npix[l];
+                    const int base = (int)entry_of(lt->nside_sca[l], 0);
+                    float *dst = A.S_next + lt->s_off[l] + (int64_t)cj * npix;
+                    float B = 0.f, Cc = 0.f;
+#pragma unroll
+                    for (int q = 0; q < NL; ++q)
+                        if (q == l) {
+                            B = hgB[q];
+                            Cc = hgC[q];
+                        }
+                    for (int p = lane; p < npix; p += 64) {
+                        const float4 v = sca[base + p];
+                        const float mu = fmaf(v.x, nx, fmaf(v.y, ny, v.z * nz));
+                        const float den = fmaf(Cc, mu, B);
+                        const float r = rsqrtf(den);
+                        atomic_add_f32(dst + p, Fj * (r * r * r));
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- wave-level FP64 tallies
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        if (l < nl) {
+            const double ve = wave_sum((double)esc[l]);
+            const double vc = wave_sum((double)cut[l]);
+            const double vs = wave_sum((double)skp[l]);
+            if (lane == 0) {
+                if (ve != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], ve);
+                if (vc != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_CUT], vc);
+                if (vs != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_SKIPPED], vs);
+            }
+        }
+    }
+    if (A.counters) {
+        const uint64_t v[8] = {wave_sum_u64(n_cross), wave_sum_u64(n_rays), wave_sum_u64(n_split), wave_sum_u64(n_cut),
+                               wave_sum_u64(n_esc), wave_sum_u64(n_dep), wave_sum_u64(n_skip), wave_sum_u64(n_max)};
+        if (lane == 0)
+            for (int i = 0; i < 8; ++i)
+                if (v[i]) atomicAdd((unsigned long long *)&A.counters[i], (unsigned long long)v[i]);
+    }
+}
+
 // U += U_k (and U_pass = U_k), absorbed / scattered tallies from U_k in FP64,
 // U_LL <- U when requested.  grid.y = wavelength
 __global__ void k_finish_u(const float *U_k, float *U, float *U_pass, float *U_LL, int set_ull, int ull_only,
@@ -638,7 +1065,7 @@ static int nside_from_rule(double g, double n_fwhm, int k_max)
     if (fwhm <= 0.0) return 1;
     const double tmin = fwhm / n_fwhm;
     double k = std::floor(0.5 * std::log2(4.0 * kPi / (12.0 * tmin * tmin)));
-    k = std::max(0.0, std::min((double)k_max, k));
+    k = std::max(0.0, std::min((double)std::min(k_max, 3), k));   // Nside_sca <= 8
     return 1 << (int)k;
 }
 
@@ -672,7 +1099,7 @@ static void free_grid(Grid &g)
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
     void *ptrs[] = {g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
-                    g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dirs, g.wtab};
+                    g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.invz, g.sca64, g.wtab, g.queue};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -693,8 +1120,11 @@ static int validate_desc(const dartray_grid_desc *d)
         if (!(d->albedo[l] >= 0.f && d->albedo[l] <= 1.f)) return fail(DARTRAY_E_INVALID, "albedo must lie in [0, 1]");
         if (!(d->g[l] > -1.f && d->g[l] < 1.f)) return fail(DARTRAY_E_INVALID, "g must lie in (-1, 1)");
         const int ns = d->nside_sca[l];
-        if (ns < 0 || (ns > 0 && (ns & (ns - 1))) || ns > 64) return fail(DARTRAY_E_INVALID, "nside_sca must be 0 or a power of two <= 64");
+        if (ns < 0 || (ns > 0 && (ns & (ns - 1))) || ns > kMaxNsideSca) return fail(DARTRAY_E_INVALID, "nside_sca must be 0 or a power of two <= 8");
     }
+    if (d->nside_max < 0 || d->nside_max > kMaxNsideCap || (d->nside_max & (d->nside_max - 1)))
+        return fail(DARTRAY_E_INVALID, "nside_max must be 0 or a power of two <= 1024");
+    if (d->k_max < 0) return fail(DARTRAY_E_INVALID, "k_max must be >= 0");
     if (!(d->n_fwhm > 0.0)) {
         for (int l = 0; l < d->n_lambda; ++l)
             if (d->nside_sca[l] == 0) return fail(DARTRAY_E_INVALID, "n_fwhm must be > 0 with nside_sca = 0");
@@ -849,8 +1279,9 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     g.w_row = lt.w_off[nl];
     g.stream = (hipStream_t)stream;
 
-    const size_t nray_fixed = 12 * (size_t)kMaxNsideFixed * kMaxNsideFixed;
     const size_t nray_w = 12 * (size_t)kMaxNsideWTable * kMaxNsideWTable;
+    const int32_t cap = std::max(64, (int)d->nside_max);
+    const int64_t ndir = 4 * (4 * (int64_t)cap * cap - 1);   // all levels 1 .. cap
     // direction-binned work array: all 768 Nside-8 directions when they fit
     // in 8 GiB, else as many as fit
     const size_t per_dir = (size_t)nl * (size_t)n;
@@ -862,8 +1293,9 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
         dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
         dalloc(g, &g.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
-        dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dirs, nray_fixed),
-        dalloc(g, &g.wtab, nray_w * (size_t)g.w_row),
+        dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir),
+        dalloc(g, &g.invz, (size_t)ndir * nl), dalloc(g, &g.sca64, 3 * (size_t)kScaDirs),
+        dalloc(g, &g.wtab, nray_w * (size_t)g.w_row), dalloc(g, &g.queue, 1),
     };
     for (int r : rcs)
         if (r) {
@@ -873,6 +1305,8 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
             return fail(DARTRAY_E_OOM, msg);
         }
     g.ubar_floats = nb_cap * per_dir;
+    g.nside_cap = cap;
+    g.ndir_all = ndir;
     hipStream_t s = g.stream;
     hipError_t e = hipSuccess;
     std::vector<float> rho_f(d->rho, d->rho + n);
@@ -1034,8 +1468,17 @@ static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_
         if (!f->U || !f->S_total || !f->S_pending || !f->S_next) return fail(DARTRAY_E_INVALID, "U and S buffers required");
         if (o->adaptive && !f->U_LL) return fail(DARTRAY_E_INVALID, "adaptive passes need U_LL");
     }
-    if (o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays are not available in this build");
-    if (o->nside > kMaxNsideFixed) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 64");
+    if (o->nside > g.nside_cap) return fail(DARTRAY_E_INVALID, "nside above the grid's nside_max");
+    if (o->adaptive) {
+        if (o->nside_max < o->nside || (o->nside_max & (o->nside_max - 1)) || o->nside_max > g.nside_cap)
+            return fail(DARTRAY_E_INVALID, "adaptive nside_max must be a power of two in [nside, grid nside_max]");
+        int depth = 0;
+        while ((o->nside << depth) < o->nside_max) ++depth;
+        if (depth > kMaxDepthAdaptive) return fail(DARTRAY_E_INVALID, "more than 12 split levels");
+        if (!(o->n_rays_min > 0.f)) return fail(DARTRAY_E_INVALID, "n_rays_min must be > 0");
+        if (!(o->f_U >= 0.f) && !(o->a_RT > 0.f)) return fail(DARTRAY_E_INVALID, "f_U must be >= 0, or a_RT > 0");
+        if (g.n_lambda > 16) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays carry at most 16 wavelengths");
+    }
     if ((f->counters == nullptr) && (o->flags & DARTRAY_FLAG_COUNTERS))
         return fail(DARTRAY_E_INVALID, "counters buffer required by DARTRAY_FLAG_COUNTERS");
     if (scatter && !g.have_s1) return fail(DARTRAY_E_STATE, "scatter_iter needs a prior direct pass");
@@ -1053,27 +1496,42 @@ static void frame_of(const dartray_trace_opts *o, Frame &f)
         for (int i = 0; i < 9; ++i) f.R[i] = (i % 4 == 0) ? 1.0 : 0.0;
 }
 
-static int ensure_tables(Grid &g, int nside, const Frame &f, bool need_w)
+static int ensure_dirs(Grid &g, const Frame &f)
 {
-    const bool same_frame = std::memcmp(g.dirs_frame, f.R, sizeof(f.R)) == 0;
+    if (g.dirs_valid && std::memcmp(g.dirs_frame, f.R, sizeof(f.R)) == 0) return DARTRAY_OK;
+    hipLaunchKernelGGL(k_dir_all, dim3((unsigned)((g.ndir_all + 255) / 256)), dim3(256), 0, g.stream, g.dir_all,
+                       g.ndir_all, f);
+    DR_LAUNCH_CHECK("k_dir_all");
+    hipLaunchKernelGGL(k_sca64, dim3((kScaDirs + 255) / 256), dim3(256), 0, g.stream, g.sca64, f);
+    DR_LAUNCH_CHECK("k_sca64");
+    g.dirs_valid = true;
+    g.invz_valid = false;
+    g.wtab_valid = false;
+    std::memcpy(g.dirs_frame, f.R, sizeof(f.R));
+    return DARTRAY_OK;
+}
+
+static int ensure_wtab(Grid &g, int nside, const Frame &f)
+{
+    if (g.wtab_valid && g.wtab_nside == nside) return DARTRAY_OK;
+    if (nside > kMaxNsideWTable) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 16");
     const int64_t nray = 12 * (int64_t)nside * nside;
-    if (!(g.dirs_valid && g.dirs_nside == nside && same_frame)) {
-        hipLaunchKernelGGL(k_dirs, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, g.stream, g.dirs, nside, nray, f);
-        DR_LAUNCH_CHECK("k_dirs");
-        g.dirs_valid = true;
-        g.dirs_nside = nside;
-        g.wtab_valid = false;
-        std::memcpy(g.dirs_frame, f.R, sizeof(f.R));
-    }
-    if (need_w && !(g.wtab_valid && g.wtab_nside == nside)) {
-        if (nside > kMaxNsideWTable) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 16 with scattering");
-        const int64_t tot = nray * g.n_lambda;
-        hipLaunchKernelGGL(k_wtab, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, g.stream, g.wtab, g.d_lt, nside,
-                           nray, g.w_row, f);
-        DR_LAUNCH_CHECK("k_wtab");
-        g.wtab_valid = true;
-        g.wtab_nside = nside;
-    }
+    const int64_t tot = nray * g.n_lambda;
+    hipLaunchKernelGGL(k_wtab, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, g.stream, g.wtab, g.d_lt, g.sca64, nside,
+                       nray, g.w_row, f);
+    DR_LAUNCH_CHECK("k_wtab");
+    g.wtab_valid = true;
+    g.wtab_nside = nside;
+    return DARTRAY_OK;
+}
+
+static int ensure_invz(Grid &g, const Frame &f)
+{
+    if (g.invz_valid) return DARTRAY_OK;
+    hipLaunchKernelGGL(k_invz, dim3((unsigned)((g.ndir_all + 127) / 128)), dim3(128), 0, g.stream, g.invz, g.d_lt,
+                       g.sca64, (int64_t)0, g.ndir_all, f);
+    DR_LAUNCH_CHECK("k_invz");
+    g.invz_valid = true;
     return DARTRAY_OK;
 }
 
@@ -1121,8 +1579,9 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     const int64_t n = g.n;
     Frame fr;
     frame_of(o, fr);
-    int rc = ensure_tables(g, o->nside, fr, true);
+    int rc = ensure_dirs(g, fr);
     if (rc) return rc;
+    if ((rc = ensure_wtab(g, o->nside, fr))) return rc;
     const int64_t nray = 12 * (int64_t)o->nside * o->nside;
     int log2n = 0;
     while ((1 << log2n) < o->nside) ++log2n;
@@ -1140,7 +1599,7 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
                 g.max_level};
     A.src_list = g.src_list;
     A.n_src = g.n_src;
-    A.dirs = g.dirs;
+    A.dirs = g.dir_all + entry_of(o->nside, 0);
     A.rho = g.rho;
     A.inv_vc = g.inv_vc;
     A.emis_lum = g.emis_lum;
@@ -1190,6 +1649,77 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     return DARTRAY_OK;
 }
 
+template <int NL>
+static void launch_adaptive(const AdaptArgs &A, int mode, hipStream_t s, unsigned blocks)
+{
+    if (mode == 0) hipLaunchKernelGGL((k_march_adaptive<NL, 0>), dim3(blocks), dim3(256), 0, s, A);
+    else if (mode == 1) hipLaunchKernelGGL((k_march_adaptive<NL, 1>), dim3(blocks), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL((k_march_adaptive<NL, 2>), dim3(blocks), dim3(256), 0, s, A);
+}
+
+static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+{
+    const int nl = g.n_lambda;
+    const int64_t n = g.n;
+    const bool step1 = !scatter && o->mode == DARTRAY_MODE_STEP1;
+    Frame fr;
+    frame_of(o, fr);
+    int rc = ensure_dirs(g, fr);
+    if (rc) return rc;
+    if (!step1 && (rc = ensure_invz(g, fr))) return rc;
+    if ((rc = fill<float>(g, g.U_k, (size_t)nl * n, 0.f))) return rc;
+    if (!step1 && (rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
+    if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
+    if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
+    if ((rc = fill<unsigned long long>(g, g.queue, 1, 0ull))) return rc;
+    if ((rc = select_sources(g, o, f, scatter))) return rc;
+
+    AdaptArgs A{};
+    A.geo = Geo{g.leaf_box, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
+                g.max_level};
+    A.src_list = g.src_list;
+    A.n_src = g.n_src;
+    A.dirs = g.dir_all;
+    A.invz = g.invz;
+    A.rho = g.rho;
+    A.inv_vc = g.inv_vc;
+    A.emis_lum = g.emis_lum;
+    A.S_pending = f->S_pending;
+    A.U_LL = f->U_LL;
+    A.lt = g.d_lt;
+    A.U_k = g.U_k;
+    A.S_next = f->S_next;
+    A.tally = f->tally;
+    A.counters = (o->flags & DARTRAY_FLAG_COUNTERS) ? f->counters : nullptr;
+    A.queue = g.queue;
+    A.n = n;
+    A.mode = step1 ? 0 : (scatter ? 2 : 1);
+    A.nside0 = o->nside;
+    int l2 = 0;
+    while ((1 << l2) < o->nside) ++l2;
+    A.log2_nside0 = l2;
+    int depth = 0;
+    while ((o->nside << depth) < o->nside_max) ++depth;
+    A.max_depth = depth;
+    A.n_rays = o->n_rays_min;
+    A.f_U = o->f_U;
+    A.a_RT = o->a_RT;
+    A.r_pre_fine = (float)((double)o->r_pre / g.h_fine);
+    A.h_fine = (float)g.h_fine;
+    A.c_light = (float)g.c_light;
+    A.max_steps = o->max_steps;
+    A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
+    const unsigned blocks = 2048;
+    if ((rc = prof_mark(g))) return rc;
+    if (nl <= 1) launch_adaptive<1>(A, A.mode, g.stream, blocks);
+    else if (nl <= 4) launch_adaptive<4>(A, A.mode, g.stream, blocks);
+    else if (nl <= 8) launch_adaptive<8>(A, A.mode, g.stream, blocks);
+    else launch_adaptive<16>(A, A.mode, g.stream, blocks);
+    DR_LAUNCH_CHECK("k_march_adaptive");
+    if ((rc = prof_mark(g))) return rc;
+    return DARTRAY_OK;
+}
+
 static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
 {
     const int nl = g.n_lambda;
@@ -1223,7 +1753,8 @@ int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dar
     Grid &g = grid->g;
     int rc = check_opts(g, opts, fields, false);
     if (rc) return rc;
-    if ((rc = run_fixed_pass(g, opts, fields, false))) return rc;
+    rc = opts->adaptive ? run_adaptive_pass(g, opts, fields, false) : run_fixed_pass(g, opts, fields, false);
+    if (rc) return rc;
     return finish_pass(g, opts, fields, false);
 }
 
@@ -1233,7 +1764,8 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
     Grid &g = grid->g;
     int rc = check_opts(g, opts, fields, true);
     if (rc) return rc;
-    if ((rc = run_fixed_pass(g, opts, fields, true))) return rc;
+    rc = opts->adaptive ? run_adaptive_pass(g, opts, fields, true) : run_fixed_pass(g, opts, fields, true);
+    if (rc) return rc;
     if ((rc = finish_pass(g, opts, fields, true))) return rc;
     if (r_k) {
         const int nl = g.n_lambda;

@@ -14,8 +14,11 @@ namespace dr {
 
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr int kMaxLambda = 64;            // wavelengths per grid
-constexpr int kMaxNsideFixed = 64;        // fixed-mode ray Nside with tabulated directions
 constexpr int kMaxNsideWTable = 16;       // fixed-mode ray Nside with a tabulated phase table
+constexpr int kMaxNsideCap = 1024;        // largest ray Nside of any table
+constexpr int kMaxNsideSca = 8;           // largest Nside of the scattered source function
+constexpr int kScaDirs = 1020;            // pixels of Nside 1, 2, 4 and 8 together
+constexpr int kMaxDepthAdaptive = 12;     // split levels an adaptive ray tree may use
 constexpr double kPi = 3.14159265358979323846;
 
 // Per-wavelength constants used by every kernel (constant memory image).
@@ -71,13 +74,20 @@ struct Grid {
     bool have_s1 = false;
     float *ubar = nullptr;                // direction-binned energy density (fixed mode)
     size_t ubar_floats = 0;
-    float4 *dirs = nullptr;               // fixed-mode direction table
-    float *wtab = nullptr;                // fixed-mode phase weights [r][w_row]
-    int32_t dirs_nside = 0;
+    // direction tables: entry 4 (N^2 - 1) + pix holds nested pixel pix at
+    // Nside N, for N = 1, 2, 4, ... nside_cap, rotated by the current frame
+    int32_t nside_cap = 64;
+    int64_t ndir_all = 0;
+    float4 *dir_all = nullptr;
+    float *invz = nullptr;                // [entry][n_lambda] 1 / sum_p Phi(n_p . n)
+    double *sca64 = nullptr;              // FP64 scattered-light pixel directions, first kScaDirs entries
     double dirs_frame[9] = {0};
     bool dirs_valid = false;
+    bool invz_valid = false;
+    float *wtab = nullptr;                // fixed-mode phase weights [r][w_row]
     int32_t wtab_nside = 0;
     bool wtab_valid = false;
+    unsigned long long *queue = nullptr;  // work counter of the adaptive march
 
     size_t bytes = 0;
 

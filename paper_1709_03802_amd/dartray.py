@@ -64,6 +64,7 @@ class GridDesc(C.Structure):
         ("n_fwhm", C.c_double),
         ("k_max", C.c_int32),
         ("c_light", C.c_double),
+        ("nside_max", C.c_int32),
     ]
 
 
@@ -160,7 +161,7 @@ def _stream_handle(stream):
 class Grid:
     """Device-side grid built from a ``workloads.Grid``."""
 
-    def __init__(self, grid, stream=None):
+    def __init__(self, grid, stream=None, nside_max=None):
         import torch
         L = load_library()
         self.src = grid
@@ -192,6 +193,7 @@ class Grid:
         d.n_fwhm = float(grid.n_fwhm)
         d.k_max = int(grid.k_max)
         d.c_light = float(grid.c_light)
+        d.nside_max = int(nside_max or 0)
         h = C.c_void_p()
         _check(L.dartray_grid_create(C.byref(d), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h

@@ -325,6 +325,15 @@ def disk_small(target_leaves=3000, max_level=4, f_U=1e-3, nside_max=64, n_scatte
     return Workload("disk_small", grid, pol, f"coarse disk octree, {grid.n} leaves")
 
 
+def disk_tiny(target_leaves=600, max_level=3, f_U=1e-3, nside_max=32, n_scatter=2) -> Workload:
+    """A very coarse disk octree (about 1000 leaves) for adaptive-path parity."""
+    grid, tmax = disk_model(target_leaves=target_leaves, max_level=max_level, eps_lum=1e-3, tol=0.3)
+    lo, hi = grid.box()
+    pol = RayPolicy(adaptive=True, nside=4, nside_max=nside_max, n_rays_min=4.0, f_U=f_U,
+                    r_pre=0.15 * float(np.max(hi - lo)), step1=True, n_scatter=n_scatter)
+    return Workload("disk_tiny", grid, pol, f"very coarse disk octree, {grid.n} leaves")
+
+
 def gaussian_field(n: int, slope: float, seed: int) -> np.ndarray:
     """Periodic Gaussian random field with P(k) ~ k^slope, zero mean, unit variance."""
     rng = np.random.default_rng(seed)
@@ -420,6 +429,8 @@ def by_name(name: str) -> Workload:
         return disk()
     if name == "disk_small":
         return disk_small()
+    if name == "disk_tiny":
+        return disk_tiny()
     if name == "clumpy128":
         return clumpy()
     raise KeyError(name)

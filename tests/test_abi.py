@@ -51,7 +51,7 @@ def test_struct_layout_matches_header(tmp_path):
 #include "dartray.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(dartray_grid_desc), sizeof(dartray_trace_opts), sizeof(dartray_fields));
-  printf("%zu %zu %zu %zu\\n", offsetof(dartray_grid_desc, c_light), offsetof(dartray_trace_opts, frame),
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(dartray_grid_desc, c_light), offsetof(dartray_grid_desc, nside_max), offsetof(dartray_trace_opts, frame),
          offsetof(dartray_trace_opts, max_steps), offsetof(dartray_fields, counters));
   return 0;
 }
@@ -61,7 +61,7 @@ int main(void) {
     out = subprocess.check_output([str(exe)]).decode().split()
     got = [int(x) for x in out]
     want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC),
-            dartray.GridDesc.c_light.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
+            dartray.GridDesc.c_light.offset, dartray.GridDesc.nside_max.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
             dartray.FieldsC.counters.offset]
     assert got == want
 
@@ -96,6 +96,7 @@ def _desc(grid):
     d.n_fwhm = 5.0
     d.k_max = 2
     d.c_light = 1.0
+    d.nside_max = 0
     return d, keep
 
 

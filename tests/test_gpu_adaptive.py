@@ -1,0 +1,141 @@
+"""GPU parity of the adaptive path (ray splitting, blocking, per-wavelength
+skip, step 1) against the FP64 oracle.
+
+Each pass is compared in isolation: both sides get the same frozen inputs
+(U_LL and, for scattering passes, the pending scattered luminosity from the
+oracle), so the only differences are FP32 arithmetic and the block/split
+decisions it flips.  A flipped decision moves one ray's contribution between
+neighbouring cells, so the gate is: at least 99% of cells within 1e-4, every
+cell within 1e-2, split and cut counts within 0.1%, luminosity balance within
+1e-6.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1709_03802_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dr():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1709_03802_amd import dartray
+    dartray.load_library()
+    return dartray
+
+
+def as_f32(grid):
+    g = grid.copy()
+    for name in ("rho", "emis", "kappa", "albedo", "g"):
+        setattr(g, name, getattr(g, name).astype(np.float32).astype(np.float64))
+    return g
+
+
+def rel(x, ref):
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    both = (np.abs(ref) > 0) | (np.abs(x) > 0)
+    e = np.abs(x - ref)[both] / np.maximum(np.abs(ref[both]), 1e-300)
+    return e
+
+
+def gate(name, e, frac_tol=0.01, hard=1e-2):
+    bad = float(np.mean(e > 1e-4)) if e.size else 0.0
+    print(f"{name}: max {e.max():.3g} p99 {np.quantile(e, 0.99):.3g} p99.9 {np.quantile(e, 0.999):.3g} "
+          f"frac>1e-4 {bad:.4f}", flush=True)
+    assert bad <= frac_tol, f"{name}: {bad:.4f} of elements above 1e-4"
+    assert e.max() <= hard, f"{name}: max rel err {e.max()}"
+
+
+def check_counts(c_gpu, c_ref, dr, orc):
+    for gi, oi, name in ((dr.C_SPLITS, orc.C_SPLITS, "splits"), (dr.C_CUTS, orc.C_CUTS, "cuts"),
+                         (dr.C_CROSSINGS, orc.C_CROSS, "crossings"), (dr.C_RAYS, orc.C_RAYS, "rays")):
+        a, b = int(c_gpu[gi]), int(c_ref[oi])
+        print(f"  {name}: gpu {a} oracle {b}", flush=True)
+        assert abs(a - b) <= 1e-3 * max(b, 1) + 2, name
+
+
+def check_balance(t):
+    em = t[:, 0]
+    resid = t[:, 1:6].sum(axis=1) - em
+    assert np.all(np.abs(resid) <= 1e-6 * np.abs(em) + 1e-300), resid / em
+
+
+def run_frozen(dr, orc, wl, frame=None):
+    import torch
+    g32 = as_f32(wl.grid)
+    pol = wl.policy
+    m = orc.Model(g32)
+    ref = orc.run(m, pol, frame=frame)
+    G = dr.Grid(g32, nside_max=pol.nside_max)
+    f = dr.Fields(G, keep_pass_u=True)
+    nl, n = G.nl, G.n
+    # step 1
+    dr.trace_direct(G, dr.make_opts(pol, dr.MODE_STEP1, frame), f)
+    torch.cuda.synchronize()
+    r0 = ref.passes[0]
+    gate("step1 U_LL", rel(f.U_LL.cpu().numpy(), r0.U))
+    check_counts(f.counters.cpu().numpy(), r0.counters, dr, orc)
+    check_balance(f.tally.cpu().numpy())
+    U_LL = r0.U.copy()
+    U_run = np.zeros((nl, n))
+    for k in range(1, len(ref.passes)):
+        rk = ref.passes[k]
+        f.U_LL.copy_(torch.as_tensor(U_LL, dtype=torch.float32))
+        if k == 1:
+            dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, frame), f)
+        else:
+            f.S_pending.copy_(torch.as_tensor(np.concatenate([ref.passes[k - 1].S, np.zeros(f.S_pending.numel() - G.s_size)]),
+                                              dtype=torch.float32))
+            dr.scatter_iter(G, dr.make_opts(pol, dr.MODE_DIRECT, frame), f)
+        torch.cuda.synchronize()
+        gate(f"pass {k} U_k", rel(f.U_pass.cpu().numpy(), rk.U))
+        gate(f"pass {k} S", rel(f.S_pending.cpu().numpy()[:G.s_size], rk.S))
+        t = f.tally.cpu().numpy()
+        check_balance(t)
+        np.testing.assert_allclose(t[:, 0], rk.tally[:, 0], rtol=1e-5)
+        check_counts(f.counters.cpu().numpy(), rk.counters, dr, orc)
+        U_run += rk.U
+        U_LL = U_run.copy()
+    G.close()
+
+
+def test_adaptive_disk_tiny_frozen_passes(dr, orc):
+    run_frozen(dr, orc, W.disk_tiny())
+
+
+def test_adaptive_disk_tiny_rotated(dr, orc):
+    run_frozen(dr, orc, W.disk_tiny(n_scatter=1), frame=W.rotation(8))
+
+
+def test_adaptive_without_splitting_equals_fixed_rays(dr, orc):
+    # nside_max = nside and f_U = 0: no split, no block -> the fixed-ray result
+    import torch
+    wl = W.plain16(n=8, nside=4, lambdas=np.array([0.3, 1.0]))
+    g32 = as_f32(wl.grid)
+    pa = W.RayPolicy(adaptive=True, nside=4, nside_max=4, f_U=0.0, step1=False, n_scatter=1)
+    G = dr.Grid(g32)
+    a = dr.run(G, pa)
+    b = dr.run(G, wl.policy, passes=2)
+    torch.cuda.synchronize()
+    e = rel(a.fields.U.cpu().numpy(), b.fields.U.cpu().numpy())
+    assert e.max() < 1e-5
+    e = rel(a.fields.S_total.cpu().numpy()[:G.s_size], b.fields.S_total.cpu().numpy()[:G.s_size])
+    assert e.max() < 1e-5
+
+
+def test_adaptive_end_to_end_disk_tiny(dr, orc):
+    # chained passes on both sides; decisions may flip and propagate
+    import torch
+    wl = W.disk_tiny()
+    g32 = as_f32(wl.grid)
+    ref = orc.run(orc.Model(g32), wl.policy)
+    G = dr.Grid(g32, nside_max=wl.policy.nside_max)
+    out = dr.run(G, wl.policy)
+    torch.cuda.synchronize()
+    gate("end-to-end U", rel(out.fields.U.cpu().numpy(), ref.U))
+    for t in out.tallies:
+        check_balance(t)
