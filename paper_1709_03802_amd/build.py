@@ -11,7 +11,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdartray.so")
+CEIL_LIB = os.path.join(PKG, "libdrceil.so")
 SOURCES = [os.path.join(CSRC, "dartray.hip")]
+CEIL_SOURCES = [os.path.join(CSRC, "ceilings.hip")]
 HEADERS = [os.path.join(CSRC, "dr_internal.h"), os.path.join(INCLUDE, "dartray.h")]
 
 HIPCC_FLAGS = [
@@ -31,12 +33,13 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Always recompiles (the caller decides when to build)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    for lib, srcs in ((LIB, SOURCES), (CEIL_LIB, CEIL_SOURCES)):
+        tmp = lib + ".tmp"
+        cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -284,7 +284,7 @@ __global__ void k_scan_scatter(const int32_t *flags, const int32_t *morton, int6
 // ---------------------------------------------------------------------------
 
 struct Geo {
-    const int4 *leaf_box;
+    const LeafRec *rec;
     const int32_t *root_tab;
     const int32_t *nodes;
     int32_t fine[3];
@@ -344,18 +344,18 @@ __device__ inline float exit_t(const Ray &R, const int4 b, int &axis)
     return best;
 }
 
-// the face neighbour across the exit face that contains the exit point
-template <bool UNIFORM>
-__device__ inline int32_t next_leaf(const Geo &g, const Ray &R, const int4 b, int axis, float te)
+// the leaf across the exit face that contains the exit point: one load of the
+// face-neighbour code, plus a descent when the region across is subdivided
+__device__ inline int32_t next_leaf(const Geo &g, const Ray &R, const int4 b, const int32_t *nb, int axis, float te)
 {
+    const int32_t code = nb[2 * axis + (R.n[axis] > 0.f ? 1 : 0)];
+    if (code >= -1) return code;            // a leaf, or outside the root block
     const int lo[3] = {b.x, b.y, b.z};
     int f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (a == axis) {
             f[a] = R.n[a] > 0.f ? lo[a] + b.w : lo[a] - 1;
-        } else if (UNIFORM) {
-            f[a] = lo[a];
         } else {
             int q = fine_coord(fmaf(te, R.n[a], R.o[a]), R.n[a]);
             q = q < lo[a] ? lo[a] : q;
@@ -363,7 +363,14 @@ __device__ inline int32_t next_leaf(const Geo &g, const Ray &R, const int4 b, in
             f[a] = q;
         }
     }
-    return locate_fine(g, f[0], f[1], f[2]);
+    int32_t v = -code - 2;                  // internal node at this leaf's level
+    int bit = 30 - __clz(b.w);              // log2(span) - 1
+    while (v >= 0) {
+        const int oct = ((f[0] >> bit) & 1) | (((f[1] >> bit) & 1) << 1) | (((f[2] >> bit) & 1) << 2);
+        v = g.nodes[v * 8 + oct];
+        --bit;
+    }
+    return -v - 1;
 }
 
 __global__ void k_debug_cells(Geo g, int nrays, const double *origin, const double *dir, int max_cross,
@@ -383,14 +390,15 @@ __global__ void k_debug_cells(Geo g, int nrays, const double *origin, const doub
     float t = 0.f;
     int m = 0;
     while (c >= 0 && m < max_cross) {
-        const int4 b = g.leaf_box[c];
+        const LeafRec &rc = g.rec[c];
+        const int4 b = rc.box;
         int axis;
         const float te = exit_t(R, b, axis);
         cells[(int64_t)i * max_cross + m] = c;
         lengths[(int64_t)i * max_cross + m] = te > t ? te - t : 0.f;
         ++m;
         if (te > t) t = te;
-        c = next_leaf<false>(g, R, b, axis, te);
+        c = next_leaf(g, R, b, rc.nb, axis, te);
     }
     counts[i] = m;
 }
@@ -405,8 +413,6 @@ struct FixedArgs {
     const int32_t *src_list;
     const int32_t *n_src;
     const float4 *dirs;
-    const float *rho;
-    const float *inv_vc;
     const float *emis_lum;       // direct pass
     const float *S_pending;      // scatter pass
     const LambdaTable *lt;
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
         R.n[0] = nd.x;
         R.n[1] = nd.y;
         R.n[2] = nd.z;
-        int4 b = A.geo.leaf_box[s];
+        int4 b = A.geo.rec[s].box;
         const float half = 0.5f * (float)b.w;
         R.o[0] = (float)b.x + half;
         R.o[1] = (float)b.y + half;
@@ -496,12 +502,17 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
         float t = 0.f;
         int64_t steps = 0;
         while (true) {
+            const LeafRec &rc = A.geo.rec[c];
+            b = rc.box;
+            const float rho = rc.rho;
+            const float ivc = rc.ivc;
+            int32_t nbc[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
             int axis;
             const float te = exit_t(R, b, axis);
             const float len = te - t;
             if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
-                const float rho = A.rho[c];
-                const float ivc = A.inv_vc[c];
                 const float lp = len * A.h_fine;
                 float *ub = A.ubar + (size_t)rl * A.n + c;
                 const size_t lstride = (size_t)A.nb * A.n;
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
                 ++ncross;
                 t = te;
             }
-            const int32_t nx = next_leaf<UNIFORM>(A.geo, R, b, axis, te);
+            const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
             if (nx < 0) break;
             ++steps;
             if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
@@ -528,7 +539,6 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
                 break;
             }
             c = nx;
-            b = A.geo.leaf_box[c];
         }
 #pragma unroll
         for (int l = 0; l < NL; ++l) esc[l] += L[l];
@@ -593,7 +603,7 @@ __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const fl
     float *srow = S_next + lt->s_off[l] + c * (int64_t)npix + p0;
 #pragma unroll
     for (int j = 0; j < PCH; ++j) srow[j] += f * acc[j];
-    if (blockIdx.y == 0) U_k[(int64_t)l * n + c] += accU;
+    if (blockIdx.y == 0) U_k[c * lt->n_lambda + l] += accU;
 }
 
 // ---------------------------------------------------------------------------
@@ -621,12 +631,9 @@ struct AdaptArgs {
     const int32_t *n_src;
     const float4 *dirs;          // all-level direction table
     const float *invz;           // [entry][n_lambda]
-    const float *rho;
-    const float *inv_vc;
     const float *emis_lum;
     const float *S_pending;
-    const float *U_LL;
-    const uint8_t *mask;
+    const float *ull_t;          // [n][n_lambda] copy of U_LL
     const LambdaTable *lt;
     float *U_k;
     float *S_next;
@@ -659,92 +666,67 @@ template <int NL, int MODE>
 __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
 {
     constexpr bool STEP1 = MODE == 0;
-    __shared__ float4 sca[kScaDirs];
-    for (int i = threadIdx.x; i < kScaDirs; i += blockDim.x) sca[i] = A.dirs[i];
-    __syncthreads();
-
+    constexpr int kBlock = 256;
+    __shared__ float4 sca[STEP1 ? 1 : kScaDirs];
+    __shared__ float s_kap[NL], s_alb[NL], s_hgA[NL], s_hgB[NL], s_hgC[NL];
+    __shared__ double s_esc[NL], s_cut[NL];
+    // per-thread deposit staging for the cooperative scattered-light deposit
+    __shared__ float s_F[STEP1 ? 1 : NL][STEP1 ? 1 : kBlock];
+    __shared__ float4 s_dep[STEP1 ? 1 : kBlock];     // direction xyz, cell id (bits) in w
+    // energy-density deposits of the step, written out wave-cooperatively:
+    // one atomic instruction stores the NL values of 64 / NL crossings
+    __shared__ float s_du[NL][kBlock];
+    __shared__ int32_t s_cell[kBlock];
+    __shared__ uint8_t s_list[kBlock];
     const LambdaTable *lt = A.lt;
     const int nl = lt->n_lambda;
+    if (!STEP1)
+        for (int i = threadIdx.x; i < kScaDirs; i += blockDim.x) sca[i] = A.dirs[i];
+    if (threadIdx.x < NL) {
+        const int l = threadIdx.x;
+        const float g = l < nl ? lt->g[l] : 0.f;
+        s_kap[l] = l < nl ? lt->kappa[l] : 0.f;
+        s_alb[l] = l < nl ? lt->albedo[l] : 0.f;
+        s_hgA[l] = (1.f - g * g) / (4.f * 3.14159265358979f);   // Henyey-Greenstein prefactor
+        s_hgB[l] = 1.f + g * g;
+        s_hgC[l] = -2.f * g;
+        s_esc[l] = 0.0;
+        s_cut[l] = 0.0;
+    }
+    __syncthreads();
+
     const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
     const int nsrc = *A.n_src;
     const uint64_t nitems = (uint64_t)nsrc * (uint64_t)(12 * A.nside0 * A.nside0);
     const float f_U = A.f_U >= 0.f ? A.f_U : (nsrc > 0 ? 4.f * A.a_RT / (float)nsrc : 0.f);
 
-    float kap[NL], hgA[NL], hgB[NL], hgC[NL];
+    float skp[NL];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        const float g = l < nl ? lt->g[l] : 0.f;
-        kap[l] = l < nl ? lt->kappa[l] : 0.f;
-        hgA[l] = (1.f - g * g) / (4.f * 3.14159265358979f);   // HG prefactor
-        hgB[l] = 1.f + g * g;
-        hgC[l] = -2.f * g;
-    }
-
-    // tallies and counters of this lane
-    float esc[NL], cut[NL], skp[NL];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) esc[l] = cut[l] = skp[l] = 0.f;
+    for (int l = 0; l < NL; ++l) skp[l] = 0.f;
     uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_skip = 0, n_max = 0;
 
     // ray state
-    bool has_ray = false;
-    bool has_item = false;
-    bool done = false;            // the work counter is exhausted for this lane
+    bool has_ray = false, has_item = false, pending = false, done = false;
     int32_t s = 0;
     float o[3] = {0.f, 0.f, 0.f};
     int depth = 0;
     int pix = 0;
     float t = 0.f;
     int32_t c = -1;
-    int4 b = make_int4(0, 0, 0, 1);
+    int64_t e = 0;                 // direction table entry of the ray
     Ray R;
-    float L[NL], iz[NL];
+    float L[NL];
     float st_t[kMaxDepthAdaptive + 1];
     float st_L[kMaxDepthAdaptive + 1][NL];
     int64_t steps = 0;
     float omega_hp = 0.f;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) L[l] = iz[l] = 0.f;
-
-    // set up the ray (depth, pix) from distance t: direction, 1/Z, first cell
-    auto start_ray = [&]() {
-        const int64_t N = (int64_t)A.nside0 << depth;
-        const int64_t e = entry_of(N, pix);
-        const float4 nd = A.dirs[e];
-        R.n[0] = nd.x;
-        R.n[1] = nd.y;
-        R.n[2] = nd.z;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            R.o[a] = o[a];
-            R.inv[a] = 1.0f / R.n[a];
-        }
-        if (!STEP1) {
-#pragma unroll
-            for (int l = 0; l < NL; ++l) iz[l] = l < nl ? A.invz[e * nl + l] : 0.f;
-        }
-        omega_hp = 3.14159265358979f / (3.f * (float)N * (float)N);   // 4 pi / (12 N^2)
-        steps = 0;
-        if (t == 0.f) {
-            c = s;
-        } else {
-            c = locate_fine(A.geo, fine_coord(fmaf(t, R.n[0], o[0]), R.n[0]),
-                            fine_coord(fmaf(t, R.n[1], o[1]), R.n[1]), fine_coord(fmaf(t, R.n[2], o[2]), R.n[2]));
-        }
-        if (c >= 0) {
-            b = A.geo.leaf_box[c];
-            has_ray = true;
-        } else {
-#pragma unroll
-            for (int l = 0; l < NL; ++l) esc[l] += L[l];
-            ++n_esc;
-            has_ray = false;
-        }
-    };
+    for (int l = 0; l < NL; ++l) L[l] = 0.f;
 
     while (true) {
-        // ---- lanes without a ray: next sibling, or a new item
-        if (!has_ray && has_item) {
+        // ---- lanes without a ray: next sibling from the stack
+        if (!has_ray && !pending && has_item) {
             while (depth > 0 && (pix & 3) == 3) {
                 --depth;
                 pix >>= 2;
@@ -754,24 +736,27 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                 t = st_t[depth];
 #pragma unroll
                 for (int l = 0; l < NL; ++l) L[l] = st_L[depth][l];
-                start_ray();
+                pending = true;
             } else {
                 has_item = false;
             }
         }
-        const uint64_t need = __ballot(!has_ray && !has_item && !done);
+        // ---- ... or a new item (top pixel r0, source), 64 at a time per wave
+        const bool want = !has_ray && !pending && !has_item && !done;
+        const uint64_t need = __ballot(want);
         if (need) {
-            const int k = __popcll(need);
+            const int leader = __ffsll((unsigned long long)need) - 1;
             unsigned long long base = 0;
-            if (lane == __ffsll((unsigned long long)need) - 1) base = atomicAdd(A.queue, (unsigned long long)k);
-            base = __shfl(base, __ffsll((unsigned long long)need) - 1, 64);
-            if (!has_ray && !has_item && !done) {
+            if (lane == leader) base = atomicAdd(A.queue, (unsigned long long)__popcll(need));
+            base = __shfl(base, leader, 64);
+            if (want) {
                 const uint64_t it = base + __popcll(need & ((1ull << lane) - 1ull));
-                if (it >= nitems) done = true;
-                if (it < nitems) {
+                if (it >= nitems) {
+                    done = true;
+                } else {
                     const int r0 = (int)(it / (uint64_t)nsrc);
                     s = A.src_list[it - (uint64_t)r0 * nsrc];
-                    const int4 sb = A.geo.leaf_box[s];
+                    const int4 sb = A.geo.rec[s].box;
                     const float half = 0.5f * (float)sb.w;
                     o[0] = (float)sb.x + half;
                     o[1] = (float)sb.y + half;
@@ -800,32 +785,60 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                         lsum += v;
                     }
                     has_item = true;
+                    depth = 0;
+                    pix = r0;
+                    t = 0.f;
                     if (lsum > 0.f) {
                         ++n_rays;
-                        depth = 0;
-                        pix = r0;
-                        t = 0.f;
-                        start_ray();
-                    } else {
-                        depth = 0;
-                        pix = 3;   // nothing to trace; the item ends at the next refill
+                        pending = true;
                     }
                 }
             }
         }
+        // ---- start pending rays: direction, first cell
+        if (pending) {
+            pending = false;
+            const int64_t N = (int64_t)A.nside0 << depth;
+            e = entry_of(N, pix);
+            const float4 nd = A.dirs[e];
+            R.n[0] = nd.x;
+            R.n[1] = nd.y;
+            R.n[2] = nd.z;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R.o[a] = o[a];
+                R.inv[a] = 1.0f / R.n[a];
+            }
+            omega_hp = 3.14159265358979f / (3.f * (float)N * (float)N);   // 4 pi / (12 N^2)
+            steps = 0;
+            c = (t == 0.f) ? s
+                           : locate_fine(A.geo, fine_coord(fmaf(t, R.n[0], o[0]), R.n[0]),
+                                         fine_coord(fmaf(t, R.n[1], o[1]), R.n[1]),
+                                         fine_coord(fmaf(t, R.n[2], o[2]), R.n[2]));
+            if (c >= 0) {
+                has_ray = true;
+            } else {
+#pragma unroll
+                for (int l = 0; l < NL; ++l)
+                    if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
+                ++n_esc;
+            }
+        }
         if (__ballot(has_ray) == 0) {
-            if (__ballot(has_item) == 0) break;
+            if (__ballot(has_item || pending) == 0) break;
             continue;
         }
-        (void)done;
 
         // ---- one crossing per lane with a ray
         bool deposit = false;
-        float F[NL];
-#pragma unroll
-        for (int l = 0; l < NL; ++l) F[l] = 0.f;
-        int32_t cdep = 0;
+        bool udep = false;
         if (has_ray) {
+            const LeafRec &rc = A.geo.rec[c];
+            const int4 b = rc.box;
+            const float rho_c = rc.rho;
+            int32_t nbc[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
             int axis;
             const float te = exit_t(R, b, axis);
             const float len = te - t;
@@ -839,36 +852,33 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                 const float d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
                 const float side = (float)b.w * h;
                 const float lp = len * h;
-                const float rho_c = A.rho[c];
-                float ext[NL], em1[NL];
-                bool sig[NL];
-                bool any_sig = false;
+                float em1[NL];
+                uint32_t sigm = 0;
                 const float thr = f_U * omega_hp * d2 * A.c_light;
+                const float *ull = A.ull_t + (int64_t)c * nl;
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
-                    sig[l] = false;
-                    ext[l] = 0.f;
                     em1[l] = 0.f;
                     if (l < nl) {
-                        const float tau = kap[l] * rho_c * lp;
+                        const float tau = s_kap[l] * rho_c * lp;
                         em1[l] = expm1f(-tau);
-                        ext[l] = -L[l] * em1[l];
-                        if (STEP1) {
-                            sig[l] = true;
-                        } else {
-                            const float lavg = tau > 0.f ? ext[l] / tau : L[l];
-                            sig[l] = lavg > 0.f && (d2 == 0.f || lavg >= thr * A.U_LL[(int64_t)l * A.n + c]);
+                        bool sg = true;
+                        if (!STEP1) {
+                            const float ext = -L[l] * em1[l];
+                            const float lavg = tau > 0.f ? ext / tau : L[l];
+                            sg = lavg > 0.f && (d2 == 0.f || lavg >= thr * ull[l]);
                         }
-                        any_sig |= sig[l];
+                        sigm |= (uint32_t)sg << l;
                     }
                 }
                 if (STEP1 && t_in >= A.r_pre_fine) {
                     action = 2;
                 } else if (d2 > 0.f && omega_hp * A.n_rays * d2 > side * side) {   // Eq. 2
-                    if (any_sig && depth < A.max_depth) action = 1;
-                    else if (!any_sig) action = 2;
+                    if (sigm && depth < A.max_depth) action = 1;
+                    else if (!sigm) action = 2;
                 }
                 if (action == 1) {
+                    // split: child 0 starts next iteration, siblings wait on the stack
                     ++n_split;
                     ++depth;
                     st_t[depth] = t_in;
@@ -879,45 +889,54 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                     }
                     pix = 4 * pix;
                     t = t_in;
-                    start_ray();
+                    has_ray = false;
+                    pending = true;
                 } else if (action == 2) {
                     ++n_cut;
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) cut[l] += L[l];
+                    for (int l = 0; l < NL; ++l)
+                        if (l < nl) atomicAdd(&s_cut[l], (double)L[l]);
                     has_ray = false;
                 } else {
-                    const float ivc = A.inv_vc[c];
+                    const float ivc = rc.ivc;
                     ++n_cross;
+                    udep = true;
+                    s_cell[threadIdx.x] = c;
+                    const float *izr = A.invz + e * nl;
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
                         if (l < nl) {
-                            if (sig[l]) {
-                                const float alpha = kap[l] * rho_c;
-                                const float du = alpha > 0.f ? ext[l] * (ivc / alpha) : L[l] * lp * ivc;
-                                atomic_add_f32(A.U_k + (int64_t)l * A.n + c, du);
+                            const float ext = -L[l] * em1[l];
+                            float Fl = 0.f;
+                            float du = 0.f;
+                            if ((sigm >> l) & 1u) {
+                                const float alpha = s_kap[l] * rho_c;
+                                du = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
                                 ++n_dep;
-                                if (!STEP1) F[l] = lt->albedo[l] * ext[l] * iz[l] * hgA[l];
+                                if (!STEP1) Fl = s_alb[l] * ext * izr[l] * s_hgA[l];
                             } else {
-                                skp[l] += ext[l];
+                                skp[l] += ext;
                                 ++n_skip;
                             }
+                            if (!STEP1) {
+                                s_F[l][threadIdx.x] = Fl;
+                                deposit |= Fl != 0.f;
+                            }
+                            s_du[l][threadIdx.x] = du;
                             L[l] = fmaf(L[l], em1[l], L[l]);
                         }
                     }
-                    if (!STEP1) {
-#pragma unroll
-                        for (int l = 0; l < NL; ++l) deposit |= F[l] != 0.f;
-                    }
-                    cdep = c;
+                    if (!STEP1 && deposit) s_dep[threadIdx.x] = make_float4(R.n[0], R.n[1], R.n[2], __int_as_float(c));
                     t = te;
                 }
             }
             if (has_ray && action == 0) {
-                const int32_t nx = next_leaf<false>(A.geo, R, b, axis, te);
+                const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
                 ++steps;
                 if (nx < 0) {
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) esc[l] += L[l];
+                    for (int l = 0; l < NL; ++l)
+                        if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
                     ++n_esc;
                     has_ray = false;
                 } else if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
@@ -925,60 +944,68 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                     has_ray = false;
                 } else {
                     c = nx;
-                    b = A.geo.leaf_box[c];
                 }
             }
         }
 
-        // ---- cooperative scattered-light deposit
+        // ---- energy-density deposits: lanes q of an instruction take value
+        // q % NL of the (q / NL)-th depositing lane, so each crossing's NL
+        // values go out as one contiguous request
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        {
+            const uint64_t um = __ballot(udep);
+            if (udep) s_list[wbase + __popcll(um & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int cnt = __popcll(um);
+            constexpr int PER = 64 / NL;
+            for (int k0 = 0; k0 < cnt; k0 += PER) {
+                const int q = k0 + lane / NL;
+                const int l = lane % NL;
+                if (q < cnt && l < nl) {
+                    const int j = s_list[wbase + q];
+                    const float v = s_du[l][wbase + j];
+                    if (v != 0.f) atomic_add_f32(A.U_k + (int64_t)s_cell[wbase + j] * nl + l, v);
+                }
+            }
+        }
+
+        // ---- cooperative scattered-light deposit: for each depositing lane,
+        // the wave adds its phase-weighted luminosity to the cell's pixel row
         if (!STEP1) {
             uint64_t m = __ballot(deposit);
             while (m) {
                 const int j = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
-                const int cj = readlane_i(cdep, j);
-                const float nx = readlane_f(R.n[0], j), ny = readlane_f(R.n[1], j), nz = readlane_f(R.n[2], j);
+                const float4 dj = s_dep[wbase + j];
+                const int cj = __float_as_int(dj.w);
                 for (int l = 0; l < nl; ++l) {
-                    float Fl = 0.f;
-#pragma unroll
-                    for (int q = 0; q < NL; ++q)
-                        if (q == l) Fl = F[q];
-                    const float Fj = readlane_f(Fl, j);
+                    const float Fj = s_F[l][wbase + j];
                     if (Fj == 0.f) continue;
                     const int npix = lt->npix[l];
                     const int base = (int)entry_of(lt->nside_sca[l], 0);
                     float *dst = A.S_next + lt->s_off[l] + (int64_t)cj * npix;
-                    float B = 0.f, Cc = 0.f;
-#pragma unroll
-                    for (int q = 0; q < NL; ++q)
-                        if (q == l) {
-                            B = hgB[q];
-                            Cc = hgC[q];
-                        }
+                    const float B = s_hgB[l], Cc = s_hgC[l];
                     for (int p = lane; p < npix; p += 64) {
                         const float4 v = sca[base + p];
-                        const float mu = fmaf(v.x, nx, fmaf(v.y, ny, v.z * nz));
-                        const float den = fmaf(Cc, mu, B);
-                        const float r = rsqrtf(den);
+                        const float mu = fmaf(v.x, dj.x, fmaf(v.y, dj.y, v.z * dj.z));
+                        const float r = rsqrtf(fmaf(Cc, mu, B));
                         atomic_add_f32(dst + p, Fj * (r * r * r));
                     }
                 }
             }
         }
     }
+    (void)done;
 
-    // ---- wave-level FP64 tallies
+    // ---- FP64 tallies: skipped per wave, escaped and cut per block
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         if (l < nl) {
-            const double ve = wave_sum((double)esc[l]);
-            const double vc = wave_sum((double)cut[l]);
             const double vs = wave_sum((double)skp[l]);
-            if (lane == 0) {
-                if (ve != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], ve);
-                if (vc != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_CUT], vc);
-                if (vs != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_SKIPPED], vs);
-            }
+            if (lane == 0 && vs != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_SKIPPED], vs);
         }
     }
     if (A.counters) {
@@ -987,6 +1014,12 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
         if (lane == 0)
             for (int i = 0; i < 8; ++i)
                 if (v[i]) atomicAdd((unsigned long long *)&A.counters[i], (unsigned long long)v[i]);
+    }
+    __syncthreads();
+    if (threadIdx.x < NL && threadIdx.x < nl) {
+        const int l = threadIdx.x;
+        if (s_esc[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], s_esc[l]);
+        if (s_cut[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_CUT], s_cut[l]);
     }
 }
 
@@ -1000,7 +1033,7 @@ __global__ void k_finish_u(const float *U_k, float *U, float *U_pass, float *U_L
     double ext = 0.0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = (int64_t)l * n + c;
-        const float uk = U_k[i];
+        const float uk = U_k[c * lt->n_lambda + l];
         if (ull_only) {
             U_LL[i] = uk;
         } else {
@@ -1035,6 +1068,24 @@ __global__ void k_finish_s(const float *S_next, float *S_total, float *S_pending
     }
     const double b = block_sum(acc, sh);
     if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&ssum[l], b);
+}
+
+// [nl][n] -> [n][nl]
+__global__ void k_transpose_ull(const float *U_LL, float *ull_t, int64_t n, int nl)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * nl; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / nl;
+        const int l = (int)(i - c * nl);
+        ull_t[i] = U_LL[(int64_t)l * n + c];
+    }
+}
+
+__global__ void k_set_rho(LeafRec *rec, float *rho_arr, const float *rho, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        rec[i].rho = rho[i];
+        rho_arr[i] = rho[i];
+    }
 }
 
 __global__ void k_check_finite(const float *a, int64_t n, int32_t *bad)
@@ -1098,7 +1149,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
+    void *ptrs[] = {g.rec, g.ull_t, g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
                     g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.invz, g.sca64, g.wtab, g.queue};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1231,6 +1282,37 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     for (int32_t v : nodes)
         if (v == kUnset) return fail(DARTRAY_E_INVALID, "leaves do not tile the root block");
 
+    // leaf records with face-neighbour codes
+    auto region_code = [&](int lv, const int64_t q[3]) -> int32_t {
+        for (int a = 0; a < 3; ++a)
+            if (q[a] < 0 || q[a] >= ((int64_t)d->nroot[a] << lv)) return -1;
+        const int64_t root = ((q[2] >> lv) * d->nroot[1] + (q[1] >> lv)) * d->nroot[0] + (q[0] >> lv);
+        int32_t code = root_tab[(size_t)root];
+        for (int lev = 0; lev < lv; ++lev) {
+            if (code < 0) return -code - 1;          // a coarser leaf covers the region
+            const int bit = lv - lev - 1;
+            const int oct = (int)(((q[0] >> bit) & 1) | (((q[1] >> bit) & 1) << 1) | (((q[2] >> bit) & 1) << 2));
+            code = nodes[(size_t)code * 8 + oct];
+        }
+        return code < 0 ? (-code - 1) : -(code + 2);
+    };
+    std::vector<LeafRec> recs((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        LeafRec &r = recs[(size_t)i];
+        std::memset(&r, 0, sizeof(r));
+        r.box = boxes[(size_t)i];
+        r.rho = d->rho[i];
+        r.ivc = inv_vc[(size_t)i];
+        r.level = d->leaf_level[i];
+        const int lv = d->leaf_level[i];
+        for (int a = 0; a < 3; ++a)
+            for (int dir = 0; dir < 2; ++dir) {
+                int64_t q[3] = {d->leaf_ijk[3 * i], d->leaf_ijk[3 * i + 1], d->leaf_ijk[3 * i + 2]};
+                q[a] += dir ? 1 : -1;
+                r.nb[2 * a + dir] = region_code(lv, q);
+            }
+    }
+
     std::vector<int32_t> morton((size_t)n);
     for (int64_t i = 0; i < n; ++i) morton[i] = (int32_t)i;
     std::stable_sort(morton.begin(), morton.end(), [&](int32_t a, int32_t b) { return keys[a] < keys[b]; });
@@ -1288,6 +1370,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, ((size_t)8 << 30) / (4 * per_dir)));
     int rcs[] = {
         dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
+        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
         dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.d_lt, 1),
         dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
@@ -1314,6 +1397,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
     };
     cp(g.leaf_box, boxes.data(), sizeof(int4) * n);
+    cp(g.rec, recs.data(), sizeof(LeafRec) * n);
     cp(g.rho, rho_f.data(), sizeof(float) * n);
     cp(g.inv_vc, inv_vc.data(), sizeof(float) * n);
     cp(g.emis_lum, emis_lum.data(), sizeof(float) * nl * n);
@@ -1390,7 +1474,9 @@ int dartray_grid_set_rho(dartray_grid *grid, const float *rho_device)
 {
     if (!grid || !rho_device) return fail(DARTRAY_E_INVALID, "null argument");
     Grid &g = grid->g;
-    DR_HIP(hipMemcpyAsync(g.rho, rho_device, sizeof(float) * g.n, hipMemcpyDeviceToDevice, g.stream));
+    hipLaunchKernelGGL(k_set_rho, dim3((unsigned)std::min<int64_t>((g.n + 255) / 256, 4096)), dim3(256), 0, g.stream,
+                       g.rec, g.rho, rho_device, g.n);
+    DR_LAUNCH_CHECK("k_set_rho");
     return DARTRAY_OK;
 }
 
@@ -1424,7 +1510,7 @@ int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *or
     if (e == hipSuccess) e = hipMemcpyAsync(d_o, o.data(), sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice, g.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_d, dd.data(), sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice, g.stream);
     if (e == hipSuccess) {
-        Geo geo{g.leaf_box, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]},
+        Geo geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]},
                 {g.nroot[0], g.nroot[1], g.nroot[2]}, g.max_level};
         hipLaunchKernelGGL(k_debug_cells, dim3((n_rays + 63) / 64), dim3(64), 0, g.stream, geo, n_rays, d_o, d_d,
                            max_cross, d_c, d_l, d_n);
@@ -1595,13 +1681,11 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     const size_t per_dir = (size_t)nl * n;
     const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
     FixedArgs A{};
-    A.geo = Geo{g.leaf_box, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
+    A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
     A.src_list = g.src_list;
     A.n_src = g.n_src;
     A.dirs = g.dir_all + entry_of(o->nside, 0);
-    A.rho = g.rho;
-    A.inv_vc = g.inv_vc;
     A.emis_lum = g.emis_lum;
     A.S_pending = f->S_pending;
     A.lt = g.d_lt;
@@ -1673,19 +1757,22 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
     if ((rc = fill<unsigned long long>(g, g.queue, 1, 0ull))) return rc;
     if ((rc = select_sources(g, o, f, scatter))) return rc;
+    if (!step1) {
+        hipLaunchKernelGGL(k_transpose_ull, dim3((unsigned)std::min<int64_t>((n * nl + 255) / 256, 8192)), dim3(256), 0,
+                           g.stream, f->U_LL, g.ull_t, n, nl);
+        DR_LAUNCH_CHECK("k_transpose_ull");
+    }
 
     AdaptArgs A{};
-    A.geo = Geo{g.leaf_box, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
+    A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
     A.src_list = g.src_list;
     A.n_src = g.n_src;
     A.dirs = g.dir_all;
     A.invz = g.invz;
-    A.rho = g.rho;
-    A.inv_vc = g.inv_vc;
     A.emis_lum = g.emis_lum;
     A.S_pending = f->S_pending;
-    A.U_LL = f->U_LL;
+    A.ull_t = g.ull_t;
     A.lt = g.d_lt;
     A.U_k = g.U_k;
     A.S_next = f->S_next;

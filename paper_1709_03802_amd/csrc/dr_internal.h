@@ -34,6 +34,20 @@ struct LambdaTable {
     int32_t w_off[kMaxLambda + 1];        // start of wavelength l in a per-direction weight row
 };
 
+// One leaf, one 64-byte record: box in finest-level units, density,
+// 1/(V c), and the six face-neighbour codes (index 2*axis + (direction > 0)):
+// a leaf id (>= 0) when one leaf covers the same-size region across the face,
+// -1 outside the root block, -(node + 2) when that region is subdivided.
+struct alignas(64) LeafRec {
+    int4 box;          // x, y, z lower corner, span
+    float rho;
+    float ivc;         // 1 / (V c)
+    int32_t nb[6];
+    int32_t level;
+    int32_t pad[3];
+};
+static_assert(sizeof(LeafRec) == 64, "leaf record must be one 64-byte line");
+
 struct Grid {
     // geometry
     int64_t n = 0;
@@ -55,6 +69,7 @@ struct Grid {
 
     // device arrays owned by the handle
     int4 *leaf_box = nullptr;             // lower corner in fine units + span
+    LeafRec *rec = nullptr;               // [n] leaf records
     float *rho = nullptr;
     float *inv_vc = nullptr;              // 1 / (V c)
     float *emis_lum = nullptr;            // [nl][n] 4 pi j V
@@ -64,7 +79,8 @@ struct Grid {
     LambdaTable *d_lt = nullptr;
 
     // work arrays
-    float *U_k = nullptr;                 // [nl][n]
+    float *U_k = nullptr;                 // [n][nl] (wavelength fastest)
+    float *ull_t = nullptr;               // [n][nl] copy of U_LL for the march
     int32_t *flags = nullptr;             // [n] source flags, then scan
     int32_t *src_list = nullptr;          // [n] compacted sources
     int32_t *scan_blocks = nullptr;       // block sums
