@@ -1,12 +1,16 @@
 """Benchmark of the ray-march hot path on one MI355X.
 
-A step is one whole radiative-transfer run of the workload: (step 1,) the
-direct-light pass and the scattering iterations, every ray-cell crossing at
-every wavelength the rays carry.  The metric is ray-cell crossings x
-wavelengths per second, with the device's own crossing counter as numerator.
-The same run checks the result against the FP64 oracle (full workload when the
-oracle finishes in seconds, otherwise a source subset) and times the oracle on
-the host cores as the CPU baseline.
+A step is one whole radiative-transfer run of the workload: step 1 (adaptive
+rays), the direct-light pass and the scattering iterations, over every
+emitting cell, every ray-cell crossing at every wavelength the rays carry.
+The metric is ray-cell crossings x wavelengths per second; the numerator is
+the device's own crossing counter from the first (untimed) run.
+
+The same invocation checks the GPU against the FP64 oracle (on a seeded
+source subset when the oracle cannot run the whole workload in seconds),
+checks the FP64 luminosity balance of every pass, times the oracle on the
+host cores as the CPU baseline, and measures the dominant march kernel with
+HIP events on the library's stream for the roofline figure.
 
 Prints one JSON line.
 """
@@ -15,7 +19,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -36,92 +39,125 @@ def as_f32(grid):
     return g
 
 
-def make_workload(name):
-    from paper_1709_03802_amd import workloads as W
-    return W.by_name(name)
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain16")
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="disk", choices=["disk", "plain16", "plain16_l32", "plain16_l4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--sample-sources", type=int, default=96,
+                    help="disk: seeded emitting cells whose step 1 is checked against the oracle and timed on the CPU")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (sources shard across GPUs "
-                                   "additively, see the design notes, but no multi-GPU path is built)"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1. Sources shard additively "
+                                   "across GPUs (design notes), but no multi-GPU path is built."}))
         sys.exit(2)
 
     import torch
     from paper_1709_03802_amd import dartray as dr
+    from paper_1709_03802_amd import workloads as W
 
     torch.cuda.set_device(0)
-    wl = make_workload(args.workload)
+    wl = W.by_name(args.workload)
     grid = as_f32(wl.grid)
     pol = wl.policy
-    G = dr.Grid(grid)
+    G = dr.Grid(grid, nside_max=max(pol.nside_max, 64))
     f = dr.Fields(G)
+    log(f"workload {wl.name}: {wl.description}")
 
-    def step():
-        f.U.zero_()
-        return dr.run(G, pol, fields=f, collect=False)
-
-    # first run: counters + parity
+    # ---- first run: counters, balance
+    f.U.zero_()
     out = dr.run(G, pol, fields=f, collect=True)
     torch.cuda.synchronize()
     counters = np.array(out.counters)
     crossings = int(counters[:, dr.C_CROSSINGS].sum())
     cross_lambda = crossings * grid.n_lambda
-    print(f"[bench] workload {wl.name}: {grid.n} cells, {grid.n_lambda} wavelengths, "
-          f"{crossings} crossings per run", file=sys.stderr, flush=True)
+    balance = max(float(np.max(np.abs(t[:, 1:6].sum(axis=1) - t[:, 0]) / np.maximum(t[:, 0], 1e-300)))
+                  for t in out.tallies)
+    per_pass = [int(c[dr.C_CROSSINGS]) for c in counters]
+    log(f"{crossings} crossings per run ({per_pass}), max luminosity-balance residual {balance:.2e}")
 
-    parity = None
-    cpu = None
+    # ---- parity and CPU baseline against the FP64 oracle
+    parity, cpu = None, None
     if not args.no_cpu_baseline:
         import oracle
         m = oracle.Model(grid)
         nthreads = os.cpu_count() or 1
-        t0 = time.perf_counter()
-        ref = oracle.run(m, pol, n_threads=nthreads)
-        t_cpu = time.perf_counter() - t0
-        ref_cross = sum(int(r.counters[oracle.C_CROSS]) for r in ref.passes)
-        U = f.U.cpu().numpy()
-        S = f.S_total.cpu().numpy()[:G.s_size]
-        eu = np.abs(U - ref.U) / np.maximum(np.abs(ref.U), 1e-30)
-        es = np.abs(S - ref.S_total) / np.maximum(np.abs(ref.S_total), 1e-30)
-        parity = {"U_max_rel": float(eu.max()), "S_max_rel": float(es.max()),
-                  "gate": 1e-4, "pass": bool(eu.max() <= 1e-4 and es.max() <= 1e-4)}
+        if pol.adaptive:
+            rng = np.random.default_rng(1709)
+            sample = np.zeros(grid.n, dtype=np.uint8)
+            sample[rng.choice(np.flatnonzero(grid.emis.sum(axis=0) > 0), args.sample_sources, replace=False)] = 1
+            t0 = time.perf_counter()
+            ref = m.run_pass(oracle.STEP1, pol, source_mask=sample, n_threads=nthreads)
+            t_cpu = time.perf_counter() - t0
+            fs = dr.Fields(G)
+            dr.trace_direct(G, dr.make_opts(pol, dr.MODE_STEP1, source_mask=torch.as_tensor(sample).cuda()), fs)
+            torch.cuda.synchronize()
+            got = fs.U_LL.cpu().numpy().astype(np.float64)
+            ref_U = ref.U
+            ref_cross = int(ref.counters[oracle.C_CROSS])
+            gpu_cross = int(fs.counters.cpu().numpy()[dr.C_CROSSINGS])
+            what = f"step 1 of {args.sample_sources} seeded emitting cells"
+        else:
+            t0 = time.perf_counter()
+            ref_run = oracle.run(m, pol, n_threads=nthreads)
+            t_cpu = time.perf_counter() - t0
+            got = f.U.cpu().numpy().astype(np.float64)
+            ref_U = ref_run.U
+            ref_cross = sum(int(r.counters[oracle.C_CROSS]) for r in ref_run.passes)
+            gpu_cross = crossings
+            what = f"full {wl.name} run (all passes)"
+        nz = (np.abs(ref_U) > 0) | (np.abs(got) > 0)
+        e = np.abs(got - ref_U)[nz] / np.maximum(np.abs(ref_U[nz]), 1e-300)
+        parity = {"checked": what, "U_max_rel": float(e.max()), "U_p999_rel": float(np.quantile(e, 0.999)),
+                  "crossings_gpu": gpu_cross, "crossings_oracle": ref_cross, "gate": 1e-4,
+                  "pass": bool(e.max() <= 1e-4)}
         cpu = {"value": ref_cross * grid.n_lambda / t_cpu, "unit": "crossings*lambda/s", "cores": nthreads,
-               "kind": "oracle", "sample": f"full {wl.name} run (all passes), {t_cpu:.1f} s"}
-        print(f"[bench] oracle {t_cpu:.1f} s, parity {parity}", file=sys.stderr, flush=True)
+               "kind": "oracle", "sample": f"{what}, {ref_cross} crossings x {grid.n_lambda} wavelengths in {t_cpu:.1f} s"}
+        log(f"oracle: {what} in {t_cpu:.1f} s; parity {parity}")
+
+    # ---- timed steps
+    def step():
+        f.U.zero_()
+        dr.run(G, pol, fields=f, collect=False)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    G.profile(True)
+    kinds = dr.PROF_STEP1 if pol.adaptive else dr.PROF_FIXED
+    G.profile(kinds)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    march_ms, launches = G.profile_read()
-    G.profile(False)
+    kern_ms, launches = G.profile_read()
+    G.profile(0)
 
     ms_per_step = 1e3 * dt / args.steps
     value = cross_lambda / (dt / args.steps)
-    # algorithmic bytes of the march kernel per crossing: rho, 1/(V c) and the
-    # cell record (uniform: root-table code, octree: 16-byte box); per
-    # crossing x wavelength one 4-byte read-modify-write of the binned deposit
-    per_cross = 12 if G.n and grid.max_level == 0 else 24
-    bytes_per_step = crossings * per_cross + cross_lambda * 8
+    # algorithmic bytes of the dominant march kernel per crossing: the
+    # 64-byte leaf record read, and the energy-density row read-modify-write
+    # (adaptive: n_lambda FP64 accumulators; fixed: one FP32 direction bin
+    # per wavelength)
+    if pol.adaptive:
+        kern_cross = per_pass[0]
+        per_cross = 64 + 2 * 8 * grid.n_lambda
+        kernel = "k_march_adaptive (step 1)"
+    else:
+        kern_cross = crossings
+        per_cross = 64 + 2 * 4 * grid.n_lambda
+        kernel = "k_march_fixed"
     launches_per_step = launches / args.steps
-    avg_launch_ms = march_ms / max(launches, 1)
-    achieved = (bytes_per_step / launches_per_step) / (avg_launch_ms * 1e-3) / 1e9
+    avg_ms = kern_ms / max(launches, 1)
+    achieved = (kern_cross * per_cross / launches_per_step) / (avg_ms * 1e-3) / 1e9
     res = {
-        "metric": "ray-cell crossings x lambda per second (1 MI355X), rel err <= 1e-4 vs FP64 oracle",
+        "metric": "ray-cell crossings x lambda per second (1 MI355X) at rel err <= 1e-4 vs the FP64 oracle",
         "value": value,
         "unit": "crossings*lambda/s",
         "n_gpus": 1,
@@ -133,13 +169,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "cells": int(grid.n), "n_lambda": int(grid.n_lambda),
-                   "rays": ("adaptive" if pol.adaptive else f"nside {pol.nside}"),
-                   "passes": (1 if pol.step1 and pol.adaptive else 0) + 1 + pol.n_scatter,
-                   "crossings_per_step": crossings, "parallelism": "single GPU"},
+        "config": {"workload": wl.name, "description": wl.description, "cells": int(grid.n),
+                   "n_lambda": int(grid.n_lambda),
+                   "rays": (f"adaptive nside {pol.nside}..{pol.nside_max}, N_rays {pol.n_rays_min}, f_U {pol.f_U}"
+                            if pol.adaptive else f"fixed nside {pol.nside}"),
+                   "passes": (["step1"] if pol.adaptive and pol.step1 else []) + ["direct"] +
+                             [f"scatter{k + 1}" for k in range(pol.n_scatter)],
+                   "crossings_per_step": crossings, "crossings_per_pass": per_pass,
+                   "balance_max_rel": balance, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_march_fixed", "avg_launch_ms": avg_launch_ms},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                     "avg_launch_ms": avg_ms, "bytes_per_crossing": per_cross,
+                     "crossings_per_launch": kern_cross / launches_per_step},
         "cpu_baseline": cpu,
         "parity": parity,
     }

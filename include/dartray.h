@@ -237,9 +237,14 @@ int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *or
                             int32_t max_cross, int64_t *cells, float *lengths, int32_t *counts);
 
 /* Timing of the ray-march kernels with HIP events recorded on the grid's
- * stream around every march launch.  enable != 0 clears earlier records and
- * starts recording; 0 stops. */
-int dartray_profile_enable(dartray_grid *grid, int32_t enable);
+ * stream around every march launch of the selected kinds.  kinds is a mask of
+ * DARTRAY_PROF_* bits; a nonzero mask clears earlier records and starts
+ * recording, 0 stops. */
+#define DARTRAY_PROF_FIXED 1        /* fixed-Nside march launches */
+#define DARTRAY_PROF_STEP1 2        /* adaptive step-1 march launches */
+#define DARTRAY_PROF_SCATTERING 4   /* adaptive direct / scattering march launches */
+#define DARTRAY_PROF_ALL 7
+int dartray_profile_enable(dartray_grid *grid, int32_t kinds);
 
 /* Sum of the recorded march-kernel durations (ms) and the number of launches
  * since recording started; synchronises the stream. */

@@ -18,6 +18,7 @@
 // and wavelength replaces the N_pix accumulates of a direct deposit.
 
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -136,7 +137,7 @@ __host__ __device__ inline int64_t entry_nside(int64_t e)
 
 __host__ __device__ inline int64_t entry_of(int64_t nside, int64_t pix) { return 4 * (nside * nside - 1) + pix; }
 
-__global__ void k_dir_all(float4 *dirs, int64_t total, Frame f)
+__global__ void k_dir_all(float4 *dirs, double4 *dirs64, int64_t total, Frame f)
 {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= total) return;
@@ -144,6 +145,7 @@ __global__ void k_dir_all(float4 *dirs, int64_t total, Frame f)
     double v[3];
     dr_pix_vec(N, e - entry_of(N, 0), f.R, v);
     dirs[e] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.f);
+    dirs64[e] = make_double4(v[0], v[1], v[2], 0.0);
 }
 
 __global__ void k_sca64(double *out, Frame f)
@@ -310,32 +312,40 @@ __device__ inline int32_t locate_fine(const Geo &g, int fx, int fy, int fz)
 
 // fine-level cell coordinate of position p along an axis with direction
 // component d: on a face, the side d points to (upper side for d == 0)
-__device__ inline int fine_coord(float p, float d)
+template <typename T>
+__device__ inline int fine_coord(T p, T d)
 {
-    const float fl = floorf(p);
+    const T fl = floor(p);
     int i = (int)fl;
-    if (p == fl && d < 0.f) i -= 1;
+    if (p == fl && d < T(0)) i -= 1;
     return i;
 }
 
-struct Ray {
-    float o[3];       // origin (source-cell centre), fine units
-    float n[3];       // unit direction
-    float inv[3];     // 1/n (unused for zero components)
+// A ray in finest-level cell units.  The fixed-Nside march uses FP32; the
+// adaptive march keeps its geometry in FP64 so that its split, block and
+// step-1 extent decisions are taken on the same values as in exact arithmetic.
+template <typename T>
+struct RayT {
+    T o[3];       // origin (source-cell centre), fine units
+    T n[3];       // unit direction
+    T inv[3];     // 1/n (unused for zero components)
 };
+using Ray = RayT<float>;
 
 // exit distance from the leaf with box b along ray R, and the exit axis
-__device__ inline float exit_t(const Ray &R, const int4 b, int &axis)
+// (exact ties resolved x before y before z)
+template <typename T>
+__device__ inline T exit_t(const RayT<T> &R, const int4 b, int &axis)
 {
-    const float INF = __builtin_huge_valf();
+    const T INF = T(__builtin_huge_valf());
     const int lo[3] = {b.x, b.y, b.z};
-    float best = INF;
+    T best = INF;
     axis = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float t = INF;
-        if (R.n[a] > 0.f) t = ((float)(lo[a] + b.w) - R.o[a]) * R.inv[a];
-        else if (R.n[a] < 0.f) t = ((float)lo[a] - R.o[a]) * R.inv[a];
+        T t = INF;
+        if (R.n[a] > T(0)) t = ((T)(lo[a] + b.w) - R.o[a]) * R.inv[a];
+        else if (R.n[a] < T(0)) t = ((T)lo[a] - R.o[a]) * R.inv[a];
         if (t < best) {
             best = t;
             axis = a;
@@ -346,18 +356,19 @@ __device__ inline float exit_t(const Ray &R, const int4 b, int &axis)
 
 // the leaf across the exit face that contains the exit point: one load of the
 // face-neighbour code, plus a descent when the region across is subdivided
-__device__ inline int32_t next_leaf(const Geo &g, const Ray &R, const int4 b, const int32_t *nb, int axis, float te)
+template <typename T>
+__device__ inline int32_t next_leaf(const Geo &g, const RayT<T> &R, const int4 b, const int32_t *nb, int axis, T te)
 {
-    const int32_t code = nb[2 * axis + (R.n[axis] > 0.f ? 1 : 0)];
+    const int32_t code = nb[2 * axis + (R.n[axis] > T(0) ? 1 : 0)];
     if (code >= -1) return code;            // a leaf, or outside the root block
     const int lo[3] = {b.x, b.y, b.z};
     int f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (a == axis) {
-            f[a] = R.n[a] > 0.f ? lo[a] + b.w : lo[a] - 1;
+            f[a] = R.n[a] > T(0) ? lo[a] + b.w : lo[a] - 1;
         } else {
-            int q = fine_coord(fmaf(te, R.n[a], R.o[a]), R.n[a]);
+            int q = fine_coord<T>(fma(te, R.n[a], R.o[a]), R.n[a]);
             q = q < lo[a] ? lo[a] : q;
             q = q > lo[a] + b.w - 1 ? lo[a] + b.w - 1 : q;
             f[a] = q;
@@ -567,7 +578,7 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
 template <int PCH>
 __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const float *wtab, const LambdaTable *lt,
                                                       const float *rho, const float *inv_vc, int64_t n, int r0,
-                                                      int nb, int w_row, float *U_k, float *S_next)
+                                                      int nb, int w_row, double *U_k, float *S_next)
 {
     __shared__ float ws[64][PCH];
     const int l = blockIdx.z;
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const fl
     float *srow = S_next + lt->s_off[l] + c * (int64_t)npix + p0;
 #pragma unroll
     for (int j = 0; j < PCH; ++j) srow[j] += f * acc[j];
-    if (blockIdx.y == 0) U_k[c * lt->n_lambda + l] += accU;
+    if (blockIdx.y == 0) U_k[c * lt->n_lambda + l] += (double)accU;
 }
 
 // ---------------------------------------------------------------------------
@@ -629,17 +640,25 @@ struct AdaptArgs {
     Geo geo;
     const int32_t *src_list;
     const int32_t *n_src;
-    const float4 *dirs;          // all-level direction table
+    const float4 *dirs;          // all-level direction table (FP32; j_sca pixels)
+    const double4 *dirs64;       // all-level direction table (FP64; ray geometry)
     const float *invz;           // [entry][n_lambda]
     const float *emis_lum;
     const float *S_pending;
     const float *ull_t;          // [n][n_lambda] copy of U_LL
     const LambdaTable *lt;
-    float *U_k;
+    double *U_k;
     float *S_next;
     double *tally;
     uint64_t *counters;
     unsigned long long *queue;
+    // deposit log (0 capacity: deposit with atomics)
+    uint32_t *log_key;
+    uint32_t *log_dir;
+    float *log_du;
+    unsigned long long *log_count;
+    int64_t log_cap;
+    int64_t log_limit;           // no new items once the log holds this many tuples
     int64_t n;
     int32_t mode;                // 0 step 1, 1 direct, 2 scatter
     int32_t nside0;
@@ -651,6 +670,8 @@ struct AdaptArgs {
     float r_pre_fine;            // step-1 extent in fine units
     float h_fine;
     float c_light;
+    double r_pre_fine64;
+    double h_fine64;
     int64_t max_steps;
     int64_t hard_cap;
 };
@@ -709,18 +730,18 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
     // ray state
     bool has_ray = false, has_item = false, pending = false, done = false;
     int32_t s = 0;
-    float o[3] = {0.f, 0.f, 0.f};
+    double o[3] = {0.0, 0.0, 0.0};
     int depth = 0;
     int pix = 0;
-    float t = 0.f;
+    double t = 0.0;                // distance from the source, fine units
     int32_t c = -1;
     int64_t e = 0;                 // direction table entry of the ray
-    Ray R;
+    RayT<double> R;
     float L[NL];
-    float st_t[kMaxDepthAdaptive + 1];
+    double st_t[kMaxDepthAdaptive + 1];
     float st_L[kMaxDepthAdaptive + 1][NL];
     int64_t steps = 0;
-    float omega_hp = 0.f;
+    double omega_hp = 0.0;
 #pragma unroll
     for (int l = 0; l < NL; ++l) L[l] = 0.f;
 
@@ -747,20 +768,29 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
         if (need) {
             const int leader = __ffsll((unsigned long long)need) - 1;
             unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(A.queue, (unsigned long long)__popcll(need));
+            int stop = 0;
+            if (lane == leader) {
+                if (!STEP1 && A.log_cap > 0 &&
+                    __hip_atomic_load(A.log_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                        (unsigned long long)A.log_limit)
+                    stop = 1;   // the log is nearly full: finish current items, take no new ones
+                else
+                    base = atomicAdd(A.queue, (unsigned long long)__popcll(need));
+            }
             base = __shfl(base, leader, 64);
+            stop = __shfl(stop, leader, 64);
             if (want) {
                 const uint64_t it = base + __popcll(need & ((1ull << lane) - 1ull));
-                if (it >= nitems) {
+                if (stop || it >= nitems) {
                     done = true;
                 } else {
                     const int r0 = (int)(it / (uint64_t)nsrc);
                     s = A.src_list[it - (uint64_t)r0 * nsrc];
                     const int4 sb = A.geo.rec[s].box;
-                    const float half = 0.5f * (float)sb.w;
-                    o[0] = (float)sb.x + half;
-                    o[1] = (float)sb.y + half;
-                    o[2] = (float)sb.z + half;
+                    const double half = 0.5 * (double)sb.w;
+                    o[0] = (double)sb.x + half;
+                    o[1] = (double)sb.y + half;
+                    o[2] = (double)sb.z + half;
                     float lsum = 0.f;
                     const float inv_nray0 = 1.f / (float)(12 * A.nside0 * A.nside0);
 #pragma unroll
@@ -787,7 +817,7 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                     has_item = true;
                     depth = 0;
                     pix = r0;
-                    t = 0.f;
+                    t = 0.0;
                     if (lsum > 0.f) {
                         ++n_rays;
                         pending = true;
@@ -800,21 +830,21 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
             pending = false;
             const int64_t N = (int64_t)A.nside0 << depth;
             e = entry_of(N, pix);
-            const float4 nd = A.dirs[e];
+            const double4 nd = A.dirs64[e];
             R.n[0] = nd.x;
             R.n[1] = nd.y;
             R.n[2] = nd.z;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 R.o[a] = o[a];
-                R.inv[a] = 1.0f / R.n[a];
+                R.inv[a] = 1.0 / R.n[a];
             }
-            omega_hp = 3.14159265358979f / (3.f * (float)N * (float)N);   // 4 pi / (12 N^2)
+            omega_hp = kPi / (3.0 * (double)N * (double)N);   // 4 pi / (12 N^2)
             steps = 0;
-            c = (t == 0.f) ? s
-                           : locate_fine(A.geo, fine_coord(fmaf(t, R.n[0], o[0]), R.n[0]),
-                                         fine_coord(fmaf(t, R.n[1], o[1]), R.n[1]),
-                                         fine_coord(fmaf(t, R.n[2], o[2]), R.n[2]));
+            c = (t == 0.0) ? s
+                           : locate_fine(A.geo, fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0]),
+                                         fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1]),
+                                         fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2]));
             if (c >= 0) {
                 has_ray = true;
             } else {
@@ -840,21 +870,31 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
 #pragma unroll
             for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
             int axis;
-            const float te = exit_t(R, b, axis);
-            const float len = te - t;
+            double te = exit_t<double>(R, b, axis);
+            if (STEP1 && fabs(te - A.r_pre_fine64) <= 1e-9 * A.r_pre_fine64) {
+                // HEALPix z components are rational and cell faces lie on an
+                // integer lattice, so a face can sit exactly at the step-1
+                // extent: take the correctly rounded quotient there, which is
+                // exact whenever the exact distance is representable
+                const double face = (R.n[axis] > 0.0) ? (double)((axis == 0 ? b.x : axis == 1 ? b.y : b.z) + b.w)
+                                                       : (double)(axis == 0 ? b.x : axis == 1 ? b.y : b.z);
+                te = (face - R.o[axis]) / R.n[axis];
+            }
+            const double len = te - t;
             int action = 0;   // 0 continue, 1 split, 2 cut
-            if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes: no deposit, no decision
-                const float t_in = t;
-                const float dx = ((float)b.x + 0.5f * (float)b.w - o[0]);
-                const float dy = ((float)b.y + 0.5f * (float)b.w - o[1]);
-                const float dz = ((float)b.z + 0.5f * (float)b.w - o[2]);
-                const float h = A.h_fine;
-                const float d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
-                const float side = (float)b.w * h;
-                const float lp = len * h;
+            if (len > 1e-6 * ((double)b.w + te)) {   // shorter segments are grazes: no deposit, no decision
+                const double t_in = t;
+                // source-to-cell-centre offsets are exact half-integers in fine units
+                const double dx = ((double)b.x + 0.5 * (double)b.w - o[0]);
+                const double dy = ((double)b.y + 0.5 * (double)b.w - o[1]);
+                const double dz = ((double)b.z + 0.5 * (double)b.w - o[2]);
+                const double h = A.h_fine64;
+                const double d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
+                const double side = (double)b.w * h;
+                const float lp = (float)(len * h);
                 float em1[NL];
                 uint32_t sigm = 0;
-                const float thr = f_U * omega_hp * d2 * A.c_light;
+                const float thr = (float)(f_U * omega_hp * d2 * A.c_light);
                 const float *ull = A.ull_t + (int64_t)c * nl;
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
@@ -866,14 +906,14 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                         if (!STEP1) {
                             const float ext = -L[l] * em1[l];
                             const float lavg = tau > 0.f ? ext / tau : L[l];
-                            sg = lavg > 0.f && (d2 == 0.f || lavg >= thr * ull[l]);
+                            sg = lavg > 0.f && (d2 == 0.0 || lavg >= thr * ull[l]);
                         }
                         sigm |= (uint32_t)sg << l;
                     }
                 }
-                if (STEP1 && t_in >= A.r_pre_fine) {
+                if (STEP1 && t_in >= A.r_pre_fine64) {
                     action = 2;
-                } else if (d2 > 0.f && omega_hp * A.n_rays * d2 > side * side) {   // Eq. 2
+                } else if (d2 > 0.0 && omega_hp * (double)A.n_rays * d2 > side * side) {   // Eq. 2
                     if (sigm && depth < A.max_depth) action = 1;
                     else if (!sigm) action = 2;
                 }
@@ -926,12 +966,13 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                             L[l] = fmaf(L[l], em1[l], L[l]);
                         }
                     }
-                    if (!STEP1 && deposit) s_dep[threadIdx.x] = make_float4(R.n[0], R.n[1], R.n[2], __int_as_float(c));
+                    if (!STEP1 && deposit)
+                        s_dep[threadIdx.x] = make_float4((float)R.n[0], (float)R.n[1], (float)R.n[2], __int_as_float(c));
                     t = te;
                 }
             }
             if (has_ray && action == 0) {
-                const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
+                const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
                 ++steps;
                 if (nx < 0) {
 #pragma unroll
@@ -951,6 +992,29 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
         // ---- energy-density deposits: lanes q of an instruction take value
         // q % NL of the (q / NL)-th depositing lane, so each crossing's NL
         // values go out as one contiguous request
+        // ---- log the deposits (scattering passes); what does not fit in the
+        // log is deposited with atomics below
+        if (!STEP1 && A.log_cap > 0) {
+            const uint64_t lm = __ballot(udep);
+            if (lm) {
+                const int leader = __ffsll((unsigned long long)lm) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(A.log_count, (unsigned long long)__popcll(lm));
+                base = __shfl(base, leader, 64);
+                if (udep) {
+                    const unsigned long long slot = base + __popcll(lm & ((1ull << lane) - 1ull));
+                    if (slot < (unsigned long long)A.log_cap) {
+                        A.log_key[slot] = (uint32_t)s_cell[threadIdx.x];
+                        A.log_dir[slot] = (uint32_t)e;
+#pragma unroll
+                        for (int l = 0; l < NL; ++l)
+                            if (l < nl) A.log_du[(int64_t)l * A.log_cap + slot] = s_du[l][threadIdx.x];
+                        udep = false;
+                        deposit = false;
+                    }
+                }
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         {
@@ -967,7 +1031,7 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                 if (q < cnt && l < nl) {
                     const int j = s_list[wbase + q];
                     const float v = s_du[l][wbase + j];
-                    if (v != 0.f) atomic_add_f32(A.U_k + (int64_t)s_cell[wbase + j] * nl + l, v);
+                    if (v != 0.f) atomic_add_f64(A.U_k + (int64_t)s_cell[wbase + j] * nl + l, (double)v);
                 }
             }
         }
@@ -1023,9 +1087,154 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Expansion of the sorted deposit log.  Thread slots cover every
+// (wavelength, j_sca pixel) pair plus one energy-density slot per wavelength;
+// a block walks a contiguous range of cell-sorted tuples, accumulates each
+// cell's contributions in compensated (Kahan) registers and adds them to
+// S_next / U_k when the cell changes.  The scattered luminosity of a tuple is
+// albedo c alpha V du w(p|n) (the deposit du = ext / (alpha V c)).
+// ---------------------------------------------------------------------------
+
+constexpr int kExpandSlots = 8;        // slots per thread: up to 2048 per block
+constexpr int kExpandBatch = 64;       // tuples staged in LDS at a time
+
+__global__ void k_iota(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+struct ExpandArgs {
+    const uint32_t *key;       // sorted cells
+    const uint32_t *idx;       // tuple index of each sorted entry
+    const uint32_t *dir;       // direction entry per tuple
+    const float *du;           // [nl][cap]
+    const float4 *dirs;
+    const float *invz;
+    const LambdaTable *lt;
+    const LeafRec *rec;
+    double *U_k;
+    float *S_next;
+    int64_t cnt;
+    int64_t cap;
+    int64_t chunk;
+    int32_t w_row;
+};
+
+template <int NL>
+__global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
+{
+    __shared__ float4 sca[kScaDirs];
+    __shared__ int32_t t_cell[kExpandBatch];
+    __shared__ float4 t_n[kExpandBatch];
+    __shared__ float t_a[NL][kExpandBatch];     // du * 1/Z: scattered-light coefficient
+    __shared__ float t_du[NL][kExpandBatch];
+    const LambdaTable *lt = X.lt;
+    const int nl = lt->n_lambda;
+    for (int i = threadIdx.x; i < kScaDirs; i += blockDim.x) sca[i] = X.dirs[i];
+
+    // slot assignment
+    int kind[kExpandSlots], lam[kExpandSlots], pix[kExpandSlots];
+    float npx[kExpandSlots], npy[kExpandSlots], npz[kExpandSlots], hB[kExpandSlots], hC[kExpandSlots];
+    float acc[kExpandSlots], cmp[kExpandSlots];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kExpandSlots; ++k) {
+        const int sl = threadIdx.x + 256 * k;
+        kind[k] = 0;
+        lam[k] = 0;
+        pix[k] = 0;
+        npx[k] = npy[k] = npz[k] = hB[k] = hC[k] = 0.f;
+        acc[k] = cmp[k] = 0.f;
+        if (sl < X.w_row) {
+            int l = 0;
+            while (l + 1 < nl && lt->w_off[l + 1] <= sl) ++l;
+            kind[k] = 1;
+            lam[k] = l;
+            pix[k] = sl - lt->w_off[l];
+            const float4 v = sca[entry_of(lt->nside_sca[l], 0) + pix[k]];
+            npx[k] = v.x;
+            npy[k] = v.y;
+            npz[k] = v.z;
+            const float g = lt->g[l];
+            hB[k] = 1.f + g * g;
+            hC[k] = -2.f * g;
+        } else if (sl < X.w_row + nl) {
+            kind[k] = 2;
+            lam[k] = sl - X.w_row;
+        }
+    }
+
+    const int64_t i0 = blockIdx.x * X.chunk;
+    const int64_t i1 = min(X.cnt, i0 + X.chunk);
+    int32_t cur = -1;
+
+    auto flush = [&]() {
+        if (cur < 0) return;
+        const LeafRec &r = X.rec[cur];
+#pragma unroll
+        for (int k = 0; k < kExpandSlots; ++k) {
+            const float v = acc[k] - cmp[k];
+            if (kind[k] == 1 && v != 0.f) {
+                const int l = lam[k];
+                const float g = lt->g[l];
+                const float scale = lt->albedo[l] * lt->kappa[l] * r.rho / r.ivc * ((1.f - g * g) / (4.f * 3.14159265358979f));
+                atomic_add_f32(X.S_next + lt->s_off[l] + (int64_t)cur * lt->npix[l] + pix[k], scale * v);
+            } else if (kind[k] == 2 && v != 0.f) {
+                atomic_add_f64(X.U_k + (int64_t)cur * nl + lam[k], (double)v);
+            }
+            acc[k] = cmp[k] = 0.f;
+        }
+    };
+
+    for (int64_t i = i0; i < i1; i += kExpandBatch) {
+        const int nb = (int)min((int64_t)kExpandBatch, i1 - i);
+        __syncthreads();
+        if (threadIdx.x < nb) {
+            const int64_t j = i + threadIdx.x;
+            const uint32_t orig = X.idx[j];
+            const uint32_t e = X.dir[orig];
+            t_cell[threadIdx.x] = (int32_t)X.key[j];
+            t_n[threadIdx.x] = X.dirs[e];
+            for (int l = 0; l < nl; ++l) {
+                const float d = X.du[(int64_t)l * X.cap + orig];
+                t_du[l][threadIdx.x] = d;
+                t_a[l][threadIdx.x] = d * X.invz[(int64_t)e * nl + l];
+            }
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nb; ++jj) {
+            const int32_t cell = t_cell[jj];
+            if (cell != cur) {
+                flush();
+                cur = cell;
+            }
+            const float4 n = t_n[jj];
+#pragma unroll
+            for (int k = 0; k < kExpandSlots; ++k) {
+                float v = 0.f;
+                if (kind[k] == 1) {
+                    const float mu = fmaf(npx[k], n.x, fmaf(npy[k], n.y, npz[k] * n.z));
+                    const float r = rsqrtf(fmaf(hC[k], mu, hB[k]));
+                    v = t_a[lam[k]][jj] * (r * r * r);
+                } else if (kind[k] == 2) {
+                    v = t_du[lam[k]][jj];
+                }
+                // compensated sum: acc holds the sum, cmp the rounding error
+                const float y = v - cmp[k];
+                const float t = acc[k] + y;
+                cmp[k] = (t - acc[k]) - y;
+                acc[k] = t;
+            }
+        }
+    }
+    flush();
+}
+
 // U += U_k (and U_pass = U_k), absorbed / scattered tallies from U_k in FP64,
 // U_LL <- U when requested.  grid.y = wavelength
-__global__ void k_finish_u(const float *U_k, float *U, float *U_pass, float *U_LL, int set_ull, int ull_only,
+__global__ void k_finish_u(const double *U_k, float *U, float *U_pass, float *U_LL, int set_ull, int ull_only,
                            const LambdaTable *lt, const float *rho, const float *inv_vc, int64_t n, double *tally)
 {
     __shared__ double sh[16];
@@ -1033,7 +1242,8 @@ __global__ void k_finish_u(const float *U_k, float *U, float *U_pass, float *U_L
     double ext = 0.0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = (int64_t)l * n + c;
-        const float uk = U_k[c * lt->n_lambda + l];
+        const double ukd = U_k[c * lt->n_lambda + l];
+        const float uk = (float)ukd;
         if (ull_only) {
             U_LL[i] = uk;
         } else {
@@ -1042,7 +1252,7 @@ __global__ void k_finish_u(const float *U_k, float *U, float *U_pass, float *U_L
             if (U_pass) U_pass[i] = uk;
             if (set_ull) U_LL[i] = u;
         }
-        ext += (double)lt->kappa[l] * (double)rho[c] / (double)inv_vc[c] * (double)uk;
+        ext += (double)lt->kappa[l] * (double)rho[c] / (double)inv_vc[c] * ukd;
     }
     const double b = block_sum(ext, sh);
     if (threadIdx.x == 0 && b != 0.0) {
@@ -1150,7 +1360,8 @@ static void free_grid(Grid &g)
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
     void *ptrs[] = {g.rec, g.ull_t, g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
-                    g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.invz, g.sca64, g.wtab, g.queue};
+                    g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
+                    g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -1376,7 +1587,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
         dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
         dalloc(g, &g.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
-        dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir),
+        dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir), dalloc(g, &g.dir64, (size_t)ndir),
         dalloc(g, &g.invz, (size_t)ndir * nl), dalloc(g, &g.sca64, 3 * (size_t)kScaDirs),
         dalloc(g, &g.wtab, nray_w * (size_t)g.w_row), dalloc(g, &g.queue, 1),
     };
@@ -1390,6 +1601,33 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     g.ubar_floats = nb_cap * per_dir;
     g.nside_cap = cap;
     g.ndir_all = ndir;
+    // deposit log for the scattering passes of adaptive rays (wavelength rows
+    // of at most 2048 slots per expansion block)
+    if (nl <= 16 && g.w_row + nl <= 256 * kExpandSlots) {
+        const int64_t lcap = std::min<int64_t>((int64_t)1 << 27, std::max<int64_t>((int64_t)1 << 16, 256 * n));
+        int rl[] = {dalloc(g, &g.log_key, (size_t)lcap), dalloc(g, &g.log_key2, (size_t)lcap),
+                    dalloc(g, &g.log_idx, (size_t)lcap), dalloc(g, &g.log_idx2, (size_t)lcap),
+                    dalloc(g, &g.log_dir, (size_t)lcap), dalloc(g, &g.log_du, (size_t)lcap * nl),
+                    dalloc(g, &g.log_count, 1)};
+        int bad = 0;
+        for (int r : rl) bad |= r;
+        while ((1ll << g.key_bits) < n) ++g.key_bits;
+        if (!bad) {
+            hipcub::DoubleBuffer<uint32_t> kb(g.log_key, g.log_key2), vb(g.log_idx, g.log_idx2);
+            size_t tb = 0;
+            hipError_t qe = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, kb, vb, (int)lcap, 0, g.key_bits, g.stream);
+            if (qe != hipSuccess) bad = 1;
+            else bad = dalloc(g, (char **)&g.sort_tmp, tb);
+            g.sort_tmp_bytes = tb;
+        }
+        if (bad) {
+            std::string msg = g_last_error;
+            free_grid(g);
+            delete h;
+            return fail(DARTRAY_E_OOM, "deposit log: " + msg);
+        }
+        g.log_cap = lcap;
+    }
     hipStream_t s = g.stream;
     hipError_t e = hipSuccess;
     std::vector<float> rho_f(d->rho, d->rho + n);
@@ -1439,10 +1677,10 @@ int64_t dartray_s_offset(const dartray_grid *grid, int32_t l)
     return grid->g.lt.s_off[l];
 }
 
-int dartray_profile_enable(dartray_grid *grid, int32_t enable)
+int dartray_profile_enable(dartray_grid *grid, int32_t kinds)
 {
     if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
-    grid->g.prof = enable != 0;
+    grid->g.prof = kinds & DARTRAY_PROF_ALL;
     grid->g.ev_used = 0;
     return DARTRAY_OK;
 }
@@ -1586,7 +1824,7 @@ static int ensure_dirs(Grid &g, const Frame &f)
 {
     if (g.dirs_valid && std::memcmp(g.dirs_frame, f.R, sizeof(f.R)) == 0) return DARTRAY_OK;
     hipLaunchKernelGGL(k_dir_all, dim3((unsigned)((g.ndir_all + 255) / 256)), dim3(256), 0, g.stream, g.dir_all,
-                       g.ndir_all, f);
+                       g.dir64, g.ndir_all, f);
     DR_LAUNCH_CHECK("k_dir_all");
     hipLaunchKernelGGL(k_sca64, dim3((kScaDirs + 255) / 256), dim3(256), 0, g.stream, g.sca64, f);
     DR_LAUNCH_CHECK("k_sca64");
@@ -1642,7 +1880,7 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
 // record a timing event on the grid's stream (profiling only)
 static int prof_mark(Grid &g)
 {
-    if (!g.prof) return DARTRAY_OK;
+    if (!(g.prof & g.prof_kind)) return DARTRAY_OK;
     if (g.ev_used == g.ev_pool.size()) {
         hipEvent_t e;
         DR_HIP(hipEventCreate(&e));
@@ -1672,7 +1910,7 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     int log2n = 0;
     while ((1 << log2n) < o->nside) ++log2n;
 
-    if ((rc = fill<float>(g, g.U_k, (size_t)nl * n, 0.f))) return rc;
+    if ((rc = fill<double>(g, g.U_k, (size_t)nl * n, 0.0))) return rc;
     if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
     if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
     if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
@@ -1680,6 +1918,7 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
 
     const size_t per_dir = (size_t)nl * n;
     const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
+    g.prof_kind = DARTRAY_PROF_FIXED;
     FixedArgs A{};
     A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
@@ -1751,7 +1990,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     int rc = ensure_dirs(g, fr);
     if (rc) return rc;
     if (!step1 && (rc = ensure_invz(g, fr))) return rc;
-    if ((rc = fill<float>(g, g.U_k, (size_t)nl * n, 0.f))) return rc;
+    if ((rc = fill<double>(g, g.U_k, (size_t)nl * n, 0.0))) return rc;
     if (!step1 && (rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
     if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
     if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
@@ -1793,17 +2032,75 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     A.a_RT = o->a_RT;
     A.r_pre_fine = (float)((double)o->r_pre / g.h_fine);
     A.h_fine = (float)g.h_fine;
+    A.r_pre_fine64 = (double)o->r_pre / g.h_fine;
+    A.h_fine64 = g.h_fine;
+    A.dirs64 = g.dir64;
     A.c_light = (float)g.c_light;
     A.max_steps = o->max_steps;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
     const unsigned blocks = 2048;
-    if ((rc = prof_mark(g))) return rc;
-    if (nl <= 1) launch_adaptive<1>(A, A.mode, g.stream, blocks);
-    else if (nl <= 4) launch_adaptive<4>(A, A.mode, g.stream, blocks);
-    else if (nl <= 8) launch_adaptive<8>(A, A.mode, g.stream, blocks);
-    else launch_adaptive<16>(A, A.mode, g.stream, blocks);
-    DR_LAUNCH_CHECK("k_march_adaptive");
-    if ((rc = prof_mark(g))) return rc;
+    const bool use_log = !step1 && g.log_cap > 0;
+    g.prof_kind = step1 ? DARTRAY_PROF_STEP1 : DARTRAY_PROF_SCATTERING;
+    A.log_key = g.log_key;
+    A.log_dir = g.log_dir;
+    A.log_du = g.log_du;
+    A.log_count = g.log_count;
+    A.log_cap = use_log ? g.log_cap : 0;
+    A.log_limit = use_log ? g.log_cap - g.log_cap / 4 : 0;
+    int32_t nsrc_h = 0;
+    if (use_log) {
+        DR_HIP(hipMemcpyAsync(&nsrc_h, g.n_src, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipStreamSynchronize(g.stream));
+    }
+    const unsigned long long nitems = (unsigned long long)nsrc_h * (unsigned long long)(12 * o->nside * o->nside);
+    g.log_chunks = 0;
+    while (true) {
+        if (use_log && (rc = fill<unsigned long long>(g, g.log_count, 1, 0ull))) return rc;
+        if ((rc = prof_mark(g))) return rc;
+        if (nl <= 1) launch_adaptive<1>(A, A.mode, g.stream, blocks);
+        else if (nl <= 4) launch_adaptive<4>(A, A.mode, g.stream, blocks);
+        else if (nl <= 8) launch_adaptive<8>(A, A.mode, g.stream, blocks);
+        else launch_adaptive<16>(A, A.mode, g.stream, blocks);
+        DR_LAUNCH_CHECK("k_march_adaptive");
+        if ((rc = prof_mark(g))) return rc;
+        ++g.log_chunks;
+        if (!use_log) break;
+        unsigned long long hc[2] = {0, 0};
+        DR_HIP(hipMemcpyAsync(&hc[0], g.log_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipMemcpyAsync(&hc[1], g.queue, sizeof(unsigned long long), hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipStreamSynchronize(g.stream));
+        const int64_t cnt = (int64_t)std::min<unsigned long long>(hc[0], (unsigned long long)g.log_cap);
+        if (cnt > 0) {
+            hipLaunchKernelGGL(k_iota, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 8192)), dim3(256), 0,
+                               g.stream, g.log_idx, cnt);
+            DR_LAUNCH_CHECK("k_iota");
+            hipcub::DoubleBuffer<uint32_t> kb(g.log_key, g.log_key2), vb(g.log_idx, g.log_idx2);
+            size_t tb = g.sort_tmp_bytes;
+            DR_HIP(hipcub::DeviceRadixSort::SortPairs(g.sort_tmp, tb, kb, vb, (int)cnt, 0, g.key_bits, g.stream));
+            ExpandArgs X{};
+            X.key = kb.Current();
+            X.idx = vb.Current();
+            X.dir = g.log_dir;
+            X.du = g.log_du;
+            X.dirs = g.dir_all;
+            X.invz = g.invz;
+            X.lt = g.d_lt;
+            X.rec = g.rec;
+            X.U_k = g.U_k;
+            X.S_next = f->S_next;
+            X.cnt = cnt;
+            X.cap = g.log_cap;
+            X.chunk = 2048;
+            X.w_row = g.w_row;
+            const unsigned eb = (unsigned)((cnt + X.chunk - 1) / X.chunk);
+            if (nl <= 1) hipLaunchKernelGGL(k_expand<1>, dim3(eb), dim3(256), 0, g.stream, X);
+            else if (nl <= 4) hipLaunchKernelGGL(k_expand<4>, dim3(eb), dim3(256), 0, g.stream, X);
+            else if (nl <= 8) hipLaunchKernelGGL(k_expand<8>, dim3(eb), dim3(256), 0, g.stream, X);
+            else hipLaunchKernelGGL(k_expand<16>, dim3(eb), dim3(256), 0, g.stream, X);
+            DR_LAUNCH_CHECK("k_expand");
+        }
+        if (hc[1] >= nitems) break;
+    }
     return DARTRAY_OK;
 }
 

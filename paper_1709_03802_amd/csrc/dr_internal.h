@@ -79,7 +79,7 @@ struct Grid {
     LambdaTable *d_lt = nullptr;
 
     // work arrays
-    float *U_k = nullptr;                 // [n][nl] (wavelength fastest)
+    double *U_k = nullptr;                // [n][nl] (wavelength fastest), FP64 accumulator of FP32 deposits
     float *ull_t = nullptr;               // [n][nl] copy of U_LL for the march
     int32_t *flags = nullptr;             // [n] source flags, then scan
     int32_t *src_list = nullptr;          // [n] compacted sources
@@ -95,6 +95,7 @@ struct Grid {
     int32_t nside_cap = 64;
     int64_t ndir_all = 0;
     float4 *dir_all = nullptr;
+    double4 *dir64 = nullptr;             // the same directions in FP64
     float *invz = nullptr;                // [entry][n_lambda] 1 / sum_p Phi(n_p . n)
     double *sca64 = nullptr;              // FP64 scattered-light pixel directions, first kScaDirs entries
     double dirs_frame[9] = {0};
@@ -105,10 +106,25 @@ struct Grid {
     bool wtab_valid = false;
     unsigned long long *queue = nullptr;  // work counter of the adaptive march
 
+    // deposit log of the adaptive passes that scatter light: one tuple
+    // (cell, direction entry, per-wavelength energy-density deposit) per
+    // depositing crossing, radix-sorted by cell and expanded per cell
+    int64_t log_cap = 0;
+    uint32_t *log_key = nullptr, *log_key2 = nullptr;
+    uint32_t *log_idx = nullptr, *log_idx2 = nullptr;
+    uint32_t *log_dir = nullptr;
+    float *log_du = nullptr;              // [nl][log_cap]
+    unsigned long long *log_count = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    int32_t key_bits = 1;
+    int64_t log_chunks = 0;               // launches of the last adaptive pass
+
     size_t bytes = 0;
 
     // march-kernel timing
-    bool prof = false;
+    int32_t prof = 0;                     // DARTRAY_PROF_* mask
+    int32_t prof_kind = 0;                // kind of the launch being marked
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
 };
