@@ -64,6 +64,11 @@ def xcc_hist(blocks=4096):
 
 
 if __name__ == "__main__":
+    import sys
+    if len(sys.argv) > 2 and sys.argv[1] == "copy":
+        # one copy of the given number of bytes (read + write), warm-up plus timed launch
+        print(f"copy {copy_bandwidth(int(sys.argv[2])) / 1e9:.0f} GB/s", flush=True)
+        sys.exit(0)
     print("xcc histogram", xcc_hist(), flush=True)
     print(f"copy {copy_bandwidth() / 1e9:.0f} GB/s (read + write)", flush=True)
     for fp in (1 << 20, 8 << 20, 128 << 20, 1 << 30, 8 << 30):
