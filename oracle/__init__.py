@@ -113,6 +113,9 @@ def lib():
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.orc_run_pass.restype = C.c_int
+        L.orc_adjoint_pass.argtypes = [C.c_void_p, C.POINTER(PassOpts), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_adjoint_pass.restype = C.c_int
         _lib = L
     return _lib
 
@@ -265,6 +268,47 @@ class Model:
         if rc != 0:
             raise ValueError(f"oracle pass failed (status {rc})")
         return PassResult(U_k.reshape(self.nl, self.n), S_next[:self.s_size], tally.reshape(self.nl, 8), counters)
+
+
+def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
+    o = PassOpts()
+    o.mode = mode
+    o.adaptive = 1 if policy.adaptive else 0
+    o.nside = int(policy.nside)
+    o.nside_max = int(policy.nside_max)
+    o.n_rays_min = float(policy.n_rays_min)
+    o.f_U = float(policy.f_U)
+    o.r_pre = float(policy.r_pre)
+    fr = np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)
+    o.frame = (C.c_double * 9)(*fr.ravel().tolist())
+    keep = None
+    if source_mask is not None:
+        keep = np.ascontiguousarray(source_mask, dtype=np.uint8)
+        o.source_mask = _p(keep, C.c_uint8)
+    o.n_threads = int(n_threads)
+    return o, keep
+
+
+def adjoint(model: Model, policy, run_result, Ubar, Sbar_last=None, frame=None, source_mask=None, n_threads=0):
+    """dJ/drho for a loss J(U, S_total) given dJ/dU (and optionally dJ/dS of the
+    last, unprocessed order), by reverse passes over a fixed-ray run."""
+    Ubar = np.ascontiguousarray(Ubar, dtype=np.float64).reshape(model.nl, model.n)
+    rho_bar = np.zeros(model.n)
+    passes = [r for r in run_result.passes]
+    pend = [None] + [passes[k - 1].S for k in range(1, len(passes))]   # emission of pass k
+    Sbar = None if Sbar_last is None else np.ascontiguousarray(Sbar_last, dtype=np.float64)
+    for k in range(len(passes) - 1, -1, -1):
+        mode = DIRECT if k == 0 else SCATTER
+        o, keep = _opts(mode, policy, frame, source_mask if k == 0 else None, n_threads)
+        Sbar_k = np.zeros(max(model.s_size, 1))
+        Sp = None if pend[k] is None else np.ascontiguousarray(pend[k], dtype=np.float64)
+        rc = lib().orc_adjoint_pass(model.h, C.byref(o), None if Sp is None else _p(Sp, C.c_double),
+                                    _p(Ubar, C.c_double), None if Sbar is None else _p(Sbar, C.c_double),
+                                    _p(rho_bar, C.c_double), _p(Sbar_k, C.c_double))
+        if rc != 0:
+            raise ValueError(f"oracle adjoint failed (status {rc})")
+        Sbar = Sbar_k[:model.s_size] if k > 0 else None
+    return rho_bar
 
 
 @dataclass

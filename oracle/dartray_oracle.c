@@ -742,3 +742,149 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     free(pv);
     return failed ? ORC_E_OOM : ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of one fixed-Nside pass (reverse mode, FP64).                      */
+/*                                                                            */
+/* For a ray with crossings m = 0..M-1 of length l_m in cells c_m, luminosity  */
+/* L_m at entry (L_{m+1} = L_m e^{-tau_m}) and tau_m = kappa rho_{c_m} l_m, the */
+/* pass contributes J_ray = sum_m L_m a_m(tau_m) with                          */
+/*   a_m(tau) = l_m E(tau) Ubar(c_m) / (V c) + albedo (1 - e^{-tau}) sbar_m,    */
+/*   E(tau) = (1 - e^{-tau}) / tau,  sbar_m = sum_p w(p|n) Sbar_next(c_m, p),   */
+/* where Ubar = dJ/dU and Sbar_next = dJ/dS of the luminosity this pass        */
+/* scatters.  With G_m = a_m + e^{-tau_m} G_{m+1} (G_M = 0):                   */
+/*   dJ/dtau_m = L_m (a_m'(tau_m) - e^{-tau_m} G_{m+1}),                       */
+/*   dJ/drho_c += kappa l_m dJ/dtau_m over the crossings in c,                 */
+/*   dJ/dL_0 = G_0, which for a scattering pass flows to the pending           */
+/*   luminosity the ray was launched from (the inverse of the launch rule).    */
+/* ------------------------------------------------------------------------ */
+
+static void orc_E(double tau, double *E, double *dE)
+{
+    if (tau < 1e-4) {
+        *E = 1.0 - tau / 2.0 + tau * tau / 6.0;
+        *dE = -0.5 + tau / 3.0 - tau * tau / 8.0;
+    } else {
+        double em = exp(-tau);
+        *E = -expm1(-tau) / tau;
+        *dE = (em * (1.0 + tau) - 1.0) / (tau * tau);
+    }
+}
+
+/* Ubar [n_lambda][n]; Sbar_next [S size] or NULL (zero); S_pending: the
+ * pass's emission (scattering pass) or NULL (direct pass); rho_bar [n] is
+ * accumulated; Sbar_k [S size] is overwritten for scattering passes. */
+int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pending, const double *Ubar,
+                     const double *Sbar_next, double *rho_bar, double *Sbar_k)
+{
+    const orc_grid_desc *d = &m->d;
+    const int nl = d->n_lambda;
+    const int64_t n = d->n_leaves;
+    if (o->adaptive || nl > 64 || o->nside <= 0 || !is_pow2(o->nside)) return ORC_E_INVALID;
+    const int scatter = o->mode == ORC_SCATTER;
+    if (scatter && (!S_pending || !Sbar_k)) return ORC_E_INVALID;
+    int64_t ssize = m->s_offset[nl];
+    int64_t wsize = ssize / n;
+    int64_t nside = o->nside;
+    int64_t nray = 12 * nside * nside;
+    if (scatter) memset(Sbar_k, 0, sizeof(double) * (size_t)ssize);
+    double *pv = (double *)malloc(sizeof(double) * 3 * (size_t)(wsize > 0 ? wsize : 1));
+    if (!pv) return ORC_E_OOM;
+    for (int l = 0; l < nl; ++l) orc_pixel_table(m->nside_sca[l], o->frame, pv + 3 * (m->s_offset[l] / n));
+    int nthreads = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
+    int64_t maxc = 4 * (m->fine[0] + m->fine[1] + m->fine[2]) + 64;
+    int failed = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        double *w = (double *)malloc(sizeof(double) * (size_t)(wsize > 0 ? wsize : 1));
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxc);
+        double *lens = (double *)malloc(sizeof(double) * (size_t)maxc);
+        double *tins = (double *)malloc(sizeof(double) * (size_t)maxc);
+        double *Lm = (double *)malloc(sizeof(double) * (size_t)maxc);
+        if (!w || !cells || !lens || !tins || !Lm) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t s = 0; s < n; ++s) {
+                if (!scatter && o->source_mask && !o->source_mask[s]) continue;
+                const double *xs = &m->centre[3 * s];
+                for (int64_t r = 0; r < nray; ++r) {
+                    double nvec[3];
+                    orc_ray_dir(o, nside, r, nvec);
+                    int64_t nc = orc_trace_cells(m, xs, nvec, 0.0, maxc, cells, lens, tins);
+                    for (int l = 0; l < nl; ++l)
+                        orc_hg_weights_tab(12 * (int64_t)m->nside_sca[l] * m->nside_sca[l], pv + 3 * (m->s_offset[l] / n),
+                                           d->g[l], nvec, w + m->s_offset[l] / n);
+                    for (int l = 0; l < nl; ++l) {
+                        /* rays with zero launch luminosity still carry sensitivity
+                         * (dJ/dL_0 = G_0) back to the pending luminosity */
+                        double L0 = orc_launch(m, o, S_pending, s, l, nside, r);
+                        if (!scatter && !(L0 > 0.0)) continue;
+                        const double kap = d->kappa[l], om = d->albedo[l], cl = d->c_light;
+                        int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
+                        const double *wl = w + m->s_offset[l] / n;
+                        /* forward: luminosity at entry of each (non-graze) crossing */
+                        double L = L0;
+                        for (int64_t k = 0; k < nc; ++k) {
+                            int64_t c = cells[k];
+                            double te = tins[k] + lens[k];
+                            Lm[k] = L;
+                            if (lens[k] > 1e-6 * (m->side[c] + te)) L *= exp(-kap * d->rho[c] * lens[k]);
+                        }
+                        /* backward suffix recursion */
+                        double G = 0.0;
+                        for (int64_t k = nc - 1; k >= 0; --k) {
+                            int64_t c = cells[k];
+                            double len = lens[k], te = tins[k] + len;
+                            if (!(len > 1e-6 * (m->side[c] + te))) continue;
+                            double vol = m->side[c] * m->side[c] * m->side[c];
+                            double tau = kap * d->rho[c] * len;
+                            double em = exp(-tau), E, dE;
+                            orc_E(tau, &E, &dE);
+                            double sb = 0.0;
+                            if (Sbar_next) {
+                                const double *row = Sbar_next + m->s_offset[l] + c * npix;
+                                for (int64_t q = 0; q < npix; ++q) sb += wl[q] * row[q];
+                            }
+                            double ub = Ubar[(int64_t)l * n + c];
+                            double a = len * E * ub / (vol * cl) + om * (1.0 - em) * sb;
+                            double da = len * dE * ub / (vol * cl) + om * em * sb;
+                            double dtau = Lm[k] * (da - em * G);
+                            G = a + em * G;
+                            double v = kap * len * dtau;
+#pragma omp atomic
+                            rho_bar[c] += v;
+                        }
+                        if (scatter) {
+                            int64_t ns = m->nside_sca[l];
+                            double *srow = Sbar_k + m->s_offset[l] + s * npix;
+                            if (nside >= ns) {
+                                int64_t shift = 0;
+                                while ((ns << shift) < nside) ++shift;
+                                double v = G * (double)npix / (double)nray;
+#pragma omp atomic
+                                srow[r >> (2 * shift)] += v;
+                            } else {
+                                int64_t shift = 0;
+                                while ((nside << shift) < ns) ++shift;
+                                int64_t nch = (int64_t)1 << (2 * shift);
+                                for (int64_t q = r * nch; q < (r + 1) * nch; ++q) {
+#pragma omp atomic
+                                    srow[q] += G;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        free(w);
+        free(cells);
+        free(lens);
+        free(tins);
+        free(Lm);
+    }
+    free(pv);
+    return failed ? ORC_E_OOM : ORC_OK;
+}
