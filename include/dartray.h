@@ -218,13 +218,25 @@ int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dar
 int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields, double *r_k);
 
 /*
- * Gradient of a loss of U with respect to rho, by an adjoint march that
- * recomputes every ray in reverse (no ray storage).  fwd holds the forward
- * run's fields; dJ_dU [n_lambda][n] (device) is dLoss/dU; dJ_drho [n] (device)
- * is overwritten.  Not available in this build: returns DARTRAY_E_UNSUPPORTED.
+ * Gradient dJ/drho of a loss J of the energy density U with respect to the
+ * per-cell dust density, by an adjoint march over the passes of a fixed-ray
+ * run in reverse order (scattering iteration n_scatter down to the direct
+ * pass).  Rays are recomputed, not stored: each ray is walked twice, first for
+ * the total of its loss-weighted deposits, then for the derivative at every
+ * crossing as a prefix difference (FP64); the result flows from each pass to
+ * the scattered luminosity that fed it through the inverse launch rule.
+ * Fixed rays only (opts->adaptive = 0, opts->nside <= 16) and at most 8
+ * wavelengths; opts must be those of the forward run, and the grid's rho the
+ * forward run's.  This extends the method (the paper has no gradients).
+ *  n_scatter  scattering iterations of the forward run (>= 0)
+ *  S_hist     host array of n_scatter device pointers; S_hist[k-1] is the
+ *             pending scattered luminosity iteration k processed (S_pending
+ *             before that dartray_scatter_iter call), S layout
+ *  dJ_dU      device float [n_lambda][n]
+ *  dJ_drho    device float [n], overwritten
  */
-int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, const dartray_fields *fwd,
-                          const float *dJ_dU, const float *dJ_dj, const float *dJ_desc, float *dJ_drho);
+int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, int32_t n_scatter,
+                          const float *const *S_hist, const float *dJ_dU, float *dJ_drho);
 
 /*
  * Test helper: the cells crossed by n_rays rays (host arrays: origin[3i],

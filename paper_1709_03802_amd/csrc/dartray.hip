@@ -1232,6 +1232,215 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
     flush();
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of fixed-ray passes.  For a ray with luminosity L_0 l_m at the
+// entry of crossing m (l_0 = 1), the loss-weighted deposit of the crossing is
+// L_0 l_m a_m(tau_m) with
+//   a_m(tau) = l E(tau) Ubar / (V c) + albedo (1 - e^{-tau}) sbar_m,
+//   E(tau) = (1 - e^{-tau}) / tau,  sbar_m = sum_p w(p|n) Sbar_next(c_m, p).
+// With G = sum_m l_m a_m and the prefix P_m = sum_{i<=m} l_i a_i,
+//   dJ/dtau_m = L_0 (l_m a_m'(tau_m) - (G - P_m)),  dJ/drho += kappa l dJ/dtau,
+// and dJ/dL_0 = G goes to the pending luminosity the ray was launched from.
+// ---------------------------------------------------------------------------
+
+// sbar[l][rl][c] = sum_p w_l(p | r0 + rl) Sbar[l][c][p]; grid (cells / 256, nb, nl)
+__global__ __launch_bounds__(256) void k_sbar_gather(float *sig, const float *wtab, const LambdaTable *lt,
+                                                      const float *Sbar, int64_t n, int r0, int nb, int w_row)
+{
+    const int l = blockIdx.z;
+    const int rl = blockIdx.y;
+    const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (c >= n) return;
+    const int npix = lt->npix[l];
+    const float *w = wtab + (int64_t)(r0 + rl) * w_row + lt->w_off[l];
+    const float *row = Sbar + lt->s_off[l] + c * (int64_t)npix;
+    float acc = 0.f;
+    for (int p = 0; p < npix; ++p) acc = fmaf(w[p], row[p], acc);
+    sig[((int64_t)l * nb + rl) * n + c] = acc;
+}
+
+struct AdjArgs {
+    Geo geo;
+    const int32_t *src_list;
+    const int32_t *n_src;
+    const float4 *dirs;          // directions of this Nside
+    const float *emis_lum;       // direct pass
+    const float *S_pending;      // scattering pass: its emission
+    const LambdaTable *lt;
+    const float *ubar_t;         // dJ/dU, [n][n_lambda]
+    const float *sig;            // sbar per (wavelength, direction, cell), or null
+    double *rho_bar;
+    float *sbar_k;               // dJ/dS of the pass's emission (scattering pass)
+    int64_t n;
+    int32_t scatter;
+    int32_t r0;
+    int32_t nb;
+    int32_t log2_nside_ray;
+    float inv_nray;
+    float h_fine;
+    int64_t hard_cap;
+};
+
+// E(tau) = (1 - e^{-tau}) / tau and E'(tau) from em1 = e^{-tau} - 1
+__device__ inline void eprime(float tau, float em1, float &E, float &dE)
+{
+    if (tau < 0.05f) {
+        E = 1.f + tau * (-0.5f + tau * (1.f / 6.f + tau * (-1.f / 24.f + tau * (1.f / 120.f))));
+        dE = -0.5f + tau * (1.f / 3.f + tau * (-0.125f + tau * (1.f / 30.f + tau * (-1.f / 144.f))));
+    } else {
+        E = -em1 / tau;
+        dE = fmaf(em1, 1.f + tau, tau) / (tau * tau);
+    }
+}
+
+template <int NL, bool UNIFORM>
+__global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
+{
+    const LambdaTable *lt = A.lt;
+    const int nl = lt->n_lambda;
+    const int lane = threadIdx.x & 63;
+    (void)lane;
+    const int64_t wid = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int nsrc = *A.n_src;
+    const int64_t ntiles = (nsrc + 63) >> 6;
+    const int64_t nitems = ntiles * A.nb;
+    float kap[NL], alb[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        kap[l] = l < nl ? lt->kappa[l] : 0.f;
+        alb[l] = l < nl ? lt->albedo[l] : 0.f;
+    }
+    for (int64_t it = wid; it < nitems; it += nw) {
+        const int64_t tile = it / A.nb;
+        const int rl = (int)(it - tile * A.nb);
+        const int r = A.r0 + rl;
+        const int64_t si = tile * 64 + (threadIdx.x & 63);
+        if (si >= nsrc) continue;
+        const int32_t s = A.src_list[si];
+        const float4 nd = A.dirs[r];
+        Ray R;
+        R.n[0] = nd.x;
+        R.n[1] = nd.y;
+        R.n[2] = nd.z;
+        const int4 sb = A.geo.rec[s].box;
+        const float half = 0.5f * (float)sb.w;
+        R.o[0] = (float)sb.x + half;
+        R.o[1] = (float)sb.y + half;
+        R.o[2] = (float)sb.z + half;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
+        float L0[NL];
+        float lsum = 0.f;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            float v = 0.f;
+            if (l < nl) {
+                if (!A.scatter) {
+                    v = A.emis_lum[(int64_t)l * A.n + s] * A.inv_nray;
+                } else {
+                    const int npix = lt->npix[l];
+                    const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
+                    const int ls = 31 - __clz(lt->nside_sca[l]);
+                    if (A.log2_nside_ray >= ls) {
+                        v = row[r >> (2 * (A.log2_nside_ray - ls))] * ((float)npix * A.inv_nray);
+                    } else {
+                        const int sh = 2 * (ls - A.log2_nside_ray);
+                        for (int q = r << sh; q < ((r + 1) << sh); ++q) v += row[q];
+                    }
+                }
+            }
+            L0[l] = v;
+            lsum += v;
+        }
+        // the direct pass's emission does not depend on rho: rays that carry
+        // nothing contribute nothing; scattered light needs dJ/dL_0 regardless
+        if (!A.scatter && !(lsum > 0.f)) continue;
+
+        double G[NL], P[NL];
+        float ell[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            G[l] = 0.0;
+            P[l] = 0.0;
+        }
+        for (int walk = 0; walk < 2; ++walk) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) ell[l] = 1.f;
+            int32_t c = s;
+            float t = 0.f;
+            int64_t steps = 0;
+            while (true) {
+                const LeafRec &rc = A.geo.rec[c];
+                const int4 b = rc.box;
+                int32_t nbc[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+                int axis;
+                const float te = exit_t(R, b, axis);
+                const float len = te - t;
+                if (len > 1e-6f * ((float)b.w + te)) {
+                    const float rho = rc.rho;
+                    const float ivc = rc.ivc;
+                    const float lp = len * A.h_fine;
+                    double rb = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        if (l < nl) {
+                            const float alpha = kap[l] * rho;
+                            const float tau = alpha * lp;
+                            const float em1 = expm1f(-tau);
+                            float E, dE;
+                            eprime(tau, em1, E, dE);
+                            const float ub = A.ubar_t[(int64_t)c * nl + l];
+                            const float sg = A.sig ? A.sig[((int64_t)l * A.nb + rl) * A.n + c] : 0.f;
+                            const float a = lp * E * ivc * ub - alb[l] * em1 * sg;
+                            if (walk == 0) {
+                                G[l] += (double)ell[l] * (double)a;
+                            } else {
+                                const float ap = lp * dE * ivc * ub + alb[l] * (1.f + em1) * sg;
+                                P[l] += (double)ell[l] * (double)a;
+                                const double dtau = (double)L0[l] * ((double)ell[l] * (double)ap - (G[l] - P[l]));
+                                rb += (double)kap[l] * (double)lp * dtau;
+                            }
+                            ell[l] = fmaf(ell[l], em1, ell[l]);
+                        }
+                    }
+                    if (walk == 1 && rb != 0.0) atomic_add_f64(A.rho_bar + c, rb);
+                    t = te;
+                }
+                const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
+                if (nx < 0) break;
+                if (++steps >= A.hard_cap) break;
+                c = nx;
+            }
+        }
+        if (A.scatter) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (l < nl && G[l] != 0.0) {
+                    const int npix = lt->npix[l];
+                    float *row = A.sbar_k + lt->s_off[l] + (int64_t)s * npix;
+                    const int ls = 31 - __clz(lt->nside_sca[l]);
+                    if (A.log2_nside_ray >= ls) {
+                        atomic_add_f32(row + (r >> (2 * (A.log2_nside_ray - ls))),
+                                       (float)(G[l] * ((double)npix * (double)A.inv_nray)));
+                    } else {
+                        const int sh = 2 * (ls - A.log2_nside_ray);
+                        for (int q = r << sh; q < ((r + 1) << sh); ++q) atomic_add_f32(row + q, (float)G[l]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_rho_out(const double *rb, float *out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)rb[i];
+}
+
 // U += U_k (and U_pass = U_k), absorbed / scattered tallies from U_k in FP64,
 // U_LL <- U when requested.  grid.y = wavelength
 __global__ void k_finish_u(const double *U_k, float *U, float *U_pass, float *U_LL, int set_ull, int ull_only,
@@ -1359,7 +1568,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.rec, g.ull_t, g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
+    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
                     g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -1581,7 +1790,8 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, ((size_t)8 << 30) / (4 * per_dir)));
     int rcs[] = {
         dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
-        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)),
+        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n),
+        dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
         dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.d_lt, 1),
         dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
@@ -2167,17 +2377,98 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
     return DARTRAY_OK;
 }
 
-int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, const dartray_fields *fwd,
-                          const float *dJ_dU, const float *dJ_dj, const float *dJ_desc, float *dJ_drho)
+int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, int32_t n_scatter,
+                          const float *const *S_hist, const float *dJ_dU, float *dJ_drho)
 {
-    (void)opts;
-    (void)fwd;
-    (void)dJ_dU;
-    (void)dJ_dj;
-    (void)dJ_desc;
-    (void)dJ_drho;
     if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
-    return fail(DARTRAY_E_UNSUPPORTED, "the adjoint march is not available in this build");
+    Grid &g = grid->g;
+    if (!opts || !dJ_dU || !dJ_drho || n_scatter < 0 || (n_scatter > 0 && !S_hist))
+        return fail(DARTRAY_E_INVALID, "bad argument");
+    for (int k = 0; k < n_scatter; ++k)
+        if (!S_hist[k]) return fail(DARTRAY_E_INVALID, "null S_hist entry");
+    if (opts->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "the adjoint covers fixed rays only");
+    if (opts->nside <= 0 || (opts->nside & (opts->nside - 1)) || opts->nside > kMaxNsideWTable)
+        return fail(DARTRAY_E_INVALID, "adjoint nside must be a power of two <= 16");
+    if (g.n_lambda > 8) return fail(DARTRAY_E_UNSUPPORTED, "the adjoint carries at most 8 wavelengths");
+    const int nl = g.n_lambda;
+    const int64_t n = g.n;
+    Frame fr;
+    frame_of(opts, fr);
+    int rc = ensure_dirs(g, fr);
+    if (rc) return rc;
+    if ((rc = ensure_wtab(g, opts->nside, fr))) return rc;
+    const int64_t nray = 12 * (int64_t)opts->nside * opts->nside;
+    int log2n = 0;
+    while ((1 << log2n) < opts->nside) ++log2n;
+    if ((rc = fill<double>(g, g.rho_bar, (size_t)n, 0.0))) return rc;
+    hipLaunchKernelGGL(k_transpose_ull, dim3((unsigned)std::min<int64_t>((n * nl + 255) / 256, 8192)), dim3(256), 0,
+                       g.stream, dJ_dU, g.ull_t, n, nl);
+    DR_LAUNCH_CHECK("k_transpose_ull");
+    const size_t per_dir = (size_t)nl * n;
+    const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
+    AdjArgs A{};
+    A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
+                g.max_level};
+    A.src_list = g.src_list;
+    A.n_src = g.n_src;
+    A.dirs = g.dir_all + entry_of(opts->nside, 0);
+    A.emis_lum = g.emis_lum;
+    A.lt = g.d_lt;
+    A.ubar_t = g.ull_t;
+    A.rho_bar = g.rho_bar;
+    A.n = n;
+    A.log2_nside_ray = log2n;
+    A.inv_nray = (float)(1.0 / (double)nray);
+    A.h_fine = (float)g.h_fine;
+    A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
+    const float *sbar_next = nullptr;
+    for (int k = n_scatter; k >= 0; --k) {
+        const bool scatter = k > 0;
+        float *sbar_k = scatter ? g.sbar[k & 1] : nullptr;
+        if (scatter) {
+            if ((rc = fill<float>(g, sbar_k, (size_t)g.s_size, 0.f))) return rc;
+            // every cell may feed scattered light back: all cells are sources
+            DR_HIP(hipMemcpyAsync(g.src_list, g.morton, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, g.stream));
+            if ((rc = fill<int32_t>(g, g.n_src, 1, (int32_t)n))) return rc;
+        } else {
+            dartray_fields tmp{};
+            tmp.tally = g.dsum;   // emitted luminosity sums are not needed here
+            if ((rc = fill<double>(g, g.dsum, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
+            if ((rc = select_sources(g, opts, &tmp, false))) return rc;
+        }
+        A.scatter = scatter ? 1 : 0;
+        A.S_pending = scatter ? S_hist[k - 1] : nullptr;
+        A.sbar_k = sbar_k;
+        for (int64_t r0 = 0; r0 < nray; r0 += nb_max) {
+            const int nb = (int)std::min<int64_t>(nb_max, nray - r0);
+            A.r0 = (int)r0;
+            A.nb = nb;
+            A.sig = nullptr;
+            if (sbar_next) {
+                hipLaunchKernelGGL(k_sbar_gather, dim3((unsigned)((n + 255) / 256), nb, nl), dim3(256), 0, g.stream, g.ubar,
+                                   g.wtab, g.d_lt, sbar_next, n, (int)r0, nb, g.w_row);
+                DR_LAUNCH_CHECK("k_sbar_gather");
+                A.sig = g.ubar;
+            }
+            const unsigned blocks = 2048;
+            if (nl <= 1) {
+                if (g.uniform) hipLaunchKernelGGL((k_march_adjoint<1, true>), dim3(blocks), dim3(256), 0, g.stream, A);
+                else hipLaunchKernelGGL((k_march_adjoint<1, false>), dim3(blocks), dim3(256), 0, g.stream, A);
+            } else if (nl <= 4) {
+                if (g.uniform) hipLaunchKernelGGL((k_march_adjoint<4, true>), dim3(blocks), dim3(256), 0, g.stream, A);
+                else hipLaunchKernelGGL((k_march_adjoint<4, false>), dim3(blocks), dim3(256), 0, g.stream, A);
+            } else {
+                if (g.uniform) hipLaunchKernelGGL((k_march_adjoint<8, true>), dim3(blocks), dim3(256), 0, g.stream, A);
+                else hipLaunchKernelGGL((k_march_adjoint<8, false>), dim3(blocks), dim3(256), 0, g.stream, A);
+            }
+            DR_LAUNCH_CHECK("k_march_adjoint");
+        }
+        sbar_next = sbar_k;
+    }
+    hipLaunchKernelGGL(k_rho_out, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, g.stream,
+                       g.rho_bar, dJ_drho, n);
+    DR_LAUNCH_CHECK("k_rho_out");
+    return DARTRAY_OK;
 }
 
 }  // extern "C"

@@ -120,6 +120,10 @@ struct Grid {
     int32_t key_bits = 1;
     int64_t log_chunks = 0;               // launches of the last adaptive pass
 
+    // adjoint work arrays
+    double *rho_bar = nullptr;            // [n] FP64 accumulator of dJ/drho
+    float *sbar[2] = {nullptr, nullptr};  // [s_size] dJ/dS of consecutive orders
+
     size_t bytes = 0;
 
     // march-kernel timing

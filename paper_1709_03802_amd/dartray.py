@@ -120,8 +120,8 @@ def load_library():
     L.dartray_grid_set_rho.argtypes = [C.c_void_p, C.c_void_p]
     L.dartray_trace_direct.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC)]
     L.dartray_scatter_iter.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.POINTER(C.c_double)]
-    L.dartray_trace_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.c_void_p,
-                                        C.c_void_p, C.c_void_p, C.c_void_p]
+    L.dartray_trace_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.c_int32, C.POINTER(C.c_void_p),
+                                        C.c_void_p, C.c_void_p]
     L.dartray_debug_ray_cells.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                           C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_float),
                                           C.POINTER(C.c_int32)]
@@ -293,12 +293,58 @@ def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields) -> float:
     return rk.value
 
 
-def trace_adjoint(grid: Grid, opts: TraceOpts, fields: Fields, dJ_dU, dJ_drho, dJ_dj=None, dJ_desc=None):
-    fc = fields.c()
-    _check(load_library().dartray_trace_adjoint(
-        grid.h, C.byref(opts), C.byref(fc), C.c_void_p(dJ_dU.data_ptr()),
-        None if dJ_dj is None else C.c_void_p(dJ_dj.data_ptr()),
-        None if dJ_desc is None else C.c_void_p(dJ_desc.data_ptr()), C.c_void_p(dJ_drho.data_ptr())))
+def trace_adjoint(grid: Grid, opts: TraceOpts, S_hist, dJ_dU, dJ_drho):
+    """dJ/drho into dJ_drho (device float [n]) for dJ_dU (device [nl, n]).
+
+    S_hist: the S_pending tensors each scattering iteration of the forward run
+    processed, in order (``DartRayFn`` keeps them)."""
+    arr = (C.c_void_p * max(len(S_hist), 1))(*[t.data_ptr() for t in S_hist])
+    _check(load_library().dartray_trace_adjoint(grid.h, C.byref(opts), len(S_hist), arr,
+                                                C.c_void_p(dJ_dU.data_ptr()), C.c_void_p(dJ_drho.data_ptr())))
+
+
+def _autograd():
+    import torch
+
+    class DartRayFn(torch.autograd.Function):
+        """rho (device float [n]) -> U (device float [n_lambda, n]) for a fixed-ray
+        run (direct pass + policy.n_scatter scattering iterations); backward
+        by the adjoint march."""
+
+        @staticmethod
+        def forward(ctx, rho, grid, policy, frame=None):
+            grid.set_rho(rho.detach().contiguous())
+            f = Fields(grid)
+            opts = make_opts(policy, MODE_DIRECT, frame, counters=False)
+            trace_direct(grid, opts, f)
+            hist = []
+            for _ in range(policy.n_scatter):
+                hist.append(f.S_pending.clone())
+                scatter_iter(grid, opts, f)
+            ctx.grid, ctx.opts, ctx.hist = grid, opts, hist
+            ctx.save_for_backward(rho)
+            return f.U.clone()
+
+        @staticmethod
+        def backward(ctx, gU):
+            (rho,) = ctx.saved_tensors
+            ctx.grid.set_rho(rho.detach().contiguous())
+            drho = torch.empty_like(rho)
+            trace_adjoint(ctx.grid, ctx.opts, ctx.hist, gU.contiguous().to(torch.float32), drho)
+            return drho, None, None, None
+
+    return DartRayFn
+
+
+_fn = None
+
+
+def rfed(rho, grid: Grid, policy, frame=None):
+    """Differentiable energy density U(rho) (see ``DartRayFn``)."""
+    global _fn
+    if _fn is None:
+        _fn = _autograd()
+    return _fn.apply(rho, grid, policy, frame)
 
 
 def debug_ray_cells(grid: Grid, origins, dirs, max_cross=4096):
