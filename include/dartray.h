@@ -265,6 +265,34 @@ int dartray_profile_read(dartray_grid *grid, double *march_ms, int64_t *launches
 /* Bytes of device work memory the handle holds. */
 int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes);
 
+/*
+ * Launch parameters of the fixed-ray passes (the autotuner's search space).
+ * A zero field takes the default.  They change speed only: any setting gives
+ * the same deposits, up to the order of FP32 additions into the bins.
+ *  lambda_tile  wavelengths one march launch carries (1, 4, 8, 16, 32, 64;
+ *               default all): the ray geometry is recomputed once per tile,
+ *               so a tile of all wavelengths is the batched form of Sect. 3.3
+ *               and a tile of 1 is the plain per-wavelength form
+ *  block_waves  64-lane waves per workgroup of the march (1, 2 or 4; default 4)
+ *  grid_blocks  workgroups of the persistent march (1 .. 65536; default 2048)
+ *  dir_batch    directions binned between two flushes (default: as many as
+ *               the handle's bin array holds)
+ *  item_order   0: a wave's next work item is the next direction of the same
+ *               64-source tile; 1: the next source tile of the same direction
+ */
+typedef struct {
+    int32_t lambda_tile;
+    int32_t block_waves;
+    int32_t grid_blocks;
+    int32_t dir_batch;
+    int32_t item_order;
+} dartray_tuning;
+
+/* Set / read the handle's fixed-ray launch parameters.  Invalid values give
+ * DARTRAY_E_INVALID and leave the setting unchanged. */
+int dartray_set_tuning(dartray_grid *grid, const dartray_tuning *tuning);
+int dartray_get_tuning(const dartray_grid *grid, dartray_tuning *tuning);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *dartray_last_error(void);
 

@@ -427,13 +427,16 @@ struct FixedArgs {
     const float *emis_lum;       // direct pass
     const float *S_pending;      // scatter pass
     const LambdaTable *lt;
-    float *ubar;
+    float *ubar;                 // [nb][n][n_lambda] direction-binned energy density
     double *tally;
-    uint64_t *counters;
+    uint64_t *counters;          // null: this launch does not count
     int64_t n;
     int32_t scatter;
     int32_t r0;
     int32_t nb;
+    int32_t l0;                  // wavelengths l0 .. l0 + nlc - 1 ride on this launch
+    int32_t nlc;
+    int32_t order;               // 0: a wave's next item is the next direction, 1: the next source tile
     int32_t nside_ray;
     int32_t log2_nside_ray;
     float inv_nray;
@@ -442,12 +445,40 @@ struct FixedArgs {
     int64_t hard_cap;            // bound no straight ray can exceed; ends any loop
 };
 
-template <int NL, bool UNIFORM>
+// Launch luminosity of source s along ray r at wavelength l: the direct pass
+// spreads 4 pi j V evenly over the rays; a scattering pass takes the pending
+// scattered luminosity of the nested pixel that contains r (scaled by
+// N_pix / N_ray), or sums the pixels inside r when rays are coarser.
+__device__ inline float fixed_launch(const FixedArgs &A, const LambdaTable *lt, int l, int32_t s, int r)
+{
+    if (!A.scatter) return A.emis_lum[(int64_t)l * A.n + s] * A.inv_nray;
+    const int npix = lt->npix[l];
+    const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
+    const int ls = 31 - __clz(lt->nside_sca[l]);
+    if (A.log2_nside_ray >= ls) return row[r >> (2 * (A.log2_nside_ray - ls))] * ((float)npix * A.inv_nray);
+    float v = 0.f;
+    const int sh = 2 * (ls - A.log2_nside_ray);
+    for (int q = r << sh; q < ((r + 1) << sh); ++q) v += row[q];
+    return v;
+}
+
+// Fixed-Nside march.  A work item is (64 Morton-consecutive sources, one
+// direction); the wave's lanes walk their rays in lock step, one cell per
+// iteration, and the iteration's deposits go out wave-cooperatively: the NL
+// wavelength values of a crossing are one contiguous row of the bin array, and
+// one atomic instruction carries 64 / NL crossings.
+template <int NL>
 __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
 {
+    constexpr int kBlock = 256;
+    __shared__ float s_du[NL][kBlock];
+    __shared__ int32_t s_cell[kBlock];
+    __shared__ uint8_t s_list[kBlock];
     const LambdaTable *lt = A.lt;
     const int nl = lt->n_lambda;
+    const int nlc = A.nlc, l0 = A.l0;
     const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
     const int64_t wid = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int nsrc = *A.n_src;
@@ -458,163 +489,216 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         esc[l] = 0.f;
-        kap[l] = l < nl ? lt->kappa[l] : 0.f;
+        kap[l] = l < nlc ? lt->kappa[l0 + l] : 0.f;
     }
     uint32_t ncross = 0, nrays = 0, nmax = 0;
 
     for (int64_t it = wid; it < nitems; it += nw) {
-        const int64_t tile = it / A.nb;
-        const int rl = (int)(it - tile * A.nb);
+        int64_t tile;
+        int rl;
+        if (A.order == 0) {
+            tile = it / A.nb;
+            rl = (int)(it - tile * A.nb);
+        } else {
+            rl = (int)(it / ntiles);
+            tile = it - (int64_t)rl * ntiles;
+        }
         const int r = A.r0 + rl;
         const int64_t si = tile * 64 + lane;
-        if (si >= nsrc) continue;
-        const int32_t s = A.src_list[si];
-        const float4 nd = A.dirs[r];
+        bool active = si < nsrc;
+        int32_t c = 0;
         Ray R;
-        R.n[0] = nd.x;
-        R.n[1] = nd.y;
-        R.n[2] = nd.z;
-        int4 b = A.geo.rec[s].box;
-        const float half = 0.5f * (float)b.w;
-        R.o[0] = (float)b.x + half;
-        R.o[1] = (float)b.y + half;
-        R.o[2] = (float)b.z + half;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
-
-        // launch luminosity
         float L[NL];
-        float lsum = 0.f;
 #pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            float v = 0.f;
-            if (l < nl) {
-                if (!A.scatter) {
-                    v = A.emis_lum[(int64_t)l * A.n + s] * A.inv_nray;
-                } else {
-                    const int npix = lt->npix[l];
-                    const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
-                    const int ls = 31 - __clz(lt->nside_sca[l]);
-                    if (A.log2_nside_ray >= ls) {
-                        v = row[r >> (2 * (A.log2_nside_ray - ls))] * ((float)npix * A.inv_nray);
-                    } else {
-                        const int sh = 2 * (ls - A.log2_nside_ray);
-                        for (int q = r << sh; q < ((r + 1) << sh); ++q) v += row[q];
-                    }
+        for (int l = 0; l < NL; ++l) L[l] = 0.f;
+        if (active) {
+            const int32_t s = A.src_list[si];
+            const float4 nd = A.dirs[r];
+            R.n[0] = nd.x;
+            R.n[1] = nd.y;
+            R.n[2] = nd.z;
+            const int4 b = A.geo.rec[s].box;
+            const float half = 0.5f * (float)b.w;
+            R.o[0] = (float)b.x + half;
+            R.o[1] = (float)b.y + half;
+            R.o[2] = (float)b.z + half;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
+            float lsum = 0.f;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (l < nlc) {
+                    L[l] = fixed_launch(A, lt, l0 + l, s, r);
+                    lsum += L[l];
                 }
             }
-            L[l] = v;
-            lsum += v;
+            // the counting launch traces a ray when any wavelength carries light
+            if (!(lsum > 0.f) && A.counters)
+                for (int l = 0; l < nl; ++l)
+                    if (l < l0 || l >= l0 + nlc) lsum += fixed_launch(A, lt, l, s, r);
+            active = lsum > 0.f;
+            c = s;
+            if (active) ++nrays;
         }
-        if (!(lsum > 0.f)) continue;
-        ++nrays;
-
-        int32_t c = s;
         float t = 0.f;
         int64_t steps = 0;
-        while (true) {
-            const LeafRec &rc = A.geo.rec[c];
-            b = rc.box;
-            const float rho = rc.rho;
-            const float ivc = rc.ivc;
-            int32_t nbc[6];
+        float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
+        while (__ballot(active)) {
+            bool dep = false;
+            if (active) {
+                const LeafRec &rc = A.geo.rec[c];
+                const int4 b = rc.box;
+                const float rho = rc.rho;
+                const float ivc = rc.ivc;
+                int32_t nbc[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
-            int axis;
-            const float te = exit_t(R, b, axis);
-            const float len = te - t;
-            if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
-                const float lp = len * A.h_fine;
-                float *ub = A.ubar + (size_t)rl * A.n + c;
-                const size_t lstride = (size_t)A.nb * A.n;
+                for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+                int axis;
+                const float te = exit_t(R, b, axis);
+                const float len = te - t;
+                if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
+                    const float lp = len * A.h_fine;
 #pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    if (l < nl) {
-                        const float alpha = kap[l] * rho;
-                        const float tau = alpha * lp;
-                        const float em1 = expm1f(-tau);          // exp(-tau) - 1
-                        const float ext = -L[l] * em1;
-                        const float du = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
-                        atomic_add_f32(ub + l * lstride, du);
-                        L[l] = fmaf(L[l], em1, L[l]);
+                    for (int l = 0; l < NL; ++l) {
+                        if (l < nlc) {
+                            const float alpha = kap[l] * rho;
+                            const float tau = alpha * lp;
+                            const float em1 = expm1f(-tau);          // exp(-tau) - 1
+                            const float ext = -L[l] * em1;
+                            s_du[l][threadIdx.x] = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
+                            L[l] = fmaf(L[l], em1, L[l]);
+                        }
+                    }
+                    s_cell[threadIdx.x] = c;
+                    dep = true;
+                    ++ncross;
+                    t = te;
+                }
+                const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
+                if (nx < 0) {
+                    active = false;
+                } else {
+                    ++steps;
+                    if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
+                        ++nmax;
+                        active = false;
+                    } else {
+                        c = nx;
                     }
                 }
-                ++ncross;
-                t = te;
-            }
-            const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
-            if (nx < 0) break;
-            ++steps;
-            if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
-                ++nmax;
-                break;
-            }
-            c = nx;
-        }
+                if (!active) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l) esc[l] += L[l];
+                    for (int l = 0; l < NL; ++l) esc[l] += L[l];
+                }
+            }
+            // lanes q of an instruction add value q % NL of the (q / NL)-th
+            // depositing lane
+            const uint64_t dm = __ballot(dep);
+            if (dm) {
+                if (dep) s_list[wbase + __popcll(dm & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int cnt = __popcll(dm);
+                constexpr int PER = 64 / NL;
+                for (int k0 = 0; k0 < cnt; k0 += PER) {
+                    const int q = k0 + lane / NL;
+                    const int l = lane % NL;
+                    if (q < cnt && l < nlc) {
+                        const int j = s_list[wbase + q];
+                        atomic_add_f32(ubase + (size_t)s_cell[wbase + j] * nl + l, s_du[l][wbase + j]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
     }
     // wave-level FP64 reductions of the tallies
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-        if (l < nl) {
+        if (l < nlc) {
             const double v = wave_sum((double)esc[l]);
-            if (lane == 0 && v != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
+            if (lane == 0 && v != 0.0) atomic_add_f64(&A.tally[(l0 + l) * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
         }
     }
-    const uint64_t wc = wave_sum_u64(ncross), wr = wave_sum_u64(nrays), wm = wave_sum_u64(nmax);
-    if (lane == 0 && A.counters) {
-        if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_CROSSINGS], (unsigned long long)wc);
-        if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_RAYS], (unsigned long long)wr);
-        if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_ESCAPES], (unsigned long long)(wr - wm));
-        if (wm) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_MAXSTEP], (unsigned long long)wm);
-        if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_DEPOSITS], (unsigned long long)(wc * nl));
-        // deposits count the counted crossings times the wavelengths carried
+    if (A.counters) {
+        const uint64_t wc = wave_sum_u64(ncross), wr = wave_sum_u64(nrays), wm = wave_sum_u64(nmax);
+        if (lane == 0) {
+            if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_CROSSINGS], (unsigned long long)wc);
+            if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_RAYS], (unsigned long long)wr);
+            if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_ESCAPES], (unsigned long long)(wr - wm));
+            if (wm) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_MAXSTEP], (unsigned long long)wm);
+            // deposits count the counted crossings times the wavelengths carried
+            if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_DEPOSITS], (unsigned long long)(wc * nl));
+        }
     }
 }
 
-// U_k[l][c] += sum_r ubar[l][r][c];  S[l][c][p] += albedo c alpha V sum_r ubar[l][r][c] w_l(p|r)
-// grid: x = cell tiles of 256, y = pixel chunks of PCH, z = wavelength
+// Flush of one direction batch:
+//   U_k[c][l] += sum_r ubar[r][c][l]
+//   S[l][c][p] += albedo kappa rho V c sum_r ubar[r][c][l] w_l(p|r)
+// A block holds 256 / NLP cells x NLP wavelength slots (NLP = n_lambda rounded
+// up to a power of two), so its bin reads are one contiguous range per
+// direction; blockIdx.y picks a chunk of PCH pixels.  The phase weights of RB
+// directions are staged in LDS as [direction][wavelength][PCH + 1] (the odd row
+// stride spreads the wavelengths over the banks).
 template <int PCH>
 __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const float *wtab, const LambdaTable *lt,
                                                       const float *rho, const float *inv_vc, int64_t n, int r0,
-                                                      int nb, int w_row, double *U_k, float *S_next)
+                                                      int nb, int w_row, int log2_nlp, int rb_stage, double *U_k,
+                                                      float *S_next)
 {
-    __shared__ float ws[64][PCH];
-    const int l = blockIdx.z;
-    const int npix = lt->npix[l];
+    extern __shared__ float ws[];
+    constexpr int PS = PCH + 1;
+    const int nl = lt->n_lambda;
+    const int l = threadIdx.x & ((1 << log2_nlp) - 1);
+    const int64_t c = blockIdx.x * (int64_t)(256 >> log2_nlp) + (threadIdx.x >> log2_nlp);
     const int p0 = blockIdx.y * PCH;
-    if (p0 >= npix) return;
-    const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
-    const bool ok = c < n;
+    const bool ok = c < n && l < nl;
+    const int npix = ok ? lt->npix[l] : 0;
+    const bool pix = ok && p0 < npix;
     float acc[PCH];
 #pragma unroll
     for (int j = 0; j < PCH; ++j) acc[j] = 0.f;
     float accU = 0.f;
-    const float *ub = ubar + (size_t)l * nb * n + (ok ? c : 0);
-    for (int rb = 0; rb < nb; rb += 64) {
-        const int cnt = min(64, nb - rb);
+    const float *ub = ubar + (ok ? (size_t)c * nl + l : 0);
+    const size_t rstride = (size_t)n * nl;
+    const float *wsl = ws + (size_t)(ok ? l : 0) * PS;
+    for (int rb = 0; rb < nb; rb += rb_stage) {
+        const int cnt = min(rb_stage, nb - rb);
         __syncthreads();
-        for (int e = threadIdx.x; e < cnt * PCH; e += 256) {
-            const int i = e / PCH, j = e - (e / PCH) * PCH;
-            ws[i][j] = wtab[(int64_t)(r0 + rb + i) * w_row + lt->w_off[l] + p0 + j];
+        for (int e = threadIdx.x; e < cnt * nl * PCH; e += 256) {
+            const int i = e / (nl * PCH);
+            const int rem = e - i * (nl * PCH);
+            const int ll = rem / PCH, j = rem - (rem / PCH) * PCH;
+            const int p = p0 + j;
+            ws[(i * nl + ll) * PS + j] =
+                p < lt->npix[ll] ? wtab[(int64_t)(r0 + rb + i) * w_row + lt->w_off[ll] + p] : 0.f;
         }
         __syncthreads();
         if (ok) {
             for (int i = 0; i < cnt; ++i) {
-                const float u = ub[(size_t)(rb + i) * n];
+                const float u = ub[(size_t)(rb + i) * rstride];
                 accU += u;
+                if (pix) {
+                    const float *w = wsl + (size_t)i * nl * PS;
 #pragma unroll
-                for (int j = 0; j < PCH; ++j) acc[j] = fmaf(u, ws[i][j], acc[j]);
+                    for (int j = 0; j < PCH; ++j) acc[j] = fmaf(u, w[j], acc[j]);
+                }
             }
         }
     }
     if (!ok) return;
-    const float f = lt->albedo[l] * lt->kappa[l] * rho[c] / inv_vc[c];
-    float *srow = S_next + lt->s_off[l] + c * (int64_t)npix + p0;
+    if (pix) {
+        const float f = lt->albedo[l] * lt->kappa[l] * rho[c] / inv_vc[c];
+        float *srow = S_next + lt->s_off[l] + c * (int64_t)npix + p0;
 #pragma unroll
-    for (int j = 0; j < PCH; ++j) srow[j] += f * acc[j];
-    if (blockIdx.y == 0) U_k[c * lt->n_lambda + l] += (double)accU;
+        for (int j = 0; j < PCH; ++j)
+            if (p0 + j < npix) srow[j] += f * acc[j];
+    }
+    if (blockIdx.y == 0) U_k[c * nl + l] += (double)accU;
 }
 
 // ---------------------------------------------------------------------------
@@ -1785,9 +1869,12 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     const int32_t cap = std::max(64, (int)d->nside_max);
     const int64_t ndir = 4 * (4 * (int64_t)cap * cap - 1);   // all levels 1 .. cap
     // direction-binned work array: all 768 Nside-8 directions when they fit
-    // in 8 GiB, else as many as fit
+    // in half the free device memory (at most 128 GiB), else as many as fit
     const size_t per_dir = (size_t)nl * (size_t)n;
-    size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, ((size_t)8 << 30) / (4 * per_dir)));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) free_b = (size_t)16 << 30;
+    const size_t bin_budget = std::min<size_t>(free_b / 2, (size_t)128 << 30);
+    size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, bin_budget / (4 * per_dir)));
     int rcs[] = {
         dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
         dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n),
@@ -1915,6 +2002,28 @@ int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes)
 {
     if (!grid || !bytes) return fail(DARTRAY_E_INVALID, "null argument");
     *bytes = grid->g.bytes;
+    return DARTRAY_OK;
+}
+
+int dartray_set_tuning(dartray_grid *grid, const dartray_tuning *t)
+{
+    if (!grid || !t) return fail(DARTRAY_E_INVALID, "null argument");
+    const int lt = t->lambda_tile;
+    if (!(lt == 0 || lt == 1 || lt == 4 || lt == 8 || lt == 16 || lt == 32 || lt == 64))
+        return fail(DARTRAY_E_INVALID, "lambda_tile must be 0, 1, 4, 8, 16, 32 or 64");
+    if (!(t->block_waves == 0 || t->block_waves == 1 || t->block_waves == 2 || t->block_waves == 4))
+        return fail(DARTRAY_E_INVALID, "block_waves must be 0, 1, 2 or 4");
+    if (t->grid_blocks < 0 || t->grid_blocks > 65536) return fail(DARTRAY_E_INVALID, "grid_blocks out of range");
+    if (t->dir_batch < 0) return fail(DARTRAY_E_INVALID, "dir_batch must be >= 0");
+    if (t->item_order != 0 && t->item_order != 1) return fail(DARTRAY_E_INVALID, "item_order must be 0 or 1");
+    grid->g.tune = *t;
+    return DARTRAY_OK;
+}
+
+int dartray_get_tuning(const dartray_grid *grid, dartray_tuning *t)
+{
+    if (!grid || !t) return fail(DARTRAY_E_INVALID, "null argument");
+    *t = grid->g.tune;
     return DARTRAY_OK;
 }
 
@@ -2100,35 +2209,41 @@ static int prof_mark(Grid &g)
     return DARTRAY_OK;
 }
 
-template <int NL>
-static void launch_fixed(const FixedArgs &A, bool uniform, hipStream_t s, unsigned blocks)
+static int nl_template(int k) { return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+static void launch_fixed(const FixedArgs &A, int nlt, hipStream_t s, unsigned blocks, unsigned threads)
 {
-    if (uniform) hipLaunchKernelGGL((k_march_fixed<NL, true>), dim3(blocks), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_march_fixed<NL, false>), dim3(blocks), dim3(256), 0, s, A);
+    switch (nlt) {
+    case 1: hipLaunchKernelGGL((k_march_fixed<1>), dim3(blocks), dim3(threads), 0, s, A); break;
+    case 4: hipLaunchKernelGGL((k_march_fixed<4>), dim3(blocks), dim3(threads), 0, s, A); break;
+    case 8: hipLaunchKernelGGL((k_march_fixed<8>), dim3(blocks), dim3(threads), 0, s, A); break;
+    case 16: hipLaunchKernelGGL((k_march_fixed<16>), dim3(blocks), dim3(threads), 0, s, A); break;
+    case 32: hipLaunchKernelGGL((k_march_fixed<32>), dim3(blocks), dim3(threads), 0, s, A); break;
+    default: hipLaunchKernelGGL((k_march_fixed<64>), dim3(blocks), dim3(threads), 0, s, A); break;
+    }
 }
 
-static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+// wavelengths per march launch under the grid's tuning
+static int lambda_chunk(const Grid &g)
 {
-    const int nl = g.n_lambda;
-    const int64_t n = g.n;
-    Frame fr;
-    frame_of(o, fr);
-    int rc = ensure_dirs(g, fr);
-    if (rc) return rc;
-    if ((rc = ensure_wtab(g, o->nside, fr))) return rc;
+    const int t = g.tune.lambda_tile > 0 ? g.tune.lambda_tile : g.n_lambda;
+    return std::min(t, g.n_lambda);
+}
+
+// directions binned between two flushes
+static int dir_batch(const Grid &g, int64_t nray)
+{
+    const size_t per_dir = (size_t)g.n_lambda * (size_t)g.n;
+    int64_t nb = std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
+    if (g.tune.dir_batch > 0) nb = std::min<int64_t>(nb, g.tune.dir_batch);
+    return (int)std::max<int64_t>(nb, 1);
+}
+
+static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+{
     const int64_t nray = 12 * (int64_t)o->nside * o->nside;
     int log2n = 0;
     while ((1 << log2n) < o->nside) ++log2n;
-
-    if ((rc = fill<double>(g, g.U_k, (size_t)nl * n, 0.0))) return rc;
-    if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
-    if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
-    if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
-    if ((rc = select_sources(g, o, f, scatter))) return rc;
-
-    const size_t per_dir = (size_t)nl * n;
-    const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
-    g.prof_kind = DARTRAY_PROF_FIXED;
     FixedArgs A{};
     A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
@@ -2141,43 +2256,93 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     A.ubar = g.ubar;
     A.tally = f->tally;
     A.counters = (o->flags & DARTRAY_FLAG_COUNTERS) ? f->counters : nullptr;
-    A.n = n;
+    A.n = g.n;
     A.scatter = scatter ? 1 : 0;
+    A.order = g.tune.item_order;
     A.nside_ray = o->nside;
     A.log2_nside_ray = log2n;
     A.inv_nray = (float)(1.0 / (double)nray);
     A.h_fine = (float)g.h_fine;
     A.max_steps = o->max_steps;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
-    const unsigned march_blocks = 2048;
-    for (int64_t r0 = 0; r0 < nray; r0 += nb_max) {
-        const int nb = (int)std::min<int64_t>(nb_max, nray - r0);
-        A.r0 = (int)r0;
-        A.nb = nb;
-        if ((rc = fill<float>(g, g.ubar, (size_t)nb * per_dir, 0.f))) return rc;
+    return A;
+}
+
+// one march launch per wavelength chunk over directions r0 .. r0 + nb - 1
+static int march_fixed_batch(Grid &g, FixedArgs A, int r0, int nb)
+{
+    const int chunk = lambda_chunk(g);
+    const unsigned threads = 64u * (unsigned)(g.tune.block_waves > 0 ? g.tune.block_waves : 4);
+    const unsigned blocks = (unsigned)(g.tune.grid_blocks > 0 ? g.tune.grid_blocks : 2048);
+    uint64_t *counters = A.counters;
+    A.r0 = r0;
+    A.nb = nb;
+    int rc;
+    for (int l0 = 0; l0 < g.n_lambda; l0 += chunk) {
+        A.l0 = l0;
+        A.nlc = std::min(chunk, g.n_lambda - l0);
+        A.counters = l0 == 0 ? counters : nullptr;
         if ((rc = prof_mark(g))) return rc;
-        if (nl <= 1) launch_fixed<1>(A, g.uniform, g.stream, march_blocks);
-        else if (nl <= 4) launch_fixed<4>(A, g.uniform, g.stream, march_blocks);
-        else if (nl <= 8) launch_fixed<8>(A, g.uniform, g.stream, march_blocks);
-        else if (nl <= 16) launch_fixed<16>(A, g.uniform, g.stream, march_blocks);
-        else if (nl <= 32) launch_fixed<32>(A, g.uniform, g.stream, march_blocks);
-        else launch_fixed<64>(A, g.uniform, g.stream, march_blocks);
+        launch_fixed(A, nl_template(A.nlc), g.stream, blocks, threads);
         DR_LAUNCH_CHECK("k_march_fixed");
         if ((rc = prof_mark(g))) return rc;
-        // flush: pixel chunks of 12 or 48
-        int min_npix = 1 << 30;
-        for (int l = 0; l < nl; ++l) min_npix = std::min(min_npix, g.lt.npix[l]);
-        int max_npix = 0;
-        for (int l = 0; l < nl; ++l) max_npix = std::max(max_npix, g.lt.npix[l]);
-        const unsigned cx = (unsigned)((n + 255) / 256);
-        if (min_npix % 48 == 0) {
-            hipLaunchKernelGGL(k_flush_fixed<48>, dim3(cx, max_npix / 48, nl), dim3(256), 0, g.stream, g.ubar, g.wtab,
-                               g.d_lt, g.rho, g.inv_vc, n, (int)r0, nb, g.w_row, g.U_k, f->S_next);
-        } else {
-            hipLaunchKernelGGL(k_flush_fixed<12>, dim3(cx, max_npix / 12, nl), dim3(256), 0, g.stream, g.ubar, g.wtab,
-                               g.d_lt, g.rho, g.inv_vc, n, (int)r0, nb, g.w_row, g.U_k, f->S_next);
-        }
-        DR_LAUNCH_CHECK("k_flush_fixed");
+    }
+    return DARTRAY_OK;
+}
+
+static int flush_fixed_batch(Grid &g, float *S_next, int r0, int nb)
+{
+    const int nl = g.n_lambda;
+    const int64_t n = g.n;
+    int log2_nlp = 0;
+    while ((1 << log2_nlp) < nl) ++log2_nlp;
+    int min_npix = 1 << 30, max_npix = 0;
+    for (int l = 0; l < nl; ++l) {
+        min_npix = std::min(min_npix, g.lt.npix[l]);
+        max_npix = std::max(max_npix, g.lt.npix[l]);
+    }
+    const int pch = (min_npix % 48 == 0) ? 48 : 12;
+    int rb_stage = 16;
+    while (rb_stage > 1 && (size_t)rb_stage * nl * (pch + 1) * sizeof(float) > (size_t)48 * 1024) rb_stage >>= 1;
+    const size_t lds = (size_t)rb_stage * nl * (pch + 1) * sizeof(float);
+    const int64_t per_block = 256 >> log2_nlp;
+    const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)(max_npix / pch));
+    if (pch == 48)
+        hipLaunchKernelGGL(k_flush_fixed<48>, grid, dim3(256), lds, g.stream, g.ubar, g.wtab, g.d_lt, g.rho, g.inv_vc,
+                           n, r0, nb, g.w_row, log2_nlp, rb_stage, g.U_k, S_next);
+    else
+        hipLaunchKernelGGL(k_flush_fixed<12>, grid, dim3(256), lds, g.stream, g.ubar, g.wtab, g.d_lt, g.rho, g.inv_vc,
+                           n, r0, nb, g.w_row, log2_nlp, rb_stage, g.U_k, S_next);
+    DR_LAUNCH_CHECK("k_flush_fixed");
+    return DARTRAY_OK;
+}
+
+static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+{
+    const int nl = g.n_lambda;
+    const int64_t n = g.n;
+    Frame fr;
+    frame_of(o, fr);
+    int rc = ensure_dirs(g, fr);
+    if (rc) return rc;
+    if ((rc = ensure_wtab(g, o->nside, fr))) return rc;
+    const int64_t nray = 12 * (int64_t)o->nside * o->nside;
+
+    if ((rc = fill<double>(g, g.U_k, (size_t)nl * n, 0.0))) return rc;
+    if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
+    if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
+    if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
+    if ((rc = select_sources(g, o, f, scatter))) return rc;
+
+    const size_t per_dir = (size_t)nl * n;
+    const int nb_max = dir_batch(g, nray);
+    g.prof_kind = DARTRAY_PROF_FIXED;
+    const FixedArgs A = fixed_args(g, o, f, scatter);
+    for (int64_t r0 = 0; r0 < nray; r0 += nb_max) {
+        const int nb = (int)std::min<int64_t>(nb_max, nray - r0);
+        if ((rc = fill<float>(g, g.ubar, (size_t)nb * per_dir, 0.f))) return rc;
+        if ((rc = march_fixed_batch(g, A, (int)r0, nb))) return rc;
+        if ((rc = flush_fixed_batch(g, f->S_next, (int)r0, nb))) return rc;
     }
     return DARTRAY_OK;
 }

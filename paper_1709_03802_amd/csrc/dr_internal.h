@@ -125,6 +125,7 @@ struct Grid {
     float *sbar[2] = {nullptr, nullptr};  // [s_size] dJ/dS of consecutive orders
 
     size_t bytes = 0;
+    dartray_tuning tune{};                // fixed-ray launch parameters (zero = default)
 
     // march-kernel timing
     int32_t prof = 0;                     // DARTRAY_PROF_* mask

@@ -38,6 +38,7 @@ EXPORTS = [
     "dartray_s_offset", "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter",
     "dartray_trace_adjoint", "dartray_debug_ray_cells", "dartray_workspace_bytes",
     "dartray_last_error", "dartray_version", "dartray_profile_enable", "dartray_profile_read",
+    "dartray_set_tuning", "dartray_get_tuning",
 ]
 
 
@@ -99,6 +100,20 @@ class FieldsC(C.Structure):
     ]
 
 
+class Tuning(C.Structure):
+    """dartray_tuning: launch parameters of the fixed-ray passes (0 = default)."""
+    _fields_ = [
+        ("lambda_tile", C.c_int32),
+        ("block_waves", C.c_int32),
+        ("grid_blocks", C.c_int32),
+        ("dir_batch", C.c_int32),
+        ("item_order", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -128,12 +143,14 @@ def load_library():
     L.dartray_workspace_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
     L.dartray_profile_enable.argtypes = [C.c_void_p, C.c_int32]
     L.dartray_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.dartray_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.dartray_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.dartray_last_error.restype = C.c_char_p
     L.dartray_version.restype = C.c_char_p
     for name in ("dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
                  "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter", "dartray_trace_adjoint",
                  "dartray_debug_ray_cells", "dartray_workspace_bytes", "dartray_profile_enable",
-                 "dartray_profile_read"):
+                 "dartray_profile_read", "dartray_set_tuning", "dartray_get_tuning"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -234,6 +251,20 @@ class Grid:
         n = C.c_int64()
         _check(load_library().dartray_profile_read(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_tuning(self, **kw):
+        """Set fixed-ray launch parameters (fields of ``Tuning``; others keep their value)."""
+        t = self.tuning()
+        for k, v in kw.items():
+            if k not in dict(Tuning._fields_):
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _check(load_library().dartray_set_tuning(self.h, C.byref(t)))
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(load_library().dartray_get_tuning(self.h, C.byref(t)))
+        return t
 
     def set_rho(self, rho_dev):
         _check(load_library().dartray_grid_set_rho(self.h, C.c_void_p(rho_dev.data_ptr())))

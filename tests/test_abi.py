@@ -50,9 +50,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "dartray.h"
 int main(void) {
-  printf("%zu %zu %zu\\n", sizeof(dartray_grid_desc), sizeof(dartray_trace_opts), sizeof(dartray_fields));
+  printf("%zu %zu %zu %zu\\n", sizeof(dartray_grid_desc), sizeof(dartray_trace_opts), sizeof(dartray_fields), sizeof(dartray_tuning));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(dartray_grid_desc, c_light), offsetof(dartray_grid_desc, nside_max), offsetof(dartray_trace_opts, frame),
          offsetof(dartray_trace_opts, max_steps), offsetof(dartray_fields, counters));
+  printf("%zu\\n", offsetof(dartray_tuning, item_order));
   return 0;
 }
 """)
@@ -60,9 +61,9 @@ int main(void) {
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)])
     out = subprocess.check_output([str(exe)]).decode().split()
     got = [int(x) for x in out]
-    want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC),
+    want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC), C.sizeof(dartray.Tuning),
             dartray.GridDesc.c_light.offset, dartray.GridDesc.nside_max.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
-            dartray.FieldsC.counters.offset]
+            dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset]
     assert got == want
 
 
@@ -145,3 +146,5 @@ def test_null_arguments(lib):
     assert lib.dartray_trace_direct(None, None, None) == dartray.E_INVALID
     assert lib.dartray_scatter_iter(None, None, None, None) == dartray.E_INVALID
     assert lib.dartray_grid_destroy(None) == dartray.OK
+    assert lib.dartray_set_tuning(None, None) == dartray.E_INVALID
+    assert lib.dartray_get_tuning(None, None) == dartray.E_INVALID

@@ -42,12 +42,16 @@ def rel_err(x, ref):
     return np.abs(x - ref) / np.maximum(np.abs(ref), 1e-30)
 
 
-def compare_run(dr, orc, grid, policy, frame=None, source_mask=None, passes=None, tol=TOL, label=""):
+def compare_run(dr, orc, grid, policy, frame=None, source_mask=None, passes=None, tol=TOL, label="", tuning=None,
+                ref=None):
     import torch
     g32 = as_f32(grid)
     m = orc.Model(g32)
-    ref = orc.run(m, policy, frame=frame, source_mask=source_mask, passes=passes)
+    if ref is None:
+        ref = orc.run(m, policy, frame=frame, source_mask=source_mask, passes=passes)
     G = dr.Grid(g32)
+    if tuning:
+        G.set_tuning(**tuning)
     mask_t = None if source_mask is None else torch.as_tensor(source_mask.astype(np.uint8)).cuda()
     out = dr.run(G, policy, frame=frame, source_mask=mask_t, passes=passes)
     torch.cuda.synchronize()
@@ -187,3 +191,66 @@ def test_max_steps_guard(dr):
     c = f.counters.cpu().numpy()
     assert c[dr.C_MAXSTEP] > 0
     assert c[dr.C_MAXSTEP] + c[dr.C_ESCAPES] == c[dr.C_RAYS]
+
+
+TUNINGS = [
+    {},
+    {"lambda_tile": 1},
+    {"lambda_tile": 4, "block_waves": 1, "grid_blocks": 7},
+    {"lambda_tile": 4, "dir_batch": 100, "item_order": 1, "block_waves": 2},
+    {"lambda_tile": 8, "dir_batch": 1, "grid_blocks": 300},
+]
+
+
+def test_launch_parameters_do_not_change_results(dr, orc):
+    """Every tuning (wavelength tiles with a ragged last tile, workgroup
+    shapes, direction batches that do not divide the ray count, item order)
+    matches the oracle."""
+    wl = W.plain16(n=12, nside=4, lambdas=np.array([0.15, 0.3, 0.55, 1.2, 2.2]), n_scatter=2)
+    g32 = as_f32(wl.grid)
+    ref = orc.run(orc.Model(g32), wl.policy)
+    for t in TUNINGS:
+        compare_run(dr, orc, wl.grid, wl.policy, label=f"tuning {t}", tuning=t, ref=ref)
+
+
+def test_tuning_validation(dr):
+    G = dr.Grid(W.plain16(n=4, nside=2).grid)
+    for bad in ({"lambda_tile": 3}, {"block_waves": 3}, {"grid_blocks": -1}, {"grid_blocks": 70000},
+                {"dir_batch": -2}, {"item_order": 2}):
+        with pytest.raises(dr.DartRayError) as e:
+            G.set_tuning(**bad)
+        assert e.value.code == dr.E_INVALID
+    G.set_tuning(lambda_tile=4, dir_batch=10)
+    assert G.tuning().as_dict()["dir_batch"] == 10
+
+
+def test_32_wavelengths_one_march_equals_per_wavelength_marches(dr, orc):
+    """The batched form (one march carries all 32 wavelengths) and the plain
+    per-wavelength form (32 marches of one wavelength) give the same fields;
+    four of the wavelengths are checked against the oracle run at those
+    wavelengths alone (wavelengths do not couple)."""
+    import torch
+    wl = W.by_name("plain16_l32")
+    g32 = as_f32(wl.grid)
+    outs = []
+    for tile in (0, 1):
+        G = dr.Grid(g32)
+        G.set_tuning(lambda_tile=tile)
+        out = dr.run(G, wl.policy)
+        torch.cuda.synchronize()
+        outs.append((out.fields.U.cpu().numpy().astype(np.float64),
+                     out.fields.S_total.cpu().numpy()[:G.s_size].astype(np.float64), G.s_offset))
+        assert out.counters[0][dr.C_CROSSINGS] > 0
+    d_u = rel_err(outs[1][0], outs[0][0]).max()
+    d_s = rel_err(outs[1][1], outs[0][1]).max()
+    print(f"32 wavelengths: tile 32 vs tile 1: U {d_u:.3g}, S {d_s:.3g}", flush=True)
+    assert d_u <= 1e-5 and d_s <= 1e-5
+    pick = [0, 9, 20, 31]
+    sub = W.plain16(nside=wl.policy.nside, n_scatter=wl.policy.n_scatter, lambdas=np.asarray(wl.grid.lambdas_um)[pick])
+    ref = orc.run(orc.Model(as_f32(sub.grid)), sub.policy)
+    U, S, off = outs[0]
+    m = orc.Model(as_f32(sub.grid))
+    for k, l in enumerate(pick):
+        eu = rel_err(U[l], ref.U[k]).max()
+        es = rel_err(S[off[l]:off[l + 1]], ref.S_total[m.s_offset[k]:m.s_offset[k + 1]]).max()
+        assert eu <= TOL and es <= TOL, (l, eu, es)
