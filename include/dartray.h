@@ -293,6 +293,41 @@ typedef struct {
 int dartray_set_tuning(dartray_grid *grid, const dartray_tuning *tuning);
 int dartray_get_tuning(const dartray_grid *grid, dartray_tuning *tuning);
 
+/*
+ * Batches of models (fixed rays).  The sources of independent models are
+ * independent work (Sect. 3.4 parallelises over sources); a batch runs the
+ * passes of several grid handles together: per pass and direction batch one
+ * persistent march launch takes (model, 64-source tile, direction) items of
+ * every model, models in descending order of size, and one flush launch
+ * covers every model's cells.  The handles must share the stream and the
+ * number of wavelengths, stay owned by the caller and outlive the batch; the
+ * first handle's tuning applies to the whole batch.
+ */
+typedef struct dartray_batch dartray_batch;
+
+/* Group n_models distinct handles.  Allocates three small device arrays. */
+int dartray_batch_create(dartray_grid *const *grids, int32_t n_models, dartray_batch **out);
+
+/* Release a batch (not its grids).  Accepts NULL. */
+int dartray_batch_destroy(dartray_batch *batch);
+
+/* Direct pass then n_scatter scattering iterations of every model: fields[m]
+ * receives model m's results as dartray_trace_direct followed by
+ * dartray_scatter_iter would (opts: fixed rays, DARTRAY_MODE_DIRECT, no
+ * source mask).  Synchronises the stream once, before any pass, to upload
+ * the per-model launch arguments; the passes are queued asynchronously. */
+int dartray_batch_run(dartray_batch *batch, const dartray_trace_opts *opts, dartray_fields *const *fields,
+                      int32_t n_scatter);
+
+/* The same sequence recorded by stream capture into a HIP graph (the stream
+ * must not be the legacy NULL stream).  The field buffers named here are
+ * baked into the graph; every replay rewrites them. */
+int dartray_batch_capture(dartray_batch *batch, const dartray_trace_opts *opts, dartray_fields *const *fields,
+                          int32_t n_scatter);
+
+/* Launch the captured graph on the batch's stream (DARTRAY_E_STATE if none). */
+int dartray_batch_replay(dartray_batch *batch);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *dartray_last_error(void);
 

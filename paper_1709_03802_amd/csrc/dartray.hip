@@ -416,7 +416,7 @@ __global__ void k_debug_cells(Geo g, int nrays, const double *origin, const doub
 
 // ---------------------------------------------------------------------------
 // Fixed-Nside march: lanes are 64 Morton-consecutive sources, one direction
-// per wave.  Deposits go to ubar[l][r - r0][c].
+// per wave.  Deposits go to the direction bins ubar[r - r0][c][l].
 // ---------------------------------------------------------------------------
 
 struct FixedArgs {
@@ -462,169 +462,171 @@ __device__ inline float fixed_launch(const FixedArgs &A, const LambdaTable *lt, 
     return v;
 }
 
-// Fixed-Nside march.  A work item is (64 Morton-consecutive sources, one
-// direction); the wave's lanes walk their rays in lock step, one cell per
-// iteration, and the iteration's deposits go out wave-cooperatively: the NL
-// wavelength values of a crossing are one contiguous row of the bin array, and
-// one atomic instruction carries 64 / NL crossings.
+// per-wave accumulators of the tallies and counters
 template <int NL>
-__global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
+struct FixedAcc {
+    float esc[NL];
+    uint32_t ncross, nrays, nmax;
+    __device__ void clear()
+    {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) esc[l] = 0.f;
+        ncross = nrays = nmax = 0;
+    }
+};
+
+// LDS staging of one wave's deposits (256-thread workgroups at most)
+template <int NL>
+struct FixedStage {
+    float du[NL][256];
+    int32_t cell[256];
+    uint8_t list[256];
+};
+
+// One work item (64 sources of source tile `tile`, direction r0 + rl): the
+// wave's lanes walk their rays in lock step, one cell per iteration, and the
+// iteration's deposits go out wave-cooperatively: the wavelength values of a
+// crossing are one contiguous row of the bin array, and one atomic
+// instruction carries 64 / NL crossings.
+template <int NL>
+__device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, FixedStage<NL> &st, FixedAcc<NL> &acc)
 {
-    constexpr int kBlock = 256;
-    __shared__ float s_du[NL][kBlock];
-    __shared__ int32_t s_cell[kBlock];
-    __shared__ uint8_t s_list[kBlock];
     const LambdaTable *lt = A.lt;
     const int nl = lt->n_lambda;
     const int nlc = A.nlc, l0 = A.l0;
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
-    const int64_t wid = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int nsrc = *A.n_src;
-    const int64_t ntiles = (nsrc + 63) >> 6;
-    const int64_t nitems = ntiles * A.nb;
-
-    float esc[NL], kap[NL];
+    const int r = A.r0 + rl;
+    const int64_t si = tile * 64 + lane;
+    bool active = si < nsrc;
+    int32_t c = 0;
+    Ray R;
+    float L[NL], kap[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-        esc[l] = 0.f;
+        L[l] = 0.f;
         kap[l] = l < nlc ? lt->kappa[l0 + l] : 0.f;
     }
-    uint32_t ncross = 0, nrays = 0, nmax = 0;
-
-    for (int64_t it = wid; it < nitems; it += nw) {
-        int64_t tile;
-        int rl;
-        if (A.order == 0) {
-            tile = it / A.nb;
-            rl = (int)(it - tile * A.nb);
-        } else {
-            rl = (int)(it / ntiles);
-            tile = it - (int64_t)rl * ntiles;
-        }
-        const int r = A.r0 + rl;
-        const int64_t si = tile * 64 + lane;
-        bool active = si < nsrc;
-        int32_t c = 0;
-        Ray R;
-        float L[NL];
+    if (active) {
+        const int32_t s = A.src_list[si];
+        const float4 nd = A.dirs[r];
+        R.n[0] = nd.x;
+        R.n[1] = nd.y;
+        R.n[2] = nd.z;
+        const int4 b = A.geo.rec[s].box;
+        const float half = 0.5f * (float)b.w;
+        R.o[0] = (float)b.x + half;
+        R.o[1] = (float)b.y + half;
+        R.o[2] = (float)b.z + half;
 #pragma unroll
-        for (int l = 0; l < NL; ++l) L[l] = 0.f;
-        if (active) {
-            const int32_t s = A.src_list[si];
-            const float4 nd = A.dirs[r];
-            R.n[0] = nd.x;
-            R.n[1] = nd.y;
-            R.n[2] = nd.z;
-            const int4 b = A.geo.rec[s].box;
-            const float half = 0.5f * (float)b.w;
-            R.o[0] = (float)b.x + half;
-            R.o[1] = (float)b.y + half;
-            R.o[2] = (float)b.z + half;
+        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
+        float lsum = 0.f;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
-            float lsum = 0.f;
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                if (l < nlc) {
-                    L[l] = fixed_launch(A, lt, l0 + l, s, r);
-                    lsum += L[l];
-                }
+        for (int l = 0; l < NL; ++l) {
+            if (l < nlc) {
+                L[l] = fixed_launch(A, lt, l0 + l, s, r);
+                lsum += L[l];
             }
-            // the counting launch traces a ray when any wavelength carries light
-            if (!(lsum > 0.f) && A.counters)
-                for (int l = 0; l < nl; ++l)
-                    if (l < l0 || l >= l0 + nlc) lsum += fixed_launch(A, lt, l, s, r);
-            active = lsum > 0.f;
-            c = s;
-            if (active) ++nrays;
         }
-        float t = 0.f;
-        int64_t steps = 0;
-        float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
-        while (__ballot(active)) {
-            bool dep = false;
-            if (active) {
-                const LeafRec &rc = A.geo.rec[c];
-                const int4 b = rc.box;
-                const float rho = rc.rho;
-                const float ivc = rc.ivc;
-                int32_t nbc[6];
+        // the counting launch traces a ray when any wavelength carries light
+        if (!(lsum > 0.f) && A.counters)
+            for (int l = 0; l < nl; ++l)
+                if (l < l0 || l >= l0 + nlc) lsum += fixed_launch(A, lt, l, s, r);
+        active = lsum > 0.f;
+        c = s;
+        if (active) ++acc.nrays;
+    }
+    float t = 0.f;
+    int64_t steps = 0;
+    float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
+    while (__ballot(active)) {
+        bool dep = false;
+        if (active) {
+            const LeafRec &rc = A.geo.rec[c];
+            const int4 b = rc.box;
+            const float rho = rc.rho;
+            const float ivc = rc.ivc;
+            int32_t nbc[6];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
-                int axis;
-                const float te = exit_t(R, b, axis);
-                const float len = te - t;
-                if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
-                    const float lp = len * A.h_fine;
+            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+            int axis;
+            const float te = exit_t(R, b, axis);
+            const float len = te - t;
+            if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
+                const float lp = len * A.h_fine;
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        if (l < nlc) {
-                            const float alpha = kap[l] * rho;
-                            const float tau = alpha * lp;
-                            const float em1 = expm1f(-tau);          // exp(-tau) - 1
-                            const float ext = -L[l] * em1;
-                            s_du[l][threadIdx.x] = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
-                            L[l] = fmaf(L[l], em1, L[l]);
-                        }
+                for (int l = 0; l < NL; ++l) {
+                    if (l < nlc) {
+                        const float alpha = kap[l] * rho;
+                        const float tau = alpha * lp;
+                        const float em1 = expm1f(-tau);          // exp(-tau) - 1
+                        const float ext = -L[l] * em1;
+                        st.du[l][threadIdx.x] = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
+                        L[l] = fmaf(L[l], em1, L[l]);
                     }
-                    s_cell[threadIdx.x] = c;
-                    dep = true;
-                    ++ncross;
-                    t = te;
                 }
-                const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
-                if (nx < 0) {
+                st.cell[threadIdx.x] = c;
+                dep = true;
+                ++acc.ncross;
+                t = te;
+            }
+            const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
+            if (nx < 0) {
+                active = false;
+            } else {
+                ++steps;
+                if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
+                    ++acc.nmax;
                     active = false;
                 } else {
-                    ++steps;
-                    if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
-                        ++nmax;
-                        active = false;
-                    } else {
-                        c = nx;
-                    }
-                }
-                if (!active) {
-#pragma unroll
-                    for (int l = 0; l < NL; ++l) esc[l] += L[l];
+                    c = nx;
                 }
             }
-            // lanes q of an instruction add value q % NL of the (q / NL)-th
-            // depositing lane
-            const uint64_t dm = __ballot(dep);
-            if (dm) {
-                if (dep) s_list[wbase + __popcll(dm & ((1ull << lane) - 1ull))] = (uint8_t)lane;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int cnt = __popcll(dm);
-                constexpr int PER = 64 / NL;
-                for (int k0 = 0; k0 < cnt; k0 += PER) {
-                    const int q = k0 + lane / NL;
-                    const int l = lane % NL;
-                    if (q < cnt && l < nlc) {
-                        const int j = s_list[wbase + q];
-                        atomic_add_f32(ubase + (size_t)s_cell[wbase + j] * nl + l, s_du[l][wbase + j]);
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (!active) {
+#pragma unroll
+                for (int l = 0; l < NL; ++l) acc.esc[l] += L[l];
             }
         }
+        // lanes q of an instruction add value q % NL of the (q / NL)-th
+        // depositing lane
+        const uint64_t dm = __ballot(dep);
+        if (dm) {
+            if (dep) st.list[wbase + __popcll(dm & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int cnt = __popcll(dm);
+            constexpr int PER = 64 / NL;
+            for (int k0 = 0; k0 < cnt; k0 += PER) {
+                const int q = k0 + lane / NL;
+                const int l = lane % NL;
+                if (q < cnt && l < nlc) {
+                    const int j = st.list[wbase + q];
+                    atomic_add_f32(ubase + (size_t)st.cell[wbase + j] * nl + l, st.du[l][wbase + j]);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
-    // wave-level FP64 reductions of the tallies
+}
+
+// wave-level FP64 reduction of the accumulators into A's tallies and counters
+template <int NL>
+__device__ void fixed_commit(const FixedArgs &A, FixedAcc<NL> &acc)
+{
+    const int lane = threadIdx.x & 63;
+    const int nl = A.lt->n_lambda;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-        if (l < nlc) {
-            const double v = wave_sum((double)esc[l]);
-            if (lane == 0 && v != 0.0) atomic_add_f64(&A.tally[(l0 + l) * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
+        if (l < A.nlc) {
+            const double v = wave_sum((double)acc.esc[l]);
+            if (lane == 0 && v != 0.0) atomic_add_f64(&A.tally[(A.l0 + l) * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
         }
     }
     if (A.counters) {
-        const uint64_t wc = wave_sum_u64(ncross), wr = wave_sum_u64(nrays), wm = wave_sum_u64(nmax);
+        const uint64_t wc = wave_sum_u64(acc.ncross), wr = wave_sum_u64(acc.nrays), wm = wave_sum_u64(acc.nmax);
         if (lane == 0) {
             if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_CROSSINGS], (unsigned long long)wc);
             if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_RAYS], (unsigned long long)wr);
@@ -634,6 +636,99 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
             if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_DEPOSITS], (unsigned long long)(wc * nl));
         }
     }
+    acc.clear();
+}
+
+__device__ inline void fixed_item_index(const FixedArgs &A, int64_t it, int64_t ntiles, int64_t &tile, int &rl)
+{
+    if (A.order == 0) {
+        tile = it / A.nb;
+        rl = (int)(it - tile * A.nb);
+    } else {
+        rl = (int)(it / ntiles);
+        tile = it - (int64_t)rl * ntiles;
+    }
+}
+
+template <int NL>
+__global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
+{
+    __shared__ FixedStage<NL> st;
+    const int64_t wid = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int nsrc = *A.n_src;
+    const int64_t ntiles = (nsrc + 63) >> 6;
+    const int64_t nitems = ntiles * A.nb;
+    FixedAcc<NL> acc;
+    acc.clear();
+    for (int64_t it = wid; it < nitems; it += nw) {
+        int64_t tile;
+        int rl;
+        fixed_item_index(A, it, ntiles, tile, rl);
+        fixed_item<NL>(A, tile, rl, nsrc, st, acc);
+    }
+    fixed_commit<NL>(A, acc);
+}
+
+// Several models in one persistent launch.  The work items of model m are
+// item_off[m] .. item_off[m + 1] - 1 (models in descending order of expected
+// work); a wave strides over all of them and commits its tallies whenever it
+// moves on to another model.
+struct BatchMarch {
+    const FixedArgs *models;     // [n_models], r0 / nb / l0 / nlc taken from here
+    const int64_t *item_off;     // [n_models + 1]
+    int32_t n_models;
+    int32_t r0, nb, l0, nlc;
+    int32_t count;               // 0: no counters in this launch
+};
+
+template <int NL>
+__global__ __launch_bounds__(256) void k_march_fixed_multi(const BatchMarch B)
+{
+    __shared__ FixedStage<NL> st;
+    const int64_t wid = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t nitems = B.item_off[B.n_models];
+    FixedAcc<NL> acc;
+    acc.clear();
+    int mcur = -1;
+    FixedArgs A{};
+    int nsrc = 0;
+    int64_t ntiles = 0;
+    for (int64_t it = wid; it < nitems; it += nw) {
+        int m = mcur < 0 ? 0 : mcur;
+        while (it >= B.item_off[m + 1]) ++m;
+        m = __builtin_amdgcn_readfirstlane(m);
+        if (m != mcur) {
+            if (mcur >= 0) fixed_commit<NL>(A, acc);
+            A = B.models[m];
+            A.r0 = B.r0;
+            A.nb = B.nb;
+            A.l0 = B.l0;
+            A.nlc = B.nlc;
+            if (!B.count) A.counters = nullptr;
+            nsrc = *A.n_src;
+            ntiles = (nsrc + 63) >> 6;
+            mcur = m;
+        }
+        int64_t tile;
+        int rl;
+        fixed_item_index(A, it - B.item_off[m], ntiles, tile, rl);
+        fixed_item<NL>(A, tile, rl, nsrc, st, acc);
+    }
+    if (mcur >= 0) fixed_commit<NL>(A, acc);
+}
+
+// item_off[m + 1] = item_off[m] + ceil(n_src(model order[m]) / 64) nb
+__global__ void k_batch_items(const FixedArgs *models, int n_models, int nb, int64_t *item_off)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t acc = 0;
+    item_off[0] = 0;
+    for (int m = 0; m < n_models; ++m) {
+        acc += (int64_t)((*models[m].n_src + 63) >> 6) * nb;
+        item_off[m + 1] = acc;
+    }
 }
 
 // Flush of one direction batch:
@@ -641,21 +736,35 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
 //   S[l][c][p] += albedo kappa rho V c sum_r ubar[r][c][l] w_l(p|r)
 // A block holds 256 / NLP cells x NLP wavelength slots (NLP = n_lambda rounded
 // up to a power of two), so its bin reads are one contiguous range per
-// direction; blockIdx.y picks a chunk of PCH pixels.  The phase weights of RB
-// directions are staged in LDS as [direction][wavelength][PCH + 1] (the odd row
-// stride spreads the wavelengths over the banks).
+// direction; the block's pixel chunk is PCH pixels from by * PCH.  The phase
+// weights of rb_stage directions are staged in LDS as
+// [direction][wavelength][PCH + 1] (the odd row stride spreads the
+// wavelengths over the banks).
+struct FlushArgs {
+    const float *ubar;
+    const float *wtab;
+    const LambdaTable *lt;
+    const float *rho;
+    const float *inv_vc;
+    double *U_k;
+    float *S_next;
+    int64_t n;
+    int32_t w_row;
+    int32_t bx;                  // blocks along the cells (multi-model launch)
+    int64_t block0;              // first block of this model (multi-model launch)
+};
+
 template <int PCH>
-__global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const float *wtab, const LambdaTable *lt,
-                                                      const float *rho, const float *inv_vc, int64_t n, int r0,
-                                                      int nb, int w_row, int log2_nlp, int rb_stage, double *U_k,
-                                                      float *S_next)
+__device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, int r0, int nb, int log2_nlp,
+                            int rb_stage)
 {
-    extern __shared__ float ws[];
     constexpr int PS = PCH + 1;
+    const LambdaTable *lt = F.lt;
     const int nl = lt->n_lambda;
+    const int64_t n = F.n;
     const int l = threadIdx.x & ((1 << log2_nlp) - 1);
-    const int64_t c = blockIdx.x * (int64_t)(256 >> log2_nlp) + (threadIdx.x >> log2_nlp);
-    const int p0 = blockIdx.y * PCH;
+    const int64_t c = bx * (int64_t)(256 >> log2_nlp) + (threadIdx.x >> log2_nlp);
+    const int p0 = by * PCH;
     const bool ok = c < n && l < nl;
     const int npix = ok ? lt->npix[l] : 0;
     const bool pix = ok && p0 < npix;
@@ -663,7 +772,7 @@ __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const fl
 #pragma unroll
     for (int j = 0; j < PCH; ++j) acc[j] = 0.f;
     float accU = 0.f;
-    const float *ub = ubar + (ok ? (size_t)c * nl + l : 0);
+    const float *ub = F.ubar + (ok ? (size_t)c * nl + l : 0);
     const size_t rstride = (size_t)n * nl;
     const float *wsl = ws + (size_t)(ok ? l : 0) * PS;
     for (int rb = 0; rb < nb; rb += rb_stage) {
@@ -675,7 +784,7 @@ __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const fl
             const int ll = rem / PCH, j = rem - (rem / PCH) * PCH;
             const int p = p0 + j;
             ws[(i * nl + ll) * PS + j] =
-                p < lt->npix[ll] ? wtab[(int64_t)(r0 + rb + i) * w_row + lt->w_off[ll] + p] : 0.f;
+                p < lt->npix[ll] ? F.wtab[(int64_t)(r0 + rb + i) * F.w_row + lt->w_off[ll] + p] : 0.f;
         }
         __syncthreads();
         if (ok) {
@@ -692,13 +801,36 @@ __global__ __launch_bounds__(256) void k_flush_fixed(const float *ubar, const fl
     }
     if (!ok) return;
     if (pix) {
-        const float f = lt->albedo[l] * lt->kappa[l] * rho[c] / inv_vc[c];
-        float *srow = S_next + lt->s_off[l] + c * (int64_t)npix + p0;
+        const float f = lt->albedo[l] * lt->kappa[l] * F.rho[c] / F.inv_vc[c];
+        float *srow = F.S_next + lt->s_off[l] + c * (int64_t)npix + p0;
 #pragma unroll
         for (int j = 0; j < PCH; ++j)
             if (p0 + j < npix) srow[j] += f * acc[j];
     }
-    if (blockIdx.y == 0) U_k[c * nl + l] += (double)accU;
+    if (by == 0) F.U_k[c * nl + l] += (double)accU;
+}
+
+template <int PCH>
+__global__ __launch_bounds__(256) void k_flush_fixed(const FlushArgs F, int r0, int nb, int log2_nlp, int rb_stage)
+{
+    extern __shared__ float ws[];
+    flush_block<PCH>(F, ws, blockIdx.x, blockIdx.y, r0, nb, log2_nlp, rb_stage);
+}
+
+// all models of a batch: a flat grid, model m owning blocks block0 .. (its
+// cell blocks x pixel chunks)
+template <int PCH>
+__global__ __launch_bounds__(256) void k_flush_fixed_multi(const FlushArgs *models, int n_models, int r0, int nb,
+                                                            int log2_nlp, int rb_stage)
+{
+    extern __shared__ float ws[];
+    int m = 0;
+    while (m + 1 < n_models && (int64_t)blockIdx.x >= models[m + 1].block0) ++m;
+    m = __builtin_amdgcn_readfirstlane(m);
+    const FlushArgs F = models[m];
+    const int64_t b = (int64_t)blockIdx.x - F.block0;
+    const int64_t by = b / F.bx;
+    flush_block<PCH>(F, ws, b - by * F.bx, (int)by, r0, nb, log2_nlp, rb_stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -2290,29 +2422,55 @@ static int march_fixed_batch(Grid &g, FixedArgs A, int r0, int nb)
     return DARTRAY_OK;
 }
 
-static int flush_fixed_batch(Grid &g, float *S_next, int r0, int nb)
+// flush launch shape shared by single- and multi-model passes
+struct FlushShape {
+    int log2_nlp, pch, rb_stage, max_npix;
+    int64_t per_block;
+    size_t lds;
+};
+
+static FlushShape flush_shape(const Grid &g)
 {
+    FlushShape f{};
     const int nl = g.n_lambda;
-    const int64_t n = g.n;
-    int log2_nlp = 0;
-    while ((1 << log2_nlp) < nl) ++log2_nlp;
-    int min_npix = 1 << 30, max_npix = 0;
+    while ((1 << f.log2_nlp) < nl) ++f.log2_nlp;
+    int min_npix = 1 << 30;
     for (int l = 0; l < nl; ++l) {
         min_npix = std::min(min_npix, g.lt.npix[l]);
-        max_npix = std::max(max_npix, g.lt.npix[l]);
+        f.max_npix = std::max(f.max_npix, g.lt.npix[l]);
     }
-    const int pch = (min_npix % 48 == 0) ? 48 : 12;
-    int rb_stage = 16;
-    while (rb_stage > 1 && (size_t)rb_stage * nl * (pch + 1) * sizeof(float) > (size_t)48 * 1024) rb_stage >>= 1;
-    const size_t lds = (size_t)rb_stage * nl * (pch + 1) * sizeof(float);
-    const int64_t per_block = 256 >> log2_nlp;
-    const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)(max_npix / pch));
-    if (pch == 48)
-        hipLaunchKernelGGL(k_flush_fixed<48>, grid, dim3(256), lds, g.stream, g.ubar, g.wtab, g.d_lt, g.rho, g.inv_vc,
-                           n, r0, nb, g.w_row, log2_nlp, rb_stage, g.U_k, S_next);
+    f.pch = (min_npix % 48 == 0) ? 48 : 12;
+    f.rb_stage = 16;
+    while (f.rb_stage > 1 && (size_t)f.rb_stage * nl * (f.pch + 1) * sizeof(float) > (size_t)48 * 1024) f.rb_stage >>= 1;
+    f.lds = (size_t)f.rb_stage * nl * (f.pch + 1) * sizeof(float);
+    f.per_block = 256 >> f.log2_nlp;
+    return f;
+}
+
+static FlushArgs flush_args(Grid &g, float *S_next)
+{
+    FlushArgs F{};
+    F.ubar = g.ubar;
+    F.wtab = g.wtab;
+    F.lt = g.d_lt;
+    F.rho = g.rho;
+    F.inv_vc = g.inv_vc;
+    F.U_k = g.U_k;
+    F.S_next = S_next;
+    F.n = g.n;
+    F.w_row = g.w_row;
+    return F;
+}
+
+static int flush_fixed_batch(Grid &g, float *S_next, int r0, int nb)
+{
+    const FlushShape fs = flush_shape(g);
+    const FlushArgs F = flush_args(g, S_next);
+    const dim3 grid((unsigned)((g.n + fs.per_block - 1) / fs.per_block), (unsigned)(fs.max_npix / fs.pch));
+    if (fs.pch == 48)
+        hipLaunchKernelGGL(k_flush_fixed<48>, grid, dim3(256), fs.lds, g.stream, F, r0, nb, fs.log2_nlp, fs.rb_stage);
     else
-        hipLaunchKernelGGL(k_flush_fixed<12>, grid, dim3(256), lds, g.stream, g.ubar, g.wtab, g.d_lt, g.rho, g.inv_vc,
-                           n, r0, nb, g.w_row, log2_nlp, rb_stage, g.U_k, S_next);
+        hipLaunchKernelGGL(k_flush_fixed<12>, grid, dim3(256), fs.lds, g.stream, F, r0, nb, fs.log2_nlp, fs.rb_stage);
     DR_LAUNCH_CHECK("k_flush_fixed");
     return DARTRAY_OK;
 }
@@ -2633,6 +2791,282 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     hipLaunchKernelGGL(k_rho_out, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, g.stream,
                        g.rho_bar, dJ_drho, n);
     DR_LAUNCH_CHECK("k_rho_out");
+    return DARTRAY_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of models: every pass of every model in one persistent march launch
+// and one flush launch per direction batch, optionally recorded once as a HIP
+// graph and replayed.
+// ---------------------------------------------------------------------------
+
+struct dartray_batch {
+    std::vector<dartray_grid *> grids;   // processing order: descending expected work
+    std::vector<int> caller;             // caller's index of each processed model
+    hipStream_t stream = nullptr;
+    int32_t n_lambda = 0;
+    dr::FixedArgs *d_args = nullptr;     // [2][n_models]: direct-pass and scattering-pass arguments
+    dr::FlushArgs *d_flush = nullptr;    // [n_models]
+    int64_t *d_item_off = nullptr;       // [n_models + 1]
+    std::vector<dr::FixedArgs> h_args;
+    std::vector<dr::FlushArgs> h_flush;
+    int64_t flush_blocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace dr {
+
+static void batch_free(dartray_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_args) (void)hipFree(b->d_args);
+    if (b->d_flush) (void)hipFree(b->d_flush);
+    if (b->d_item_off) (void)hipFree(b->d_item_off);
+    delete b;
+}
+
+static void launch_fixed_multi(const BatchMarch &B, int nlt, hipStream_t s, unsigned blocks, unsigned threads)
+{
+    switch (nlt) {
+    case 1: hipLaunchKernelGGL((k_march_fixed_multi<1>), dim3(blocks), dim3(threads), 0, s, B); break;
+    case 4: hipLaunchKernelGGL((k_march_fixed_multi<4>), dim3(blocks), dim3(threads), 0, s, B); break;
+    case 8: hipLaunchKernelGGL((k_march_fixed_multi<8>), dim3(blocks), dim3(threads), 0, s, B); break;
+    case 16: hipLaunchKernelGGL((k_march_fixed_multi<16>), dim3(blocks), dim3(threads), 0, s, B); break;
+    case 32: hipLaunchKernelGGL((k_march_fixed_multi<32>), dim3(blocks), dim3(threads), 0, s, B); break;
+    default: hipLaunchKernelGGL((k_march_fixed_multi<64>), dim3(blocks), dim3(threads), 0, s, B); break;
+    }
+}
+
+// argument checks and the device copies of every model's pass arguments;
+// fields[k] belongs to the caller's model k
+static int batch_prepare(dartray_batch *b, const dartray_trace_opts *o, dartray_fields *const *fields,
+                         const std::vector<int> &caller_index)
+{
+    if (!o || !fields) return fail(DARTRAY_E_INVALID, "null opts or fields");
+    if (o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "batches run fixed rays only");
+    if (o->mode != DARTRAY_MODE_DIRECT) return fail(DARTRAY_E_INVALID, "batches start with the direct pass");
+    if (o->source_mask) return fail(DARTRAY_E_UNSUPPORTED, "batches take no source mask");
+    const size_t nm = b->grids.size();
+    for (size_t k = 0; k < nm; ++k) {
+        Grid &g = b->grids[k]->g;
+        dartray_fields *f = fields[caller_index[k]];
+        int rc = check_opts(g, o, f, false);
+        if (rc) return rc;
+        if (o->nside > kMaxNsideWTable) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 16");
+        Frame fr;
+        frame_of(o, fr);
+        if ((rc = ensure_dirs(g, fr))) return rc;
+        if ((rc = ensure_wtab(g, o->nside, fr))) return rc;
+        b->h_args[k] = fixed_args(g, o, f, false);
+        b->h_args[nm + k] = fixed_args(g, o, f, true);
+        b->h_flush[k] = flush_args(g, f->S_next);
+    }
+    // flat flush grid: model k owns (cell blocks) x (pixel chunks) blocks
+    const FlushShape fs0 = flush_shape(b->grids[0]->g);
+    int pch = fs0.pch;
+    for (size_t k = 0; k < nm; ++k) pch = std::min(pch, flush_shape(b->grids[k]->g).pch);
+    int64_t blk = 0;
+    for (size_t k = 0; k < nm; ++k) {
+        const Grid &g = b->grids[k]->g;
+        const FlushShape fs = flush_shape(g);
+        const int64_t bx = (g.n + fs.per_block - 1) / fs.per_block;
+        b->h_flush[k].bx = (int32_t)bx;
+        b->h_flush[k].block0 = blk;
+        blk += bx * (fs.max_npix / pch);
+    }
+    if (blk > (int64_t)INT32_MAX) return fail(DARTRAY_E_UNSUPPORTED, "batch too large for one flush launch");
+    b->flush_blocks = blk;
+    DR_HIP(hipMemcpyAsync(b->d_args, b->h_args.data(), sizeof(FixedArgs) * 2 * nm, hipMemcpyHostToDevice, b->stream));
+    DR_HIP(hipMemcpyAsync(b->d_flush, b->h_flush.data(), sizeof(FlushArgs) * nm, hipMemcpyHostToDevice, b->stream));
+    DR_HIP(hipStreamSynchronize(b->stream));
+    return DARTRAY_OK;
+}
+
+// the pass sequence: direct pass, then n_scatter scattering iterations
+static int batch_sequence(dartray_batch *b, const dartray_trace_opts *o, dartray_fields *const *fields,
+                          const std::vector<int> &caller_index, int n_scatter)
+{
+    const int nm = (int)b->grids.size();
+    const int nl = b->n_lambda;
+    const int64_t nray = 12 * (int64_t)o->nside * o->nside;
+    Grid &g0 = b->grids[0]->g;
+    int nb = (int)nray;
+    for (int k = 0; k < nm; ++k) nb = std::min(nb, dir_batch(b->grids[k]->g, nray));
+    const FlushShape fs0 = flush_shape(g0);
+    int pch = fs0.pch;
+    size_t lds = 0;
+    for (int k = 0; k < nm; ++k) {
+        const FlushShape fs = flush_shape(b->grids[k]->g);
+        pch = std::min(pch, fs.pch);
+    }
+    int rb_stage = 16;
+    while (rb_stage > 1 && (size_t)rb_stage * nl * (pch + 1) * sizeof(float) > (size_t)48 * 1024) rb_stage >>= 1;
+    lds = (size_t)rb_stage * nl * (pch + 1) * sizeof(float);
+    const int chunk = lambda_chunk(g0);
+    const unsigned threads = 64u * (unsigned)(g0.tune.block_waves > 0 ? g0.tune.block_waves : 4);
+    const unsigned blocks = (unsigned)(g0.tune.grid_blocks > 0 ? g0.tune.grid_blocks : 2048);
+    const bool counting = (o->flags & DARTRAY_FLAG_COUNTERS) != 0;
+    int rc;
+    for (int pass = 0; pass <= n_scatter; ++pass) {
+        const bool scatter = pass > 0;
+        for (int k = 0; k < nm; ++k) {
+            Grid &g = b->grids[k]->g;
+            dartray_fields *f = fields[caller_index[k]];
+            if ((rc = fill<double>(g, g.U_k, (size_t)nl * g.n, 0.0))) return rc;
+            if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
+            if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
+            if (counting && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
+            if ((rc = select_sources(g, o, f, scatter))) return rc;
+        }
+        const FixedArgs *args = b->d_args + (scatter ? nm : 0);
+        for (int64_t r0 = 0; r0 < nray; r0 += nb) {
+            const int nbb = (int)std::min<int64_t>(nb, nray - r0);
+            for (int k = 0; k < nm; ++k) {
+                Grid &g = b->grids[k]->g;
+                if ((rc = fill<float>(g, g.ubar, (size_t)nbb * nl * g.n, 0.f))) return rc;
+            }
+            hipLaunchKernelGGL(k_batch_items, dim3(1), dim3(64), 0, b->stream, args, nm, nbb, b->d_item_off);
+            DR_LAUNCH_CHECK("k_batch_items");
+            for (int l0 = 0; l0 < nl; l0 += chunk) {
+                BatchMarch B{};
+                B.models = args;
+                B.item_off = b->d_item_off;
+                B.n_models = nm;
+                B.r0 = (int)r0;
+                B.nb = nbb;
+                B.l0 = l0;
+                B.nlc = std::min(chunk, nl - l0);
+                B.count = l0 == 0 ? 1 : 0;
+                launch_fixed_multi(B, nl_template(B.nlc), b->stream, blocks, threads);
+                DR_LAUNCH_CHECK("k_march_fixed_multi");
+            }
+            if (pch == 48)
+                hipLaunchKernelGGL(k_flush_fixed_multi<48>, dim3((unsigned)b->flush_blocks), dim3(256), lds, b->stream,
+                                   b->d_flush, nm, (int)r0, nbb, fs0.log2_nlp, rb_stage);
+            else
+                hipLaunchKernelGGL(k_flush_fixed_multi<12>, dim3((unsigned)b->flush_blocks), dim3(256), lds, b->stream,
+                                   b->d_flush, nm, (int)r0, nbb, fs0.log2_nlp, rb_stage);
+            DR_LAUNCH_CHECK("k_flush_fixed_multi");
+        }
+        for (int k = 0; k < nm; ++k) {
+            Grid &g = b->grids[k]->g;
+            if ((rc = finish_pass(g, o, fields[caller_index[k]], scatter))) return rc;
+        }
+    }
+    return DARTRAY_OK;
+}
+
+}  // namespace dr
+
+extern "C" {
+
+int dartray_batch_create(dartray_grid *const *grids, int32_t n_models, dartray_batch **out)
+{
+    if (!out) return fail(DARTRAY_E_INVALID, "null out");
+    *out = nullptr;
+    if (!grids || n_models <= 0) return fail(DARTRAY_E_INVALID, "need at least one grid");
+    for (int m = 0; m < n_models; ++m) {
+        if (!grids[m]) return fail(DARTRAY_E_INVALID, "null grid in batch");
+        if (grids[m]->g.stream != grids[0]->g.stream) return fail(DARTRAY_E_INVALID, "grids of a batch share one stream");
+        if (grids[m]->g.n_lambda != grids[0]->g.n_lambda)
+            return fail(DARTRAY_E_INVALID, "grids of a batch carry the same number of wavelengths");
+        for (int k = 0; k < m; ++k)
+            if (grids[k] == grids[m]) return fail(DARTRAY_E_INVALID, "a grid appears twice in the batch");
+    }
+    auto *b = new dartray_batch;
+    b->stream = grids[0]->g.stream;
+    b->n_lambda = grids[0]->g.n_lambda;
+    // descending expected work: sources x rays x path length ~ n^(4/3)
+    std::vector<int> idx(n_models);
+    for (int m = 0; m < n_models; ++m) idx[m] = m;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return grids[a]->g.n > grids[c]->g.n; });
+    for (int m : idx) {
+        b->grids.push_back(grids[m]);
+        b->caller.push_back(m);
+    }
+    b->h_args.resize(2 * (size_t)n_models);
+    b->h_flush.resize(n_models);
+    if (hipMalloc(&b->d_args, sizeof(dr::FixedArgs) * 2 * n_models) != hipSuccess ||
+        hipMalloc(&b->d_flush, sizeof(dr::FlushArgs) * n_models) != hipSuccess ||
+        hipMalloc(&b->d_item_off, sizeof(int64_t) * (n_models + 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        dr::batch_free(b);
+        return fail(DARTRAY_E_OOM, "batch argument arrays");
+    }
+    *out = b;
+    return DARTRAY_OK;
+}
+
+int dartray_batch_destroy(dartray_batch *b)
+{
+    if (b) dr::batch_free(b);
+    return DARTRAY_OK;
+}
+
+int dartray_batch_run(dartray_batch *b, const dartray_trace_opts *opts, dartray_fields *const *fields,
+                      int32_t n_scatter)
+{
+    if (!b) return fail(DARTRAY_E_INVALID, "null batch");
+    if (n_scatter < 0) return fail(DARTRAY_E_INVALID, "n_scatter must be >= 0");
+    int rc = dr::batch_prepare(b, opts, fields, b->caller);
+    if (rc) return rc;
+    return dr::batch_sequence(b, opts, fields, b->caller, n_scatter);
+}
+
+int dartray_batch_capture(dartray_batch *b, const dartray_trace_opts *opts, dartray_fields *const *fields,
+                          int32_t n_scatter)
+{
+    if (!b) return fail(DARTRAY_E_INVALID, "null batch");
+    if (n_scatter < 0) return fail(DARTRAY_E_INVALID, "n_scatter must be >= 0");
+    int rc = dr::batch_prepare(b, opts, fields, b->caller);
+    if (rc) return rc;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    // no event records inside the graph
+    std::vector<int32_t> prof(b->grids.size());
+    for (size_t k = 0; k < b->grids.size(); ++k) {
+        prof[k] = b->grids[k]->g.prof;
+        b->grids[k]->g.prof = 0;
+    }
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) rc = hip_fail(e, "hipStreamBeginCapture");
+    int rs = rc ? rc : dr::batch_sequence(b, opts, fields, b->caller, n_scatter);
+    if (!rc) {
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(b->stream, &gr);
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+        else if (rs) {
+            (void)hipGraphDestroy(gr);
+            rc = rs;
+        } else {
+            b->graph = gr;
+            e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                rc = hip_fail(e, "hipGraphInstantiate");
+            }
+        }
+    }
+    for (size_t k = 0; k < b->grids.size(); ++k) b->grids[k]->g.prof = prof[k];
+    return rc;
+}
+
+int dartray_batch_replay(dartray_batch *b)
+{
+    if (!b) return fail(DARTRAY_E_INVALID, "null batch");
+    if (!b->exec) return fail(DARTRAY_E_STATE, "no captured graph");
+    hipError_t e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return DARTRAY_OK;
 }
 

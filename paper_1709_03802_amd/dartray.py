@@ -38,7 +38,8 @@ EXPORTS = [
     "dartray_s_offset", "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter",
     "dartray_trace_adjoint", "dartray_debug_ray_cells", "dartray_workspace_bytes",
     "dartray_last_error", "dartray_version", "dartray_profile_enable", "dartray_profile_read",
-    "dartray_set_tuning", "dartray_get_tuning",
+    "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create", "dartray_batch_destroy",
+    "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay",
 ]
 
 
@@ -145,12 +146,18 @@ def load_library():
     L.dartray_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.dartray_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.dartray_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.dartray_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]
+    L.dartray_batch_destroy.argtypes = [C.c_void_p]
+    L.dartray_batch_run.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.POINTER(FieldsC)), C.c_int32]
+    L.dartray_batch_capture.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.POINTER(FieldsC)), C.c_int32]
+    L.dartray_batch_replay.argtypes = [C.c_void_p]
     L.dartray_last_error.restype = C.c_char_p
     L.dartray_version.restype = C.c_char_p
     for name in ("dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
                  "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter", "dartray_trace_adjoint",
                  "dartray_debug_ray_cells", "dartray_workspace_bytes", "dartray_profile_enable",
-                 "dartray_profile_read", "dartray_set_tuning", "dartray_get_tuning"):
+                 "dartray_profile_read", "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create",
+                 "dartray_batch_destroy", "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -292,6 +299,49 @@ class Fields:
             t = getattr(self, name)
             setattr(f, name, None if t is None else t.data_ptr())
         return f
+
+
+class Batch:
+    """Several grids (one stream, one wavelength count) whose fixed-ray passes
+    run together: one persistent march launch and one flush launch per
+    direction batch for all models; ``capture`` records the whole pass
+    sequence as a HIP graph that ``replay`` relaunches."""
+
+    def __init__(self, grids):
+        L = load_library()
+        self.grids = list(grids)
+        arr = (C.c_void_p * len(self.grids))(*[g.h.value for g in self.grids])
+        h = C.c_void_p()
+        _check(L.dartray_batch_create(arr, len(self.grids), C.byref(h)))
+        self.h = h
+
+    def _args(self, policy, fields, frame, counters):
+        if len(fields) != len(self.grids):
+            raise ValueError("one Fields per grid")
+        self._fc = [f.c() for f in fields]
+        arr = (C.POINTER(FieldsC) * len(fields))(*[C.pointer(fc) for fc in self._fc])
+        return make_opts(policy, MODE_DIRECT, frame, counters=counters), arr
+
+    def run(self, policy, fields, frame=None, counters=True):
+        opts, arr = self._args(policy, fields, frame, counters)
+        _check(load_library().dartray_batch_run(self.h, C.byref(opts), arr, int(policy.n_scatter)))
+
+    def capture(self, policy, fields, frame=None, counters=True):
+        """Record direct pass + policy.n_scatter iterations into fields (kept
+        by the caller: the graph writes to these buffers on every replay)."""
+        opts, arr = self._args(policy, fields, frame, counters)
+        _check(load_library().dartray_batch_capture(self.h, C.byref(opts), arr, int(policy.n_scatter)))
+
+    def replay(self):
+        _check(load_library().dartray_batch_replay(self.h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.dartray_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=True, max_steps=0) -> TraceOpts:

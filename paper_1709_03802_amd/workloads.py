@@ -248,12 +248,17 @@ def plain16(n_lambda: int = 1, n: int = 16, nside: int = 8, n_scatter: int = 2,
 
 def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
                nroot=(5, 5, 1), root_size=6.0, max_level=7, target_leaves=200_000,
-               eps_lum=2e-5, lambdas=DISK_LAMBDAS, tol=0.05, tau_max=None):
+               eps_lum=2e-5, lambdas=DISK_LAMBDAS, tol=0.05, tau_max=None, keep_best=False, peak=False):
     """Double-exponential stars + dust disk on an octree.
 
     A cell is split when its V-band optical depth across it exceeds tau_max or
     when its stellar luminosity exceeds eps_lum of the total; tau_max is
-    bisected so that the leaf count lands within ``tol`` of ``target_leaves``.
+    bisected so that the leaf count lands within ``tol`` of ``target_leaves``
+    (if it never does: the last build, or with ``keep_best`` the build whose
+    count was closest to the target in ratio).  The split test takes the
+    densities at the cell centre, or with ``peak`` at the cell's point nearest
+    to the mid-plane and the axis (so that thin disks between two cell
+    centres are still resolved).
     """
     lo = tuple(-0.5 * np.asarray(nroot, dtype=np.float64) * root_size)
     kr0 = tau_v_faceon / (2.0 * hd_z)          # face-on central tau through the plane
@@ -268,18 +273,31 @@ def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
 
     l_tot = 4.0 * math.pi * 2.0 * math.pi * h_r ** 2 * 2.0 * h_z   # j0 = 1, infinite disk
 
+    def nearest(c, s):
+        if not peak:
+            return c
+        rr = np.hypot(c[:, 0], c[:, 1])
+        shrink = np.maximum(rr - s / math.sqrt(2.0), 0.0) / np.maximum(rr, 1e-300)
+        return np.stack([c[:, 0] * shrink, c[:, 1] * shrink,
+                         np.sign(c[:, 2]) * np.maximum(np.abs(c[:, 2]) - 0.5 * s, 0.0)], axis=1)
+
     def build(tmax):
         def want(c, s):
-            return (dust(c) * s > tmax) | (4.0 * math.pi * stars(c) * s ** 3 > eps_lum * l_tot)
+            p = nearest(c, s)
+            return (dust(p) * s > tmax) | (4.0 * math.pi * stars(p) * s ** 3 > eps_lum * l_tot)
         return refine_octree(nroot, lo, root_size, max_level, want)
 
     if tau_max is None:
         a, b = 1e-3, 10.0
         level, ijk = build(math.sqrt(a * b))
+        best = None
         for _ in range(60):
             mid = math.sqrt(a * b)
             level, ijk = build(mid)
             n = level.shape[0]
+            miss = abs(math.log(n / target_leaves))
+            if best is None or miss < best[0]:
+                best = (miss, mid, level, ijk)
             if abs(n - target_leaves) <= tol * target_leaves:
                 tau_max = mid
                 break
@@ -289,6 +307,8 @@ def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
                 b = mid
         else:
             tau_max = math.sqrt(a * b)
+            if keep_best:
+                _, tau_max, level, ijk = best
     else:
         level, ijk = build(tau_max)
 
@@ -416,6 +436,33 @@ def rotation(seed: int) -> np.ndarray:
         [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
         [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
     ])
+
+
+def disk_batch(n_models=16, leaves=(1e3, 1e5), seed=1709, nside=8, n_scatter=2, tol=0.25):
+    """Independent disk models of uneven size for batched runs.
+
+    Model m has seeded scale lengths, scale heights and face-on optical depth
+    (stars h_R in [2, 4], h_z in [0.2, 0.4]; dust 1.5 h_R and h_z / 2 each
+    scaled by [0.8, 1.2]; tau_V in [0.5, 2]) and a leaf-count target drawn
+    log-uniformly in ``leaves``.  Returns a list of Workloads sharing one
+    fixed-ray policy (Nside ``nside``, no cutoff, direct + n_scatter)."""
+    rng = np.random.default_rng(seed)
+    pol = RayPolicy(adaptive=False, nside=nside, nside_max=nside, n_scatter=n_scatter)
+    out = []
+    for m in range(n_models):
+        target = float(np.exp(rng.uniform(np.log(leaves[0]), np.log(leaves[1]))))
+        h_r = rng.uniform(2.0, 4.0)
+        h_z = rng.uniform(0.2, 0.4)
+        hd_r = 1.5 * h_r * rng.uniform(0.8, 1.2)
+        hd_z = 0.5 * h_z * rng.uniform(0.8, 1.2)
+        tau = rng.uniform(0.5, 2.0)
+        max_level = int(np.clip(np.ceil(np.log(target / 25.0) / np.log(8.0)) + 2, 3, 7))
+        grid, tmax = disk_model(h_r=h_r, h_z=h_z, hd_r=hd_r, hd_z=hd_z, tau_v_faceon=tau, max_level=max_level,
+                                target_leaves=int(target), eps_lum=40.0 / target, tol=tol, keep_best=True,
+                                peak=True)
+        out.append(Workload(f"disk_batch{m}", grid, pol,
+                            f"disk model {m}: {grid.n} leaves, h_R {h_r:.2f}, h_z {h_z:.2f}, tau_V {tau:.2f}"))
+    return out
 
 
 def by_name(name: str) -> Workload:
