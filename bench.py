@@ -43,6 +43,102 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def wall(fn, repeats):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / repeats
+
+
+def run_crossings(out):
+    return int(sum(int(c[0]) for c in out.counters))
+
+
+def batched_lambda(dr, W, repeats=3):
+    """32 wavelengths in one march against the per-wavelength forms: the same
+    grid with one-wavelength march tiles, and 32 one-wavelength grids."""
+    wl = W.by_name("plain16_l32")
+    pol = wl.policy
+    G = dr.Grid(as_f32(wl.grid))
+    f = dr.Fields(G)
+    xl = run_crossings(dr.run(G, pol, fields=f)) * wl.grid.n_lambda
+
+    def with_tile(tile):
+        def fn():
+            G.set_tuning(lambda_tile=tile)
+            dr.run(G, pol, fields=f, collect=False)
+        return fn
+
+    singles = []
+    for lam in wl.grid.lambdas_um:
+        g1 = as_f32(W.plain16(lambdas=np.array([lam]), nside=pol.nside, n_scatter=pol.n_scatter).grid)
+        G1 = dr.Grid(g1)
+        singles.append((G1, dr.Fields(G1)))
+
+    def per_lambda_runs():
+        for G1, f1 in singles:
+            dr.run(G1, pol, fields=f1, collect=False)
+
+    res = {}
+    for name, fn in (("one_march", with_tile(0)), ("tile1", with_tile(1)), ("runs", per_lambda_runs)):
+        fn()
+        res[name] = wall(fn, repeats)
+    G.set_tuning(lambda_tile=0)
+    return {"workload": f"{wl.name}: {wl.description}, direct + {pol.n_scatter} scattering",
+            "crossings_x_lambda": xl,
+            "one_march_ms": 1e3 * res["one_march"], "one_wavelength_tiles_ms": 1e3 * res["tile1"],
+            "one_wavelength_runs_ms": 1e3 * res["runs"],
+            "value_one_march": xl / res["one_march"], "value_per_wavelength_runs": xl / res["runs"],
+            "speedup_vs_tiles": res["tile1"] / res["one_march"], "speedup_vs_runs": res["runs"] / res["one_march"]}
+
+
+def batched_models(dr, W, repeats=2):
+    """Sixteen disk models of uneven size: one after another, as one batch,
+    and as a replayed HIP graph of the batch."""
+    import torch
+    models = W.disk_batch(16)
+    pol = models[0].policy
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        Gs = [dr.Grid(as_f32(m.grid), stream=s) for m in models]
+        fs = [dr.Fields(G) for G in Gs]
+        fg = [dr.Fields(G) for G in Gs]
+    torch.cuda.synchronize()
+    xl = sum(run_crossings(dr.run(G, pol, fields=f)) for G, f in zip(Gs, fs)) * models[0].grid.n_lambda
+    B = dr.Batch(Gs)
+    B.capture(pol, fg, counters=False)
+
+    def sequential():
+        for G, f in zip(Gs, fs):
+            dr.run(G, pol, fields=f, collect=False)
+
+    res = {}
+    for name, fn in (("sequential", sequential), ("batch", lambda: B.run(pol, fs, counters=False)),
+                     ("graph", B.replay)):
+        fn()
+        res[name] = wall(fn, repeats)
+    B.close()
+    return {"workload": f"{len(models)} disk models, {min(m.grid.n for m in models)}..{max(m.grid.n for m in models)} "
+                        f"leaves ({sum(m.grid.n for m in models)} total), {models[0].grid.n_lambda} wavelengths, "
+                        f"fixed Nside {pol.nside}, direct + {pol.n_scatter} scattering",
+            "crossings_x_lambda": xl,
+            "sequential_ms": 1e3 * res["sequential"], "batch_ms": 1e3 * res["batch"], "graph_ms": 1e3 * res["graph"],
+            "value_graph": xl / res["graph"], "speedup_graph_vs_sequential": res["sequential"] / res["graph"]}
+
+
+def autotuned(dr, W):
+    """The autotuner on the 32-wavelength uniform grid (no cache)."""
+    from paper_1709_03802_amd import autotune as AT
+    wl = W.by_name("plain16_l32")
+    G = dr.Grid(as_f32(wl.grid))
+    setting, ms, log = AT.tune(G, wl.policy, cache_path=None, rounds=2, repeats=3)
+    return {"workload": wl.name, "pass": "scattering iteration", "setting": setting, "tuned_ms": ms,
+            "start_ms": log[0][1], "evaluations": len(log)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="disk", choices=["disk", "plain16", "plain16_l32", "plain16_l4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-wavelength, batched-model and autotuner measurements")
     ap.add_argument("--sample-sources", type=int, default=96,
                     help="disk: seeded emitting cells whose step 1 is checked against the oracle and timed on the CPU")
     args = ap.parse_args()
@@ -184,6 +282,16 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
     }
+    if not args.no_extras:
+        log("batched wavelengths ...")
+        res["batched_lambda"] = batched_lambda(dr, W)
+        log(f"batched wavelengths: {res['batched_lambda']}")
+        log("batched models ...")
+        res["batched_models"] = batched_models(dr, W)
+        log(f"batched models: {res['batched_models']}")
+        log("autotuner ...")
+        res["autotune"] = autotuned(dr, W)
+        log(f"autotuner: {res['autotune']}")
     print(json.dumps(res), flush=True)
 
 

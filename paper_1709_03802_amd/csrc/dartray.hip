@@ -208,31 +208,55 @@ __global__ void k_invz(float *invz, const LambdaTable *lt, const double *sca64, 
 // stable compaction into src_list.
 // ---------------------------------------------------------------------------
 
+// Direct pass: flag the cells (Morton order) that emit at some wavelength
+// and are allowed by the mask; sum the launched luminosity per wavelength.
 __global__ void k_source_flags(int32_t *flags, const int32_t *morton, int64_t n, const LambdaTable *lt,
-                               const float *emis_lum, const float *S_pending, const uint8_t *mask, int scatter,
-                               double *tally)
+                               const float *emis_lum, const uint8_t *mask, double *tally)
 {
     __shared__ double sh[16];
     const int nl = lt->n_lambda;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t c = i < n ? morton[i] : -1;
     bool any = false;
-    const bool allowed = c >= 0 && (scatter || mask == nullptr || mask[c] != 0);
+    const bool allowed = c >= 0 && (mask == nullptr || mask[c] != 0);
     for (int l = 0; l < nl; ++l) {
-        double e = 0.0;
-        if (allowed) {
-            if (!scatter) {
-                e = emis_lum[(int64_t)l * n + c];
-            } else {
-                const float *row = S_pending + lt->s_off[l] + c * (int64_t)lt->npix[l];
-                for (int p = 0; p < lt->npix[l]; ++p) e += row[p];
-            }
-        }
+        const double e = allowed ? (double)emis_lum[(int64_t)l * n + c] : 0.0;
         any |= e > 0.0;
         const double b = block_sum(e, sh);
         if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_EMITTED], b);
     }
     if (i < n) flags[i] = any ? 1 : 0;
+}
+
+// Scattering pass, step 1: a coalesced sweep of wavelength blockIdx.y's block
+// of the pending scattered luminosity flags every cell with a positive entry
+// (cell_flag indexed by cell) and sums the block in FP64.  S is never
+// negative, so a positive entry is the same as a positive row sum.
+__global__ void k_sflag_sweep(const float *S, const LambdaTable *lt, uint8_t *cell_flag, double *tally)
+{
+    __shared__ double sh[16];
+    const int l = blockIdx.y;
+    const int64_t lo = lt->s_off[l], hi = lt->s_off[l + 1];
+    const uint32_t npix = (uint32_t)lt->npix[l];
+    const bool small = hi - lo < ((int64_t)1 << 32);
+    double acc = 0.0;
+    for (int64_t i = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = S[i];
+        if (v > 0.f) {
+            const int64_t cell = small ? (int64_t)((uint32_t)(i - lo) / npix) : (i - lo) / (int64_t)npix;
+            cell_flag[cell] = 1;
+        }
+        acc += (double)v;
+    }
+    const double b = block_sum(acc, sh);
+    if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_EMITTED], b);
+}
+
+// Scattering pass, step 2: flags in Morton order for the compaction.
+__global__ void k_sflag_gather(int32_t *flags, const int32_t *morton, const uint8_t *cell_flag, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        flags[i] = cell_flag[morton[i]];
 }
 
 constexpr int kScanBlock = 1024;
@@ -359,14 +383,22 @@ __device__ inline T exit_t(const RayT<T> &R, const int4 b, int &axis)
 template <typename T>
 __device__ inline int32_t next_leaf(const Geo &g, const RayT<T> &R, const int4 b, const int32_t *nb, int axis, T te)
 {
-    const int32_t code = nb[2 * axis + (R.n[axis] > T(0) ? 1 : 0)];
+    // no runtime index into the ray or the neighbour array: those would be
+    // kept in scratch memory; the sign comes from an unrolled compare and
+    // the code from a register vector
+    bool pos = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pos = a == axis ? R.n[a] > T(0) : pos;
+    typedef int32_t nb8 __attribute__((ext_vector_type(8)));
+    const nb8 nv = {nb[0], nb[1], nb[2], nb[3], nb[4], nb[5], -1, -1};
+    const int32_t code = nv[2 * axis + (pos ? 1 : 0)];
     if (code >= -1) return code;            // a leaf, or outside the root block
     const int lo[3] = {b.x, b.y, b.z};
     int f[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (a == axis) {
-            f[a] = R.n[a] > T(0) ? lo[a] + b.w : lo[a] - 1;
+            f[a] = pos ? lo[a] + b.w : lo[a] - 1;
         } else {
             int q = fine_coord<T>(fma(te, R.n[a], R.o[a]), R.n[a]);
             q = q < lo[a] ? lo[a] : q;
@@ -462,26 +494,30 @@ __device__ inline float fixed_launch(const FixedArgs &A, const LambdaTable *lt, 
     return v;
 }
 
-// per-wave accumulators of the tallies and counters
+// per-lane counters
 template <int NL>
 struct FixedAcc {
-    float esc[NL];
     uint32_t ncross, nrays, nmax;
-    __device__ void clear()
-    {
-#pragma unroll
-        for (int l = 0; l < NL; ++l) esc[l] = 0.f;
-        ncross = nrays = nmax = 0;
-    }
+    __device__ void clear() { ncross = nrays = nmax = 0; }
 };
 
-// LDS staging of one wave's deposits (256-thread workgroups at most)
+// LDS of the march (256-thread workgroups at most): each wave's deposit
+// staging, its wavelengths' opacities and its FP64 escaped-luminosity sums
 template <int NL>
 struct FixedStage {
     float du[NL][256];
     int32_t cell[256];
     uint8_t list[256];
+    float kap[4][NL];
+    double esc[4][NL];
 };
+
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // One work item (64 sources of source tile `tile`, direction r0 + rl): the
 // wave's lanes walk their rays in lock step, one cell per iteration, and the
@@ -496,17 +532,17 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     const int nlc = A.nlc, l0 = A.l0;
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
+    const int w = threadIdx.x >> 6;
     const int r = A.r0 + rl;
     const int64_t si = tile * 64 + lane;
     bool active = si < nsrc;
     int32_t c = 0;
     Ray R;
-    float L[NL], kap[NL];
+    float L[NL];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        L[l] = 0.f;
-        kap[l] = l < nlc ? lt->kappa[l0 + l] : 0.f;
-    }
+    for (int l = 0; l < NL; ++l) L[l] = 0.f;
+    if (lane < NL) st.kap[w][lane] = lane < nlc ? lt->kappa[l0 + lane] : 0.f;
+    wave_sync_lds();
     if (active) {
         const int32_t s = A.src_list[si];
         const float4 nd = A.dirs[r];
@@ -557,7 +593,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
                     if (l < nlc) {
-                        const float alpha = kap[l] * rho;
+                        const float alpha = st.kap[w][l] * rho;
                         const float tau = alpha * lp;
                         const float em1 = expm1f(-tau);          // exp(-tau) - 1
                         const float ext = -L[l] * em1;
@@ -584,7 +620,8 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
             }
             if (!active) {
 #pragma unroll
-                for (int l = 0; l < NL; ++l) acc.esc[l] += L[l];
+                for (int l = 0; l < NL; ++l)
+                    if (l < nlc && L[l] != 0.f) atomicAdd(&st.esc[w][l], (double)L[l]);
             }
         }
         // lanes q of an instruction add value q % NL of the (q / NL)-th
@@ -592,9 +629,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
         const uint64_t dm = __ballot(dep);
         if (dm) {
             if (dep) st.list[wbase + __popcll(dm & ((1ull << lane) - 1ull))] = (uint8_t)lane;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync_lds();
             const int cnt = __popcll(dm);
             constexpr int PER = 64 / NL;
             for (int k0 = 0; k0 < cnt; k0 += PER) {
@@ -605,26 +640,25 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                     atomic_add_f32(ubase + (size_t)st.cell[wbase + j] * nl + l, st.du[l][wbase + j]);
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync_lds();
         }
     }
 }
 
-// wave-level FP64 reduction of the accumulators into A's tallies and counters
+// the wave's escaped-luminosity sums and counters into A's tallies
 template <int NL>
-__device__ void fixed_commit(const FixedArgs &A, FixedAcc<NL> &acc)
+__device__ void fixed_commit(const FixedArgs &A, FixedStage<NL> &st, FixedAcc<NL> &acc)
 {
     const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int nl = A.lt->n_lambda;
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        if (l < A.nlc) {
-            const double v = wave_sum((double)acc.esc[l]);
-            if (lane == 0 && v != 0.0) atomic_add_f64(&A.tally[(A.l0 + l) * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
-        }
+    wave_sync_lds();
+    if (lane < NL) {
+        const double v = st.esc[w][lane];
+        if (lane < A.nlc && v != 0.0) atomic_add_f64(&A.tally[(A.l0 + lane) * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], v);
+        st.esc[w][lane] = 0.0;
     }
+    wave_sync_lds();
     if (A.counters) {
         const uint64_t wc = wave_sum_u64(acc.ncross), wr = wave_sum_u64(acc.nrays), wm = wave_sum_u64(acc.nmax);
         if (lane == 0) {
@@ -661,13 +695,14 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
     const int64_t nitems = ntiles * A.nb;
     FixedAcc<NL> acc;
     acc.clear();
+    if ((threadIdx.x & 63) < NL) st.esc[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
     for (int64_t it = wid; it < nitems; it += nw) {
         int64_t tile;
         int rl;
         fixed_item_index(A, it, ntiles, tile, rl);
         fixed_item<NL>(A, tile, rl, nsrc, st, acc);
     }
-    fixed_commit<NL>(A, acc);
+    fixed_commit<NL>(A, st, acc);
 }
 
 // Several models in one persistent launch.  The work items of model m are
@@ -691,6 +726,7 @@ __global__ __launch_bounds__(256) void k_march_fixed_multi(const BatchMarch B)
     const int64_t nitems = B.item_off[B.n_models];
     FixedAcc<NL> acc;
     acc.clear();
+    if ((threadIdx.x & 63) < NL) st.esc[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
     int mcur = -1;
     FixedArgs A{};
     int nsrc = 0;
@@ -700,7 +736,7 @@ __global__ __launch_bounds__(256) void k_march_fixed_multi(const BatchMarch B)
         while (it >= B.item_off[m + 1]) ++m;
         m = __builtin_amdgcn_readfirstlane(m);
         if (m != mcur) {
-            if (mcur >= 0) fixed_commit<NL>(A, acc);
+            if (mcur >= 0) fixed_commit<NL>(A, st, acc);
             A = B.models[m];
             A.r0 = B.r0;
             A.nb = B.nb;
@@ -716,7 +752,7 @@ __global__ __launch_bounds__(256) void k_march_fixed_multi(const BatchMarch B)
         fixed_item_index(A, it - B.item_off[m], ntiles, tile, rl);
         fixed_item<NL>(A, tile, rl, nsrc, st, acc);
     }
-    if (mcur >= 0) fixed_commit<NL>(A, acc);
+    if (mcur >= 0) fixed_commit<NL>(A, st, acc);
 }
 
 // item_off[m + 1] = item_off[m] + ceil(n_src(model order[m]) / 64) nb
@@ -754,6 +790,8 @@ struct FlushArgs {
     int64_t block0;              // first block of this model (multi-model launch)
 };
 
+constexpr int kFlushStage = 16;   // most directions staged at once
+
 template <int PCH>
 __device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, int r0, int nb, int log2_nlp,
                             int rb_stage)
@@ -761,6 +799,12 @@ __device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, i
     constexpr int PS = PCH + 1;
     const LambdaTable *lt = F.lt;
     const int nl = lt->n_lambda;
+    __shared__ int s_npix[kMaxLambda], s_woff[kMaxLambda];
+    if (threadIdx.x < nl) {
+        s_npix[threadIdx.x] = lt->npix[threadIdx.x];
+        s_woff[threadIdx.x] = lt->w_off[threadIdx.x];
+    }
+    __syncthreads();
     const int64_t n = F.n;
     const int l = threadIdx.x & ((1 << log2_nlp) - 1);
     const int64_t c = bx * (int64_t)(256 >> log2_nlp) + (threadIdx.x >> log2_nlp);
@@ -775,26 +819,57 @@ __device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, i
     const float *ub = F.ubar + (ok ? (size_t)c * nl + l : 0);
     const size_t rstride = (size_t)n * nl;
     const float *wsl = ws + (size_t)(ok ? l : 0) * PS;
+    // the bins of the next stage are loaded while the current one is summed
+    float un[kFlushStage];
+#pragma unroll
+    for (int i = 0; i < kFlushStage; ++i) un[i] = (ok && i < min(rb_stage, nb)) ? ub[(size_t)i * rstride] : 0.f;
     for (int rb = 0; rb < nb; rb += rb_stage) {
         const int cnt = min(rb_stage, nb - rb);
+        float uc[kFlushStage];
+#pragma unroll
+        for (int i = 0; i < kFlushStage; ++i) {
+            uc[i] = un[i];
+            const int rn = rb + rb_stage + i;
+            un[i] = (ok && i < rb_stage && rn < nb) ? ub[(size_t)rn * rstride] : 0.f;
+        }
         __syncthreads();
-        for (int e = threadIdx.x; e < cnt * nl * PCH; e += 256) {
-            const int i = e / (nl * PCH);
-            const int rem = e - i * (nl * PCH);
-            const int ll = rem / PCH, j = rem - (rem / PCH) * PCH;
-            const int p = p0 + j;
-            ws[(i * nl + ll) * PS + j] =
-                p < lt->npix[ll] ? F.wtab[(int64_t)(r0 + rb + i) * F.w_row + lt->w_off[ll] + p] : 0.f;
+        {
+            // element e of the stage is weight j of row (direction i, wavelength
+            // ll); eight independent loads in flight per thread
+            const int total = cnt * nl * PCH;
+            const float inv_nl = 1.f / (float)nl;
+            for (int e0 = threadIdx.x; e0 < total; e0 += 8 * 256) {
+                float v[8];
+                int dst[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int e = e0 + k * 256;
+                    const int row = e / PCH;
+                    const int j = e - row * PCH;
+                    const int i = (int)(((float)row + 0.5f) * inv_nl);
+                    const int ll = row - i * nl;
+                    const int p = p0 + j;
+                    const bool in = e < total && p < s_npix[ll];
+                    v[k] = in ? F.wtab[(int64_t)(r0 + rb + i) * F.w_row + s_woff[ll] + p] : 0.f;
+                    dst[k] = e < total ? row * PS + j : -1;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (dst[k] >= 0) ws[dst[k]] = v[k];
+            }
         }
         __syncthreads();
         if (ok) {
-            for (int i = 0; i < cnt; ++i) {
-                const float u = ub[(size_t)(rb + i) * rstride];
-                accU += u;
-                if (pix) {
-                    const float *w = wsl + (size_t)i * nl * PS;
 #pragma unroll
-                    for (int j = 0; j < PCH; ++j) acc[j] = fmaf(u, w[j], acc[j]);
+            for (int i = 0; i < kFlushStage; ++i) {
+                if (i < cnt) {
+                    const float u = uc[i];
+                    accU += u;
+                    if (pix) {
+                        const float *w = wsl + (size_t)i * nl * PS;
+#pragma unroll
+                        for (int j = 0; j < PCH; ++j) acc[j] = fmaf(u, w[j], acc[j]);
+                    }
                 }
             }
         }
@@ -1785,7 +1860,7 @@ static void free_grid(Grid &g)
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
     void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
-                    g.flags, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
+                    g.flags, g.cell_flag, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -2013,7 +2088,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
         dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.d_lt, 1),
-        dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
+        dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
         dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
         dalloc(g, &g.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
         dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir), dalloc(g, &g.dir64, (size_t)ndir),
@@ -2310,14 +2385,33 @@ static int ensure_invz(Grid &g, const Frame &f)
     return DARTRAY_OK;
 }
 
+// blocks per wavelength for sweeps over the scattered-luminosity arrays:
+// about 16 elements per thread, at most 1024
+static unsigned s_blocks(const Grid &g)
+{
+    int64_t longest = 0;
+    for (int l = 0; l < g.n_lambda; ++l) longest = std::max<int64_t>(longest, g.lt.s_off[l + 1] - g.lt.s_off[l]);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (longest + 4095) / 4096));
+}
+
 static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fields *f, bool scatter)
 {
     const int64_t n = g.n;
     const unsigned nblk = (unsigned)((n + kScanBlock - 1) / kScanBlock);
-    hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, g.morton,
-                       n, g.d_lt, g.emis_lum, scatter ? f->S_pending : nullptr, scatter ? nullptr : o->source_mask,
-                       scatter ? 1 : 0, f->tally);
-    DR_LAUNCH_CHECK("k_source_flags");
+    if (!scatter) {
+        hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, g.morton,
+                           n, g.d_lt, g.emis_lum, o->source_mask, f->tally);
+        DR_LAUNCH_CHECK("k_source_flags");
+    } else {
+        int rc = fill<uint8_t>(g, g.cell_flag, (size_t)n, (uint8_t)0);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_sflag_sweep, dim3(s_blocks(g), g.n_lambda), dim3(256), 0, g.stream, f->S_pending, g.d_lt,
+                           g.cell_flag, f->tally);
+        DR_LAUNCH_CHECK("k_sflag_sweep");
+        hipLaunchKernelGGL(k_sflag_gather, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
+                           g.stream, g.flags, g.morton, g.cell_flag, n);
+        DR_LAUNCH_CHECK("k_sflag_gather");
+    }
     hipLaunchKernelGGL(k_scan_count, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, n, g.scan_blocks);
     DR_LAUNCH_CHECK("k_scan_count");
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, g.stream, g.scan_blocks, (int64_t)nblk, g.n_src);
@@ -2650,7 +2744,7 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
     int rc;
     double *ssum = g.dsum;
     if ((rc = fill<double>(g, ssum, (size_t)nl, 0.0))) return rc;
-    hipLaunchKernelGGL(k_finish_s, dim3(1024, nl), dim3(256), 0, g.stream, f->S_next, f->S_total, f->S_pending,
+    hipLaunchKernelGGL(k_finish_s, dim3(s_blocks(g), nl), dim3(256), 0, g.stream, f->S_next, f->S_total, f->S_pending,
                        scatter ? 1 : 0, g.d_lt, g.s_size, ssum);
     DR_LAUNCH_CHECK("k_finish_s");
     if (!scatter) {

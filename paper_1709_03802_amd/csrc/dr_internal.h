@@ -82,6 +82,7 @@ struct Grid {
     double *U_k = nullptr;                // [n][nl] (wavelength fastest), FP64 accumulator of FP32 deposits
     float *ull_t = nullptr;               // [n][nl] copy of U_LL for the march
     int32_t *flags = nullptr;             // [n] source flags, then scan
+    uint8_t *cell_flag = nullptr;         // [n] scattering-pass source flags by cell
     int32_t *src_list = nullptr;          // [n] compacted sources
     int32_t *scan_blocks = nullptr;       // block sums
     int32_t *n_src = nullptr;             // [1]

@@ -367,8 +367,13 @@ def trace_direct(grid: Grid, opts: TraceOpts, fields: Fields):
     _check(load_library().dartray_trace_direct(grid.h, C.byref(opts), C.byref(fc)))
 
 
-def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields) -> float:
+def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields, want_rk=True):
+    """One scattering iteration; returns r_k (a host synchronisation) or,
+    with want_rk=False, None and stays asynchronous."""
     fc = fields.c()
+    if not want_rk:
+        _check(load_library().dartray_scatter_iter(grid.h, C.byref(opts), C.byref(fc), None))
+        return None
     rk = C.c_double()
     _check(load_library().dartray_scatter_iter(grid.h, C.byref(opts), C.byref(fc), C.byref(rk)))
     return rk.value
@@ -464,7 +469,9 @@ def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Field
         if k == 0:
             trace_direct(grid, make_opts(policy, MODE_DIRECT, frame, source_mask), f)
         else:
-            rks.append(scatter_iter(grid, make_opts(policy, MODE_DIRECT, frame), f))
+            rk = scatter_iter(grid, make_opts(policy, MODE_DIRECT, frame), f, want_rk=collect)
+            if collect:
+                rks.append(rk)
         if collect:
             tallies.append(f.tally.cpu().numpy().copy())
             counters.append(f.counters.cpu().numpy().copy())
