@@ -336,6 +336,11 @@ __device__ inline int32_t locate_fine(const Geo &g, int fx, int fy, int fz)
 
 // fine-level cell coordinate of position p along an axis with direction
 // component d: on a face, the side d points to (upper side for d == 0)
+// Transmitted fraction e^{-tau} from em1 = e^{-tau} - 1: 1 + em1 in thin
+// cells, where it keeps extinguished + transmitted equal to the input to the
+// last bit; exp itself in thick cells, where 1 + em1 would cancel.
+__device__ inline float transmit(float tau, float em1) { return tau < 0.5f ? 1.f + em1 : expf(-tau); }
+
 template <typename T>
 __device__ inline int fine_coord(T p, T d)
 {
@@ -345,9 +350,10 @@ __device__ inline int fine_coord(T p, T d)
     return i;
 }
 
-// A ray in finest-level cell units.  The fixed-Nside march uses FP32; the
-// adaptive march keeps its geometry in FP64 so that its split, block and
-// step-1 extent decisions are taken on the same values as in exact arithmetic.
+// A ray in finest-level cell units.  The marches keep their geometry in FP64:
+// distances along a ray reach hundreds of cells, and the adaptive march takes
+// its split, block and step-1 extent decisions on these values.  The FP32
+// instance serves the debugging traversal only.
 template <typename T>
 struct RayT {
     T o[3];       // origin (source-cell centre), fine units
@@ -455,7 +461,7 @@ struct FixedArgs {
     Geo geo;
     const int32_t *src_list;
     const int32_t *n_src;
-    const float4 *dirs;
+    const double4 *dirs;         // FP64 directions of this Nside
     const float *emis_lum;       // direct pass
     const float *S_pending;      // scatter pass
     const LambdaTable *lt;
@@ -472,7 +478,7 @@ struct FixedArgs {
     int32_t nside_ray;
     int32_t log2_nside_ray;
     float inv_nray;
-    float h_fine;
+    double h_fine;
     int64_t max_steps;           // caller's per-ray limit (0 = none)
     int64_t hard_cap;            // bound no straight ray can exceed; ends any loop
 };
@@ -537,7 +543,9 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     const int64_t si = tile * 64 + lane;
     bool active = si < nsrc;
     int32_t c = 0;
-    Ray R;
+    // FP64 geometry: distances along a ray reach hundreds of cells, where FP32
+    // would leave segments near the graze limit with percent-level errors
+    RayT<double> R;
     float L[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) L[l] = 0.f;
@@ -545,17 +553,17 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     wave_sync_lds();
     if (active) {
         const int32_t s = A.src_list[si];
-        const float4 nd = A.dirs[r];
+        const double4 nd = A.dirs[r];
         R.n[0] = nd.x;
         R.n[1] = nd.y;
         R.n[2] = nd.z;
         const int4 b = A.geo.rec[s].box;
-        const float half = 0.5f * (float)b.w;
-        R.o[0] = (float)b.x + half;
-        R.o[1] = (float)b.y + half;
-        R.o[2] = (float)b.z + half;
+        const double half = 0.5 * (double)b.w;
+        R.o[0] = (double)b.x + half;
+        R.o[1] = (double)b.y + half;
+        R.o[2] = (double)b.z + half;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
+        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0 / R.n[a];
         float lsum = 0.f;
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
@@ -572,7 +580,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
         c = s;
         if (active) ++acc.nrays;
     }
-    float t = 0.f;
+    double t = 0.0;
     int64_t steps = 0;
     float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
     while (__ballot(active)) {
@@ -586,10 +594,10 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
 #pragma unroll
             for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
             int axis;
-            const float te = exit_t(R, b, axis);
-            const float len = te - t;
-            if (len > 1e-6f * ((float)b.w + te)) {   // shorter segments are grazes
-                const float lp = len * A.h_fine;
+            const double te = exit_t(R, b, axis);
+            const double len = te - t;
+            if (len > 1e-6 * ((double)b.w + te)) {   // shorter segments are grazes
+                const float lp = (float)(len * A.h_fine);
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
                     if (l < nlc) {
@@ -598,7 +606,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                         const float em1 = expm1f(-tau);          // exp(-tau) - 1
                         const float ext = -L[l] * em1;
                         st.du[l][threadIdx.x] = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
-                        L[l] = fmaf(L[l], em1, L[l]);
+                        L[l] = tau < 0.5f ? fmaf(L[l], em1, L[l]) : L[l] * expf(-tau);   // transmit(), fused
                     }
                 }
                 st.cell[threadIdx.x] = c;
@@ -606,7 +614,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                 ++acc.ncross;
                 t = te;
             }
-            const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
+            const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
             if (nx < 0) {
                 active = false;
             } else {
@@ -1254,7 +1262,10 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
                                 deposit |= Fl != 0.f;
                             }
                             s_du[l][threadIdx.x] = du;
-                            L[l] = fmaf(L[l], em1[l], L[l]);
+                            {
+                                const float tau = s_kap[l] * rho_c * lp;
+                                L[l] = tau < 0.5f ? fmaf(L[l], em1[l], L[l]) : L[l] * expf(-tau);   // transmit(), fused
+                            }
                         }
                     }
                     if (!STEP1 && deposit)
@@ -1554,7 +1565,7 @@ struct AdjArgs {
     Geo geo;
     const int32_t *src_list;
     const int32_t *n_src;
-    const float4 *dirs;          // directions of this Nside
+    const double4 *dirs;         // FP64 directions of this Nside
     const float *emis_lum;       // direct pass
     const float *S_pending;      // scattering pass: its emission
     const LambdaTable *lt;
@@ -1568,7 +1579,7 @@ struct AdjArgs {
     int32_t nb;
     int32_t log2_nside_ray;
     float inv_nray;
-    float h_fine;
+    double h_fine;
     int64_t hard_cap;
 };
 
@@ -1609,18 +1620,18 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
         const int64_t si = tile * 64 + (threadIdx.x & 63);
         if (si >= nsrc) continue;
         const int32_t s = A.src_list[si];
-        const float4 nd = A.dirs[r];
-        Ray R;
+        const double4 nd = A.dirs[r];
+        RayT<double> R;              // FP64 geometry, as in the forward march
         R.n[0] = nd.x;
         R.n[1] = nd.y;
         R.n[2] = nd.z;
         const int4 sb = A.geo.rec[s].box;
-        const float half = 0.5f * (float)sb.w;
-        R.o[0] = (float)sb.x + half;
-        R.o[1] = (float)sb.y + half;
-        R.o[2] = (float)sb.z + half;
+        const double half = 0.5 * (double)sb.w;
+        R.o[0] = (double)sb.x + half;
+        R.o[1] = (double)sb.y + half;
+        R.o[2] = (double)sb.z + half;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0f / R.n[a];
+        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0 / R.n[a];
         float L0[NL];
         float lsum = 0.f;
 #pragma unroll
@@ -1659,7 +1670,7 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
 #pragma unroll
             for (int l = 0; l < NL; ++l) ell[l] = 1.f;
             int32_t c = s;
-            float t = 0.f;
+            double t = 0.0;
             int64_t steps = 0;
             while (true) {
                 const LeafRec &rc = A.geo.rec[c];
@@ -1668,12 +1679,12 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
 #pragma unroll
                 for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
                 int axis;
-                const float te = exit_t(R, b, axis);
-                const float len = te - t;
-                if (len > 1e-6f * ((float)b.w + te)) {
+                const double te = exit_t(R, b, axis);
+                const double len = te - t;
+                if (len > 1e-6 * ((double)b.w + te)) {
                     const float rho = rc.rho;
                     const float ivc = rc.ivc;
-                    const float lp = len * A.h_fine;
+                    const float lp = (float)(len * A.h_fine);
                     double rb = 0.0;
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
@@ -1689,18 +1700,18 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
                             if (walk == 0) {
                                 G[l] += (double)ell[l] * (double)a;
                             } else {
-                                const float ap = lp * dE * ivc * ub + alb[l] * (1.f + em1) * sg;
+                                const float ap = lp * dE * ivc * ub + alb[l] * transmit(tau, em1) * sg;
                                 P[l] += (double)ell[l] * (double)a;
                                 const double dtau = (double)L0[l] * ((double)ell[l] * (double)ap - (G[l] - P[l]));
                                 rb += (double)kap[l] * (double)lp * dtau;
                             }
-                            ell[l] = fmaf(ell[l], em1, ell[l]);
+                            ell[l] *= transmit(tau, em1);
                         }
                     }
                     if (walk == 1 && rb != 0.0) atomic_add_f64(A.rho_bar + c, rb);
                     t = te;
                 }
-                const int32_t nx = next_leaf(A.geo, R, b, nbc, axis, te);
+                const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
                 if (nx < 0) break;
                 if (++steps >= A.hard_cap) break;
                 c = nx;
@@ -2475,7 +2486,7 @@ static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields
                 g.max_level};
     A.src_list = g.src_list;
     A.n_src = g.n_src;
-    A.dirs = g.dir_all + entry_of(o->nside, 0);
+    A.dirs = g.dir64 + entry_of(o->nside, 0);
     A.emis_lum = g.emis_lum;
     A.S_pending = f->S_pending;
     A.lt = g.d_lt;
@@ -2488,7 +2499,7 @@ static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields
     A.nside_ray = o->nside;
     A.log2_nside_ray = log2n;
     A.inv_nray = (float)(1.0 / (double)nray);
-    A.h_fine = (float)g.h_fine;
+    A.h_fine = g.h_fine;
     A.max_steps = o->max_steps;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
     return A;
@@ -2828,7 +2839,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
                 g.max_level};
     A.src_list = g.src_list;
     A.n_src = g.n_src;
-    A.dirs = g.dir_all + entry_of(opts->nside, 0);
+    A.dirs = g.dir64 + entry_of(opts->nside, 0);
     A.emis_lum = g.emis_lum;
     A.lt = g.d_lt;
     A.ubar_t = g.ull_t;
@@ -2836,7 +2847,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     A.n = n;
     A.log2_nside_ray = log2n;
     A.inv_nray = (float)(1.0 / (double)nray);
-    A.h_fine = (float)g.h_fine;
+    A.h_fine = g.h_fine;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
     const float *sbar_next = nullptr;
     for (int k = n_scatter; k >= 0; --k) {
