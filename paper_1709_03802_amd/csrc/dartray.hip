@@ -982,8 +982,18 @@ __device__ inline float readlane_f(float v, int j)
 
 __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
 
+// waves per SIMD the compiler must allow for the adaptive march (register
+// budget): step 1, and the passes that scatter light
+#ifndef DR_WAVES_STEP1
+#define DR_WAVES_STEP1 4
+#endif
+#ifndef DR_WAVES_SCATTER
+#define DR_WAVES_SCATTER 1
+#endif
+
 template <int NL, int MODE>
-__global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? DR_WAVES_STEP1 : DR_WAVES_SCATTER, 8)))
+void k_march_adaptive(const AdaptArgs A)
 {
     constexpr bool STEP1 = MODE == 0;
     constexpr int kBlock = 256;
@@ -1391,14 +1401,14 @@ __global__ __launch_bounds__(256) void k_march_adaptive(const AdaptArgs A)
 
 // ---------------------------------------------------------------------------
 // Expansion of the sorted deposit log.  Thread slots cover every
-// (wavelength, j_sca pixel) pair plus one energy-density slot per wavelength;
-// a block walks a contiguous range of cell-sorted tuples, accumulates each
-// cell's contributions in compensated (Kahan) registers and adds them to
-// S_next / U_k when the cell changes.  The scattered luminosity of a tuple is
+// (wavelength, j_sca pixel) pair, and the first n_lambda threads also sum the
+// energy density; a block walks a contiguous range of cell-sorted tuples,
+// accumulates each cell's contributions in compensated (Kahan) registers and
+// adds them to S_next / U_k when the cell changes.  The scattered luminosity of a tuple is
 // albedo c alpha V du w(p|n) (the deposit du = ext / (alpha V c)).
 // ---------------------------------------------------------------------------
 
-constexpr int kExpandSlots = 8;        // slots per thread: up to 2048 per block
+constexpr int kExpandSlots = 8;        // pixel slots per thread: up to 2048 per block
 constexpr int kExpandBatch = 64;       // tuples staged in LDS at a time
 
 __global__ void k_iota(uint32_t *p, int64_t n)
@@ -1424,49 +1434,49 @@ struct ExpandArgs {
     int32_t w_row;
 };
 
-template <int NL>
+template <int NL, int SLOTS>
 __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
 {
     __shared__ float4 sca[kScaDirs];
     __shared__ int32_t t_cell[kExpandBatch];
     __shared__ float4 t_n[kExpandBatch];
-    __shared__ float t_a[NL][kExpandBatch];     // du * 1/Z: scattered-light coefficient
+    __shared__ float t_a[NL + 1][kExpandBatch];   // du / Z per wavelength; row NL stays zero
     __shared__ float t_du[NL][kExpandBatch];
     const LambdaTable *lt = X.lt;
     const int nl = lt->n_lambda;
     for (int i = threadIdx.x; i < kScaDirs; i += blockDim.x) sca[i] = X.dirs[i];
-
-    // slot assignment
-    int kind[kExpandSlots], lam[kExpandSlots], pix[kExpandSlots];
-    float npx[kExpandSlots], npy[kExpandSlots], npz[kExpandSlots], hB[kExpandSlots], hC[kExpandSlots];
-    float acc[kExpandSlots], cmp[kExpandSlots];
+    if (threadIdx.x < kExpandBatch) t_a[NL][threadIdx.x] = 0.f;
     __syncthreads();
+
+    // slot k of this thread is pixel slot threadIdx.x + 256 k of the
+    // concatenated per-wavelength rows; the Henyey-Greenstein denominator is
+    // hB + (hC n_p) . n, so each slot keeps hC n_p and hB.  Slots past the
+    // rows read the zero row of t_a.
+    int lam[SLOTS];
+    float cx[SLOTS], cy[SLOTS], cz[SLOTS], hb[SLOTS], acc[SLOTS], cmp[SLOTS];
 #pragma unroll
-    for (int k = 0; k < kExpandSlots; ++k) {
+    for (int k = 0; k < SLOTS; ++k) {
         const int sl = threadIdx.x + 256 * k;
-        kind[k] = 0;
-        lam[k] = 0;
-        pix[k] = 0;
-        npx[k] = npy[k] = npz[k] = hB[k] = hC[k] = 0.f;
+        lam[k] = NL;
+        cx[k] = cy[k] = cz[k] = 0.f;
+        hb[k] = 1.f;
         acc[k] = cmp[k] = 0.f;
         if (sl < X.w_row) {
             int l = 0;
             while (l + 1 < nl && lt->w_off[l + 1] <= sl) ++l;
-            kind[k] = 1;
             lam[k] = l;
-            pix[k] = sl - lt->w_off[l];
-            const float4 v = sca[entry_of(lt->nside_sca[l], 0) + pix[k]];
-            npx[k] = v.x;
-            npy[k] = v.y;
-            npz[k] = v.z;
+            const float4 v = sca[entry_of(lt->nside_sca[l], 0) + (sl - lt->w_off[l])];
             const float g = lt->g[l];
-            hB[k] = 1.f + g * g;
-            hC[k] = -2.f * g;
-        } else if (sl < X.w_row + nl) {
-            kind[k] = 2;
-            lam[k] = sl - X.w_row;
+            const float hC = -2.f * g;
+            cx[k] = hC * v.x;
+            cy[k] = hC * v.y;
+            cz[k] = hC * v.z;
+            hb[k] = 1.f + g * g;
         }
     }
+    // energy density: thread l < nl sums wavelength l
+    float accU = 0.f, cmpU = 0.f;
+    const int ul = threadIdx.x < nl ? (int)threadIdx.x : 0;
 
     const int64_t i0 = blockIdx.x * X.chunk;
     const int64_t i1 = min(X.cnt, i0 + X.chunk);
@@ -1476,18 +1486,22 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
         if (cur < 0) return;
         const LeafRec &r = X.rec[cur];
 #pragma unroll
-        for (int k = 0; k < kExpandSlots; ++k) {
+        for (int k = 0; k < SLOTS; ++k) {
             const float v = acc[k] - cmp[k];
-            if (kind[k] == 1 && v != 0.f) {
+            if (lam[k] < NL && v != 0.f) {
                 const int l = lam[k];
                 const float g = lt->g[l];
                 const float scale = lt->albedo[l] * lt->kappa[l] * r.rho / r.ivc * ((1.f - g * g) / (4.f * 3.14159265358979f));
-                atomic_add_f32(X.S_next + lt->s_off[l] + (int64_t)cur * lt->npix[l] + pix[k], scale * v);
-            } else if (kind[k] == 2 && v != 0.f) {
-                atomic_add_f64(X.U_k + (int64_t)cur * nl + lam[k], (double)v);
+                const int p = (int)threadIdx.x + 256 * k - lt->w_off[l];
+                atomic_add_f32(X.S_next + lt->s_off[l] + (int64_t)cur * lt->npix[l] + p, scale * v);
             }
             acc[k] = cmp[k] = 0.f;
         }
+        if (threadIdx.x < nl) {
+            const float v = accU - cmpU;
+            if (v != 0.f) atomic_add_f64(X.U_k + (int64_t)cur * nl + threadIdx.x, (double)v);
+        }
+        accU = cmpU = 0.f;
     };
 
     for (int64_t i = i0; i < i1; i += kExpandBatch) {
@@ -1499,10 +1513,13 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
             const uint32_t e = X.dir[orig];
             t_cell[threadIdx.x] = (int32_t)X.key[j];
             t_n[threadIdx.x] = X.dirs[e];
-            for (int l = 0; l < nl; ++l) {
-                const float d = X.du[(int64_t)l * X.cap + orig];
-                t_du[l][threadIdx.x] = d;
-                t_a[l][threadIdx.x] = d * X.invz[(int64_t)e * nl + l];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (l < nl) {
+                    const float d = X.du[(int64_t)l * X.cap + orig];
+                    t_du[l][threadIdx.x] = d;
+                    t_a[l][threadIdx.x] = d * X.invz[(int64_t)e * nl + l];
+                }
             }
         }
         __syncthreads();
@@ -1514,20 +1531,20 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
             }
             const float4 n = t_n[jj];
 #pragma unroll
-            for (int k = 0; k < kExpandSlots; ++k) {
-                float v = 0.f;
-                if (kind[k] == 1) {
-                    const float mu = fmaf(npx[k], n.x, fmaf(npy[k], n.y, npz[k] * n.z));
-                    const float r = rsqrtf(fmaf(hC[k], mu, hB[k]));
-                    v = t_a[lam[k]][jj] * (r * r * r);
-                } else if (kind[k] == 2) {
-                    v = t_du[lam[k]][jj];
-                }
+            for (int k = 0; k < SLOTS; ++k) {
+                const float r = rsqrtf(fmaf(cx[k], n.x, fmaf(cy[k], n.y, fmaf(cz[k], n.z, hb[k]))));
+                const float v = t_a[lam[k]][jj] * (r * r * r);
                 // compensated sum: acc holds the sum, cmp the rounding error
                 const float y = v - cmp[k];
                 const float t = acc[k] + y;
                 cmp[k] = (t - acc[k]) - y;
                 acc[k] = t;
+            }
+            {
+                const float y = t_du[ul][jj] - cmpU;
+                const float t = accU + y;
+                cmpU = (t - accU) - y;
+                accU = t;
             }
         }
     }
@@ -2118,7 +2135,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     g.ndir_all = ndir;
     // deposit log for the scattering passes of adaptive rays (wavelength rows
     // of at most 2048 slots per expansion block)
-    if (nl <= 16 && g.w_row + nl <= 256 * kExpandSlots) {
+    if (nl <= 16 && g.w_row <= 256 * kExpandSlots) {
         const int64_t lcap = std::min<int64_t>((int64_t)1 << 27, std::max<int64_t>((int64_t)1 << 16, 256 * n));
         int rl[] = {dalloc(g, &g.log_key, (size_t)lcap), dalloc(g, &g.log_key2, (size_t)lcap),
                     dalloc(g, &g.log_idx, (size_t)lcap), dalloc(g, &g.log_idx2, (size_t)lcap),
@@ -2611,6 +2628,30 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
 }
 
 template <int NL>
+static void launch_expand_nl(const ExpandArgs &X, int slots, hipStream_t s, unsigned blocks)
+{
+    switch (slots) {
+    case 1: hipLaunchKernelGGL((k_expand<NL, 1>), dim3(blocks), dim3(256), 0, s, X); break;
+    case 2: hipLaunchKernelGGL((k_expand<NL, 2>), dim3(blocks), dim3(256), 0, s, X); break;
+    case 3: hipLaunchKernelGGL((k_expand<NL, 3>), dim3(blocks), dim3(256), 0, s, X); break;
+    case 4: hipLaunchKernelGGL((k_expand<NL, 4>), dim3(blocks), dim3(256), 0, s, X); break;
+    case 5: hipLaunchKernelGGL((k_expand<NL, 5>), dim3(blocks), dim3(256), 0, s, X); break;
+    case 6: hipLaunchKernelGGL((k_expand<NL, 6>), dim3(blocks), dim3(256), 0, s, X); break;
+    case 7: hipLaunchKernelGGL((k_expand<NL, 7>), dim3(blocks), dim3(256), 0, s, X); break;
+    default: hipLaunchKernelGGL((k_expand<NL, 8>), dim3(blocks), dim3(256), 0, s, X); break;
+    }
+}
+
+// expansion with ceil(w_row / 256) pixel slots per thread (at most 8)
+static void launch_expand(const ExpandArgs &X, int nl, int slots, hipStream_t s, unsigned blocks)
+{
+    if (nl <= 1) launch_expand_nl<1>(X, slots, s, blocks);
+    else if (nl <= 4) launch_expand_nl<4>(X, slots, s, blocks);
+    else if (nl <= 8) launch_expand_nl<8>(X, slots, s, blocks);
+    else launch_expand_nl<16>(X, slots, s, blocks);
+}
+
+template <int NL>
 static void launch_adaptive(const AdaptArgs &A, int mode, hipStream_t s, unsigned blocks)
 {
     if (mode == 0) hipLaunchKernelGGL((k_march_adaptive<NL, 0>), dim3(blocks), dim3(256), 0, s, A);
@@ -2731,10 +2772,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
             X.chunk = 2048;
             X.w_row = g.w_row;
             const unsigned eb = (unsigned)((cnt + X.chunk - 1) / X.chunk);
-            if (nl <= 1) hipLaunchKernelGGL(k_expand<1>, dim3(eb), dim3(256), 0, g.stream, X);
-            else if (nl <= 4) hipLaunchKernelGGL(k_expand<4>, dim3(eb), dim3(256), 0, g.stream, X);
-            else if (nl <= 8) hipLaunchKernelGGL(k_expand<8>, dim3(eb), dim3(256), 0, g.stream, X);
-            else hipLaunchKernelGGL(k_expand<16>, dim3(eb), dim3(256), 0, g.stream, X);
+            launch_expand(X, nl, (g.w_row + 255) / 256, g.stream, eb);
             DR_LAUNCH_CHECK("k_expand");
         }
         if (hc[1] >= nitems) break;
