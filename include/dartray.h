@@ -165,6 +165,10 @@ typedef struct {
  *  S_next    [s_size]       work array of the pass (overwritten)
  *  tally     [n_lambda][8]  FP64, overwritten by each pass (DARTRAY_T_*)
  *  counters  [8]            uint64, overwritten when DARTRAY_FLAG_COUNTERS
+ *  escape    [n_lambda][12 nside^2]  nullable; fixed rays only: luminosity of
+ *                           the pass leaving the root block, by ray direction
+ *                           (summed over sources; FP64 sums, FP32 output),
+ *                           overwritten by each pass
  * S arrays hold one block per wavelength, block l starting at
  * dartray_s_offset(grid, l), laid out [n][12 nside_sca(l)^2] with the HEALPix
  * nested pixel index fastest.  S[l][c][p] is the luminosity scattered by cell
@@ -179,6 +183,7 @@ typedef struct {
     float *S_next;
     double *tally;
     uint64_t *counters;
+    float *escape;
 } dartray_fields;
 
 /* Build the device-side grid: validate, copy to the GPU, build the leaf
@@ -218,8 +223,9 @@ int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dar
 int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields, double *r_k);
 
 /*
- * Gradient dJ/drho of a loss J of the energy density U with respect to the
- * per-cell dust density, by an adjoint march over the passes of a fixed-ray
+ * Gradient dJ/drho of a loss J of the energy density U and of the escaping
+ * luminosity F (escape summed over the passes) with respect to the per-cell
+ * dust density, by an adjoint march over the passes of a fixed-ray
  * run in reverse order (scattering iteration n_scatter down to the direct
  * pass).  Rays are recomputed, not stored: each ray is walked twice, first for
  * the total of its loss-weighted deposits, then for the derivative at every
@@ -232,11 +238,14 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
  *  S_hist     host array of n_scatter device pointers; S_hist[k-1] is the
  *             pending scattered luminosity iteration k processed (S_pending
  *             before that dartray_scatter_iter call), S layout
- *  dJ_dU      device float [n_lambda][n]
+ *  dJ_dU      device float [n_lambda][n], or NULL for a loss without U
+ *  dJ_desc    device float [n_lambda][12 nside^2], or NULL for a loss
+ *             without the escaping luminosity (it enters each ray as the
+ *             terminal value of the reverse recursion)
  *  dJ_drho    device float [n], overwritten
  */
 int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, int32_t n_scatter,
-                          const float *const *S_hist, const float *dJ_dU, float *dJ_drho);
+                          const float *const *S_hist, const float *dJ_dU, const float *dJ_desc, float *dJ_drho);
 
 /*
  * Test helper: the cells crossed by n_rays rays (host arrays: origin[3i],

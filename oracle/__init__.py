@@ -111,10 +111,11 @@ def lib():
         L.orc_trace_cells.restype = C.c_int64
         L.orc_run_pass.argtypes = [C.c_void_p, C.POINTER(PassOpts), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                   C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.orc_run_pass.restype = C.c_int
         L.orc_adjoint_pass.argtypes = [C.c_void_p, C.POINTER(PassOpts), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]
         L.orc_adjoint_pass.restype = C.c_int
         _lib = L
     return _lib
@@ -258,16 +259,19 @@ class Model:
         S_next = np.zeros(max(self.s_size, 1))
         tally = np.zeros(self.nl * 8)
         counters = np.zeros(8, dtype=np.int64)
+        nray0 = 12 * int(policy.nside) ** 2
+        escape = np.zeros(self.nl * nray0)
         Sp = None if S_pending is None else np.ascontiguousarray(S_pending, dtype=np.float64)
         ULL = None if U_LL is None else np.ascontiguousarray(U_LL, dtype=np.float64).ravel()
         rc = lib().orc_run_pass(self.h, C.byref(o),
                                 None if Sp is None else _p(Sp, C.c_double),
                                 None if ULL is None else _p(ULL, C.c_double),
                                 _p(U_k, C.c_double), _p(S_next, C.c_double), _p(tally, C.c_double),
-                                _p(counters, C.c_int64))
+                                _p(counters, C.c_int64), _p(escape, C.c_double))
         if rc != 0:
             raise ValueError(f"oracle pass failed (status {rc})")
-        return PassResult(U_k.reshape(self.nl, self.n), S_next[:self.s_size], tally.reshape(self.nl, 8), counters)
+        return PassResult(U_k.reshape(self.nl, self.n), S_next[:self.s_size], tally.reshape(self.nl, 8), counters,
+                          escape.reshape(self.nl, nray0))
 
 
 def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
@@ -289,10 +293,16 @@ def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
     return o, keep
 
 
-def adjoint(model: Model, policy, run_result, Ubar, Sbar_last=None, frame=None, source_mask=None, n_threads=0):
-    """dJ/drho for a loss J(U, S_total) given dJ/dU (and optionally dJ/dS of the
-    last, unprocessed order), by reverse passes over a fixed-ray run."""
+def adjoint(model: Model, policy, run_result, Ubar=None, Sbar_last=None, frame=None, source_mask=None, n_threads=0,
+            Ebar=None):
+    """dJ/drho for a loss J(U, S_total, F) given dJ/dU (and optionally dJ/dS of
+    the last, unprocessed order, and dJ/dF for the escaping luminosity F summed
+    over the passes, [n_lambda][12 nside^2]), by reverse passes over a
+    fixed-ray run."""
+    if Ubar is None:
+        Ubar = np.zeros((model.nl, model.n))
     Ubar = np.ascontiguousarray(Ubar, dtype=np.float64).reshape(model.nl, model.n)
+    Eb = None if Ebar is None else np.ascontiguousarray(Ebar, dtype=np.float64).reshape(model.nl, -1)
     rho_bar = np.zeros(model.n)
     passes = [r for r in run_result.passes]
     pend = [None] + [passes[k - 1].S for k in range(1, len(passes))]   # emission of pass k
@@ -304,6 +314,7 @@ def adjoint(model: Model, policy, run_result, Ubar, Sbar_last=None, frame=None, 
         Sp = None if pend[k] is None else np.ascontiguousarray(pend[k], dtype=np.float64)
         rc = lib().orc_adjoint_pass(model.h, C.byref(o), None if Sp is None else _p(Sp, C.c_double),
                                     _p(Ubar, C.c_double), None if Sbar is None else _p(Sbar, C.c_double),
+                                    None if Eb is None else _p(Eb, C.c_double),
                                     _p(rho_bar, C.c_double), _p(Sbar_k, C.c_double))
         if rc != 0:
             raise ValueError(f"oracle adjoint failed (status {rc})")
@@ -317,6 +328,7 @@ class PassResult:
     S: np.ndarray          # [S size]
     tally: np.ndarray      # [nl, 8]
     counters: np.ndarray   # [8]
+    escape: np.ndarray     # [nl, 12 nside^2] escaping luminosity by launch pixel
 
 
 @dataclass
@@ -326,6 +338,7 @@ class RunResult:
     S_total: np.ndarray    # all scattering orders, S_1 .. S_{K+1}
     S_pending: np.ndarray  # last, unprocessed order
     passes: list           # PassResult per pass (step 1 first when present)
+    escape: np.ndarray     # escaping luminosity summed over the passes after step 1
 
 
 def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_init=None,
@@ -351,6 +364,7 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
     U = np.zeros((model.nl, model.n))
     S_total = np.zeros(model.s_size)
     S_pending = None
+    escape = np.zeros((model.nl, 12 * int(policy.nside) ** 2))
     for k in range(n_pass):
         mode = DIRECT if k == 0 else SCATTER
         r = model.run_pass(mode, policy, S_pending=S_pending, U_LL=U_LL, frame=frame,
@@ -359,6 +373,7 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
         U += r.U
         S_total += r.S
         S_pending = r.S
+        escape += r.escape
         if policy.adaptive:
             U_LL = U.copy()
-    return RunResult(U=U, U_LL=U_LL, S_total=S_total, S_pending=S_pending, passes=results)
+    return RunResult(U=U, U_LL=U_LL, S_total=S_total, S_pending=S_pending, passes=results, escape=escape)

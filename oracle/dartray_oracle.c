@@ -456,6 +456,8 @@ typedef struct {
     orc_ray *stack;
     double *lbuf;
     int64_t cap;
+    double *esc;        /* [n_lambda][nray0] escaping luminosity per launch pixel, or NULL */
+    int64_t nray0;
 } orc_thread;
 
 static inline void orc_add(double *p, double v, int atomic)
@@ -616,13 +618,20 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
     }
     for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_ESCAPED] += L[l];
     th->count[C_ESCAPES]++;
+    if (th->esc) {
+        /* attributed to the launch pixel the ray descends from */
+        int64_t top = ray->pix >> (2 * ray->level);
+        for (int l = 0; l < nl; ++l) th->esc[(int64_t)l * th->nray0 + top] += L[l];
+    }
 }
 
 /* Run one pass.  Outputs (overwritten): U_k [n_lambda][n], S_next [S size]
- * (untouched in step 1), tally [n_lambda][8], counters [8].  Inputs: S_pending
+ * (untouched in step 1), tally [n_lambda][8], counters [8], and escape
+ * [n_lambda][12 nside^2] when not NULL: the luminosity leaving the root block,
+ * by the launch pixel of the ray (the initial Nside).  Inputs: S_pending
  * (scatter pass), U_LL (adaptive direct/scatter passes). */
 int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pending, const double *U_LL,
-                 double *U_k, double *S_next, double *tally, int64_t *counters)
+                 double *U_k, double *S_next, double *tally, int64_t *counters, double *escape)
 {
     const orc_grid_desc *d = &m->d;
     const int nl = d->n_lambda;
@@ -644,6 +653,7 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     int levels = 0;
     if (o->adaptive) while (((int64_t)o->nside << levels) < o->nside_max) ++levels;
     int64_t nray0 = 12 * (int64_t)o->nside * o->nside;
+    if (escape) memset(escape, 0, sizeof(double) * (size_t)(nl * nray0));
     int failed = 0;
     /* j_sca pixel centre vectors, one block per wavelength (rotated frame) */
     double *pv = (double *)malloc(sizeof(double) * 3 * (size_t)(wsize > 0 ? wsize : 1));
@@ -667,7 +677,9 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
         th.cap = 3 * (int64_t)levels + 8;
         th.stack = (orc_ray *)malloc(sizeof(orc_ray) * (size_t)th.cap);
         th.lbuf = (double *)malloc(sizeof(double) * (size_t)(th.cap * nl));
-        int ok = th.w && th.stack && th.lbuf && th.U && (o->mode == ORC_STEP1 || th.S);
+        th.nray0 = nray0;
+        th.esc = escape ? (double *)calloc((size_t)(nl * nray0), sizeof(double)) : NULL;
+        int ok = th.w && th.stack && th.lbuf && th.U && (o->mode == ORC_STEP1 || th.S) && (!escape || th.esc);
         if (!ok) {
 #pragma omp atomic write
             failed = 1;
@@ -729,6 +741,8 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
                 }
                 for (int i = 0; i < nl * N_TALLY; ++i) tally[i] += th.tally[i];
                 for (int i = 0; i < N_COUNT; ++i) counters[i] += th.count[i];
+                if (escape)
+                    for (int64_t i = 0; i < nl * nray0; ++i) escape[i] += th.esc[i];
             }
         }
         if (!atomic) {
@@ -738,6 +752,7 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
         free(th.w);
         free(th.stack);
         free(th.lbuf);
+        free(th.esc);
     }
     free(pv);
     return failed ? ORC_E_OOM : ORC_OK;
@@ -752,7 +767,9 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
 /*   a_m(tau) = l_m E(tau) Ubar(c_m) / (V c) + albedo (1 - e^{-tau}) sbar_m,    */
 /*   E(tau) = (1 - e^{-tau}) / tau,  sbar_m = sum_p w(p|n) Sbar_next(c_m, p),   */
 /* where Ubar = dJ/dU and Sbar_next = dJ/dS of the luminosity this pass        */
-/* scatters.  With G_m = a_m + e^{-tau_m} G_{m+1} (G_M = 0):                   */
+/* scatters.  A loss on the escaping luminosity adds L_M Ebar(r) for the ray's */
+/* pixel r, L_M being what leaves the block.  With                             */
+/* G_m = a_m + e^{-tau_m} G_{m+1} and G_M = Ebar(r) (zero without that loss):  */
 /*   dJ/dtau_m = L_m (a_m'(tau_m) - e^{-tau_m} G_{m+1}),                       */
 /*   dJ/drho_c += kappa l_m dJ/dtau_m over the crossings in c,                 */
 /*   dJ/dL_0 = G_0, which for a scattering pass flows to the pending           */
@@ -771,11 +788,12 @@ static void orc_E(double tau, double *E, double *dE)
     }
 }
 
-/* Ubar [n_lambda][n]; Sbar_next [S size] or NULL (zero); S_pending: the
- * pass's emission (scattering pass) or NULL (direct pass); rho_bar [n] is
- * accumulated; Sbar_k [S size] is overwritten for scattering passes. */
+/* Ubar [n_lambda][n]; Sbar_next [S size] or NULL (zero); Ebar
+ * [n_lambda][12 nside^2] or NULL (zero); S_pending: the pass's emission
+ * (scattering pass) or NULL (direct pass); rho_bar [n] is accumulated; Sbar_k
+ * [S size] is overwritten for scattering passes. */
 int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pending, const double *Ubar,
-                     const double *Sbar_next, double *rho_bar, double *Sbar_k)
+                     const double *Sbar_next, const double *Ebar, double *rho_bar, double *Sbar_k)
 {
     const orc_grid_desc *d = &m->d;
     const int nl = d->n_lambda;
@@ -832,8 +850,8 @@ int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S
                             Lm[k] = L;
                             if (lens[k] > 1e-6 * (m->side[c] + te)) L *= exp(-kap * d->rho[c] * lens[k]);
                         }
-                        /* backward suffix recursion */
-                        double G = 0.0;
+                        /* backward suffix recursion from the escaping end */
+                        double G = Ebar ? Ebar[(int64_t)l * nray + r] : 0.0;
                         for (int64_t k = nc - 1; k >= 0; --k) {
                             int64_t c = cells[k];
                             double len = lens[k], te = tins[k] + len;

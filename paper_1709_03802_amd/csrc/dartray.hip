@@ -468,6 +468,7 @@ struct FixedArgs {
     float *ubar;                 // [nb][n][n_lambda] direction-binned energy density
     double *tally;
     uint64_t *counters;          // null: this launch does not count
+    double *esc_dir;             // [n_lambda][nray] escape by direction, or null
     int64_t n;
     int32_t scatter;
     int32_t r0;
@@ -516,6 +517,7 @@ struct FixedStage {
     uint8_t list[256];
     float kap[4][NL];
     double esc[4][NL];
+    double edir[4][NL];          // this item's escape (one direction per item)
 };
 
 __device__ inline void wave_sync_lds()
@@ -629,7 +631,10 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
             if (!active) {
 #pragma unroll
                 for (int l = 0; l < NL; ++l)
-                    if (l < nlc && L[l] != 0.f) atomicAdd(&st.esc[w][l], (double)L[l]);
+                    if (l < nlc && L[l] != 0.f) {
+                        atomicAdd(&st.esc[w][l], (double)L[l]);
+                        if (A.esc_dir) atomicAdd(&st.edir[w][l], (double)L[l]);
+                    }
             }
         }
         // lanes q of an instruction add value q % NL of the (q / NL)-th
@@ -650,6 +655,17 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
             }
             wave_sync_lds();
         }
+    }
+    if (A.esc_dir) {
+        // all rays of the item share direction r: one FP64 add per wavelength
+        wave_sync_lds();
+        if (lane < NL) {
+            const double v = st.edir[w][lane];
+            if (lane < nlc && v != 0.0)
+                atomic_add_f64(A.esc_dir + (int64_t)(l0 + lane) * (12 << (2 * A.log2_nside_ray)) + r, v);
+            st.edir[w][lane] = 0.0;
+        }
+        wave_sync_lds();
     }
 }
 
@@ -703,7 +719,10 @@ __global__ __launch_bounds__(256) void k_march_fixed(const FixedArgs A)
     const int64_t nitems = ntiles * A.nb;
     FixedAcc<NL> acc;
     acc.clear();
-    if ((threadIdx.x & 63) < NL) st.esc[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
+    if ((threadIdx.x & 63) < NL) {
+        st.esc[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
+        st.edir[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
+    }
     for (int64_t it = wid; it < nitems; it += nw) {
         int64_t tile;
         int rl;
@@ -734,7 +753,10 @@ __global__ __launch_bounds__(256) void k_march_fixed_multi(const BatchMarch B)
     const int64_t nitems = B.item_off[B.n_models];
     FixedAcc<NL> acc;
     acc.clear();
-    if ((threadIdx.x & 63) < NL) st.esc[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
+    if ((threadIdx.x & 63) < NL) {
+        st.esc[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
+        st.edir[threadIdx.x >> 6][threadIdx.x & 63] = 0.0;
+    }
     int mcur = -1;
     FixedArgs A{};
     int nsrc = 0;
@@ -1590,6 +1612,7 @@ struct AdjArgs {
     const float *sig;            // sbar per (wavelength, direction, cell), or null
     double *rho_bar;
     float *sbar_k;               // dJ/dS of the pass's emission (scattering pass)
+    const float *ebar;           // dJ/dF [n_lambda][nray] of the escaping luminosity, or null
     int64_t n;
     int32_t scatter;
     int32_t r0;
@@ -1733,6 +1756,13 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
                 if (++steps >= A.hard_cap) break;
                 c = nx;
             }
+            if (walk == 0 && A.ebar) {
+                // loss on the escaping luminosity: the terminal value of the recursion
+                const int64_t nray = (int64_t)12 << (2 * A.log2_nside_ray);
+#pragma unroll
+                for (int l = 0; l < NL; ++l)
+                    if (l < nl) G[l] += (double)ell[l] * (double)A.ebar[(int64_t)l * nray + r];
+            }
         }
         if (A.scatter) {
 #pragma unroll
@@ -1752,6 +1782,12 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
             }
         }
     }
+}
+
+__global__ void k_to_f32(const double *a, float *out, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)a[i];
 }
 
 __global__ void k_rho_out(const double *rb, float *out, int64_t n)
@@ -1887,7 +1923,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
+    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
                     g.flags, g.cell_flag, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -2112,7 +2148,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, bin_budget / (4 * per_dir)));
     int rcs[] = {
         dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
-        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n),
+        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n), dalloc(g, &g.esc64, (size_t)nl * 12 * kMaxNsideWTable * kMaxNsideWTable),
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
         dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.d_lt, 1),
@@ -2357,6 +2393,7 @@ static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_
         if (!(o->f_U >= 0.f) && !(o->a_RT > 0.f)) return fail(DARTRAY_E_INVALID, "f_U must be >= 0, or a_RT > 0");
         if (g.n_lambda > 16) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays carry at most 16 wavelengths");
     }
+    if (f->escape && o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "escape by direction covers fixed rays only");
     if ((f->counters == nullptr) && (o->flags & DARTRAY_FLAG_COUNTERS))
         return fail(DARTRAY_E_INVALID, "counters buffer required by DARTRAY_FLAG_COUNTERS");
     if (scatter && !g.have_s1) return fail(DARTRAY_E_STATE, "scatter_iter needs a prior direct pass");
@@ -2510,6 +2547,7 @@ static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields
     A.ubar = g.ubar;
     A.tally = f->tally;
     A.counters = (o->flags & DARTRAY_FLAG_COUNTERS) ? f->counters : nullptr;
+    A.esc_dir = f->escape ? g.esc64 : nullptr;
     A.n = g.n;
     A.scatter = scatter ? 1 : 0;
     A.order = g.tune.item_order;
@@ -2612,6 +2650,7 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
     if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
     if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
+    if (f->escape && (rc = fill<double>(g, g.esc64, (size_t)nl * nray, 0.0))) return rc;
     if ((rc = select_sources(g, o, f, scatter))) return rc;
 
     const size_t per_dir = (size_t)nl * n;
@@ -2789,6 +2828,11 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
                        g.stream, g.U_k, f->U, f->U_pass, f->U_LL, o->adaptive ? 1 : 0, step1 ? 1 : 0, g.d_lt, g.rho,
                        g.inv_vc, n, f->tally);
     DR_LAUNCH_CHECK("k_finish_u");
+    if (f->escape && !o->adaptive) {
+        const int64_t ne = (int64_t)nl * 12 * o->nside * o->nside;
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, g.stream, g.esc64, f->escape, ne);
+        DR_LAUNCH_CHECK("k_to_f32");
+    }
     if (step1) return DARTRAY_OK;
     int rc;
     double *ssum = g.dsum;
@@ -2844,11 +2888,11 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
 }
 
 int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, int32_t n_scatter,
-                          const float *const *S_hist, const float *dJ_dU, float *dJ_drho)
+                          const float *const *S_hist, const float *dJ_dU, const float *dJ_desc, float *dJ_drho)
 {
     if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
     Grid &g = grid->g;
-    if (!opts || !dJ_dU || !dJ_drho || n_scatter < 0 || (n_scatter > 0 && !S_hist))
+    if (!opts || !dJ_drho || n_scatter < 0 || (n_scatter > 0 && !S_hist))
         return fail(DARTRAY_E_INVALID, "bad argument");
     for (int k = 0; k < n_scatter; ++k)
         if (!S_hist[k]) return fail(DARTRAY_E_INVALID, "null S_hist entry");
@@ -2867,9 +2911,13 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     int log2n = 0;
     while ((1 << log2n) < opts->nside) ++log2n;
     if ((rc = fill<double>(g, g.rho_bar, (size_t)n, 0.0))) return rc;
-    hipLaunchKernelGGL(k_transpose_ull, dim3((unsigned)std::min<int64_t>((n * nl + 255) / 256, 8192)), dim3(256), 0,
-                       g.stream, dJ_dU, g.ull_t, n, nl);
-    DR_LAUNCH_CHECK("k_transpose_ull");
+    if (dJ_dU) {
+        hipLaunchKernelGGL(k_transpose_ull, dim3((unsigned)std::min<int64_t>((n * nl + 255) / 256, 8192)), dim3(256), 0,
+                           g.stream, dJ_dU, g.ull_t, n, nl);
+        DR_LAUNCH_CHECK("k_transpose_ull");
+    } else if ((rc = fill<float>(g, g.ull_t, (size_t)n * nl, 0.f))) {
+        return rc;
+    }
     const size_t per_dir = (size_t)nl * n;
     const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
     AdjArgs A{};
@@ -2882,6 +2930,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     A.lt = g.d_lt;
     A.ubar_t = g.ull_t;
     A.rho_bar = g.rho_bar;
+    A.ebar = dJ_desc;
     A.n = n;
     A.log2_nside_ray = log2n;
     A.inv_nray = (float)(1.0 / (double)nray);
@@ -3063,6 +3112,7 @@ static int batch_sequence(dartray_batch *b, const dartray_trace_opts *o, dartray
             if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
             if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
             if (counting && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
+            if (f->escape && (rc = fill<double>(g, g.esc64, (size_t)nl * nray, 0.0))) return rc;
             if ((rc = select_sources(g, o, f, scatter))) return rc;
         }
         const FixedArgs *args = b->d_args + (scatter ? nm : 0);

@@ -121,6 +121,8 @@ struct Grid {
     int32_t key_bits = 1;
     int64_t log_chunks = 0;               // launches of the last adaptive pass
 
+    double *esc64 = nullptr;              // [nl][12 * 16^2] FP64 escape by direction (fixed rays)
+
     // adjoint work arrays
     double *rho_bar = nullptr;            // [n] FP64 accumulator of dJ/drho
     float *sbar[2] = {nullptr, nullptr};  // [s_size] dJ/dS of consecutive orders

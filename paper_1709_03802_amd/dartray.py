@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import Optional
 
 import numpy as np
@@ -98,6 +98,7 @@ class FieldsC(C.Structure):
         ("S_next", C.c_void_p),
         ("tally", C.c_void_p),
         ("counters", C.c_void_p),
+        ("escape", C.c_void_p),
     ]
 
 
@@ -137,7 +138,7 @@ def load_library():
     L.dartray_trace_direct.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC)]
     L.dartray_scatter_iter.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.POINTER(C.c_double)]
     L.dartray_trace_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.c_int32, C.POINTER(C.c_void_p),
-                                        C.c_void_p, C.c_void_p]
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
     L.dartray_debug_ray_cells.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                           C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_float),
                                           C.POINTER(C.c_int32)]
@@ -280,7 +281,9 @@ class Grid:
 class Fields:
     """Caller-owned device buffers (torch tensors) of one run."""
 
-    def __init__(self, grid: Grid, keep_pass_u=False):
+    def __init__(self, grid: Grid, keep_pass_u=False, escape_nside=None):
+        """escape_nside: allocate the per-direction escape output of fixed-ray
+        passes with that ray Nside."""
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         f32 = dict(dtype=torch.float32, device=dev)
@@ -292,10 +295,11 @@ class Fields:
         self.S_next = torch.zeros(max(grid.s_size, 1), **f32)
         self.tally = torch.zeros((grid.nl, 8), dtype=torch.float64, device=dev)
         self.counters = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.escape = (torch.zeros((grid.nl, 12 * escape_nside ** 2), **f32) if escape_nside else None)
 
     def c(self) -> FieldsC:
         f = FieldsC()
-        for name in ("U", "U_LL", "U_pass", "S_total", "S_pending", "S_next", "tally", "counters"):
+        for name in ("U", "U_LL", "U_pass", "S_total", "S_pending", "S_next", "tally", "counters", "escape"):
             t = getattr(self, name)
             setattr(f, name, None if t is None else t.data_ptr())
         return f
@@ -379,44 +383,53 @@ def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields, want_rk=True):
     return rk.value
 
 
-def trace_adjoint(grid: Grid, opts: TraceOpts, S_hist, dJ_dU, dJ_drho):
-    """dJ/drho into dJ_drho (device float [n]) for dJ_dU (device [nl, n]).
+def trace_adjoint(grid: Grid, opts: TraceOpts, S_hist, dJ_dU, dJ_drho, dJ_desc=None):
+    """dJ/drho into dJ_drho (device float [n]) for dJ_dU (device [nl, n] or
+    None) and dJ_desc (device [nl, 12 nside^2] or None: the derivative with
+    respect to the escaping luminosity summed over the passes).
 
     S_hist: the S_pending tensors each scattering iteration of the forward run
     processed, in order (``DartRayFn`` keeps them)."""
     arr = (C.c_void_p * max(len(S_hist), 1))(*[t.data_ptr() for t in S_hist])
     _check(load_library().dartray_trace_adjoint(grid.h, C.byref(opts), len(S_hist), arr,
-                                                C.c_void_p(dJ_dU.data_ptr()), C.c_void_p(dJ_drho.data_ptr())))
+                                                None if dJ_dU is None else C.c_void_p(dJ_dU.data_ptr()),
+                                                None if dJ_desc is None else C.c_void_p(dJ_desc.data_ptr()),
+                                                C.c_void_p(dJ_drho.data_ptr())))
 
 
 def _autograd():
     import torch
 
     class DartRayFn(torch.autograd.Function):
-        """rho (device float [n]) -> U (device float [n_lambda, n]) for a fixed-ray
-        run (direct pass + policy.n_scatter scattering iterations); backward
-        by the adjoint march."""
+        """rho (device float [n]) -> (U [n_lambda, n], F [n_lambda, 12 nside^2])
+        for a fixed-ray run (direct pass + policy.n_scatter scattering
+        iterations), F being the escaping luminosity by direction summed over
+        the passes; backward by the adjoint march."""
 
         @staticmethod
         def forward(ctx, rho, grid, policy, frame=None):
             grid.set_rho(rho.detach().contiguous())
-            f = Fields(grid)
+            f = Fields(grid, escape_nside=policy.nside)
             opts = make_opts(policy, MODE_DIRECT, frame, counters=False)
             trace_direct(grid, opts, f)
+            F = f.escape.clone()
             hist = []
             for _ in range(policy.n_scatter):
                 hist.append(f.S_pending.clone())
-                scatter_iter(grid, opts, f)
+                scatter_iter(grid, opts, f, want_rk=False)
+                F += f.escape
             ctx.grid, ctx.opts, ctx.hist = grid, opts, hist
             ctx.save_for_backward(rho)
-            return f.U.clone()
+            return f.U.clone(), F
 
         @staticmethod
-        def backward(ctx, gU):
+        def backward(ctx, gU, gF):
             (rho,) = ctx.saved_tensors
             ctx.grid.set_rho(rho.detach().contiguous())
             drho = torch.empty_like(rho)
-            trace_adjoint(ctx.grid, ctx.opts, ctx.hist, gU.contiguous().to(torch.float32), drho)
+            gU = None if gU is None else gU.contiguous().to(torch.float32)
+            gF = None if gF is None else gF.contiguous().to(torch.float32)
+            trace_adjoint(ctx.grid, ctx.opts, ctx.hist, gU, drho, dJ_desc=gF)
             return drho, None, None, None
 
     return DartRayFn
@@ -425,12 +438,18 @@ def _autograd():
 _fn = None
 
 
-def rfed(rho, grid: Grid, policy, frame=None):
-    """Differentiable energy density U(rho) (see ``DartRayFn``)."""
+def rfed_escape(rho, grid: Grid, policy, frame=None):
+    """Differentiable (U(rho), F(rho)): energy density and escaping luminosity
+    by direction (see ``DartRayFn``)."""
     global _fn
     if _fn is None:
         _fn = _autograd()
     return _fn.apply(rho, grid, policy, frame)
+
+
+def rfed(rho, grid: Grid, policy, frame=None):
+    """Differentiable energy density U(rho)."""
+    return rfed_escape(rho, grid, policy, frame)[0]
 
 
 def debug_ray_cells(grid: Grid, origins, dirs, max_cross=4096):
@@ -452,13 +471,18 @@ class RunOutput:
     tallies: list            # per pass, numpy [nl, 8]
     counters: list           # per pass, numpy [8]
     r_k: list
+    escape: list = field(default_factory=list)   # per pass after step 1, [nl, 12 nside^2] (fixed rays)
 
 
 def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Fields] = None,
-        collect=True, passes=None) -> RunOutput:
-    """Step 1 (adaptive + step1), direct pass, scattering iterations."""
-    f = Fields(grid) if fields is None else fields
-    tallies, counters, rks = [], [], []
+        collect=True, passes=None, escape=False) -> RunOutput:
+    """Step 1 (adaptive + step1), direct pass, scattering iterations.  With
+    ``escape`` (fixed rays) the new Fields carry the per-direction escape."""
+    if fields is None:
+        f = Fields(grid, escape_nside=policy.nside if escape and not policy.adaptive else None)
+    else:
+        f = fields
+    tallies, counters, rks, escapes = [], [], [], []
     if policy.adaptive and policy.step1:
         trace_direct(grid, make_opts(policy, MODE_STEP1, frame, source_mask), f)
         if collect:
@@ -475,4 +499,6 @@ def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Field
         if collect:
             tallies.append(f.tally.cpu().numpy().copy())
             counters.append(f.counters.cpu().numpy().copy())
-    return RunOutput(f, tallies, counters, rks)
+            if f.escape is not None and not policy.adaptive:
+                escapes.append(f.escape.cpu().numpy().copy())
+    return RunOutput(f, tallies, counters, rks, escapes)

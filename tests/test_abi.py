@@ -53,7 +53,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(dartray_grid_desc), sizeof(dartray_trace_opts), sizeof(dartray_fields), sizeof(dartray_tuning));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(dartray_grid_desc, c_light), offsetof(dartray_grid_desc, nside_max), offsetof(dartray_trace_opts, frame),
          offsetof(dartray_trace_opts, max_steps), offsetof(dartray_fields, counters));
-  printf("%zu\\n", offsetof(dartray_tuning, item_order));
+  printf("%zu %zu\\n", offsetof(dartray_tuning, item_order), offsetof(dartray_fields, escape));
   return 0;
 }
 """)
@@ -63,7 +63,7 @@ int main(void) {
     got = [int(x) for x in out]
     want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC), C.sizeof(dartray.Tuning),
             dartray.GridDesc.c_light.offset, dartray.GridDesc.nside_max.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
-            dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset]
+            dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset, dartray.FieldsC.escape.offset]
     assert got == want
 
 

@@ -96,6 +96,36 @@ def test_gradient_plain16_four_wavelengths(dr, orc):
     assert err <= 1e-4
 
 
+def test_escape_loss_gradient_vs_oracle(dr, orc):
+    """Loss on the escaping luminosity by direction plus the energy-density
+    loss, 16^3 x 4 wavelengths: GPU autograd against the oracle adjoint."""
+    import torch
+    wl = W.by_name("plain16_l4")
+    grid = as_f32(wl.grid)
+    t = grid.copy()
+    t.rho = W.perturbed_rho(grid.rho, 0.3, seed=3802)
+    rt = orc.run(orc.Model(t), wl.policy)
+    m = orc.Model(grid)
+    r = orc.run(m, wl.policy)
+    dF = np.log(r.escape) - np.log(rt.escape)
+    dU = np.log(r.U) - np.log(rt.U)
+    Jo = float(np.sum(dF * dF) + 0.1 * np.sum(dU * dU))
+    go = orc.adjoint(m, wl.policy, r, 0.2 * dU / r.U, Ebar=2 * dF / r.escape)
+    G = dr.Grid(grid)
+    rho = torch.tensor(grid.rho, dtype=torch.float32, device="cuda", requires_grad=True)
+    U, F = dr.rfed_escape(rho, G, wl.policy)
+    Fs = torch.tensor(rt.escape, dtype=torch.float32, device="cuda")
+    Us = torch.tensor(rt.U, dtype=torch.float32, device="cuda")
+    J = ((torch.log(F) - torch.log(Fs)) ** 2).sum() + 0.1 * ((torch.log(U) - torch.log(Us)) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    gg = rho.grad.cpu().numpy().astype(np.float64)
+    err = np.abs(gg - go).max() / np.abs(go).max()
+    print(f"escape + U loss: J gpu {float(J):.6g} oracle {Jo:.6g}; max |g - g_oracle| / max |g| = {err:.3g}", flush=True)
+    assert float(J) == pytest.approx(Jo, rel=1e-4)
+    assert err <= 1e-4
+
+
 def test_adjoint_rejects_adaptive(dr):
     import torch
     wl = W.disk_tiny()
@@ -104,6 +134,9 @@ def test_adjoint_rejects_adaptive(dr):
     out = torch.zeros(G.n, device="cuda")
     with pytest.raises(dr.DartRayError) as e:
         dr.trace_adjoint(G, dr.make_opts(wl.policy), [], gU, out)
+    assert e.value.code == dr.E_UNSUPPORTED
+    with pytest.raises(dr.DartRayError) as e:
+        dr.trace_adjoint(G, dr.make_opts(wl.policy), [], None, out, dJ_desc=None)
     assert e.value.code == dr.E_UNSUPPORTED
 
 

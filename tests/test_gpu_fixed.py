@@ -254,3 +254,30 @@ def test_32_wavelengths_one_march_equals_per_wavelength_marches(dr, orc):
         eu = rel_err(U[l], ref.U[k]).max()
         es = rel_err(S[off[l]:off[l + 1]], ref.S_total[m.s_offset[k]:m.s_offset[k + 1]]).max()
         assert eu <= TOL and es <= TOL, (l, eu, es)
+
+
+def test_escape_by_direction_every_pass(dr, orc):
+    """The luminosity leaving the grid by ray direction, per pass, against the
+    oracle (1e-4), and its sum against the FP64 escaped tally."""
+    import torch
+    wl = W.by_name("plain16_l4")
+    g32 = as_f32(wl.grid)
+    ref = orc.run(orc.Model(g32), wl.policy)
+    G = dr.Grid(g32)
+    out = dr.run(G, wl.policy, escape=True)
+    torch.cuda.synchronize()
+    assert len(out.escape) == len(ref.passes)
+    for k, (e, r) in enumerate(zip(out.escape, ref.passes)):
+        err = rel_err(e, r.escape).max()
+        print(f"pass {k}: escape by direction max rel {err:.3g}", flush=True)
+        assert err <= TOL
+        np.testing.assert_allclose(e.astype(np.float64).sum(axis=1), out.tallies[k][:, dr.T_ESCAPED], rtol=1e-5)
+
+
+def test_escape_rejected_for_adaptive_rays(dr):
+    wl = W.disk_tiny()
+    G = dr.Grid(wl.grid)
+    f = dr.Fields(G, escape_nside=wl.policy.nside)
+    with pytest.raises(dr.DartRayError) as e:
+        dr.trace_direct(G, dr.make_opts(wl.policy, dr.MODE_STEP1), f)
+    assert e.value.code == dr.E_UNSUPPORTED

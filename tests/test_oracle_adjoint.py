@@ -80,3 +80,41 @@ def test_adjoint_zero_at_target(orc):
     J, Ubar = loss_and_ubar(r.U, r.U)
     assert J == 0.0
     assert np.all(orc.adjoint(m, pol, r, Ubar) == 0.0)
+
+
+def escape_loss(run, Fstar):
+    d = np.log(run.escape) - np.log(Fstar)
+    return float(np.sum(d * d)), 2.0 * d / run.escape
+
+
+@pytest.mark.parametrize("n,nside,n_scatter", [(3, 2, 1), (4, 1, 2)])
+def test_escape_loss_adjoint_matches_central_differences(orc, n, nside, n_scatter):
+    """A loss on the escaping luminosity by direction, alone and together with
+    the energy-density loss, against central differences on every cell."""
+    grid, pol = setup(n, nside, [0.3, 1.0], n_scatter, seed=3)
+    target = grid.copy()
+    target.rho = W.perturbed_rho(grid.rho, 0.3, seed=3802)
+    _, rt = forward(orc, target, pol)
+    m, r = forward(orc, grid, pol)
+    _, Ebar = escape_loss(r, rt.escape)
+    _, Ubar = loss_and_ubar(r.U, rt.U)
+    g_e = orc.adjoint(m, pol, r, None, Ebar=Ebar)
+    g_both = orc.adjoint(m, pol, r, Ubar, Ebar=Ebar)
+    g_u = orc.adjoint(m, pol, r, Ubar)
+    np.testing.assert_allclose(g_both, g_e + g_u, rtol=1e-12, atol=1e-15 * np.abs(g_both).max())
+
+    def J(rho):
+        g = grid.copy()
+        g.rho = rho
+        _, rr = forward(orc, g, pol)
+        return escape_loss(rr, rt.escape)[0]
+
+    fd = np.zeros(grid.n)
+    for c in range(grid.n):
+        h = 1e-5 * grid.rho[c]
+        rp = grid.rho.copy()
+        rp[c] += h
+        rm = grid.rho.copy()
+        rm[c] -= h
+        fd[c] = (J(rp) - J(rm)) / (2 * h)
+    np.testing.assert_allclose(g_e, fd, rtol=2e-5, atol=2e-6 * np.abs(fd).max())

@@ -218,3 +218,38 @@ def test_rotated_frame_preserves_totals(orc):
     assert t1[orc.T_EMITTED] == pytest.approx(t0[orc.T_EMITTED], rel=1e-14)
     assert t1[orc.T_ABSORBED] + t1[orc.T_SCATTERED] + t1[orc.T_ESCAPED] == pytest.approx(t1[orc.T_EMITTED], rel=1e-12)
     assert abs(t1[orc.T_ESCAPED] / t0[orc.T_ESCAPED] - 1) < 0.05
+
+
+def test_escape_by_direction_closed_form(orc):
+    """Escaping luminosity per launch pixel: L0 exp(-kappa rho d(n)) with d
+    the source-to-boundary distance along n, for every pixel."""
+    n, kr = 8, 3.0
+    grid = uniform_grid(n, rho=kr)
+    m = orc.Model(grid)
+    s = (3 * n + 2) * n + 5
+    r = m.run_pass(orc.DIRECT, FIXED4, source_mask=one_source(grid, s))
+    o = grid.centres()[s]
+    L0 = 4 * math.pi * 1.0 * (1 / n) ** 3 / 192
+    want = np.array([L0 * math.exp(-kr * exit_dist(o, d)) for d in ray_dirs(orc, 4)])
+    np.testing.assert_allclose(r.escape[0], want, rtol=1e-12)
+    assert r.escape[0].sum() == pytest.approx(r.tally[0, orc.T_ESCAPED], rel=1e-13)
+
+
+def test_escape_transparent_medium_and_sums(orc):
+    """With no dust every ray leaves with its launch luminosity; in general the
+    escape summed over pixels is the escaped tally, for fixed and adaptive
+    rays (children attributed to their launch pixel) and scattering passes."""
+    grid = uniform_grid(5, rho=0.0)
+    m = orc.Model(grid)
+    r = m.run_pass(orc.DIRECT, FIXED4)
+    tot = r.tally[0, orc.T_EMITTED]
+    np.testing.assert_allclose(r.escape[0], tot / 192, rtol=1e-12)
+    wl = W.plain16(n=6, nside=2, lambdas=np.array([0.2, 1.0]), n_scatter=2)
+    run = orc.run(orc.Model(wl.grid), wl.policy)
+    for p in run.passes:
+        np.testing.assert_allclose(p.escape.sum(axis=1), p.tally[:, orc.T_ESCAPED], rtol=1e-12)
+    np.testing.assert_allclose(run.escape, sum(p.escape for p in run.passes), rtol=1e-14)
+    ad = W.disk_tiny()
+    mm = orc.Model(ad.grid)
+    rp = mm.run_pass(orc.STEP1, ad.policy)
+    np.testing.assert_allclose(rp.escape.sum(axis=1), rp.tally[:, orc.T_ESCAPED], rtol=1e-12, atol=1e-300)
