@@ -339,6 +339,7 @@ class RunResult:
     S_pending: np.ndarray  # last, unprocessed order
     passes: list           # PassResult per pass (step 1 first when present)
     escape: np.ndarray     # escaping luminosity summed over the passes after step 1
+    r_k: list              # per scattering iteration: sum S_next / sum S after the direct pass
 
 
 def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_init=None,
@@ -348,6 +349,8 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
     U_LL is the step-1 result, then the running U after every pass (the
     footnote of Sect. 2).  ``U_LL_init`` replaces step 1 by a given U_LL.
     ``passes`` limits the number of passes after step 1 (direct counts as 1).
+    With policy.f_L > 0 the iterations stop once the pending scattered
+    luminosity falls below f_L times the total scattered in the direct pass.
     """
     results = []
     U_LL = None
@@ -361,6 +364,8 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
         else:
             U_LL = np.zeros((model.nl, model.n))
     n_pass = 1 + policy.n_scatter if passes is None else passes
+    f_L = float(getattr(policy, "f_L", 0.0))
+    r_k = []
     U = np.zeros((model.nl, model.n))
     S_total = np.zeros(model.s_size)
     S_pending = None
@@ -376,4 +381,12 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
         escape += r.escape
         if policy.adaptive:
             U_LL = U.copy()
-    return RunResult(U=U, U_LL=U_LL, S_total=S_total, S_pending=S_pending, passes=results, escape=escape)
+        if k == 0:
+            s1 = float(np.sum(r.S))
+        else:
+            # pending scattered luminosity over the total scattered in the direct pass
+            r_k.append(float(np.sum(r.S)) / s1 if s1 > 0.0 else 0.0)
+            if f_L > 0.0 and r_k[-1] < f_L:
+                break
+    return RunResult(U=U, U_LL=U_LL, S_total=S_total, S_pending=S_pending, passes=results, escape=escape,
+                     r_k=r_k)

@@ -476,7 +476,8 @@ class RunOutput:
 
 def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Fields] = None,
         collect=True, passes=None, escape=False) -> RunOutput:
-    """Step 1 (adaptive + step1), direct pass, scattering iterations.  With
+    """Step 1 (adaptive + step1), direct pass, scattering iterations (at most
+    policy.n_scatter; with policy.f_L > 0 they stop once r_k < f_L).  With
     ``escape`` (fixed rays) the new Fields carry the per-direction escape."""
     if fields is None:
         f = Fields(grid, escape_nside=policy.nside if escape and not policy.adaptive else None)
@@ -489,16 +490,19 @@ def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Field
             tallies.append(f.tally.cpu().numpy().copy())
             counters.append(f.counters.cpu().numpy().copy())
     n_pass = 1 + policy.n_scatter if passes is None else passes
+    f_L = float(getattr(policy, "f_L", 0.0))
     for k in range(n_pass):
         if k == 0:
             trace_direct(grid, make_opts(policy, MODE_DIRECT, frame, source_mask), f)
         else:
-            rk = scatter_iter(grid, make_opts(policy, MODE_DIRECT, frame), f, want_rk=collect)
-            if collect:
+            rk = scatter_iter(grid, make_opts(policy, MODE_DIRECT, frame), f, want_rk=collect or f_L > 0.0)
+            if rk is not None:
                 rks.append(rk)
         if collect:
             tallies.append(f.tally.cpu().numpy().copy())
             counters.append(f.counters.cpu().numpy().copy())
             if f.escape is not None and not policy.adaptive:
                 escapes.append(f.escape.cpu().numpy().copy())
+        if k > 0 and f_L > 0.0 and rks[-1] < f_L:
+            break   # convergence test of the scattering iterations (Sect. 2)
     return RunOutput(f, tallies, counters, rks, escapes)

@@ -112,7 +112,10 @@ class RayPolicy:
     f_U: float = 0.0            # adaptive: blocking threshold of Eq. 1
     r_pre: float = 0.0          # adaptive: step-1 extent
     step1: bool = False         # run step 1 (lower-limit RFED) first
-    n_scatter: int = 2          # scattering iterations after the direct pass
+    n_scatter: int = 2          # scattering iterations after the direct pass (the most run)
+    f_L: float = 0.0            # stop once the pending scattered luminosity is below f_L
+                                # times the total scattered in the direct pass (Sect. 2);
+                                # 0 runs all n_scatter iterations
 
 
 @dataclasses.dataclass

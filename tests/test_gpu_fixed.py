@@ -281,3 +281,22 @@ def test_escape_rejected_for_adaptive_rays(dr):
     with pytest.raises(dr.DartRayError) as e:
         dr.trace_direct(G, dr.make_opts(wl.policy, dr.MODE_STEP1), f)
     assert e.value.code == dr.E_UNSUPPORTED
+
+
+def test_scattering_iterations_stop_at_f_L_like_the_oracle(dr, orc):
+    """With f_L the GPU run stops after the same iteration as the oracle and its
+    FP64 ratios r_k agree (1e-5)."""
+    import dataclasses
+    import torch
+    wl = W.plain16(n=12, nside=4, lambdas=np.array([0.3, 1.0]), n_scatter=8)
+    g32 = as_f32(wl.grid)
+    m = orc.Model(g32)
+    full = orc.run(m, wl.policy)
+    f_L = 0.5 * (full.r_k[2] + full.r_k[3])
+    pol = dataclasses.replace(wl.policy, f_L=f_L)
+    ref = orc.run(m, pol)
+    out = dr.run(dr.Grid(g32), pol)
+    torch.cuda.synchronize()
+    assert len(out.r_k) == len(ref.r_k) == 4
+    np.testing.assert_allclose(out.r_k, ref.r_k, rtol=1e-5)
+    assert rel_err(out.fields.U.cpu().numpy(), ref.U).max() <= TOL

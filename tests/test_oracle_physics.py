@@ -253,3 +253,21 @@ def test_escape_transparent_medium_and_sums(orc):
     mm = orc.Model(ad.grid)
     rp = mm.run_pass(orc.STEP1, ad.policy)
     np.testing.assert_allclose(rp.escape.sum(axis=1), rp.tally[:, orc.T_ESCAPED], rtol=1e-12, atol=1e-300)
+
+
+def test_scattering_iterations_stop_at_f_L(orc):
+    """The iterations stop at the first r_k (pending over the luminosity
+    scattered in the direct pass) below f_L; the result equals a run with that
+    many iterations, and r_k decreases."""
+    import dataclasses
+    wl = W.plain16(n=6, nside=2, lambdas=np.array([0.3, 1.0]), n_scatter=8)
+    m = orc.Model(wl.grid)
+    full = orc.run(m, wl.policy)
+    assert all(a > b for a, b in zip(full.r_k, full.r_k[1:]))
+    f_L = 0.5 * (full.r_k[1] + full.r_k[2])            # falls between iterations 2 and 3
+    stop = orc.run(m, dataclasses.replace(wl.policy, f_L=f_L))
+    assert len(stop.r_k) == 3 and stop.r_k[-1] < f_L <= stop.r_k[-2]
+    fixed = orc.run(m, dataclasses.replace(wl.policy, n_scatter=3))
+    np.testing.assert_allclose(stop.U, fixed.U, rtol=1e-13)   # thread reduction order
+    s1 = full.passes[0].S.sum()
+    np.testing.assert_allclose(full.r_k, [p.S.sum() / s1 for p in full.passes[1:]], rtol=1e-15)
