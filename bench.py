@@ -30,6 +30,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# scattered 64-byte atomic requests per second, measured on MI355X with
+# paper_1709_03802_amd/ceilings.py (profiles/k_march_adaptive_step1_disk.md)
+ATOMIC_PEAK_PER_S = 2.11e10
+
+# HBM bytes per step-1 launch on the disk workload from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
+PMC_TRAFFIC = {
+    "workload": "disk",
+    "bytes_per_launch": 2.8174e13 + 2.0443e13,
+    "sources_sha256": "46c7ce2e451284157e125ab3cf3c0b8f7a7910c577966ab22326273bba08e6c0",
+    "profile": "profiles/k_march_adaptive_step1_disk.md",
+}
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dartray.hip", "dr_internal.h"):
+        with open(os.path.join(ROOT, "paper_1709_03802_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def as_f32(grid):
@@ -254,6 +275,10 @@ def main():
     launches_per_step = launches / args.steps
     avg_ms = kern_ms / max(launches, 1)
     achieved = (kern_cross * per_cross / launches_per_step) / (avg_ms * 1e-3) / 1e9
+    req_rate = (kern_cross / launches_per_step) / (avg_ms * 1e-3)
+    traffic = None
+    if wl.name == PMC_TRAFFIC["workload"] and sources_sha256() == PMC_TRAFFIC["sources_sha256"]:
+        traffic = PMC_TRAFFIC["bytes_per_launch"]
     res = {
         "metric": "ray-cell crossings x lambda per second (1 MI355X) at rel err <= 1e-4 vs the FP64 oracle",
         "value": value,
@@ -276,9 +301,14 @@ def main():
                    "crossings_per_step": crossings, "crossings_per_pass": per_pass,
                    "balance_max_rel": balance, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "avg_launch_ms": avg_ms, "bytes_per_crossing": per_cross,
                      "crossings_per_launch": kern_cross / launches_per_step},
+        # the deposits are one 64-byte atomic request per crossing (rocprofv3
+        # TCC_ATOMIC equals the crossing count): the request rate against the
+        # measured ceiling is the binding roofline of this kernel
+        "atomic_roofline": {"achieved": req_rate, "peak": ATOMIC_PEAK_PER_S, "unit": "requests/s",
+                            "frac": req_rate / ATOMIC_PEAK_PER_S, "requests_per_crossing": 1},
         "cpu_baseline": cpu,
         "parity": parity,
     }
