@@ -2172,7 +2172,14 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     // deposit log for the scattering passes of adaptive rays (wavelength rows
     // of at most 2048 slots per expansion block)
     if (nl <= 16 && g.w_row <= 256 * kExpandSlots) {
-        const int64_t lcap = std::min<int64_t>((int64_t)1 << 27, std::max<int64_t>((int64_t)1 << 16, 256 * n));
+        // up to 1024 tuples per cell within an eighth of the free memory (at
+        // most 16 GiB): fewer log-full restarts of the march per pass
+        size_t fr = 0, tt = 0;
+        if (hipMemGetInfo(&fr, &tt) != hipSuccess || fr == 0) fr = (size_t)16 << 30;
+        const int64_t per_tuple = 20 + 4 * (int64_t)nl;
+        const int64_t by_mem = (int64_t)(std::min<size_t>(fr / 8, (size_t)16 << 30) / (size_t)per_tuple);
+        const int64_t lcap = std::max<int64_t>((int64_t)1 << 16,
+                                               std::min<int64_t>(std::min<int64_t>((int64_t)1 << 28, 1024 * n), by_mem));
         int rl[] = {dalloc(g, &g.log_key, (size_t)lcap), dalloc(g, &g.log_key2, (size_t)lcap),
                     dalloc(g, &g.log_idx, (size_t)lcap), dalloc(g, &g.log_idx2, (size_t)lcap),
                     dalloc(g, &g.log_dir, (size_t)lcap), dalloc(g, &g.log_du, (size_t)lcap * nl),
