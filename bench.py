@@ -165,7 +165,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="disk", choices=["disk", "plain16", "plain16_l32", "plain16_l4"])
+    ap.add_argument("--workload", default="disk", choices=["disk", "plain16", "plain16_l32", "plain16_l4", "clumpy128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-wavelength, batched-model and autotuner measurements")
@@ -222,6 +222,24 @@ def main():
             ref_cross = int(ref.counters[oracle.C_CROSS])
             gpu_cross = int(fs.counters.cpu().numpy()[dr.C_CROSSINGS])
             what = f"step 1 of {args.sample_sources} seeded emitting cells"
+        elif grid.n > 100_000:
+            # too large for the oracle's whole run: the direct pass of seeded
+            # star cells over the whole grid
+            rng = np.random.default_rng(1709)
+            sample = np.zeros(grid.n, dtype=np.uint8)
+            sample[rng.choice(np.flatnonzero(grid.emis.sum(axis=0) > 0), args.sample_sources // 2, replace=False)] = 1
+            t0 = time.perf_counter()
+            ref = m.run_pass(oracle.DIRECT, pol, source_mask=sample, n_threads=nthreads)
+            t_cpu = time.perf_counter() - t0
+            fs = dr.Fields(G)
+            dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=torch.as_tensor(sample).cuda()), fs)
+            torch.cuda.synchronize()
+            got = fs.U.cpu().numpy().astype(np.float64)
+            ref_U = ref.U
+            ref_cross = int(ref.counters[oracle.C_CROSS])
+            gpu_cross = int(fs.counters.cpu().numpy()[dr.C_CROSSINGS])
+            what = f"direct pass of {args.sample_sources // 2} seeded star cells"
+            del fs
         else:
             t0 = time.perf_counter()
             ref_run = oracle.run(m, pol, n_threads=nthreads)
@@ -271,11 +289,14 @@ def main():
     else:
         kern_cross = crossings
         per_cross = 64 + 2 * 4 * grid.n_lambda
-        kernel = "k_march_fixed"
+        kernel = f"k_march_fixed<{grid.n_lambda}>" if grid.n_lambda in (1, 4, 8, 16, 32, 64) else "k_march_fixed"
     launches_per_step = launches / args.steps
     avg_ms = kern_ms / max(launches, 1)
     achieved = (kern_cross * per_cross / launches_per_step) / (avg_ms * 1e-3) / 1e9
-    req_rate = (kern_cross / launches_per_step) / (avg_ms * 1e-3)
+    # 64-byte atomic requests per crossing: one row of n_lambda FP64 (adaptive)
+    # or FP32 (fixed) values, at least one request
+    rpc = max(1.0, (8 if pol.adaptive else 4) * grid.n_lambda / 64.0)
+    req_rate = rpc * (kern_cross / launches_per_step) / (avg_ms * 1e-3)
     traffic = None
     if wl.name == PMC_TRAFFIC["workload"] and sources_sha256() == PMC_TRAFFIC["sources_sha256"]:
         traffic = PMC_TRAFFIC["bytes_per_launch"]
@@ -304,11 +325,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "avg_launch_ms": avg_ms, "bytes_per_crossing": per_cross,
                      "crossings_per_launch": kern_cross / launches_per_step},
-        # the deposits are one 64-byte atomic request per crossing (rocprofv3
-        # TCC_ATOMIC equals the crossing count): the request rate against the
-        # measured ceiling is the binding roofline of this kernel
+        # the deposits are one 64-byte atomic request per crossing at up to 8
+        # FP64 or 16 FP32 wavelengths (rocprofv3 TCC_ATOMIC equals the step-1
+        # crossing count): the request rate against the measured ceiling is
+        # the binding roofline of the march
         "atomic_roofline": {"achieved": req_rate, "peak": ATOMIC_PEAK_PER_S, "unit": "requests/s",
-                            "frac": req_rate / ATOMIC_PEAK_PER_S, "requests_per_crossing": 1},
+                            "frac": req_rate / ATOMIC_PEAK_PER_S, "requests_per_crossing": rpc},
         "cpu_baseline": cpu,
         "parity": parity,
     }
