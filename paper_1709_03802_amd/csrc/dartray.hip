@@ -845,7 +845,7 @@ __device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, i
     float acc[PCH];
 #pragma unroll
     for (int j = 0; j < PCH; ++j) acc[j] = 0.f;
-    float accU = 0.f;
+    double accU = 0.0;           // sum over up to 768 direction bins
     const float *ub = F.ubar + (ok ? (size_t)c * nl + l : 0);
     const size_t rstride = (size_t)n * nl;
     const float *wsl = ws + (size_t)(ok ? l : 0) * PS;
@@ -894,7 +894,7 @@ __device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, i
             for (int i = 0; i < kFlushStage; ++i) {
                 if (i < cnt) {
                     const float u = uc[i];
-                    accU += u;
+                    accU += (double)u;
                     if (pix) {
                         const float *w = wsl + (size_t)i * nl * PS;
 #pragma unroll
@@ -912,7 +912,7 @@ __device__ void flush_block(const FlushArgs &F, float *ws, int64_t bx, int by, i
         for (int j = 0; j < PCH; ++j)
             if (p0 + j < npix) srow[j] += f * acc[j];
     }
-    if (by == 0) F.U_k[c * nl + l] += (double)accU;
+    if (by == 0) F.U_k[c * nl + l] += accU;
 }
 
 template <int PCH>

@@ -369,7 +369,7 @@ def gaussian_field(n: int, slope: float, seed: int) -> np.ndarray:
     amp = np.zeros_like(k)
     nz = k > 0
     amp[nz] = k[nz] ** (slope / 2.0)
-    field = np.fft.irfftn(fk * amp, s=(n, n, n))
+    field = np.fft.irfftn(fk * amp, s=(n, n, n), axes=(0, 1, 2))
     field -= field.mean()
     field /= field.std()
     return field
