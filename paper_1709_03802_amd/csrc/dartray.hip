@@ -334,13 +334,13 @@ __device__ inline int32_t locate_fine(const Geo &g, int fx, int fy, int fz)
     return -v - 1;
 }
 
-// fine-level cell coordinate of position p along an axis with direction
-// component d: on a face, the side d points to (upper side for d == 0)
 // Transmitted fraction e^{-tau} from em1 = e^{-tau} - 1: 1 + em1 in thin
 // cells, where it keeps extinguished + transmitted equal to the input to the
 // last bit; exp itself in thick cells, where 1 + em1 would cancel.
 __device__ inline float transmit(float tau, float em1) { return tau < 0.5f ? 1.f + em1 : expf(-tau); }
 
+// fine-level cell coordinate of position p along an axis with direction
+// component d: on a face, the side d points to (upper side for d == 0)
 template <typename T>
 __device__ inline int fine_coord(T p, T d)
 {
@@ -1070,6 +1070,7 @@ void k_march_adaptive(const AdaptArgs A)
     RayT<double> R;
     float L[NL];
     double st_t[kMaxDepthAdaptive + 1];
+    int32_t st_c[kMaxDepthAdaptive + 1];   // cell in which the level's parent split
     float st_L[kMaxDepthAdaptive + 1][NL];
     int64_t steps = 0;
     double omega_hp = 0.0;
@@ -1172,10 +1173,20 @@ void k_march_adaptive(const AdaptArgs A)
             }
             omega_hp = kPi / (3.0 * (double)N * (double)N);   // 4 pi / (12 N^2)
             steps = 0;
-            c = (t == 0.0) ? s
-                           : locate_fine(A.geo, fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0]),
-                                         fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1]),
-                                         fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2]));
+            if (t == 0.0) {
+                c = s;
+            } else {
+                // a child starts at its parent's entry distance: mostly inside
+                // the cell where the parent split, which then needs no descent
+                const int fx = fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0]);
+                const int fy = fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1]);
+                const int fz = fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2]);
+                const int32_t cp = st_c[depth];
+                const int4 pb = A.geo.rec[cp].box;
+                const bool inside = fx >= pb.x && fx < pb.x + pb.w && fy >= pb.y && fy < pb.y + pb.w &&
+                                    fz >= pb.z && fz < pb.z + pb.w;
+                c = inside ? cp : locate_fine(A.geo, fx, fy, fz);
+            }
             if (c >= 0) {
                 has_ray = true;
             } else {
@@ -1253,6 +1264,7 @@ void k_march_adaptive(const AdaptArgs A)
                     ++n_split;
                     ++depth;
                     st_t[depth] = t_in;
+                    st_c[depth] = c;
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
                         L[l] *= 0.25f;
