@@ -339,6 +339,32 @@ __device__ inline int32_t locate_fine(const Geo &g, int fx, int fy, int fz)
 // last bit; exp itself in thick cells, where 1 + em1 would cancel.
 __device__ inline float transmit(float tau, float em1) { return tau < 0.5f ? 1.f + em1 : expf(-tau); }
 
+// em1 = e^{-tau} - 1 for tau >= 0 at a few FP32 operations: below 0.5 the
+// Taylor series of expm1 through the x^8 / 8! term (truncation under 1.5e-8
+// relative), above it one hardware base-2 exponential minus 1 (no
+// cancellation there, e^{-tau} <= 0.61; relative error about tau * 6e-8 from
+// rounding tau log2(e)).  Sets thick when the second branch was taken, in
+// which case tr holds e^{-tau}.
+__device__ inline float fast_em1(float tau, bool &thick, float &tr)
+{
+    thick = tau >= 0.5f;
+    if (!thick) {
+        const float x = -tau;
+        float p = 1.f / 40320.f;
+        p = fmaf(p, x, 1.f / 5040.f);
+        p = fmaf(p, x, 1.f / 720.f);
+        p = fmaf(p, x, 1.f / 120.f);
+        p = fmaf(p, x, 1.f / 24.f);
+        p = fmaf(p, x, 1.f / 6.f);
+        p = fmaf(p, x, 0.5f);
+        p = fmaf(p, x, 1.f);
+        tr = 0.f;
+        return p * x;
+    }
+    tr = __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
+    return tr - 1.f;
+}
+
 // fine-level cell coordinate of position p along an axis with direction
 // component d: on a face, the side d points to (upper side for d == 0)
 template <typename T>
@@ -605,10 +631,13 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                     if (l < nlc) {
                         const float alpha = st.kap[w][l] * rho;
                         const float tau = alpha * lp;
-                        const float em1 = expm1f(-tau);          // exp(-tau) - 1
+                        bool thick;
+                        float tr;
+                        const float em1 = fast_em1(tau, thick, tr);   // exp(-tau) - 1
                         const float ext = -L[l] * em1;
-                        st.du[l][threadIdx.x] = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
-                        L[l] = tau < 0.5f ? fmaf(L[l], em1, L[l]) : L[l] * expf(-tau);   // transmit(), fused
+                        st.du[l][threadIdx.x] =
+                            alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
+                        L[l] = thick ? L[l] * tr : fmaf(L[l], em1, L[l]);   // transmit(), fused
                     }
                 }
                 st.cell[threadIdx.x] = c;
@@ -1243,7 +1272,9 @@ void k_march_adaptive(const AdaptArgs A)
                     em1[l] = 0.f;
                     if (l < nl) {
                         const float tau = s_kap[l] * rho_c * lp;
-                        em1[l] = expm1f(-tau);
+                        bool thick;
+                        float tr;
+                        em1[l] = fast_em1(tau, thick, tr);
                         bool sg = true;
                         if (!STEP1) {
                             const float ext = -L[l] * em1[l];
@@ -1294,7 +1325,7 @@ void k_march_adaptive(const AdaptArgs A)
                             float du = 0.f;
                             if ((sigm >> l) & 1u) {
                                 const float alpha = s_kap[l] * rho_c;
-                                du = alpha > 0.f ? ext * (ivc / alpha) : L[l] * lp * ivc;
+                                du = alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
                                 ++n_dep;
                                 if (!STEP1) Fl = s_alb[l] * ext * izr[l] * s_hgA[l];
                             } else {
@@ -1307,8 +1338,10 @@ void k_march_adaptive(const AdaptArgs A)
                             }
                             s_du[l][threadIdx.x] = du;
                             {
+                                // transmit(), fused; e^{-tau} again in thick cells (1 + em1 cancels)
                                 const float tau = s_kap[l] * rho_c * lp;
-                                L[l] = tau < 0.5f ? fmaf(L[l], em1[l], L[l]) : L[l] * expf(-tau);   // transmit(), fused
+                                L[l] = tau < 0.5f ? fmaf(L[l], em1[l], L[l])
+                                                  : L[l] * __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
                             }
                         }
                     }
