@@ -1041,6 +1041,9 @@ __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlan
 #ifndef DR_WAVES_SCATTER
 #define DR_WAVES_SCATTER 1
 #endif
+#ifndef DR_PENDING_MIN
+#define DR_PENDING_MIN 4
+#endif
 
 template <int NL, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? DR_WAVES_STEP1 : DR_WAVES_SCATTER, 8)))
@@ -1186,8 +1189,12 @@ void k_march_adaptive(const AdaptArgs A)
                 }
             }
         }
-        // ---- start pending rays: direction, first cell
-        if (pending) {
+        // ---- start pending rays: direction, first cell.  The start is a
+        // divergent stretch of code, so it waits until DR_PENDING_MIN lanes
+        // have a ray to start, or no lane has one to march
+        const uint64_t pend_m = __ballot(pending);
+        const bool start_now = __popcll(pend_m) >= DR_PENDING_MIN || __ballot(has_ray) == 0;
+        if (pending && start_now) {
             pending = false;
             const int64_t N = (int64_t)A.nside0 << depth;
             e = entry_of(N, pix);
