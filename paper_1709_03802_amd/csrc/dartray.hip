@@ -1044,6 +1044,12 @@ __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlan
 #ifndef DR_PENDING_MIN
 #define DR_PENDING_MIN 4
 #endif
+#ifndef DR_FETCH_MIN_STEP1
+#define DR_FETCH_MIN_STEP1 4
+#endif
+#ifndef DR_FETCH_MIN_SCATTER
+#define DR_FETCH_MIN_SCATTER 32
+#endif
 
 template <int NL, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? DR_WAVES_STEP1 : DR_WAVES_SCATTER, 8)))
@@ -1129,7 +1135,10 @@ void k_march_adaptive(const AdaptArgs A)
         // ---- ... or a new item (top pixel r0, source), 64 at a time per wave
         const bool want = !has_ray && !pending && !has_item && !done;
         const uint64_t need = __ballot(want);
-        if (need) {
+        // new items are taken several lanes at a time (their set-up is a
+        // divergent stretch), or when no lane has anything else to do
+        constexpr int kFetchMin = STEP1 ? DR_FETCH_MIN_STEP1 : DR_FETCH_MIN_SCATTER;
+        if (need && (__popcll(need) >= kFetchMin || __ballot(has_ray || pending || has_item) == 0)) {
             const int leader = __ffsll((unsigned long long)need) - 1;
             unsigned long long base = 0;
             int stop = 0;
