@@ -19,10 +19,13 @@
  *    never frees them.  The library owns only what dartray_grid_create
  *    allocates (geometry, tables, work arrays) and frees it in
  *    dartray_grid_destroy.  No entry point other than dartray_grid_create
- *    allocates device memory.
+ *    and dartray_batch_create (three small argument arrays) allocates device
+ *    memory.
  *  - Work is queued on the stream given to dartray_grid_create and is
  *    asynchronous, except where a host output is returned (dartray_scatter_iter's
- *    r_k, dartray_debug_ray_cells): those synchronise that stream.
+ *    r_k, dartray_debug_ray_cells), in adaptive scattering passes (which read
+ *    the deposit-log fill between launches) and when a batch uploads its
+ *    arguments: those synchronise that stream.
  *  - One grid handle must not be used by two threads or streams at once.
  *  - Precision: geometry and deposits in FP32; the luminosity tallies and the
  *    convergence ratio are FP64 reductions.
