@@ -23,9 +23,9 @@
  *    memory.
  *  - Work is queued on the stream given to dartray_grid_create and is
  *    asynchronous, except where a host output is returned (dartray_scatter_iter's
- *    r_k, dartray_debug_ray_cells), in adaptive scattering passes (which read
- *    the deposit-log fill between launches) and when a batch uploads its
- *    arguments: those synchronise that stream.
+ *    r_k, dartray_debug_ray_cells), in adaptive-ray passes (which read the
+ *    source count, and the deposit-log fill between launches) and when a
+ *    batch uploads its arguments: those synchronise that stream.
  *  - One grid handle must not be used by two threads or streams at once.
  *  - Precision: geometry and deposits in FP32; the luminosity tallies and the
  *    convergence ratio are FP64 reductions.
