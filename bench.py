@@ -38,8 +38,8 @@ ATOMIC_PEAK_PER_S = 2.11e10
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
 PMC_TRAFFIC = {
     "workload": "disk",
-    "bytes_per_launch": 2.8174e13 + 2.0443e13,
-    "sources_sha256": "46c7ce2e451284157e125ab3cf3c0b8f7a7910c577966ab22326273bba08e6c0",
+    "bytes_per_launch": 2.6183e13 + 1.9905e13,
+    "sources_sha256": "3ad824937259d450a06f24762792c85c9fc62d1f756c35a4db9d04aa4b313e6a",
     "profile": "profiles/k_march_adaptive_step1_disk.md",
 }
 
