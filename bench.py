@@ -150,6 +150,33 @@ def batched_models(dr, W, repeats=2):
             "value_graph": xl / res["graph"], "speedup_graph_vs_sequential": res["sequential"] / res["graph"]}
 
 
+def adjoint_timing(dr, W, repeats=3):
+    """Forward run and adjoint march of the four-wavelength 16^3 grid (the
+    gradient configuration) and of a 64^3 clumpy grid at 4 wavelengths."""
+    import torch
+    out = {}
+    for name, wl in (("plain16_l4", W.by_name("plain16_l4")),
+                     ("clumpy64_l4", W.clumpy(n=64, n_lambda=4, n_stars=625, n_scatter=2))):
+        G = dr.Grid(as_f32(wl.grid))
+        xl = run_crossings(dr.run(G, wl.policy)) * wl.grid.n_lambda
+        rho = torch.tensor(wl.grid.rho, dtype=torch.float32, device="cuda", requires_grad=True)
+
+        def fwd():
+            return dr.rfed_escape(rho, G, wl.policy)
+
+        def fwd_bwd():
+            U, F = fwd()
+            (U.log().sum() + F.log().sum()).backward()
+
+        fwd_bwd()
+        t_f = wall(lambda: fwd(), repeats)
+        t_fb = wall(fwd_bwd, repeats)
+        out[name] = {"crossings_x_lambda": xl, "forward_ms": 1e3 * t_f, "forward_backward_ms": 1e3 * t_fb,
+                     "backward_ms": 1e3 * (t_fb - t_f),
+                     "backward_value": xl / max(t_fb - t_f, 1e-9), "unit": "crossings*lambda/s (adjoint)"}
+    return out
+
+
 def autotuned(dr, W):
     """The autotuner on the 32-wavelength uniform grid (no cache)."""
     from paper_1709_03802_amd import autotune as AT
@@ -344,6 +371,9 @@ def main():
         log("autotuner ...")
         res["autotune"] = autotuned(dr, W)
         log(f"autotuner: {res['autotune']}")
+        log("adjoint ...")
+        res["adjoint"] = adjoint_timing(dr, W)
+        log(f"adjoint: {res['adjoint']}")
     print(json.dumps(res), flush=True)
 
 
