@@ -1059,7 +1059,7 @@ void k_march_adaptive(const AdaptArgs A)
     constexpr int kBlock = 256;
     __shared__ float4 sca[STEP1 ? 1 : kScaDirs];
     __shared__ float s_kap[NL], s_alb[NL], s_hgA[NL], s_hgB[NL], s_hgC[NL];
-    __shared__ double s_esc[NL], s_cut[NL];
+    __shared__ double s_esc[NL], s_cut[NL], s_skp[NL];
     // per-thread deposit staging for the cooperative scattered-light deposit
     __shared__ float s_F[STEP1 ? 1 : NL][STEP1 ? 1 : kBlock];
     __shared__ float4 s_dep[STEP1 ? 1 : kBlock];     // direction xyz, cell id (bits) in w
@@ -1082,6 +1082,7 @@ void k_march_adaptive(const AdaptArgs A)
         s_hgC[l] = -2.f * g;
         s_esc[l] = 0.0;
         s_cut[l] = 0.0;
+        s_skp[l] = 0.0;
     }
     __syncthreads();
 
@@ -1130,6 +1131,14 @@ void k_march_adaptive(const AdaptArgs A)
                 pending = true;
             } else {
                 has_item = false;
+                // the item's skipped luminosity joins the block's FP64 sum:
+                // per-lane FP32 sums over many items would lose low bits
+#pragma unroll
+                for (int l = 0; l < NL; ++l)
+                    if (l < nl && skp[l] != 0.f) {
+                        atomicAdd(&s_skp[l], (double)skp[l]);
+                        skp[l] = 0.f;
+                    }
             }
         }
         // ---- ... or a new item (top pixel r0, source), 64 at a time per wave
@@ -1459,12 +1468,12 @@ void k_march_adaptive(const AdaptArgs A)
     }
     (void)done;
 
-    // ---- FP64 tallies: skipped per wave, escaped and cut per block
+    // ---- FP64 tallies per block (skipped: what the lanes still hold)
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         if (l < nl) {
             const double vs = wave_sum((double)skp[l]);
-            if (lane == 0 && vs != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_SKIPPED], vs);
+            if (vs != 0.0 && lane == 0) atomicAdd(&s_skp[l], vs);
         }
     }
     if (A.counters) {
@@ -1479,6 +1488,7 @@ void k_march_adaptive(const AdaptArgs A)
         const int l = threadIdx.x;
         if (s_esc[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], s_esc[l]);
         if (s_cut[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_CUT], s_cut[l]);
+        if (s_skp[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_SKIPPED], s_skp[l]);
     }
 }
 
