@@ -126,6 +126,17 @@ def test_escape_loss_gradient_vs_oracle(dr, orc):
     assert err <= 1e-4
 
 
+def test_gradient_direct_pass_only(dr, orc):
+    """No scattering iterations: the adjoint of the direct pass alone."""
+    wl = W.plain16(n=8, nside=4, lambdas=np.array([0.3, 1.0]), n_scatter=0)
+    grid = as_f32(wl.grid)
+    Ustar = target(orc, grid, wl.policy)
+    Jg, gg = gpu_grad(dr, grid, wl.policy, Ustar)
+    Jo, go = oracle_grad(orc, grid, wl.policy, Ustar)
+    assert Jg == pytest.approx(Jo, rel=1e-4)
+    assert np.abs(gg - go).max() <= 1e-4 * np.abs(go).max()
+
+
 def test_adjoint_rejects_adaptive(dr):
     import torch
     wl = W.disk_tiny()

@@ -300,3 +300,33 @@ def test_scattering_iterations_stop_at_f_L_like_the_oracle(dr, orc):
     assert len(out.r_k) == len(ref.r_k) == 4
     np.testing.assert_allclose(out.r_k, ref.r_k, rtol=1e-5)
     assert rel_err(out.fields.U.cpu().numpy(), ref.U).max() <= TOL
+
+
+def _uniform(n, rho, albedo=0.6, g=0.5, n_lambda=1):
+    level, ijk = W.uniform_leaves((n, n, n))
+    lam = W.log_lambdas(n_lambda) if n_lambda > 1 else np.array([0.55])
+    kappa, alb, gg = W.dust_law(lam)
+    if n_lambda == 1:
+        alb, gg = np.array([albedo]), np.array([g])
+    c = (ijk + 0.5) / n - 0.5
+    j = np.exp(-np.sqrt((c ** 2).sum(axis=1)) / 0.2)
+    return W.Grid(nroot=(n, n, n), lo=(0.0, 0.0, 0.0), root_size=1.0 / n, level=level, ijk=ijk,
+                  rho=np.full(n ** 3, float(rho)), emis=np.repeat(j[None, :], len(lam), axis=0),
+                  kappa=kappa, albedo=alb, g=gg, nside_sca=np.full(len(lam), 2, dtype=np.int32), lambdas_um=lam)
+
+
+@pytest.mark.parametrize("case", ["one_cell", "no_dust", "albedo_0", "isotropic"])
+def test_degenerate_media(dr, orc, case):
+    """A grid of one cell, a dust-free grid (every deposit takes the alpha = 0
+    branch), albedo 0 (the scattering iterations have no sources) and
+    isotropic scattering (g = 0), each against the oracle."""
+    pol = W.RayPolicy(adaptive=False, nside=4, nside_max=4, n_scatter=2)
+    grid = {"one_cell": _uniform(1, 2.0), "no_dust": _uniform(5, 0.0), "albedo_0": _uniform(5, 2.0, albedo=0.0),
+            "isotropic": _uniform(5, 2.0, g=0.0)}[case]
+    compare_run(dr, orc, grid, pol, label=case)
+
+
+def test_64_wavelengths(dr, orc):
+    """The widest wavelength set one march carries (64, the largest tile)."""
+    compare_run(dr, orc, _uniform(6, 2.0, n_lambda=64), W.RayPolicy(adaptive=False, nside=2, nside_max=2, n_scatter=1),
+                label="64 wavelengths")
