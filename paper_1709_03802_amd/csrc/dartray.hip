@@ -1527,8 +1527,13 @@ struct ExpandArgs {
     int32_t w_row;
 };
 
+#ifndef DR_WAVES_EXPAND
+#define DR_WAVES_EXPAND 4
+#endif
+
 template <int NL, int SLOTS>
-__global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DR_WAVES_EXPAND, 8)))
+void k_expand(const ExpandArgs X)
 {
     __shared__ float4 sca[kScaDirs];
     __shared__ int32_t t_cell[kExpandBatch];
@@ -1546,14 +1551,14 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
     // hB + (hC n_p) . n, so each slot keeps hC n_p and hB.  Slots past the
     // rows read the zero row of t_a.
     int lam[SLOTS];
-    float cx[SLOTS], cy[SLOTS], cz[SLOTS], hb[SLOTS], acc[SLOTS], cmp[SLOTS];
+    float cx[SLOTS], cy[SLOTS], cz[SLOTS], hb[SLOTS], acc[SLOTS], cmp[SLOTS], part[SLOTS];
 #pragma unroll
     for (int k = 0; k < SLOTS; ++k) {
         const int sl = threadIdx.x + 256 * k;
         lam[k] = NL;
         cx[k] = cy[k] = cz[k] = 0.f;
         hb[k] = 1.f;
-        acc[k] = cmp[k] = 0.f;
+        acc[k] = cmp[k] = part[k] = 0.f;
         if (sl < X.w_row) {
             int l = 0;
             while (l + 1 < nl && lt->w_off[l + 1] <= sl) ++l;
@@ -1568,8 +1573,26 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
         }
     }
     // energy density: thread l < nl sums wavelength l
-    float accU = 0.f, cmpU = 0.f;
+    float accU = 0.f, cmpU = 0.f, partU = 0.f;
     const int ul = threadIdx.x < nl ? (int)threadIdx.x : 0;
+
+    // plain sums over at most one staged batch of tuples fold into the
+    // compensated (Kahan) accumulators: acc holds the sum, cmp its rounding error
+    auto fold = [&]() {
+#pragma unroll
+        for (int k = 0; k < SLOTS; ++k) {
+            const float y = part[k] - cmp[k];
+            const float t = acc[k] + y;
+            cmp[k] = (t - acc[k]) - y;
+            acc[k] = t;
+            part[k] = 0.f;
+        }
+        const float y = partU - cmpU;
+        const float t = accU + y;
+        cmpU = (t - accU) - y;
+        accU = t;
+        partU = 0.f;
+    };
 
     const int64_t i0 = blockIdx.x * X.chunk;
     const int64_t i1 = min(X.cnt, i0 + X.chunk);
@@ -1577,6 +1600,7 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
 
     auto flush = [&]() {
         if (cur < 0) return;
+        fold();
         const LeafRec &r = X.rec[cur];
 #pragma unroll
         for (int k = 0; k < SLOTS; ++k) {
@@ -1626,20 +1650,11 @@ __global__ __launch_bounds__(256) void k_expand(const ExpandArgs X)
 #pragma unroll
             for (int k = 0; k < SLOTS; ++k) {
                 const float r = rsqrtf(fmaf(cx[k], n.x, fmaf(cy[k], n.y, fmaf(cz[k], n.z, hb[k]))));
-                const float v = t_a[lam[k]][jj] * (r * r * r);
-                // compensated sum: acc holds the sum, cmp the rounding error
-                const float y = v - cmp[k];
-                const float t = acc[k] + y;
-                cmp[k] = (t - acc[k]) - y;
-                acc[k] = t;
+                part[k] = fmaf(t_a[lam[k]][jj], r * r * r, part[k]);
             }
-            {
-                const float y = t_du[ul][jj] - cmpU;
-                const float t = accU + y;
-                cmpU = (t - accU) - y;
-                accU = t;
-            }
+            partU += t_du[ul][jj];
         }
+        fold();
     }
     flush();
 }
