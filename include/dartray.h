@@ -27,8 +27,10 @@
  *    source count, and the deposit-log fill between launches) and when a
  *    batch uploads its arguments: those synchronise that stream.
  *  - One grid handle must not be used by two threads or streams at once.
- *  - Precision: geometry and deposits in FP32; the luminosity tallies and the
- *    convergence ratio are FP64 reductions.
+ *  - Precision: ray geometry (positions, directions, exit distances) in
+ *    FP64; luminosities, attenuation and deposits in FP32; energy-density
+ *    accumulators, the luminosity tallies, the escape by direction and the
+ *    convergence ratio in FP64.
  */
 #ifndef DARTRAY_H
 #define DARTRAY_H

@@ -2,20 +2,24 @@
 // (Natale et al. 2017, arXiv:1709.03802): host API and kernels.
 //
 // Data layout on the device:
-//  * leaves: int4 box (lower corner in finest-level cell units, span) plus
-//    rho and 1/(V c) in structure-of-arrays form; positions along rays are in
-//    finest-level cell units so that cell faces and source-cell centres are
-//    exact in FP32;
+//  * leaves: one 64-byte record per leaf (int4 box: lower corner in
+//    finest-level cell units and span; rho; 1/(V c); six face-neighbour
+//    codes); positions along rays are in finest-level cell units so that cell
+//    faces and source-cell centres are exact, and ray geometry is FP64;
 //  * locator: one code per root cell and 8 codes per internal octree node;
 //    code >= 0 is an internal node, code < 0 is leaf -code-1;
+//  * energy-density accumulators: FP64, [cell][wavelength];
 //  * S arrays: one block per wavelength, [cell][HEALPix nested pixel].
 //
 // Fixed-Nside passes bin the energy-density deposits by ray direction
-// (ubar[l][r][c]); because every ray of direction r shares the phase-function
-// row w(.|r), the scattered source function follows exactly from
-// S[l][c][p] = albedo c alpha V * sum_r ubar[l][r][c] w_l(p|r), computed by a
-// flush kernel after each batch of directions.  One accumulate per crossing
-// and wavelength replaces the N_pix accumulates of a direct deposit.
+// (ubar[r][c][l], wavelength fastest); because every ray of direction r
+// shares the phase-function row w(.|r), the scattered source function follows
+// exactly from S[l][c][p] = albedo c alpha V * sum_r ubar[r][c][l] w_l(p|r),
+// computed by a flush kernel after each batch of directions.  One row of
+// accumulates per crossing replaces the N_pix accumulates per wavelength of a
+// direct deposit.  Adaptive rays have no fixed direction set: their passes
+// that scatter light log (cell, direction, deposit) tuples, sort them by cell
+// and expand each cell's tuples over the pixels in registers.
 
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
