@@ -6,7 +6,9 @@ library alone.  The C source is ``dartray_oracle.c``; ``build()`` compiles it
 with gcc into ``liboracle.so`` next to it.
 
 Python-side helpers here only marshal arrays and chain passes in the order of
-the paper's algorithm (Sect. 2: step 1, direct light, scattering iterations).
+the paper's algorithm (Sect. 2: step 1, direct light, scattering iterations
+until the f_L test or the iteration limit), and chain the adjoint passes in
+reverse order.
 """
 
 from __future__ import annotations

@@ -55,7 +55,18 @@
  *  - a segment shorter than 1e-6 (cell side + exit distance) is a graze: it
  *    deposits nothing, counts as no crossing and takes no split or block
  *    decision (at an exact tie its length is zero; the threshold keeps the
- *    rounding of near-ties in any precision out of the result).
+ *    rounding of near-ties in any precision out of the result);
+ *  - outputs beyond the paper: the luminosity a ray carries out of the root
+ *    block, by the launch pixel it descends from, and the adjoint of
+ *    fixed-ray passes (orc_adjoint_pass).
+ *
+ * Pins (CPU tests): closed forms for HEALPix, the phase function, slab and
+ * cube transmission (in total and per direction), the thin-medium energy
+ * density and the point-source field; exact luminosity balance; symmetry,
+ * additivity and linearity; the adjoint against central differences.  The
+ * split and block logic has no closed form: it is pinned only through the
+ * luminosity balance (with its cut and skipped terms) and its fixed-ray limit
+ * (parity partly pinned).
  */
 
 #include <math.h>
