@@ -30,9 +30,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# scattered 64-byte atomic requests per second, measured on MI355X with
-# paper_1709_03802_amd/ceilings.py (profiles/k_march_adaptive_step1_disk.md)
-ATOMIC_PEAK_PER_S = 2.11e10
+# random 64-byte atomic rows per second, measured on MI355X with
+# paper_1709_03802_amd/ceilings.py (profiles/k_march_adaptive_step1_disk.md):
+# rows of 8 FP64 values (the adaptive marches' energy-density rows, footprints
+# up to 128 MiB) and rows of 16 FP32 values (the fixed march's direction bins)
+ATOMIC_PEAK_ROWS_F64 = 2.35e10
+ATOMIC_PEAK_ROWS_F32 = 2.06e10
 
 # HBM bytes per step-1 launch on the disk workload from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
@@ -324,6 +327,7 @@ def main():
     # or FP32 (fixed) values, at least one request
     rpc = max(1.0, (8 if pol.adaptive else 4) * grid.n_lambda / 64.0)
     req_rate = rpc * (kern_cross / launches_per_step) / (avg_ms * 1e-3)
+    atomic_peak = ATOMIC_PEAK_ROWS_F64 if pol.adaptive else ATOMIC_PEAK_ROWS_F32
     traffic = None
     if wl.name == PMC_TRAFFIC["workload"] and sources_sha256() == PMC_TRAFFIC["sources_sha256"]:
         traffic = PMC_TRAFFIC["bytes_per_launch"]
@@ -356,8 +360,8 @@ def main():
         # FP64 or 16 FP32 wavelengths (rocprofv3 TCC_ATOMIC equals the step-1
         # crossing count): the request rate against the measured ceiling is
         # the binding roofline of the march
-        "atomic_roofline": {"achieved": req_rate, "peak": ATOMIC_PEAK_PER_S, "unit": "requests/s",
-                            "frac": req_rate / ATOMIC_PEAK_PER_S, "requests_per_crossing": rpc},
+        "atomic_roofline": {"achieved": req_rate, "peak": atomic_peak, "unit": "64-byte atomic rows/s",
+                            "frac": req_rate / atomic_peak, "requests_per_crossing": rpc},
         "cpu_baseline": cpu,
         "parity": parity,
     }

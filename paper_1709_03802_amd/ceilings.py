@@ -47,6 +47,16 @@ def atomics_grouped(footprint, group):
     return run(5 if group == 64 else 6, footprint)
 
 
+def atomic_rows_f64(footprint):
+    """FP64 atomic adds on random 64-byte rows of 8 doubles: rows per second."""
+    return run(7, footprint)
+
+
+def atomic_rows_f32(footprint):
+    """FP32 atomic adds on random 64-byte rows of 16 floats: rows per second."""
+    return run(8, footprint)
+
+
 def lds_atomics():
     return run(3, 0, 256)
 
@@ -77,5 +87,9 @@ if __name__ == "__main__":
     for fp in (8 << 20, 1 << 30):
         print(f"atomics {fp >> 20} MiB in 64-float groups {atomics_grouped(fp, 64) / 1e9:.1f} G lane-ops/s, "
               f"8-float groups {atomics_grouped(fp, 8) / 1e9:.1f} G lane-ops/s", flush=True)
+    for fp in (8 << 20, 16 << 20, 128 << 20, 1 << 30):
+        print(f"FP64 atomic rows (8 doubles), {fp >> 20} MiB: {atomic_rows_f64(fp) / 1e9:.2f} G rows/s; "
+              f"FP32 atomic rows (16 floats): {atomic_rows_f32(fp) / 1e9:.2f} G rows/s", flush=True)
+    print(f"FP32 atomic rows (16 floats), 8192 MiB: {atomic_rows_f32(8 << 30) / 1e9:.2f} G rows/s", flush=True)
     print(f"LDS atomics {lds_atomics() / 1e12:.2f} T/s", flush=True)
     print(f"exp {exp_rate() / 1e12:.2f} T/s", flush=True)

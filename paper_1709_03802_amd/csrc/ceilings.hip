@@ -59,6 +59,32 @@ __global__ void k_atomic_grouped(float *p, uint32_t ngroups, int group, int iter
     }
 }
 
+// FP64 atomics in groups of 8 consecutive doubles (one 64-byte row per group,
+// 8 rows per 64-lane instruction) at random row indices
+__global__ void k_atomic_rows_f64(double *p, uint32_t nrows, int iters)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t x = lcg((blockIdx.x * blockDim.x + threadIdx.x) / 8 + 1717u);
+    for (int k = 0; k < iters; ++k) {
+        x = lcg(x);
+        __hip_atomic_fetch_add(p + (size_t)(x % nrows) * 8 + (lane & 7), 1.0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// FP32 atomics in 64-byte rows of 16 floats (4 rows per 64-lane instruction)
+// at random row indices
+__global__ void k_atomic_rows_f32(float *p, uint32_t nrows, int iters)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t x = lcg((blockIdx.x * blockDim.x + threadIdx.x) / 16 + 2929u);
+    for (int k = 0; k < iters; ++k) {
+        x = lcg(x);
+        __hip_atomic_fetch_add(p + (size_t)(x % nrows) * 16 + (lane & 15), 1.0f, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 __global__ void k_lds_atomic(float *out, int iters)
 {
     __shared__ float s[4096];
@@ -111,7 +137,9 @@ extern "C" {
 // which: 0 copy (bytes/s, read + write), 1 device-scope atomics (ops/s),
 // 2 per-XCD workgroup-scope atomics (ops/s), 3 LDS atomics (ops/s),
 // 4 exp (ops/s), 5 atomics in groups of 64 consecutive floats, 6 in groups of
-// 8 (lane-ops/s).  footprint: bytes for 0-2 and 5-6.  Returns 0 on success.
+// 8 (lane-ops/s), 7 FP64 atomics in 64-byte rows of 8 doubles (rows/s),
+// 8 FP32 atomics in 64-byte rows of 16 floats (rows/s).
+// footprint: bytes for 0-2 and 5-8.  Returns 0 on success.
 int drceil_run(int which, size_t footprint, int iters, double *per_s)
 {
     Timer tm;
@@ -119,7 +147,7 @@ int drceil_run(int which, size_t footprint, int iters, double *per_s)
     const int blocks = 4096, threads = 256;
     hipError_t e = hipSuccess;
     double ops = 0.0;
-    if (which <= 2 || which >= 5) {
+    if (which <= 2 || which >= 5) {   // footprint-sized buffer
         e = hipMalloc(&buf, footprint);
         if (e != hipSuccess) return -2;
         (void)hipMemset(buf, 0, footprint);
@@ -146,6 +174,14 @@ int drceil_run(int which, size_t footprint, int iters, double *per_s)
         } else if (which == 2) {
             hipLaunchKernelGGL(k_atomic_xcd, dim3(blocks), dim3(threads), 0, 0, buf, (uint32_t)(footprint / 4 / 8), iters);
             ops = (double)blocks * threads * iters;
+        } else if (which == 7) {
+            hipLaunchKernelGGL(k_atomic_rows_f64, dim3(blocks), dim3(threads), 0, 0, (double *)buf,
+                               (uint32_t)(footprint / 64), iters);
+            ops = (double)blocks * threads * iters / 8.0;
+        } else if (which == 8) {
+            hipLaunchKernelGGL(k_atomic_rows_f32, dim3(blocks), dim3(threads), 0, 0, buf, (uint32_t)(footprint / 64),
+                               iters);
+            ops = (double)blocks * threads * iters / 16.0;
         } else if (which == 5 || which == 6) {
             const int group = which == 5 ? 64 : 8;
             hipLaunchKernelGGL(k_atomic_grouped, dim3(blocks), dim3(threads), 0, 0, buf,
