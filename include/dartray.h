@@ -98,7 +98,7 @@ typedef struct dartray_grid dartray_grid;   /* opaque handle */
  * the scattered source function at that wavelength (a power of two, or 0 to
  * apply the resolution rule of Eq. 5-6 with n_fwhm and the cap k_max).
  * Values must be finite, rho and emis >= 0, 0 <= albedo <= 1, |g| < 1,
- * nside_sca <= 8.
+ * nside_sca <= 8; n_leaves * n_lambda < 2^32 (DARTRAY_E_UNSUPPORTED above).
  */
 typedef struct {
     int32_t nroot[3];

@@ -1439,7 +1439,9 @@ void k_march_adaptive(const AdaptArgs A)
                 if (q < cnt && l < nl) {
                     const int j = s_list[wbase + q];
                     const float v = s_du[l][wbase + j];
-                    if (v != 0.f) atomic_add_f64(A.U_k + (int64_t)s_cell[wbase + j] * nl + l, (double)v);
+                    // 32-bit row offsets: n * n_lambda < 2^32 is checked at grid creation
+                    const uint32_t off = (uint32_t)s_cell[wbase + j] * (uint32_t)nl + (uint32_t)l;
+                    if (STEP1 || v != 0.f) atomic_add_f64(A.U_k + off, (double)v);
                 }
             }
         }
@@ -2025,6 +2027,8 @@ static int validate_desc(const dartray_grid_desc *d)
     if (!d) return fail(DARTRAY_E_INVALID, "null grid description");
     if (d->n_leaves <= 0 || d->n_leaves > (int64_t)INT32_MAX) return fail(DARTRAY_E_INVALID, "n_leaves out of range");
     if (d->n_lambda <= 0 || d->n_lambda > kMaxLambda) return fail(DARTRAY_E_INVALID, "n_lambda must be 1..64");
+    if (d->n_leaves * (int64_t)d->n_lambda >= ((int64_t)1 << 32))
+        return fail(DARTRAY_E_UNSUPPORTED, "n_leaves x n_lambda must be below 2^32");
     if (!(d->root_size > 0.0) || !std::isfinite(d->root_size)) return fail(DARTRAY_E_INVALID, "root_size must be > 0");
     if (!(d->c_light > 0.0)) return fail(DARTRAY_E_INVALID, "c_light must be > 0");
     for (int a = 0; a < 3; ++a)
