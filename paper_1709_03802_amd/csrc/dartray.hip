@@ -1262,6 +1262,7 @@ void k_march_adaptive(const AdaptArgs A)
         // ---- one crossing per lane with a ray
         bool deposit = false;
         bool udep = false;
+        int dslot = 0;   // this lane's slot in the wave's compacted deposit staging
         if (has_ray) {
             const LeafRec &rc = A.geo.rec[c];
             const int4 b = rc.box;
@@ -1344,7 +1345,9 @@ void k_march_adaptive(const AdaptArgs A)
                     const float ivc = rc.ivc;
                     ++n_cross;
                     udep = true;
-                    s_cell[threadIdx.x] = c;
+                    // the lanes depositing in this step fill the staging in lane order
+                    dslot = wbase + __popcll(__ballot(true) & ((1ull << lane) - 1ull));
+                    s_cell[dslot] = c;
                     const float *izr = A.invz + e * nl;
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
@@ -1365,7 +1368,7 @@ void k_march_adaptive(const AdaptArgs A)
                                 s_F[l][threadIdx.x] = Fl;
                                 deposit |= Fl != 0.f;
                             }
-                            s_du[l][threadIdx.x] = du;
+                            s_du[l][dslot] = du;
                             {
                                 // transmit(), fused; e^{-tau} again in thick cells (1 + em1 cancels)
                                 const float tau = s_kap[l] * rho_c * lp;
@@ -1412,11 +1415,11 @@ void k_march_adaptive(const AdaptArgs A)
                 if (udep) {
                     const unsigned long long slot = base + __popcll(lm & ((1ull << lane) - 1ull));
                     if (slot < (unsigned long long)A.log_cap) {
-                        A.log_key[slot] = (uint32_t)s_cell[threadIdx.x];
+                        A.log_key[slot] = (uint32_t)s_cell[dslot];
                         A.log_dir[slot] = (uint32_t)e;
 #pragma unroll
                         for (int l = 0; l < NL; ++l)
-                            if (l < nl) A.log_du[(int64_t)l * A.log_cap + slot] = s_du[l][threadIdx.x];
+                            if (l < nl) A.log_du[(int64_t)l * A.log_cap + slot] = s_du[l][dslot];
                         udep = false;
                         deposit = false;
                     }
@@ -1426,8 +1429,10 @@ void k_march_adaptive(const AdaptArgs A)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         {
+            // step 1: every depositing lane's row sits at its compacted slot;
+            // other passes: the lanes the log did not take are listed by slot
             const uint64_t um = __ballot(udep);
-            if (udep) s_list[wbase + __popcll(um & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+            if (!STEP1 && udep) s_list[wbase + __popcll(um & ((1ull << lane) - 1ull))] = (uint8_t)(dslot - wbase);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1437,7 +1442,7 @@ void k_march_adaptive(const AdaptArgs A)
                 const int q = k0 + lane / NL;
                 const int l = lane % NL;
                 if (q < cnt && l < nl) {
-                    const int j = s_list[wbase + q];
+                    const int j = STEP1 ? q : (int)s_list[wbase + q];
                     const float v = s_du[l][wbase + j];
                     // 32-bit row offsets: n * n_lambda < 2^32 is checked at grid creation
                     const uint32_t off = (uint32_t)s_cell[wbase + j] * (uint32_t)nl + (uint32_t)l;
