@@ -41,8 +41,8 @@ ATOMIC_PEAK_ROWS_F32 = 2.06e10
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
 PMC_TRAFFIC = {
     "workload": "disk",
-    "bytes_per_launch": 2.6183e13 + 1.9905e13,
-    "sources_sha256": "3ad824937259d450a06f24762792c85c9fc62d1f756c35a4db9d04aa4b313e6a",
+    "bytes_per_launch": 2.6099e13 + 1.9904e13,
+    "sources_sha256": "96a8929d048700cff6706c05c055e6f766bc44e16bfb42de02214ecee7f72d2d",
     "profile": "profiles/k_march_adaptive_step1_disk.md",
 }
 
@@ -324,10 +324,21 @@ def main():
     avg_ms = kern_ms / max(launches, 1)
     achieved = (kern_cross * per_cross / launches_per_step) / (avg_ms * 1e-3) / 1e9
     # 64-byte atomic requests per crossing: one row of n_lambda FP64 (adaptive)
-    # or FP32 (fixed) values, at least one request
-    rpc = max(1.0, (8 if pol.adaptive else 4) * grid.n_lambda / 64.0)
-    req_rate = rpc * (kern_cross / launches_per_step) / (avg_ms * 1e-3)
+    # or FP32 (fixed) values.  A row narrower than 64 bytes shares its segment
+    # with the rows of neighbouring cells, so its request count depends on which
+    # lanes hit one segment, and no measured ceiling has that access pattern:
+    # no atomic roofline is given then
+    row_bytes = (8 if pol.adaptive else 4) * grid.n_lambda
     atomic_peak = ATOMIC_PEAK_ROWS_F64 if pol.adaptive else ATOMIC_PEAK_ROWS_F32
+    if row_bytes >= 64:
+        rpc = row_bytes / 64.0
+        req_rate = rpc * (kern_cross / launches_per_step) / (avg_ms * 1e-3)
+        atomic_roof = {"achieved": req_rate, "peak": atomic_peak, "unit": "64-byte atomic rows/s",
+                       "frac": req_rate / atomic_peak, "requests_per_crossing": rpc}
+    else:
+        atomic_roof = {"achieved": None, "peak": None, "unit": "64-byte atomic rows/s", "frac": None,
+                       "requests_per_crossing": None,
+                       "note": f"{row_bytes}-byte rows share 64-byte segments; no matching ceiling"}
     traffic = None
     if wl.name == PMC_TRAFFIC["workload"] and sources_sha256() == PMC_TRAFFIC["sources_sha256"]:
         traffic = PMC_TRAFFIC["bytes_per_launch"]
@@ -356,12 +367,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "avg_launch_ms": avg_ms, "bytes_per_crossing": per_cross,
                      "crossings_per_launch": kern_cross / launches_per_step},
-        # the deposits are one 64-byte atomic request per crossing at up to 8
-        # FP64 or 16 FP32 wavelengths (rocprofv3 TCC_ATOMIC equals the step-1
+        # the deposits are one 64-byte atomic request per crossing at 8 FP64
+        # or 16 FP32 wavelengths (rocprofv3 TCC_ATOMIC equals the step-1
         # crossing count): the request rate against the measured ceiling is
         # the binding roofline of the march
-        "atomic_roofline": {"achieved": req_rate, "peak": atomic_peak, "unit": "64-byte atomic rows/s",
-                            "frac": req_rate / atomic_peak, "requests_per_crossing": rpc},
+        "atomic_roofline": atomic_roof,
         "cpu_baseline": cpu,
         "parity": parity,
     }
