@@ -338,11 +338,10 @@ __device__ inline int32_t locate_fine(const Geo &g, int fx, int fy, int fz)
     return -v - 1;
 }
 
-// Transmitted fraction e^{-tau} from em1 = e^{-tau} - 1: 1 + em1 in thin
+// The transmitted fraction e^{-tau} is 1 + em1 (em1 = e^{-tau} - 1) in thin
 // cells, where it keeps extinguished + transmitted equal to the input to the
-// last bit; exp itself in thick cells, where 1 + em1 would cancel.
-__device__ inline float transmit(float tau, float em1) { return tau < 0.5f ? 1.f + em1 : expf(-tau); }
-
+// last bit, and e^{-tau} itself in thick cells, where 1 + em1 would cancel.
+//
 // em1 = e^{-tau} - 1 for tau >= 0 at a few FP32 operations: below 0.5 the
 // Taylor series of expm1 through the x^8 / 8! term (truncation under 1.5e-8
 // relative), above it one hardware base-2 exponential minus 1 (no
@@ -641,7 +640,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                         const float ext = -L[l] * em1;
                         st.du[l][threadIdx.x] =
                             alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
-                        L[l] = thick ? L[l] * tr : fmaf(L[l], em1, L[l]);   // transmit(), fused
+                        L[l] = thick ? L[l] * tr : fmaf(L[l], em1, L[l]);   // transmission, fused
                     }
                 }
                 st.cell[threadIdx.x] = c;
@@ -1370,7 +1369,7 @@ void k_march_adaptive(const AdaptArgs A)
                             }
                             s_du[l][dslot] = du;
                             {
-                                // transmit(), fused; e^{-tau} again in thick cells (1 + em1 cancels)
+                                // transmission, fused; e^{-tau} again in thick cells (1 + em1 cancels)
                                 const float tau = s_kap[l] * rho_c * lp;
                                 L[l] = tau < 0.5f ? fmaf(L[l], em1[l], L[l])
                                                   : L[l] * __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
@@ -1681,20 +1680,70 @@ void k_expand(const ExpandArgs X)
 // and dJ/dL_0 = G goes to the pending luminosity the ray was launched from.
 // ---------------------------------------------------------------------------
 
-// sbar[l][rl][c] = sum_p w_l(p | r0 + rl) Sbar[l][c][p]; grid (cells / 256, nb, nl)
+// sig[(rl n + c) n_lambda + l] = sum_p w_l(p | r0 + rl) Sbar_l[c][p]: per
+// wavelength, the direction weights (nb x npix) times the transposed gradient
+// of the pending scattered light (npix x cells).  Both operands pass through
+// LDS in stages of kGK pixels; a block covers kGT directions x kGT cells, a
+// thread 4 x 4 of them, summing over the pixels in order.  Grid (cells / kGT,
+// directions / kGT).
+constexpr int kGT = 64;
+constexpr int kGK = 32;
+
 __global__ __launch_bounds__(256) void k_sbar_gather(float *sig, const float *wtab, const LambdaTable *lt,
                                                       const float *Sbar, int64_t n, int r0, int nb, int w_row)
 {
-    const int l = blockIdx.z;
-    const int rl = blockIdx.y;
-    const int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x;
-    if (c >= n) return;
-    const int npix = lt->npix[l];
-    const float *w = wtab + (int64_t)(r0 + rl) * w_row + lt->w_off[l];
-    const float *row = Sbar + lt->s_off[l] + c * (int64_t)npix;
-    float acc = 0.f;
-    for (int p = 0; p < npix; ++p) acc = fmaf(w[p], row[p], acc);
-    sig[((int64_t)l * nb + rl) * n + c] = acc;
+    __shared__ __align__(16) float sW[kGK][kGT + 4];
+    __shared__ __align__(16) float sS[kGK][kGT + 4];
+    const int nl = lt->n_lambda;
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int64_t c0 = (int64_t)blockIdx.x * kGT;
+    const int d0 = (int)blockIdx.y * kGT;
+    for (int l = 0; l < nl; ++l) {
+        const int npix = lt->npix[l];
+        const float *S = Sbar + lt->s_off[l];
+        const float *W = wtab + lt->w_off[l];
+        float acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+        for (int k0 = 0; k0 < npix; k0 += kGK) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kGT * kGK / 256; ++q) {
+                const int e = tid + 256 * q;
+                const int row = e / kGK, kk = e % kGK;
+                const int k = k0 + kk;
+                const int64_t c = c0 + row;
+                const int d = d0 + row;
+                sS[kk][row] = (c < n && k < npix) ? S[c * npix + k] : 0.f;
+                sW[kk][row] = (d < nb && k < npix) ? W[(int64_t)(r0 + d) * w_row + k] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll 8
+            for (int kk = 0; kk < kGK; ++kk) {
+                const float4 a = *reinterpret_cast<const float4 *>(&sW[kk][4 * ty]);
+                const float4 b = *reinterpret_cast<const float4 *>(&sS[kk][4 * tx]);
+                const float av[4] = {a.x, a.y, a.z, a.w};
+                const float bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int d = d0 + 4 * ty + i;
+            if (d >= nb) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t c = c0 + 4 * tx + j;
+                if (c < n) sig[((int64_t)d * n + c) * nl + l] = acc[i][j];
+            }
+        }
+    }
 }
 
 struct AdjArgs {
@@ -1706,7 +1755,7 @@ struct AdjArgs {
     const float *S_pending;      // scattering pass: its emission
     const LambdaTable *lt;
     const float *ubar_t;         // dJ/dU, [n][n_lambda]
-    const float *sig;            // sbar per (wavelength, direction, cell), or null
+    const float *sig;            // sbar per (direction, cell, wavelength), or null
     double *rho_bar;
     float *sbar_k;               // dJ/dS of the pass's emission (scattering pass)
     const float *ebar;           // dJ/dF [n_lambda][nray] of the escaping luminosity, or null
@@ -1828,21 +1877,24 @@ __global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
                         if (l < nl) {
                             const float alpha = kap[l] * rho;
                             const float tau = alpha * lp;
-                            const float em1 = expm1f(-tau);
+                            bool thick;
+                            float tr;
+                            const float em1 = fast_em1(tau, thick, tr);
+                            const float T = thick ? tr : 1.f + em1;   // e^{-tau}
                             float E, dE;
                             eprime(tau, em1, E, dE);
                             const float ub = A.ubar_t[(int64_t)c * nl + l];
-                            const float sg = A.sig ? A.sig[((int64_t)l * A.nb + rl) * A.n + c] : 0.f;
+                            const float sg = A.sig ? A.sig[((int64_t)rl * A.n + c) * nl + l] : 0.f;
                             const float a = lp * E * ivc * ub - alb[l] * em1 * sg;
                             if (walk == 0) {
                                 G[l] += (double)ell[l] * (double)a;
                             } else {
-                                const float ap = lp * dE * ivc * ub + alb[l] * transmit(tau, em1) * sg;
+                                const float ap = lp * dE * ivc * ub + alb[l] * T * sg;
                                 P[l] += (double)ell[l] * (double)a;
                                 const double dtau = (double)L0[l] * ((double)ell[l] * (double)ap - (G[l] - P[l]));
                                 rb += (double)kap[l] * (double)lp * dtau;
                             }
-                            ell[l] *= transmit(tau, em1);
+                            ell[l] *= T;
                         }
                     }
                     if (walk == 1 && rb != 0.0) atomic_add_f64(A.rho_bar + c, rb);
@@ -3066,8 +3118,8 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
             A.nb = nb;
             A.sig = nullptr;
             if (sbar_next) {
-                hipLaunchKernelGGL(k_sbar_gather, dim3((unsigned)((n + 255) / 256), nb, nl), dim3(256), 0, g.stream, g.ubar,
-                                   g.wtab, g.d_lt, sbar_next, n, (int)r0, nb, g.w_row);
+                hipLaunchKernelGGL(k_sbar_gather, dim3((unsigned)((n + kGT - 1) / kGT), (unsigned)((nb + kGT - 1) / kGT)),
+                                   dim3(256), 0, g.stream, g.ubar, g.wtab, g.d_lt, sbar_next, n, (int)r0, nb, g.w_row);
                 DR_LAUNCH_CHECK("k_sbar_gather");
                 A.sig = g.ubar;
             }
