@@ -36,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # up to 128 MiB) and rows of 16 FP32 values (the fixed march's direction bins)
 ATOMIC_PEAK_ROWS_F64 = 2.35e10
 ATOMIC_PEAK_ROWS_F32 = 2.06e10
+# scattered single-value atomics, one lane per 64-byte segment
+ATOMIC_PEAK_SINGLE = 2.11e10
 
 # HBM bytes per step-1 launch on the disk workload from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
@@ -158,8 +160,8 @@ def adjoint_timing(dr, W, repeats=3):
     gradient configuration) and of a 64^3 clumpy grid at 4 wavelengths."""
     import torch
     out = {}
-    for name, wl in (("plain16_l4", W.by_name("plain16_l4")),
-                     ("clumpy64_l4", W.clumpy(n=64, n_lambda=4, n_stars=625, n_scatter=2))):
+    for name in ("plain16_l4", "clumpy64_l4"):
+        wl = W.by_name(name)
         G = dr.Grid(as_f32(wl.grid))
         xl = run_crossings(dr.run(G, wl.policy)) * wl.grid.n_lambda
         rho = torch.tensor(wl.grid.rho, dtype=torch.float32, device="cuda", requires_grad=True)
@@ -190,12 +192,125 @@ def autotuned(dr, W):
             "start_ms": log[0][1], "evaluations": len(log)}
 
 
+def adjoint_bench(args):
+    """The gradient configuration: a forward run (direct pass + scattering
+    iterations, untimed) and, timed, its adjoint march for dJ/drho with
+    J = sum ln U + sum ln F (F the escaping luminosity by direction)."""
+    import torch
+    from paper_1709_03802_amd import dartray as dr
+    from paper_1709_03802_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.by_name(args.workload)
+    pol = wl.policy
+    if pol.adaptive:
+        print(json.dumps({"error": "the adjoint covers fixed-ray workloads (plain16_l4, clumpy64_l4, plain16, ...)"}))
+        sys.exit(2)
+    grid = as_f32(wl.grid)
+    nl = grid.n_lambda
+    G = dr.Grid(grid)
+    log(f"adjoint, workload {wl.name}: {wl.description}")
+    out = dr.run(G, pol, collect=True)
+    torch.cuda.synchronize()
+    counters = np.array(out.counters)
+    per_pass = [int(c[dr.C_CROSSINGS]) for c in counters]
+    crossings = sum(per_pass)
+    rho = torch.tensor(grid.rho, dtype=torch.float32, device="cuda", requires_grad=True)
+
+    def forward():
+        rho.grad = None
+        U, F = dr.rfed_escape(rho, G, pol)
+        return U.log().sum() + F.log().sum()
+
+    parity, cpu = None, None
+    if not args.no_cpu_baseline and grid.n <= 100_000:
+        import oracle
+        J = forward()
+        J.backward()
+        torch.cuda.synchronize()
+        g_gpu = rho.grad.cpu().numpy().astype(np.float64)
+        m = oracle.Model(grid)
+        nthreads = os.cpu_count() or 1
+        r = oracle.run(m, pol, n_threads=nthreads)
+        t0 = time.perf_counter()
+        g_ref = oracle.adjoint(m, pol, r, 1.0 / r.U, Ebar=1.0 / r.escape, n_threads=nthreads)
+        t_cpu = time.perf_counter() - t0
+        err = float(np.abs(g_gpu - g_ref).max() / np.abs(g_ref).max())
+        parity = {"checked": "dJ/drho of the full run against the oracle's adjoint", "max_err_over_max_grad": err,
+                  "gate": 1e-4, "pass": bool(err <= 1e-4)}
+        cpu = {"value": crossings * nl / t_cpu, "unit": "crossings*lambda/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"adjoint of the full {wl.name} run, {crossings} crossings x {nl} wavelengths in {t_cpu:.1f} s"}
+        log(f"oracle adjoint in {t_cpu:.1f} s; parity {parity}")
+
+    t_f = wall(lambda: forward(), 2)
+    for _ in range(args.warmup):
+        forward().backward()
+    torch.cuda.synchronize()
+    G.profile(dr.PROF_ADJOINT)
+    t_b = 0.0
+    for _ in range(args.steps):
+        J = forward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t_b += time.perf_counter() - t0
+    kern_ms, launches = G.profile_read()
+    G.profile(0)
+    ms_per_step = 1e3 * t_b / args.steps
+    kern_s = 1e-3 * kern_ms / args.steps
+    # per crossing, each of the two walks reads the 64-byte leaf record, the
+    # dJ/dU row and the scattered-light gradient row (n_lambda FP32 each); the
+    # second walk adds the FP64 density gradient of the cell
+    per_cross = 2 * (64 + 2 * 4 * nl) + 16
+    achieved = crossings * per_cross / kern_s / 1e9
+    res = {
+        "metric": "adjoint ray-cell crossings x lambda per second (1 MI355X), dJ/drho at <= 1e-4 of max |dJ/drho| "
+                  "vs the FP64 oracle's adjoint",
+        "value": crossings * nl / (t_b / args.steps),
+        "unit": "crossings*lambda/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "description": wl.description, "cells": int(grid.n), "n_lambda": nl,
+                   "rays": f"fixed nside {pol.nside}", "passes": ["direct"] + [f"scatter{k + 1}" for k in range(pol.n_scatter)],
+                   "crossings_per_run": crossings, "crossings_per_pass": per_pass,
+                   "step": "backward of one forward run (the forward is run, untimed, before each step)",
+                   "forward_ms": 1e3 * t_f, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_march_adjoint<{nl_template(nl)}>",
+                     "avg_launch_ms": kern_ms / max(launches, 1), "launches_per_step": launches / args.steps,
+                     "bytes_per_crossing": per_cross, "crossings_per_step": crossings},
+        # one FP64 density-gradient atomic per crossing at most (lanes whose
+        # cells share a 64-byte segment share a request)
+        "atomic_roofline": {"achieved": crossings / kern_s, "peak": ATOMIC_PEAK_SINGLE,
+                            "unit": "FP64 atomics/s (one per crossing, upper bound on requests)",
+                            "frac": crossings / kern_s / ATOMIC_PEAK_SINGLE},
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def nl_template(k):
+    return 1 if k <= 1 else 4 if k <= 4 else 8
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="disk", choices=["disk", "plain16", "plain16_l32", "plain16_l4", "clumpy128"])
+    ap.add_argument("--workload", default="disk",
+                    choices=["disk", "plain16", "plain16_l32", "plain16_l4", "clumpy64_l4", "clumpy128"])
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint march (dJ/drho) of a fixed-ray workload instead of the forward passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-wavelength, batched-model and autotuner measurements")
@@ -206,6 +321,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1. Sources shard additively "
                                    "across GPUs (design notes), but no multi-GPU path is built."}))
         sys.exit(2)
+    if args.adjoint:
+        adjoint_bench(args)
+        return
 
     import torch
     from paper_1709_03802_amd import dartray as dr

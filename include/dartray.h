@@ -269,7 +269,8 @@ int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *or
 #define DARTRAY_PROF_FIXED 1        /* fixed-Nside march launches */
 #define DARTRAY_PROF_STEP1 2        /* adaptive step-1 march launches */
 #define DARTRAY_PROF_SCATTERING 4   /* adaptive direct / scattering march launches */
-#define DARTRAY_PROF_ALL 7
+#define DARTRAY_PROF_ADJOINT 8      /* adjoint march launches (dartray_trace_adjoint) */
+#define DARTRAY_PROF_ALL 15
 int dartray_profile_enable(dartray_grid *grid, int32_t kinds);
 
 /* Sum of the recorded march-kernel durations (ms) and the number of launches

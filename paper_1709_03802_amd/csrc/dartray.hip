@@ -1781,8 +1781,15 @@ __device__ inline void eprime(float tau, float em1, float &E, float &dE)
     }
 }
 
+// waves per SIMD the compiler must allow for the adjoint march: its loads
+// depend on the previous crossing, so occupancy hides their latency
+#ifndef DR_WAVES_ADJOINT
+#define DR_WAVES_ADJOINT 4
+#endif
+
 template <int NL, bool UNIFORM>
-__global__ __launch_bounds__(256) void k_march_adjoint(const AdjArgs A)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NL <= 4 ? DR_WAVES_ADJOINT : 2, 8)))
+void k_march_adjoint(const AdjArgs A)
 {
     const LambdaTable *lt = A.lt;
     const int nl = lt->n_lambda;
@@ -3095,6 +3102,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     A.h_fine = g.h_fine;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
     const float *sbar_next = nullptr;
+    g.prof_kind = DARTRAY_PROF_ADJOINT;
     for (int k = n_scatter; k >= 0; --k) {
         const bool scatter = k > 0;
         float *sbar_k = scatter ? g.sbar[k & 1] : nullptr;
@@ -3124,6 +3132,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
                 A.sig = g.ubar;
             }
             const unsigned blocks = 2048;
+            if ((rc = prof_mark(g))) return rc;
             if (nl <= 1) {
                 if (g.uniform) hipLaunchKernelGGL((k_march_adjoint<1, true>), dim3(blocks), dim3(256), 0, g.stream, A);
                 else hipLaunchKernelGGL((k_march_adjoint<1, false>), dim3(blocks), dim3(256), 0, g.stream, A);
@@ -3135,6 +3144,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
                 else hipLaunchKernelGGL((k_march_adjoint<8, false>), dim3(blocks), dim3(256), 0, g.stream, A);
             }
             DR_LAUNCH_CHECK("k_march_adjoint");
+            if ((rc = prof_mark(g))) return rc;
         }
         sbar_next = sbar_k;
     }

@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(PKG, "libdartray.so")
 
 OK, E_INVALID, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 MODE_STEP1, MODE_DIRECT = 0, 1
-PROF_FIXED, PROF_STEP1, PROF_SCATTERING, PROF_ALL = 1, 2, 4, 7
+PROF_FIXED, PROF_STEP1, PROF_SCATTERING, PROF_ADJOINT, PROF_ALL = 1, 2, 4, 8, 15
 FLAG_COUNTERS = 1
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
 C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)

@@ -483,4 +483,6 @@ def by_name(name: str) -> Workload:
         return disk_tiny()
     if name == "clumpy128":
         return clumpy()
+    if name == "clumpy64_l4":
+        return clumpy(n=64, n_lambda=4, n_stars=625, n_scatter=2)
     raise KeyError(name)
