@@ -43,9 +43,19 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
 PMC_TRAFFIC = {
     "workload": "disk",
-    "bytes_per_launch": 2.6099e13 + 1.9904e13,
-    "sources_sha256": "96a8929d048700cff6706c05c055e6f766bc44e16bfb42de02214ecee7f72d2d",
+    "bytes_per_launch": 2.6095e13 + 1.9904e13,
+    "sources_sha256": "280d0b4d6557d327fcb19ed55efcaaf03e720492f6f6f5e0462b3aa797e4b799",
     "profile": "profiles/k_march_adaptive_step1_disk.md",
+}
+# the same for the adjoint march of the 64^3 clumpy grid at 4 wavelengths, per
+# backward step (three launches): HBM bytes, and atomic requests from
+# rocprofv3 TCC_ATOMIC (lanes whose cells share a 64-byte segment share one)
+PMC_ADJOINT = {
+    "workload": "clumpy64",
+    "bytes_per_step": 2.0571e12 + 2.870e11,
+    "atomic_requests_per_step": 7.4183e9,
+    "sources_sha256": "280d0b4d6557d327fcb19ed55efcaaf03e720492f6f6f5e0462b3aa797e4b799",
+    "profile": "profiles/k_march_adjoint_clumpy64_l4.md",
 }
 
 
@@ -242,6 +252,21 @@ def adjoint_bench(args):
                "sample": f"adjoint of the full {wl.name} run, {crossings} crossings x {nl} wavelengths in {t_cpu:.1f} s"}
         log(f"oracle adjoint in {t_cpu:.1f} s; parity {parity}")
 
+    # the order of work items (tile- or direction-major) that suits the grid:
+    # one timed backward of each
+    order_ms = {}
+    for order in (0, 1):
+        G.set_tuning(item_order=order)
+        forward().backward()
+        J = forward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        order_ms[order] = 1e3 * (time.perf_counter() - t0)
+    best = min(order_ms, key=order_ms.get)
+    G.set_tuning(item_order=best)
+    log(f"item order: backward ms {order_ms}, using {best}")
     t_f = wall(lambda: forward(), 2)
     for _ in range(args.warmup):
         forward().backward()
@@ -264,6 +289,16 @@ def adjoint_bench(args):
     # second walk adds the FP64 density gradient of the cell
     per_cross = 2 * (64 + 2 * 4 * nl) + 16
     achieved = crossings * per_cross / kern_s / 1e9
+    measured = wl.name == PMC_ADJOINT["workload"] and sources_sha256() == PMC_ADJOINT["sources_sha256"]
+    if measured:
+        req_rate = PMC_ADJOINT["atomic_requests_per_step"] / kern_s
+        atomic_roof = {"achieved": req_rate, "peak": ATOMIC_PEAK_SINGLE, "unit": "atomic requests/s",
+                       "frac": req_rate / ATOMIC_PEAK_SINGLE,
+                       "requests_per_crossing": PMC_ADJOINT["atomic_requests_per_step"] / crossings}
+    else:
+        atomic_roof = {"achieved": None, "peak": ATOMIC_PEAK_SINGLE, "unit": "atomic requests/s", "frac": None,
+                       "requests_per_crossing": None,
+                       "note": "at most one FP64 request per crossing; the count is measured for clumpy64_l4 only"}
     res = {
         "metric": "adjoint ray-cell crossings x lambda per second (1 MI355X), dJ/drho at <= 1e-4 of max |dJ/drho| "
                   "vs the FP64 oracle's adjoint",
@@ -282,16 +317,18 @@ def adjoint_bench(args):
                    "rays": f"fixed nside {pol.nside}", "passes": ["direct"] + [f"scatter{k + 1}" for k in range(pol.n_scatter)],
                    "crossings_per_run": crossings, "crossings_per_pass": per_pass,
                    "step": "backward of one forward run (the forward is run, untimed, before each step)",
-                   "forward_ms": 1e3 * t_f, "parallelism": "single GPU"},
+                   "forward_ms": 1e3 * t_f, "item_order": best,
+                   "backward_ms_by_item_order": {str(k): v for k, v in order_ms.items()},
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_march_adjoint<{nl_template(nl)}>",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": PMC_ADJOINT["bytes_per_step"] / launches * args.steps if measured and launches else None,
+                     "kernel": f"k_march_adjoint<{nl_template(nl)}>",
                      "avg_launch_ms": kern_ms / max(launches, 1), "launches_per_step": launches / args.steps,
                      "bytes_per_crossing": per_cross, "crossings_per_step": crossings},
-        # one FP64 density-gradient atomic per crossing at most (lanes whose
-        # cells share a 64-byte segment share a request)
-        "atomic_roofline": {"achieved": crossings / kern_s, "peak": ATOMIC_PEAK_SINGLE,
-                            "unit": "FP64 atomics/s (one per crossing, upper bound on requests)",
-                            "frac": crossings / kern_s / ATOMIC_PEAK_SINGLE},
+        # the FP64 density-gradient atomics of the second walk against the
+        # scattered single-value atomic ceiling
+        "atomic_roofline": atomic_roof,
         "cpu_baseline": cpu,
         "parity": parity,
     }

@@ -294,6 +294,7 @@ int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes);
  *               the handle's bin array holds)
  *  item_order   0: a wave's next work item is the next direction of the same
  *               64-source tile; 1: the next source tile of the same direction
+ *               (also the order of the adjoint march)
  */
 typedef struct {
     int32_t lambda_tile;

@@ -1763,6 +1763,7 @@ struct AdjArgs {
     int32_t scatter;
     int32_t r0;
     int32_t nb;
+    int32_t order;               // 0: tile-major items, 1: direction-major
     int32_t log2_nside_ray;
     float inv_nray;
     double h_fine;
@@ -1807,8 +1808,16 @@ void k_march_adjoint(const AdjArgs A)
         alb[l] = l < nl ? lt->albedo[l] : 0.f;
     }
     for (int64_t it = wid; it < nitems; it += nw) {
-        const int64_t tile = it / A.nb;
-        const int rl = (int)(it - tile * A.nb);
+        // item order as in the forward march (tuning item_order)
+        int64_t tile;
+        int rl;
+        if (A.order == 0) {
+            tile = it / A.nb;
+            rl = (int)(it - tile * A.nb);
+        } else {
+            rl = (int)(it / ntiles);
+            tile = it - (int64_t)rl * ntiles;
+        }
         const int r = A.r0 + rl;
         const int64_t si = tile * 64 + (threadIdx.x & 63);
         if (si >= nsrc) continue;
@@ -3097,6 +3106,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     A.rho_bar = g.rho_bar;
     A.ebar = dJ_desc;
     A.n = n;
+    A.order = g.tune.item_order;
     A.log2_nside_ray = log2n;
     A.inv_nray = (float)(1.0 / (double)nray);
     A.h_fine = g.h_fine;

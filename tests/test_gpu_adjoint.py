@@ -185,3 +185,23 @@ def test_gradient_plain16_four_wavelengths_central_differences_on_20_cells(dr, o
         worst = max(worst, abs(fd - gg[c]) / scale)
     print(f"16^3 x 4, 20 cells: max |fd - g| / max |g| = {worst:.3g}", flush=True)
     assert worst <= 2e-3
+
+
+def test_gradient_same_in_both_item_orders(dr):
+    """Tile-major and direction-major work items (tuning item_order) give the
+    same gradient up to the order of the atomic sums."""
+    import torch
+    wl = W.plain16(n=8, nside=4, lambdas=np.array([0.3, 1.0]), n_scatter=2)
+    grid = as_f32(wl.grid)
+    G = dr.Grid(grid)
+    grads = []
+    for order in (0, 1):
+        G.set_tuning(item_order=order)
+        rho = torch.tensor(grid.rho, dtype=torch.float32, device="cuda", requires_grad=True)
+        U, F = dr.rfed_escape(rho, G, wl.policy)
+        (U.log().sum() + F.log().sum()).backward()
+        torch.cuda.synchronize()
+        grads.append(rho.grad.cpu().numpy().astype(np.float64))
+    err = np.abs(grads[0] - grads[1]).max() / np.abs(grads[0]).max()
+    print(f"item orders: max |g0 - g1| / max |g0| = {err:.3g}", flush=True)
+    assert err <= 1e-5
