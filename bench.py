@@ -43,8 +43,8 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
 PMC_TRAFFIC = {
     "workload": "disk",
-    "bytes_per_launch": 2.6095e13 + 1.9904e13,
-    "sources_sha256": "280d0b4d6557d327fcb19ed55efcaaf03e720492f6f6f5e0462b3aa797e4b799",
+    "bytes_per_launch": 2.6099e13 + 1.9904e13,
+    "sources_sha256": "f081944074b88cfffee9218ae445b4ba3f62dbb820555dc4be4f0da912a8d59e",
     "profile": "profiles/k_march_adaptive_step1_disk.md",
 }
 # the same for the adjoint march of the 64^3 clumpy grid at 4 wavelengths, per
@@ -52,9 +52,9 @@ PMC_TRAFFIC = {
 # rocprofv3 TCC_ATOMIC (lanes whose cells share a 64-byte segment share one)
 PMC_ADJOINT = {
     "workload": "clumpy64",
-    "bytes_per_step": 2.0571e12 + 2.870e11,
-    "atomic_requests_per_step": 7.4183e9,
-    "sources_sha256": "280d0b4d6557d327fcb19ed55efcaaf03e720492f6f6f5e0462b3aa797e4b799",
+    "bytes_per_step": 2.0585e12 + 2.870e11,
+    "atomic_requests_per_step": 7.4175e9,
+    "sources_sha256": "f081944074b88cfffee9218ae445b4ba3f62dbb820555dc4be4f0da912a8d59e",
     "profile": "profiles/k_march_adjoint_clumpy64_l4.md",
 }
 

@@ -1682,32 +1682,37 @@ void k_expand(const ExpandArgs X)
 
 // sig[(rl n + c) n_lambda + l] = sum_p w_l(p | r0 + rl) Sbar_l[c][p]: per
 // wavelength, the direction weights (nb x npix) times the transposed gradient
-// of the pending scattered light (npix x cells).  Both operands pass through
-// LDS in stages of kGK pixels; a block covers kGT directions x kGT cells, a
-// thread 4 x 4 of them, summing over the pixels in order.  Grid (cells / kGT,
-// directions / kGT).
+// of the pending scattered light (npix x cells), a dense contraction on the
+// matrix cores (FP32 MFMA 16x16x4).  Both operands pass through LDS in stages
+// of kGK pixels (zero past npix); a block covers kGT directions x kGT cells,
+// each of its four waves a 32 x 32 quarter as 2 x 2 MFMA tiles.  Grid (cells
+// / kGT, directions / kGT).
 constexpr int kGT = 64;
 constexpr int kGK = 32;
+typedef float float4v __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_sbar_gather(float *sig, const float *wtab, const LambdaTable *lt,
                                                       const float *Sbar, int64_t n, int r0, int nb, int w_row)
 {
-    __shared__ __align__(16) float sW[kGK][kGT + 4];
-    __shared__ __align__(16) float sS[kGK][kGT + 4];
+    __shared__ float sW[kGK][kGT + 4];
+    __shared__ float sS[kGK][kGT + 4];
     const int nl = lt->n_lambda;
     const int tid = threadIdx.x;
-    const int ty = tid >> 4, tx = tid & 15;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int dq = 32 * (wave >> 1), cq = 32 * (wave & 1);   // this wave's quarter of the tile
+    const int li = lane & 15, lk = lane >> 4;                  // MFMA operand row / k of this lane
     const int64_t c0 = (int64_t)blockIdx.x * kGT;
     const int d0 = (int)blockIdx.y * kGT;
     for (int l = 0; l < nl; ++l) {
         const int npix = lt->npix[l];
         const float *S = Sbar + lt->s_off[l];
         const float *W = wtab + lt->w_off[l];
-        float acc[4][4];
+        float4v acc[2][2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+            for (int j = 0; j < 2; ++j) acc[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < npix; k0 += kGK) {
             __syncthreads();
 #pragma unroll
@@ -1721,26 +1726,29 @@ __global__ __launch_bounds__(256) void k_sbar_gather(float *sig, const float *wt
                 sW[kk][row] = (d < nb && k < npix) ? W[(int64_t)(r0 + d) * w_row + k] : 0.f;
             }
             __syncthreads();
-#pragma unroll 8
-            for (int kk = 0; kk < kGK; ++kk) {
-                const float4 a = *reinterpret_cast<const float4 *>(&sW[kk][4 * ty]);
-                const float4 b = *reinterpret_cast<const float4 *>(&sS[kk][4 * tx]);
-                const float av[4] = {a.x, a.y, a.z, a.w};
-                const float bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+            for (int ks = 0; ks < kGK; ks += 4) {
+                // A (16 directions x 4 pixels): lane holds A[li][lk];
+                // B (4 pixels x 16 cells): lane holds B[lk][li]
+                const float a0 = sW[ks + lk][dq + li], a1 = sW[ks + lk][dq + 16 + li];
+                const float b0 = sS[ks + lk][cq + li], b1 = sS[ks + lk][cq + 16 + li];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
             }
         }
+        // result element v of this lane: row 4 lk + v, column li of the 16 x 16 tile
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int d = d0 + 4 * ty + i;
-            if (d >= nb) continue;
+        for (int i = 0; i < 2; ++i) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t c = c0 + 4 * tx + j;
-                if (c < n) sig[((int64_t)d * n + c) * nl + l] = acc[i][j];
+            for (int j = 0; j < 2; ++j) {
+                const int64_t c = c0 + cq + 16 * j + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int d = d0 + dq + 16 * i + 4 * lk + v;
+                    if (d < nb && c < n) sig[((int64_t)d * n + c) * nl + l] = acc[i][j][v];
+                }
             }
         }
     }
