@@ -43,8 +43,8 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
 PMC_TRAFFIC = {
     "workload": "disk",
-    "bytes_per_launch": 2.6099e13 + 1.9904e13,
-    "sources_sha256": "f081944074b88cfffee9218ae445b4ba3f62dbb820555dc4be4f0da912a8d59e",
+    "bytes_per_launch": 2.6299e+13 + 1.9904e+13,
+    "sources_sha256": "608cac3514d632f4c5c1d8321b02dd29be5e62db23aefc70b98a06407b3bc601",
     "profile": "profiles/k_march_adaptive_step1_disk.md",
 }
 # the same for the adjoint march of the 64^3 clumpy grid at 4 wavelengths, per
@@ -52,9 +52,9 @@ PMC_TRAFFIC = {
 # rocprofv3 TCC_ATOMIC (lanes whose cells share a 64-byte segment share one)
 PMC_ADJOINT = {
     "workload": "clumpy64",
-    "bytes_per_step": 2.0585e12 + 2.870e11,
-    "atomic_requests_per_step": 7.4175e9,
-    "sources_sha256": "f081944074b88cfffee9218ae445b4ba3f62dbb820555dc4be4f0da912a8d59e",
+    "bytes_per_step": 2.0580e+12 + 2.8701e+11,
+    "atomic_requests_per_step": 7.4174e+09,
+    "sources_sha256": "608cac3514d632f4c5c1d8321b02dd29be5e62db23aefc70b98a06407b3bc601",
     "profile": "profiles/k_march_adjoint_clumpy64_l4.md",
 }
 

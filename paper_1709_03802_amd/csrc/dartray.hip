@@ -2096,7 +2096,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.d_lt, g.U_k,
+    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.U_k,
                     g.flags, g.cell_flag, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -2266,6 +2266,12 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     std::vector<int32_t> morton((size_t)n);
     for (int64_t i = 0; i < n; ++i) morton[i] = (int32_t)i;
     std::stable_sort(morton.begin(), morton.end(), [&](int32_t a, int32_t b) { return keys[a] < keys[b]; });
+    // source order of the adaptive passes: a source's ray tree grows with the
+    // fineness of the cells around it, so the finest levels go first and the
+    // work queue ends on the lightest items (Morton order within a level)
+    std::vector<int32_t> by_level(morton);
+    std::stable_sort(by_level.begin(), by_level.end(),
+                     [&](int32_t a, int32_t b) { return d->leaf_level[a] > d->leaf_level[b]; });
 
     LambdaTable lt{};
     lt.n_lambda = nl;
@@ -2326,7 +2332,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n), dalloc(g, &g.esc64, (size_t)nl * 12 * kMaxNsideWTable * kMaxNsideWTable),
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
-        dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.d_lt, 1),
+        dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.by_level, (size_t)n), dalloc(g, &g.d_lt, 1),
         dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
         dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
         dalloc(g, &g.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
@@ -2392,6 +2398,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     cp(g.root_tab, root_tab.data(), sizeof(int32_t) * nroot);
     cp(g.nodes, nodes.data(), sizeof(int32_t) * nodes.size());
     cp(g.morton, morton.data(), sizeof(int32_t) * n);
+    cp(g.by_level, by_level.data(), sizeof(int32_t) * n);
     cp(g.d_lt, &lt, sizeof(LambdaTable));
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors go out of scope
     if (e != hipSuccess) {
@@ -2645,8 +2652,10 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
 {
     const int64_t n = g.n;
     const unsigned nblk = (unsigned)((n + kScanBlock - 1) / kScanBlock);
+    // the order in which sources become work items
+    const int32_t *order = o->adaptive ? g.by_level : g.morton;
     if (!scatter) {
-        hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, g.morton,
+        hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, order,
                            n, g.d_lt, g.emis_lum, o->source_mask, f->tally);
         DR_LAUNCH_CHECK("k_source_flags");
     } else {
@@ -2656,14 +2665,14 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
                            g.cell_flag, f->tally);
         DR_LAUNCH_CHECK("k_sflag_sweep");
         hipLaunchKernelGGL(k_sflag_gather, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
-                           g.stream, g.flags, g.morton, g.cell_flag, n);
+                           g.stream, g.flags, order, g.cell_flag, n);
         DR_LAUNCH_CHECK("k_sflag_gather");
     }
     hipLaunchKernelGGL(k_scan_count, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, n, g.scan_blocks);
     DR_LAUNCH_CHECK("k_scan_count");
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, g.stream, g.scan_blocks, (int64_t)nblk, g.n_src);
     DR_LAUNCH_CHECK("k_scan_blocks");
-    hipLaunchKernelGGL(k_scan_scatter, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, g.morton, n,
+    hipLaunchKernelGGL(k_scan_scatter, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, order, n,
                        g.scan_blocks, g.src_list);
     DR_LAUNCH_CHECK("k_scan_scatter");
     return DARTRAY_OK;

@@ -76,6 +76,7 @@ struct Grid {
     int32_t *root_tab = nullptr;          // root cell -> node code
     int32_t *nodes = nullptr;             // [8 * n_internal] child codes
     int32_t *morton = nullptr;            // leaves in Morton order
+    int32_t *by_level = nullptr;          // leaves finest level first, Morton order within a level
     LambdaTable *d_lt = nullptr;
 
     // work arrays
