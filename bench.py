@@ -210,12 +210,12 @@ def adjoint_bench(args):
     from paper_1709_03802_amd import dartray as dr
     from paper_1709_03802_amd import workloads as W
 
-    torch.cuda.set_device(0)
     wl = W.by_name(args.workload)
     pol = wl.policy
     if pol.adaptive:
         print(json.dumps({"error": "the adjoint covers fixed-ray workloads (plain16_l4, clumpy64_l4, plain16, ...)"}))
         sys.exit(2)
+    torch.cuda.set_device(0)
     grid = as_f32(wl.grid)
     nl = grid.n_lambda
     G = dr.Grid(grid)
@@ -357,8 +357,8 @@ def main():
                          "for a whole oracle run use a quarter of them for a direct pass")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1. Sources shard additively "
-                                   "across GPUs (design notes), but no multi-GPU path is built."}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1. Sources shard additively "
+                                   "across GPUs, but no multi-GPU path exists."}))
         sys.exit(2)
     if args.adjoint:
         adjoint_bench(args)

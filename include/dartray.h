@@ -48,7 +48,7 @@ extern "C" {
 #define DARTRAY_E_OOM (-2)          /* device allocation failed (create only) */
 #define DARTRAY_E_DEVICE (-3)       /* HIP runtime error; message has the HIP string */
 #define DARTRAY_E_STATE (-4)        /* call out of sequence (e.g. scatter before direct) */
-#define DARTRAY_E_UNSUPPORTED (-5)  /* valid request this build does not handle */
+#define DARTRAY_E_UNSUPPORTED (-5)  /* valid request the library does not handle */
 #define DARTRAY_E_NUMERIC (-6)      /* non-finite value produced by a pass */
 
 /* pass modes */
