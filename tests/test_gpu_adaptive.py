@@ -59,6 +59,9 @@ def check_counts(c_gpu, c_ref, dr, orc):
         a, b = int(c_gpu[gi]), int(c_ref[oi])
         print(f"  {name}: gpu {a} oracle {b}", flush=True)
         assert abs(a - b) <= 1e-3 * max(b, 1) + 2, name
+    # every ray ends once: a split ends one ray and starts four
+    c = [int(v) for v in c_gpu]
+    assert c[dr.C_ESCAPES] + c[dr.C_CUTS] + c[dr.C_MAXSTEP] == c[dr.C_RAYS] + 3 * c[dr.C_SPLITS]
 
 
 def check_balance(t):

@@ -271,3 +271,26 @@ def test_scattering_iterations_stop_at_f_L(orc):
     np.testing.assert_allclose(stop.U, fixed.U, rtol=1e-13)   # thread reduction order
     s1 = full.passes[0].S.sum()
     np.testing.assert_allclose(full.r_k, [p.S.sum() / s1 for p in full.passes[1:]], rtol=1e-15)
+
+
+def test_every_adaptive_ray_ends_once(orc):
+    """Split bookkeeping (Sect. 3.1.1): a split ends one ray and starts four,
+    so over a pass escapes + cuts + step-limit stops = launched rays + 3
+    splits.  A lost or duplicated child breaks it; checked in step 1, the
+    direct pass and the scattering passes of an adaptive random octree, and
+    with a small step limit that stops rays early."""
+    g = W.random_octree(nroot=(2, 2, 2), root_size=0.5, max_level=3, p_split=0.4, seed=11, n_lambda=3)
+    pol = W.RayPolicy(adaptive=True, nside=4, nside_max=16, n_rays_min=4.0, f_U=1e-3, r_pre=0.5, step1=True,
+                      n_scatter=2)
+    m = orc.Model(g)
+
+    def ends_once(c):
+        assert c[orc.C_ESCAPES] + c[orc.C_CUTS] + c[orc.C_MAXSTEP] == c[orc.C_RAYS] + 3 * c[orc.C_SPLITS]
+
+    r = orc.run(m, pol)
+    assert all(p.counters[orc.C_SPLITS] > 0 for p in r.passes)
+    for p in r.passes:
+        ends_once(p.counters)
+    short = m.run_pass(orc.STEP1, pol, max_steps=3)
+    assert short.counters[orc.C_MAXSTEP] > 0
+    ends_once(short.counters)
