@@ -65,8 +65,8 @@
  * density and the point-source field; exact luminosity balance; symmetry,
  * additivity and linearity; the adjoint against central differences.  The
  * split and block logic has no closed form: it is pinned only through the
- * luminosity balance (with its cut and skipped terms) and its fixed-ray limit
- * (parity partly pinned).
+ * luminosity balance (with its cut and skipped terms), its fixed-ray limit and
+ * the ray bookkeeping (every ray ends once) (parity partly pinned).
  */
 
 #include <math.h>
