@@ -65,8 +65,10 @@
  * density and the point-source field; exact luminosity balance; symmetry,
  * additivity and linearity; the adjoint against central differences.  The
  * split and block logic has no closed form: it is pinned only through the
- * luminosity balance (with its cut and skipped terms), its fixed-ray limit and
- * the ray bookkeeping (every ray ends once) (parity partly pinned).
+ * luminosity balance (with its cut and skipped terms), its fixed-ray limit,
+ * the ray bookkeeping (every ray ends once) and the step-1 extent (nothing
+ * reaches a cell lying R_pre or farther from the source) (parity partly
+ * pinned).
  */
 
 #include <math.h>

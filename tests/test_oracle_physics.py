@@ -294,3 +294,24 @@ def test_every_adaptive_ray_ends_once(orc):
     short = m.run_pass(orc.STEP1, pol, max_steps=3)
     assert short.counters[orc.C_MAXSTEP] > 0
     ends_once(short.counters)
+
+
+def test_step1_deposits_stop_at_r_pre(orc):
+    """Step 1 (Sect. 2, R_pre): a crossing whose entry distance is >= R_pre is
+    cut, so a cell whose nearest point lies R_pre or farther from the source
+    receives nothing, while cells well inside are reached."""
+    g = W.random_octree(nroot=(2, 2, 2), root_size=0.5, max_level=3, p_split=0.4, seed=5, n_lambda=1)
+    c = g.centres()
+    s = int(np.argmin(((c - 0.5) ** 2).sum(axis=1)))
+    g.emis[:] = 0.0
+    g.emis[:, s] = 1.0
+    r_pre = 0.3
+    pol = W.RayPolicy(adaptive=True, nside=4, nside_max=64, n_rays_min=4.0, f_U=1e-3, r_pre=r_pre, step1=True,
+                      n_scatter=0)
+    U = orc.Model(g).run_pass(orc.STEP1, pol).U[0]
+    half = g.side()[:, None] / 2
+    d = np.maximum(np.maximum(c - half - c[s], c[s] - (c + half)), 0.0)
+    dmin = np.sqrt((d ** 2).sum(axis=1))
+    assert np.all(U[dmin >= r_pre] == 0.0)
+    assert np.count_nonzero(dmin >= r_pre) > 0
+    assert np.mean(U[dmin < 0.5 * r_pre] > 0) > 0.9
