@@ -103,7 +103,8 @@ class FieldsC(C.Structure):
 
 
 class Tuning(C.Structure):
-    """dartray_tuning: launch parameters of the fixed-ray passes (0 = default)."""
+    """dartray_tuning: launch parameters of the fixed-ray passes (0 = default);
+    item_order also sets the order of the adjoint march's work items."""
     _fields_ = [
         ("lambda_tile", C.c_int32),
         ("block_waves", C.c_int32),
