@@ -74,6 +74,7 @@ class PassOpts(C.Structure):
         ("source_mask", C.POINTER(C.c_uint8)),
         ("max_steps", C.c_int64),
         ("n_threads", C.c_int32),
+        ("a_RT", C.c_double),
     ]
 
 
@@ -111,6 +112,12 @@ def lib():
                                       C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
         L.orc_trace_cells.restype = C.c_int64
+        L.orc_crossings.argtypes = L.orc_trace_cells.argtypes
+        L.orc_crossings.restype = C.c_int64
+        L.orc_is_graze.argtypes = [C.c_double, C.c_double]
+        L.orc_is_graze.restype = C.c_int
+        L.orc_count_sources.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
+        L.orc_count_sources.restype = C.c_int64
         L.orc_run_pass.argtypes = [C.c_void_p, C.POINTER(PassOpts), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -239,24 +246,23 @@ class Model:
                                   _p(cells, C.c_int64), _p(lens, C.c_double), _p(tin, C.c_double))
         return cells[:n], lens[:n], tin[:n]
 
+    def crossings(self, o, d, t0=0.0, max_cross=100000):
+        """Crossings of positive length as a pass walks them (grazes folded)."""
+        cells = np.zeros(max_cross, dtype=np.int64)
+        lens = np.zeros(max_cross)
+        tin = np.zeros(max_cross)
+        n = lib().orc_crossings(self.h, _dvec(o), _dvec(d), float(t0), max_cross,
+                                _p(cells, C.c_int64), _p(lens, C.c_double), _p(tin, C.c_double))
+        return cells[:n], lens[:n], tin[:n]
+
+    def count_sources(self, mode, S_pending=None):
+        Sp = None if S_pending is None else np.ascontiguousarray(S_pending, dtype=np.float64)
+        return int(lib().orc_count_sources(self.h, mode, None if Sp is None else _p(Sp, C.c_double)))
+
     def run_pass(self, mode, policy, S_pending=None, U_LL=None, frame=None, source_mask=None,
                  max_steps=0, n_threads=0):
-        o = PassOpts()
-        o.mode = mode
-        o.adaptive = 1 if policy.adaptive else 0
-        o.nside = int(policy.nside)
-        o.nside_max = int(policy.nside_max)
-        o.n_rays_min = float(policy.n_rays_min)
-        o.f_U = float(policy.f_U)
-        o.r_pre = float(policy.r_pre)
-        fr = np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)
-        o.frame = (C.c_double * 9)(*fr.ravel().tolist())
-        mask = None
-        if source_mask is not None:
-            mask = np.ascontiguousarray(source_mask, dtype=np.uint8)
-            o.source_mask = _p(mask, C.c_uint8)
+        o, mask = _opts(mode, policy, frame, source_mask, n_threads)
         o.max_steps = int(max_steps)
-        o.n_threads = int(n_threads)
         U_k = np.zeros(self.nl * self.n)
         S_next = np.zeros(max(self.s_size, 1))
         tally = np.zeros(self.nl * 8)
@@ -284,6 +290,7 @@ def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
     o.nside_max = int(policy.nside_max)
     o.n_rays_min = float(policy.n_rays_min)
     o.f_U = float(policy.f_U)
+    o.a_RT = float(getattr(policy, "a_RT", 0.0))
     o.r_pre = float(policy.r_pre)
     fr = np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)
     o.frame = (C.c_double * 9)(*fr.ravel().tolist())

@@ -52,23 +52,45 @@
  *    belong to the side the direction points to, the upper side when the
  *    component is zero); a ray through an edge or corner therefore crosses
  *    zero-length segments;
- *  - a segment shorter than 1e-6 (cell side + exit distance) is a graze: it
- *    deposits nothing, counts as no crossing and takes no split or block
- *    decision (at an exact tie its length is zero; the threshold keeps the
- *    rounding of near-ties in any precision out of the result);
+ *  - a segment whose length is zero up to the rounding of its two end
+ *    distances -- no longer than 2^-46 of its exit distance, some 32 to 64
+ *    units in the last place of an FP64 distance -- is an edge or corner
+ *    graze: a ray through an edge or corner of a cell crosses it with zero
+ *    length in exact arithmetic, and the paper is silent on such crossings.
+ *    A graze deposits nothing, counts as no crossing and takes no split or
+ *    block decision; the ray's distance is not advanced, so the rounding
+ *    residue folds into the next segment.  The forward passes and the
+ *    adjoint walk rays with this same rule (orc_is_graze);
  *  - outputs beyond the paper: the luminosity a ray carries out of the root
  *    block, by the launch pixel it descends from, and the adjoint of
  *    fixed-ray passes (orc_adjoint_pass).
  *
- * Pins (CPU tests): closed forms for HEALPix, the phase function, slab and
- * cube transmission (in total and per direction), the thin-medium energy
- * density and the point-source field; exact luminosity balance; symmetry,
- * additivity and linearity; the adjoint against central differences.  The
- * split and block logic has no closed form: it is pinned only through the
- * luminosity balance (with its cut and skipped terms), its fixed-ray limit,
- * the ray bookkeeping (every ray ends once) and the step-1 extent (nothing
- * reaches a cell lying R_pre or farther from the source) (parity partly
- * pinned).
+ * Pins (CPU tests), by function:
+ *  - orc_healpix_vec: ring closed forms of Gorski et al. (z and phi per ring),
+ *    an independently written ang2pix (children inside their parent), the
+ *    symmetry of the pixel set;
+ *  - orc_hg, orc_hg_fwhm, orc_k_hp: normalisation over the sphere by
+ *    quadrature, the g = 0 limit, the FWHM against its closed form, and the
+ *    Eq. 5 resolution putting between 3 and 30 pixel centres inside the FWHM
+ *    around any direction (Sect. 3.1.2: several points sample the peak);
+ *  - orc_step, orc_trace_cells, orc_crossings, orc_is_graze: brute-force slab
+ *    intersection on uniform grids and random octrees; a segment 1e-9 of a
+ *    cell long is a crossing; graze lengths fold so that crossings add up to
+ *    the chord;
+ *  - orc_run_pass, fixed rays: exp(-tau) through a cube and a layered slab,
+ *    the thin-medium sum U V c = sum L d, the 1/(4 pi r^2 c) field, exact
+ *    luminosity balance, albedo and g limits, symmetry, additivity,
+ *    linearity, escape by direction, the launch rule when rays are coarser
+ *    than the j_sca pixels;
+ *  - orc_run_pass, adaptive rays (orc_follow): hand-built rows of cells where
+ *    Eq. 2 must split at a known crossing or must not, the Nside scaling of
+ *    the beam, the Eq. 8 estimate a part in 1e9 above and below the threshold,
+ *    blocking only when insignificant at every wavelength, brute force of all
+ *    rays and their children, luminosity balance with cut and skipped terms,
+ *    the fixed-ray limit, every ray ending once, the step-1 extent, and Eq. 11
+ *    (N_s counted independently; the a_RT 0.05 / 0.005 property of Sect. 5);
+ *  - orc_adjoint_pass: central differences on every cell (also in a frame
+ *    with near-ties), a dot-product test, zero gradient at the target.
  */
 
 #include <math.h>
@@ -128,6 +150,7 @@ typedef struct {
     const uint8_t *source_mask; /* [n] or NULL */
     int64_t max_steps;      /* per ray; <= 0 means unlimited */
     int32_t n_threads;
+    double a_RT;            /* accuracy parameter of Eq. 11, used when f_U < 0 */
 } orc_pass_opts;
 
 /* ------------------------------------------------------------------------ */
@@ -447,6 +470,45 @@ int64_t orc_trace_cells(const orc_model *m, const double o[3], const double d[3]
     return n;
 }
 
+/* A segment [t, te] whose length is zero up to the rounding of t and te: a
+ * ray through an edge or corner of a cell (Sect. 2 is silent on these).  The
+ * bound is 2^-46 of the exit distance, a few tens of units in the last place
+ * of an FP64 distance: the exit distances of one exact tie, each computed
+ * from an exact face position and a direction rounded to FP64, differ by a
+ * few units in the last place. */
+int orc_is_graze(double len, double te)
+{
+    return !(len > 0x1p-46 * te);
+}
+
+/* Crossings of positive length of the ray o + t d from t = t0, walked as a
+ * radiative-transfer pass walks it: grazes are skipped without advancing the
+ * distance, so their length folds into the next crossing.  Writes leaf ids,
+ * lengths and entry distances; returns the count, at most max_cross. */
+int64_t orc_crossings(const orc_model *m, const double o[3], const double d[3], double t0,
+                      int64_t max_cross, int64_t *cells, double *lengths, double *t_in)
+{
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = o[a] + t0 * d[a];
+    int64_t c = orc_locate(m, p, d);
+    double t = t0;
+    int64_t n = 0;
+    while (c >= 0 && n < max_cross) {
+        double te;
+        int64_t nx = orc_step(m, c, o, d, &te);
+        double len = te > t ? te - t : 0.0;
+        if (!orc_is_graze(len, te)) {
+            cells[n] = c;
+            lengths[n] = len;
+            t_in[n] = t;
+            ++n;
+            t = te;
+        }
+        c = nx;
+    }
+    return n;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One radiative-transfer pass                                               */
 /* ------------------------------------------------------------------------ */
@@ -548,9 +610,9 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
         double te;
         int64_t next = orc_step(m, c, xs, n, &te);
         double len = te > t ? te - t : 0.0;
-        /* a segment shorter than 1e-6 (cell side + exit distance) is a graze of
-         * an edge or corner: nothing is deposited and no decision is taken */
-        if (len > 1e-6 * (m->side[c] + te)) {
+        /* a graze of an edge or corner: nothing is deposited, no decision is
+         * taken and t is not advanced */
+        if (!orc_is_graze(len, te)) {
             double t_in = t;
             double dc2 = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -638,6 +700,33 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
     }
 }
 
+/* Luminosity source s emits at wavelength l in this pass: 4 pi j V for the
+ * direct light and step 1, the pending scattered luminosity of the cell summed
+ * over its j_sca pixels in a scattering pass. */
+static double orc_emitted(const orc_model *m, int mode, const double *S_pending, int64_t s, int l)
+{
+    const orc_grid_desc *d = &m->d;
+    if (mode != ORC_SCATTER)
+        return 4.0 * M_PI * d->emis[(int64_t)l * d->n_leaves + s] * m->side[s] * m->side[s] * m->side[s];
+    int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
+    double e = 0.0;
+    for (int64_t q = 0; q < npix; ++q) e += S_pending[m->s_offset[l] + s * npix + q];
+    return e;
+}
+
+/* N_s of Eq. 11: the radiation sources of the pass in the whole model (cells
+ * emitting at some wavelength), whatever subset of them a pass traces. */
+int64_t orc_count_sources(const orc_model *m, int mode, const double *S_pending)
+{
+    int64_t ns = 0;
+    for (int64_t s = 0; s < m->d.n_leaves; ++s) {
+        int any = 0;
+        for (int l = 0; l < m->d.n_lambda && !any; ++l) any = orc_emitted(m, mode, S_pending, s, l) > 0.0;
+        ns += any;
+    }
+    return ns;
+}
+
 /* Run one pass.  Outputs (overwritten): U_k [n_lambda][n], S_next [S size]
  * (untouched in step 1), tally [n_lambda][8], counters [8], and escape
  * [n_lambda][12 nside^2] when not NULL: the luminosity leaving the root block,
@@ -653,6 +742,14 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     if (o->adaptive && (o->nside_max < o->nside || !is_pow2(o->nside_max) || !(o->n_rays_min > 0.0))) return ORC_E_INVALID;
     if (o->mode == ORC_SCATTER && !S_pending) return ORC_E_INVALID;
     if (o->adaptive && o->mode != ORC_STEP1 && !U_LL) return ORC_E_INVALID;
+    orc_pass_opts eff = *o;
+    if (o->adaptive && o->mode != ORC_STEP1 && o->f_U < 0.0) {
+        /* Eq. 11: f_U = 4 a_RT / N_s */
+        if (!(o->a_RT > 0.0)) return ORC_E_INVALID;
+        int64_t ns = orc_count_sources(m, o->mode, S_pending);
+        eff.f_U = ns > 0 ? 4.0 * o->a_RT / (double)ns : 0.0;
+    }
+    o = &eff;
     int64_t ssize = m->s_offset[nl];
     int64_t wsize = ssize / n;
     int nthreads = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
@@ -702,18 +799,10 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
 #pragma omp for schedule(dynamic, 1)
             for (int64_t s = 0; s < n; ++s) {
                 if (o->source_mask && !o->source_mask[s]) continue;
-                if (o->mode == ORC_STEP1 && o->adaptive == 0) { /* step 1 only makes sense with R_pre */ }
                 /* emitted luminosity of this source */
                 double emitted_any = 0.0;
                 for (int l = 0; l < nl; ++l) {
-                    double e;
-                    if (o->mode != ORC_SCATTER) {
-                        e = 4.0 * M_PI * d->emis[(int64_t)l * n + s] * m->side[s] * m->side[s] * m->side[s];
-                    } else {
-                        int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
-                        e = 0.0;
-                        for (int64_t q = 0; q < npix; ++q) e += S_pending[m->s_offset[l] + s * npix + q];
-                    }
+                    double e = orc_emitted(m, o->mode, S_pending, s, l);
                     th.tally[l * N_TALLY + T_EMITTED] += e;
                     emitted_any += e;
                 }
@@ -843,7 +932,8 @@ int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S
                 for (int64_t r = 0; r < nray; ++r) {
                     double nvec[3];
                     orc_ray_dir(o, nside, r, nvec);
-                    int64_t nc = orc_trace_cells(m, xs, nvec, 0.0, maxc, cells, lens, tins);
+                    /* the crossings of the forward pass: grazes skipped and folded */
+                    int64_t nc = orc_crossings(m, xs, nvec, 0.0, maxc, cells, lens, tins);
                     for (int l = 0; l < nl; ++l)
                         orc_hg_weights_tab(12 * (int64_t)m->nside_sca[l] * m->nside_sca[l], pv + 3 * (m->s_offset[l] / n),
                                            d->g[l], nvec, w + m->s_offset[l] / n);
@@ -855,20 +945,17 @@ int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S
                         const double kap = d->kappa[l], om = d->albedo[l], cl = d->c_light;
                         int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
                         const double *wl = w + m->s_offset[l] / n;
-                        /* forward: luminosity at entry of each (non-graze) crossing */
+                        /* forward: luminosity at entry of each crossing */
                         double L = L0;
                         for (int64_t k = 0; k < nc; ++k) {
-                            int64_t c = cells[k];
-                            double te = tins[k] + lens[k];
                             Lm[k] = L;
-                            if (lens[k] > 1e-6 * (m->side[c] + te)) L *= exp(-kap * d->rho[c] * lens[k]);
+                            L *= exp(-kap * d->rho[cells[k]] * lens[k]);
                         }
                         /* backward suffix recursion from the escaping end */
                         double G = Ebar ? Ebar[(int64_t)l * nray + r] : 0.0;
                         for (int64_t k = nc - 1; k >= 0; --k) {
                             int64_t c = cells[k];
-                            double len = lens[k], te = tins[k] + len;
-                            if (!(len > 1e-6 * (m->side[c] + te))) continue;
+                            double len = lens[k];
                             double vol = m->side[c] * m->side[c] * m->side[c];
                             double tau = kap * d->rho[c] * len;
                             double em = exp(-tau), E, dE;

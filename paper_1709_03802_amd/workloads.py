@@ -109,7 +109,8 @@ class RayPolicy:
     nside: int = 8              # fixed mode: ray Nside; adaptive: initial Nside
     nside_max: int = 8          # adaptive: highest ray Nside
     n_rays_min: float = 4.0     # adaptive: N_rays of Eq. 2
-    f_U: float = 0.0            # adaptive: blocking threshold of Eq. 1
+    f_U: float = 0.0            # adaptive: blocking threshold of Eq. 1; < 0 selects Eq. 11
+    a_RT: float = 0.0           # adaptive: accuracy parameter of Eq. 11 (f_U = 4 a_RT / N_s)
     r_pre: float = 0.0          # adaptive: step-1 extent
     step1: bool = False         # run step 1 (lower-limit RFED) first
     n_scatter: int = 2          # scattering iterations after the direct pass (the most run)
