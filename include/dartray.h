@@ -28,9 +28,15 @@
  *    batch uploads its arguments: those synchronise that stream.
  *  - One grid handle must not be used by two threads or streams at once.
  *  - Precision: ray geometry (positions, directions, exit distances) in
- *    FP64; luminosities, attenuation and deposits in FP32; energy-density
- *    accumulators, the luminosity tallies, the escape by direction and the
- *    convergence ratio in FP64.
+ *    FP64; luminosities, attenuation and deposits in FP32, except that the
+ *    adaptive direct and scattering passes carry each ray's luminosity in
+ *    FP64 for their significance decisions; energy-density accumulators, the
+ *    luminosity tallies, the escape by direction and the convergence ratio
+ *    in FP64.
+ *  - Non-finite results: every pass records in a device word whether all of
+ *    its U and S values are finite; the calls that synchronise anyway (r_k
+ *    requested, adaptive passes) and every call with DARTRAY_FLAG_CHECK read
+ *    it and return DARTRAY_E_NUMERIC when one was not.
  */
 #ifndef DARTRAY_H
 #define DARTRAY_H
@@ -57,6 +63,8 @@ extern "C" {
 
 /* option flags */
 #define DARTRAY_FLAG_COUNTERS 1u    /* fill fields->counters */
+#define DARTRAY_FLAG_CHECK 2u       /* synchronise after the pass and return DARTRAY_E_NUMERIC
+                                       if it produced a non-finite U or S value */
 
 /* tally slots, per wavelength, FP64, in luminosity units */
 #define DARTRAY_T_EMITTED 0         /* luminosity launched by the pass's sources */
@@ -68,7 +76,8 @@ extern "C" {
 #define DARTRAY_N_TALLY 8
 
 /* counter slots (uint64) */
-#define DARTRAY_C_CROSSINGS 0       /* traversed crossings longer than 1e-6 (cell side + distance) */
+#define DARTRAY_C_CROSSINGS 0       /* traversed crossings (edge and corner grazes, zero
+                                       length up to FP64 rounding, excluded) */
 #define DARTRAY_C_RAYS 1            /* rays launched from sources */
 #define DARTRAY_C_SPLITS 2          /* rays replaced by 4 children (Eq. 2) */
 #define DARTRAY_C_CUTS 3            /* rays blocked */
@@ -99,6 +108,8 @@ typedef struct dartray_grid dartray_grid;   /* opaque handle */
  * apply the resolution rule of Eq. 5-6 with n_fwhm and the cap k_max).
  * Values must be finite, rho and emis >= 0, 0 <= albedo <= 1, |g| < 1,
  * nside_sca <= 8; n_leaves * n_lambda < 2^32 (DARTRAY_E_UNSUPPORTED above).
+ * The Eq. 5 rule is applied with k_max <= 3 (Nside_sca <= 8): a larger k_max
+ * with some nside_sca = 0 gives DARTRAY_E_UNSUPPORTED.
  */
 typedef struct {
     int32_t nroot[3];
@@ -136,11 +147,17 @@ typedef struct {
  *   wavelengths below the threshold skip their deposits (Sect. 3.2).  In step
  *   1 the significance test is "entry distance < r_pre" and rays are cut at
  *   r_pre.  f_U < 0 selects f_U = 4 a_RT / N_s (Eq. 11) with N_s the number
- *   of sources of the pass.
+ *   of radiation sources of the pass in the whole model (cells that emit at
+ *   some wavelength, whether or not source_mask selects them).  The
+ *   significance decisions are taken in FP64 (the ray's FP64 launch
+ *   luminosity attenuated by its FP64 column density).
  * frame: row-major rotation applied to every HEALPix direction (rays and
  *   scattered-light pixels alike); identity when all zero.
- * source_mask: optional device uint8[n]; sources with 0 are skipped (direct
- *   pass and step 1 only).  Used for source-subset runs.
+ * source_mask: optional device uint8[n]; sources with 0 are skipped, in
+ *   step 1, the direct pass and the scattering iterations alike (the
+ *   emitted tally counts the selected sources only).  The passes are
+ *   additive over sources (Sect. 3.4), so complementary masks add up to the
+ *   unmasked pass when the other inputs (U_LL, S_pending) are the same.
  * max_steps: per-ray crossing limit (0 = unlimited); rays hitting it stop and
  *   are counted in DARTRAY_C_MAXSTEP.
  */
@@ -149,10 +166,10 @@ typedef struct {
     int32_t adaptive;
     int32_t nside;
     int32_t nside_max;
-    float n_rays_min;
-    float f_U;
-    float a_RT;
-    float r_pre;
+    double n_rays_min;
+    double f_U;
+    double a_RT;
+    double r_pre;
     double frame[9];
     const uint8_t *source_mask;  /* device, nullable */
     uint32_t flags;              /* DARTRAY_FLAG_* */
@@ -244,23 +261,31 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
  *             pending scattered luminosity iteration k processed (S_pending
  *             before that dartray_scatter_iter call), S layout
  *  dJ_dU      device float [n_lambda][n], or NULL for a loss without U
+ *  dJ_dS      device float, S layout, or NULL: the derivative with respect
+ *             to S_total, the scattered luminosity of every order (for a loss
+ *             on j_sca = S_total / (V 4 pi / N_pix), dJ/dS = dJ/dj_sca /
+ *             (V 4 pi / N_pix)); every order's S receives it
  *  dJ_desc    device float [n_lambda][12 nside^2], or NULL for a loss
  *             without the escaping luminosity (it enters each ray as the
  *             terminal value of the reverse recursion)
  *  dJ_drho    device float [n], overwritten
  */
 int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, int32_t n_scatter,
-                          const float *const *S_hist, const float *dJ_dU, const float *dJ_desc, float *dJ_drho);
+                          const float *const *S_hist, const float *dJ_dU, const float *dJ_dS,
+                          const float *dJ_desc, float *dJ_drho);
 
 /*
  * Test helper: the cells crossed by n_rays rays (host arrays: origin[3i],
- * dir[3i], in grid coordinates), computed by the device traversal.  Up to
- * max_cross crossings per ray are written to cells[i * max_cross + m] (leaf id)
- * and lengths[...] (path length, 0 for zero-length segments); counts[i] gets
- * the number written.  Synchronises the stream.
+ * dir[3i], in grid coordinates), computed by the marches' own FP64 traversal
+ * (exit distances, face-neighbour steps and tie rules of Sect. 2 as the
+ * passes walk rays).  Up to max_cross segments per ray are written to
+ * cells[i * max_cross + m] (leaf id) and lengths[...] (FP64 path length, 0
+ * for zero-length segments, which are listed); counts[i] gets the number
+ * written.  Allocates and frees small device buffers; synchronises the
+ * stream.
  */
 int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *origin, const double *dir,
-                            int32_t max_cross, int64_t *cells, float *lengths, int32_t *counts);
+                            int32_t max_cross, int64_t *cells, double *lengths, int32_t *counts);
 
 /* Timing of the ray-march kernels with HIP events recorded on the grid's
  * stream around every march launch of the selected kinds.  kinds is a mask of
@@ -277,8 +302,11 @@ int dartray_profile_enable(dartray_grid *grid, int32_t kinds);
  * since recording started; synchronises the stream. */
 int dartray_profile_read(dartray_grid *grid, double *march_ms, int64_t *launches);
 
-/* Bytes of device work memory the handle holds. */
-int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes);
+/* Device memory: with opts NULL, every byte the handle holds; with opts, the
+ * bytes of the handle's work arrays that a pass with these options uses
+ * (accumulators, tables, direction bins or deposit log), beyond the caller's
+ * fields.  All of it is allocated by dartray_grid_create. */
+int dartray_workspace_bytes(const dartray_grid *grid, const dartray_trace_opts *opts, size_t *bytes);
 
 /*
  * Launch parameters of the fixed-ray passes (the autotuner's search space).

@@ -303,10 +303,11 @@ def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
 
 
 def adjoint(model: Model, policy, run_result, Ubar=None, Sbar_last=None, frame=None, source_mask=None, n_threads=0,
-            Ebar=None):
+            Ebar=None, Sbar_total=None):
     """dJ/drho for a loss J(U, S_total, F) given dJ/dU (and optionally dJ/dS of
-    the last, unprocessed order, and dJ/dF for the escaping luminosity F summed
-    over the passes, [n_lambda][12 nside^2]), by reverse passes over a
+    the last, unprocessed order, dJ/dS_total -- S_total = S_1 + ... + S_{K+1},
+    so every order receives it -- and dJ/dF for the escaping luminosity F
+    summed over the passes, [n_lambda][12 nside^2]), by reverse passes over a
     fixed-ray run."""
     if Ubar is None:
         Ubar = np.zeros((model.nl, model.n))
@@ -315,7 +316,14 @@ def adjoint(model: Model, policy, run_result, Ubar=None, Sbar_last=None, frame=N
     rho_bar = np.zeros(model.n)
     passes = [r for r in run_result.passes]
     pend = [None] + [passes[k - 1].S for k in range(1, len(passes))]   # emission of pass k
-    Sbar = None if Sbar_last is None else np.ascontiguousarray(Sbar_last, dtype=np.float64)
+    St = None if Sbar_total is None else np.ascontiguousarray(Sbar_total, dtype=np.float64)
+
+    def plus(a, b):
+        if a is None:
+            return b
+        return a if b is None else np.ascontiguousarray(a + b)
+
+    Sbar = plus(None if Sbar_last is None else np.ascontiguousarray(Sbar_last, dtype=np.float64), St)
     for k in range(len(passes) - 1, -1, -1):
         mode = DIRECT if k == 0 else SCATTER
         o, keep = _opts(mode, policy, frame, source_mask if k == 0 else None, n_threads)
@@ -327,7 +335,7 @@ def adjoint(model: Model, policy, run_result, Ubar=None, Sbar_last=None, frame=N
                                     _p(rho_bar, C.c_double), _p(Sbar_k, C.c_double))
         if rc != 0:
             raise ValueError(f"oracle adjoint failed (status {rc})")
-        Sbar = Sbar_k[:model.s_size] if k > 0 else None
+        Sbar = plus(Sbar_k[:model.s_size], St) if k > 0 else None
     return rho_bar
 
 

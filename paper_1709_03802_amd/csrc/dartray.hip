@@ -213,30 +213,35 @@ __global__ void k_invz(float *invz, const LambdaTable *lt, const double *sca64, 
 // ---------------------------------------------------------------------------
 
 // Direct pass: flag the cells (Morton order) that emit at some wavelength
-// and are allowed by the mask; sum the launched luminosity per wavelength.
+// and are allowed by the mask; sum the launched luminosity per wavelength;
+// count every emitting cell, mask or not (N_s of Eq. 11).
 __global__ void k_source_flags(int32_t *flags, const int32_t *morton, int64_t n, const LambdaTable *lt,
-                               const float *emis_lum, const uint8_t *mask, double *tally)
+                               const float *emis_lum, const uint8_t *mask, double *tally, int32_t *n_all)
 {
     __shared__ double sh[16];
     const int nl = lt->n_lambda;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t c = i < n ? morton[i] : -1;
-    bool any = false;
+    bool emits = false;
     const bool allowed = c >= 0 && (mask == nullptr || mask[c] != 0);
     for (int l = 0; l < nl; ++l) {
-        const double e = allowed ? (double)emis_lum[(int64_t)l * n + c] : 0.0;
-        any |= e > 0.0;
-        const double b = block_sum(e, sh);
+        const double e = c >= 0 ? (double)emis_lum[(int64_t)l * n + c] : 0.0;
+        emits |= e > 0.0;
+        const double b = block_sum(allowed ? e : 0.0, sh);
         if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_EMITTED], b);
     }
-    if (i < n) flags[i] = any ? 1 : 0;
+    if (i < n) flags[i] = (emits && allowed) ? 1 : 0;
+    const uint64_t em = __ballot(emits);
+    if ((threadIdx.x & 63) == 0 && em) atomicAdd(n_all, (int32_t)__popcll(em));
 }
 
 // Scattering pass, step 1: a coalesced sweep of wavelength blockIdx.y's block
 // of the pending scattered luminosity flags every cell with a positive entry
-// (cell_flag indexed by cell) and sums the block in FP64.  S is never
-// negative, so a positive entry is the same as a positive row sum.
-__global__ void k_sflag_sweep(const float *S, const LambdaTable *lt, uint8_t *cell_flag, double *tally)
+// (cell_flag indexed by cell) and sums the block over the cells the mask
+// allows in FP64.  S is never negative, so a positive entry is the same as a
+// positive row sum.
+__global__ void k_sflag_sweep(const float *S, const LambdaTable *lt, const uint8_t *mask, uint8_t *cell_flag,
+                              double *tally)
 {
     __shared__ double sh[16];
     const int l = blockIdx.y;
@@ -249,18 +254,26 @@ __global__ void k_sflag_sweep(const float *S, const LambdaTable *lt, uint8_t *ce
         if (v > 0.f) {
             const int64_t cell = small ? (int64_t)((uint32_t)(i - lo) / npix) : (i - lo) / (int64_t)npix;
             cell_flag[cell] = 1;
+            if (mask == nullptr || mask[cell] != 0) acc += (double)v;
         }
-        acc += (double)v;
     }
     const double b = block_sum(acc, sh);
     if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_EMITTED], b);
 }
 
-// Scattering pass, step 2: flags in Morton order for the compaction.
-__global__ void k_sflag_gather(int32_t *flags, const int32_t *morton, const uint8_t *cell_flag, int64_t n)
+// Scattering pass, step 2: flags in Morton order for the compaction (cells
+// holding scattered light that the mask allows), and the count of every cell
+// holding scattered light (N_s of Eq. 11).
+__global__ void k_sflag_gather(int32_t *flags, const int32_t *morton, const uint8_t *cell_flag, const uint8_t *mask,
+                               int64_t n, int32_t *n_all)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        flags[i] = cell_flag[morton[i]];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = morton[i];
+        const bool has = cell_flag[c] != 0;
+        flags[i] = (has && (mask == nullptr || mask[c] != 0)) ? 1 : 0;
+        const uint64_t hm = __ballot(has);
+        if ((threadIdx.x & 63) == 0 && hm) atomicAdd(n_all, (int32_t)__popcll(hm));
+    }
 }
 
 constexpr int kScanBlock = 1024;
@@ -379,17 +392,24 @@ __device__ inline int fine_coord(T p, T d)
     return i;
 }
 
+// A segment [t, te] of a ray whose length is zero up to the rounding of its
+// two end distances -- at most 2^-46 of the exit distance, a few tens of ulps
+// of an FP64 distance -- is a ray through an edge or corner of the cell
+// (zero length in exact arithmetic).  It deposits nothing, takes no decision
+// and does not advance the ray's distance, so the residue folds into the next
+// crossing.  Every march and the adjoint use this one rule.
+__host__ __device__ inline bool is_graze(double len, double te) { return !(len > 0x1p-46 * te); }
+
 // A ray in finest-level cell units.  The marches keep their geometry in FP64:
 // distances along a ray reach hundreds of cells, and the adaptive march takes
-// its split, block and step-1 extent decisions on these values.  The FP32
-// instance serves the debugging traversal only.
+// its split, block and step-1 extent decisions on these values.  The
+// debugging traversal runs the same FP64 instance.
 template <typename T>
 struct RayT {
     T o[3];       // origin (source-cell centre), fine units
     T n[3];       // unit direction
     T inv[3];     // 1/n (unused for zero components)
 };
-using Ray = RayT<float>;
 
 // exit distance from the leaf with box b along ray R, and the exit axis
 // (exact ties resolved x before y before z)
@@ -451,32 +471,35 @@ __device__ inline int32_t next_leaf(const Geo &g, const RayT<T> &R, const int4 b
     return -v - 1;
 }
 
+// The traversal of the marches (FP64 exit distances, face-neighbour steps)
+// for given rays: every segment, zero-length ones included.
 __global__ void k_debug_cells(Geo g, int nrays, const double *origin, const double *dir, int max_cross,
-                              int64_t *cells, float *lengths, int32_t *counts)
+                              int64_t *cells, double *lengths, int32_t *counts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrays) return;
-    Ray R;
-    float p[3];
+    RayT<double> R;
     for (int a = 0; a < 3; ++a) {
-        R.o[a] = (float)origin[3 * i + a];
-        R.n[a] = (float)dir[3 * i + a];
-        R.inv[a] = 1.0f / R.n[a];
-        p[a] = R.o[a];
+        R.o[a] = origin[3 * i + a];
+        R.n[a] = dir[3 * i + a];
+        R.inv[a] = 1.0 / R.n[a];
     }
-    int32_t c = locate_fine(g, fine_coord(p[0], R.n[0]), fine_coord(p[1], R.n[1]), fine_coord(p[2], R.n[2]));
-    float t = 0.f;
+    int32_t c = locate_fine(g, fine_coord<double>(R.o[0], R.n[0]), fine_coord<double>(R.o[1], R.n[1]),
+                            fine_coord<double>(R.o[2], R.n[2]));
+    double t = 0.0;
     int m = 0;
     while (c >= 0 && m < max_cross) {
         const LeafRec &rc = g.rec[c];
         const int4 b = rc.box;
+        int32_t nbc[6];
+        for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
         int axis;
-        const float te = exit_t(R, b, axis);
+        const double te = exit_t<double>(R, b, axis);
         cells[(int64_t)i * max_cross + m] = c;
-        lengths[(int64_t)i * max_cross + m] = te > t ? te - t : 0.f;
+        lengths[(int64_t)i * max_cross + m] = te > t ? te - t : 0.0;
         ++m;
         if (te > t) t = te;
-        c = next_leaf(g, R, b, rc.nb, axis, te);
+        c = next_leaf<double>(g, R, b, nbc, axis, te);
     }
     counts[i] = m;
 }
@@ -627,7 +650,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
             int axis;
             const double te = exit_t(R, b, axis);
             const double len = te - t;
-            if (len > 1e-6 * ((double)b.w + te)) {   // shorter segments are grazes
+            if (!is_graze(len, te)) {
                 const float lp = (float)(len * A.h_fine);
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
@@ -997,8 +1020,10 @@ struct AdaptArgs {
     const double4 *dirs64;       // all-level direction table (FP64; ray geometry)
     const float *invz;           // [entry][n_lambda]
     const float *emis_lum;
+    const double *lum64;         // [n_lambda][n] 4 pi j V in FP64 (direct pass launch)
     const float *S_pending;
     const float *ull_t;          // [n][n_lambda] copy of U_LL
+    const int32_t *n_all;        // sources of the pass in the whole model (N_s of Eq. 11)
     const LambdaTable *lt;
     double *U_k;
     float *S_next;
@@ -1017,13 +1042,11 @@ struct AdaptArgs {
     int32_t nside0;
     int32_t log2_nside0;
     int32_t max_depth;           // levels above nside0 a ray may reach
-    float n_rays;                // N_rays of Eq. 2
-    float f_U;                   // < 0: 4 a_RT / N_s
-    float a_RT;
-    float r_pre_fine;            // step-1 extent in fine units
-    float h_fine;
-    float c_light;
-    double r_pre_fine64;
+    double n_rays;               // N_rays of Eq. 2
+    double f_U;                  // < 0: 4 a_RT / N_s (Eq. 11)
+    double a_RT;
+    double c_light;
+    double r_pre_fine64;         // step-1 extent in fine units
     double h_fine64;
     int64_t max_steps;
     int64_t hard_cap;
@@ -1042,7 +1065,7 @@ __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlan
 #define DR_WAVES_STEP1 4
 #endif
 #ifndef DR_WAVES_SCATTER
-#define DR_WAVES_SCATTER 1
+#define DR_WAVES_SCATTER 2
 #endif
 #ifndef DR_PENDING_MIN
 #define DR_PENDING_MIN 4
@@ -1093,14 +1116,24 @@ void k_march_adaptive(const AdaptArgs A)
     const int wbase = threadIdx.x & ~63;
     const int nsrc = *A.n_src;
     const uint64_t nitems = (uint64_t)nsrc * (uint64_t)(12 * A.nside0 * A.nside0);
-    const float f_U = A.f_U >= 0.f ? A.f_U : (nsrc > 0 ? 4.f * A.a_RT / (float)nsrc : 0.f);
+    double f_U = A.f_U;
+    if (!(f_U >= 0.0)) {
+        const int ns_all = *A.n_all;
+        f_U = ns_all > 0 ? 4.0 * A.a_RT / (double)ns_all : 0.0;
+    }
 
     float skp[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) skp[l] = 0.f;
     uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_skip = 0, n_max = 0;
 
-    // ray state
+    // ray state.  Step 1 carries the ray's luminosity in FP32 (its decisions
+    // are geometric).  The passes that take per-wavelength significance
+    // decisions (Eq. 1 / Eq. 8) carry the item's FP64 launch luminosity L0
+    // and the column density N = sum rho l from the source to the ray's
+    // position: the luminosity at any point is L0 4^-depth e^{-kappa N}, in
+    // FP64 as in the oracle, so no decision rests on FP32 rounding or
+    // underflow.
     bool has_ray = false, has_item = false, pending = false, done = false;
     int32_t s = 0;
     double o[3] = {0.0, 0.0, 0.0};
@@ -1110,14 +1143,24 @@ void k_march_adaptive(const AdaptArgs A)
     int32_t c = -1;
     int64_t e = 0;                 // direction table entry of the ray
     RayT<double> R;
-    float L[NL];
+    float L[STEP1 ? NL : 1];
+    double L0[STEP1 ? 1 : NL];
+    double colN = 0.0;             // column density, physical length units
     double st_t[kMaxDepthAdaptive + 1];
     int32_t st_c[kMaxDepthAdaptive + 1];   // cell in which the level's parent split
-    float st_L[kMaxDepthAdaptive + 1][NL];
+    float st_L[STEP1 ? kMaxDepthAdaptive + 1 : 1][STEP1 ? NL : 1];
+    double st_N[STEP1 ? 1 : kMaxDepthAdaptive + 1];
     int64_t steps = 0;
     double omega_hp = 0.0;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) L[l] = 0.f;
+    for (int l = 0; l < (STEP1 ? NL : 1); ++l) L[l] = 0.f;
+#pragma unroll
+    for (int l = 0; l < (STEP1 ? 1 : NL); ++l) L0[l] = 0.0;
+    // luminosity the ray carries at its current position, wavelength l
+    auto lum = [&](int l) -> double {
+        if constexpr (STEP1) return (double)L[l];
+        else return L0[l] * ldexp(1.0, -2 * depth) * exp(-(double)s_kap[l] * colN);
+    };
 
     while (true) {
         // ---- lanes without a ray: next sibling from the stack
@@ -1129,8 +1172,12 @@ void k_march_adaptive(const AdaptArgs A)
             if (depth > 0) {
                 ++pix;
                 t = st_t[depth];
+                if constexpr (STEP1) {
 #pragma unroll
-                for (int l = 0; l < NL; ++l) L[l] = st_L[depth][l];
+                    for (int l = 0; l < NL; ++l) L[l] = st_L[depth][l];
+                } else {
+                    colN = st_N[depth];
+                }
                 pending = true;
             } else {
                 has_item = false;
@@ -1176,34 +1223,47 @@ void k_march_adaptive(const AdaptArgs A)
                     o[0] = (double)sb.x + half;
                     o[1] = (double)sb.y + half;
                     o[2] = (double)sb.z + half;
-                    float lsum = 0.f;
-                    const float inv_nray0 = 1.f / (float)(12 * A.nside0 * A.nside0);
+                    double lsum = 0.0;
+                    if constexpr (STEP1) {
+                        const float inv_nray0 = 1.f / (float)(12 * A.nside0 * A.nside0);
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        float v = 0.f;
-                        if (l < nl) {
-                            if (MODE != 2) {
-                                v = A.emis_lum[(int64_t)l * A.n + s] * inv_nray0;
-                            } else {
-                                const int npix = lt->npix[l];
-                                const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
-                                const int ls = 31 - __clz(lt->nside_sca[l]);
-                                if (A.log2_nside0 >= ls) {
-                                    v = row[r0 >> (2 * (A.log2_nside0 - ls))] * ((float)npix * inv_nray0);
+                        for (int l = 0; l < NL; ++l) {
+                            L[l] = l < nl ? A.emis_lum[(int64_t)l * A.n + s] * inv_nray0 : 0.f;
+                            lsum += (double)L[l];
+                        }
+                    } else {
+                        // launch luminosity in FP64: 4 pi j V / N_ray (direct light), or
+                        // S N_pix / N_ray from the pixel holding the ray (scattered light;
+                        // the sum over the pixels inside the ray when rays are coarser)
+                        const double nray0 = 12.0 * (double)A.nside0 * (double)A.nside0;
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) {
+                            double v = 0.0;
+                            if (l < nl) {
+                                if (MODE != 2) {
+                                    v = A.lum64[(int64_t)l * A.n + s] / nray0;
                                 } else {
-                                    const int sh = 2 * (ls - A.log2_nside0);
-                                    for (int q = r0 << sh; q < ((r0 + 1) << sh); ++q) v += row[q];
+                                    const int npix = lt->npix[l];
+                                    const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
+                                    const int ls = 31 - __clz(lt->nside_sca[l]);
+                                    if (A.log2_nside0 >= ls) {
+                                        v = (double)row[r0 >> (2 * (A.log2_nside0 - ls))] * (double)npix / nray0;
+                                    } else {
+                                        const int sh = 2 * (ls - A.log2_nside0);
+                                        for (int q = r0 << sh; q < ((r0 + 1) << sh); ++q) v += (double)row[q];
+                                    }
                                 }
                             }
+                            L0[l] = v;
+                            lsum += v;
                         }
-                        L[l] = v;
-                        lsum += v;
+                        colN = 0.0;
                     }
                     has_item = true;
                     depth = 0;
                     pix = r0;
                     t = 0.0;
-                    if (lsum > 0.f) {
+                    if (lsum > 0.0) {
                         ++n_rays;
                         pending = true;
                     }
@@ -1249,7 +1309,7 @@ void k_march_adaptive(const AdaptArgs A)
             } else {
 #pragma unroll
                 for (int l = 0; l < NL; ++l)
-                    if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
+                    if (l < nl) atomicAdd(&s_esc[l], lum(l));
                 ++n_esc;
             }
         }
@@ -1282,7 +1342,7 @@ void k_march_adaptive(const AdaptArgs A)
             }
             const double len = te - t;
             int action = 0;   // 0 continue, 1 split, 2 cut
-            if (len > 1e-6 * ((double)b.w + te)) {   // shorter segments are grazes: no deposit, no decision
+            if (!is_graze(len, te)) {
                 const double t_in = t;
                 // source-to-cell-centre offsets are exact half-integers in fine units
                 const double dx = ((double)b.x + 0.5 * (double)b.w - o[0]);
@@ -1292,25 +1352,41 @@ void k_march_adaptive(const AdaptArgs A)
                 const double d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
                 const double side = (double)b.w * h;
                 const float lp = (float)(len * h);
-                float em1[NL];
+                // step 1: e^{-tau} - 1 per wavelength (FP32); other passes: the
+                // energy-density deposit and the extinguished luminosity of the
+                // crossing, computed in FP64 and rounded once
+                float em1[STEP1 ? NL : 1];
+                float du32[STEP1 ? 1 : NL], ext32[STEP1 ? 1 : NL];
                 uint32_t sigm = 0;
-                const float thr = (float)(f_U * omega_hp * d2 * A.c_light);
                 const float *ull = A.ull_t + (int64_t)c * nl;
 #pragma unroll
                 for (int l = 0; l < NL; ++l) {
-                    em1[l] = 0.f;
-                    if (l < nl) {
-                        const float tau = s_kap[l] * rho_c * lp;
-                        bool thick;
-                        float tr;
-                        em1[l] = fast_em1(tau, thick, tr);
-                        bool sg = true;
-                        if (!STEP1) {
-                            const float ext = -L[l] * em1[l];
-                            const float lavg = tau > 0.f ? ext / tau : L[l];
-                            sg = lavg > 0.f && (d2 == 0.0 || lavg >= thr * ull[l]);
+                    if constexpr (STEP1) {
+                        em1[l] = 0.f;
+                        if (l < nl) {
+                            const float tau = s_kap[l] * rho_c * lp;
+                            bool thick;
+                            float tr;
+                            em1[l] = fast_em1(tau, thick, tr);
+                            sigm |= 1u << l;
                         }
-                        sigm |= (uint32_t)sg << l;
+                    } else {
+                        du32[l] = 0.f;
+                        ext32[l] = 0.f;
+                        if (l < nl) {
+                            // Eq. 8 estimate <L> / (Omega_HP d^2 c) against f_U U_LL (Eq. 1), in FP64
+                            const double lenp = len * h;
+                            const double alpha = (double)s_kap[l] * (double)rho_c;
+                            const double tau = alpha * lenp;
+                            const double Lin = lum(l);
+                            const double ext = Lin * -expm1(-tau);
+                            const double lavg = tau > 0.0 ? ext / tau : Lin;
+                            const bool sg = lavg > 0.0 &&
+                                            (d2 == 0.0 || lavg / (omega_hp * d2 * A.c_light) >= f_U * (double)ull[l]);
+                            sigm |= (uint32_t)sg << l;
+                            ext32[l] = (float)ext;
+                            du32[l] = (float)((alpha > 0.0 ? ext / alpha : Lin * lenp) * (double)rc.ivc);
+                        }
                     }
                 }
                 if (STEP1 && t_in >= A.r_pre_fine64) {
@@ -1325,10 +1401,14 @@ void k_march_adaptive(const AdaptArgs A)
                     ++depth;
                     st_t[depth] = t_in;
                     st_c[depth] = c;
+                    if constexpr (STEP1) {
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        L[l] *= 0.25f;
-                        st_L[depth][l] = L[l];
+                        for (int l = 0; l < NL; ++l) {
+                            L[l] *= 0.25f;
+                            st_L[depth][l] = L[l];
+                        }
+                    } else {
+                        st_N[depth] = colN;   // children restart with the column density of the split point
                     }
                     pix = 4 * pix;
                     t = t_in;
@@ -1338,7 +1418,7 @@ void k_march_adaptive(const AdaptArgs A)
                     ++n_cut;
 #pragma unroll
                     for (int l = 0; l < NL; ++l)
-                        if (l < nl) atomicAdd(&s_cut[l], (double)L[l]);
+                        if (l < nl) atomicAdd(&s_cut[l], lum(l));
                     has_ray = false;
                 } else {
                     const float ivc = rc.ivc;
@@ -1351,33 +1431,38 @@ void k_march_adaptive(const AdaptArgs A)
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
                         if (l < nl) {
-                            const float ext = -L[l] * em1[l];
-                            float Fl = 0.f;
-                            float du = 0.f;
-                            if ((sigm >> l) & 1u) {
+                            if constexpr (STEP1) {
+                                const float ext = -L[l] * em1[l];
                                 const float alpha = s_kap[l] * rho_c;
-                                du = alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
+                                s_du[l][dslot] = alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
                                 ++n_dep;
-                                if (!STEP1) Fl = s_alb[l] * ext * izr[l] * s_hgA[l];
-                            } else {
-                                skp[l] += ext;
-                                ++n_skip;
-                            }
-                            if (!STEP1) {
-                                s_F[l][threadIdx.x] = Fl;
-                                deposit |= Fl != 0.f;
-                            }
-                            s_du[l][dslot] = du;
-                            {
                                 // transmission, fused; e^{-tau} again in thick cells (1 + em1 cancels)
-                                const float tau = s_kap[l] * rho_c * lp;
+                                const float tau = alpha * lp;
                                 L[l] = tau < 0.5f ? fmaf(L[l], em1[l], L[l])
                                                   : L[l] * __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
+                            } else {
+                                float Fl = 0.f;
+                                float du = 0.f;
+                                if ((sigm >> l) & 1u) {
+                                    du = du32[l];
+                                    ++n_dep;
+                                    Fl = s_alb[l] * ext32[l] * izr[l] * s_hgA[l];
+                                } else {
+                                    skp[l] += ext32[l];
+                                    ++n_skip;
+                                }
+                                s_F[l][threadIdx.x] = Fl;
+                                deposit |= Fl != 0.f;
+                                s_du[l][dslot] = du;
                             }
                         }
                     }
-                    if (!STEP1 && deposit)
-                        s_dep[threadIdx.x] = make_float4((float)R.n[0], (float)R.n[1], (float)R.n[2], __int_as_float(c));
+                    if constexpr (!STEP1) {
+                        colN += (double)rho_c * (len * h);   // the crossing attenuates every wavelength
+                        if (deposit)
+                            s_dep[threadIdx.x] =
+                                make_float4((float)R.n[0], (float)R.n[1], (float)R.n[2], __int_as_float(c));
+                    }
                     t = te;
                 }
             }
@@ -1387,7 +1472,7 @@ void k_march_adaptive(const AdaptArgs A)
                 if (nx < 0) {
 #pragma unroll
                     for (int l = 0; l < NL; ++l)
-                        if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
+                        if (l < nl) atomicAdd(&s_esc[l], lum(l));
                     ++n_esc;
                     has_ray = false;
                 } else if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
@@ -1891,7 +1976,7 @@ void k_march_adjoint(const AdjArgs A)
                 int axis;
                 const double te = exit_t(R, b, axis);
                 const double len = te - t;
-                if (len > 1e-6 * ((double)b.w + te)) {
+                if (!is_graze(len, te)) {
                     const float rho = rc.rho;
                     const float ivc = rc.ivc;
                     const float lp = (float)(len * A.h_fine);
@@ -1957,6 +2042,12 @@ void k_march_adjoint(const AdjArgs A)
     }
 }
 
+__global__ void k_add_f32(float *a, const float *b, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] += b[i];
+}
+
 __global__ void k_to_f32(const double *a, float *out, int64_t n)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1971,15 +2062,24 @@ __global__ void k_rho_out(const double *rb, float *out, int64_t n)
 
 // U += U_k (and U_pass = U_k), absorbed / scattered tallies from U_k in FP64,
 // U_LL <- U when requested.  grid.y = wavelength
+// bit 0 of the device error word when any lane saw a non-finite value
+__device__ inline void flag_nonfinite(bool bad, uint32_t *err)
+{
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(err, 1u);
+}
+
 __global__ void k_finish_u(const double *U_k, float *U, float *U_pass, float *U_LL, int set_ull, int ull_only,
-                           const LambdaTable *lt, const float *rho, const float *inv_vc, int64_t n, double *tally)
+                           const LambdaTable *lt, const float *rho, const float *inv_vc, int64_t n, double *tally,
+                           uint32_t *err)
 {
     __shared__ double sh[16];
     const int l = blockIdx.y;
     double ext = 0.0;
+    bool bad = false;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = (int64_t)l * n + c;
         const double ukd = U_k[c * lt->n_lambda + l];
+        bad |= !isfinite(ukd);
         const float uk = (float)ukd;
         if (ull_only) {
             U_LL[i] = uk;
@@ -1991,6 +2091,7 @@ __global__ void k_finish_u(const double *U_k, float *U, float *U_pass, float *U_
         }
         ext += (double)lt->kappa[l] * (double)rho[c] / (double)inv_vc[c] * ukd;
     }
+    flag_nonfinite(bad, err);
     const double b = block_sum(ext, sh);
     if (threadIdx.x == 0 && b != 0.0) {
         const double om = lt->albedo[l];
@@ -2001,18 +2102,21 @@ __global__ void k_finish_u(const double *U_k, float *U, float *U_pass, float *U_
 
 // S_total (=|+=) S_next, S_pending = S_next, per-wavelength FP64 sums of S_next
 __global__ void k_finish_s(const float *S_next, float *S_total, float *S_pending, int accumulate,
-                           const LambdaTable *lt, int64_t s_size, double *ssum)
+                           const LambdaTable *lt, int64_t s_size, double *ssum, uint32_t *err)
 {
     __shared__ double sh[16];
     const int l = blockIdx.y;
     const int64_t lo = lt->s_off[l], hi = lt->s_off[l + 1];
     double acc = 0.0;
+    bool bad = false;
     for (int64_t i = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x) {
         const float v = S_next[i];
+        bad |= !isfinite(v);
         S_total[i] = accumulate ? S_total[i] + v : v;
         S_pending[i] = v;
         acc += v;
     }
+    flag_nonfinite(bad, err);
     const double b = block_sum(acc, sh);
     if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&ssum[l], b);
 }
@@ -2033,12 +2137,6 @@ __global__ void k_set_rho(LeafRec *rec, float *rho_arr, const float *rho, int64_
         rec[i].rho = rho[i];
         rho_arr[i] = rho[i];
     }
-}
-
-__global__ void k_check_finite(const float *a, int64_t n, int32_t *bad)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (!isfinite(a[i])) *bad = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -2063,7 +2161,7 @@ static int nside_from_rule(double g, double n_fwhm, int k_max)
     if (fwhm <= 0.0) return 1;
     const double tmin = fwhm / n_fwhm;
     double k = std::floor(0.5 * std::log2(4.0 * kPi / (12.0 * tmin * tmin)));
-    k = std::max(0.0, std::min((double)std::min(k_max, 3), k));   // Nside_sca <= 8
+    k = std::max(0.0, std::min((double)k_max, k));   // k_max <= 3 is checked at grid creation
     return 1 << (int)k;
 }
 
@@ -2096,7 +2194,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.U_k,
+    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.n_all, g.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.U_k,
                     g.flags, g.cell_flag, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -2126,6 +2224,9 @@ static int validate_desc(const dartray_grid_desc *d)
     if (d->nside_max < 0 || d->nside_max > kMaxNsideCap || (d->nside_max & (d->nside_max - 1)))
         return fail(DARTRAY_E_INVALID, "nside_max must be 0 or a power of two <= 1024");
     if (d->k_max < 0) return fail(DARTRAY_E_INVALID, "k_max must be >= 0");
+    for (int l = 0; l < d->n_lambda; ++l)
+        if (d->nside_sca[l] == 0 && d->k_max > 3)
+            return fail(DARTRAY_E_UNSUPPORTED, "the Eq. 5 rule is applied with k_max <= 3 (Nside_sca <= 8)");
     if (!(d->n_fwhm > 0.0)) {
         for (int l = 0; l < d->n_lambda; ++l)
             if (d->nside_sca[l] == 0) return fail(DARTRAY_E_INVALID, "n_fwhm must be > 0 with nside_sca = 0");
@@ -2289,11 +2390,16 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         lt.w_off[l + 1] = lt.w_off[l] + lt.npix[l];
     }
 
+    // luminosity 4 pi j V of each cell: FP64 (launch luminosity of the passes
+    // that take FP64 significance decisions) and rounded to FP32
     std::vector<float> emis_lum((size_t)(nl * n));
+    std::vector<double> lum64((size_t)(nl * n));
     for (int l = 0; l < nl; ++l)
         for (int64_t i = 0; i < n; ++i) {
             const double side = d->root_size / (double)((int64_t)1 << d->leaf_level[i]);
-            emis_lum[(size_t)(l * n + i)] = (float)(4.0 * kPi * (double)d->emis[(int64_t)l * n + i] * side * side * side);
+            const double v = 4.0 * kPi * (double)d->emis[(int64_t)l * n + i] * side * side * side;
+            lum64[(size_t)(l * n + i)] = v;
+            emis_lum[(size_t)(l * n + i)] = (float)v;
         }
 
     // --- device side ------------------------------------------------------
@@ -2331,7 +2437,8 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
         dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n), dalloc(g, &g.esc64, (size_t)nl * 12 * kMaxNsideWTable * kMaxNsideWTable),
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
-        dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
+        dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.lum64, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
+        dalloc(g, &g.n_all, 1), dalloc(g, &g.err_word, 1),
         dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.by_level, (size_t)n), dalloc(g, &g.d_lt, 1),
         dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
         dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
@@ -2395,6 +2502,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     cp(g.rho, rho_f.data(), sizeof(float) * n);
     cp(g.inv_vc, inv_vc.data(), sizeof(float) * n);
     cp(g.emis_lum, emis_lum.data(), sizeof(float) * nl * n);
+    cp(g.lum64, lum64.data(), sizeof(double) * nl * n);
     cp(g.root_tab, root_tab.data(), sizeof(int32_t) * nroot);
     cp(g.nodes, nodes.data(), sizeof(int32_t) * nodes.size());
     cp(g.morton, morton.data(), sizeof(int32_t) * n);
@@ -2458,10 +2566,29 @@ int dartray_profile_read(dartray_grid *grid, double *march_ms, int64_t *launches
     return DARTRAY_OK;
 }
 
-int dartray_workspace_bytes(const dartray_grid *grid, size_t *bytes)
+int dartray_workspace_bytes(const dartray_grid *grid, const dartray_trace_opts *opts, size_t *bytes)
 {
     if (!grid || !bytes) return fail(DARTRAY_E_INVALID, "null argument");
-    *bytes = grid->g.bytes;
+    const Grid &g = grid->g;
+    if (!opts) {
+        *bytes = g.bytes;
+        return DARTRAY_OK;
+    }
+    const size_t n = (size_t)g.n, nl = (size_t)g.n_lambda;
+    // every pass: FP64 energy-density accumulators, source selection, tables
+    size_t b = n * nl * sizeof(double) + n * (2 * sizeof(int32_t) + 1) + (size_t)g.ndir_all * (sizeof(float4) + sizeof(double4)) +
+               3 * (size_t)kScaDirs * sizeof(double);
+    const bool step1 = opts->adaptive && opts->mode == DARTRAY_MODE_STEP1;
+    if (!opts->adaptive) {
+        const int64_t nray = 12 * (int64_t)opts->nside * opts->nside;
+        const size_t nb = (size_t)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / std::max<size_t>(1, n * nl)));
+        b += nb * n * nl * sizeof(float) + (size_t)nray * (size_t)g.w_row * sizeof(float);
+    } else if (!step1) {
+        b += n * nl * sizeof(float) + (size_t)g.ndir_all * nl * sizeof(float);   // U_LL copy, phase normalisation
+        if (g.log_cap > 0)
+            b += (size_t)g.log_cap * (5 * sizeof(uint32_t) + nl * sizeof(float)) + g.sort_tmp_bytes;
+    }
+    *bytes = b;
     return DARTRAY_OK;
 }
 
@@ -2498,7 +2625,7 @@ int dartray_grid_set_rho(dartray_grid *grid, const float *rho_device)
 }
 
 int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *origin, const double *dir,
-                            int32_t max_cross, int64_t *cells, float *lengths, int32_t *counts)
+                            int32_t max_cross, int64_t *cells, double *lengths, int32_t *counts)
 {
     if (!grid || !origin || !dir || !cells || !lengths || !counts || n_rays <= 0 || max_cross <= 0)
         return fail(DARTRAY_E_INVALID, "bad argument");
@@ -2516,13 +2643,13 @@ int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *or
     }
     double *d_o = nullptr, *d_d = nullptr;
     int64_t *d_c = nullptr;
-    float *d_l = nullptr;
+    double *d_l = nullptr;
     int32_t *d_n = nullptr;
     const size_t tot = (size_t)n_rays * max_cross;
     hipError_t e = hipMalloc((void **)&d_o, sizeof(double) * 3 * n_rays);
     if (e == hipSuccess) e = hipMalloc((void **)&d_d, sizeof(double) * 3 * n_rays);
     if (e == hipSuccess) e = hipMalloc((void **)&d_c, sizeof(int64_t) * tot);
-    if (e == hipSuccess) e = hipMalloc((void **)&d_l, sizeof(float) * tot);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_l, sizeof(double) * tot);
     if (e == hipSuccess) e = hipMalloc((void **)&d_n, sizeof(int32_t) * n_rays);
     if (e == hipSuccess) e = hipMemcpyAsync(d_o, o.data(), sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice, g.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_d, dd.data(), sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice, g.stream);
@@ -2534,7 +2661,7 @@ int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *or
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(cells, d_c, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, g.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(lengths, d_l, sizeof(float) * tot, hipMemcpyDeviceToHost, g.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(lengths, d_l, sizeof(double) * tot, hipMemcpyDeviceToHost, g.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(counts, d_n, sizeof(int32_t) * n_rays, hipMemcpyDeviceToHost, g.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g.stream);
     (void)hipFree(d_o);
@@ -2543,7 +2670,8 @@ int dartray_debug_ray_cells(dartray_grid *grid, int32_t n_rays, const double *or
     (void)hipFree(d_l);
     (void)hipFree(d_n);
     if (e != hipSuccess) return hip_fail(e, "debug_ray_cells");
-    for (size_t i = 0; i < tot; ++i) lengths[i] = (float)(lengths[i] * g.h_fine);
+    for (int i = 0; i < n_rays; ++i)
+        for (int m = 0; m < counts[i]; ++m) lengths[(size_t)i * max_cross + m] *= g.h_fine;
     return DARTRAY_OK;
 }
 
@@ -2578,8 +2706,10 @@ static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_
         int depth = 0;
         while ((o->nside << depth) < o->nside_max) ++depth;
         if (depth > kMaxDepthAdaptive) return fail(DARTRAY_E_INVALID, "more than 12 split levels");
-        if (!(o->n_rays_min > 0.f)) return fail(DARTRAY_E_INVALID, "n_rays_min must be > 0");
-        if (!(o->f_U >= 0.f) && !(o->a_RT > 0.f)) return fail(DARTRAY_E_INVALID, "f_U must be >= 0, or a_RT > 0");
+        if (!(o->n_rays_min > 0.0) || !std::isfinite(o->n_rays_min)) return fail(DARTRAY_E_INVALID, "n_rays_min must be > 0");
+        if (!std::isfinite(o->f_U) || (!(o->f_U >= 0.0) && !(o->a_RT > 0.0 && std::isfinite(o->a_RT))))
+            return fail(DARTRAY_E_INVALID, "f_U must be >= 0, or < 0 with a_RT > 0 (Eq. 11)");
+        if (!std::isfinite(o->r_pre)) return fail(DARTRAY_E_INVALID, "r_pre must be finite");
         if (g.n_lambda > 16) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays carry at most 16 wavelengths");
     }
     if (f->escape && o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "escape by direction covers fixed rays only");
@@ -2654,18 +2784,20 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
     const unsigned nblk = (unsigned)((n + kScanBlock - 1) / kScanBlock);
     // the order in which sources become work items
     const int32_t *order = o->adaptive ? g.by_level : g.morton;
+    int rc = fill<int32_t>(g, g.n_all, 1, 0);
+    if (rc) return rc;
+    if ((rc = fill<uint32_t>(g, g.err_word, 1, 0u))) return rc;   // the pass's own error word
     if (!scatter) {
         hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, order,
-                           n, g.d_lt, g.emis_lum, o->source_mask, f->tally);
+                           n, g.d_lt, g.emis_lum, o->source_mask, f->tally, g.n_all);
         DR_LAUNCH_CHECK("k_source_flags");
     } else {
-        int rc = fill<uint8_t>(g, g.cell_flag, (size_t)n, (uint8_t)0);
-        if (rc) return rc;
+        if ((rc = fill<uint8_t>(g, g.cell_flag, (size_t)n, (uint8_t)0))) return rc;
         hipLaunchKernelGGL(k_sflag_sweep, dim3(s_blocks(g), g.n_lambda), dim3(256), 0, g.stream, f->S_pending, g.d_lt,
-                           g.cell_flag, f->tally);
+                           o->source_mask, g.cell_flag, f->tally);
         DR_LAUNCH_CHECK("k_sflag_sweep");
         hipLaunchKernelGGL(k_sflag_gather, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
-                           g.stream, g.flags, order, g.cell_flag, n);
+                           g.stream, g.flags, order, g.cell_flag, o->source_mask, n, g.n_all);
         DR_LAUNCH_CHECK("k_sflag_gather");
     }
     hipLaunchKernelGGL(k_scan_count, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, n, g.scan_blocks);
@@ -2919,8 +3051,10 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     A.dirs = g.dir_all;
     A.invz = g.invz;
     A.emis_lum = g.emis_lum;
+    A.lum64 = g.lum64;
     A.S_pending = f->S_pending;
     A.ull_t = g.ull_t;
+    A.n_all = g.n_all;
     A.lt = g.d_lt;
     A.U_k = g.U_k;
     A.S_next = f->S_next;
@@ -2939,12 +3073,10 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     A.n_rays = o->n_rays_min;
     A.f_U = o->f_U;
     A.a_RT = o->a_RT;
-    A.r_pre_fine = (float)((double)o->r_pre / g.h_fine);
-    A.h_fine = (float)g.h_fine;
-    A.r_pre_fine64 = (double)o->r_pre / g.h_fine;
+    A.r_pre_fine64 = o->r_pre / g.h_fine;
     A.h_fine64 = g.h_fine;
     A.dirs64 = g.dir64;
-    A.c_light = (float)g.c_light;
+    A.c_light = g.c_light;
     A.max_steps = o->max_steps;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
     const unsigned blocks = 2048;
@@ -3017,7 +3149,7 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
     const bool step1 = !scatter && o->mode == DARTRAY_MODE_STEP1;
     hipLaunchKernelGGL(k_finish_u, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024), nl), dim3(256), 0,
                        g.stream, g.U_k, f->U, f->U_pass, f->U_LL, o->adaptive ? 1 : 0, step1 ? 1 : 0, g.d_lt, g.rho,
-                       g.inv_vc, n, f->tally);
+                       g.inv_vc, n, f->tally, g.err_word);
     DR_LAUNCH_CHECK("k_finish_u");
     if (f->escape && !o->adaptive) {
         const int64_t ne = (int64_t)nl * 12 * o->nside * o->nside;
@@ -3029,12 +3161,22 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
     double *ssum = g.dsum;
     if ((rc = fill<double>(g, ssum, (size_t)nl, 0.0))) return rc;
     hipLaunchKernelGGL(k_finish_s, dim3(s_blocks(g), nl), dim3(256), 0, g.stream, f->S_next, f->S_total, f->S_pending,
-                       scatter ? 1 : 0, g.d_lt, g.s_size, ssum);
+                       scatter ? 1 : 0, g.d_lt, g.s_size, ssum, g.err_word);
     DR_LAUNCH_CHECK("k_finish_s");
     if (!scatter) {
         DR_HIP(hipMemcpyAsync(g.s1_sum, ssum, sizeof(double) * nl, hipMemcpyDeviceToDevice, g.stream));
         g.have_s1 = true;
     }
+    return DARTRAY_OK;
+}
+
+// Read the pass's device error word (synchronises the stream).
+static int check_err(Grid &g)
+{
+    uint32_t w = 0;
+    DR_HIP(hipMemcpyAsync(&w, g.err_word, sizeof(w), hipMemcpyDeviceToHost, g.stream));
+    DR_HIP(hipStreamSynchronize(g.stream));
+    if (w & 1u) return fail(DARTRAY_E_NUMERIC, "the pass produced a non-finite energy density or scattered luminosity");
     return DARTRAY_OK;
 }
 
@@ -3050,7 +3192,9 @@ int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dar
     if (rc) return rc;
     rc = opts->adaptive ? run_adaptive_pass(g, opts, fields, false) : run_fixed_pass(g, opts, fields, false);
     if (rc) return rc;
-    return finish_pass(g, opts, fields, false);
+    if ((rc = finish_pass(g, opts, fields, false))) return rc;
+    if ((opts->flags & DARTRAY_FLAG_CHECK) || opts->adaptive) return check_err(g);
+    return DARTRAY_OK;
 }
 
 int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields, double *r_k)
@@ -3075,11 +3219,13 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
         }
         *r_k = sb > 0.0 ? sa / sb : 0.0;
     }
+    if ((opts->flags & DARTRAY_FLAG_CHECK) || opts->adaptive || r_k) return check_err(g);
     return DARTRAY_OK;
 }
 
 int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, int32_t n_scatter,
-                          const float *const *S_hist, const float *dJ_dU, const float *dJ_desc, float *dJ_drho)
+                          const float *const *S_hist, const float *dJ_dU, const float *dJ_dS, const float *dJ_desc,
+                          float *dJ_drho)
 {
     if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
     Grid &g = grid->g;
@@ -3128,7 +3274,9 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     A.inv_nray = (float)(1.0 / (double)nray);
     A.h_fine = g.h_fine;
     A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
-    const float *sbar_next = nullptr;
+    // S_total holds every order S_1 .. S_{K+1}: dJ/dS_total reaches each of
+    // them directly, the last (never re-emitted) one only directly
+    const float *sbar_next = dJ_dS;
     g.prof_kind = DARTRAY_PROF_ADJOINT;
     for (int k = n_scatter; k >= 0; --k) {
         const bool scatter = k > 0;
@@ -3172,6 +3320,11 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
             }
             DR_LAUNCH_CHECK("k_march_adjoint");
             if ((rc = prof_mark(g))) return rc;
+        }
+        if (scatter && dJ_dS) {
+            hipLaunchKernelGGL(k_add_f32, dim3((unsigned)std::min<int64_t>((g.s_size + 255) / 256, 8192)), dim3(256), 0,
+                               g.stream, sbar_k, dJ_dS, g.s_size);
+            DR_LAUNCH_CHECK("k_add_f32");
         }
         sbar_next = sbar_k;
     }

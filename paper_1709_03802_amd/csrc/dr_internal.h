@@ -73,6 +73,7 @@ struct Grid {
     float *rho = nullptr;
     float *inv_vc = nullptr;              // 1 / (V c)
     float *emis_lum = nullptr;            // [nl][n] 4 pi j V
+    double *lum64 = nullptr;              // [nl][n] 4 pi j V in FP64 (launch luminosity of the FP64-decision passes)
     int32_t *root_tab = nullptr;          // root cell -> node code
     int32_t *nodes = nullptr;             // [8 * n_internal] child codes
     int32_t *morton = nullptr;            // leaves in Morton order
@@ -86,7 +87,9 @@ struct Grid {
     uint8_t *cell_flag = nullptr;         // [n] scattering-pass source flags by cell
     int32_t *src_list = nullptr;          // [n] compacted sources
     int32_t *scan_blocks = nullptr;       // block sums
-    int32_t *n_src = nullptr;             // [1]
+    int32_t *n_src = nullptr;             // [1] sources the pass traces (after the source mask)
+    int32_t *n_all = nullptr;             // [1] sources of the pass in the whole model (N_s of Eq. 11)
+    uint32_t *err_word = nullptr;         // [1] device error word: bit 0 non-finite U or S
     double *dsum = nullptr;               // [4 * kMaxLambda] FP64 scratch sums
     double *s1_sum = nullptr;             // [kMaxLambda] sum of S after the direct pass
     bool have_s1 = false;

@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(PKG, "libdartray.so")
 OK, E_INVALID, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 MODE_STEP1, MODE_DIRECT = 0, 1
 PROF_FIXED, PROF_STEP1, PROF_SCATTERING, PROF_ADJOINT, PROF_ALL = 1, 2, 4, 8, 15
-FLAG_COUNTERS = 1
+FLAG_COUNTERS, FLAG_CHECK = 1, 2
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
 C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)
 
@@ -77,10 +77,10 @@ class TraceOpts(C.Structure):
         ("adaptive", C.c_int32),
         ("nside", C.c_int32),
         ("nside_max", C.c_int32),
-        ("n_rays_min", C.c_float),
-        ("f_U", C.c_float),
-        ("a_RT", C.c_float),
-        ("r_pre", C.c_float),
+        ("n_rays_min", C.c_double),
+        ("f_U", C.c_double),
+        ("a_RT", C.c_double),
+        ("r_pre", C.c_double),
         ("frame", C.c_double * 9),
         ("source_mask", C.c_void_p),
         ("flags", C.c_uint32),
@@ -139,11 +139,11 @@ def load_library():
     L.dartray_trace_direct.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC)]
     L.dartray_scatter_iter.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.POINTER(C.c_double)]
     L.dartray_trace_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.c_int32, C.POINTER(C.c_void_p),
-                                        C.c_void_p, C.c_void_p, C.c_void_p]
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.dartray_debug_ray_cells.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                          C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_float),
+                                          C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                           C.POINTER(C.c_int32)]
-    L.dartray_workspace_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    L.dartray_workspace_bytes.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.c_size_t)]
     L.dartray_profile_enable.argtypes = [C.c_void_p, C.c_int32]
     L.dartray_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.dartray_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
@@ -247,9 +247,11 @@ class Grid:
     def npix(self, l):
         return 12 * self.nside_sca[l] ** 2
 
-    def workspace_bytes(self) -> int:
+    def workspace_bytes(self, opts: Optional["TraceOpts"] = None) -> int:
+        """Device bytes the handle holds, or with opts those a pass with these
+        options uses."""
         b = C.c_size_t()
-        _check(load_library().dartray_workspace_bytes(self.h, C.byref(b)))
+        _check(load_library().dartray_workspace_bytes(self.h, None if opts is None else C.byref(opts), C.byref(b)))
         return b.value
 
     def profile(self, kinds=PROF_ALL):
@@ -349,7 +351,8 @@ class Batch:
         self.close()
 
 
-def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=True, max_steps=0) -> TraceOpts:
+def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=True, max_steps=0,
+              check=False) -> TraceOpts:
     o = TraceOpts()
     o.mode = mode
     o.adaptive = 1 if policy.adaptive else 0
@@ -357,12 +360,12 @@ def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=T
     o.nside_max = int(policy.nside_max)
     o.n_rays_min = float(policy.n_rays_min)
     o.f_U = float(policy.f_U)
-    o.a_RT = 0.0
+    o.a_RT = float(getattr(policy, "a_RT", 0.0))
     o.r_pre = float(policy.r_pre)
     fr = np.zeros(9) if frame is None else np.asarray(frame, dtype=np.float64).ravel()
     o.frame = (C.c_double * 9)(*fr.tolist())
     o.source_mask = None if source_mask is None else source_mask.data_ptr()
-    o.flags = FLAG_COUNTERS if counters else 0
+    o.flags = (FLAG_COUNTERS if counters else 0) | (FLAG_CHECK if check else 0)
     o.max_steps = int(max_steps)
     return o
 
@@ -384,16 +387,19 @@ def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields, want_rk=True):
     return rk.value
 
 
-def trace_adjoint(grid: Grid, opts: TraceOpts, S_hist, dJ_dU, dJ_drho, dJ_desc=None):
+def trace_adjoint(grid: Grid, opts: TraceOpts, S_hist, dJ_dU, dJ_drho, dJ_desc=None, dJ_dS=None):
     """dJ/drho into dJ_drho (device float [n]) for dJ_dU (device [nl, n] or
-    None) and dJ_desc (device [nl, 12 nside^2] or None: the derivative with
-    respect to the escaping luminosity summed over the passes).
+    None), dJ_dS (device, S layout, or None: the derivative with respect to
+    S_total, the scattered luminosity of every order) and dJ_desc (device
+    [nl, 12 nside^2] or None: the derivative with respect to the escaping
+    luminosity summed over the passes).
 
     S_hist: the S_pending tensors each scattering iteration of the forward run
     processed, in order (``DartRayFn`` keeps them)."""
     arr = (C.c_void_p * max(len(S_hist), 1))(*[t.data_ptr() for t in S_hist])
     _check(load_library().dartray_trace_adjoint(grid.h, C.byref(opts), len(S_hist), arr,
                                                 None if dJ_dU is None else C.c_void_p(dJ_dU.data_ptr()),
+                                                None if dJ_dS is None else C.c_void_p(dJ_dS.data_ptr()),
                                                 None if dJ_desc is None else C.c_void_p(dJ_desc.data_ptr()),
                                                 C.c_void_p(dJ_drho.data_ptr())))
 
@@ -402,10 +408,12 @@ def _autograd():
     import torch
 
     class DartRayFn(torch.autograd.Function):
-        """rho (device float [n]) -> (U [n_lambda, n], F [n_lambda, 12 nside^2])
-        for a fixed-ray run (direct pass + policy.n_scatter scattering
-        iterations), F being the escaping luminosity by direction summed over
-        the passes; backward by the adjoint march."""
+        """rho (device float [n]) -> (U [n_lambda, n], F [n_lambda, 12 nside^2],
+        S_total [s_size]) for a fixed-ray run (direct pass + policy.n_scatter
+        scattering iterations), F being the escaping luminosity by direction
+        summed over the passes and S_total the scattered luminosity of every
+        order (j_sca = S_total / (V 4 pi / N_pix)); backward by the adjoint
+        march."""
 
         @staticmethod
         def forward(ctx, rho, grid, policy, frame=None):
@@ -421,16 +429,17 @@ def _autograd():
                 F += f.escape
             ctx.grid, ctx.opts, ctx.hist = grid, opts, hist
             ctx.save_for_backward(rho)
-            return f.U.clone(), F
+            return f.U.clone(), F, f.S_total[:grid.s_size].clone()
 
         @staticmethod
-        def backward(ctx, gU, gF):
+        def backward(ctx, gU, gF, gS):
             (rho,) = ctx.saved_tensors
             ctx.grid.set_rho(rho.detach().contiguous())
             drho = torch.empty_like(rho)
             gU = None if gU is None else gU.contiguous().to(torch.float32)
             gF = None if gF is None else gF.contiguous().to(torch.float32)
-            trace_adjoint(ctx.grid, ctx.opts, ctx.hist, gU, drho, dJ_desc=gF)
+            gS = None if gS is None else gS.contiguous().to(torch.float32)
+            trace_adjoint(ctx.grid, ctx.opts, ctx.hist, gU, drho, dJ_desc=gF, dJ_dS=gS)
             return drho, None, None, None
 
     return DartRayFn
@@ -439,13 +448,20 @@ def _autograd():
 _fn = None
 
 
-def rfed_escape(rho, grid: Grid, policy, frame=None):
-    """Differentiable (U(rho), F(rho)): energy density and escaping luminosity
-    by direction (see ``DartRayFn``)."""
+def rfed_full(rho, grid: Grid, policy, frame=None):
+    """Differentiable (U(rho), F(rho), S_total(rho)): energy density, escaping
+    luminosity by direction and scattered luminosity of every order (see
+    ``DartRayFn``)."""
     global _fn
     if _fn is None:
         _fn = _autograd()
     return _fn.apply(rho, grid, policy, frame)
+
+
+def rfed_escape(rho, grid: Grid, policy, frame=None):
+    """Differentiable (U(rho), F(rho)): energy density and escaping luminosity
+    by direction (see ``DartRayFn``)."""
+    return rfed_full(rho, grid, policy, frame)[:2]
 
 
 def rfed(rho, grid: Grid, policy, frame=None):
@@ -458,10 +474,10 @@ def debug_ray_cells(grid: Grid, origins, dirs, max_cross=4096):
     d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
     nr = o.shape[0]
     cells = np.zeros((nr, max_cross), dtype=np.int64)
-    lens = np.zeros((nr, max_cross), dtype=np.float32)
+    lens = np.zeros((nr, max_cross), dtype=np.float64)
     counts = np.zeros(nr, dtype=np.int32)
     _check(load_library().dartray_debug_ray_cells(grid.h, nr, _ptr(o, C.c_double), _ptr(d, C.c_double), max_cross,
-                                                  _ptr(cells, C.c_int64), _ptr(lens, C.c_float),
+                                                  _ptr(cells, C.c_int64), _ptr(lens, C.c_double),
                                                   _ptr(counts, C.c_int32)))
     return [(cells[i, :counts[i]], lens[i, :counts[i]]) for i in range(nr)]
 

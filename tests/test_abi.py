@@ -54,6 +54,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", offsetof(dartray_grid_desc, c_light), offsetof(dartray_grid_desc, nside_max), offsetof(dartray_trace_opts, frame),
          offsetof(dartray_trace_opts, max_steps), offsetof(dartray_fields, counters));
   printf("%zu %zu\\n", offsetof(dartray_tuning, item_order), offsetof(dartray_fields, escape));
+  printf("%zu %zu %zu\\n", offsetof(dartray_trace_opts, f_U), offsetof(dartray_trace_opts, r_pre), offsetof(dartray_trace_opts, flags));
   return 0;
 }
 """)
@@ -63,7 +64,8 @@ int main(void) {
     got = [int(x) for x in out]
     want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC), C.sizeof(dartray.Tuning),
             dartray.GridDesc.c_light.offset, dartray.GridDesc.nside_max.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
-            dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset, dartray.FieldsC.escape.offset]
+            dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset, dartray.FieldsC.escape.offset,
+            dartray.TraceOpts.f_U.offset, dartray.TraceOpts.r_pre.offset, dartray.TraceOpts.flags.offset]
     assert got == want
 
 
@@ -138,6 +140,21 @@ def test_malformed_descriptions_rejected_before_device_work(lib, breakage):
     assert rc == dartray.E_INVALID
     assert h.value is None
     assert len(lib.dartray_last_error()) > 0
+
+
+def test_eq5_rule_beyond_k_max_3_is_unsupported(lib):
+    """The j_sca resolution of Eq. 5 is capped at k = 3 (Nside_sca 8): a
+    larger k_max with the rule in use is refused, not silently capped; with
+    every nside_sca given explicitly k_max plays no part."""
+    from paper_1709_03802_amd import workloads as W
+    from paper_1709_03802_amd import dartray
+    grid = W.random_octree(seed=5)
+    grid.nside_sca[:] = 0
+    d, keep = _desc(grid)
+    d.k_max = 4
+    h = C.c_void_p()
+    assert lib.dartray_grid_create(C.byref(d), None, C.byref(h)) == dartray.E_UNSUPPORTED
+    assert h.value is None and b"k_max" in lib.dartray_last_error()
 
 
 def test_null_arguments(lib):

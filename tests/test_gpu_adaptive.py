@@ -1,13 +1,14 @@
 """GPU parity of the adaptive path (ray splitting, blocking, per-wavelength
 skip, step 1) against the FP64 oracle.
 
-Each pass is compared in isolation: both sides get the same frozen inputs
-(U_LL and, for scattering passes, the pending scattered luminosity from the
-oracle), so the only differences are FP32 arithmetic and the block/split
-decisions it flips.  A flipped decision moves one ray's contribution between
-neighbouring cells, so the gate is: at least 99% of cells within 1e-4, every
-cell within 1e-2, split and cut counts within 0.1%, luminosity balance within
-1e-6.
+Each pass is compared in isolation: both sides get the same frozen inputs,
+rounded to FP32 (the grid, U_LL and, for scattering passes, the pending
+scattered luminosity), so only arithmetic differs.  Both sides take every
+split, block and skip decision in FP64 (geometry, and the ray's luminosity
+in the passes that test significance), so the decisions agree: split, cut,
+crossing, deposit and skip counts are equal, every U and S element is
+within 1e-4 (relative, with a 1e-30 floor), and the luminosity balance holds
+within 1e-6.
 """
 
 import numpy as np
@@ -16,6 +17,7 @@ import pytest
 from paper_1709_03802_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -34,31 +36,35 @@ def as_f32(grid):
     return g
 
 
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
 def rel(x, ref):
+    """Per-element relative error (1e-30 floor) over the elements either side
+    holds as nonzero."""
     x = np.asarray(x, np.float64)
     ref = np.asarray(ref, np.float64)
     both = (np.abs(ref) > 0) | (np.abs(x) > 0)
-    e = np.abs(x - ref)[both] / np.maximum(np.abs(ref[both]), 1e-300)
-    return e
+    return np.abs(x - ref)[both] / np.maximum(np.abs(ref[both]), 1e-30)
 
 
-def gate(name, e, frac_tol=0.01, hard=1e-2):
+def gate(name, e, tol=TOL):
     if e.size == 0:
         print(f"{name}: zero on both sides", flush=True)
         return
-    bad = float(np.mean(e > 1e-4))
-    print(f"{name}: max {e.max():.3g} p99 {np.quantile(e, 0.99):.3g} p99.9 {np.quantile(e, 0.999):.3g} "
-          f"frac>1e-4 {bad:.4f}", flush=True)
-    assert bad <= frac_tol, f"{name}: {bad:.4f} of elements above 1e-4"
-    assert e.max() <= hard, f"{name}: max rel err {e.max()}"
+    print(f"{name}: max {e.max():.3g} p99.9 {np.quantile(e, 0.999):.3g}", flush=True)
+    assert e.max() <= tol, f"{name}: max rel err {e.max()}"
 
 
 def check_counts(c_gpu, c_ref, dr, orc):
     for gi, oi, name in ((dr.C_SPLITS, orc.C_SPLITS, "splits"), (dr.C_CUTS, orc.C_CUTS, "cuts"),
-                         (dr.C_CROSSINGS, orc.C_CROSS, "crossings"), (dr.C_RAYS, orc.C_RAYS, "rays")):
+                         (dr.C_CROSSINGS, orc.C_CROSS, "crossings"), (dr.C_RAYS, orc.C_RAYS, "rays"),
+                         (dr.C_DEPOSITS, orc.C_DEPOSITS, "deposits"), (dr.C_SKIPS, orc.C_SKIPS, "skips"),
+                         (dr.C_ESCAPES, orc.C_ESCAPES, "escapes")):
         a, b = int(c_gpu[gi]), int(c_ref[oi])
         print(f"  {name}: gpu {a} oracle {b}", flush=True)
-        assert abs(a - b) <= 1e-3 * max(b, 1) + 2, name
+        assert a == b, name
     # every ray ends once: a split ends one ray and starts four
     c = [int(v) for v in c_gpu]
     assert c[dr.C_ESCAPES] + c[dr.C_CUTS] + c[dr.C_MAXSTEP] == c[dr.C_RAYS] + 3 * c[dr.C_SPLITS]
@@ -70,31 +76,42 @@ def check_balance(t):
     assert np.all(np.abs(resid) <= 1e-6 * np.abs(em) + 1e-300), resid / em
 
 
+def check_tallies(t, t_ref):
+    em = t_ref[:, 0]
+    np.testing.assert_allclose(t[:, 0], em, rtol=1e-6)
+    for col in range(1, 6):
+        assert np.all(np.abs(t[:, col] - t_ref[:, col]) <= 1e-6 * em + 1e-300), col
+
+
 def run_frozen(dr, orc, wl, frame=None):
+    """Step 1, the direct pass and the scattering passes, each from the same
+    FP32-rounded inputs on both sides (U_LL: the oracle's running U)."""
     import torch
     g32 = as_f32(wl.grid)
     pol = wl.policy
     m = orc.Model(g32)
-    ref = orc.run(m, pol, frame=frame)
     G = dr.Grid(g32, nside_max=pol.nside_max)
     f = dr.Fields(G, keep_pass_u=True)
     nl, n = G.nl, G.n
     # step 1
+    r0 = m.run_pass(orc.STEP1, pol, frame=frame)
     dr.trace_direct(G, dr.make_opts(pol, dr.MODE_STEP1, frame), f)
     torch.cuda.synchronize()
-    r0 = ref.passes[0]
     gate("step1 U_LL", rel(f.U_LL.cpu().numpy(), r0.U))
     check_counts(f.counters.cpu().numpy(), r0.counters, dr, orc)
     check_balance(f.tally.cpu().numpy())
-    U_LL = r0.U.copy()
+    ull = f32(r0.U)
     U_run = np.zeros((nl, n))
-    for k in range(1, len(ref.passes)):
-        rk = ref.passes[k]
-        f.U_LL.copy_(torch.as_tensor(U_LL, dtype=torch.float32))
-        if k == 1:
+    S_prev = None
+    for k in range(1 + pol.n_scatter):
+        f.U_LL.copy_(torch.as_tensor(ull, dtype=torch.float32))
+        if k == 0:
+            rk = m.run_pass(orc.DIRECT, pol, U_LL=ull, frame=frame)
             dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, frame), f)
         else:
-            f.S_pending.copy_(torch.as_tensor(np.concatenate([ref.passes[k - 1].S, np.zeros(f.S_pending.numel() - G.s_size)]),
+            sp = f32(S_prev)
+            rk = m.run_pass(orc.SCATTER, pol, S_pending=sp, U_LL=ull, frame=frame)
+            f.S_pending.copy_(torch.as_tensor(np.concatenate([sp, np.zeros(f.S_pending.numel() - G.s_size)]),
                                               dtype=torch.float32))
             dr.scatter_iter(G, dr.make_opts(pol, dr.MODE_DIRECT, frame), f)
         torch.cuda.synchronize()
@@ -102,10 +119,11 @@ def run_frozen(dr, orc, wl, frame=None):
         gate(f"pass {k} S", rel(f.S_pending.cpu().numpy()[:G.s_size], rk.S))
         t = f.tally.cpu().numpy()
         check_balance(t)
-        np.testing.assert_allclose(t[:, 0], rk.tally[:, 0], rtol=1e-5)
+        check_tallies(t, rk.tally)
         check_counts(f.counters.cpu().numpy(), rk.counters, dr, orc)
         U_run += rk.U
-        U_LL = U_run.copy()
+        ull = f32(U_run)
+        S_prev = rk.S
     G.close()
 
 
@@ -134,7 +152,10 @@ def test_adaptive_without_splitting_equals_fixed_rays(dr, orc):
 
 
 def test_adaptive_end_to_end_disk_tiny(dr, orc):
-    # chained passes on both sides; decisions may flip and propagate
+    """Chained passes on both sides (each side's own U_LL and pending light,
+    FP32 on the GPU): a decision taken within the FP32 rounding of the
+    chained inputs could go either way, so the gate is 1e-4 on 99.9% of the
+    cells and 1e-2 on all, and every pass balances."""
     import torch
     wl = W.disk_tiny()
     g32 = as_f32(wl.grid)
@@ -142,9 +163,36 @@ def test_adaptive_end_to_end_disk_tiny(dr, orc):
     G = dr.Grid(g32, nside_max=wl.policy.nside_max)
     out = dr.run(G, wl.policy)
     torch.cuda.synchronize()
-    gate("end-to-end U", rel(out.fields.U.cpu().numpy(), ref.U))
+    e = rel(out.fields.U.cpu().numpy(), ref.U)
+    print(f"end-to-end U: max {e.max():.3g} p99.9 {np.quantile(e, 0.999):.3g}", flush=True)
+    assert np.quantile(e, 0.999) <= TOL and e.max() <= 1e-2
     for t in out.tallies:
         check_balance(t)
+
+
+def test_eq11_accuracy_parameter_selects_f_u(dr, orc):
+    """f_U < 0 with a_RT: f_U = 4 a_RT / N_s (Eq. 11), N_s counting every
+    emitting cell of the model even when a source mask selects a subset; the
+    direct pass matches the oracle's with the same rule."""
+    import torch
+    wl = W.disk_tiny()
+    g32 = as_f32(wl.grid)
+    m = orc.Model(g32)
+    pol = W.RayPolicy(**{**wl.policy.__dict__, "f_U": -1.0, "a_RT": 0.05})
+    ull = f32(m.run_pass(orc.STEP1, wl.policy).U)
+    mask = np.zeros(g32.n, np.uint8)
+    mask[np.random.default_rng(4).choice(g32.n, g32.n // 3, replace=False)] = 1
+    G = dr.Grid(g32, nside_max=pol.nside_max)
+    for msk in (None, mask):
+        ref = m.run_pass(orc.DIRECT, pol, U_LL=ull, source_mask=msk)
+        f = dr.Fields(G, keep_pass_u=True)
+        f.U_LL.copy_(torch.as_tensor(ull, dtype=torch.float32))
+        mt = None if msk is None else torch.as_tensor(msk).cuda()
+        dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=mt), f)
+        torch.cuda.synchronize()
+        gate("a_RT direct U_k", rel(f.U_pass.cpu().numpy(), ref.U))
+        check_counts(f.counters.cpu().numpy(), ref.counters, dr, orc)
+    G.close()
 
 
 def _degenerate_grid(case):
