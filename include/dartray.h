@@ -245,6 +245,24 @@ int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dar
 int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields, double *r_k);
 
 /*
+ * The direct pass of dartray_trace_direct for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the pass's work arrays
+ * (energy-density accumulators, direction bins, source list, scan sums,
+ * error word) taken from a static device array of 64 MiB per GPU instead of
+ * the handle's own.  It calls no hipMalloc, hipFree or other allocating
+ * routine (the first call on a device looks up that device's array once).
+ * Fixed rays only (opts->adaptive = 0, opts->nside <= 16); a grid whose work
+ * arrays exceed the 64 MiB (n_leaves * n_lambda * 12 bytes plus one
+ * direction of bins, n_leaves * n_lambda * 4 bytes, and small parts) gives
+ * DARTRAY_E_UNSUPPORTED with the size in the message, before any output is
+ * written.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (on different streams or threads) race.  Outputs and state as
+ * dartray_trace_direct.
+ */
+int dartray_trace_direct_noalloc(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields);
+
+/*
  * Gradient dJ/drho of a loss J of the energy density U and of the escaping
  * luminosity F (escape summed over the passes) with respect to the per-cell
  * dust density, by an adjoint march over the passes of a fixed-ray

@@ -29,6 +29,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -2194,8 +2195,8 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.n_all, g.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.U_k,
-                    g.flags, g.cell_flag, g.src_list, g.scan_blocks, g.n_src, g.dsum, g.s1_sum, g.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
+    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
+                    g.own.flags, g.cell_flag, g.own.src_list, g.own.scan_blocks, g.own.n_src, g.own.dsum, g.s1_sum, g.own.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -2422,6 +2423,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     g.s_size = lt.s_off[nl];
     g.w_row = lt.w_off[nl];
     g.stream = (hipStream_t)stream;
+    if (hipGetDevice(&g.device) != hipSuccess) g.device = 0;
 
     const size_t nray_w = 12 * (size_t)kMaxNsideWTable * kMaxNsideWTable;
     const int32_t cap = std::max(64, (int)d->nside_max);
@@ -2435,15 +2437,15 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     size_t nb_cap = std::min<size_t>(768, std::max<size_t>(1, bin_budget / (4 * per_dir)));
     int rcs[] = {
         dalloc(g, &g.leaf_box, (size_t)n), dalloc(g, &g.rho, (size_t)n), dalloc(g, &g.inv_vc, (size_t)n),
-        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n), dalloc(g, &g.esc64, (size_t)nl * 12 * kMaxNsideWTable * kMaxNsideWTable),
+        dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n), dalloc(g, &g.own.esc64, (size_t)nl * 12 * kMaxNsideWTable * kMaxNsideWTable),
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.lum64, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
-        dalloc(g, &g.n_all, 1), dalloc(g, &g.err_word, 1),
+        dalloc(g, &g.own.n_all, 1), dalloc(g, &g.own.err_word, 1),
         dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.by_level, (size_t)n), dalloc(g, &g.d_lt, 1),
-        dalloc(g, &g.U_k, (size_t)(nl * n)), dalloc(g, &g.flags, (size_t)n), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.src_list, (size_t)n),
-        dalloc(g, &g.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.n_src, 1),
-        dalloc(g, &g.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
-        dalloc(g, &g.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir), dalloc(g, &g.dir64, (size_t)ndir),
+        dalloc(g, &g.own.U_k, (size_t)(nl * n)), dalloc(g, &g.own.flags, (size_t)n), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.own.src_list, (size_t)n),
+        dalloc(g, &g.own.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.own.n_src, 1),
+        dalloc(g, &g.own.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
+        dalloc(g, &g.own.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir), dalloc(g, &g.dir64, (size_t)ndir),
         dalloc(g, &g.invz, (size_t)ndir * nl), dalloc(g, &g.sca64, 3 * (size_t)kScaDirs),
         dalloc(g, &g.wtab, nray_w * (size_t)g.w_row), dalloc(g, &g.queue, 1),
     };
@@ -2454,7 +2456,8 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
             delete h;
             return fail(DARTRAY_E_OOM, msg);
         }
-    g.ubar_floats = nb_cap * per_dir;
+    g.own.ubar_floats = nb_cap * per_dir;
+    g.w = g.own;
     g.nside_cap = cap;
     g.ndir_all = ndir;
     // deposit log for the scattering passes of adaptive rays (wavelength rows
@@ -2581,7 +2584,7 @@ int dartray_workspace_bytes(const dartray_grid *grid, const dartray_trace_opts *
     const bool step1 = opts->adaptive && opts->mode == DARTRAY_MODE_STEP1;
     if (!opts->adaptive) {
         const int64_t nray = 12 * (int64_t)opts->nside * opts->nside;
-        const size_t nb = (size_t)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / std::max<size_t>(1, n * nl)));
+        const size_t nb = (size_t)std::min<int64_t>(nray, (int64_t)(g.w.ubar_floats / std::max<size_t>(1, n * nl)));
         b += nb * n * nl * sizeof(float) + (size_t)nray * (size_t)g.w_row * sizeof(float);
     } else if (!step1) {
         b += n * nl * sizeof(float) + (size_t)g.ndir_all * nl * sizeof(float);   // U_LL copy, phase normalisation
@@ -2784,12 +2787,12 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
     const unsigned nblk = (unsigned)((n + kScanBlock - 1) / kScanBlock);
     // the order in which sources become work items
     const int32_t *order = o->adaptive ? g.by_level : g.morton;
-    int rc = fill<int32_t>(g, g.n_all, 1, 0);
+    int rc = fill<int32_t>(g, g.w.n_all, 1, 0);
     if (rc) return rc;
-    if ((rc = fill<uint32_t>(g, g.err_word, 1, 0u))) return rc;   // the pass's own error word
+    if ((rc = fill<uint32_t>(g, g.w.err_word, 1, 0u))) return rc;   // the pass's own error word
     if (!scatter) {
-        hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.flags, order,
-                           n, g.d_lt, g.emis_lum, o->source_mask, f->tally, g.n_all);
+        hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.w.flags, order,
+                           n, g.d_lt, g.emis_lum, o->source_mask, f->tally, g.w.n_all);
         DR_LAUNCH_CHECK("k_source_flags");
     } else {
         if ((rc = fill<uint8_t>(g, g.cell_flag, (size_t)n, (uint8_t)0))) return rc;
@@ -2797,15 +2800,15 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
                            o->source_mask, g.cell_flag, f->tally);
         DR_LAUNCH_CHECK("k_sflag_sweep");
         hipLaunchKernelGGL(k_sflag_gather, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
-                           g.stream, g.flags, order, g.cell_flag, o->source_mask, n, g.n_all);
+                           g.stream, g.w.flags, order, g.cell_flag, o->source_mask, n, g.w.n_all);
         DR_LAUNCH_CHECK("k_sflag_gather");
     }
-    hipLaunchKernelGGL(k_scan_count, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, n, g.scan_blocks);
+    hipLaunchKernelGGL(k_scan_count, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.w.flags, n, g.w.scan_blocks);
     DR_LAUNCH_CHECK("k_scan_count");
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, g.stream, g.scan_blocks, (int64_t)nblk, g.n_src);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, g.stream, g.w.scan_blocks, (int64_t)nblk, g.w.n_src);
     DR_LAUNCH_CHECK("k_scan_blocks");
-    hipLaunchKernelGGL(k_scan_scatter, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.flags, order, n,
-                       g.scan_blocks, g.src_list);
+    hipLaunchKernelGGL(k_scan_scatter, dim3(nblk), dim3(kScanBlock), 0, g.stream, g.w.flags, order, n,
+                       g.w.scan_blocks, g.w.src_list);
     DR_LAUNCH_CHECK("k_scan_scatter");
     return DARTRAY_OK;
 }
@@ -2848,7 +2851,7 @@ static int lambda_chunk(const Grid &g)
 static int dir_batch(const Grid &g, int64_t nray)
 {
     const size_t per_dir = (size_t)g.n_lambda * (size_t)g.n;
-    int64_t nb = std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
+    int64_t nb = std::min<int64_t>(nray, (int64_t)(g.w.ubar_floats / per_dir));
     if (g.tune.dir_batch > 0) nb = std::min<int64_t>(nb, g.tune.dir_batch);
     return (int)std::max<int64_t>(nb, 1);
 }
@@ -2861,16 +2864,16 @@ static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields
     FixedArgs A{};
     A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
-    A.src_list = g.src_list;
-    A.n_src = g.n_src;
+    A.src_list = g.w.src_list;
+    A.n_src = g.w.n_src;
     A.dirs = g.dir64 + entry_of(o->nside, 0);
     A.emis_lum = g.emis_lum;
     A.S_pending = f->S_pending;
     A.lt = g.d_lt;
-    A.ubar = g.ubar;
+    A.ubar = g.w.ubar;
     A.tally = f->tally;
     A.counters = (o->flags & DARTRAY_FLAG_COUNTERS) ? f->counters : nullptr;
-    A.esc_dir = f->escape ? g.esc64 : nullptr;
+    A.esc_dir = f->escape ? g.w.esc64 : nullptr;
     A.n = g.n;
     A.scatter = scatter ? 1 : 0;
     A.order = g.tune.item_order;
@@ -2933,12 +2936,12 @@ static FlushShape flush_shape(const Grid &g)
 static FlushArgs flush_args(Grid &g, float *S_next)
 {
     FlushArgs F{};
-    F.ubar = g.ubar;
+    F.ubar = g.w.ubar;
     F.wtab = g.wtab;
     F.lt = g.d_lt;
     F.rho = g.rho;
     F.inv_vc = g.inv_vc;
-    F.U_k = g.U_k;
+    F.U_k = g.w.U_k;
     F.S_next = S_next;
     F.n = g.n;
     F.w_row = g.w_row;
@@ -2969,11 +2972,11 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     if ((rc = ensure_wtab(g, o->nside, fr))) return rc;
     const int64_t nray = 12 * (int64_t)o->nside * o->nside;
 
-    if ((rc = fill<double>(g, g.U_k, (size_t)nl * n, 0.0))) return rc;
+    if ((rc = fill<double>(g, g.w.U_k, (size_t)nl * n, 0.0))) return rc;
     if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
     if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
     if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
-    if (f->escape && (rc = fill<double>(g, g.esc64, (size_t)nl * nray, 0.0))) return rc;
+    if (f->escape && (rc = fill<double>(g, g.w.esc64, (size_t)nl * nray, 0.0))) return rc;
     if ((rc = select_sources(g, o, f, scatter))) return rc;
 
     const size_t per_dir = (size_t)nl * n;
@@ -2982,7 +2985,7 @@ static int run_fixed_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *
     const FixedArgs A = fixed_args(g, o, f, scatter);
     for (int64_t r0 = 0; r0 < nray; r0 += nb_max) {
         const int nb = (int)std::min<int64_t>(nb_max, nray - r0);
-        if ((rc = fill<float>(g, g.ubar, (size_t)nb * per_dir, 0.f))) return rc;
+        if ((rc = fill<float>(g, g.w.ubar, (size_t)nb * per_dir, 0.f))) return rc;
         if ((rc = march_fixed_batch(g, A, (int)r0, nb))) return rc;
         if ((rc = flush_fixed_batch(g, f->S_next, (int)r0, nb))) return rc;
     }
@@ -3031,7 +3034,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     int rc = ensure_dirs(g, fr);
     if (rc) return rc;
     if (!step1 && (rc = ensure_invz(g, fr))) return rc;
-    if ((rc = fill<double>(g, g.U_k, (size_t)nl * n, 0.0))) return rc;
+    if ((rc = fill<double>(g, g.w.U_k, (size_t)nl * n, 0.0))) return rc;
     if (!step1 && (rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
     if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
     if (f->counters && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
@@ -3046,17 +3049,17 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     AdaptArgs A{};
     A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
-    A.src_list = g.src_list;
-    A.n_src = g.n_src;
+    A.src_list = g.w.src_list;
+    A.n_src = g.w.n_src;
     A.dirs = g.dir_all;
     A.invz = g.invz;
     A.emis_lum = g.emis_lum;
     A.lum64 = g.lum64;
     A.S_pending = f->S_pending;
     A.ull_t = g.ull_t;
-    A.n_all = g.n_all;
+    A.n_all = g.w.n_all;
     A.lt = g.d_lt;
-    A.U_k = g.U_k;
+    A.U_k = g.w.U_k;
     A.S_next = f->S_next;
     A.tally = f->tally;
     A.counters = (o->flags & DARTRAY_FLAG_COUNTERS) ? f->counters : nullptr;
@@ -3090,7 +3093,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     A.log_limit = use_log ? g.log_cap - g.log_cap / 4 : 0;
     int32_t nsrc_h = 0;
     if (use_log) {
-        DR_HIP(hipMemcpyAsync(&nsrc_h, g.n_src, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipMemcpyAsync(&nsrc_h, g.w.n_src, sizeof(int32_t), hipMemcpyDeviceToHost, g.stream));
         DR_HIP(hipStreamSynchronize(g.stream));
     }
     const unsigned long long nitems = (unsigned long long)nsrc_h * (unsigned long long)(12 * o->nside * o->nside);
@@ -3127,7 +3130,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
             X.invz = g.invz;
             X.lt = g.d_lt;
             X.rec = g.rec;
-            X.U_k = g.U_k;
+            X.U_k = g.w.U_k;
             X.S_next = f->S_next;
             X.cnt = cnt;
             X.cap = g.log_cap;
@@ -3148,20 +3151,20 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
     const int64_t n = g.n;
     const bool step1 = !scatter && o->mode == DARTRAY_MODE_STEP1;
     hipLaunchKernelGGL(k_finish_u, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024), nl), dim3(256), 0,
-                       g.stream, g.U_k, f->U, f->U_pass, f->U_LL, o->adaptive ? 1 : 0, step1 ? 1 : 0, g.d_lt, g.rho,
-                       g.inv_vc, n, f->tally, g.err_word);
+                       g.stream, g.w.U_k, f->U, f->U_pass, f->U_LL, o->adaptive ? 1 : 0, step1 ? 1 : 0, g.d_lt, g.rho,
+                       g.inv_vc, n, f->tally, g.w.err_word);
     DR_LAUNCH_CHECK("k_finish_u");
     if (f->escape && !o->adaptive) {
         const int64_t ne = (int64_t)nl * 12 * o->nside * o->nside;
-        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, g.stream, g.esc64, f->escape, ne);
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, g.stream, g.w.esc64, f->escape, ne);
         DR_LAUNCH_CHECK("k_to_f32");
     }
     if (step1) return DARTRAY_OK;
     int rc;
-    double *ssum = g.dsum;
+    double *ssum = g.w.dsum;
     if ((rc = fill<double>(g, ssum, (size_t)nl, 0.0))) return rc;
     hipLaunchKernelGGL(k_finish_s, dim3(s_blocks(g), nl), dim3(256), 0, g.stream, f->S_next, f->S_total, f->S_pending,
-                       scatter ? 1 : 0, g.d_lt, g.s_size, ssum, g.err_word);
+                       scatter ? 1 : 0, g.d_lt, g.s_size, ssum, g.w.err_word);
     DR_LAUNCH_CHECK("k_finish_s");
     if (!scatter) {
         DR_HIP(hipMemcpyAsync(g.s1_sum, ssum, sizeof(double) * nl, hipMemcpyDeviceToDevice, g.stream));
@@ -3174,7 +3177,7 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
 static int check_err(Grid &g)
 {
     uint32_t w = 0;
-    DR_HIP(hipMemcpyAsync(&w, g.err_word, sizeof(w), hipMemcpyDeviceToHost, g.stream));
+    DR_HIP(hipMemcpyAsync(&w, g.w.err_word, sizeof(w), hipMemcpyDeviceToHost, g.stream));
     DR_HIP(hipStreamSynchronize(g.stream));
     if (w & 1u) return fail(DARTRAY_E_NUMERIC, "the pass produced a non-finite energy density or scattered luminosity");
     return DARTRAY_OK;
@@ -3209,7 +3212,7 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
     if (r_k) {
         const int nl = g.n_lambda;
         double a[kMaxLambda], b[kMaxLambda];
-        DR_HIP(hipMemcpyAsync(a, g.dsum, sizeof(double) * nl, hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipMemcpyAsync(a, g.w.dsum, sizeof(double) * nl, hipMemcpyDeviceToHost, g.stream));
         DR_HIP(hipMemcpyAsync(b, g.s1_sum, sizeof(double) * nl, hipMemcpyDeviceToHost, g.stream));
         DR_HIP(hipStreamSynchronize(g.stream));
         double sa = 0.0, sb = 0.0;
@@ -3256,12 +3259,12 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
         return rc;
     }
     const size_t per_dir = (size_t)nl * n;
-    const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.ubar_floats / per_dir));
+    const int nb_max = (int)std::min<int64_t>(nray, (int64_t)(g.w.ubar_floats / per_dir));
     AdjArgs A{};
     A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
-    A.src_list = g.src_list;
-    A.n_src = g.n_src;
+    A.src_list = g.w.src_list;
+    A.n_src = g.w.n_src;
     A.dirs = g.dir64 + entry_of(opts->nside, 0);
     A.emis_lum = g.emis_lum;
     A.lt = g.d_lt;
@@ -3284,12 +3287,12 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
         if (scatter) {
             if ((rc = fill<float>(g, sbar_k, (size_t)g.s_size, 0.f))) return rc;
             // every cell may feed scattered light back: all cells are sources
-            DR_HIP(hipMemcpyAsync(g.src_list, g.morton, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, g.stream));
-            if ((rc = fill<int32_t>(g, g.n_src, 1, (int32_t)n))) return rc;
+            DR_HIP(hipMemcpyAsync(g.w.src_list, g.morton, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, g.stream));
+            if ((rc = fill<int32_t>(g, g.w.n_src, 1, (int32_t)n))) return rc;
         } else {
             dartray_fields tmp{};
-            tmp.tally = g.dsum;   // emitted luminosity sums are not needed here
-            if ((rc = fill<double>(g, g.dsum, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
+            tmp.tally = g.w.dsum;   // emitted luminosity sums are not needed here
+            if ((rc = fill<double>(g, g.w.dsum, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
             if ((rc = select_sources(g, opts, &tmp, false))) return rc;
         }
         A.scatter = scatter ? 1 : 0;
@@ -3302,9 +3305,9 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
             A.sig = nullptr;
             if (sbar_next) {
                 hipLaunchKernelGGL(k_sbar_gather, dim3((unsigned)((n + kGT - 1) / kGT), (unsigned)((nb + kGT - 1) / kGT)),
-                                   dim3(256), 0, g.stream, g.ubar, g.wtab, g.d_lt, sbar_next, n, (int)r0, nb, g.w_row);
+                                   dim3(256), 0, g.stream, g.w.ubar, g.wtab, g.d_lt, sbar_next, n, (int)r0, nb, g.w_row);
                 DR_LAUNCH_CHECK("k_sbar_gather");
-                A.sig = g.ubar;
+                A.sig = g.w.ubar;
             }
             const unsigned blocks = 2048;
             if ((rc = prof_mark(g))) return rc;
@@ -3456,11 +3459,11 @@ static int batch_sequence(dartray_batch *b, const dartray_trace_opts *o, dartray
         for (int k = 0; k < nm; ++k) {
             Grid &g = b->grids[k]->g;
             dartray_fields *f = fields[caller_index[k]];
-            if ((rc = fill<double>(g, g.U_k, (size_t)nl * g.n, 0.0))) return rc;
+            if ((rc = fill<double>(g, g.w.U_k, (size_t)nl * g.n, 0.0))) return rc;
             if ((rc = fill<float>(g, f->S_next, (size_t)g.s_size, 0.f))) return rc;
             if ((rc = fill<double>(g, f->tally, (size_t)nl * DARTRAY_N_TALLY, 0.0))) return rc;
             if (counting && (rc = fill<uint64_t>(g, f->counters, DARTRAY_N_COUNT, 0))) return rc;
-            if (f->escape && (rc = fill<double>(g, g.esc64, (size_t)nl * nray, 0.0))) return rc;
+            if (f->escape && (rc = fill<double>(g, g.w.esc64, (size_t)nl * nray, 0.0))) return rc;
             if ((rc = select_sources(g, o, f, scatter))) return rc;
         }
         const FixedArgs *args = b->d_args + (scatter ? nm : 0);
@@ -3468,7 +3471,7 @@ static int batch_sequence(dartray_batch *b, const dartray_trace_opts *o, dartray
             const int nbb = (int)std::min<int64_t>(nb, nray - r0);
             for (int k = 0; k < nm; ++k) {
                 Grid &g = b->grids[k]->g;
-                if ((rc = fill<float>(g, g.ubar, (size_t)nbb * nl * g.n, 0.f))) return rc;
+                if ((rc = fill<float>(g, g.w.ubar, (size_t)nbb * nl * g.n, 0.f))) return rc;
             }
             hipLaunchKernelGGL(k_batch_items, dim3(1), dim3(64), 0, b->stream, args, nm, nbb, b->d_item_off);
             DR_LAUNCH_CHECK("k_batch_items");
@@ -3609,6 +3612,121 @@ int dartray_batch_replay(dartray_batch *b)
     hipError_t e = hipGraphLaunch(b->exec, b->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return DARTRAY_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Direct pass that allocates nothing.  Its work arrays (energy-density
+// accumulators, direction bins, source list, scan sums, tallies' scratch,
+// error word) are carved from `scratch`, a static device array of
+// kScratchBytes per GPU, instead of the handle's own arrays; the kernels are
+// those of dartray_trace_direct.
+// ---------------------------------------------------------------------------
+
+namespace dr {
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static void *g_scratch_ptr[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept: in host code the array's
+// name is only a stand-in, never a device address.
+static int scratch_base(char **out)
+{
+    int dev = 0;
+    DR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(DARTRAY_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(DARTRAY_E_DEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (char *)g_scratch_ptr[dev];
+    return DARTRAY_OK;
+}
+
+// Work arrays of a fixed-ray direct pass laid out in the scratch array: the
+// fixed-size parts first, the direction bins take what remains (at least one
+// direction).  Sizes beyond kScratchBytes are refused.
+static int scratch_work(const Grid &g, const dartray_trace_opts *o, const dartray_fields *f, char *base, PassWork &w)
+{
+    const size_t n = (size_t)g.n, nl = (size_t)g.n_lambda;
+    const size_t nray = 12 * (size_t)o->nside * (size_t)o->nside;
+    const size_t nblk = (n + kScanBlock - 1) / kScanBlock;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    const size_t o_uk = take(n * nl * sizeof(double)), o_flags = take(n * sizeof(int32_t)),
+                 o_src = take(n * sizeof(int32_t)), o_scan = take(nblk * sizeof(int32_t)), o_nsrc = take(sizeof(int32_t)),
+                 o_nall = take(sizeof(int32_t)), o_err = take(sizeof(uint32_t)),
+                 o_dsum = take(4 * (size_t)kMaxLambda * sizeof(double)),
+                 o_esc = f->escape ? take(nl * nray * sizeof(double)) : 0;
+    off = (off + 255) & ~(size_t)255;
+    const size_t per_dir = n * nl * sizeof(float);
+    if (off + per_dir > kScratchBytes) {
+        return fail(DARTRAY_E_UNSUPPORTED, "the allocation-free direct pass needs " + std::to_string(off + per_dir) +
+                                               " bytes of scratch for this grid; its limit is " +
+                                               std::to_string(kScratchBytes) + " bytes");
+    }
+    w.U_k = (double *)(base + o_uk);
+    w.flags = (int32_t *)(base + o_flags);
+    w.src_list = (int32_t *)(base + o_src);
+    w.scan_blocks = (int32_t *)(base + o_scan);
+    w.n_src = (int32_t *)(base + o_nsrc);
+    w.n_all = (int32_t *)(base + o_nall);
+    w.err_word = (uint32_t *)(base + o_err);
+    w.dsum = (double *)(base + o_dsum);
+    w.esc64 = f->escape ? (double *)(base + o_esc) : nullptr;
+    w.ubar = (float *)(base + off);
+    w.ubar_floats = (kScratchBytes - off) / sizeof(float);
+    return DARTRAY_OK;
+}
+
+}  // namespace dr
+
+extern "C" {
+
+int dartray_trace_direct_noalloc(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields)
+{
+    if (!grid) return fail(DARTRAY_E_INVALID, "null grid");
+    Grid &g = grid->g;
+    int rc = check_opts(g, opts, fields, false);
+    if (rc) return rc;
+    if (opts->adaptive || opts->mode != DARTRAY_MODE_DIRECT)
+        return fail(DARTRAY_E_UNSUPPORTED, "the allocation-free direct pass covers fixed rays only");
+    if (opts->nside > kMaxNsideWTable) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 16");
+    int prev = 0;
+    DR_HIP(hipGetDevice(&prev));
+    if (prev != g.device) DR_HIP(hipSetDevice(g.device));
+    char *base = nullptr;
+    PassWork w{};
+    rc = scratch_base(&base);
+    if (!rc) rc = scratch_work(g, opts, fields, base, w);
+    if (!rc) {
+        // the pass runs on the scratch work set; no timing events are created
+        const int32_t prof = g.prof;
+        g.prof = 0;
+        g.w = w;
+        rc = run_fixed_pass(g, opts, fields, false);
+        if (!rc) rc = finish_pass(g, opts, fields, false);
+        if (!rc && (opts->flags & DARTRAY_FLAG_CHECK)) rc = check_err(g);
+        g.w = g.own;
+        g.prof = prof;
+    }
+    if (prev != g.device) (void)hipSetDevice(prev);
+    return rc;
 }
 
 }  // extern "C"

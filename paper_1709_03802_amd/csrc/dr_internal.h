@@ -48,6 +48,22 @@ struct alignas(64) LeafRec {
 };
 static_assert(sizeof(LeafRec) == 64, "leaf record must be one 64-byte line");
 
+// Per-pass work arrays (device): everything a fixed-ray direct pass writes
+// besides the caller's fields and the handle's persistent state.
+struct PassWork {
+    double *U_k = nullptr;                // [n][nl] (wavelength fastest), FP64 accumulator of FP32 deposits
+    int32_t *flags = nullptr;             // [n] source flags, then scan
+    int32_t *src_list = nullptr;          // [n] compacted sources
+    int32_t *scan_blocks = nullptr;       // block sums
+    int32_t *n_src = nullptr;             // [1] sources the pass traces (after the source mask)
+    int32_t *n_all = nullptr;             // [1] sources of the pass in the whole model (N_s of Eq. 11)
+    uint32_t *err_word = nullptr;         // [1] device error word: bit 0 non-finite U or S
+    double *dsum = nullptr;               // [4 * kMaxLambda] FP64 scratch sums
+    double *esc64 = nullptr;              // [nl][12 * 16^2] FP64 escape by direction (fixed rays)
+    float *ubar = nullptr;                // direction-binned energy density (fixed mode)
+    size_t ubar_floats = 0;
+};
+
 struct Grid {
     // geometry
     int64_t n = 0;
@@ -66,6 +82,7 @@ struct Grid {
     int32_t w_row = 0;                    // sum over wavelengths of npix
 
     hipStream_t stream = nullptr;
+    int device = 0;                       // device current at creation (the stream's device)
 
     // device arrays owned by the handle
     int4 *leaf_box = nullptr;             // lower corner in fine units + span
@@ -80,21 +97,15 @@ struct Grid {
     int32_t *by_level = nullptr;          // leaves finest level first, Morton order within a level
     LambdaTable *d_lt = nullptr;
 
-    // work arrays
-    double *U_k = nullptr;                // [n][nl] (wavelength fastest), FP64 accumulator of FP32 deposits
+    // work arrays of a pass: `own` is what dartray_grid_create allocated,
+    // `w` the set the pass functions use (own, except inside the entry point
+    // that allocates nothing, which points w into its static scratch array)
+    PassWork own{};
+    PassWork w{};
     float *ull_t = nullptr;               // [n][nl] copy of U_LL for the march
-    int32_t *flags = nullptr;             // [n] source flags, then scan
     uint8_t *cell_flag = nullptr;         // [n] scattering-pass source flags by cell
-    int32_t *src_list = nullptr;          // [n] compacted sources
-    int32_t *scan_blocks = nullptr;       // block sums
-    int32_t *n_src = nullptr;             // [1] sources the pass traces (after the source mask)
-    int32_t *n_all = nullptr;             // [1] sources of the pass in the whole model (N_s of Eq. 11)
-    uint32_t *err_word = nullptr;         // [1] device error word: bit 0 non-finite U or S
-    double *dsum = nullptr;               // [4 * kMaxLambda] FP64 scratch sums
     double *s1_sum = nullptr;             // [kMaxLambda] sum of S after the direct pass
     bool have_s1 = false;
-    float *ubar = nullptr;                // direction-binned energy density (fixed mode)
-    size_t ubar_floats = 0;
     // direction tables: entry 4 (N^2 - 1) + pix holds nested pixel pix at
     // Nside N, for N = 1, 2, 4, ... nside_cap, rotated by the current frame
     int32_t nside_cap = 64;
@@ -125,7 +136,6 @@ struct Grid {
     int32_t key_bits = 1;
     int64_t log_chunks = 0;               // launches of the last adaptive pass
 
-    double *esc64 = nullptr;              // [nl][12 * 16^2] FP64 escape by direction (fixed rays)
 
     // adjoint work arrays
     double *rho_bar = nullptr;            // [n] FP64 accumulator of dJ/drho

@@ -39,7 +39,7 @@ EXPORTS = [
     "dartray_trace_adjoint", "dartray_debug_ray_cells", "dartray_workspace_bytes",
     "dartray_last_error", "dartray_version", "dartray_profile_enable", "dartray_profile_read",
     "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create", "dartray_batch_destroy",
-    "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay",
+    "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay", "dartray_trace_direct_noalloc",
 ]
 
 
@@ -137,6 +137,7 @@ def load_library():
     L.dartray_s_offset.restype = C.c_int64
     L.dartray_grid_set_rho.argtypes = [C.c_void_p, C.c_void_p]
     L.dartray_trace_direct.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC)]
+    L.dartray_trace_direct_noalloc.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC)]
     L.dartray_scatter_iter.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(FieldsC), C.POINTER(C.c_double)]
     L.dartray_trace_adjoint.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.c_int32, C.POINTER(C.c_void_p),
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -156,7 +157,8 @@ def load_library():
     L.dartray_last_error.restype = C.c_char_p
     L.dartray_version.restype = C.c_char_p
     for name in ("dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
-                 "dartray_grid_set_rho", "dartray_trace_direct", "dartray_scatter_iter", "dartray_trace_adjoint",
+                 "dartray_grid_set_rho", "dartray_trace_direct", "dartray_trace_direct_noalloc",
+                 "dartray_scatter_iter", "dartray_trace_adjoint",
                  "dartray_debug_ray_cells", "dartray_workspace_bytes", "dartray_profile_enable",
                  "dartray_profile_read", "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create",
                  "dartray_batch_destroy", "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay"):
@@ -373,6 +375,13 @@ def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=T
 def trace_direct(grid: Grid, opts: TraceOpts, fields: Fields):
     fc = fields.c()
     _check(load_library().dartray_trace_direct(grid.h, C.byref(opts), C.byref(fc)))
+
+
+def trace_direct_noalloc(grid: Grid, opts: TraceOpts, fields: Fields):
+    """The direct pass without any device allocation (fixed rays; work arrays
+    in the library's static per-GPU scratch array)."""
+    fc = fields.c()
+    _check(load_library().dartray_trace_direct_noalloc(grid.h, C.byref(opts), C.byref(fc)))
 
 
 def scatter_iter(grid: Grid, opts: TraceOpts, fields: Fields, want_rk=True):
