@@ -6,10 +6,15 @@ emitting cell, every ray-cell crossing at every wavelength the rays carry.
 The metric is ray-cell crossings x wavelengths per second; the numerator is
 the device's own crossing counter from the first (untimed) run.
 
-The same invocation checks the GPU against the FP64 oracle (on a seeded
-source subset when the oracle cannot run the whole workload in seconds),
+The default line times the galaxy disk (207,848 octree leaves, 8
+wavelengths, adaptive rays: step 1, direct, 3 scattering passes) for
+--steps runs, and in the same invocation one run of the largest
+configuration, the 128^3 clumpy medium (16 wavelengths, direct + 4
+scattering passes), reported under "largest".  Each workload is checked
+against the FP64 oracle on seeded source subsets of every pass kind its step
+runs (step 1, direct, scattering: the passes are additive over sources),
 checks the FP64 luminosity balance of every pass, times the oracle on the
-host cores as the CPU baseline, and measures the dominant march kernel with
+host cores as the CPU baseline, and measures its dominant march kernel with
 HIP events on the library's stream for the roofline figure.
 
 Prints one JSON line.
@@ -39,13 +44,15 @@ ATOMIC_PEAK_ROWS_F32 = 2.06e10
 # scattered single-value atomics, one lane per 64-byte segment
 ATOMIC_PEAK_SINGLE = 2.11e10
 
-# HBM bytes per step-1 launch on the disk workload from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (scaled by a plain copy), valid for the kernel sources hashed here
+# HBM bytes per launch of the dominant march kernel of each workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a plain copy), valid for the
+# kernel sources hashed here (null traffic once the sources change)
 PMC_TRAFFIC = {
-    "workload": "disk",
-    "bytes_per_launch": 2.6299e+13 + 1.9904e+13,
-    "sources_sha256": "608cac3514d632f4c5c1d8321b02dd29be5e62db23aefc70b98a06407b3bc601",
-    "profile": "profiles/k_march_adaptive_step1_disk.md",
+    "disk": {
+        "bytes_per_launch": 2.6299e+13 + 1.9904e+13,
+        "sources_sha256": "608cac3514d632f4c5c1d8321b02dd29be5e62db23aefc70b98a06407b3bc601",
+        "profile": "profiles/k_march_adaptive_step1_disk.md",
+    },
 }
 # the same for the adjoint march of the 64^3 clumpy grid at 4 wavelengths, per
 # backward step (three launches): HBM bytes, and atomic requests from
@@ -346,6 +353,276 @@ def nl_template(k):
     return 1 if k <= 1 else 4 if k <= 4 else 8
 
 
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def rel_max(x, ref):
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nz = (np.abs(ref) > 0) | (np.abs(x) > 0)
+    if not nz.any():
+        return 0.0
+    return float((np.abs(x - ref)[nz] / np.maximum(np.abs(ref[nz]), 1e-30)).max())
+
+
+def seeded_mask(n, cells, k, seed):
+    rng = np.random.default_rng(seed)
+    mask = np.zeros(n, dtype=np.uint8)
+    mask[rng.choice(cells, min(k, len(cells)), replace=False)] = 1
+    return mask
+
+
+def synthetic_pending(m, grid, n_held, n_traced, seed):
+    """Pending scattered luminosity held by n_held seeded dusty cells (random
+    pixel values scaled by the cell's stellar luminosity), and the mask that
+    selects n_traced of them as the sources of a scattering pass."""
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(np.flatnonzero(grid.rho > 0), n_held, replace=False)
+    S = np.zeros(m.s_size)
+    for l in range(grid.n_lambda):
+        blk = S[m.s_offset[l]:m.s_offset[l + 1]].reshape(grid.n, -1)
+        lum = 4 * np.pi * grid.emis[l, cells] * grid.side()[cells] ** 3 + 1e-6
+        blk[cells] = rng.random((cells.size, blk.shape[1])) * lum[:, None] / blk.shape[1]
+    mask = np.zeros(grid.n, dtype=np.uint8)
+    mask[cells[:n_traced]] = 1
+    return f32(S), mask
+
+
+def compare_pass(dr, oracle, m, G, f, ref, what, with_s=True):
+    """One pass of the GPU (fields f, U_pass kept) against the oracle's."""
+    eu = rel_max(f.U_pass.cpu().numpy(), ref.U)
+    es = None
+    if with_s:
+        es = max(rel_max(f.S_pending[G.s_offset[l]:G.s_offset[l + 1]].cpu().numpy(),
+                         ref.S[m.s_offset[l]:m.s_offset[l + 1]]) for l in range(G.nl))
+    c = f.counters.cpu().numpy()
+    same = all(int(c[a]) == int(ref.counters[b]) for a, b in
+               ((dr.C_CROSSINGS, oracle.C_CROSS), (dr.C_RAYS, oracle.C_RAYS), (dr.C_SPLITS, oracle.C_SPLITS),
+                (dr.C_CUTS, oracle.C_CUTS), (dr.C_DEPOSITS, oracle.C_DEPOSITS), (dr.C_SKIPS, oracle.C_SKIPS)))
+    return {"checked": what, "U_max_rel": eu, "S_max_rel": es, "crossings": int(ref.counters[oracle.C_CROSS]),
+            "counters_equal": bool(same), "pass": bool(eu <= 1e-4 and (es is None or es <= 1e-4) and same)}
+
+
+def parity_and_cpu(dr, G, grid, pol, wl_name, sample_sources):
+    """Seeded source subsets of every pass kind the step runs, against the
+    FP64 oracle with the same FP32 inputs; the oracle's time on the first
+    (largest) subset is the CPU baseline."""
+    import torch
+    import oracle
+    m = oracle.Model(grid)
+    nthreads = os.cpu_count() or 1
+    emitting = np.flatnonzero(grid.emis.sum(axis=0) > 0)
+    checks = []
+    cpu = None
+    if pol.adaptive:
+        # step 1 of many sources (CPU baseline), then the direct pass and a
+        # scattering pass of a few, U_LL frozen to the step-1 result
+        mask = seeded_mask(grid.n, emitting, sample_sources, 1709)
+        t0 = time.perf_counter()
+        r1 = m.run_pass(oracle.STEP1, pol, source_mask=mask, n_threads=nthreads)
+        t_cpu = time.perf_counter() - t0
+        f = dr.Fields(G, keep_pass_u=True)
+        dr.trace_direct(G, dr.make_opts(pol, dr.MODE_STEP1, source_mask=torch.as_tensor(mask).cuda()), f)
+        torch.cuda.synchronize()
+        f.U_pass.copy_(f.U_LL)
+        c1 = compare_pass(dr, oracle, m, G, f, r1, f"step 1 of {int(mask.sum())} seeded emitting cells",
+                          with_s=False)
+        checks.append(c1)
+        cpu = {"value": c1["crossings"] * grid.n_lambda / t_cpu, "unit": "crossings*lambda/s", "cores": nthreads,
+               "kind": "oracle", "sample": f"{c1['checked']}, {c1['crossings']} crossings x {grid.n_lambda} "
+                                          f"wavelengths in {t_cpu:.1f} s"}
+        ull = f32(r1.U)
+        dmask = seeded_mask(grid.n, emitting, 4, 1710)
+        r2 = m.run_pass(oracle.DIRECT, pol, U_LL=ull, source_mask=dmask, n_threads=nthreads)
+        f2 = dr.Fields(G, keep_pass_u=True)
+        f2.U_LL.copy_(torch.as_tensor(ull, dtype=torch.float32))
+        dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=torch.as_tensor(dmask).cuda()), f2)
+        torch.cuda.synchronize()
+        checks.append(compare_pass(dr, oracle, m, G, f2, r2, "direct pass of 4 seeded emitting cells, U_LL from "
+                                   "the step-1 sample"))
+        Sp, smask = synthetic_pending(m, grid, 104, 4, 1711)
+        r3 = m.run_pass(oracle.SCATTER, pol, S_pending=Sp, U_LL=ull, source_mask=smask, n_threads=nthreads)
+        f2.U_LL.copy_(torch.as_tensor(ull, dtype=torch.float32))
+        f2.S_pending[:G.s_size].copy_(torch.as_tensor(Sp, dtype=torch.float32))
+        dr.scatter_iter(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=torch.as_tensor(smask).cuda()), f2,
+                        want_rk=False)
+        torch.cuda.synchronize()
+        checks.append(compare_pass(dr, oracle, m, G, f2, r3, "scattering pass of 4 of 104 seeded cells holding "
+                                   "synthetic pending light"))
+        del f, f2
+    elif grid.n > 100_000:
+        # too large for the oracle's whole run: the direct pass of seeded star
+        # cells (CPU baseline) and a scattering pass of a few seeded cells
+        mask = seeded_mask(grid.n, emitting, sample_sources // 4, 1709)
+        t0 = time.perf_counter()
+        r2 = m.run_pass(oracle.DIRECT, pol, source_mask=mask, n_threads=nthreads)
+        t_cpu = time.perf_counter() - t0
+        f = dr.Fields(G, keep_pass_u=True)
+        dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=torch.as_tensor(mask).cuda()), f)
+        torch.cuda.synchronize()
+        c2 = compare_pass(dr, oracle, m, G, f, r2, f"direct pass of {int(mask.sum())} seeded star cells")
+        checks.append(c2)
+        cpu = {"value": c2["crossings"] * grid.n_lambda / t_cpu, "unit": "crossings*lambda/s", "cores": nthreads,
+               "kind": "oracle", "sample": f"{c2['checked']}, {c2['crossings']} crossings x {grid.n_lambda} "
+                                          f"wavelengths in {t_cpu:.1f} s"}
+        del r2
+        Sp, smask = synthetic_pending(m, grid, 116, 16, 1711)
+        r3 = m.run_pass(oracle.SCATTER, pol, S_pending=Sp, source_mask=smask, n_threads=nthreads)
+        f.S_pending[:G.s_size].copy_(torch.as_tensor(Sp, dtype=torch.float32))
+        dr.scatter_iter(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=torch.as_tensor(smask).cuda()), f,
+                        want_rk=False)
+        torch.cuda.synchronize()
+        checks.append(compare_pass(dr, oracle, m, G, f, r3, "scattering pass of 16 of 116 seeded cells holding "
+                                   "synthetic pending light"))
+        del f, r3, Sp
+    else:
+        t0 = time.perf_counter()
+        ref = oracle.run(m, pol, n_threads=nthreads)
+        t_cpu = time.perf_counter() - t0
+        out = dr.run(G, pol)
+        torch.cuda.synchronize()
+        eu = rel_max(out.fields.U.cpu().numpy(), ref.U)
+        es = rel_max(out.fields.S_total.cpu().numpy()[:G.s_size], ref.S_total)
+        ref_cross = sum(int(r.counters[oracle.C_CROSS]) for r in ref.passes)
+        gpu_cross = sum(int(c[dr.C_CROSSINGS]) for c in out.counters)
+        checks.append({"checked": f"full {wl_name} run (all passes)", "U_max_rel": eu, "S_max_rel": es,
+                       "crossings": ref_cross, "counters_equal": ref_cross == gpu_cross,
+                       "pass": bool(eu <= 1e-4 and es <= 1e-4 and ref_cross == gpu_cross)})
+        cpu = {"value": ref_cross * grid.n_lambda / t_cpu, "unit": "crossings*lambda/s", "cores": nthreads,
+               "kind": "oracle", "sample": f"full {wl_name} run, {ref_cross} crossings x {grid.n_lambda} wavelengths "
+                                          f"in {t_cpu:.1f} s"}
+    parity = {"checks": checks, "gate": "max rel err <= 1e-4 on every U and S element of each checked pass, "
+                                        "counters equal", "pass": all(c["pass"] for c in checks)}
+    log(f"parity {parity}")
+    return parity, cpu
+
+
+def algorithmic_bytes(pol, grid):
+    """What the method itself moves per crossing of the march: the crossed
+    cell's record (octree: leaf key and density, 16 B; uniform grid: the
+    density, 4 B, the index being arithmetic) and one FP32 accumulate per
+    wavelength (4 B read, 4 B written)."""
+    return (16 if grid.max_level > 0 else 4) + 8 * grid.n_lambda
+
+
+def measure(dr, W, name, steps, warmup, args, timed_counting=False):
+    """Time `steps` whole runs of workload `name` (after `warmup` runs) and
+    return its measurement: value, roofline of the dominant march, atomic
+    roofline, parity, CPU baseline.  With timed_counting the first run (with
+    counters) is the one timed, after a warm-up of the direct pass alone."""
+    import torch
+    wl = W.by_name(name)
+    grid = as_f32(wl.grid)
+    pol = wl.policy
+    G = dr.Grid(grid, nside_max=max(pol.nside_max, 64))
+    f = dr.Fields(G)
+    log(f"workload {wl.name}: {wl.description}")
+    kinds = dr.PROF_STEP1 if pol.adaptive else dr.PROF_FIXED
+    if timed_counting:
+        dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT), f)
+        f.U.zero_()
+        torch.cuda.synchronize()
+        G.profile(kinds)
+        t0 = time.perf_counter()
+        out = dr.run(G, pol, fields=f, collect=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps_done = 1
+    else:
+        f.U.zero_()
+        out = dr.run(G, pol, fields=f, collect=True)
+        torch.cuda.synchronize()
+    counters = np.array(out.counters)
+    crossings = int(counters[:, dr.C_CROSSINGS].sum())
+    cross_lambda = crossings * grid.n_lambda
+    balance = max(float(np.max(np.abs(t[:, 1:6].sum(axis=1) - t[:, 0]) / np.maximum(t[:, 0], 1e-300)))
+                  for t in out.tallies)
+    per_pass = [int(c[dr.C_CROSSINGS]) for c in counters]
+    log(f"{crossings} crossings per run ({per_pass}), max luminosity-balance residual {balance:.2e}")
+    if not timed_counting:
+        def step():
+            f.U.zero_()
+            dr.run(G, pol, fields=f, collect=False)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        G.profile(kinds)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps_done = steps
+    kern_ms, launches = G.profile_read()
+    G.profile(0)
+    del f
+
+    parity, cpu = (None, None) if args.no_cpu_baseline else parity_and_cpu(dr, G, grid, pol, wl.name,
+                                                                           args.sample_sources)
+    ms_per_step = 1e3 * dt / steps_done
+    value = cross_lambda / (dt / steps_done)
+    if pol.adaptive:
+        kern_cross = per_pass[0]
+        kernel = f"k_march_adaptive<{nl_pow2(grid.n_lambda)}, 0> (step 1)"
+        impl_bytes = 64 + 2 * 8 * grid.n_lambda
+    else:
+        kern_cross = crossings
+        kernel = f"k_march_fixed<{nl_pow2(grid.n_lambda)}>"
+        impl_bytes = 64 + 2 * 4 * grid.n_lambda
+    per_cross = algorithmic_bytes(pol, grid)
+    launches_per_step = launches / steps_done
+    avg_ms = kern_ms / max(launches, 1)
+    cross_per_launch = kern_cross / launches_per_step
+    achieved = cross_per_launch * per_cross / (avg_ms * 1e-3) / 1e9
+    # 64-byte atomic requests per crossing: one row of n_lambda FP64
+    # (adaptive) or FP32 (fixed) values; a row narrower than 64 bytes shares
+    # its segment with neighbouring cells' rows and has no matching ceiling
+    row_bytes = (8 if pol.adaptive else 4) * grid.n_lambda
+    atomic_peak = ATOMIC_PEAK_ROWS_F64 if pol.adaptive else ATOMIC_PEAK_ROWS_F32
+    if row_bytes >= 64:
+        rpc = row_bytes / 64.0
+        req_rate = rpc * cross_per_launch / (avg_ms * 1e-3)
+        atomic_roof = {"achieved": req_rate, "peak": atomic_peak, "unit": "64-byte atomic rows/s",
+                       "frac": req_rate / atomic_peak, "requests_per_crossing": rpc}
+    else:
+        atomic_roof = {"achieved": None, "peak": None, "unit": "64-byte atomic rows/s", "frac": None,
+                       "requests_per_crossing": None,
+                       "note": f"{row_bytes}-byte rows share 64-byte segments; no matching ceiling"}
+    pmc = PMC_TRAFFIC.get(wl.name)
+    traffic = pmc["bytes_per_launch"] if pmc and sources_sha256() == pmc["sources_sha256"] else None
+    return {
+        "value": value, "ms_per_step": ms_per_step, "steps": steps_done,
+        "config": {"workload": wl.name, "description": wl.description, "cells": int(grid.n),
+                   "n_lambda": int(grid.n_lambda),
+                   "rays": (f"adaptive nside {pol.nside}..{pol.nside_max}, N_rays {pol.n_rays_min}, f_U {pol.f_U}"
+                            if pol.adaptive else f"fixed nside {pol.nside}"),
+                   "passes": (["step1"] if pol.adaptive and pol.step1 else []) + ["direct"] +
+                             [f"scatter{k + 1}" for k in range(pol.n_scatter)],
+                   "crossings_per_step": crossings, "crossings_per_pass": per_pass,
+                   "balance_max_rel": balance, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+                     "avg_launch_ms": avg_ms, "bytes_per_crossing": per_cross,
+                     "bytes_per_crossing_note": "the method's own bytes: cell record (octree key + density 16 B, "
+                                                "uniform density 4 B) and one FP32 accumulate (4 B read + 4 B "
+                                                "written) per wavelength",
+                     "implementation_bytes_per_crossing": impl_bytes,
+                     "crossings_per_launch": cross_per_launch},
+        # the deposits are one 64-byte atomic request per crossing at 8 FP64
+        # or 16 FP32 wavelengths: the request rate against the measured
+        # ceiling of that access pattern
+        "atomic_roofline": atomic_roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+
+
+def nl_pow2(k):
+    return 1 if k <= 1 else 4 if k <= 4 else 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,7 +634,8 @@ def main():
                     help="time the adjoint march (dJ/drho) of a fixed-ray workload instead of the forward passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched-wavelength, batched-model and autotuner measurements")
+                    help="skip the largest configuration's run and the batched-wavelength, batched-model, "
+                         "autotuner and adjoint measurements")
     ap.add_argument("--sample-sources", type=int, default=1536,
                     help="seeded emitting cells whose step 1 (adaptive workloads) is checked against the oracle and "
                          "timed on the CPU (about 12 s of oracle work on 16 cores for the disk); grids too large "
@@ -376,170 +654,35 @@ def main():
     from paper_1709_03802_amd import workloads as W
 
     torch.cuda.set_device(0)
-    wl = W.by_name(args.workload)
-    grid = as_f32(wl.grid)
-    pol = wl.policy
-    G = dr.Grid(grid, nside_max=max(pol.nside_max, 64))
-    f = dr.Fields(G)
-    log(f"workload {wl.name}: {wl.description}")
-
-    # ---- first run: counters, balance
-    f.U.zero_()
-    out = dr.run(G, pol, fields=f, collect=True)
-    torch.cuda.synchronize()
-    counters = np.array(out.counters)
-    crossings = int(counters[:, dr.C_CROSSINGS].sum())
-    cross_lambda = crossings * grid.n_lambda
-    balance = max(float(np.max(np.abs(t[:, 1:6].sum(axis=1) - t[:, 0]) / np.maximum(t[:, 0], 1e-300)))
-                  for t in out.tallies)
-    per_pass = [int(c[dr.C_CROSSINGS]) for c in counters]
-    log(f"{crossings} crossings per run ({per_pass}), max luminosity-balance residual {balance:.2e}")
-
-    # ---- parity and CPU baseline against the FP64 oracle
-    parity, cpu = None, None
-    if not args.no_cpu_baseline:
-        import oracle
-        m = oracle.Model(grid)
-        nthreads = os.cpu_count() or 1
-        if pol.adaptive:
-            rng = np.random.default_rng(1709)
-            sample = np.zeros(grid.n, dtype=np.uint8)
-            sample[rng.choice(np.flatnonzero(grid.emis.sum(axis=0) > 0), args.sample_sources, replace=False)] = 1
-            t0 = time.perf_counter()
-            ref = m.run_pass(oracle.STEP1, pol, source_mask=sample, n_threads=nthreads)
-            t_cpu = time.perf_counter() - t0
-            fs = dr.Fields(G)
-            dr.trace_direct(G, dr.make_opts(pol, dr.MODE_STEP1, source_mask=torch.as_tensor(sample).cuda()), fs)
-            torch.cuda.synchronize()
-            got = fs.U_LL.cpu().numpy().astype(np.float64)
-            ref_U = ref.U
-            ref_cross = int(ref.counters[oracle.C_CROSS])
-            gpu_cross = int(fs.counters.cpu().numpy()[dr.C_CROSSINGS])
-            what = f"step 1 of {args.sample_sources} seeded emitting cells"
-        elif grid.n > 100_000:
-            # too large for the oracle's whole run: the direct pass of seeded
-            # star cells over the whole grid
-            rng = np.random.default_rng(1709)
-            sample = np.zeros(grid.n, dtype=np.uint8)
-            sample[rng.choice(np.flatnonzero(grid.emis.sum(axis=0) > 0), args.sample_sources // 4, replace=False)] = 1
-            t0 = time.perf_counter()
-            ref = m.run_pass(oracle.DIRECT, pol, source_mask=sample, n_threads=nthreads)
-            t_cpu = time.perf_counter() - t0
-            fs = dr.Fields(G)
-            dr.trace_direct(G, dr.make_opts(pol, dr.MODE_DIRECT, source_mask=torch.as_tensor(sample).cuda()), fs)
-            torch.cuda.synchronize()
-            got = fs.U.cpu().numpy().astype(np.float64)
-            ref_U = ref.U
-            ref_cross = int(ref.counters[oracle.C_CROSS])
-            gpu_cross = int(fs.counters.cpu().numpy()[dr.C_CROSSINGS])
-            what = f"direct pass of {args.sample_sources // 4} seeded star cells"
-            del fs
-        else:
-            t0 = time.perf_counter()
-            ref_run = oracle.run(m, pol, n_threads=nthreads)
-            t_cpu = time.perf_counter() - t0
-            got = f.U.cpu().numpy().astype(np.float64)
-            ref_U = ref_run.U
-            ref_cross = sum(int(r.counters[oracle.C_CROSS]) for r in ref_run.passes)
-            gpu_cross = crossings
-            what = f"full {wl.name} run (all passes)"
-        nz = (np.abs(ref_U) > 0) | (np.abs(got) > 0)
-        e = np.abs(got - ref_U)[nz] / np.maximum(np.abs(ref_U[nz]), 1e-300)
-        parity = {"checked": what, "U_max_rel": float(e.max()), "U_p999_rel": float(np.quantile(e, 0.999)),
-                  "crossings_gpu": gpu_cross, "crossings_oracle": ref_cross, "gate": 1e-4,
-                  "pass": bool(e.max() <= 1e-4)}
-        cpu = {"value": ref_cross * grid.n_lambda / t_cpu, "unit": "crossings*lambda/s", "cores": nthreads,
-               "kind": "oracle", "sample": f"{what}, {ref_cross} crossings x {grid.n_lambda} wavelengths in {t_cpu:.1f} s"}
-        log(f"oracle: {what} in {t_cpu:.1f} s; parity {parity}")
-
-    # ---- timed steps
-    def step():
-        f.U.zero_()
-        dr.run(G, pol, fields=f, collect=False)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kinds = dr.PROF_STEP1 if pol.adaptive else dr.PROF_FIXED
-    G.profile(kinds)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kern_ms, launches = G.profile_read()
-    G.profile(0)
-
-    ms_per_step = 1e3 * dt / args.steps
-    value = cross_lambda / (dt / args.steps)
-    # algorithmic bytes of the dominant march kernel per crossing: the
-    # 64-byte leaf record read, and the energy-density row read-modify-write
-    # (adaptive: n_lambda FP64 accumulators; fixed: one FP32 direction bin
-    # per wavelength)
-    if pol.adaptive:
-        kern_cross = per_pass[0]
-        per_cross = 64 + 2 * 8 * grid.n_lambda
-        kernel = "k_march_adaptive (step 1)"
-    else:
-        kern_cross = crossings
-        per_cross = 64 + 2 * 4 * grid.n_lambda
-        kernel = f"k_march_fixed<{grid.n_lambda}>" if grid.n_lambda in (1, 4, 8, 16, 32, 64) else "k_march_fixed"
-    launches_per_step = launches / args.steps
-    avg_ms = kern_ms / max(launches, 1)
-    achieved = (kern_cross * per_cross / launches_per_step) / (avg_ms * 1e-3) / 1e9
-    # 64-byte atomic requests per crossing: one row of n_lambda FP64 (adaptive)
-    # or FP32 (fixed) values.  A row narrower than 64 bytes shares its segment
-    # with the rows of neighbouring cells, so its request count depends on which
-    # lanes hit one segment, and no measured ceiling has that access pattern:
-    # no atomic roofline is given then
-    row_bytes = (8 if pol.adaptive else 4) * grid.n_lambda
-    atomic_peak = ATOMIC_PEAK_ROWS_F64 if pol.adaptive else ATOMIC_PEAK_ROWS_F32
-    if row_bytes >= 64:
-        rpc = row_bytes / 64.0
-        req_rate = rpc * (kern_cross / launches_per_step) / (avg_ms * 1e-3)
-        atomic_roof = {"achieved": req_rate, "peak": atomic_peak, "unit": "64-byte atomic rows/s",
-                       "frac": req_rate / atomic_peak, "requests_per_crossing": rpc}
-    else:
-        atomic_roof = {"achieved": None, "peak": None, "unit": "64-byte atomic rows/s", "frac": None,
-                       "requests_per_crossing": None,
-                       "note": f"{row_bytes}-byte rows share 64-byte segments; no matching ceiling"}
-    traffic = None
-    if wl.name == PMC_TRAFFIC["workload"] and sources_sha256() == PMC_TRAFFIC["sources_sha256"]:
-        traffic = PMC_TRAFFIC["bytes_per_launch"]
+    head = measure(dr, W, args.workload, args.steps, args.warmup, args)
+    parity_ok = head["parity"]["pass"] if head["parity"] else None
     res = {
         "metric": "ray-cell crossings x lambda per second (1 MI355X) at rel err <= 1e-4 vs the FP64 oracle",
-        "value": value,
+        "value": head["value"],
         "unit": "crossings*lambda/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "description": wl.description, "cells": int(grid.n),
-                   "n_lambda": int(grid.n_lambda),
-                   "rays": (f"adaptive nside {pol.nside}..{pol.nside_max}, N_rays {pol.n_rays_min}, f_U {pol.f_U}"
-                            if pol.adaptive else f"fixed nside {pol.nside}"),
-                   "passes": (["step1"] if pol.adaptive and pol.step1 else []) + ["direct"] +
-                             [f"scatter{k + 1}" for k in range(pol.n_scatter)],
-                   "crossings_per_step": crossings, "crossings_per_pass": per_pass,
-                   "balance_max_rel": balance, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                     "avg_launch_ms": avg_ms, "bytes_per_crossing": per_cross,
-                     "crossings_per_launch": kern_cross / launches_per_step},
-        # the deposits are one 64-byte atomic request per crossing at 8 FP64
-        # or 16 FP32 wavelengths (rocprofv3 TCC_ATOMIC equals the step-1
-        # crossing count): the request rate against the measured ceiling is
-        # the binding roofline of the march
-        "atomic_roofline": atomic_roof,
-        "cpu_baseline": cpu,
-        "parity": parity,
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "atomic_roofline": head["atomic_roofline"],
+        "cpu_baseline": head["cpu_baseline"],
+        "parity": head["parity"],
+        "parity_pass": parity_ok,
     }
     if not args.no_extras:
+        if args.workload != "clumpy128":
+            log("largest configuration: one run of clumpy128 ...")
+            big = measure(dr, W, "clumpy128", 1, 0, args, timed_counting=True)
+            res["largest"] = big
+            log(f"largest: value {big['value']:.4g}, {big['ms_per_step']:.0f} ms, roofline {big['roofline']}")
+            torch.cuda.empty_cache()
         log("batched wavelengths ...")
         res["batched_lambda"] = batched_lambda(dr, W)
         log(f"batched wavelengths: {res['batched_lambda']}")
