@@ -58,6 +58,9 @@ class GridDesc(C.Structure):
         ("n_fwhm", C.c_double),
         ("k_max", C.c_int32),
         ("c_light", C.c_double),
+        ("n_point", C.c_int64),
+        ("point_pos", C.POINTER(C.c_double)),
+        ("point_lum", C.POINTER(C.c_double)),
     ]
 
 
@@ -75,6 +78,21 @@ class PassOpts(C.Structure):
         ("max_steps", C.c_int64),
         ("n_threads", C.c_int32),
         ("a_RT", C.c_double),
+    ]
+
+
+class Observer(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("dir", C.c_double * 3),
+        ("up", C.c_double * 3),
+        ("centre", C.c_double * 3),
+        ("pixel_size", C.c_double),
+        ("nx", C.c_int32),
+        ("ny", C.c_int32),
+        ("pos", C.c_double * 3),
+        ("nside_map", C.c_int32),
+        ("frame", C.c_double * 9),
     ]
 
 
@@ -126,6 +144,10 @@ def lib():
                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]
         L.orc_adjoint_pass.restype = C.c_int
+        L.orc_healpix_pix.argtypes = [C.c_int64, C.POINTER(C.c_double)]
+        L.orc_healpix_pix.restype = C.c_int64
+        L.orc_observe.argtypes = [C.c_void_p, C.POINTER(Observer), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_observe.restype = C.c_int
         _lib = L
     return _lib
 
@@ -151,6 +173,29 @@ def healpix_vec(nside: int, pix: int) -> np.ndarray:
 
 def healpix_vecs(nside: int) -> np.ndarray:
     return np.array([healpix_vec(nside, p) for p in range(12 * nside * nside)])
+
+
+def healpix_pix(nside: int, v) -> int:
+    return int(lib().orc_healpix_pix(nside, _dvec(v)))
+
+
+def observer(kind, dir=(0, 0, 1), up=(0, 1, 0), centre=(0, 0, 0), pixel_size=1.0, nx=1, ny=1, pos=(0, 0, 0),
+             nside_map=1, frame=None) -> Observer:
+    """kind 'distant' (image of nx x ny pixels of edge pixel_size centred on
+    `centre`, seen from direction `dir`) or 'internal' (all-sky HEALPix map at
+    nside_map seen from `pos`)."""
+    o = Observer()
+    o.kind = 0 if kind == "distant" else 1
+    o.dir = (C.c_double * 3)(*[float(x) for x in dir])
+    o.up = (C.c_double * 3)(*[float(x) for x in up])
+    o.centre = (C.c_double * 3)(*[float(x) for x in centre])
+    o.pixel_size = float(pixel_size)
+    o.nx, o.ny = int(nx), int(ny)
+    o.pos = (C.c_double * 3)(*[float(x) for x in pos])
+    o.nside_map = int(nside_map)
+    fr = np.eye(3) if frame is None else np.asarray(frame, dtype=np.float64)
+    o.frame = (C.c_double * 9)(*fr.ravel().tolist())
+    return o
 
 
 def hg(g: float, mu: float) -> float:
@@ -192,6 +237,8 @@ class Model:
             albedo=np.ascontiguousarray(grid.albedo, dtype=np.float64),
             g=np.ascontiguousarray(grid.g, dtype=np.float64),
             nside_sca=np.ascontiguousarray(grid.nside_sca, dtype=np.int32),
+            point_pos=np.ascontiguousarray(getattr(grid, "point_pos", np.zeros((0, 3))), dtype=np.float64),
+            point_lum=np.ascontiguousarray(getattr(grid, "point_lum", np.zeros((0, 0))), dtype=np.float64),
         )
         k = self._keep
         d = GridDesc()
@@ -211,6 +258,10 @@ class Model:
         d.n_fwhm = float(grid.n_fwhm)
         d.k_max = int(grid.k_max)
         d.c_light = float(grid.c_light)
+        d.n_point = int(k["point_pos"].shape[0])
+        if d.n_point:
+            d.point_pos = _p(k["point_pos"], C.c_double)
+            d.point_lum = _p(k["point_lum"], C.c_double)
         self._desc = d
         h = C.c_void_p()
         rc = lib().orc_model_create(C.byref(d), C.byref(h))
@@ -258,6 +309,17 @@ class Model:
     def count_sources(self, mode, S_pending=None):
         Sp = None if S_pending is None else np.ascontiguousarray(S_pending, dtype=np.float64)
         return int(lib().orc_count_sources(self.h, mode, None if Sp is None else _p(Sp, C.c_double)))
+
+    def observe(self, obs: Observer, S_total=None) -> np.ndarray:
+        """Observer map [n_lambda, npix]: surface brightness of every cell's
+        emission (and scattered light from S_total) attenuated to the observer."""
+        npix = obs.nx * obs.ny if obs.kind == 0 else 12 * obs.nside_map ** 2
+        out = np.zeros(self.nl * npix)
+        St = None if S_total is None else np.ascontiguousarray(S_total, dtype=np.float64)
+        rc = lib().orc_observe(self.h, C.byref(obs), None if St is None else _p(St, C.c_double), _p(out, C.c_double))
+        if rc != 0:
+            raise ValueError(f"oracle observe failed (status {rc})")
+        return out.reshape(self.nl, npix)
 
     def run_pass(self, mode, policy, S_pending=None, U_LL=None, frame=None, source_mask=None,
                  max_steps=0, n_threads=0):

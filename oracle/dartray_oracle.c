@@ -124,6 +124,9 @@ typedef struct {
     double n_fwhm;
     int32_t k_max;
     double c_light;
+    int64_t n_point;        /* point sources (Sect. 3.6) */
+    const double *point_pos; /* [n_point][3] positions inside the root block */
+    const double *point_lum; /* [n_lambda][n_point] luminosity */
 } orc_grid_desc;
 
 typedef struct {
@@ -136,6 +139,7 @@ typedef struct {
     double *side;           /* [n] */
     int32_t *nside_sca;     /* [n_lambda] effective */
     int64_t *s_offset;      /* [n_lambda + 1] start of each wavelength block of S */
+    int64_t *point_cell;    /* [n_point] leaf holding each point source */
 } orc_model;
 
 typedef struct {
@@ -206,6 +210,57 @@ void orc_healpix_vec(int64_t nside, int64_t pix, double v[3])
     v[0] = st * cos(phi);
     v[1] = st * sin(phi);
     v[2] = z;
+}
+
+/* Nested pixel at `nside` containing the direction v (need not be unit
+ * length), following the construction of Gorski et al. 2005: the
+ * equatorial belt (|z| <= 2/3) is cut by the two families of lines
+ * phi / (pi / 2) -+ (3/4) z = const, which give the face and the in-face
+ * coordinates; the polar caps by the lines of constant (1 - |z|) phi within
+ * each quarter. */
+int64_t orc_healpix_pix(int64_t nside, const double v[3])
+{
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double z = v[2] / r;
+    double phi = atan2(v[1], v[0]);
+    if (phi < 0.0) phi += 2.0 * M_PI;
+    double tt = phi / (0.5 * M_PI);             /* in [0, 4] */
+    if (tt >= 4.0) tt -= 4.0;
+    int64_t face, ix, iy;
+    if (fabs(z) <= 2.0 / 3.0) {
+        double a = (double)nside * (0.5 + tt), b = 0.75 * (double)nside * z;
+        int64_t jp = (int64_t)floor(a - b);     /* index of the ascending edge line */
+        int64_t jm = (int64_t)floor(a + b);     /* index of the descending edge line */
+        int64_t fp = jp / nside, fm = jm / nside;
+        if (fp == fm) face = (fp % 4) + 4;      /* an equatorial face */
+        else if (fp < fm) face = fp % 4;        /* a northern face */
+        else face = (fm % 4) + 8;               /* a southern face */
+        ix = jm % nside;
+        iy = nside - 1 - (jp % nside);
+    } else {
+        int64_t q = (int64_t)floor(tt);
+        if (q > 3) q = 3;
+        double tp = tt - (double)q;
+        double w = (double)nside * sqrt(3.0 * (1.0 - fabs(z)));
+        int64_t jp = (int64_t)floor(tp * w), jm = (int64_t)floor((1.0 - tp) * w);
+        if (jp > nside - 1) jp = nside - 1;
+        if (jm > nside - 1) jm = nside - 1;
+        if (z > 0.0) {
+            face = q;
+            ix = nside - 1 - jm;
+            iy = nside - 1 - jp;
+        } else {
+            face = q + 8;
+            ix = jp;
+            iy = jm;
+        }
+    }
+    int64_t sub = 0;
+    for (int bit = 0; bit < 31; ++bit) {
+        sub |= ((ix >> bit) & 1) << (2 * bit);
+        sub |= ((iy >> bit) & 1) << (2 * bit + 1);
+    }
+    return face * nside * nside + sub;
 }
 
 static void orc_rotate(const double R[9], const double a[3], double b[3])
@@ -305,10 +360,13 @@ void orc_model_destroy(orc_model *m)
     free(m->side);
     free(m->nside_sca);
     free(m->s_offset);
+    free(m->point_cell);
     free(m);
 }
 
 static int is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t orc_locate(const orc_model *m, const double p[3], const double d[3]);
 
 int orc_model_create(const orc_grid_desc *d, orc_model **out)
 {
@@ -369,6 +427,20 @@ int orc_model_create(const orc_grid_desc *d, orc_model **out)
             !(d->g[l] > -1.0 && d->g[l] < 1.0)) { orc_model_destroy(m); return ORC_E_INVALID; }
         m->nside_sca[l] = ns;
         m->s_offset[l + 1] = m->s_offset[l] + d->n_leaves * 12 * (int64_t)ns * ns;
+    }
+    /* point sources: inside the root block, finite non-negative luminosity;
+     * each belongs to the leaf holding it (a point on a face to the upper side) */
+    if (d->n_point < 0 || (d->n_point > 0 && (!d->point_pos || !d->point_lum))) { orc_model_destroy(m); return ORC_E_INVALID; }
+    m->point_cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(d->n_point > 0 ? d->n_point : 1));
+    if (!m->point_cell) { orc_model_destroy(m); return ORC_E_OOM; }
+    for (int64_t k = 0; k < d->n_point; ++k) {
+        const double up[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < d->n_lambda; ++l) {
+            double v = d->point_lum[(int64_t)l * d->n_point + k];
+            if (!(v >= 0.0) || !isfinite(v)) { orc_model_destroy(m); return ORC_E_INVALID; }
+        }
+        m->point_cell[k] = orc_locate(m, &d->point_pos[3 * k], up);
+        if (m->point_cell[k] < 0) { orc_model_destroy(m); return ORC_E_INVALID; }
     }
     *out = m;
     return ORC_OK;
@@ -552,6 +624,8 @@ static double orc_launch(const orc_model *m, const orc_pass_opts *o, const doubl
 {
     const orc_grid_desc *d = &m->d;
     double nray = 12.0 * (double)nside_ray * (double)nside_ray;
+    if (s >= d->n_leaves)   /* a point source: its luminosity spread evenly over the rays */
+        return o->mode != ORC_SCATTER ? d->point_lum[(int64_t)l * d->n_point + (s - d->n_leaves)] / nray : 0.0;
     if (o->mode != ORC_SCATTER)
         return 4.0 * M_PI * d->emis[(int64_t)l * d->n_leaves + s] * m->side[s] * m->side[s] * m->side[s] / nray;
     int64_t ns = m->nside_sca[l];
@@ -577,6 +651,22 @@ static void orc_ray_dir(const orc_pass_opts *o, int64_t nside, int64_t pix, doub
     orc_rotate(o->frame, v, n);
 }
 
+/* Where the rays of source s start: the centre of emitting cell s, or the
+ * position of point source s - n. */
+static const double *orc_source_origin(const orc_model *m, int64_t s)
+{
+    return s < m->d.n_leaves ? &m->centre[3 * s] : &m->d.point_pos[3 * (s - m->d.n_leaves)];
+}
+
+/* The source's own cell: the emitting cell itself, or the leaf holding the
+ * point source.  There the crossed cell fills the whole sky of the source
+ * (Omega_INT infinite): no split or block test, and every wavelength counts
+ * as significant. */
+static int64_t orc_source_cell(const orc_model *m, int64_t s)
+{
+    return s < m->d.n_leaves ? s : m->point_cell[s - m->d.n_leaves];
+}
+
 /* Follow one ray until it escapes, is blocked or is split. */
 static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double *U_LL,
                        int64_t s, orc_ray *ray, orc_thread *th, int64_t *stack_n)
@@ -588,7 +678,8 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
     double omega_hp = 4.0 * M_PI / (12.0 * (double)nside * (double)nside);
     double n[3];
     orc_ray_dir(o, nside, ray->pix, n);
-    const double *xs = &m->centre[3 * s];
+    const double *xs = orc_source_origin(m, s);
+    const int64_t own = orc_source_cell(m, s);
     if (o->mode != ORC_STEP1) {
         for (int l = 0; l < nl; ++l) {
             int64_t woff = m->s_offset[l] / d->n_leaves;
@@ -630,7 +721,7 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
                 } else {
                     double lavg = tau[l] > 0.0 ? ext[l] / tau[l] : L[l];
                     if (!(lavg > 0.0)) sig[l] = 0;
-                    else if (dc2 == 0.0) sig[l] = 1;
+                    else if (c == own) sig[l] = 1;
                     else sig[l] = lavg / (omega_hp * dc2 * cl) >= o->f_U * U_LL[(int64_t)l * d->n_leaves + c];
                 }
                 any_sig |= sig[l];
@@ -641,7 +732,7 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
                     th->count[C_CUTS]++;
                     return;
                 }
-                int too_large = dc2 > 0.0 &&
+                int too_large = c != own &&
                     omega_hp > (m->side[c] * m->side[c] / dc2) / o->n_rays_min;
                 if (too_large) {
                     if (any_sig && nside < o->nside_max) {
@@ -706,6 +797,8 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
 static double orc_emitted(const orc_model *m, int mode, const double *S_pending, int64_t s, int l)
 {
     const orc_grid_desc *d = &m->d;
+    if (s >= d->n_leaves)
+        return mode != ORC_SCATTER ? d->point_lum[(int64_t)l * d->n_point + (s - d->n_leaves)] : 0.0;
     if (mode != ORC_SCATTER)
         return 4.0 * M_PI * d->emis[(int64_t)l * d->n_leaves + s] * m->side[s] * m->side[s] * m->side[s];
     int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
@@ -719,7 +812,7 @@ static double orc_emitted(const orc_model *m, int mode, const double *S_pending,
 int64_t orc_count_sources(const orc_model *m, int mode, const double *S_pending)
 {
     int64_t ns = 0;
-    for (int64_t s = 0; s < m->d.n_leaves; ++s) {
+    for (int64_t s = 0; s < m->d.n_leaves + m->d.n_point; ++s) {
         int any = 0;
         for (int l = 0; l < m->d.n_lambda && !any; ++l) any = orc_emitted(m, mode, S_pending, s, l) > 0.0;
         ns += any;
@@ -752,6 +845,9 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     o = &eff;
     int64_t ssize = m->s_offset[nl];
     int64_t wsize = ssize / n;
+    /* point sources emit in step 1 and the direct pass; a source mask covers
+     * the cells, then the point sources */
+    const int64_t n_src_points = o->mode == ORC_SCATTER ? 0 : d->n_point;
     int nthreads = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
     /* private accumulators when they fit comfortably, shared atomics otherwise */
     double per_thread = 8.0 * ((double)nl * n + (o->mode == ORC_STEP1 ? 0.0 : (double)ssize));
@@ -797,7 +893,7 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
         if (ok) {
             for (int64_t k = 0; k < th.cap; ++k) th.stack[k].L = th.lbuf + k * nl;
 #pragma omp for schedule(dynamic, 1)
-            for (int64_t s = 0; s < n; ++s) {
+            for (int64_t s = 0; s < n + n_src_points; ++s) {
                 if (o->source_mask && !o->source_mask[s]) continue;
                 /* emitted luminosity of this source */
                 double emitted_any = 0.0;
@@ -926,9 +1022,9 @@ int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S
             failed = 1;
         } else {
 #pragma omp for schedule(dynamic, 1)
-            for (int64_t s = 0; s < n; ++s) {
+            for (int64_t s = 0; s < n + (scatter ? 0 : d->n_point); ++s) {
                 if (!scatter && o->source_mask && !o->source_mask[s]) continue;
-                const double *xs = &m->centre[3 * s];
+                const double *xs = orc_source_origin(m, s);
                 for (int64_t r = 0; r < nray; ++r) {
                     double nvec[3];
                     orc_ray_dir(o, nside, r, nvec);
@@ -1004,5 +1100,155 @@ int orc_adjoint_pass(const orc_model *m, const orc_pass_opts *o, const double *S
         free(Lm);
     }
     free(pv);
+    return failed ? ORC_E_OOM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Observer maps (Sect. 2: I_obs = I_0 e^{-tau}; Sect. 3.6: internal-observer */
+/* all-sky HEALPix maps).                                                     */
+/*                                                                            */
+/* Every cell is a source of luminosity per unit solid angle towards the      */
+/* observer, j V (stellar emission, isotropic) plus S[p] N_pix / (4 pi) for   */
+/* the j_sca pixel p containing that direction (scattered light), emitted at  */
+/* its centre and attenuated by the optical depth from the centre to the      */
+/* observer (the cell's own half included).  A distant observer along `dir`   */
+/* sees it on an image pixel of the plane normal to dir (surface brightness:  */
+/* the sum over the cells of a pixel over the pixel's area); an internal      */
+/* observer at `pos` sees it in the map pixel containing the direction to the */
+/* cell, as a flux over the distance squared, per the pixel's solid angle.    */
+/* The observer's own cell is left out of an internal map.                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t kind;           /* 0 distant, 1 internal */
+    double dir[3];          /* distant: unit vector from the model towards the observer */
+    double up[3];           /* distant: image up direction */
+    double centre[3];       /* distant: model point at the image centre */
+    double pixel_size;      /* distant: image pixel edge */
+    int32_t nx, ny;         /* distant: image pixels */
+    double pos[3];          /* internal: observer position */
+    int32_t nside_map;      /* internal: map Nside */
+    double frame[9];        /* rotation of the j_sca pixel directions */
+} orc_observer;
+
+static void orc_normalise(double v[3])
+{
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int a = 0; a < 3; ++a) v[a] /= r;
+}
+
+/* map [n_lambda][npix] is overwritten; S_total (S layout) may be NULL. */
+int orc_observe(const orc_model *m, const orc_observer *ob, const double *S_total, double *map)
+{
+    const orc_grid_desc *d = &m->d;
+    const int nl = d->n_lambda;
+    const int64_t n = d->n_leaves;
+    int64_t npix;
+    double e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0}, dir[3] = {0, 0, 0};
+    int64_t obs_cell = -1;
+    if (ob->kind == 0) {
+        if (ob->nx <= 0 || ob->ny <= 0 || !(ob->pixel_size > 0.0)) return ORC_E_INVALID;
+        npix = (int64_t)ob->nx * ob->ny;
+        for (int a = 0; a < 3; ++a) dir[a] = ob->dir[a];
+        orc_normalise(dir);
+        double ud = ob->up[0] * dir[0] + ob->up[1] * dir[1] + ob->up[2] * dir[2];
+        for (int a = 0; a < 3; ++a) e2[a] = ob->up[a] - ud * dir[a];
+        orc_normalise(e2);
+        e1[0] = e2[1] * dir[2] - e2[2] * dir[1];   /* e1 = e2 x dir */
+        e1[1] = e2[2] * dir[0] - e2[0] * dir[2];
+        e1[2] = e2[0] * dir[1] - e2[1] * dir[0];
+    } else if (ob->kind == 1) {
+        if (ob->nside_map <= 0 || !is_pow2(ob->nside_map)) return ORC_E_INVALID;
+        npix = 12 * (int64_t)ob->nside_map * ob->nside_map;
+        double up0[3] = {0.0, 0.0, 1.0};
+        obs_cell = orc_locate(m, ob->pos, up0);
+    } else {
+        return ORC_E_INVALID;
+    }
+    memset(map, 0, sizeof(double) * (size_t)(nl * npix));
+    int64_t maxc = 4 * (m->fine[0] + m->fine[1] + m->fine[2]) + 64;
+    int failed = 0;
+#pragma omp parallel
+    {
+        int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)maxc);
+        double *lens = (double *)malloc(sizeof(double) * (size_t)maxc);
+        double *tins = (double *)malloc(sizeof(double) * (size_t)maxc);
+        double *acc = (double *)calloc((size_t)(nl * npix), sizeof(double));
+        if (!cells || !lens || !tins || !acc) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t c = 0; c < n + d->n_point; ++c) {
+                if (c == obs_cell) continue;
+                /* a cell, or a point source (index n + k) */
+                const double *xc = orc_source_origin(m, c);
+                double nv[3], dist = INFINITY;
+                if (ob->kind == 0) {
+                    for (int a = 0; a < 3; ++a) nv[a] = dir[a];
+                } else {
+                    for (int a = 0; a < 3; ++a) nv[a] = ob->pos[a] - xc[a];
+                    dist = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+                    if (!(dist > 0.0)) continue;
+                    for (int a = 0; a < 3; ++a) nv[a] /= dist;
+                }
+                int64_t pix;
+                double weight;   /* map value per unit luminosity per steradian reaching the observer */
+                if (ob->kind == 0) {
+                    double u = 0.0, w = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        u += (xc[a] - ob->centre[a]) * e1[a];
+                        w += (xc[a] - ob->centre[a]) * e2[a];
+                    }
+                    double fx = floor(u / ob->pixel_size + 0.5 * ob->nx), fy = floor(w / ob->pixel_size + 0.5 * ob->ny);
+                    if (fx < 0.0 || fy < 0.0 || fx >= ob->nx || fy >= ob->ny) continue;
+                    pix = (int64_t)fy * ob->nx + (int64_t)fx;
+                    weight = 1.0 / (ob->pixel_size * ob->pixel_size);
+                } else {
+                    double away[3] = {-nv[0], -nv[1], -nv[2]};   /* from the observer towards the cell */
+                    pix = orc_healpix_pix(ob->nside_map, away);
+                    weight = 1.0 / (dist * dist * (4.0 * M_PI / (double)npix));
+                }
+                /* optical depth from the cell centre to the observer (or out of the block) */
+                int64_t nc = orc_crossings(m, xc, nv, 0.0, maxc, cells, lens, tins);
+                double colr = 0.0;   /* sum of rho l */
+                for (int64_t k = 0; k < nc; ++k) {
+                    double len = lens[k];
+                    if (tins[k] >= dist) break;
+                    if (tins[k] + len > dist) len = dist - tins[k];
+                    colr += d->rho[cells[k]] * len;
+                }
+                if (c >= n) {
+                    /* a point source: its luminosity per steradian, isotropic */
+                    for (int l = 0; l < nl; ++l) {
+                        double dl = d->point_lum[(int64_t)l * d->n_point + (c - n)] / (4.0 * M_PI);
+                        if (dl != 0.0) acc[(int64_t)l * npix + pix] += dl * exp(-d->kappa[l] * colr) * weight;
+                    }
+                    continue;
+                }
+                double vol = m->side[c] * m->side[c] * m->side[c];
+                /* the j_sca pixel holding the direction towards the observer, in the rotated frame */
+                double loc[3];
+                for (int a = 0; a < 3; ++a)
+                    loc[a] = ob->frame[a] * nv[0] + ob->frame[3 + a] * nv[1] + ob->frame[6 + a] * nv[2];
+                for (int l = 0; l < nl; ++l) {
+                    double dl = d->emis[(int64_t)l * n + c] * vol;
+                    if (S_total) {
+                        int64_t ns = m->nside_sca[l];
+                        int64_t np = 12 * ns * ns;
+                        dl += S_total[m->s_offset[l] + c * np + orc_healpix_pix(ns, loc)] * (double)np / (4.0 * M_PI);
+                    }
+                    if (dl == 0.0) continue;
+                    acc[(int64_t)l * npix + pix] += dl * exp(-d->kappa[l] * colr) * weight;
+                }
+            }
+#pragma omp critical
+            for (int64_t i = 0; i < nl * npix; ++i) map[i] += acc[i];
+        }
+        free(cells);
+        free(lens);
+        free(tins);
+        free(acc);
+    }
     return failed ? ORC_E_OOM : ORC_OK;
 }

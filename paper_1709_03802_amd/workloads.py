@@ -67,6 +67,14 @@ class Grid:
     n_fwhm: float = 5.0
     k_max: int = 2
     c_light: float = C_LIGHT
+    # point sources (paper Sect. 3.6): positions [n_point, 3] inside the root
+    # block and luminosities [nl, n_point]
+    point_pos: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3)))
+    point_lum: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 0)))
+
+    @property
+    def n_point(self) -> int:
+        return int(self.point_pos.shape[0])
 
     @property
     def n(self) -> int:
@@ -98,7 +106,8 @@ class Grid:
         return dataclasses.replace(
             self, level=self.level.copy(), ijk=self.ijk.copy(), rho=self.rho.copy(),
             emis=self.emis.copy(), kappa=self.kappa.copy(), albedo=self.albedo.copy(),
-            g=self.g.copy(), nside_sca=self.nside_sca.copy(), lambdas_um=self.lambdas_um.copy())
+            g=self.g.copy(), nside_sca=self.nside_sca.copy(), lambdas_um=self.lambdas_um.copy(),
+            point_pos=self.point_pos.copy(), point_lum=self.point_lum.copy())
 
 
 @dataclasses.dataclass
