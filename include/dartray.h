@@ -133,6 +133,17 @@ typedef struct {
                                     direction table (16 * 4 nside_max^2 bytes) and,
                                     for adaptive rays, the phase-normalisation
                                     table (4 * n_lambda * 4 nside_max^2 bytes) */
+    /* Point sources (Sect. 3.6): n_point isotropic sources at arbitrary
+     * positions strictly inside the root block (host point_pos[3k..3k+2], grid
+     * coordinates) with luminosity point_lum[l * n_point + k] (finite, >= 0).
+     * They emit in step 1 and the direct pass: rays start at the point and
+     * carry L / N_ray; the leaf holding the point (a point on a face belongs
+     * to the upper side) is the source's own cell, where no split or block
+     * test applies.  A source_mask then covers n + n_point entries (cells,
+     * then point sources).  n_point = 0 and null arrays: none. */
+    int32_t n_point;
+    const double *point_pos;     /* [n_point][3] */
+    const float *point_lum;      /* [n_lambda][n_point] */
 } dartray_grid_desc;
 
 /*
@@ -389,6 +400,47 @@ int dartray_batch_capture(dartray_batch *batch, const dartray_trace_opts *opts, 
 
 /* Launch the captured graph on the batch's stream (DARTRAY_E_STATE if none). */
 int dartray_batch_replay(dartray_batch *batch);
+
+/*
+ * Observer maps (Sect. 2: the intensity reaching an observer is I_0 e^{-tau};
+ * Sect. 3.6: maps seen from inside the model as HEALPix all-sky maps).
+ * Every cell is a source of luminosity per unit solid angle towards the
+ * observer: j V (stellar emission) plus S_total[p] N_pix / (4 pi) for the
+ * j_sca pixel p holding that direction (scattered light, when S_total is
+ * given), emitted at the cell centre and attenuated by
+ * exp(-kappa sum rho l) from the centre to the observer (the cell's own half
+ * included; FP64 path sums).
+ *  DISTANT: the observer is far away along the unit vector `dir` (from the
+ *    model towards the observer); the image plane has axes e2 = `up` made
+ *    orthogonal to dir and e1 = e2 x dir, nx x ny pixels of edge pixel_size
+ *    centred on the model point `centre`; a cell falls in the pixel of its
+ *    centre's projection; map[l][iy * nx + ix] is the surface brightness
+ *    (sum over the pixel's cells over the pixel area).
+ *  INTERNAL: the observer sits at `pos`; map[l][p] (HEALPix nested pixel p at
+ *    nside_map, in the grid's frame) is the sum over the cells whose
+ *    direction from the observer lies in p of the flux (luminosity per
+ *    steradian over the distance squared), per the pixel's solid angle.  The
+ *    leaf holding the observer is left out.
+ * frame: the rotation of the run's j_sca pixel directions (as
+ * dartray_trace_opts.frame; all zero = identity).
+ * map: device double [n_lambda][npix], overwritten.  Asynchronous, except an
+ * internal observer's set-up (it reads the leaf boxes back once).
+ */
+#define DARTRAY_OBS_DISTANT 0
+#define DARTRAY_OBS_INTERNAL 1
+typedef struct {
+    int32_t kind;                /* DARTRAY_OBS_* */
+    double dir[3];
+    double up[3];
+    double centre[3];
+    double pixel_size;
+    int32_t nx, ny;
+    double pos[3];
+    int32_t nside_map;
+    double frame[9];
+} dartray_observer;
+
+int dartray_observe(dartray_grid *grid, const dartray_observer *obs, const float *S_total, double *map);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *dartray_last_error(void);

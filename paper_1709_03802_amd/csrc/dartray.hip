@@ -213,25 +213,29 @@ __global__ void k_invz(float *invz, const LambdaTable *lt, const double *sca64, 
 // stable compaction into src_list.
 // ---------------------------------------------------------------------------
 
-// Direct pass: flag the cells (Morton order) that emit at some wavelength
-// and are allowed by the mask; sum the launched luminosity per wavelength;
-// count every emitting cell, mask or not (N_s of Eq. 11).
-__global__ void k_source_flags(int32_t *flags, const int32_t *morton, int64_t n, const LambdaTable *lt,
-                               const float *emis_lum, const uint8_t *mask, double *tally, int32_t *n_all)
+// Direct pass: flag the sources (cells in Morton order, then the point
+// sources n .. n + n_point - 1) that emit at some wavelength and are allowed
+// by the mask; sum the launched luminosity per wavelength; count every
+// emitting source, mask or not (N_s of Eq. 11).
+__global__ void k_source_flags(int32_t *flags, const int32_t *morton, int64_t n, int32_t n_point,
+                               const LambdaTable *lt, const float *emis_lum, const float *ps_lum,
+                               const uint8_t *mask, double *tally, int32_t *n_all)
 {
     __shared__ double sh[16];
     const int nl = lt->n_lambda;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t c = i < n ? morton[i] : -1;
+    const int64_t c = i < n + n_point ? morton[i] : -1;
     bool emits = false;
     const bool allowed = c >= 0 && (mask == nullptr || mask[c] != 0);
     for (int l = 0; l < nl; ++l) {
-        const double e = c >= 0 ? (double)emis_lum[(int64_t)l * n + c] : 0.0;
+        const double e = c < 0 ? 0.0
+                               : c < n ? (double)emis_lum[(int64_t)l * n + c]
+                                       : (double)ps_lum[(int64_t)l * n_point + (c - n)];
         emits |= e > 0.0;
         const double b = block_sum(allowed ? e : 0.0, sh);
         if (threadIdx.x == 0 && b != 0.0) atomic_add_f64(&tally[l * DARTRAY_N_TALLY + DARTRAY_T_EMITTED], b);
     }
-    if (i < n) flags[i] = (emits && allowed) ? 1 : 0;
+    if (i < n + n_point) flags[i] = (emits && allowed) ? 1 : 0;
     const uint64_t em = __ballot(emits);
     if ((threadIdx.x & 63) == 0 && em) atomicAdd(n_all, (int32_t)__popcll(em));
 }
@@ -516,6 +520,10 @@ struct FixedArgs {
     const int32_t *n_src;
     const double4 *dirs;         // FP64 directions of this Nside
     const float *emis_lum;       // direct pass
+    const double4 *ps_pos;       // point sources (index n + k): position, fine units
+    const int32_t *ps_cell;      // the leaf holding each point
+    const float *ps_lum;         // [n_lambda][n_point] luminosity
+    int32_t n_point;
     const float *S_pending;      // scatter pass
     const LambdaTable *lt;
     float *ubar;                 // [nb][n][n_lambda] direction-binned energy density
@@ -543,6 +551,7 @@ struct FixedArgs {
 // N_pix / N_ray), or sums the pixels inside r when rays are coarser.
 __device__ inline float fixed_launch(const FixedArgs &A, const LambdaTable *lt, int l, int32_t s, int r)
 {
+    if (s >= A.n) return A.scatter ? 0.f : A.ps_lum[(int64_t)l * A.n_point + (s - A.n)] * A.inv_nray;
     if (!A.scatter) return A.emis_lum[(int64_t)l * A.n + s] * A.inv_nray;
     const int npix = lt->npix[l];
     const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
@@ -612,11 +621,19 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
         R.n[0] = nd.x;
         R.n[1] = nd.y;
         R.n[2] = nd.z;
-        const int4 b = A.geo.rec[s].box;
-        const double half = 0.5 * (double)b.w;
-        R.o[0] = (double)b.x + half;
-        R.o[1] = (double)b.y + half;
-        R.o[2] = (double)b.z + half;
+        if (s < A.n) {
+            // an emitting cell: rays start at its centre
+            const int4 b = A.geo.rec[s].box;
+            const double half = 0.5 * (double)b.w;
+            R.o[0] = (double)b.x + half;
+            R.o[1] = (double)b.y + half;
+            R.o[2] = (double)b.z + half;
+        } else {
+            const double4 p = A.ps_pos[s - A.n];
+            R.o[0] = p.x;
+            R.o[1] = p.y;
+            R.o[2] = p.z;
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) R.inv[a] = 1.0 / R.n[a];
         float lsum = 0.f;
@@ -632,7 +649,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
             for (int l = 0; l < nl; ++l)
                 if (l < l0 || l >= l0 + nlc) lsum += fixed_launch(A, lt, l, s, r);
         active = lsum > 0.f;
-        c = s;
+        c = s < A.n ? s : A.ps_cell[s - A.n];
         if (active) ++acc.nrays;
     }
     double t = 0.0;
@@ -1022,6 +1039,11 @@ struct AdaptArgs {
     const float *invz;           // [entry][n_lambda]
     const float *emis_lum;
     const double *lum64;         // [n_lambda][n] 4 pi j V in FP64 (direct pass launch)
+    const double4 *ps_pos;       // point sources (index n + k): position, fine units
+    const int32_t *ps_cell;      // the leaf holding each point
+    const float *ps_lum;         // [n_lambda][n_point] luminosity
+    const double *ps_lum64;      // the same in FP64
+    int32_t n_point;
     const float *S_pending;
     const float *ull_t;          // [n][n_lambda] copy of U_LL
     const int32_t *n_all;        // sources of the pass in the whole model (N_s of Eq. 11)
@@ -1137,6 +1159,7 @@ void k_march_adaptive(const AdaptArgs A)
     // underflow.
     bool has_ray = false, has_item = false, pending = false, done = false;
     int32_t s = 0;
+    int32_t own_c = -1;            // the source's own cell (no split or block test there)
     double o[3] = {0.0, 0.0, 0.0};
     int depth = 0;
     int pix = 0;
@@ -1219,17 +1242,31 @@ void k_march_adaptive(const AdaptArgs A)
                 } else {
                     const int r0 = (int)(it / (uint64_t)nsrc);
                     s = A.src_list[it - (uint64_t)r0 * nsrc];
-                    const int4 sb = A.geo.rec[s].box;
-                    const double half = 0.5 * (double)sb.w;
-                    o[0] = (double)sb.x + half;
-                    o[1] = (double)sb.y + half;
-                    o[2] = (double)sb.z + half;
+                    if (s < A.n) {
+                        // an emitting cell: rays start at its centre, it is its own cell
+                        const int4 sb = A.geo.rec[s].box;
+                        const double half = 0.5 * (double)sb.w;
+                        o[0] = (double)sb.x + half;
+                        o[1] = (double)sb.y + half;
+                        o[2] = (double)sb.z + half;
+                        own_c = s;
+                    } else {
+                        // a point source: rays start at the point, in the leaf holding it
+                        const double4 pp = A.ps_pos[s - A.n];
+                        o[0] = pp.x;
+                        o[1] = pp.y;
+                        o[2] = pp.z;
+                        own_c = A.ps_cell[s - A.n];
+                    }
+                    const int32_t kp = s - (int32_t)A.n;   // point index when s >= n
                     double lsum = 0.0;
                     if constexpr (STEP1) {
                         const float inv_nray0 = 1.f / (float)(12 * A.nside0 * A.nside0);
 #pragma unroll
                         for (int l = 0; l < NL; ++l) {
-                            L[l] = l < nl ? A.emis_lum[(int64_t)l * A.n + s] * inv_nray0 : 0.f;
+                            L[l] = l >= nl ? 0.f
+                                   : s < A.n ? A.emis_lum[(int64_t)l * A.n + s] * inv_nray0
+                                             : A.ps_lum[(int64_t)l * A.n_point + kp] * inv_nray0;
                             lsum += (double)L[l];
                         }
                     } else {
@@ -1242,7 +1279,8 @@ void k_march_adaptive(const AdaptArgs A)
                             double v = 0.0;
                             if (l < nl) {
                                 if (MODE != 2) {
-                                    v = A.lum64[(int64_t)l * A.n + s] / nray0;
+                                    v = (s < A.n ? A.lum64[(int64_t)l * A.n + s]
+                                                 : A.ps_lum64[(int64_t)l * A.n_point + kp]) / nray0;
                                 } else {
                                     const int npix = lt->npix[l];
                                     const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
@@ -1292,7 +1330,7 @@ void k_march_adaptive(const AdaptArgs A)
             omega_hp = kPi / (3.0 * (double)N * (double)N);   // 4 pi / (12 N^2)
             steps = 0;
             if (t == 0.0) {
-                c = s;
+                c = own_c;
             } else {
                 // a child starts at its parent's entry distance: mostly inside
                 // the cell where the parent split, which then needs no descent
@@ -1383,7 +1421,7 @@ void k_march_adaptive(const AdaptArgs A)
                             const double ext = Lin * -expm1(-tau);
                             const double lavg = tau > 0.0 ? ext / tau : Lin;
                             const bool sg = lavg > 0.0 &&
-                                            (d2 == 0.0 || lavg / (omega_hp * d2 * A.c_light) >= f_U * (double)ull[l]);
+                                            (c == own_c || lavg / (omega_hp * d2 * A.c_light) >= f_U * (double)ull[l]);
                             sigm |= (uint32_t)sg << l;
                             ext32[l] = (float)ext;
                             du32[l] = (float)((alpha > 0.0 ? ext / alpha : Lin * lenp) * (double)rc.ivc);
@@ -1392,7 +1430,7 @@ void k_march_adaptive(const AdaptArgs A)
                 }
                 if (STEP1 && t_in >= A.r_pre_fine64) {
                     action = 2;
-                } else if (d2 > 0.0 && omega_hp * (double)A.n_rays * d2 > side * side) {   // Eq. 2
+                } else if (c != own_c && omega_hp * (double)A.n_rays * d2 > side * side) {   // Eq. 2
                     if (sigm && depth < A.max_depth) action = 1;
                     else if (!sigm) action = 2;
                 }
@@ -1846,6 +1884,10 @@ struct AdjArgs {
     const int32_t *n_src;
     const double4 *dirs;         // FP64 directions of this Nside
     const float *emis_lum;       // direct pass
+    const double4 *ps_pos;       // point sources of the direct pass (index n + k)
+    const int32_t *ps_cell;
+    const float *ps_lum;
+    int32_t n_point;
     const float *S_pending;      // scattering pass: its emission
     const LambdaTable *lt;
     const float *ubar_t;         // dJ/dU, [n][n_lambda]
@@ -1921,11 +1963,20 @@ void k_march_adjoint(const AdjArgs A)
         R.n[0] = nd.x;
         R.n[1] = nd.y;
         R.n[2] = nd.z;
-        const int4 sb = A.geo.rec[s].box;
-        const double half = 0.5 * (double)sb.w;
-        R.o[0] = (double)sb.x + half;
-        R.o[1] = (double)sb.y + half;
-        R.o[2] = (double)sb.z + half;
+        int32_t c0 = s;              // the cell the ray starts in
+        if (s < A.n) {
+            const int4 sb = A.geo.rec[s].box;
+            const double half = 0.5 * (double)sb.w;
+            R.o[0] = (double)sb.x + half;
+            R.o[1] = (double)sb.y + half;
+            R.o[2] = (double)sb.z + half;
+        } else {                     // a point source of the direct pass
+            const double4 pp = A.ps_pos[s - A.n];
+            R.o[0] = pp.x;
+            R.o[1] = pp.y;
+            R.o[2] = pp.z;
+            c0 = A.ps_cell[s - A.n];
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) R.inv[a] = 1.0 / R.n[a];
         float L0[NL];
@@ -1935,7 +1986,8 @@ void k_march_adjoint(const AdjArgs A)
             float v = 0.f;
             if (l < nl) {
                 if (!A.scatter) {
-                    v = A.emis_lum[(int64_t)l * A.n + s] * A.inv_nray;
+                    v = (s < A.n ? A.emis_lum[(int64_t)l * A.n + s] : A.ps_lum[(int64_t)l * A.n_point + (s - A.n)]) *
+                        A.inv_nray;
                 } else {
                     const int npix = lt->npix[l];
                     const float *row = A.S_pending + lt->s_off[l] + (int64_t)s * npix;
@@ -1965,7 +2017,7 @@ void k_march_adjoint(const AdjArgs A)
         for (int walk = 0; walk < 2; ++walk) {
 #pragma unroll
             for (int l = 0; l < NL; ++l) ell[l] = 1.f;
-            int32_t c = s;
+            int32_t c = c0;
             double t = 0.0;
             int64_t steps = 0;
             while (true) {
@@ -2195,7 +2247,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
+    void *ptrs[] = {g.ps_pos, g.ps_xyz, g.ps_cell, g.ps_lum, g.ps_lum64, g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
                     g.own.flags, g.cell_flag, g.own.src_list, g.own.scan_blocks, g.own.n_src, g.own.dsum, g.s1_sum, g.own.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -2225,6 +2277,21 @@ static int validate_desc(const dartray_grid_desc *d)
     if (d->nside_max < 0 || d->nside_max > kMaxNsideCap || (d->nside_max & (d->nside_max - 1)))
         return fail(DARTRAY_E_INVALID, "nside_max must be 0 or a power of two <= 1024");
     if (d->k_max < 0) return fail(DARTRAY_E_INVALID, "k_max must be >= 0");
+    if (d->n_point < 0 || (d->n_point > 0 && (!d->point_pos || !d->point_lum)))
+        return fail(DARTRAY_E_INVALID, "point sources: n_point >= 0 with both arrays given");
+    if (d->n_leaves + (int64_t)d->n_point > (int64_t)INT32_MAX) return fail(DARTRAY_E_INVALID, "too many sources");
+    for (int32_t k = 0; k < d->n_point; ++k) {
+        for (int a = 0; a < 3; ++a) {
+            const double x = d->point_pos[3 * k + a];
+            const double hi = d->lo[a] + d->nroot[a] * d->root_size;
+            if (!std::isfinite(x) || !(x >= d->lo[a] && x < hi))
+                return fail(DARTRAY_E_INVALID, "point sources must lie inside the root block");
+        }
+        for (int l = 0; l < d->n_lambda; ++l) {
+            const float v = d->point_lum[(int64_t)l * d->n_point + k];
+            if (!(v >= 0.f) || !std::isfinite(v)) return fail(DARTRAY_E_INVALID, "point luminosities must be finite and >= 0");
+        }
+    }
     for (int l = 0; l < d->n_lambda; ++l)
         if (d->nside_sca[l] == 0 && d->k_max > 3)
             return fail(DARTRAY_E_UNSUPPORTED, "the Eq. 5 rule is applied with k_max <= 3 (Nside_sca <= 8)");
@@ -2374,6 +2441,44 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     std::vector<int32_t> by_level(morton);
     std::stable_sort(by_level.begin(), by_level.end(),
                      [&](int32_t a, int32_t b) { return d->leaf_level[a] > d->leaf_level[b]; });
+    // point sources follow the cells in both source orders (index n + k)
+    const int32_t np = d->n_point;
+    for (int32_t k = 0; k < np; ++k) {
+        morton.push_back((int32_t)(n + k));
+        by_level.push_back((int32_t)(n + k));
+    }
+    // the leaf holding each point source: fine-cell index (a point on a face
+    // belongs to the upper side), then down the locator
+    std::vector<double4> ps_pos((size_t)std::max(np, 1)), ps_xyz((size_t)std::max(np, 1));
+    std::vector<int32_t> ps_cell((size_t)std::max(np, 1));
+    std::vector<float> ps_lum((size_t)std::max<int64_t>(1, (int64_t)np * nl));
+    std::vector<double> ps_lum64((size_t)std::max<int64_t>(1, (int64_t)np * nl));
+    {
+        const double hf = d->root_size / (double)((int64_t)1 << lmax);
+        for (int32_t k = 0; k < np; ++k) {
+            double f[3];
+            int64_t q[3];
+            for (int a = 0; a < 3; ++a) {
+                f[a] = (d->point_pos[3 * k + a] - d->lo[a]) / hf;
+                q[a] = std::min<int64_t>(fine[a] - 1, std::max<int64_t>(0, (int64_t)std::floor(f[a])));
+            }
+            ps_pos[(size_t)k] = make_double4(f[0], f[1], f[2], 0.0);
+            ps_xyz[(size_t)k] = make_double4(d->point_pos[3 * k], d->point_pos[3 * k + 1], d->point_pos[3 * k + 2], 0.0);
+            int32_t v = root_tab[(size_t)(((q[2] >> lmax) * d->nroot[1] + (q[1] >> lmax)) * d->nroot[0] + (q[0] >> lmax))];
+            int bit = lmax - 1;
+            while (v >= 0) {
+                const int oct = (int)(((q[0] >> bit) & 1) | (((q[1] >> bit) & 1) << 1) | (((q[2] >> bit) & 1) << 2));
+                v = nodes[(size_t)v * 8 + oct];
+                --bit;
+            }
+            ps_cell[(size_t)k] = -v - 1;
+            for (int l = 0; l < nl; ++l) {
+                ps_lum[(size_t)l * np + k] = d->point_lum[(int64_t)l * np + k];
+                ps_lum64[(size_t)l * np + k] = (double)d->point_lum[(int64_t)l * np + k];
+            }
+        }
+    }
+    const int64_t n_src_max = n + np;
 
     LambdaTable lt{};
     lt.n_lambda = nl;
@@ -2408,6 +2513,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     Grid &g = h->g;
     g.n = n;
     g.n_lambda = nl;
+    g.n_point = np;
     for (int a = 0; a < 3; ++a) {
         g.nroot[a] = d->nroot[a];
         g.fine[a] = (int32_t)fine[a];
@@ -2441,9 +2547,12 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.lum64, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
         dalloc(g, &g.own.n_all, 1), dalloc(g, &g.own.err_word, 1),
-        dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n), dalloc(g, &g.by_level, (size_t)n), dalloc(g, &g.d_lt, 1),
-        dalloc(g, &g.own.U_k, (size_t)(nl * n)), dalloc(g, &g.own.flags, (size_t)n), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.own.src_list, (size_t)n),
-        dalloc(g, &g.own.scan_blocks, (size_t)((n + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.own.n_src, 1),
+        dalloc(g, &g.ps_pos, (size_t)std::max(np, 1)), dalloc(g, &g.ps_xyz, (size_t)std::max(np, 1)), dalloc(g, &g.ps_cell, (size_t)std::max(np, 1)),
+        dalloc(g, &g.ps_lum, (size_t)std::max<int64_t>(1, (int64_t)np * nl)),
+        dalloc(g, &g.ps_lum64, (size_t)std::max<int64_t>(1, (int64_t)np * nl)),
+        dalloc(g, &g.nodes, nodes.size()), dalloc(g, &g.morton, (size_t)n_src_max), dalloc(g, &g.by_level, (size_t)n_src_max), dalloc(g, &g.d_lt, 1),
+        dalloc(g, &g.own.U_k, (size_t)(nl * n)), dalloc(g, &g.own.flags, (size_t)n_src_max), dalloc(g, &g.cell_flag, (size_t)n), dalloc(g, &g.own.src_list, (size_t)n_src_max),
+        dalloc(g, &g.own.scan_blocks, (size_t)((n_src_max + kScanBlock - 1) / kScanBlock)), dalloc(g, &g.own.n_src, 1),
         dalloc(g, &g.own.dsum, 4 * kMaxLambda), dalloc(g, &g.s1_sum, kMaxLambda),
         dalloc(g, &g.own.ubar, nb_cap * per_dir), dalloc(g, &g.dir_all, (size_t)ndir), dalloc(g, &g.dir64, (size_t)ndir),
         dalloc(g, &g.invz, (size_t)ndir * nl), dalloc(g, &g.sca64, 3 * (size_t)kScaDirs),
@@ -2508,8 +2617,15 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     cp(g.lum64, lum64.data(), sizeof(double) * nl * n);
     cp(g.root_tab, root_tab.data(), sizeof(int32_t) * nroot);
     cp(g.nodes, nodes.data(), sizeof(int32_t) * nodes.size());
-    cp(g.morton, morton.data(), sizeof(int32_t) * n);
-    cp(g.by_level, by_level.data(), sizeof(int32_t) * n);
+    cp(g.morton, morton.data(), sizeof(int32_t) * n_src_max);
+    cp(g.by_level, by_level.data(), sizeof(int32_t) * n_src_max);
+    if (np > 0) {
+        cp(g.ps_pos, ps_pos.data(), sizeof(double4) * np);
+        cp(g.ps_xyz, ps_xyz.data(), sizeof(double4) * np);
+        cp(g.ps_cell, ps_cell.data(), sizeof(int32_t) * np);
+        cp(g.ps_lum, ps_lum.data(), sizeof(float) * np * nl);
+        cp(g.ps_lum64, ps_lum64.data(), sizeof(double) * np * nl);
+    }
     cp(g.d_lt, &lt, sizeof(LambdaTable));
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors go out of scope
     if (e != hipSuccess) {
@@ -2783,7 +2899,8 @@ static unsigned s_blocks(const Grid &g)
 
 static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fields *f, bool scatter)
 {
-    const int64_t n = g.n;
+    // point sources emit in step 1 and the direct pass only
+    const int64_t n = g.n + (scatter ? 0 : g.n_point);
     const unsigned nblk = (unsigned)((n + kScanBlock - 1) / kScanBlock);
     // the order in which sources become work items
     const int32_t *order = o->adaptive ? g.by_level : g.morton;
@@ -2792,7 +2909,7 @@ static int select_sources(Grid &g, const dartray_trace_opts *o, const dartray_fi
     if ((rc = fill<uint32_t>(g, g.w.err_word, 1, 0u))) return rc;   // the pass's own error word
     if (!scatter) {
         hipLaunchKernelGGL(k_source_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, g.stream, g.w.flags, order,
-                           n, g.d_lt, g.emis_lum, o->source_mask, f->tally, g.w.n_all);
+                           g.n, g.n_point, g.d_lt, g.emis_lum, g.ps_lum, o->source_mask, f->tally, g.w.n_all);
         DR_LAUNCH_CHECK("k_source_flags");
     } else {
         if ((rc = fill<uint8_t>(g, g.cell_flag, (size_t)n, (uint8_t)0))) return rc;
@@ -2868,6 +2985,10 @@ static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields
     A.n_src = g.w.n_src;
     A.dirs = g.dir64 + entry_of(o->nside, 0);
     A.emis_lum = g.emis_lum;
+    A.ps_pos = g.ps_pos;
+    A.ps_cell = g.ps_cell;
+    A.ps_lum = g.ps_lum;
+    A.n_point = g.n_point;
     A.S_pending = f->S_pending;
     A.lt = g.d_lt;
     A.ubar = g.w.ubar;
@@ -3055,6 +3176,11 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     A.invz = g.invz;
     A.emis_lum = g.emis_lum;
     A.lum64 = g.lum64;
+    A.ps_pos = g.ps_pos;
+    A.ps_cell = g.ps_cell;
+    A.ps_lum = g.ps_lum;
+    A.ps_lum64 = g.ps_lum64;
+    A.n_point = g.n_point;
     A.S_pending = f->S_pending;
     A.ull_t = g.ull_t;
     A.n_all = g.w.n_all;
@@ -3267,6 +3393,10 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     A.n_src = g.w.n_src;
     A.dirs = g.dir64 + entry_of(opts->nside, 0);
     A.emis_lum = g.emis_lum;
+    A.ps_pos = g.ps_pos;
+    A.ps_cell = g.ps_cell;
+    A.ps_lum = g.ps_lum;
+    A.n_point = g.n_point;
     A.lt = g.d_lt;
     A.ubar_t = g.ull_t;
     A.rho_bar = g.rho_bar;
@@ -3659,8 +3789,9 @@ static int scratch_base(char **out)
 static int scratch_work(const Grid &g, const dartray_trace_opts *o, const dartray_fields *f, char *base, PassWork &w)
 {
     const size_t n = (size_t)g.n, nl = (size_t)g.n_lambda;
+    const size_t ns = n + (size_t)g.n_point;       // cells and point sources
     const size_t nray = 12 * (size_t)o->nside * (size_t)o->nside;
-    const size_t nblk = (n + kScanBlock - 1) / kScanBlock;
+    const size_t nblk = (ns + kScanBlock - 1) / kScanBlock;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         off = (off + 255) & ~(size_t)255;
@@ -3668,8 +3799,8 @@ static int scratch_work(const Grid &g, const dartray_trace_opts *o, const dartra
         off += bytes;
         return at;
     };
-    const size_t o_uk = take(n * nl * sizeof(double)), o_flags = take(n * sizeof(int32_t)),
-                 o_src = take(n * sizeof(int32_t)), o_scan = take(nblk * sizeof(int32_t)), o_nsrc = take(sizeof(int32_t)),
+    const size_t o_uk = take(n * nl * sizeof(double)), o_flags = take(ns * sizeof(int32_t)),
+                 o_src = take(ns * sizeof(int32_t)), o_scan = take(nblk * sizeof(int32_t)), o_nsrc = take(sizeof(int32_t)),
                  o_nall = take(sizeof(int32_t)), o_err = take(sizeof(uint32_t)),
                  o_dsum = take(4 * (size_t)kMaxLambda * sizeof(double)),
                  o_esc = f->escape ? take(nl * nray * sizeof(double)) : 0;
@@ -3727,6 +3858,270 @@ int dartray_trace_direct_noalloc(dartray_grid *grid, const dartray_trace_opts *o
     }
     if (prev != g.device) (void)hipSetDevice(prev);
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Observer maps (Sect. 2: I_obs = I_0 e^{-tau} from every cell; Sect. 3.6:
+// internal-observer HEALPix maps).  A gather march: one lane per cell walks
+// from the cell centre towards the observer (or out of the block for a
+// distant one) summing rho l in FP64, then adds the cell's luminosity per
+// steradian towards the observer -- j V, plus S[p] N_pix / (4 pi) for the
+// j_sca pixel p holding that direction -- times e^{-kappa sum rho l} to its
+// map pixel (FP64 atomics).  Cells are taken in Morton order, so the lanes
+// of a wave start from neighbouring cells.
+// ---------------------------------------------------------------------------
+
+namespace dr {
+
+struct ObsArgs {
+    Geo geo;
+    const int32_t *morton;
+    const LambdaTable *lt;
+    const double *lum64;          // [n_lambda][n] 4 pi j V
+    const double4 *ps_pos;        // point sources (item n + k), fine units
+    const double4 *ps_xyz;        // the same, model units as given
+    const int32_t *ps_cell;
+    const double *ps_lum64;       // [n_lambda][n_point]
+    int32_t n_point;
+    const float *S;               // S_total, or null
+    double *map;                  // [n_lambda][npix]
+    int64_t n;
+    int64_t npix;
+    int32_t kind;                 // DARTRAY_OBS_*
+    int32_t nx, ny;
+    int32_t nside_map;
+    int32_t obs_cell;             // internal: the leaf holding the observer (left out)
+    double dir[3];                // distant: unit vector towards the observer
+    double e1[3], e2[3];          // distant: image axes
+    double centre[3];             // distant: image centre, model units
+    double pos[3];                // internal: observer, model units
+    double pixel;                 // distant: pixel edge, model units
+    double pix_weight;            // distant: 1 / pixel area; internal: 1 / map-pixel solid angle
+    double lo[3];                 // model-space corner of the grid
+    double h_fine;
+    double R[9];                  // frame of the j_sca pixel directions
+    int64_t hard_cap;
+};
+
+// Where a source lands on the map, from its model-space position, in plain
+// FP64 steps without fused multiply-adds: a source whose projection falls on a
+// pixel edge (a cell row seen face-on, say) goes to the pixel that ordinary
+// rounding of these steps selects, whatever the compiler would contract.
+__device__ __noinline__ int64_t obs_locate(const ObsArgs &A, const double xc[3], double nv[3], double &dist)
+{
+#pragma clang fp contract(off)
+    if (A.kind == DARTRAY_OBS_DISTANT) {
+        double u = 0.0, w = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            nv[a] = A.dir[a];
+            u += (xc[a] - A.centre[a]) * A.e1[a];
+            w += (xc[a] - A.centre[a]) * A.e2[a];
+        }
+        const double fx = floor(u / A.pixel + 0.5 * A.nx), fy = floor(w / A.pixel + 0.5 * A.ny);
+        if (!(fx >= 0.0 && fy >= 0.0 && fx < (double)A.nx && fy < (double)A.ny)) return -1;
+        dist = __builtin_huge_val();
+        return (int64_t)fy * A.nx + (int64_t)fx;
+    }
+    for (int a = 0; a < 3; ++a) nv[a] = A.pos[a] - xc[a];
+    dist = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    if (!(dist > 0.0)) return -1;
+    for (int a = 0; a < 3; ++a) nv[a] /= dist;
+    const double away[3] = {-nv[0], -nv[1], -nv[2]};   // from the observer towards the source
+    return dr_vec_pix(A.nside_map, away);
+}
+
+// model-space centre of a leaf: corner + (fine offset of the centre) x h
+__device__ __noinline__ void obs_centre(const ObsArgs &A, const int4 b, double xc[3])
+{
+#pragma clang fp contract(off)
+    const double half = 0.5 * (double)b.w;
+    xc[0] = A.lo[0] + ((double)b.x + half) * A.h_fine;
+    xc[1] = A.lo[1] + ((double)b.y + half) * A.h_fine;
+    xc[2] = A.lo[2] + ((double)b.z + half) * A.h_fine;
+}
+
+__global__ __launch_bounds__(256) void k_observe(const ObsArgs A)
+{
+    const LambdaTable *lt = A.lt;
+    const int nl = lt->n_lambda;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A.n + A.n_point;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        // a cell (Morton order), or point source i - n
+        const bool point = i >= A.n;
+        const int32_t c = point ? A.ps_cell[i - A.n] : A.morton[i];
+        if (!point && c == A.obs_cell) continue;
+        RayT<double> R;
+        double xc[3];
+        if (point) {
+            const double4 pp = A.ps_pos[i - A.n];
+            R.o[0] = pp.x;
+            R.o[1] = pp.y;
+            R.o[2] = pp.z;
+            const double4 px = A.ps_xyz[i - A.n];
+            xc[0] = px.x;
+            xc[1] = px.y;
+            xc[2] = px.z;
+        } else {
+            const int4 b = A.geo.rec[c].box;
+            const double half = 0.5 * (double)b.w;
+            R.o[0] = (double)b.x + half;
+            R.o[1] = (double)b.y + half;
+            R.o[2] = (double)b.z + half;
+            obs_centre(A, b, xc);
+        }
+        double dist;
+        const int64_t pix = obs_locate(A, xc, R.n, dist);
+        if (pix < 0) continue;
+        // the march runs in fine units; it ends at the observer (internal) or
+        // leaves the block (distant)
+        const double stop = dist / A.h_fine;
+        const double weight = A.kind == DARTRAY_OBS_DISTANT ? A.pix_weight : A.pix_weight / (dist * dist);
+        for (int a = 0; a < 3; ++a) R.inv[a] = 1.0 / R.n[a];
+        // optical depth towards the observer: sum of rho l over the crossings
+        double colr = 0.0, t = 0.0;
+        int32_t cc = c;
+        for (int64_t steps = 0; cc >= 0 && t < stop && steps < A.hard_cap; ++steps) {
+            const LeafRec &rc = A.geo.rec[cc];
+            const int4 bb = rc.box;
+            int32_t nbc[6];
+            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+            int axis;
+            const double te = exit_t<double>(R, bb, axis);
+            const double len = te - t;
+            if (!is_graze(len, te)) {
+                const double seg = (te < stop ? te : stop) - t;
+                colr += (double)rc.rho * (seg * A.h_fine);
+                t = te;
+            }
+            cc = next_leaf<double>(A.geo, R, bb, nbc, axis, te);
+        }
+        // the j_sca pixel holding the direction towards the observer, in the rotated frame
+        const double loc[3] = {A.R[0] * R.n[0] + A.R[3] * R.n[1] + A.R[6] * R.n[2],
+                               A.R[1] * R.n[0] + A.R[4] * R.n[1] + A.R[7] * R.n[2],
+                               A.R[2] * R.n[0] + A.R[5] * R.n[1] + A.R[8] * R.n[2]};
+        for (int l = 0; l < nl; ++l) {
+            if (point) {
+                const double dl = A.ps_lum64[(int64_t)l * A.n_point + (i - A.n)] / (4.0 * kPi);
+                if (dl != 0.0)
+                    atomic_add_f64(A.map + (int64_t)l * A.npix + pix, dl * exp(-(double)lt->kappa[l] * colr) * weight);
+                continue;
+            }
+            double dl = A.lum64[(int64_t)l * A.n + c] / (4.0 * kPi);
+            if (A.S) {
+                const int np = lt->npix[l];
+                dl += (double)A.S[lt->s_off[l] + (int64_t)c * np + dr_vec_pix(lt->nside_sca[l], loc)] * (double)np /
+                      (4.0 * kPi);
+            }
+            if (dl == 0.0) continue;
+            atomic_add_f64(A.map + (int64_t)l * A.npix + pix, dl * exp(-(double)lt->kappa[l] * colr) * weight);
+        }
+    }
+}
+
+}  // namespace dr
+
+extern "C" {
+
+int dartray_observe(dartray_grid *grid, const dartray_observer *obs, const float *S_total, double *map)
+{
+    if (!grid || !obs || !map) return fail(DARTRAY_E_INVALID, "null argument");
+    Grid &g = grid->g;
+    ObsArgs A{};
+    A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
+                g.max_level};
+    A.morton = g.morton;
+    A.lt = g.d_lt;
+    A.lum64 = g.lum64;
+    A.ps_pos = g.ps_pos;
+    A.ps_xyz = g.ps_xyz;
+    A.ps_cell = g.ps_cell;
+    A.ps_lum64 = g.ps_lum64;
+    A.n_point = g.n_point;
+    A.S = S_total;
+    A.map = map;
+    A.n = g.n;
+    A.kind = obs->kind;
+    A.h_fine = g.h_fine;
+    for (int a = 0; a < 3; ++a) A.lo[a] = g.lo[a];
+    A.obs_cell = -1;
+    A.hard_cap = 4 * ((int64_t)g.fine[0] + g.fine[1] + g.fine[2]) + 64;
+    bool zero = true;
+    for (int i = 0; i < 9; ++i) zero &= obs->frame[i] == 0.0;
+    for (int i = 0; i < 9; ++i) A.R[i] = zero ? ((i % 4 == 0) ? 1.0 : 0.0) : obs->frame[i];
+    if (obs->kind == DARTRAY_OBS_DISTANT) {
+        if (obs->nx <= 0 || obs->ny <= 0 || !(obs->pixel_size > 0.0) || !std::isfinite(obs->pixel_size))
+            return fail(DARTRAY_E_INVALID, "distant observer: image size and pixel size must be positive");
+        double d[3], up[3];
+        for (int a = 0; a < 3; ++a) {
+            d[a] = obs->dir[a];
+            up[a] = obs->up[a];
+        }
+        const double dn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (!(dn > 0.0) || !std::isfinite(dn)) return fail(DARTRAY_E_INVALID, "distant observer: zero direction");
+        for (int a = 0; a < 3; ++a) d[a] /= dn;
+        const double ud = up[0] * d[0] + up[1] * d[1] + up[2] * d[2];
+        double e2[3], n2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            e2[a] = up[a] - ud * d[a];
+            n2 += e2[a] * e2[a];
+        }
+        if (!(n2 > 1e-24)) return fail(DARTRAY_E_INVALID, "distant observer: up parallel to the direction");
+        for (int a = 0; a < 3; ++a) e2[a] /= std::sqrt(n2);
+        const double e1[3] = {e2[1] * d[2] - e2[2] * d[1], e2[2] * d[0] - e2[0] * d[2], e2[0] * d[1] - e2[1] * d[0]};
+        for (int a = 0; a < 3; ++a) {
+            A.dir[a] = d[a];
+            A.e1[a] = e1[a];
+            A.e2[a] = e2[a];
+            A.centre[a] = obs->centre[a];
+        }
+        A.nx = obs->nx;
+        A.ny = obs->ny;
+        A.npix = (int64_t)obs->nx * obs->ny;
+        A.pixel = obs->pixel_size;
+        A.pix_weight = 1.0 / (obs->pixel_size * obs->pixel_size);
+    } else if (obs->kind == DARTRAY_OBS_INTERNAL) {
+        const int ns = obs->nside_map;
+        if (ns <= 0 || (ns & (ns - 1)) || ns > 8192) return fail(DARTRAY_E_INVALID, "internal observer: nside_map must be a power of two <= 8192");
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(obs->pos[a])) return fail(DARTRAY_E_INVALID, "internal observer: position not finite");
+            A.pos[a] = obs->pos[a];
+        }
+        A.nside_map = ns;
+        A.npix = 12 * (int64_t)ns * ns;
+        A.pix_weight = (double)A.npix / (4.0 * kPi);
+        // the leaf holding the observer (points on a face belong to the upper side)
+        int f[3];
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+            const double u = std::floor((obs->pos[a] - g.lo[a]) / g.h_fine);
+            inside &= u >= 0.0 && u < (double)g.fine[a];
+            f[a] = inside ? (int)u : 0;
+        }
+        if (inside) {
+            std::vector<int4> boxes((size_t)g.n);
+            // the observer's leaf: one host search over the leaf boxes (set-up, not the march)
+            DR_HIP(hipMemcpyAsync(boxes.data(), g.leaf_box, sizeof(int4) * g.n, hipMemcpyDeviceToHost, g.stream));
+            DR_HIP(hipStreamSynchronize(g.stream));
+            for (int64_t c = 0; c < g.n; ++c) {
+                const int4 bx = boxes[(size_t)c];
+                if (f[0] >= bx.x && f[0] < bx.x + bx.w && f[1] >= bx.y && f[1] < bx.y + bx.w && f[2] >= bx.z &&
+                    f[2] < bx.z + bx.w) {
+                    A.obs_cell = (int32_t)c;
+                    break;
+                }
+            }
+        }
+    } else {
+        return fail(DARTRAY_E_INVALID, "unknown observer kind");
+    }
+    int rc = fill<double>(g, map, (size_t)(g.n_lambda * A.npix), 0.0);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_observe, dim3((unsigned)std::min<int64_t>((g.n + g.n_point + 255) / 256, 8192)), dim3(256), 0,
+                       g.stream, A);
+    DR_LAUNCH_CHECK("k_observe");
+    return DARTRAY_OK;
 }
 
 }  // extern "C"

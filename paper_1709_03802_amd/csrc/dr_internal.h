@@ -89,12 +89,18 @@ struct Grid {
     LeafRec *rec = nullptr;               // [n] leaf records
     float *rho = nullptr;
     float *inv_vc = nullptr;              // 1 / (V c)
+    int32_t n_point = 0;                  // point sources: source index n + k
+    double4 *ps_pos = nullptr;            // [n_point] positions, fine units
+    double4 *ps_xyz = nullptr;            // [n_point] positions as given, model units
+    int32_t *ps_cell = nullptr;           // [n_point] leaf holding each point
+    float *ps_lum = nullptr;              // [nl][n_point] luminosity
+    double *ps_lum64 = nullptr;           // [nl][n_point] luminosity, FP64
     float *emis_lum = nullptr;            // [nl][n] 4 pi j V
     double *lum64 = nullptr;              // [nl][n] 4 pi j V in FP64 (launch luminosity of the FP64-decision passes)
     int32_t *root_tab = nullptr;          // root cell -> node code
     int32_t *nodes = nullptr;             // [8 * n_internal] child codes
-    int32_t *morton = nullptr;            // leaves in Morton order
-    int32_t *by_level = nullptr;          // leaves finest level first, Morton order within a level
+    int32_t *morton = nullptr;            // leaves in Morton order, then the point sources n .. n + n_point - 1
+    int32_t *by_level = nullptr;          // leaves finest level first, Morton order within a level, then the point sources
     LambdaTable *d_lt = nullptr;
 
     // work arrays of a pass: `own` is what dartray_grid_create allocated,
@@ -225,4 +231,60 @@ __host__ __device__ inline void dr_pix_vec(int64_t nside, int64_t pix, const dou
     const double st = sqrt((1.0 - z) * (1.0 + z));
     const double a[3] = {st * cos(phi), st * sin(phi), z};
     for (int i = 0; i < 3; ++i) v[i] = R[3 * i] * a[0] + R[3 * i + 1] * a[1] + R[3 * i + 2] * a[2];
+}
+
+__host__ __device__ inline uint64_t dr_spread_bits(uint32_t v)
+{
+    // put bit k of v at bit 2k
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// Nested pixel at resolution `nside` that contains direction v (any length).
+// Between |z| = 2/3 the pixel boundaries are the lines of constant
+// phi / (pi/2) + 3z/4 and phi / (pi/2) - 3z/4 (in units of 1/nside), whose
+// integer parts give the base pixel and the in-face indices; in the polar
+// caps they are the lines of constant (phi / (pi/2) - q) sqrt(3 (1 - |z|))
+// and (1 - phi / (pi/2) + q) sqrt(3 (1 - |z|)) within quarter q.
+__host__ __device__ inline int64_t dr_vec_pix(int64_t nside, const double v[3])
+{
+    const double len = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double z = v[2] / len;
+    double phi = atan2(v[1], v[0]);
+    if (phi < 0.0) phi += 2.0 * dr::kPi;
+    double u = phi * (2.0 / dr::kPi);                 // longitude in quarter turns, [0, 4)
+    if (u >= 4.0) u -= 4.0;
+    const double N = (double)nside;
+    int64_t face, x, y;
+    if (z <= 2.0 / 3.0 && z >= -2.0 / 3.0) {
+        const int64_t up = (int64_t)floor(N * (0.5 + u) - 0.75 * N * z);    // ascending boundary index
+        const int64_t down = (int64_t)floor(N * (0.5 + u) + 0.75 * N * z);  // descending boundary index
+        const int64_t fu = up / nside, fd = down / nside;
+        face = fu == fd ? 4 + (fu & 3) : (fu < fd ? (fu & 3) : 8 + (fd & 3));
+        x = down - fd * nside;
+        y = nside - 1 - (up - fu * nside);
+    } else {
+        int64_t q = (int64_t)floor(u);
+        if (q > 3) q = 3;
+        const double frac = u - (double)q;
+        const double s = N * sqrt(3.0 * (1.0 - fabs(z)));
+        int64_t a = (int64_t)floor(frac * s), b = (int64_t)floor((1.0 - frac) * s);
+        if (a > nside - 1) a = nside - 1;
+        if (b > nside - 1) b = nside - 1;
+        if (z > 0.0) {
+            face = q;
+            x = nside - 1 - b;
+            y = nside - 1 - a;
+        } else {
+            face = 8 + q;
+            x = a;
+            y = b;
+        }
+    }
+    return face * nside * nside + (int64_t)(dr_spread_bits((uint32_t)x) | (dr_spread_bits((uint32_t)y) << 1));
 }

@@ -40,6 +40,7 @@ EXPORTS = [
     "dartray_last_error", "dartray_version", "dartray_profile_enable", "dartray_profile_read",
     "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create", "dartray_batch_destroy",
     "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay", "dartray_trace_direct_noalloc",
+    "dartray_observe",
 ]
 
 
@@ -68,6 +69,9 @@ class GridDesc(C.Structure):
         ("k_max", C.c_int32),
         ("c_light", C.c_double),
         ("nside_max", C.c_int32),
+        ("n_point", C.c_int32),
+        ("point_pos", C.POINTER(C.c_double)),
+        ("point_lum", C.POINTER(C.c_float)),
     ]
 
 
@@ -100,6 +104,42 @@ class FieldsC(C.Structure):
         ("counters", C.c_void_p),
         ("escape", C.c_void_p),
     ]
+
+
+OBS_DISTANT, OBS_INTERNAL = 0, 1
+
+
+class Observer(C.Structure):
+    """dartray_observer: a distant observer (image plane) or an internal one
+    (HEALPix all-sky map)."""
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("dir", C.c_double * 3),
+        ("up", C.c_double * 3),
+        ("centre", C.c_double * 3),
+        ("pixel_size", C.c_double),
+        ("nx", C.c_int32),
+        ("ny", C.c_int32),
+        ("pos", C.c_double * 3),
+        ("nside_map", C.c_int32),
+        ("frame", C.c_double * 9),
+    ]
+
+
+def observer(kind, dir=(0, 0, 1), up=(0, 1, 0), centre=(0, 0, 0), pixel_size=1.0, nx=1, ny=1, pos=(0, 0, 0),
+             nside_map=1, frame=None) -> Observer:
+    o = Observer()
+    o.kind = OBS_DISTANT if kind == "distant" else OBS_INTERNAL
+    o.dir = (C.c_double * 3)(*[float(x) for x in dir])
+    o.up = (C.c_double * 3)(*[float(x) for x in up])
+    o.centre = (C.c_double * 3)(*[float(x) for x in centre])
+    o.pixel_size = float(pixel_size)
+    o.nx, o.ny = int(nx), int(ny)
+    o.pos = (C.c_double * 3)(*[float(x) for x in pos])
+    o.nside_map = int(nside_map)
+    fr = np.zeros(9) if frame is None else np.asarray(frame, dtype=np.float64).ravel()
+    o.frame = (C.c_double * 9)(*fr.tolist())
+    return o
 
 
 class Tuning(C.Structure):
@@ -154,6 +194,7 @@ def load_library():
     L.dartray_batch_run.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.POINTER(FieldsC)), C.c_int32]
     L.dartray_batch_capture.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.POINTER(FieldsC)), C.c_int32]
     L.dartray_batch_replay.argtypes = [C.c_void_p]
+    L.dartray_observe.argtypes = [C.c_void_p, C.POINTER(Observer), C.c_void_p, C.c_void_p]
     L.dartray_last_error.restype = C.c_char_p
     L.dartray_version.restype = C.c_char_p
     for name in ("dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
@@ -161,7 +202,8 @@ def load_library():
                  "dartray_scatter_iter", "dartray_trace_adjoint",
                  "dartray_debug_ray_cells", "dartray_workspace_bytes", "dartray_profile_enable",
                  "dartray_profile_read", "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create",
-                 "dartray_batch_destroy", "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay"):
+                 "dartray_batch_destroy", "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay",
+                 "dartray_observe"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -204,6 +246,8 @@ class Grid:
             albedo=np.ascontiguousarray(grid.albedo, dtype=np.float32),
             g=np.ascontiguousarray(grid.g, dtype=np.float32),
             nside_sca=np.ascontiguousarray(grid.nside_sca, dtype=np.int32),
+            point_pos=np.ascontiguousarray(getattr(grid, "point_pos", np.zeros((0, 3))), dtype=np.float64),
+            point_lum=np.ascontiguousarray(getattr(grid, "point_lum", np.zeros((0, 0))), dtype=np.float32),
         )
         d = GridDesc()
         d.nroot = (C.c_int32 * 3)(*[int(x) for x in grid.nroot])
@@ -223,6 +267,10 @@ class Grid:
         d.k_max = int(grid.k_max)
         d.c_light = float(grid.c_light)
         d.nside_max = int(nside_max or 0)
+        d.n_point = int(keep["point_pos"].shape[0])
+        if d.n_point:
+            d.point_pos = _ptr(keep["point_pos"], C.c_double)
+            d.point_lum = _ptr(keep["point_lum"], C.c_float)
         h = C.c_void_p()
         _check(L.dartray_grid_create(C.byref(d), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
@@ -476,6 +524,17 @@ def rfed_escape(rho, grid: Grid, policy, frame=None):
 def rfed(rho, grid: Grid, policy, frame=None):
     """Differentiable energy density U(rho)."""
     return rfed_escape(rho, grid, policy, frame)[0]
+
+
+def observe(grid: Grid, obs: Observer, S_total=None):
+    """Observer map (device double [n_lambda, npix]) of the grid's emission and,
+    when S_total (device float, S layout) is given, its scattered light."""
+    import torch
+    npix = obs.nx * obs.ny if obs.kind == OBS_DISTANT else 12 * obs.nside_map ** 2
+    out = torch.empty((grid.nl, npix), dtype=torch.float64, device=torch.device("cuda", torch.cuda.current_device()))
+    _check(load_library().dartray_observe(grid.h, C.byref(obs), None if S_total is None else C.c_void_p(S_total.data_ptr()),
+                                          C.c_void_p(out.data_ptr())))
+    return out
 
 
 def debug_ray_cells(grid: Grid, origins, dirs, max_cross=4096):

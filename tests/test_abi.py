@@ -55,6 +55,7 @@ int main(void) {
          offsetof(dartray_trace_opts, max_steps), offsetof(dartray_fields, counters));
   printf("%zu %zu\\n", offsetof(dartray_tuning, item_order), offsetof(dartray_fields, escape));
   printf("%zu %zu %zu\\n", offsetof(dartray_trace_opts, f_U), offsetof(dartray_trace_opts, r_pre), offsetof(dartray_trace_opts, flags));
+  printf("%zu %zu %zu\\n", offsetof(dartray_grid_desc, n_point), offsetof(dartray_grid_desc, point_lum), sizeof(dartray_observer));
   return 0;
 }
 """)
@@ -65,7 +66,8 @@ int main(void) {
     want = [C.sizeof(dartray.GridDesc), C.sizeof(dartray.TraceOpts), C.sizeof(dartray.FieldsC), C.sizeof(dartray.Tuning),
             dartray.GridDesc.c_light.offset, dartray.GridDesc.nside_max.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
             dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset, dartray.FieldsC.escape.offset,
-            dartray.TraceOpts.f_U.offset, dartray.TraceOpts.r_pre.offset, dartray.TraceOpts.flags.offset]
+            dartray.TraceOpts.f_U.offset, dartray.TraceOpts.r_pre.offset, dartray.TraceOpts.flags.offset,
+            dartray.GridDesc.n_point.offset, dartray.GridDesc.point_lum.offset, C.sizeof(dartray.Observer)]
     assert got == want
 
 
@@ -155,6 +157,31 @@ def test_eq5_rule_beyond_k_max_3_is_unsupported(lib):
     h = C.c_void_p()
     assert lib.dartray_grid_create(C.byref(d), None, C.byref(h)) == dartray.E_UNSUPPORTED
     assert h.value is None and b"k_max" in lib.dartray_last_error()
+
+
+@pytest.mark.parametrize("breakage", ["outside", "on_upper_face", "nan_pos", "neg_lum", "null_array"])
+def test_malformed_point_sources_rejected(lib, breakage):
+    from paper_1709_03802_amd import workloads as W
+    from paper_1709_03802_amd import dartray
+    grid = W.random_octree(seed=5)
+    lo, hi = grid.box()
+    pos = np.array([lo + 0.3 * (hi - lo), lo + 0.7 * (hi - lo)], dtype=np.float64)
+    lum = np.ones((grid.n_lambda, 2), dtype=np.float32)
+    if breakage == "outside":
+        pos[1, 0] = hi[0] + 0.1
+    elif breakage == "on_upper_face":
+        pos[0, 2] = hi[2]
+    elif breakage == "nan_pos":
+        pos[0, 1] = np.nan
+    elif breakage == "neg_lum":
+        lum[0, 1] = -1.0
+    d, keep = _desc(grid)
+    d.n_point = 2
+    d.point_pos = pos.ctypes.data_as(C.POINTER(C.c_double))
+    d.point_lum = None if breakage == "null_array" else lum.ctypes.data_as(C.POINTER(C.c_float))
+    h = C.c_void_p()
+    assert lib.dartray_grid_create(C.byref(d), None, C.byref(h)) == dartray.E_INVALID
+    assert h.value is None and b"point" in lib.dartray_last_error()
 
 
 def test_null_arguments(lib):
