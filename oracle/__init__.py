@@ -101,6 +101,16 @@ class Observer(C.Structure):
 _lib = None
 
 
+class DustModelC(C.Structure):
+    _fields_ = [
+        ("b0", C.c_double),
+        ("x0", C.c_double),
+        ("t_max", C.c_double),
+        ("lam", C.POINTER(C.c_double)),
+        ("dlambda", C.POINTER(C.c_double)),
+    ]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -150,6 +160,12 @@ def lib():
         L.orc_healpix_pix.restype = C.c_int64
         L.orc_observe.argtypes = [C.c_void_p, C.POINTER(Observer), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_observe.restype = C.c_int
+        L.orc_absorbed.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_dust_power.argtypes = [C.c_void_p, C.POINTER(DustModelC), C.c_double]
+        L.orc_dust_power.restype = C.c_double
+        L.orc_dust_emission.argtypes = [C.c_void_p, C.POINTER(DustModelC), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_dust_emission.restype = C.c_int
         _lib = L
     return _lib
 
@@ -424,12 +440,14 @@ class RunResult:
 
 
 def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_init=None,
-        passes=None) -> RunResult:
+        passes=None, U_init=None, S_init=None) -> RunResult:
     """Step 1 (optional), the direct pass and the scattering iterations (Sect. 2).
 
     U_LL is the step-1 result, then the running U after every pass (the
     footnote of Sect. 2).  ``U_LL_init`` replaces step 1 by a given U_LL.
     ``passes`` limits the number of passes after step 1 (direct counts as 1).
+    ``U_init`` / ``S_init`` start the running U and S_total from given values
+    (a dust self-heating iteration continues the previous one's, Sect. 3.3).
     With policy.f_L > 0 the iterations stop once the pending scattered
     luminosity falls below f_L times the total scattered in the direct pass.
     """
@@ -447,8 +465,9 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
     n_pass = 1 + policy.n_scatter if passes is None else passes
     f_L = float(getattr(policy, "f_L", 0.0))
     r_k = []
-    U = np.zeros((model.nl, model.n))
-    S_total = np.zeros(model.s_size)
+    U = np.zeros((model.nl, model.n)) if U_init is None else \
+        np.array(U_init, dtype=np.float64).reshape(model.nl, model.n)
+    S_total = np.zeros(model.s_size) if S_init is None else np.array(S_init, dtype=np.float64).reshape(model.s_size)
     S_pending = None
     escape = np.zeros((model.nl, 12 * int(policy.nside) ** 2))
     for k in range(n_pass):
@@ -471,3 +490,99 @@ def run(model: Model, policy, frame=None, source_mask=None, n_threads=0, U_LL_in
                 break
     return RunResult(U=U, U_LL=U_LL, S_total=S_total, S_pending=S_pending, passes=results, escape=escape,
                      r_k=r_k)
+
+
+# ---------------------------------------------------------------------------
+# Dust emission and the self-heating loop (Sect. 3.3)
+# ---------------------------------------------------------------------------
+
+
+def _dust_c(dust):
+    lam = np.ascontiguousarray(dust.lambdas_um, dtype=np.float64)
+    dl = np.ascontiguousarray(dust.dlambda_um, dtype=np.float64)
+    d = DustModelC(float(dust.b0), float(dust.x0), float(dust.t_max), _p(lam, C.c_double), _p(dl, C.c_double))
+    return d, (lam, dl)
+
+
+def absorbed(model: Model, U) -> np.ndarray:
+    """Luminosity absorbed by the dust of each cell, summed over the grid's
+    bands: (1 - albedo) kappa rho V c U."""
+    A = np.zeros(model.n)
+    Uc = np.ascontiguousarray(U, dtype=np.float64).reshape(model.nl, model.n)
+    lib().orc_absorbed(model.h, _p(Uc, C.c_double), _p(A, C.c_double))
+    return A
+
+
+def dust_power(model: Model, dust, T: float) -> float:
+    """Power a unit dust mass emits over the model's bands at temperature T."""
+    d, keep = _dust_c(dust)
+    return float(lib().orc_dust_power(model.h, C.byref(d), float(T)))
+
+
+def dust_emission(model: Model, dust, A):
+    """Equilibrium temperature [n] and band emission j [nl, n] of every cell
+    of the emitting grid for absorbed luminosities A [n]."""
+    d, keep = _dust_c(dust)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    T = np.zeros(model.n)
+    j = np.zeros((model.nl, model.n))
+    rc = lib().orc_dust_emission(model.h, C.byref(d), _p(A, C.c_double), _p(T, C.c_double), _p(j, C.c_double))
+    if rc != 0:
+        raise ValueError("dust temperature above t_max")
+    return T, j
+
+
+@dataclass
+class SelfHeatResult:
+    T: np.ndarray          # [n] temperature of the last emission update
+    j: np.ndarray          # [nl, n] emission of the last update (what the grain emits now)
+    j_traced: np.ndarray   # [nl, n] emission whose light U and S_total hold
+    U: np.ndarray          # [nl, n] dust-emission RFED
+    S_total: np.ndarray    # dust-emission scattered luminosity
+    ratios: list           # per update after the first RT: max dj / j_prev
+    runs: list             # RunResult of every dust RT calculation
+    A_star: np.ndarray     # [n] absorbed stellar luminosity
+
+
+def dust_selfheat(star_model: Model, U_star, dust_grid, policy, dust, frame=None, n_threads=0) -> SelfHeatResult:
+    """The self-heating procedure of Sect. 3.3, with its own steps in order:
+
+    1. emission from the absorbed stellar luminosity alone;
+    2. a dust RT calculation of that emission (step 1 when the policy asks,
+       the direct pass, the scattering iterations);
+    3. the emission recomputed from the absorbed stellar plus dust light;
+    4. dj = j - j_prev;
+    5. a dust RT calculation of dj alone, with U_LL, U and S_total starting
+       from the previous iteration's U and S_total (no step 1);
+    6. steps 3-5 repeated until dj / j_prev < dust.conv at every cell and band.
+
+    dj is not negative in exact arithmetic (more absorbed light, a warmer
+    grain, more emission in every band); rounding residues below zero are
+    dropped.  The loop ends after step 4 once converged, so the returned j is
+    the converged emission and j_traced the emission whose light was traced;
+    a cell or band with j_prev = 0 < dj is not converged.
+    """
+    A_star = absorbed(star_model, U_star)
+    base = Model(dust_grid)
+    T, j = dust_emission(base, dust, A_star)
+    j_prev = np.zeros_like(j)
+    dj = j.copy()
+    U = None
+    S = None
+    ratios, runs = [], []
+    for it in range(int(dust.max_iter)):
+        g = dust_grid.copy()
+        g.emis = dj
+        r = run(Model(g), policy, frame=frame, n_threads=n_threads, U_init=U, S_init=S,
+                U_LL_init=U if (it > 0 and policy.adaptive) else None)
+        runs.append(r)
+        U, S = r.U, r.S_total
+        j_prev = j_prev + dj
+        T, j = dust_emission(base, dust, A_star + absorbed(base, U))
+        dj = np.maximum(j - j_prev, 0.0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            q = np.where(j_prev > 0.0, dj / np.where(j_prev > 0.0, j_prev, 1.0), np.where(dj > 0.0, np.inf, 0.0))
+        ratios.append(float(q.max()))
+        if ratios[-1] < dust.conv:
+            break
+    return SelfHeatResult(T=T, j=j, j_traced=j_prev, U=U, S_total=S, ratios=ratios, runs=runs, A_star=A_star)

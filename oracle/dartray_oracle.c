@@ -21,7 +21,9 @@
  * step 1 the block test is replaced by the fixed extent R_pre (caption of the
  * ray-density flowchart figure).  Multi-wavelength rays are blocked only when
  * negligible at every wavelength and skip deposits at negligible wavelengths
- * (Sect. 3.2).  Ray merging (Eq. 3) is not part of this oracle.
+ * (Sect. 3.2).  Ray merging (Eq. 3) is not part of this oracle.  Observer
+ * maps, point sources (Sect. 2, Sect. 3.6) and the dust emission of the
+ * self-heating loop (Sect. 3.3) close the file.
  *
  * Readings where the paper is silent (each one also listed in the design
  * notes of the repository):
@@ -90,7 +92,19 @@
  *    the fixed-ray limit, every ray ending once, the step-1 extent, and Eq. 11
  *    (N_s counted independently; the a_RT 0.05 / 0.005 property of Sect. 5);
  *  - orc_adjoint_pass: central differences on every cell (also in a frame
- *    with near-ties), a dot-product test, zero gradient at the target.
+ *    with near-ties), a dot-product test, zero gradient at the target;
+ *  - orc_healpix_pix, orc_observe: an independent ang2pix and the round trip
+ *    through pixel centres; transparent images integrating to the luminosity,
+ *    a face-on slab as a geometric series, the inverse-square all-sky map,
+ *    scattered light seen only inside its pixel;
+ *  - point sources: a point at a cell centre is that emitting cell, escape
+ *    and path sums in a transparent medium, balance, Eq. 11 counts, a point
+ *    seen by an observer, the adjoint against central differences;
+ *  - orc_absorbed, orc_dust_power, orc_dust_emission: the absorbed tally of
+ *    the march, the one-band closed-form temperature, emission equal to
+ *    absorption in every cell; the self-heating loop (Python side) by energy
+ *    conservation over its updates, linearity of the incremental processing,
+ *    the transparent limit and warming only.
  */
 
 #include <math.h>
@@ -1251,4 +1265,98 @@ int orc_observe(const orc_model *m, const orc_observer *ob, const double *S_tota
         free(acc);
     }
     return failed ? ORC_E_OOM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dust emission (Sect. 3.3): absorbed luminosity, equilibrium temperature,   */
+/* emission of a toy modified-blackbody grain                                  */
+/* ------------------------------------------------------------------------- */
+/*
+ * Every wavelength of a grid stands for a band: U, j and the tallies are
+ * band-integrated.  The dust of a cell absorbs (1 - albedo) of what it
+ * extinguishes, so with the deposit rule (U = ext / (alpha V c)) the band
+ * absorbs (1 - albedo) kappa rho V c U.  In equilibrium the grain re-emits
+ * that power in the emission bands as kappa_abs B_lambda(T) (Kirchhoff), band
+ * i carrying 4 pi rho V kappa_i (1 - albedo_i) B(lambda_i, T) dlambda_i, with
+ * the Planck-shaped B(lambda, T) = b0 lambda^-5 / (exp(x0 / (lambda T)) - 1).
+ * The paper leaves the grain model to the user (equilibrium or stochastic
+ * heating, its Sect. 3.3); this one stands in for it.
+ */
+typedef struct {
+    double b0;              /* scale of B */
+    double x0;              /* h c / k in the units of lambda times temperature */
+    double t_max;           /* upper end of the temperature bracket */
+    const double *lambda;   /* [n_lambda of the emitting grid] band centres */
+    const double *dlambda;  /* [n_lambda of the emitting grid] band widths */
+} orc_dust_model;
+
+/* A[c] += sum_l (1 - albedo_l) kappa_l rho_c V_c c U[l][c] */
+void orc_absorbed(const orc_model *m, const double *U, double *A)
+{
+    const orc_grid_desc *d = &m->d;
+    for (int64_t c = 0; c < d->n_leaves; ++c) {
+        double vol = m->side[c] * m->side[c] * m->side[c];
+        for (int l = 0; l < d->n_lambda; ++l)
+            A[c] += (1.0 - d->albedo[l]) * d->kappa[l] * d->rho[c] * vol * d->c_light * U[(int64_t)l * d->n_leaves + c];
+    }
+}
+
+static double orc_planck(const orc_dust_model *dm, double lambda, double T)
+{
+    if (!(T > 0.0)) return 0.0;
+    return dm->b0 / (lambda * lambda * lambda * lambda * lambda) / expm1(dm->x0 / (lambda * T));
+}
+
+/* power emitted per unit mass (rho V = 1) at temperature T, over every band */
+double orc_dust_power(const orc_model *m, const orc_dust_model *dm, double T)
+{
+    const orc_grid_desc *d = &m->d;
+    double p = 0.0;
+    for (int l = 0; l < d->n_lambda; ++l)
+        p += 4.0 * M_PI * d->kappa[l] * (1.0 - d->albedo[l]) * orc_planck(dm, dm->lambda[l], T) * dm->dlambda[l];
+    return p;
+}
+
+/*
+ * Equilibrium temperature of every cell of the emitting grid m from its
+ * absorbed luminosity A (the power per unit mass A / (rho V) equals
+ * orc_dust_power(T)), by bisection of [0, t_max] down to adjacent doubles,
+ * and the emission j[l][c] = rho kappa_l (1 - albedo_l) B(lambda_l, T) dlambda_l
+ * (per unit volume and steradian, band-integrated).  Cells without dust or
+ * without absorbed light get T = 0 and no emission.  A cell that would need
+ * more than t_max gives ORC_E_INVALID.
+ */
+int orc_dust_emission(const orc_model *m, const orc_dust_model *dm, const double *A, double *T, double *j)
+{
+    const orc_grid_desc *d = &m->d;
+    const int64_t n = d->n_leaves;
+    int bad = 0;
+    if (orc_dust_power(m, dm, dm->t_max) <= 0.0) return ORC_E_INVALID;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t c = 0; c < n; ++c) {
+        double vol = m->side[c] * m->side[c] * m->side[c];
+        double t = 0.0;
+        if (d->rho[c] > 0.0 && A[c] > 0.0) {
+            double target = A[c] / (d->rho[c] * vol);
+            double lo = 0.0, hi = dm->t_max;
+            if (orc_dust_power(m, dm, hi) < target) {
+                bad = 1;
+            } else {
+                for (;;) {
+                    double mid = 0.5 * (lo + hi);
+                    if (!(mid > lo && mid < hi)) break;
+                    if (orc_dust_power(m, dm, mid) < target)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                t = hi;
+            }
+        }
+        T[c] = t;
+        for (int l = 0; l < d->n_lambda; ++l)
+            j[(int64_t)l * n + c] =
+                d->rho[c] * d->kappa[l] * (1.0 - d->albedo[l]) * orc_planck(dm, dm->lambda[l], t) * dm->dlambda[l];
+    }
+    return bad ? ORC_E_INVALID : ORC_OK;
 }

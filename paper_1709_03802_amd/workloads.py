@@ -26,6 +26,9 @@ which are not reproduced here):
                 cells, direct + 4 scattering passes.
 * ``disk_small`` a small disk octree used for parity tests of the adaptive
                 path.
+* ``selfheat``  a dusty 16^3 cube (tau_V = 30 centre to edge) lit by embedded
+                stars in 4 bands, re-emitting in 8 infrared bands through a toy
+                equilibrium grain (dust emission with self-heating).
 """
 
 from __future__ import annotations
@@ -476,6 +479,103 @@ def disk_batch(n_models=16, leaves=(1e3, 1e5), seed=1709, nside=8, n_scatter=2, 
         out.append(Workload(f"disk_batch{m}", grid, pol,
                             f"disk model {m}: {grid.n} leaves, h_R {h_r:.2f}, h_z {h_z:.2f}, tau_V {tau:.2f}"))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Dust emission with self-heating (paper Sect. 3.3)
+# ---------------------------------------------------------------------------
+
+PLANCK_X0 = 14387.77            # h c / k in um K
+
+
+@dataclasses.dataclass
+class DustModel:
+    """A toy equilibrium grain (the paper leaves the grain model to the user).
+
+    Every wavelength of a grid stands for a band (U, j and luminosities are
+    band-integrated).  A cell absorbs (1 - albedo) kappa rho V c U per band and
+    re-emits the sum in the emission bands as 4 pi rho V kappa_i (1 - albedo_i)
+    B(lambda_i, T) dlambda_i with B(lambda, T) = b0 lambda^-5 /
+    (exp(x0 / (lambda T)) - 1), T set by that balance.
+    """
+
+    b0: float
+    x0: float
+    t_max: float
+    lambdas_um: np.ndarray      # band centres of the emitting grid
+    dlambda_um: np.ndarray      # band widths
+    conv: float = 0.01          # stop once max dj / j_prev < conv (Sect. 3.3: 1%)
+    max_iter: int = 20          # at most this many dust RT calculations
+
+
+@dataclasses.dataclass
+class DustWorkload:
+    name: str
+    stellar: Workload
+    dust_grid: Grid             # same cells, emission bands, emission set by the loop
+    dust_policy: RayPolicy
+    dust: DustModel
+    description: str = ""
+
+
+IR_LAMBDAS = np.array([8.0, 12.0, 24.0, 35.0, 70.0, 100.0, 160.0, 350.0])
+
+
+def ir_dust_law(lambdas_um: np.ndarray):
+    """kappa relative to V, albedo and g in the infrared (toy): kappa ~
+    (lambda / 0.55)^-1.4, albedo 0.05 falling as lambda^-1, g = 0.1."""
+    lam = np.asarray(lambdas_um, dtype=np.float64)
+    return (lam / 0.55) ** (-1.4), 0.05 * (8.0 / lam), np.full(lam.shape, 0.1)
+
+
+def band_widths(lam: np.ndarray) -> np.ndarray:
+    """Widths of log-centred bands: edges at geometric midpoints, the outer
+    edges mirrored."""
+    lam = np.asarray(lam, dtype=np.float64)
+    if lam.size == 1:
+        return 0.5 * lam                 # one band: half a decade-ish around its centre
+    mid = np.sqrt(lam[1:] * lam[:-1])
+    edges = np.concatenate([[lam[0] ** 2 / mid[0]], mid, [lam[-1] ** 2 / mid[-1]]])
+    return np.diff(edges)
+
+
+def selfheat(n: int = 16, tau_v: float = 30.0, b0: float = 5.8e10, nside: int = 4, n_scatter: int = 2,
+             adaptive: bool = False, ir_lambdas=IR_LAMBDAS) -> DustWorkload:
+    """A dusty cube lit by an embedded star cluster: uniform dust with
+    centre-to-edge tau_V = tau_v, stars j ~ exp(-r / 0.15) in 4 bands
+    (0.15-1 um), and the same cells emitting in 8 infrared bands (8-350 um)
+    that the dust re-absorbs (tau ~ 1 at 8 um).  The default b0 puts a cell
+    that absorbs the mean stellar luminosity per unit dust mass of the default
+    cube near 25 K.
+    """
+    level, ijk = uniform_leaves((n, n, n))
+    size = 1.0 / n
+    centre = (ijk + 0.5) * size
+    r = np.linalg.norm(centre - 0.5, axis=1)
+    rho = np.full(level.shape[0], 2.0 * tau_v)
+    lam_s = np.array([0.15, 0.3, 0.55, 1.0])
+    k_s, a_s, g_s = dust_law(lam_s)
+    emis = np.exp(-r / 0.15)[None, :] * np.array([1.0, 0.8, 0.6, 0.4])[:, None]
+    star = Grid(nroot=(n, n, n), lo=(0.0, 0.0, 0.0), root_size=size, level=level, ijk=ijk, rho=rho,
+                emis=emis, kappa=k_s, albedo=a_s, g=g_s, nside_sca=np.full(4, 2, dtype=np.int32), lambdas_um=lam_s)
+    k_d, a_d, g_d = ir_dust_law(ir_lambdas)
+    nl = len(ir_lambdas)
+    dust_grid = Grid(nroot=(n, n, n), lo=(0.0, 0.0, 0.0), root_size=size, level=level.copy(), ijk=ijk.copy(),
+                     rho=rho.copy(), emis=np.zeros((nl, level.shape[0])), kappa=k_d, albedo=a_d, g=g_d,
+                     nside_sca=np.full(nl, 1, dtype=np.int32), lambdas_um=np.asarray(ir_lambdas, np.float64))
+    dl = band_widths(ir_lambdas)
+    lam = np.asarray(ir_lambdas, np.float64)
+    dm = DustModel(b0=b0, x0=PLANCK_X0, t_max=1.0e4, lambdas_um=lam, dlambda_um=dl)
+    if adaptive:
+        pol_s = RayPolicy(adaptive=True, nside=2, nside_max=32, n_rays_min=4.0, f_U=1e-3, r_pre=0.25, step1=True,
+                          n_scatter=n_scatter)
+        pol_d = RayPolicy(adaptive=True, nside=2, nside_max=32, n_rays_min=4.0, f_U=1e-3, r_pre=0.25, step1=True,
+                          n_scatter=n_scatter)
+    else:
+        pol_s = RayPolicy(adaptive=False, nside=nside, nside_max=nside, n_scatter=n_scatter)
+        pol_d = RayPolicy(adaptive=False, nside=nside, nside_max=nside, n_scatter=n_scatter)
+    return DustWorkload(f"selfheat{n}", Workload(f"selfheat{n}_stars", star, pol_s), dust_grid, pol_d, dm,
+                        f"uniform {n}^3 cube, tau_V = {tau_v} centre to edge, embedded stars, 8 IR bands")
 
 
 def by_name(name: str) -> Workload:
