@@ -65,6 +65,8 @@ extern "C" {
 #define DARTRAY_FLAG_COUNTERS 1u    /* fill fields->counters */
 #define DARTRAY_FLAG_CHECK 2u       /* synchronise after the pass and return DARTRAY_E_NUMERIC
                                        if it produced a non-finite U or S value */
+#define DARTRAY_FLAG_CONTINUE 4u    /* DIRECT adds S_next to S_total instead of replacing it: a
+                                       run that continues an earlier one (Sect. 3.3) */
 
 /* tally slots, per wavelength, FP64, in luminosity units */
 #define DARTRAY_T_EMITTED 0         /* luminosity launched by the pass's sources */
@@ -239,9 +241,9 @@ int dartray_grid_set_rho(dartray_grid *grid, const float *rho_device);
 /*
  * Step 1 or the direct-light pass (Sect. 2, steps 1-2), by opts->mode.
  * STEP1: U_LL <- U_k of rays traced within r_pre (adaptive only).
- * DIRECT: zeroes S_total, then U <- U + U_k, S_total <- S_next,
- *   S_pending <- S_next; U_LL <- U when adaptive.  Records sum(S_next) as the
- *   reference of the convergence ratio.
+ * DIRECT: U <- U + U_k, S_total <- S_next (S_total + S_next with
+ *   DARTRAY_FLAG_CONTINUE), S_pending <- S_next; U_LL <- U when adaptive.
+ *   Records sum(S_next) as the reference of the convergence ratio.
  */
 int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dartray_fields *fields);
 
@@ -441,6 +443,82 @@ typedef struct {
 } dartray_observer;
 
 int dartray_observe(dartray_grid *grid, const dartray_observer *obs, const float *S_total, double *map);
+
+/*
+ * Dust emission and the self-heating loop (Sect. 3.3).
+ *
+ * Every wavelength of a grid stands for a band: U, j and the luminosities
+ * are band-integrated.  The dust of a cell absorbs (1 - albedo_l) kappa_l
+ * rho V c U_l in band l (with the deposit rule U = ext / (alpha V c) this is
+ * the absorbed part of what the band's rays extinguish there).  The grain
+ * model is the caller's choice in the paper (equilibrium or stochastic
+ * heating); the library offers an equilibrium grain whose emission in band i
+ * of the emitting grid is 4 pi rho V kappa_i (1 - albedo_i) B(lambda_i, T)
+ * dlambda_i, with B(lambda, T) = b0 lambda^-5 / (exp(x0 / (lambda T)) - 1) and
+ * T the temperature at which the cell emits what it absorbs (found by
+ * bisection of [0, t_max] to adjacent doubles, in FP64).
+ */
+typedef struct {
+    double b0;                   /* scale of B */
+    double x0;                   /* h c / k in the units of lambda times temperature */
+    double t_max;                /* upper end of the temperature bracket */
+    const double *lambda;        /* host [n_lambda of the emitting grid] band centres, > 0 */
+    const double *dlambda;       /* host [n_lambda of the emitting grid] band widths, > 0 */
+} dartray_dust_model;
+
+/* A[c] += sum_l (1 - albedo_l) kappa_l rho_c V_c c U[l][c].  U: device float
+ * [n_lambda][n]; A: device double [n].  Asynchronous. */
+int dartray_absorbed(const dartray_grid *grid, const float *U, double *A);
+
+/* Equilibrium temperature T (device double [n]) and band emission j (device
+ * double [n_lambda][n], per unit volume and steradian) of the emitting grid's
+ * cells for absorbed luminosities A (device double [n]).  Cells without dust
+ * or without absorbed light: T = 0, j = 0.  Synchronises; a cell that would
+ * need more than t_max gives DARTRAY_E_NUMERIC (T and j then hold 0 there). */
+int dartray_dust_emission(dartray_grid *grid, const dartray_dust_model *dm, const double *A, double *T, double *j);
+
+/* Replace the grid's emission j (device double [n_lambda][n], per unit volume
+ * and steradian, finite and >= 0; checked before anything changes, which
+ * synchronises).  Later passes launch from it. */
+int dartray_grid_set_emis(dartray_grid *grid, const double *j);
+
+/*
+ * The self-heating procedure of Sect. 3.3 on the emitting ("dust") grid, in
+ * the paper's order:
+ *  1. emission from the absorbed stellar luminosity A_star alone;
+ *  2. a dust RT calculation of it: step 1 (adaptive rays, when so->step1),
+ *     the direct pass, up to so->n_scatter scattering iterations (stopping
+ *     early once r_k < so->f_L, when f_L > 0);
+ *  3. the emission recomputed from A_star plus the dust light absorbed;
+ *  4. dj = j - j_prev (not negative in exact arithmetic: more absorbed light,
+ *     a warmer grain; rounding residues below zero are dropped);
+ *  5. a dust RT calculation of dj alone, U and S_total continuing from the
+ *     previous calculation's and U_LL = U (no step 1);
+ *  6. 3-5 repeated until dj / j_prev < so->conv at every cell and band (a
+ *     cell and band with j_prev = 0 < dj is not converged), at most
+ *     so->max_iter calculations.
+ * opts: the ray policy of every calculation (mode and DARTRAY_FLAG_CONTINUE
+ * are set by the loop).  A_star: device double [n], dartray_absorbed of the
+ * stellar run on a grid with the same cells.  fields: the dust grid's
+ * buffers; U, U_LL and S_total are overwritten by the loop's results.
+ * T [n], j [n_lambda][n]: the last update (the converged emission);
+ * j_traced [n_lambda][n]: the emission whose light U and S_total hold; work:
+ * device double [n (1 + n_lambda)]; all device, caller-owned.  ratios (host
+ * double [max_iter]) receives max dj / j_prev after each calculation and
+ * *n_rt (host) the number of calculations.  Synchronises once per
+ * calculation; returns DARTRAY_E_NUMERIC as dartray_dust_emission does.
+ */
+typedef struct {
+    int32_t step1;               /* adaptive rays: step 1 before the first calculation */
+    int32_t n_scatter;           /* scattering iterations per calculation */
+    int32_t max_iter;            /* at most this many calculations (>= 1) */
+    double f_L;                  /* 0, or the r_k below which a calculation's iterations stop */
+    double conv;                 /* convergence threshold of dj / j_prev (Sect. 3.3: 0.01) */
+} dartray_selfheat_opts;
+
+int dartray_dust_selfheat(dartray_grid *grid, const dartray_trace_opts *opts, const dartray_selfheat_opts *so,
+                          const dartray_dust_model *dm, const double *A_star, dartray_fields *fields, double *T,
+                          double *j, double *j_traced, double *work, double *ratios, int32_t *n_rt);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *dartray_last_error(void);

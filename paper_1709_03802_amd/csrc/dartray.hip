@@ -2247,7 +2247,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.ps_pos, g.ps_xyz, g.ps_cell, g.ps_lum, g.ps_lum64, g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
+    void *ptrs[] = {g.dust_word, g.ps_pos, g.ps_xyz, g.ps_cell, g.ps_lum, g.ps_lum64, g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
                     g.own.flags, g.cell_flag, g.own.src_list, g.own.scan_blocks, g.own.n_src, g.own.dsum, g.s1_sum, g.own.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -2546,7 +2546,7 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.rec, (size_t)n), dalloc(g, &g.ull_t, (size_t)(nl * n)), dalloc(g, &g.rho_bar, (size_t)n), dalloc(g, &g.own.esc64, (size_t)nl * 12 * kMaxNsideWTable * kMaxNsideWTable),
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.lum64, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
-        dalloc(g, &g.own.n_all, 1), dalloc(g, &g.own.err_word, 1),
+        dalloc(g, &g.own.n_all, 1), dalloc(g, &g.own.err_word, 1), dalloc(g, &g.dust_word, 2),
         dalloc(g, &g.ps_pos, (size_t)std::max(np, 1)), dalloc(g, &g.ps_xyz, (size_t)std::max(np, 1)), dalloc(g, &g.ps_cell, (size_t)std::max(np, 1)),
         dalloc(g, &g.ps_lum, (size_t)std::max<int64_t>(1, (int64_t)np * nl)),
         dalloc(g, &g.ps_lum64, (size_t)std::max<int64_t>(1, (int64_t)np * nl)),
@@ -3290,7 +3290,7 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
     double *ssum = g.w.dsum;
     if ((rc = fill<double>(g, ssum, (size_t)nl, 0.0))) return rc;
     hipLaunchKernelGGL(k_finish_s, dim3(s_blocks(g), nl), dim3(256), 0, g.stream, f->S_next, f->S_total, f->S_pending,
-                       scatter ? 1 : 0, g.d_lt, g.s_size, ssum, g.w.err_word);
+                       (scatter || (o->flags & DARTRAY_FLAG_CONTINUE)) ? 1 : 0, g.d_lt, g.s_size, ssum, g.w.err_word);
     DR_LAUNCH_CHECK("k_finish_s");
     if (!scatter) {
         DR_HIP(hipMemcpyAsync(g.s1_sum, ssum, sizeof(double) * nl, hipMemcpyDeviceToDevice, g.stream));
@@ -4121,6 +4121,325 @@ int dartray_observe(dartray_grid *grid, const dartray_observer *obs, const float
     hipLaunchKernelGGL(k_observe, dim3((unsigned)std::min<int64_t>((g.n + g.n_point + 255) / 256, 8192)), dim3(256), 0,
                        g.stream, A);
     DR_LAUNCH_CHECK("k_observe");
+    return DARTRAY_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Dust emission and the self-heating loop (Sect. 3.3)
+// ---------------------------------------------------------------------------
+// Every wavelength of a grid is a band.  A cell absorbs (1 - albedo) kappa
+// rho V c U per band; the equilibrium grain re-emits the sum over the
+// emitting grid's bands as 4 pi rho V kappa_i (1 - albedo_i) B(lambda_i, T)
+// dlambda_i.  One thread per cell: the temperature is a bisection of
+// [0, t_max] down to adjacent doubles, some 60-70 steps of n_lambda expm1
+// each, negligible next to a ray pass.
+
+namespace dr {
+
+struct DustBand {
+    double kabs;                  // kappa (1 - albedo)
+    double lam, dlam;             // band centre and width
+};
+
+struct DustArgs {
+    const float *rho;
+    const int4 *leaf_box;
+    double h_fine;
+    int64_t n;
+    int32_t nl;
+    double b0, x0, t_max;
+    DustBand band[kMaxLambda];
+    const double *A;              // absorbed luminosity [n]
+    double *T;                    // [n]
+    double *j;                    // [nl][n]
+    const double *j_prev;         // [nl][n] or null
+    double *dj;                   // [nl][n] max(j - j_prev, 0), with j_prev
+    unsigned long long *word;     // [0] max dj / j_prev (FP64 bits), [1] bracket overflow
+};
+
+__device__ inline double dust_planck(const DustArgs &D, double lam, double T)
+{
+    if (!(T > 0.0)) return 0.0;
+    return D.b0 / (lam * lam * lam * lam * lam) / expm1(D.x0 / (lam * T));
+}
+
+// power a unit dust mass emits at temperature T over every band
+__device__ inline double dust_power(const DustArgs &D, double T)
+{
+    double p = 0.0;
+    for (int l = 0; l < D.nl; ++l) p += 4.0 * kPi * D.band[l].kabs * dust_planck(D, D.band[l].lam, T) * D.band[l].dlam;
+    return p;
+}
+
+__global__ __launch_bounds__(256) void k_dust_emis(const DustArgs D)
+{
+    double qmax = 0.0;
+    const double p_top = dust_power(D, D.t_max);
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < D.n; c += (int64_t)gridDim.x * blockDim.x) {
+        const double side = (double)D.leaf_box[c].w * D.h_fine;
+        const double vol = side * side * side;
+        const double rho = (double)D.rho[c];
+        const double a = D.A[c];
+        double t = 0.0;
+        if (rho > 0.0 && a > 0.0) {
+            const double target = a / (rho * vol);
+            if (!(p_top >= target)) {
+                atomicMax(&D.word[1], 1ull);
+            } else {
+                double lo = 0.0, hi = D.t_max;
+                for (;;) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (!(mid > lo && mid < hi)) break;
+                    if (dust_power(D, mid) < target)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                t = hi;
+            }
+        }
+        D.T[c] = t;
+        for (int l = 0; l < D.nl; ++l) {
+            const int64_t i = (int64_t)l * D.n + c;
+            const double jl = rho * D.band[l].kabs * dust_planck(D, D.band[l].lam, t) * D.band[l].dlam;
+            D.j[i] = jl;
+            if (D.j_prev) {
+                const double jp = D.j_prev[i];
+                const double d = jl > jp ? jl - jp : 0.0;
+                D.dj[i] = d;
+                const double q = jp > 0.0 ? d / jp : (d > 0.0 ? __builtin_huge_val() : 0.0);
+                qmax = q > qmax ? q : qmax;
+            }
+        }
+    }
+    if (D.j_prev) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(qmax, off);
+            qmax = o > qmax ? o : qmax;
+        }
+        // non-negative doubles order as their bit patterns
+        if ((threadIdx.x & 63) == 0 && qmax > 0.0) atomicMax(&D.word[0], (unsigned long long)__double_as_longlong(qmax));
+    }
+}
+
+// A[c] = (base ? base[c] : A[c]) + sum_l (1 - albedo_l) kappa_l rho_c V_c c U[l][c]
+__global__ __launch_bounds__(256) void k_absorbed(const LambdaTable *lt, const float *rho, const int4 *leaf_box,
+                                                  double h_fine, double c_light, const float *U, const double *base,
+                                                  double *A, int64_t n)
+{
+    const int nl = lt->n_lambda;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        const double side = (double)leaf_box[c].w * h_fine;
+        const double vol = side * side * side;
+        const double r = (double)rho[c];
+        double s = 0.0;
+        for (int l = 0; l < nl; ++l)
+            s += (1.0 - (double)lt->albedo[l]) * (double)lt->kappa[l] * r * vol * c_light * (double)U[(int64_t)l * n + c];
+        A[c] = (base ? base[c] : A[c]) + s;
+    }
+}
+
+// 4 pi j V of every cell, FP64 and FP32: the launch luminosity of later passes
+__global__ __launch_bounds__(256) void k_set_emis(const double *j, const int4 *leaf_box, double h_fine, int64_t n,
+                                                  int32_t nl, float *emis_lum, double *lum64)
+{
+    const int64_t tot = (int64_t)nl * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i % n;
+        const double side = (double)leaf_box[c].w * h_fine;
+        const double v = 4.0 * kPi * j[i] * side * side * side;
+        lum64[i] = v;
+        emis_lum[i] = (float)v;
+    }
+}
+
+// bit 0: some j not finite or negative
+__global__ __launch_bounds__(256) void k_check_emis(const double *j, int64_t tot, uint32_t *bad)
+{
+    bool b = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x)
+        b |= !(j[i] >= 0.0) || !isfinite(j[i]);
+    if (__ballot(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+__global__ void k_add_f64(double *a, const double *b, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] += b[i];
+}
+
+static unsigned sweep_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
+static int dust_args(const Grid &g, const dartray_dust_model *dm, DustArgs &D)
+{
+    if (!dm || !dm->lambda || !dm->dlambda) return fail(DARTRAY_E_INVALID, "dust model: null argument");
+    if (!(dm->b0 > 0.0) || !std::isfinite(dm->b0) || !(dm->x0 > 0.0) || !std::isfinite(dm->x0) ||
+        !(dm->t_max > 0.0) || !std::isfinite(dm->t_max))
+        return fail(DARTRAY_E_INVALID, "dust model: b0, x0 and t_max must be finite and > 0");
+    D = DustArgs{};
+    D.rho = g.rho;
+    D.leaf_box = g.leaf_box;
+    D.h_fine = g.h_fine;
+    D.n = g.n;
+    D.nl = g.n_lambda;
+    D.b0 = dm->b0;
+    D.x0 = dm->x0;
+    D.t_max = dm->t_max;
+    for (int l = 0; l < g.n_lambda; ++l) {
+        if (!(dm->lambda[l] > 0.0) || !std::isfinite(dm->lambda[l]) || !(dm->dlambda[l] > 0.0) ||
+            !std::isfinite(dm->dlambda[l]))
+            return fail(DARTRAY_E_INVALID, "dust model: band centres and widths must be finite and > 0");
+        D.band[l].kabs = (double)g.lt.kappa[l] * (1.0 - (double)g.lt.albedo[l]);
+        D.band[l].lam = dm->lambda[l];
+        D.band[l].dlam = dm->dlambda[l];
+    }
+    return DARTRAY_OK;
+}
+
+// one emission update; with j_prev also dj and max dj / j_prev (*ratio, host)
+static int dust_update(Grid &g, DustArgs D, double *ratio)
+{
+    int rc = fill<unsigned long long>(g, g.dust_word, 2, 0ull);
+    if (rc) return rc;
+    D.word = g.dust_word;
+    hipLaunchKernelGGL(k_dust_emis, dim3(sweep_blocks(g.n)), dim3(256), 0, g.stream, D);
+    DR_LAUNCH_CHECK("k_dust_emis");
+    unsigned long long w[2] = {0, 0};
+    DR_HIP(hipMemcpyAsync(w, g.dust_word, sizeof(w), hipMemcpyDeviceToHost, g.stream));
+    DR_HIP(hipStreamSynchronize(g.stream));
+    if (w[1]) return fail(DARTRAY_E_NUMERIC, "dust temperature above t_max");
+    if (ratio) {
+        double q;
+        std::memcpy(&q, &w[0], sizeof(q));
+        *ratio = q;
+    }
+    return DARTRAY_OK;
+}
+
+static void set_emis(Grid &g, const double *j)
+{
+    hipLaunchKernelGGL(k_set_emis, dim3(sweep_blocks((int64_t)g.n_lambda * g.n)), dim3(256), 0, g.stream, j, g.leaf_box,
+                       g.h_fine, g.n, g.n_lambda, g.emis_lum, g.lum64);
+}
+
+}  // namespace dr
+
+extern "C" {
+
+int dartray_absorbed(const dartray_grid *grid, const float *U, double *A)
+{
+    if (!grid || !U || !A) return fail(DARTRAY_E_INVALID, "null argument");
+    const Grid &g = grid->g;
+    hipLaunchKernelGGL(k_absorbed, dim3(sweep_blocks(g.n)), dim3(256), 0, g.stream, g.d_lt, g.rho, g.leaf_box, g.h_fine,
+                       g.c_light, U, (const double *)nullptr, A, g.n);
+    DR_LAUNCH_CHECK("k_absorbed");
+    return DARTRAY_OK;
+}
+
+int dartray_dust_emission(dartray_grid *grid, const dartray_dust_model *dm, const double *A, double *T, double *j)
+{
+    if (!grid || !A || !T || !j) return fail(DARTRAY_E_INVALID, "null argument");
+    Grid &g = grid->g;
+    DustArgs D;
+    int rc = dust_args(g, dm, D);
+    if (rc) return rc;
+    D.A = A;
+    D.T = T;
+    D.j = j;
+    return dust_update(g, D, nullptr);
+}
+
+int dartray_grid_set_emis(dartray_grid *grid, const double *j)
+{
+    if (!grid || !j) return fail(DARTRAY_E_INVALID, "null argument");
+    Grid &g = grid->g;
+    const int64_t tot = (int64_t)g.n_lambda * g.n;
+    int rc = fill<uint32_t>(g, g.w.err_word, 1, 0u);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_check_emis, dim3(sweep_blocks(tot)), dim3(256), 0, g.stream, j, tot, g.w.err_word);
+    DR_LAUNCH_CHECK("k_check_emis");
+    uint32_t bad = 0;
+    DR_HIP(hipMemcpyAsync(&bad, g.w.err_word, sizeof(bad), hipMemcpyDeviceToHost, g.stream));
+    DR_HIP(hipStreamSynchronize(g.stream));
+    if (bad) return fail(DARTRAY_E_INVALID, "emission must be finite and >= 0");
+    set_emis(g, j);
+    DR_LAUNCH_CHECK("k_set_emis");
+    return DARTRAY_OK;
+}
+
+int dartray_dust_selfheat(dartray_grid *grid, const dartray_trace_opts *opts, const dartray_selfheat_opts *so,
+                          const dartray_dust_model *dm, const double *A_star, dartray_fields *fields, double *T,
+                          double *j, double *j_traced, double *work, double *ratios, int32_t *n_rt)
+{
+    if (!grid || !opts || !so || !A_star || !fields || !T || !j || !j_traced || !work || !ratios || !n_rt)
+        return fail(DARTRAY_E_INVALID, "null argument");
+    Grid &g = grid->g;
+    if (so->max_iter < 1 || so->max_iter > 1000) return fail(DARTRAY_E_INVALID, "max_iter must be 1..1000");
+    if (so->n_scatter < 0) return fail(DARTRAY_E_INVALID, "n_scatter must be >= 0");
+    if (!(so->conv > 0.0) || !std::isfinite(so->conv)) return fail(DARTRAY_E_INVALID, "conv must be finite and > 0");
+    if (!(so->f_L >= 0.0) || !std::isfinite(so->f_L)) return fail(DARTRAY_E_INVALID, "f_L must be finite and >= 0");
+    if (!fields->U || !fields->U_LL || !fields->S_total) return fail(DARTRAY_E_INVALID, "fields: U, U_LL and S_total required");
+    DustArgs D;
+    int rc = dust_args(g, dm, D);
+    if (rc) return rc;
+    dartray_trace_opts o = *opts;
+    o.mode = DARTRAY_MODE_DIRECT;
+    o.flags &= ~DARTRAY_FLAG_CONTINUE;
+    if ((rc = check_opts(g, &o, fields, false))) return rc;
+    *n_rt = 0;
+    const int64_t n = g.n, nln = (int64_t)g.n_lambda * g.n;
+    double *A = work, *dj = work + n;
+    // the loop's energy density starts empty, and so does what it has traced
+    if ((rc = fill<float>(g, fields->U, (size_t)nln, 0.f))) return rc;
+    if ((rc = fill<double>(g, j_traced, (size_t)nln, 0.0))) return rc;
+    // 1. emission from the stellar heating alone: dj = j (j_traced is zero)
+    DR_HIP(hipMemcpyAsync(A, A_star, sizeof(double) * n, hipMemcpyDeviceToDevice, g.stream));
+    D.A = A;
+    D.T = T;
+    D.j = j;
+    D.j_prev = j_traced;
+    D.dj = dj;
+    double q = 0.0;
+    if ((rc = dust_update(g, D, &q))) return rc;
+    set_emis(g, dj);
+    DR_LAUNCH_CHECK("k_set_emis");
+    for (int it = 0; it < so->max_iter; ++it) {
+        // 2 / 5. a dust RT calculation of dj
+        o.flags = opts->flags & ~DARTRAY_FLAG_CONTINUE;
+        if (it == 0 && o.adaptive) {
+            if (so->step1) {
+                o.mode = DARTRAY_MODE_STEP1;
+                if ((rc = dartray_trace_direct(grid, &o, fields))) return rc;
+            } else if ((rc = fill<float>(g, fields->U_LL, (size_t)nln, 0.f))) {
+                return rc;
+            }
+        }
+        // later calculations continue S_total; U_LL = U was left by the previous pass
+        if (it > 0) o.flags |= DARTRAY_FLAG_CONTINUE;
+        o.mode = DARTRAY_MODE_DIRECT;
+        if ((rc = dartray_trace_direct(grid, &o, fields))) return rc;
+        o.flags &= ~DARTRAY_FLAG_CONTINUE;
+        for (int k = 0; k < so->n_scatter; ++k) {
+            double rk = 0.0;
+            if ((rc = dartray_scatter_iter(grid, &o, fields, so->f_L > 0.0 ? &rk : nullptr))) return rc;
+            if (so->f_L > 0.0 && rk < so->f_L) break;
+        }
+        hipLaunchKernelGGL(k_add_f64, dim3(sweep_blocks(nln)), dim3(256), 0, g.stream, j_traced, (const double *)dj, nln);
+        DR_LAUNCH_CHECK("k_add_f64");
+        // 3. emission from the stellar plus the dust light absorbed; 4. dj
+        hipLaunchKernelGGL(k_absorbed, dim3(sweep_blocks(n)), dim3(256), 0, g.stream, g.d_lt, g.rho, g.leaf_box,
+                           g.h_fine, g.c_light, (const float *)fields->U, A_star, A, n);
+        DR_LAUNCH_CHECK("k_absorbed");
+        if ((rc = dust_update(g, D, &q))) return rc;
+        ratios[it] = q;
+        *n_rt = it + 1;
+        // 6. converged at every cell and band
+        if (q < so->conv) break;
+        set_emis(g, dj);
+        DR_LAUNCH_CHECK("k_set_emis");
+    }
     return DARTRAY_OK;
 }
 

@@ -127,6 +127,7 @@ struct Grid {
     int32_t wtab_nside = 0;
     bool wtab_valid = false;
     unsigned long long *queue = nullptr;  // work counter of the adaptive march
+    unsigned long long *dust_word = nullptr;  // [2] dust emission: max dj / j_prev (FP64 bits), bracket overflow
 
     // deposit log of the adaptive passes that scatter light: one tuple
     // (cell, direction entry, per-wavelength energy-density deposit) per

@@ -40,7 +40,8 @@ EXPORTS = [
     "dartray_last_error", "dartray_version", "dartray_profile_enable", "dartray_profile_read",
     "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create", "dartray_batch_destroy",
     "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay", "dartray_trace_direct_noalloc",
-    "dartray_observe",
+    "dartray_observe", "dartray_absorbed", "dartray_dust_emission", "dartray_grid_set_emis",
+    "dartray_dust_selfheat",
 ]
 
 
@@ -142,6 +143,27 @@ def observer(kind, dir=(0, 0, 1), up=(0, 1, 0), centre=(0, 0, 0), pixel_size=1.0
     return o
 
 
+class DustModelC(C.Structure):
+    """dartray_dust_model: the equilibrium grain of the emission bands."""
+    _fields_ = [
+        ("b0", C.c_double),
+        ("x0", C.c_double),
+        ("t_max", C.c_double),
+        ("lam", C.POINTER(C.c_double)),
+        ("dlambda", C.POINTER(C.c_double)),
+    ]
+
+
+class SelfHeatOpts(C.Structure):
+    _fields_ = [
+        ("step1", C.c_int32),
+        ("n_scatter", C.c_int32),
+        ("max_iter", C.c_int32),
+        ("f_L", C.c_double),
+        ("conv", C.c_double),
+    ]
+
+
 class Tuning(C.Structure):
     """dartray_tuning: launch parameters of the fixed-ray passes (0 = default);
     item_order also sets the order of the adjoint march's work items."""
@@ -195,6 +217,13 @@ def load_library():
     L.dartray_batch_capture.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.POINTER(FieldsC)), C.c_int32]
     L.dartray_batch_replay.argtypes = [C.c_void_p]
     L.dartray_observe.argtypes = [C.c_void_p, C.POINTER(Observer), C.c_void_p, C.c_void_p]
+    L.dartray_absorbed.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.dartray_dust_emission.argtypes = [C.c_void_p, C.POINTER(DustModelC), C.c_void_p, C.c_void_p, C.c_void_p]
+    L.dartray_grid_set_emis.argtypes = [C.c_void_p, C.c_void_p]
+    L.dartray_dust_selfheat.argtypes = [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(SelfHeatOpts),
+                                        C.POINTER(DustModelC), C.c_void_p, C.POINTER(FieldsC), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int32)]
     L.dartray_last_error.restype = C.c_char_p
     L.dartray_version.restype = C.c_char_p
     for name in ("dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
@@ -203,7 +232,8 @@ def load_library():
                  "dartray_debug_ray_cells", "dartray_workspace_bytes", "dartray_profile_enable",
                  "dartray_profile_read", "dartray_set_tuning", "dartray_get_tuning", "dartray_batch_create",
                  "dartray_batch_destroy", "dartray_batch_run", "dartray_batch_capture", "dartray_batch_replay",
-                 "dartray_observe"):
+                 "dartray_observe", "dartray_absorbed", "dartray_dust_emission", "dartray_grid_set_emis",
+                 "dartray_dust_selfheat"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -591,3 +621,78 @@ def run(grid: Grid, policy, frame=None, source_mask=None, fields: Optional[Field
         if k > 0 and f_L > 0.0 and rks[-1] < f_L:
             break   # convergence test of the scattering iterations (Sect. 2)
     return RunOutput(f, tallies, counters, rks, escapes)
+
+
+# ---------------------------------------------------------------------------
+# Dust emission and the self-heating loop (Sect. 3.3)
+# ---------------------------------------------------------------------------
+
+
+def _dust_c(dust):
+    lam = np.ascontiguousarray(dust.lambdas_um, dtype=np.float64)
+    dl = np.ascontiguousarray(dust.dlambda_um, dtype=np.float64)
+    d = DustModelC(float(dust.b0), float(dust.x0), float(dust.t_max), _ptr(lam, C.c_double), _ptr(dl, C.c_double))
+    return d, (lam, dl)
+
+
+def absorbed(grid: Grid, U, A=None):
+    """A (device double [n]) += the luminosity the dust of each cell absorbs
+    from the energy density U (device float [n_lambda, n])."""
+    import torch
+    if A is None:
+        A = torch.zeros(grid.n, dtype=torch.float64, device=U.device)
+    _check(load_library().dartray_absorbed(grid.h, C.c_void_p(U.data_ptr()), C.c_void_p(A.data_ptr())))
+    return A
+
+
+def dust_emission(grid: Grid, dust, A):
+    """Equilibrium temperature [n] and band emission [n_lambda, n] (device
+    double) of the emitting grid's cells for absorbed luminosities A."""
+    import torch
+    T = torch.empty(grid.n, dtype=torch.float64, device=A.device)
+    j = torch.empty((grid.nl, grid.n), dtype=torch.float64, device=A.device)
+    d, keep = _dust_c(dust)
+    _check(load_library().dartray_dust_emission(grid.h, C.byref(d), C.c_void_p(A.data_ptr()),
+                                                C.c_void_p(T.data_ptr()), C.c_void_p(j.data_ptr())))
+    return T, j
+
+
+def set_emis(grid: Grid, j):
+    """Replace the grid's emission (device double [n_lambda, n])."""
+    _check(load_library().dartray_grid_set_emis(grid.h, C.c_void_p(j.data_ptr())))
+
+
+@dataclass
+class SelfHeatOutput:
+    T: object              # device double [n]
+    j: object              # device double [nl, n], the converged emission
+    j_traced: object       # device double [nl, n], the emission whose light U holds
+    fields: Fields         # U, S_total of the dust emission
+    ratios: list           # max dj / j_prev after each dust RT calculation
+    A_star: object         # device double [n]
+
+
+def dust_selfheat(star_grid: Grid, U_star, dust_grid: Grid, policy, dust, frame=None, fields=None) -> SelfHeatOutput:
+    """Absorbed stellar luminosity from U_star (device float, the stellar
+    grid's U), then the self-heating loop on the dust grid."""
+    import torch
+    dev = U_star.device
+    A_star = absorbed(star_grid, U_star)
+    f = Fields(dust_grid) if fields is None else fields
+    n, nl = dust_grid.n, dust_grid.nl
+    T = torch.zeros(n, dtype=torch.float64, device=dev)
+    j = torch.zeros((nl, n), dtype=torch.float64, device=dev)
+    jt = torch.zeros((nl, n), dtype=torch.float64, device=dev)
+    work = torch.zeros(n * (1 + nl), dtype=torch.float64, device=dev)
+    so = SelfHeatOpts(int(bool(policy.adaptive and policy.step1)), int(policy.n_scatter), int(dust.max_iter),
+                      float(getattr(policy, "f_L", 0.0)), float(dust.conv))
+    d, keep = _dust_c(dust)
+    ratios = (C.c_double * int(dust.max_iter))()
+    n_rt = C.c_int32(0)
+    o = make_opts(policy, MODE_DIRECT, frame)
+    fc = f.c()
+    _check(load_library().dartray_dust_selfheat(dust_grid.h, C.byref(o), C.byref(so), C.byref(d),
+                                                C.c_void_p(A_star.data_ptr()), C.byref(fc), C.c_void_p(T.data_ptr()),
+                                                C.c_void_p(j.data_ptr()), C.c_void_p(jt.data_ptr()),
+                                                C.c_void_p(work.data_ptr()), ratios, C.byref(n_rt)))
+    return SelfHeatOutput(T, j, jt, f, [ratios[i] for i in range(n_rt.value)], A_star)

@@ -56,6 +56,8 @@ int main(void) {
   printf("%zu %zu\\n", offsetof(dartray_tuning, item_order), offsetof(dartray_fields, escape));
   printf("%zu %zu %zu\\n", offsetof(dartray_trace_opts, f_U), offsetof(dartray_trace_opts, r_pre), offsetof(dartray_trace_opts, flags));
   printf("%zu %zu %zu\\n", offsetof(dartray_grid_desc, n_point), offsetof(dartray_grid_desc, point_lum), sizeof(dartray_observer));
+  printf("%zu %zu %zu %zu\\n", sizeof(dartray_dust_model), offsetof(dartray_dust_model, dlambda), sizeof(dartray_selfheat_opts),
+         offsetof(dartray_selfheat_opts, conv));
   return 0;
 }
 """)
@@ -67,7 +69,9 @@ int main(void) {
             dartray.GridDesc.c_light.offset, dartray.GridDesc.nside_max.offset, dartray.TraceOpts.frame.offset, dartray.TraceOpts.max_steps.offset,
             dartray.FieldsC.counters.offset, dartray.Tuning.item_order.offset, dartray.FieldsC.escape.offset,
             dartray.TraceOpts.f_U.offset, dartray.TraceOpts.r_pre.offset, dartray.TraceOpts.flags.offset,
-            dartray.GridDesc.n_point.offset, dartray.GridDesc.point_lum.offset, C.sizeof(dartray.Observer)]
+            dartray.GridDesc.n_point.offset, dartray.GridDesc.point_lum.offset, C.sizeof(dartray.Observer),
+            C.sizeof(dartray.DustModelC), dartray.DustModelC.dlambda.offset, C.sizeof(dartray.SelfHeatOpts),
+            dartray.SelfHeatOpts.conv.offset]
     assert got == want
 
 
@@ -192,3 +196,8 @@ def test_null_arguments(lib):
     assert lib.dartray_grid_destroy(None) == dartray.OK
     assert lib.dartray_set_tuning(None, None) == dartray.E_INVALID
     assert lib.dartray_get_tuning(None, None) == dartray.E_INVALID
+    assert lib.dartray_absorbed(None, None, None) == dartray.E_INVALID
+    assert lib.dartray_dust_emission(None, None, None, None, None) == dartray.E_INVALID
+    assert lib.dartray_grid_set_emis(None, None) == dartray.E_INVALID
+    assert lib.dartray_dust_selfheat(None, None, None, None, None, None, None, None, None, None, None, None) == \
+        dartray.E_INVALID
