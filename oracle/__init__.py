@@ -80,6 +80,7 @@ class PassOpts(C.Structure):
         ("max_steps", C.c_int64),
         ("n_threads", C.c_int32),
         ("a_RT", C.c_double),
+        ("mode_2d", C.c_int32),
     ]
 
 
@@ -379,6 +380,7 @@ def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
         keep = np.ascontiguousarray(source_mask, dtype=np.uint8)
         o.source_mask = _p(keep, C.c_uint8)
     o.n_threads = int(n_threads)
+    o.mode_2d = 1 if getattr(policy, "mode_2d", False) else 0
     return o, keep
 
 

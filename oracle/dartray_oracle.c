@@ -51,9 +51,11 @@
  *  - traversal: the exit face is the axis with the smallest exit distance
  *    (exact ties resolved x before y before z) and the next leaf is the face
  *    neighbour across it that contains the exit point (points on a face
- *    belong to the side the direction points to, the upper side when the
- *    component is zero); a ray through an edge or corner therefore crosses
- *    zero-length segments;
+ *    belong to the side the direction points to; a ray lying in the face
+ *    plane, with a zero component, takes the side away from the block's
+ *    central plane, which keeps mirror-image rays on mirror-image cells, and
+ *    the upper side on the central plane itself); a ray through an edge or
+ *    corner therefore crosses zero-length segments;
  *  - a segment whose length is zero up to the rounding of its two end
  *    distances -- no longer than 2^-46 of its exit distance, some 32 to 64
  *    units in the last place of an FP64 distance -- is an edge or corner
@@ -169,6 +171,7 @@ typedef struct {
     int64_t max_steps;      /* per ray; <= 0 means unlimited */
     int32_t n_threads;
     double a_RT;            /* accuracy parameter of Eq. 11, used when f_U < 0 */
+    int32_t mode_2d;        /* 2D mode (Sect. 3.6): first-octant sources, deposits mirrored */
 } orc_pass_opts;
 
 /* ------------------------------------------------------------------------ */
@@ -219,10 +222,30 @@ void orc_healpix_vec(int64_t nside, int64_t pix, double v[3])
     int64_t jp = ((int64_t)orc_face_phi[face] * nr + ix - iy + 1 + shifted) / 2;
     if (jp > 4 * nr) jp -= 4 * nr;
     if (jp < 1) jp += 4 * nr;
-    double phi = ((double)jp - 0.5 * (double)(1 + shifted)) * (M_PI / 2.0) / (double)nr;
+    /* phi = (pi / 2) num / den: quarter turn q, and the angle m / den of a
+     * quarter turn within it.  cos and sin come from the angle measured from
+     * the nearer axis, so that the mirror images of a pixel (x, y or z
+     * reflected) give exactly the mirrored vector: a mirror-symmetric model
+     * then casts mirror-symmetric rays. */
+    int64_t num = 2 * jp - 1 - shifted, den = 2 * nr;
+    int64_t q = num / den, m = num - q * den;
+    double a, b;
+    if (2 * m < den) {
+        double t = (M_PI / 2.0) * (double)m / (double)den;
+        a = cos(t);
+        b = sin(t);
+    } else if (2 * m > den) {
+        double u = (M_PI / 2.0) * (double)(den - m) / (double)den;
+        a = sin(u);
+        b = cos(u);
+    } else {
+        a = b = sqrt(0.5);
+    }
     double st = sqrt((1.0 - z) * (1.0 + z));
-    v[0] = st * cos(phi);
-    v[1] = st * sin(phi);
+    double x = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
+    double y = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
+    v[0] = st * x;
+    v[1] = st * y;
     v[2] = z;
 }
 
@@ -448,7 +471,7 @@ int orc_model_create(const orc_grid_desc *d, orc_model **out)
     m->point_cell = (int64_t *)malloc(sizeof(int64_t) * (size_t)(d->n_point > 0 ? d->n_point : 1));
     if (!m->point_cell) { orc_model_destroy(m); return ORC_E_OOM; }
     for (int64_t k = 0; k < d->n_point; ++k) {
-        const double up[3] = {0.0, 0.0, 0.0};
+        const double up[3] = {1.0, 1.0, 1.0};   /* a point on a face belongs to the upper side */
         for (int l = 0; l < d->n_lambda; ++l) {
             double v = d->point_lum[(int64_t)l * d->n_point + k];
             if (!(v >= 0.0) || !isfinite(v)) { orc_model_destroy(m); return ORC_E_INVALID; }
@@ -474,7 +497,11 @@ static int orc_fine_index(const orc_model *m, const double p[3], const double d[
         double u = (p[a] - m->d.lo[a]) / m->h_fine;
         double fl = floor(u);
         int64_t i = (fl < -1.0) ? -1 : (fl > (double)m->fine[a]) ? m->fine[a] : (int64_t)fl;
-        if (u == fl && d[a] < 0.0) i -= 1;
+        /* on a plane of the fine grid: the side the direction points to; a
+         * ray lying in the plane (zero component) takes the side away from
+         * the block's central plane, so that mirror-image rays take
+         * mirror-image cells (on the central plane itself: the upper side) */
+        if (u == fl && (d[a] < 0.0 || (d[a] == 0.0 && 2.0 * fl < (double)m->fine[a]))) i -= 1;
         if (i < 0 || i >= m->fine[a]) inside = 0;
         f[a] = i;
     }
@@ -619,6 +646,10 @@ typedef struct {
     int64_t cap;
     double *esc;        /* [n_lambda][nray0] escaping luminosity per launch pixel, or NULL */
     int64_t nray0;
+    int nmir;           /* 8 in 2D mode, else 1 */
+    const int64_t *mir; /* 2D mode: [n][8] the mirror images of each leaf */
+    const int64_t *pmir;/* 2D mode: [sum npix][8] mirror images of the j_sca pixels */
+    const int64_t *emir;/* 2D mode: [nray0][8] mirror images of the launch pixels */
 } orc_thread;
 
 static inline void orc_add(double *p, double v, int atomic)
@@ -774,17 +805,28 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
                 double alpha = d->kappa[l] * d->rho[c];
                 if (sig[l]) {
                     double du = alpha > 0.0 ? ext[l] / (alpha * vol * cl) : L[l] * len / (vol * cl);
-                    orc_add(&th->U[(int64_t)l * d->n_leaves + c], du, th->atomic);
+                    /* 2D mode: the same deposit by each mirror image of the source */
+                    for (int M = 0; M < th->nmir; ++M) {
+                        int64_t cm = th->mir ? th->mir[8 * c + M] : c;
+                        orc_add(&th->U[(int64_t)l * d->n_leaves + cm], du, th->atomic);
+                    }
                     double om = d->albedo[l];
                     th->tally[l * N_TALLY + T_ABSORBED] += (1.0 - om) * ext[l];
                     th->tally[l * N_TALLY + T_SCATTERED] += om * ext[l];
                     th->count[C_DEPOSITS]++;
                     if (o->mode != ORC_STEP1 && om * ext[l] != 0.0) {
                         int64_t npix = 12 * (int64_t)m->nside_sca[l] * m->nside_sca[l];
-                        const double *w = th->w + m->s_offset[l] / d->n_leaves;
-                        double *row = th->S + m->s_offset[l] + c * npix;
+                        int64_t woff = m->s_offset[l] / d->n_leaves;
+                        const double *w = th->w + woff;
                         double ds = om * ext[l];
-                        for (int64_t q = 0; q < npix; ++q) orc_add(&row[q], ds * w[q], th->atomic);
+                        for (int M = 0; M < th->nmir; ++M) {
+                            int64_t cm = th->mir ? th->mir[8 * c + M] : c;
+                            double *row = th->S + m->s_offset[l] + cm * npix;
+                            for (int64_t q = 0; q < npix; ++q) {
+                                int64_t qm = th->pmir ? th->pmir[8 * (woff + q) + M] : q;
+                                orc_add(&row[qm], ds * w[q], th->atomic);
+                            }
+                        }
                     }
                 } else {
                     th->tally[l * N_TALLY + T_SKIPPED] += ext[l];
@@ -801,7 +843,10 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
     if (th->esc) {
         /* attributed to the launch pixel the ray descends from */
         int64_t top = ray->pix >> (2 * ray->level);
-        for (int l = 0; l < nl; ++l) th->esc[(int64_t)l * th->nray0 + top] += L[l];
+        for (int M = 0; M < th->nmir; ++M) {
+            int64_t tm = th->emir ? th->emir[8 * top + M] : top;
+            for (int l = 0; l < nl; ++l) th->esc[(int64_t)l * th->nray0 + tm] += L[l];
+        }
     }
 }
 
@@ -839,6 +884,91 @@ int64_t orc_count_sources(const orc_model *m, int mode, const double *S_pending)
  * [n_lambda][12 nside^2] when not NULL: the luminosity leaving the root block,
  * by the launch pixel of the ray (the initial Nside).  Inputs: S_pending
  * (scatter pass), U_LL (adaptive direct/scatter passes). */
+/*
+ * 2D mode (Sect. 3.6): an axisymmetric model on a Cartesian grid is mirror
+ * symmetric about the three planes through the block centre.  Only the
+ * sources of the first octant (centre above the block centre on every axis)
+ * are traced; every deposit is repeated by the 7 mirror images of the source
+ * into the mirror images of the crossed cell (and of the j_sca pixel, and of
+ * the launch pixel for the escape by direction), and the luminosity tallies
+ * count all 8 sources.  The grid must be mirror symmetric (leaves, density
+ * and emission), with no leaf across a mirror plane, no point sources, no
+ * source mask and the unrotated frame.  Mirror image M (bits 0, 1, 2: x, y, z
+ * reflected) of leaf c is mir[8 c + M].
+ */
+int64_t orc_healpix_pix(int64_t nside, const double v[3]);
+
+static int orc_mirror_tables(const orc_model *m, const orc_pass_opts *o, int64_t nray0, int64_t **mir_out,
+                             int64_t **pmir_out, int64_t **emir_out, uint8_t **first_out)
+{
+    const orc_grid_desc *d = &m->d;
+    const int64_t n = d->n_leaves;
+    const int nl = d->n_lambda;
+    double cb[3];
+    for (int a = 0; a < 3; ++a) cb[a] = d->lo[a] + 0.5 * d->nroot[a] * d->root_size;
+    for (int i = 0; i < 9; ++i)
+        if (o->frame[i] != ((i % 4 == 0) ? 1.0 : 0.0)) return ORC_E_INVALID;
+    if (d->n_point > 0 || o->source_mask) return ORC_E_INVALID;
+    int64_t wsize = m->s_offset[nl] / n;
+    int64_t *mir = (int64_t *)malloc(sizeof(int64_t) * 8 * (size_t)n);
+    int64_t *pmir = (int64_t *)malloc(sizeof(int64_t) * 8 * (size_t)(wsize > 0 ? wsize : 1));
+    int64_t *emir = (int64_t *)malloc(sizeof(int64_t) * 8 * (size_t)nray0);
+    uint8_t *first = (uint8_t *)malloc((size_t)n);
+    int bad = !mir || !pmir || !emir || !first;
+    for (int64_t c = 0; c < n && !bad; ++c) {
+        const double *x = &m->centre[3 * c];
+        first[c] = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (fabs(x[a] - cb[a]) < 0.5 * m->side[c]) bad = 1;   /* across a mirror plane */
+            if (!(x[a] > cb[a])) first[c] = 0;
+        }
+        for (int M = 0; M < 8 && !bad; ++M) {
+            double p[3], dir[3] = {1.0, 1.0, 1.0};
+            for (int a = 0; a < 3; ++a) p[a] = ((M >> a) & 1) ? 2.0 * cb[a] - x[a] : x[a];
+            int64_t cm = orc_locate(m, p, dir);
+            if (cm < 0 || d->level[cm] != d->level[c] || d->rho[cm] != d->rho[c]) {
+                bad = 1;
+                break;
+            }
+            for (int l = 0; l < nl; ++l)
+                if (d->emis[(int64_t)l * n + cm] != d->emis[(int64_t)l * n + c]) bad = 1;
+            mir[8 * c + M] = cm;
+        }
+    }
+    /* mirror images of HEALPix pixels: the pixel holding the reflected centre */
+    for (int pass = 0; pass < 2 && !bad; ++pass) {
+        for (int l = 0; l < (pass == 0 ? nl : 1) && !bad; ++l) {
+            int64_t ns = pass == 0 ? m->nside_sca[l] : o->nside;
+            int64_t np = 12 * ns * ns;
+            int64_t *tab = pass == 0 ? pmir + 8 * (m->s_offset[l] / n) : emir;
+            for (int64_t q = 0; q < np; ++q) {
+                double v[3], w[3], back[3];
+                orc_healpix_vec(ns, q, v);
+                for (int M = 0; M < 8; ++M) {
+                    for (int a = 0; a < 3; ++a) w[a] = ((M >> a) & 1) ? -v[a] : v[a];
+                    int64_t qm = orc_healpix_pix(ns, w);
+                    orc_healpix_vec(ns, qm, back);
+                    for (int a = 0; a < 3; ++a)
+                        if (fabs(back[a] - w[a]) > 1e-12) bad = 1;   /* the pixel set is symmetric */
+                    tab[8 * q + M] = qm;
+                }
+            }
+        }
+    }
+    if (bad) {
+        free(mir);
+        free(pmir);
+        free(emir);
+        free(first);
+        return mir && pmir && emir && first ? ORC_E_INVALID : ORC_E_OOM;
+    }
+    *mir_out = mir;
+    *pmir_out = pmir;
+    *emir_out = emir;
+    *first_out = first;
+    return ORC_OK;
+}
+
 int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pending, const double *U_LL,
                  double *U_k, double *S_next, double *tally, int64_t *counters, double *escape)
 {
@@ -862,6 +992,13 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     /* point sources emit in step 1 and the direct pass; a source mask covers
      * the cells, then the point sources */
     const int64_t n_src_points = o->mode == ORC_SCATTER ? 0 : d->n_point;
+    int64_t nray0_ = 12 * (int64_t)o->nside * o->nside;
+    int64_t *mir = NULL, *pmir = NULL, *emir = NULL;
+    uint8_t *first = NULL;
+    if (o->mode_2d) {
+        int rc = orc_mirror_tables(m, o, nray0_, &mir, &pmir, &emir, &first);
+        if (rc != ORC_OK) return rc;
+    }
     int nthreads = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
     /* private accumulators when they fit comfortably, shared atomics otherwise */
     double per_thread = 8.0 * ((double)nl * n + (o->mode == ORC_STEP1 ? 0.0 : (double)ssize));
@@ -877,7 +1014,13 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     int failed = 0;
     /* j_sca pixel centre vectors, one block per wavelength (rotated frame) */
     double *pv = (double *)malloc(sizeof(double) * 3 * (size_t)(wsize > 0 ? wsize : 1));
-    if (!pv) return ORC_E_OOM;
+    if (!pv) {
+        free(mir);
+        free(pmir);
+        free(emir);
+        free(first);
+        return ORC_E_OOM;
+    }
     for (int l = 0; l < nl; ++l) orc_pixel_table(m->nside_sca[l], o->frame, pv + 3 * (m->s_offset[l] / n));
 
 #pragma omp parallel num_threads(nthreads)
@@ -886,6 +1029,10 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
         memset(&th, 0, sizeof(th));
         th.atomic = atomic;
         th.pv = pv;
+        th.nmir = mir ? 8 : 1;
+        th.mir = mir;
+        th.pmir = pmir;
+        th.emir = emir;
         if (atomic) {
             th.U = U_k;
             th.S = S_next;
@@ -909,6 +1056,7 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
 #pragma omp for schedule(dynamic, 1)
             for (int64_t s = 0; s < n + n_src_points; ++s) {
                 if (o->source_mask && !o->source_mask[s]) continue;
+                if (first && !first[s]) continue;   /* 2D mode: first-octant sources only */
                 /* emitted luminosity of this source */
                 double emitted_any = 0.0;
                 for (int l = 0; l < nl; ++l) {
@@ -967,6 +1115,14 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
         free(th.esc);
     }
     free(pv);
+    if (mir) {
+        /* the tallies of all 8 mirror images of the traced sources */
+        for (int i = 0; i < nl * N_TALLY; ++i) tally[i] *= 8.0;
+        free(mir);
+        free(pmir);
+        free(emir);
+        free(first);
+    }
     return failed ? ORC_E_OOM : ORC_OK;
 }
 
@@ -1174,7 +1330,7 @@ int orc_observe(const orc_model *m, const orc_observer *ob, const double *S_tota
     } else if (ob->kind == 1) {
         if (ob->nside_map <= 0 || !is_pow2(ob->nside_map)) return ORC_E_INVALID;
         npix = 12 * (int64_t)ob->nside_map * ob->nside_map;
-        double up0[3] = {0.0, 0.0, 1.0};
+        double up0[3] = {1.0, 1.0, 1.0};   /* a point on a face belongs to the upper side */
         obs_cell = orc_locate(m, ob->pos, up0);
     } else {
         return ORC_E_INVALID;

@@ -129,6 +129,8 @@ class RayPolicy:
     f_L: float = 0.0            # stop once the pending scattered luminosity is below f_L
                                 # times the total scattered in the direct pass (Sect. 2);
                                 # 0 runs all n_scatter iterations
+    mode_2d: bool = False       # 2D mode (Sect. 3.6): trace the first-octant sources of a
+                                # mirror-symmetric grid, mirror their deposits
 
 
 @dataclasses.dataclass
@@ -200,8 +202,9 @@ def morton_order(level: np.ndarray, ijk: np.ndarray) -> np.ndarray:
     return np.argsort(key, kind="stable")
 
 
-def refine_octree(nroot, lo, root_size, max_level, want_split):
-    """Top-down refinement.  ``want_split(centre[n,3], side[n]) -> bool[n]``.
+def refine_octree(nroot, lo, root_size, max_level, want_split, min_level=0):
+    """Top-down refinement.  ``want_split(centre[n,3], side[n]) -> bool[n]``;
+    cells above ``min_level`` are always split.
 
     Returns (level, ijk) of the leaves in Morton order.
     """
@@ -217,6 +220,8 @@ def refine_octree(nroot, lo, root_size, max_level, want_split):
             split = np.zeros(cur_ijk.shape[0], dtype=bool)
         else:
             split = np.asarray(want_split(centre, np.full(cur_ijk.shape[0], side)), dtype=bool)
+            if level < min_level:
+                split[:] = True
         keep = ~split
         levels.append(np.full(int(keep.sum()), level, dtype=np.int32))
         ijks.append(cur_ijk[keep])
@@ -264,7 +269,8 @@ def plain16(n_lambda: int = 1, n: int = 16, nside: int = 8, n_scatter: int = 2,
 
 def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
                nroot=(5, 5, 1), root_size=6.0, max_level=7, target_leaves=200_000,
-               eps_lum=2e-5, lambdas=DISK_LAMBDAS, tol=0.05, tau_max=None, keep_best=False, peak=False):
+               eps_lum=2e-5, lambdas=DISK_LAMBDAS, tol=0.05, tau_max=None, keep_best=False, peak=False,
+               min_level=0):
     """Double-exponential stars + dust disk on an octree.
 
     A cell is split when its V-band optical depth across it exceeds tau_max or
@@ -274,7 +280,9 @@ def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
     count was closest to the target in ratio).  The split test takes the
     densities at the cell centre, or with ``peak`` at the cell's point nearest
     to the mid-plane and the axis (so that thin disks between two cell
-    centres are still resolved).
+    centres are still resolved).  ``min_level`` = 1 splits every root cube,
+    so that no leaf lies across a plane through the block centre (the grid
+    is then mirror symmetric leaf by leaf, as the 2D mode needs).
     """
     lo = tuple(-0.5 * np.asarray(nroot, dtype=np.float64) * root_size)
     kr0 = tau_v_faceon / (2.0 * hd_z)          # face-on central tau through the plane
@@ -301,7 +309,7 @@ def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
         def want(c, s):
             p = nearest(c, s)
             return (dust(p) * s > tmax) | (4.0 * math.pi * stars(p) * s ** 3 > eps_lum * l_tot)
-        return refine_octree(nroot, lo, root_size, max_level, want)
+        return refine_octree(nroot, lo, root_size, max_level, want, min_level=min_level)
 
     if tau_max is None:
         a, b = 1e-3, 10.0
@@ -341,13 +349,16 @@ def disk_model(h_r=3.0, h_z=0.3, hd_r=4.5, hd_z=0.15, tau_v_faceon=1.0,
 
 
 def disk(target_leaves=200_000, max_level=7, f_U=1e-3, n_scatter=3, nside0=4, nside_max=1024,
-         tau_max=None) -> Workload:
-    grid, tmax = disk_model(target_leaves=target_leaves, max_level=max_level, tau_max=tau_max)
+         tau_max=None, mode_2d=False) -> Workload:
+    """The galaxy disk; ``mode_2d`` splits every root cube (no leaf across a
+    plane through the centre) and runs the 2D mode."""
+    grid, tmax = disk_model(target_leaves=target_leaves, max_level=max_level, tau_max=tau_max,
+                            min_level=1 if mode_2d else 0)
     lo, hi = grid.box()
     r_pre = 0.15 * float(np.max(hi - lo))
     pol = RayPolicy(adaptive=True, nside=nside0, nside_max=nside_max, n_rays_min=4.0, f_U=f_U,
-                    r_pre=r_pre, step1=True, n_scatter=n_scatter)
-    return Workload("disk", grid, pol,
+                    r_pre=r_pre, step1=True, n_scatter=n_scatter, mode_2d=mode_2d)
+    return Workload("disk_2d" if mode_2d else "disk", grid, pol,
                     f"30x30x6 kpc double-exponential disk, {grid.n} octree leaves (tau_max={tmax:.4g}), "
                     f"{grid.n_lambda} wavelengths, adaptive rays Nside {nside0}..{nside_max}, f_U={f_U}")
 
@@ -361,12 +372,13 @@ def disk_small(target_leaves=3000, max_level=4, f_U=1e-3, nside_max=64, n_scatte
     return Workload("disk_small", grid, pol, f"coarse disk octree, {grid.n} leaves")
 
 
-def disk_tiny(target_leaves=600, max_level=3, f_U=1e-3, nside_max=32, n_scatter=2) -> Workload:
+def disk_tiny(target_leaves=600, max_level=3, f_U=1e-3, nside_max=32, n_scatter=2, mode_2d=False) -> Workload:
     """A very coarse disk octree (about 1000 leaves) for adaptive-path parity."""
-    grid, tmax = disk_model(target_leaves=target_leaves, max_level=max_level, eps_lum=1e-3, tol=0.3)
+    grid, tmax = disk_model(target_leaves=target_leaves, max_level=max_level, eps_lum=1e-3, tol=0.3,
+                            min_level=1 if mode_2d else 0)
     lo, hi = grid.box()
     pol = RayPolicy(adaptive=True, nside=4, nside_max=nside_max, n_rays_min=4.0, f_U=f_U,
-                    r_pre=0.15 * float(np.max(hi - lo)), step1=True, n_scatter=n_scatter)
+                    r_pre=0.15 * float(np.max(hi - lo)), step1=True, n_scatter=n_scatter, mode_2d=mode_2d)
     return Workload("disk_tiny", grid, pol, f"very coarse disk octree, {grid.n} leaves")
 
 
