@@ -67,6 +67,7 @@ extern "C" {
                                        if it produced a non-finite U or S value */
 #define DARTRAY_FLAG_CONTINUE 4u    /* DIRECT adds S_next to S_total instead of replacing it: a
                                        run that continues an earlier one (Sect. 3.3) */
+#define DARTRAY_FLAG_2D 8u          /* 2D mode (Sect. 3.6), see below */
 
 /* tally slots, per wavelength, FP64, in luminosity units */
 #define DARTRAY_T_EMITTED 0         /* luminosity launched by the pass's sources */
@@ -173,6 +174,20 @@ typedef struct {
  *   unmasked pass when the other inputs (U_LL, S_pending) are the same.
  * max_steps: per-ray crossing limit (0 = unlimited); rays hitting it stop and
  *   are counted in DARTRAY_C_MAXSTEP.
+ * DARTRAY_FLAG_2D (Sect. 3.6): for a model symmetric under reflection
+ *   across the three planes through the centre of the root block (an
+ *   axisymmetric model on a Cartesian grid is), only the sources of the
+ *   first octant (leaf centre above the block centre on every axis) cast
+ *   rays, and U, S and the escape by direction of each cell, pixel and
+ *   direction become the sum of what those rays left in its 8 mirror
+ *   images; the luminosity tallies count all 8 images of every source, the
+ *   counters the rays actually traced.  Requires: every leaf's mirror images
+ *   are leaves of the same size, density and emission (checked on the
+ *   device when the flag is first used after a change; DARTRAY_E_INVALID
+ *   otherwise), no leaf crosses a mirror plane, no point sources, no
+ *   source_mask, the unrotated frame; not in the adjoint, batches or the
+ *   allocation-free entry point (DARTRAY_E_UNSUPPORTED).  The unrotated
+ *   ray and pixel directions are mirror symmetric bit for bit.
  */
 typedef struct {
     int32_t mode;                /* DARTRAY_MODE_*, for dartray_trace_direct */

@@ -387,13 +387,16 @@ __device__ inline float fast_em1(float tau, bool &thick, float &tr)
 }
 
 // fine-level cell coordinate of position p along an axis with direction
-// component d: on a face, the side d points to (upper side for d == 0)
+// component d and F fine cells: on a face, the side d points to; a ray lying
+// in the face plane (d == 0) takes the side away from the block's central
+// plane, so that mirror-image rays visit mirror-image cells (the upper side
+// on the central plane itself)
 template <typename T>
-__device__ inline int fine_coord(T p, T d)
+__device__ inline int fine_coord(T p, T d, int F)
 {
     const T fl = floor(p);
     int i = (int)fl;
-    if (p == fl && d < T(0)) i -= 1;
+    if (p == fl && (d < T(0) || (d == T(0) && T(2) * fl < T(F)))) i -= 1;
     return i;
 }
 
@@ -460,7 +463,7 @@ __device__ inline int32_t next_leaf(const Geo &g, const RayT<T> &R, const int4 b
         if (a == axis) {
             f[a] = pos ? lo[a] + b.w : lo[a] - 1;
         } else {
-            int q = fine_coord<T>(fma(te, R.n[a], R.o[a]), R.n[a]);
+            int q = fine_coord<T>(fma(te, R.n[a], R.o[a]), R.n[a], g.fine[a]);
             q = q < lo[a] ? lo[a] : q;
             q = q > lo[a] + b.w - 1 ? lo[a] + b.w - 1 : q;
             f[a] = q;
@@ -489,8 +492,8 @@ __global__ void k_debug_cells(Geo g, int nrays, const double *origin, const doub
         R.n[a] = dir[3 * i + a];
         R.inv[a] = 1.0 / R.n[a];
     }
-    int32_t c = locate_fine(g, fine_coord<double>(R.o[0], R.n[0]), fine_coord<double>(R.o[1], R.n[1]),
-                            fine_coord<double>(R.o[2], R.n[2]));
+    int32_t c = locate_fine(g, fine_coord<double>(R.o[0], R.n[0], g.fine[0]), fine_coord<double>(R.o[1], R.n[1], g.fine[1]),
+                            fine_coord<double>(R.o[2], R.n[2], g.fine[2]));
     double t = 0.0;
     int m = 0;
     while (c >= 0 && m < max_cross) {
@@ -1334,9 +1337,9 @@ void k_march_adaptive(const AdaptArgs A)
             } else {
                 // a child starts at its parent's entry distance: mostly inside
                 // the cell where the parent split, which then needs no descent
-                const int fx = fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0]);
-                const int fy = fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1]);
-                const int fz = fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2]);
+                const int fx = fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0], A.geo.fine[0]);
+                const int fy = fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1], A.geo.fine[1]);
+                const int fz = fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2], A.geo.fine[2]);
                 const int32_t cp = st_c[depth];
                 const int4 pb = A.geo.rec[cp].box;
                 const bool inside = fx >= pb.x && fx < pb.x + pb.w && fy >= pb.y && fy < pb.y + pb.w &&
@@ -2247,7 +2250,7 @@ static void free_grid(Grid &g)
 {
     for (hipEvent_t e : g.ev_pool) (void)hipEventDestroy(e);
     g.ev_pool.clear();
-    void *ptrs[] = {g.dust_word, g.ps_pos, g.ps_xyz, g.ps_cell, g.ps_lum, g.ps_lum64, g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
+    void *ptrs[] = {g.mir, g.first, g.reps, g.pmir, g.esc_tmp, g.dust_word, g.ps_pos, g.ps_xyz, g.ps_cell, g.ps_lum, g.ps_lum64, g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
                     g.own.flags, g.cell_flag, g.own.src_list, g.own.scan_blocks, g.own.n_src, g.own.dsum, g.s1_sum, g.own.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
                     g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
@@ -2547,6 +2550,8 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         dalloc(g, &g.sbar[0], (size_t)lt.s_off[nl]), dalloc(g, &g.sbar[1], (size_t)lt.s_off[nl]),
         dalloc(g, &g.emis_lum, (size_t)(nl * n)), dalloc(g, &g.lum64, (size_t)(nl * n)), dalloc(g, &g.root_tab, (size_t)nroot),
         dalloc(g, &g.own.n_all, 1), dalloc(g, &g.own.err_word, 1), dalloc(g, &g.dust_word, 2),
+        dalloc(g, &g.mir, (size_t)n * 8), dalloc(g, &g.first, (size_t)n), dalloc(g, &g.reps, (size_t)(n / 8 + 1)),
+        dalloc(g, &g.pmir, (size_t)entry_of(32, 0) * 8), dalloc(g, &g.esc_tmp, (size_t)nl * 12 * 16 * 16),
         dalloc(g, &g.ps_pos, (size_t)std::max(np, 1)), dalloc(g, &g.ps_xyz, (size_t)std::max(np, 1)), dalloc(g, &g.ps_cell, (size_t)std::max(np, 1)),
         dalloc(g, &g.ps_lum, (size_t)std::max<int64_t>(1, (int64_t)np * nl)),
         dalloc(g, &g.ps_lum64, (size_t)std::max<int64_t>(1, (int64_t)np * nl)),
@@ -2740,6 +2745,7 @@ int dartray_grid_set_rho(dartray_grid *grid, const float *rho_device)
     hipLaunchKernelGGL(k_set_rho, dim3((unsigned)std::min<int64_t>((g.n + 255) / 256, 4096)), dim3(256), 0, g.stream,
                        g.rec, g.rho, rho_device, g.n);
     DR_LAUNCH_CHECK("k_set_rho");
+    g.mirror_ok = false;
     return DARTRAY_OK;
 }
 
@@ -2819,6 +2825,17 @@ static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_
         if (o->adaptive && !f->U_LL) return fail(DARTRAY_E_INVALID, "adaptive passes need U_LL");
     }
     if (o->nside > g.nside_cap) return fail(DARTRAY_E_INVALID, "nside above the grid's nside_max");
+    if (o->flags & DARTRAY_FLAG_2D) {
+        bool ident = true, zero = true;
+        for (int i = 0; i < 9; ++i) {
+            ident &= o->frame[i] == ((i % 4 == 0) ? 1.0 : 0.0);
+            zero &= o->frame[i] == 0.0;
+        }
+        if (!(ident || zero)) return fail(DARTRAY_E_UNSUPPORTED, "2D mode needs the unrotated frame");
+        if (o->source_mask) return fail(DARTRAY_E_UNSUPPORTED, "2D mode selects its own sources (no source_mask)");
+        if (g.n_point > 0) return fail(DARTRAY_E_UNSUPPORTED, "2D mode: no point sources");
+        if (f->escape && !o->adaptive && o->nside > 16) return fail(DARTRAY_E_UNSUPPORTED, "2D mode: escape by direction up to Nside 16");
+    }
     if (o->adaptive) {
         if (o->nside_max < o->nside || (o->nside_max & (o->nside_max - 1)) || o->nside_max > g.nside_cap)
             return fail(DARTRAY_E_INVALID, "adaptive nside_max must be a power of two in [nside, grid nside_max]");
@@ -3299,6 +3316,211 @@ static int finish_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, 
     return DARTRAY_OK;
 }
 
+// ---------------------------------------------------------------------------
+// 2D mode (Sect. 3.6): a model symmetric across the three planes through
+// the block centre.  The first octant's sources are traced as usual; then
+// every orbit {M c} of cells (and {(M c, M p)} of cells and scattered-light
+// pixels, {M d} of escape directions) takes the sum of what the traced rays
+// left over the orbit, which is what the 7 mirror images of each traced
+// source would have left there.  Orbits are disjoint, so each thread owns
+// one and the folds run in place, summing in FP64 in a fixed order.
+// ---------------------------------------------------------------------------
+
+__global__ void k_mirror_check(const int32_t *mir, const float *rho, const float *emis_lum, int64_t n, int nl,
+                               uint32_t *bad)
+{
+    bool b = false;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        for (int M = 1; M < 8; ++M) {
+            const int32_t m = mir[8 * c + M];
+            b |= rho[m] != rho[c];
+            for (int l = 0; l < nl; ++l) b |= emis_lum[(int64_t)l * n + m] != emis_lum[(int64_t)l * n + c];
+        }
+    }
+    if (__ballot(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+// U_k [n][nl]
+__global__ void k_mirror_u(double *U_k, const int32_t *mir, const int32_t *reps, int64_t n_reps, int nl)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_reps * nl;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = reps[i / nl];
+        const int l = (int)(i % nl);
+        int32_t cm[8];
+        double v = 0.0;
+        for (int M = 0; M < 8; ++M) {
+            cm[M] = mir[8 * r + M];
+            v += U_k[(int64_t)cm[M] * nl + l];
+        }
+        for (int M = 0; M < 8; ++M) U_k[(int64_t)cm[M] * nl + l] = v;
+    }
+}
+
+// the block of wavelength blockIdx.y of an S array
+__global__ void k_mirror_s(float *S, const LambdaTable *lt, const int32_t *mir, const int32_t *reps, int64_t n_reps,
+                           const int32_t *pmir)
+{
+    const int l = blockIdx.y;
+    const int np = lt->npix[l];
+    const int64_t e0 = entry_of(lt->nside_sca[l], 0);
+    float *blk = S + lt->s_off[l];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_reps * np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = reps[i / np];
+        const int64_t p = i % np;
+        int64_t at[8];
+        double v = 0.0;
+        for (int M = 0; M < 8; ++M) {
+            at[M] = (int64_t)mir[8 * r + M] * np + pmir[8 * (e0 + p) + M];
+            v += (double)blk[at[M]];
+        }
+        const float f = (float)v;
+        for (int M = 0; M < 8; ++M) blk[at[M]] = f;
+    }
+}
+
+// escape by direction [nl][12 nside^2], from a copy
+__global__ void k_mirror_esc(double *esc, const double *tmp, int nl, int nside, const int32_t *pmir)
+{
+    const int64_t np = 12 * (int64_t)nside * nside;
+    const int64_t e0 = entry_of(nside, 0);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np * nl; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = i / np, p = i % np;
+        double v = 0.0;
+        for (int M = 0; M < 8; ++M) v += tmp[l * np + pmir[8 * (e0 + p) + M]];
+        esc[i] = v;
+    }
+}
+
+// the luminosity tallies the march counted for the traced sources, for all 8 images
+__global__ void k_tally_x8(double *tally, int nl)
+{
+    const int l = threadIdx.x;
+    if (l >= nl) return;
+    const int cols[4] = {DARTRAY_T_EMITTED, DARTRAY_T_ESCAPED, DARTRAY_T_CUT, DARTRAY_T_SKIPPED};
+    for (int k = 0; k < 4; ++k) tally[l * DARTRAY_N_TALLY + cols[k]] *= 8.0;
+}
+
+// Mirror tables (on first use) and the symmetry of density and emission
+// (after every change of either).  Synchronises.
+static int ensure_mirror(Grid &g)
+{
+    if (!g.mirror_geo) {
+        const int64_t n = g.n;
+        for (int a = 0; a < 3; ++a)
+            if (g.fine[a] >= (1 << 21)) return fail(DARTRAY_E_UNSUPPORTED, "2D mode: grid above 2^21 finest cells per axis");
+        std::vector<int4> box((size_t)n);
+        DR_HIP(hipMemcpyAsync(box.data(), g.leaf_box, sizeof(int4) * n, hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipStreamSynchronize(g.stream));
+        // leaves tile the block, so a lower corner names one leaf
+        auto key = [](int64_t x, int64_t y, int64_t z) { return (uint64_t)x | ((uint64_t)y << 21) | ((uint64_t)z << 42); };
+        std::unordered_map<uint64_t, int32_t> at;
+        at.reserve((size_t)n * 2);
+        for (int64_t c = 0; c < n; ++c) at.emplace(key(box[c].x, box[c].y, box[c].z), (int32_t)c);
+        std::vector<int32_t> mir((size_t)n * 8), reps;
+        std::vector<uint8_t> first((size_t)n);
+        for (int64_t c = 0; c < n; ++c) {
+            const int4 b = box[c];
+            const int64_t lo[3] = {b.x, b.y, b.z};
+            bool up = true;
+            for (int a = 0; a < 3; ++a) {
+                const int64_t F = g.fine[a];
+                if (2 * lo[a] < F && F < 2 * (lo[a] + b.w))
+                    return fail(DARTRAY_E_INVALID, "2D mode: a leaf lies across a plane through the block centre");
+                up &= 2 * lo[a] + b.w > F;
+            }
+            first[c] = up ? 1 : 0;
+            if (up) reps.push_back((int32_t)c);
+            for (int M = 0; M < 8; ++M) {
+                int64_t q[3];
+                for (int a = 0; a < 3; ++a) q[a] = ((M >> a) & 1) ? g.fine[a] - lo[a] - b.w : lo[a];
+                auto it = at.find(key(q[0], q[1], q[2]));
+                if (it == at.end() || box[it->second].w != b.w)
+                    return fail(DARTRAY_E_INVALID, "2D mode: the leaves are not mirror symmetric");
+                mir[(size_t)c * 8 + M] = it->second;
+            }
+        }
+        if ((int64_t)reps.size() * 8 != n) return fail(DARTRAY_E_INVALID, "2D mode: the leaves are not mirror symmetric");
+        // mirror images of the pixels, Nside 1 .. 16: the pixel holding the
+        // reflected centre, which is that pixel's own centre bit for bit
+        const int64_t ne = entry_of(32, 0);
+        std::vector<int32_t> pm((size_t)ne * 8);
+        const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        for (int64_t N = 1; N <= 16; N *= 2)
+            for (int64_t p = 0; p < 12 * N * N; ++p) {
+                double v[3], w[3], back[3];
+                dr_pix_vec(N, p, I, v);
+                for (int M = 0; M < 8; ++M) {
+                    for (int a = 0; a < 3; ++a) w[a] = ((M >> a) & 1) ? -v[a] : v[a];
+                    const int64_t q = dr_vec_pix(N, w);
+                    dr_pix_vec(N, q, I, back);
+                    if (back[0] != w[0] || back[1] != w[1] || back[2] != w[2])
+                        return fail(DARTRAY_E_DEVICE, "2D mode: pixel set not mirror symmetric");
+                    pm[(size_t)(entry_of(N, p) * 8 + M)] = (int32_t)q;
+                }
+            }
+        DR_HIP(hipMemcpyAsync(g.mir, mir.data(), sizeof(int32_t) * mir.size(), hipMemcpyHostToDevice, g.stream));
+        DR_HIP(hipMemcpyAsync(g.first, first.data(), (size_t)n, hipMemcpyHostToDevice, g.stream));
+        DR_HIP(hipMemcpyAsync(g.reps, reps.data(), sizeof(int32_t) * reps.size(), hipMemcpyHostToDevice, g.stream));
+        DR_HIP(hipMemcpyAsync(g.pmir, pm.data(), sizeof(int32_t) * pm.size(), hipMemcpyHostToDevice, g.stream));
+        DR_HIP(hipStreamSynchronize(g.stream));
+        g.n_reps = (int64_t)reps.size();
+        g.mirror_geo = true;
+    }
+    if (!g.mirror_ok) {
+        int rc = fill<uint32_t>(g, g.w.err_word, 1, 0u);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_mirror_check, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((g.n + 255) / 256, 4096))),
+                           dim3(256), 0, g.stream, g.mir, g.rho, g.emis_lum, g.n, g.n_lambda, g.w.err_word);
+        DR_LAUNCH_CHECK("k_mirror_check");
+        uint32_t bad = 0;
+        DR_HIP(hipMemcpyAsync(&bad, g.w.err_word, sizeof(bad), hipMemcpyDeviceToHost, g.stream));
+        DR_HIP(hipStreamSynchronize(g.stream));
+        if (bad) return fail(DARTRAY_E_INVALID, "2D mode: density or emission not mirror symmetric");
+        g.mirror_ok = true;
+    }
+    return DARTRAY_OK;
+}
+
+// the opts a 2D-mode pass runs with: the first octant as the source mask
+static int prepare_2d(Grid &g, const dartray_trace_opts *o, dartray_trace_opts &o2)
+{
+    int rc = ensure_mirror(g);
+    if (rc) return rc;
+    o2 = *o;
+    o2.source_mask = g.first;
+    return DARTRAY_OK;
+}
+
+// after the march of a 2D-mode pass, before finish_pass
+static int fold_2d(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
+{
+    const int nl = g.n_lambda;
+    const unsigned ub = (unsigned)std::max<int64_t>(1, std::min<int64_t>((g.n_reps * nl + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_mirror_u, dim3(ub), dim3(256), 0, g.stream, g.w.U_k, g.mir, g.reps, g.n_reps, nl);
+    DR_LAUNCH_CHECK("k_mirror_u");
+    const bool step1 = !scatter && o->mode == DARTRAY_MODE_STEP1;
+    if (!step1) {
+        int64_t widest = 0;
+        for (int l = 0; l < nl; ++l) widest = std::max<int64_t>(widest, g.lt.npix[l]);
+        const unsigned sb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((g.n_reps * widest + 255) / 256, 2048));
+        hipLaunchKernelGGL(k_mirror_s, dim3(sb, nl), dim3(256), 0, g.stream, f->S_next, g.d_lt, g.mir, g.reps,
+                           g.n_reps, g.pmir);
+        DR_LAUNCH_CHECK("k_mirror_s");
+    }
+    if (f->escape && !o->adaptive) {
+        const int64_t ne = (int64_t)nl * 12 * o->nside * o->nside;
+        DR_HIP(hipMemcpyAsync(g.esc_tmp, g.w.esc64, sizeof(double) * ne, hipMemcpyDeviceToDevice, g.stream));
+        hipLaunchKernelGGL(k_mirror_esc, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, g.stream, g.w.esc64,
+                           (const double *)g.esc_tmp, nl, o->nside, g.pmir);
+        DR_LAUNCH_CHECK("k_mirror_esc");
+    }
+    hipLaunchKernelGGL(k_tally_x8, dim3(1), dim3(64), 0, g.stream, f->tally, nl);
+    DR_LAUNCH_CHECK("k_tally_x8");
+    return DARTRAY_OK;
+}
+
 // Read the pass's device error word (synchronises the stream).
 static int check_err(Grid &g)
 {
@@ -3319,10 +3541,15 @@ int dartray_trace_direct(dartray_grid *grid, const dartray_trace_opts *opts, dar
     Grid &g = grid->g;
     int rc = check_opts(g, opts, fields, false);
     if (rc) return rc;
-    rc = opts->adaptive ? run_adaptive_pass(g, opts, fields, false) : run_fixed_pass(g, opts, fields, false);
+    dartray_trace_opts o2;
+    const bool two_d = (opts->flags & DARTRAY_FLAG_2D) != 0;
+    if (two_d && (rc = prepare_2d(g, opts, o2))) return rc;
+    const dartray_trace_opts *o = two_d ? &o2 : opts;
+    rc = o->adaptive ? run_adaptive_pass(g, o, fields, false) : run_fixed_pass(g, o, fields, false);
     if (rc) return rc;
-    if ((rc = finish_pass(g, opts, fields, false))) return rc;
-    if ((opts->flags & DARTRAY_FLAG_CHECK) || opts->adaptive) return check_err(g);
+    if (two_d && (rc = fold_2d(g, o, fields, false))) return rc;
+    if ((rc = finish_pass(g, o, fields, false))) return rc;
+    if ((o->flags & DARTRAY_FLAG_CHECK) || o->adaptive) return check_err(g);
     return DARTRAY_OK;
 }
 
@@ -3332,9 +3559,14 @@ int dartray_scatter_iter(dartray_grid *grid, const dartray_trace_opts *opts, dar
     Grid &g = grid->g;
     int rc = check_opts(g, opts, fields, true);
     if (rc) return rc;
-    rc = opts->adaptive ? run_adaptive_pass(g, opts, fields, true) : run_fixed_pass(g, opts, fields, true);
+    dartray_trace_opts o2;
+    const bool two_d = (opts->flags & DARTRAY_FLAG_2D) != 0;
+    if (two_d && (rc = prepare_2d(g, opts, o2))) return rc;
+    const dartray_trace_opts *o = two_d ? &o2 : opts;
+    rc = o->adaptive ? run_adaptive_pass(g, o, fields, true) : run_fixed_pass(g, o, fields, true);
     if (rc) return rc;
-    if ((rc = finish_pass(g, opts, fields, true))) return rc;
+    if (two_d && (rc = fold_2d(g, o, fields, true))) return rc;
+    if ((rc = finish_pass(g, o, fields, true))) return rc;
     if (r_k) {
         const int nl = g.n_lambda;
         double a[kMaxLambda], b[kMaxLambda];
@@ -3363,6 +3595,7 @@ int dartray_trace_adjoint(dartray_grid *grid, const dartray_trace_opts *opts, in
     for (int k = 0; k < n_scatter; ++k)
         if (!S_hist[k]) return fail(DARTRAY_E_INVALID, "null S_hist entry");
     if (opts->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "the adjoint covers fixed rays only");
+    if (opts->flags & DARTRAY_FLAG_2D) return fail(DARTRAY_E_UNSUPPORTED, "the adjoint has no 2D mode");
     if (opts->nside <= 0 || (opts->nside & (opts->nside - 1)) || opts->nside > kMaxNsideWTable)
         return fail(DARTRAY_E_INVALID, "adjoint nside must be a power of two <= 16");
     if (g.n_lambda > 8) return fail(DARTRAY_E_UNSUPPORTED, "the adjoint carries at most 8 wavelengths");
@@ -3685,6 +3918,7 @@ int dartray_batch_run(dartray_batch *b, const dartray_trace_opts *opts, dartray_
                       int32_t n_scatter)
 {
     if (!b) return fail(DARTRAY_E_INVALID, "null batch");
+    if (opts && (opts->flags & DARTRAY_FLAG_2D)) return fail(DARTRAY_E_UNSUPPORTED, "batches have no 2D mode");
     if (n_scatter < 0) return fail(DARTRAY_E_INVALID, "n_scatter must be >= 0");
     int rc = dr::batch_prepare(b, opts, fields, b->caller);
     if (rc) return rc;
@@ -3695,6 +3929,7 @@ int dartray_batch_capture(dartray_batch *b, const dartray_trace_opts *opts, dart
                           int32_t n_scatter)
 {
     if (!b) return fail(DARTRAY_E_INVALID, "null batch");
+    if (opts && (opts->flags & DARTRAY_FLAG_2D)) return fail(DARTRAY_E_UNSUPPORTED, "batches have no 2D mode");
     if (n_scatter < 0) return fail(DARTRAY_E_INVALID, "n_scatter must be >= 0");
     int rc = dr::batch_prepare(b, opts, fields, b->caller);
     if (rc) return rc;
@@ -3837,6 +4072,7 @@ int dartray_trace_direct_noalloc(dartray_grid *grid, const dartray_trace_opts *o
     if (rc) return rc;
     if (opts->adaptive || opts->mode != DARTRAY_MODE_DIRECT)
         return fail(DARTRAY_E_UNSUPPORTED, "the allocation-free direct pass covers fixed rays only");
+    if (opts->flags & DARTRAY_FLAG_2D) return fail(DARTRAY_E_UNSUPPORTED, "the allocation-free direct pass has no 2D mode");
     if (opts->nside > kMaxNsideWTable) return fail(DARTRAY_E_UNSUPPORTED, "fixed-mode nside above 16");
     int prev = 0;
     DR_HIP(hipGetDevice(&prev));
@@ -4320,6 +4556,7 @@ static int dust_update(Grid &g, DustArgs D, double *ratio)
 
 static void set_emis(Grid &g, const double *j)
 {
+    g.mirror_ok = false;
     hipLaunchKernelGGL(k_set_emis, dim3(sweep_blocks((int64_t)g.n_lambda * g.n)), dim3(256), 0, g.stream, j, g.leaf_box,
                        g.h_fine, g.n, g.n_lambda, g.emis_lum, g.lum64);
 }

@@ -128,6 +128,15 @@ struct Grid {
     bool wtab_valid = false;
     unsigned long long *queue = nullptr;  // work counter of the adaptive march
     unsigned long long *dust_word = nullptr;  // [2] dust emission: max dj / j_prev (FP64 bits), bracket overflow
+    // 2D mode (mirror symmetry through the block centre), built on first use
+    bool mirror_geo = false;              // leaf and pixel mirror tables built
+    bool mirror_ok = false;               // density and emission checked symmetric since the last change
+    int32_t *mir = nullptr;               // [n][8] mirror image M (bits x, y, z) of each leaf
+    uint8_t *first = nullptr;             // [n] 1 for the leaves of the first octant
+    int32_t *reps = nullptr;              // [n / 8] the first-octant leaves
+    int64_t n_reps = 0;
+    int32_t *pmir = nullptr;              // [direction entry][8] mirror images of the HEALPix pixels, Nside <= 16
+    double *esc_tmp = nullptr;            // [nl][12 * 16^2] escape by direction before folding
 
     // deposit log of the adaptive passes that scatter light: one tuple
     // (cell, direction entry, per-wavelength energy-density deposit) per
@@ -185,8 +194,9 @@ __host__ __device__ inline uint32_t dr_compact_bits(uint64_t v)
     return (uint32_t)v;
 }
 
-// Centre of nested pixel `pix` at resolution `nside`, as (z, phi).
-__host__ __device__ inline void dr_pix_zphi(int64_t nside, int64_t pix, double *z_out, double *phi_out)
+// Centre of nested pixel `pix` at resolution `nside`: z, and the longitude
+// as the fraction num / den of a quarter turn.
+__host__ __device__ inline void dr_pix_zq(int64_t nside, int64_t pix, double *z_out, int64_t *num, int64_t *den)
 {
     // base pixels are numbered 0..11: four around the north pole, four on
     // the equator, four around the south pole
@@ -222,15 +232,37 @@ __host__ __device__ inline void dr_pix_zphi(int64_t nside, int64_t pix, double *
     if (j > 4 * q) j -= 4 * q;
     if (j < 1) j += 4 * q;
     *z_out = z;
-    *phi_out = ((double)j - 0.5 * (double)(1 + half_shift)) * (0.5 * dr::kPi) / (double)q;
+    *num = 2 * j - 1 - half_shift;                   // phi = (pi / 2) num / den
+    *den = 2 * q;
 }
 
+// Unit vector of nested pixel `pix`, rotated by R.  cos and sin of the
+// longitude come from the angle to the nearest axis of its quarter turn, so
+// that reflecting the direction across the x, y or z plane gives exactly the
+// vector of the reflected pixel (the unrotated direction set is then
+// mirror symmetric bit for bit).
 __host__ __device__ inline void dr_pix_vec(int64_t nside, int64_t pix, const double *R, double v[3])
 {
-    double z, phi;
-    dr_pix_zphi(nside, pix, &z, &phi);
+    double z;
+    int64_t num, den;
+    dr_pix_zq(nside, pix, &z, &num, &den);
+    const int64_t quarter = num / den, m = num - quarter * den;
+    double c, s;
+    if (2 * m < den) {
+        const double t = (0.5 * dr::kPi) * (double)m / (double)den;
+        c = cos(t);
+        s = sin(t);
+    } else if (2 * m > den) {
+        const double t = (0.5 * dr::kPi) * (double)(den - m) / (double)den;
+        c = sin(t);
+        s = cos(t);
+    } else {
+        c = s = sqrt(0.5);
+    }
     const double st = sqrt((1.0 - z) * (1.0 + z));
-    const double a[3] = {st * cos(phi), st * sin(phi), z};
+    const double cx = quarter == 0 ? c : quarter == 1 ? -s : quarter == 2 ? -c : s;
+    const double cy = quarter == 0 ? s : quarter == 1 ? c : quarter == 2 ? -s : -c;
+    const double a[3] = {st * cx, st * cy, z};
     for (int i = 0; i < 3; ++i) v[i] = R[3 * i] * a[0] + R[3 * i + 1] * a[1] + R[3 * i + 2] * a[2];
 }
 

@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(PKG, "libdartray.so")
 OK, E_INVALID, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 MODE_STEP1, MODE_DIRECT = 0, 1
 PROF_FIXED, PROF_STEP1, PROF_SCATTERING, PROF_ADJOINT, PROF_ALL = 1, 2, 4, 8, 15
-FLAG_COUNTERS, FLAG_CHECK = 1, 2
+FLAG_COUNTERS, FLAG_CHECK, FLAG_CONTINUE, FLAG_2D = 1, 2, 4, 8
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
 C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)
 
@@ -445,7 +445,8 @@ def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=T
     fr = np.zeros(9) if frame is None else np.asarray(frame, dtype=np.float64).ravel()
     o.frame = (C.c_double * 9)(*fr.tolist())
     o.source_mask = None if source_mask is None else source_mask.data_ptr()
-    o.flags = (FLAG_COUNTERS if counters else 0) | (FLAG_CHECK if check else 0)
+    o.flags = (FLAG_COUNTERS if counters else 0) | (FLAG_CHECK if check else 0) | \
+        (FLAG_2D if getattr(policy, "mode_2d", False) else 0)
     o.max_steps = int(max_steps)
     return o
 
