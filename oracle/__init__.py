@@ -27,7 +27,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 STEP1, DIRECT, SCATTER = 0, 1, 2
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
-C_CROSS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)
+C_CROSS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, C_MERGES = range(9)
 
 
 def build(force: bool = False) -> str:
@@ -81,6 +81,7 @@ class PassOpts(C.Structure):
         ("n_threads", C.c_int32),
         ("a_RT", C.c_double),
         ("mode_2d", C.c_int32),
+        ("n_rays_max", C.c_double),
     ]
 
 
@@ -347,7 +348,7 @@ class Model:
         U_k = np.zeros(self.nl * self.n)
         S_next = np.zeros(max(self.s_size, 1))
         tally = np.zeros(self.nl * 8)
-        counters = np.zeros(8, dtype=np.int64)
+        counters = np.zeros(16, dtype=np.int64)
         nray0 = 12 * int(policy.nside) ** 2
         escape = np.zeros(self.nl * nray0)
         Sp = None if S_pending is None else np.ascontiguousarray(S_pending, dtype=np.float64)
@@ -381,6 +382,7 @@ def _opts(mode, policy, frame=None, source_mask=None, n_threads=0):
         o.source_mask = _p(keep, C.c_uint8)
     o.n_threads = int(n_threads)
     o.mode_2d = 1 if getattr(policy, "mode_2d", False) else 0
+    o.n_rays_max = float(getattr(policy, "n_rays_max", 0.0))
     return o, keep
 
 
@@ -426,7 +428,7 @@ class PassResult:
     U: np.ndarray          # [nl, n]
     S: np.ndarray          # [S size]
     tally: np.ndarray      # [nl, 8]
-    counters: np.ndarray   # [8]
+    counters: np.ndarray   # [16] (C_* slots; the rest zero)
     escape: np.ndarray     # [nl, 12 nside^2] escaping luminosity by launch pixel
 
 

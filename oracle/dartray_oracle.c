@@ -21,7 +21,8 @@
  * step 1 the block test is replaced by the fixed extent R_pre (caption of the
  * ray-density flowchart figure).  Multi-wavelength rays are blocked only when
  * negligible at every wavelength and skip deposits at negligible wavelengths
- * (Sect. 3.2).  Ray merging (Eq. 3) is not part of this oracle.  Observer
+ * (Sect. 3.2).  With N_rays^max set, rays whose beam is too small for the
+ * crossed cell pause in a low list and four siblings merge (Eq. 3).  Observer
  * maps, point sources (Sect. 2, Sect. 3.6) and the dust emission of the
  * self-heating loop (Sect. 3.3) close the file.
  *
@@ -65,6 +66,17 @@
  *    block decision; the ray's distance is not advanced, so the rounding
  *    residue folds into the next segment.  The forward passes and the
  *    adjoint walk rays with this same rule (orc_is_graze);
+ *  - ray merging (Eq. 3 and the text after it): a ray below the launch
+ *    resolution, outside its source's cell, whose beam is smaller than
+ *    Omega_INT / N_rays^max pauses before the crossing (nothing deposited);
+ *    the four children of one split that all pause having crossed the same
+ *    grid plane merge into one ray in the parent pixel carrying the sum of
+ *    their luminosities (the average intensity of a four times wider beam)
+ *    from the mean of their distances, and the parent's walk continues with
+ *    it; paused children of a group that does not merge continue from where
+ *    they stopped and no longer pause.  Merging never goes below the launch
+ *    Nside, and N_rays^max >= 4 N_rays so that a merged beam is not at once
+ *    too large;
  *  - outputs beyond the paper: the luminosity a ray carries out of the root
  *    block, by the launch pixel it descends from, and the adjoint of
  *    fixed-ray passes (orc_adjoint_pass).
@@ -93,6 +105,12 @@
  *    rays and their children, luminosity balance with cut and skipped terms,
  *    the fixed-ray limit, every ray ending once, the step-1 extent, and Eq. 11
  *    (N_s counted independently; the a_RT 0.05 / 0.005 property of Sect. 5);
+ *  - orc_split (merging): brute force of every ray of a source on an octree
+ *    where rays split and merge (U, S, counts), no pauses reproducing the
+ *    unmerged run, balance and every ray ending once with merges, 2D mode
+ *    equal to 3D with merging;
+ *  - 2D mode (orc_mirror_tables): mirror-exact pixel vectors, 3D passes of
+ *    symmetric models symmetric, 2D passes equal to 3D passes;
  *  - orc_adjoint_pass: central differences on every cell (also in a frame
  *    with near-ties), a dot-product test, zero gradient at the target;
  *  - orc_healpix_pix, orc_observe: an independent ang2pix and the round trip
@@ -121,7 +139,7 @@
 
 enum { ORC_STEP1 = 0, ORC_DIRECT = 1, ORC_SCATTER = 2 };
 enum { T_EMITTED = 0, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED, N_TALLY = 8 };
-enum { C_CROSS = 0, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, N_COUNT = 8 };
+enum { C_CROSS = 0, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, C_MERGES, N_COUNT = 16 };
 
 typedef struct {
     int32_t nroot[3];
@@ -172,6 +190,7 @@ typedef struct {
     int32_t n_threads;
     double a_RT;            /* accuracy parameter of Eq. 11, used when f_U < 0 */
     int32_t mode_2d;        /* 2D mode (Sect. 3.6): first-octant sources, deposits mirrored */
+    double n_rays_max;      /* N_rays^max of Eq. 3 (ray merging); 0: no merging */
 } orc_pass_opts;
 
 /* ------------------------------------------------------------------------ */
@@ -528,7 +547,17 @@ int64_t orc_locate(const orc_model *m, const double p[3], const double d[3])
  * exit face that contains the exit point: on the exit axis its index follows
  * from the leaf's integer coordinates, on the other axes the exit point is
  * located and kept within the leaf's own extent. */
+static int64_t orc_step_axis(const orc_model *m, int64_t c, const double o[3], const double d[3], double *t_exit,
+                             int *exit_axis);
+
 static int64_t orc_step(const orc_model *m, int64_t c, const double o[3], const double d[3], double *t_exit)
+{
+    int axis;
+    return orc_step_axis(m, c, o, d, t_exit, &axis);
+}
+
+static int64_t orc_step_axis(const orc_model *m, int64_t c, const double o[3], const double d[3], double *t_exit,
+                             int *exit_axis)
 {
     double lo[3], hi[3];
     int64_t span = (int64_t)1 << (m->max_level - m->d.level[c]);
@@ -546,6 +575,7 @@ static int64_t orc_step(const orc_model *m, int64_t c, const double o[3], const 
         if (t < best) { best = t; axis = a; }
     }
     *t_exit = best;
+    *exit_axis = axis;
     double p[3];
     int64_t f[3];
     for (int a = 0; a < 3; ++a) p[a] = o[a] + best * d[a];
@@ -627,13 +657,6 @@ int64_t orc_crossings(const orc_model *m, const double o[3], const double d[3], 
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    int32_t level;      /* HEALPix level relative to the initial Nside */
-    int64_t pix;        /* nested pixel at Nside = nside0 << level */
-    double t_start;     /* distance already crossed from the source */
-    double *L;          /* [n_lambda] luminosity carried */
-} orc_ray;
-
-typedef struct {
     double *U;          /* private or shared accumulators */
     double *S;
     int atomic;
@@ -641,9 +664,6 @@ typedef struct {
     int64_t count[N_COUNT];
     double *w;          /* [sum npix] weights of the current ray */
     const double *pv;   /* [sum npix][3] j_sca pixel vectors of each wavelength's block */
-    orc_ray *stack;
-    double *lbuf;
-    int64_t cap;
     double *esc;        /* [n_lambda][nray0] escaping luminosity per launch pixel, or NULL */
     int64_t nray0;
     int nmir;           /* 8 in 2D mode, else 1 */
@@ -712,39 +732,130 @@ static int64_t orc_source_cell(const orc_model *m, int64_t s)
     return s < m->d.n_leaves ? s : m->point_cell[s - m->d.n_leaves];
 }
 
-/* Follow one ray until it escapes, is blocked or is split. */
-static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double *U_LL,
-                       int64_t s, orc_ray *ray, orc_thread *th, int64_t *stack_n)
+/* A ray paused in the low list (Eq. 3): the cell it was about to cross,
+ * the entry distance there, the grid plane it crossed to enter that cell
+ * (axis -1: none, it started inside) and its luminosity. */
+typedef struct {
+    int64_t c;
+    double t;
+    int axis;
+    double plane;
+    double L[64];
+} orc_low;
+
+static int orc_follow(const orc_model *m, const orc_pass_opts *o, const double *U_LL, int64_t s, int level,
+                      int64_t pix, double t_start, int64_t start_cell, const double *L_in, int can_low,
+                      orc_thread *th, orc_low *low);
+
+/* the j_sca weights w(p | n) of a ray along n, per wavelength block */
+static void orc_ray_weights(const orc_model *m, const orc_pass_opts *o, const double n[3], orc_thread *th)
+{
+    if (o->mode == ORC_STEP1) return;
+    for (int l = 0; l < m->d.n_lambda; ++l) {
+        int64_t woff = m->s_offset[l] / m->d.n_leaves;
+        orc_hg_weights_tab(12 * (int64_t)m->nside_sca[l] * m->nside_sca[l], th->pv + 3 * woff, m->d.g[l], n,
+                           th->w + woff);
+    }
+}
+
+/* v[0] + v[1] + v[2] + v[3] added in ascending order */
+static double orc_sum4(double v[4])
+{
+    for (int i = 1; i < 4; ++i)
+        for (int k = i; k > 0 && v[k] < v[k - 1]; --k) {
+            double x = v[k];
+            v[k] = v[k - 1];
+            v[k - 1] = x;
+        }
+    return ((v[0] + v[1]) + v[2]) + v[3];
+}
+
+/*
+ * The four children of a ray split at entry distance t_in (Eq. 2), each
+ * with a quarter of its luminosity, followed one after the other.  When all
+ * four end up in the low list having crossed the same grid plane, they merge
+ * (Eq. 3 and the text after it): one ray in the parent's pixel carrying the
+ * sum of their luminosities (the average intensity over a beam four times
+ * wider), from the mean of their distances; orc_split then returns 1 with
+ * that state in *merged and the parent's walk carries on with it.
+ * Otherwise the paused children carry on from where they stopped, no longer
+ * entering the low list, and orc_split returns 0 (the parent has ended).
+ */
+static int orc_split(const orc_model *m, const orc_pass_opts *o, const double *U_LL, int64_t s, int level,
+                     int64_t pix, double t_in, const double *L, orc_thread *th, orc_low *merged)
+{
+    const int nl = m->d.n_lambda;
+    th->count[C_SPLITS]++;
+    orc_low kid[4];
+    int paused[4], all = 1;
+    double Lc[64];
+    for (int l = 0; l < nl; ++l) Lc[l] = 0.25 * L[l];
+    for (int k = 0; k < 4; ++k) {
+        paused[k] = orc_follow(m, o, U_LL, s, level + 1, 4 * pix + k, t_in, -1, Lc, 1, th, &kid[k]);
+        all &= paused[k];
+    }
+    if (all) {
+        for (int k = 0; k < 4; ++k)
+            if (kid[k].axis < 0 || kid[k].axis != kid[0].axis || kid[k].plane != kid[0].plane) all = 0;
+    }
+    if (all) {
+        th->count[C_MERGES]++;
+        /* sums over the four in ascending order, so that mirror-image groups
+         * (the same siblings in another order) give the same ray */
+        double v[4];
+        for (int l = 0; l < nl; ++l) {
+            for (int k = 0; k < 4; ++k) v[k] = kid[k].L[l];
+            merged->L[l] = orc_sum4(v);
+        }
+        for (int k = 0; k < 4; ++k) v[k] = kid[k].t;
+        merged->t = 0.25 * orc_sum4(v);
+        return 1;
+    }
+    for (int k = 0; k < 4; ++k)
+        if (paused[k]) orc_follow(m, o, U_LL, s, level + 1, 4 * pix + k, kid[k].t, kid[k].c, kid[k].L, 0, th, NULL);
+    return 0;
+}
+
+/*
+ * Follow one ray of source s (pixel pix at Nside nside0 2^level) from
+ * distance t_start -- in start_cell, or the leaf found at that point when
+ * -1 -- until it escapes, is blocked, is split (its children are followed
+ * through orc_split) or, when can_low, pauses in the low list (returns 1).
+ */
+static int orc_follow(const orc_model *m, const orc_pass_opts *o, const double *U_LL, int64_t s, int level,
+                      int64_t pix, double t_start, int64_t start_cell, const double *L_in, int can_low,
+                      orc_thread *th, orc_low *low)
 {
     const orc_grid_desc *d = &m->d;
     const int nl = d->n_lambda;
     const double cl = d->c_light;
-    int64_t nside = (int64_t)o->nside << ray->level;
+    int64_t nside = (int64_t)o->nside << level;
     double omega_hp = 4.0 * M_PI / (12.0 * (double)nside * (double)nside);
     double n[3];
-    orc_ray_dir(o, nside, ray->pix, n);
+    orc_ray_dir(o, nside, pix, n);
     const double *xs = orc_source_origin(m, s);
     const int64_t own = orc_source_cell(m, s);
-    if (o->mode != ORC_STEP1) {
-        for (int l = 0; l < nl; ++l) {
-            int64_t woff = m->s_offset[l] / d->n_leaves;
-            orc_hg_weights_tab(12 * (int64_t)m->nside_sca[l] * m->nside_sca[l], th->pv + 3 * woff, d->g[l], n,
-                               th->w + woff);
-        }
+    orc_ray_weights(m, o, n, th);
+    int64_t c = start_cell;
+    if (c < 0) {
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = xs[a] + t_start * n[a];
+        c = orc_locate(m, p, n);
     }
-    double p[3];
-    for (int a = 0; a < 3; ++a) p[a] = xs[a] + ray->t_start * n[a];
-    int64_t c = orc_locate(m, p, n);
-    double t = ray->t_start;
-    double *L = ray->L;
+    double t = t_start;
+    double L[64];
+    for (int l = 0; l < nl; ++l) L[l] = L_in[l];
     double tau[64], ext[64];
     int sig[64];
     int64_t steps = 0;
+    int entry_axis = -1;      /* the grid plane crossed to enter cell c */
+    double entry_plane = 0.0;
     while (c >= 0) {
-        if (o->max_steps > 0 && steps >= o->max_steps) { th->count[C_MAXSTEP]++; return; }
+        if (o->max_steps > 0 && steps >= o->max_steps) { th->count[C_MAXSTEP]++; return 0; }
         ++steps;
         double te;
-        int64_t next = orc_step(m, c, xs, n, &te);
+        int axis;
+        int64_t next = orc_step_axis(m, c, xs, n, &te, &axis);
         double len = te > t ? te - t : 0.0;
         /* a graze of an edge or corner: nothing is deposited, no decision is
          * taken and t is not advanced */
@@ -775,29 +886,39 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
                 if (o->mode == ORC_STEP1 && t_in >= o->r_pre) {
                     for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_CUT] += L[l];
                     th->count[C_CUTS]++;
-                    return;
+                    return 0;
                 }
-                int too_large = c != own &&
-                    omega_hp > (m->side[c] * m->side[c] / dc2) / o->n_rays_min;
-                if (too_large) {
+                double omega_int = c == own ? INFINITY : m->side[c] * m->side[c] / dc2;
+                if (omega_hp > omega_int / o->n_rays_min) {           /* Eq. 2: the beam is too large */
                     if (any_sig && nside < o->nside_max) {
-                        th->count[C_SPLITS]++;
-                        for (int k = 0; k < 4; ++k) {
-                            if (*stack_n >= th->cap) abort();
-                            orc_ray *ch = &th->stack[*stack_n];
-                            ch->level = ray->level + 1;
-                            ch->pix = 4 * ray->pix + k;
-                            ch->t_start = t_in;
-                            for (int l = 0; l < nl; ++l) ch->L[l] = 0.25 * L[l];
-                            ++*stack_n;
-                        }
-                        return;
+                        orc_low mg;
+                        if (!orc_split(m, o, U_LL, s, level, pix, t_in, L, th, &mg)) return 0;
+                        /* the merged ray continues this walk from the mean distance
+                         * (the children left their own phase weights behind) */
+                        orc_ray_weights(m, o, n, th);
+                        t = mg.t;
+                        for (int l = 0; l < nl; ++l) L[l] = mg.L[l];
+                        double p[3];
+                        for (int a = 0; a < 3; ++a) p[a] = xs[a] + t * n[a];
+                        c = orc_locate(m, p, n);
+                        entry_axis = -1;
+                        continue;
                     }
                     if (!any_sig) {
                         for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_CUT] += L[l];
                         th->count[C_CUTS]++;
-                        return;
+                        return 0;
                     }
+                }
+                /* Eq. 3: the beam is too small for this cell; merging never
+                 * goes below the launch resolution */
+                if (can_low && o->n_rays_max > 0.0 && level > 0 && c != own && omega_hp < omega_int / o->n_rays_max) {
+                    low->c = c;
+                    low->t = t_in;
+                    low->axis = entry_axis;
+                    low->plane = entry_plane;
+                    for (int l = 0; l < nl; ++l) low->L[l] = L[l];
+                    return 1;
                 }
             }
             th->count[C_CROSS]++;
@@ -836,18 +957,23 @@ static void orc_follow(const orc_model *m, const orc_pass_opts *o, const double 
             }
             t = te;
         }
+        /* the plane through which the ray leaves c is the one it enters the next cell by */
+        entry_axis = axis;
+        entry_plane = n[axis] > 0.0 ? m->centre[3 * c + axis] + 0.5 * m->side[c]
+                                    : m->centre[3 * c + axis] - 0.5 * m->side[c];
         c = next;
     }
     for (int l = 0; l < nl; ++l) th->tally[l * N_TALLY + T_ESCAPED] += L[l];
     th->count[C_ESCAPES]++;
     if (th->esc) {
         /* attributed to the launch pixel the ray descends from */
-        int64_t top = ray->pix >> (2 * ray->level);
+        int64_t top = pix >> (2 * level);
         for (int M = 0; M < th->nmir; ++M) {
             int64_t tm = th->emir ? th->emir[8 * top + M] : top;
             for (int l = 0; l < nl; ++l) th->esc[(int64_t)l * th->nray0 + tm] += L[l];
         }
     }
+    return 0;
 }
 
 /* Luminosity source s emits at wavelength l in this pass: 4 pi j V for the
@@ -977,6 +1103,8 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     const int64_t n = d->n_leaves;
     if (nl > 64 || o->nside <= 0 || !is_pow2(o->nside)) return ORC_E_INVALID;
     if (o->adaptive && (o->nside_max < o->nside || !is_pow2(o->nside_max) || !(o->n_rays_min > 0.0))) return ORC_E_INVALID;
+    /* a merged beam (four times a child's) must not be too large at once (Eq. 2 against Eq. 3) */
+    if (o->n_rays_max != 0.0 && !(o->n_rays_max >= 4.0 * o->n_rays_min)) return ORC_E_INVALID;
     if (o->mode == ORC_SCATTER && !S_pending) return ORC_E_INVALID;
     if (o->adaptive && o->mode != ORC_STEP1 && !U_LL) return ORC_E_INVALID;
     orc_pass_opts eff = *o;
@@ -1007,8 +1135,6 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
     if (o->mode != ORC_STEP1) memset(S_next, 0, sizeof(double) * (size_t)ssize);
     memset(tally, 0, sizeof(double) * (size_t)(nl * N_TALLY));
     memset(counters, 0, sizeof(int64_t) * N_COUNT);
-    int levels = 0;
-    if (o->adaptive) while (((int64_t)o->nside << levels) < o->nside_max) ++levels;
     int64_t nray0 = 12 * (int64_t)o->nside * o->nside;
     if (escape) memset(escape, 0, sizeof(double) * (size_t)(nl * nray0));
     int failed = 0;
@@ -1041,18 +1167,14 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
             th.S = o->mode == ORC_STEP1 ? NULL : (double *)calloc((size_t)ssize, sizeof(double));
         }
         th.w = (double *)malloc(sizeof(double) * (size_t)(wsize > 0 ? wsize : 1));
-        th.cap = 3 * (int64_t)levels + 8;
-        th.stack = (orc_ray *)malloc(sizeof(orc_ray) * (size_t)th.cap);
-        th.lbuf = (double *)malloc(sizeof(double) * (size_t)(th.cap * nl));
         th.nray0 = nray0;
         th.esc = escape ? (double *)calloc((size_t)(nl * nray0), sizeof(double)) : NULL;
-        int ok = th.w && th.stack && th.lbuf && th.U && (o->mode == ORC_STEP1 || th.S) && (!escape || th.esc);
+        int ok = th.w && th.U && (o->mode == ORC_STEP1 || th.S) && (!escape || th.esc);
         if (!ok) {
 #pragma omp atomic write
             failed = 1;
         }
         if (ok) {
-            for (int64_t k = 0; k < th.cap; ++k) th.stack[k].L = th.lbuf + k * nl;
 #pragma omp for schedule(dynamic, 1)
             for (int64_t s = 0; s < n + n_src_points; ++s) {
                 if (o->source_mask && !o->source_mask[s]) continue;
@@ -1066,30 +1188,16 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
                 }
                 if (!(emitted_any > 0.0)) continue;
                 for (int64_t r = 0; r < nray0; ++r) {
-                    int64_t sn = 0;
-                    orc_ray *top = &th.stack[sn++];
-                    top->level = 0;
-                    top->pix = r;
-                    top->t_start = 0.0;
+                    double L0[64];
                     double lsum = 0.0;
                     for (int l = 0; l < nl; ++l) {
-                        top->L[l] = orc_launch(m, o, S_pending, s, l, o->nside, r);
-                        lsum += top->L[l];
+                        L0[l] = orc_launch(m, o, S_pending, s, l, o->nside, r);
+                        lsum += L0[l];
                     }
                     if (!(lsum > 0.0)) continue;
                     th.count[C_RAYS]++;
-                    while (sn > 0) {
-                        /* pop the last ray; copy its state since children overwrite the slot */
-                        orc_ray cur;
-                        double lcur[64];
-                        orc_ray *src = &th.stack[--sn];
-                        cur.level = src->level;
-                        cur.pix = src->pix;
-                        cur.t_start = src->t_start;
-                        for (int l = 0; l < nl; ++l) lcur[l] = src->L[l];
-                        cur.L = lcur;
-                        orc_follow(m, o, U_LL, s, &cur, &th, &sn);
-                    }
+                    orc_low unused;
+                    orc_follow(m, o, U_LL, s, 0, r, 0.0, orc_source_cell(m, s), L0, 0, &th, &unused);
                 }
             }
 #pragma omp critical
@@ -1110,8 +1218,6 @@ int orc_run_pass(const orc_model *m, const orc_pass_opts *o, const double *S_pen
             free(th.S);
         }
         free(th.w);
-        free(th.stack);
-        free(th.lbuf);
         free(th.esc);
     }
     free(pv);

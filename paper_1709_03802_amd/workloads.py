@@ -121,6 +121,7 @@ class RayPolicy:
     nside: int = 8              # fixed mode: ray Nside; adaptive: initial Nside
     nside_max: int = 8          # adaptive: highest ray Nside
     n_rays_min: float = 4.0     # adaptive: N_rays of Eq. 2
+    n_rays_max: float = 0.0     # adaptive: N_rays^max of Eq. 3 (ray merging, >= 4 n_rays_min); 0: no merging
     f_U: float = 0.0            # adaptive: blocking threshold of Eq. 1; < 0 selects Eq. 11
     a_RT: float = 0.0           # adaptive: accuracy parameter of Eq. 11 (f_U = 4 a_RT / N_s)
     r_pre: float = 0.0          # adaptive: step-1 extent
