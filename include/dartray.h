@@ -88,7 +88,8 @@ extern "C" {
 #define DARTRAY_C_DEPOSITS 5        /* crossing x wavelength deposits */
 #define DARTRAY_C_SKIPS 6           /* crossing x wavelength skipped (Sect. 3.2) */
 #define DARTRAY_C_MAXSTEP 7         /* rays stopped by max_steps */
-#define DARTRAY_N_COUNT 8
+#define DARTRAY_C_MERGES 8          /* groups of 4 rays merged into 1 (Eq. 3) */
+#define DARTRAY_N_COUNT 16          /* slots of the counters buffer (9 .. 15 stay zero) */
 
 typedef struct dartray_grid dartray_grid;   /* opaque handle */
 
@@ -174,6 +175,16 @@ typedef struct {
  *   unmasked pass when the other inputs (U_LL, S_pending) are the same.
  * max_steps: per-ray crossing limit (0 = unlimited); rays hitting it stop and
  *   are counted in DARTRAY_C_MAXSTEP.
+ * n_rays_max > 0 (adaptive rays; >= 4 n_rays_min, so that a merged beam is
+ *   not at once too large): ray merging (Eq. 3).  A ray above the launch
+ *   Nside, outside its source's cell, whose beam is smaller than the crossed
+ *   cell's solid angle over n_rays_max pauses before that crossing; when
+ *   the four children of one split all pause having crossed the same grid
+ *   plane they merge into one ray in the parent pixel that carries the sum
+ *   of their luminosities (their average intensity over the four times
+ *   wider beam) from the mean of their distances, and the parent's walk
+ *   continues with it; otherwise the paused children carry on from where
+ *   they stopped and pause no more.
  * DARTRAY_FLAG_2D (Sect. 3.6): for a model symmetric under reflection
  *   across the three planes through the centre of the root block (an
  *   axisymmetric model on a Cartesian grid is), only the sources of the
@@ -202,6 +213,7 @@ typedef struct {
     const uint8_t *source_mask;  /* device, nullable */
     uint32_t flags;              /* DARTRAY_FLAG_* */
     int64_t max_steps;
+    double n_rays_max;           /* N_rays^max of Eq. 3: ray merging (adaptive rays), 0 = none */
 } dartray_trace_opts;
 
 /*
@@ -214,7 +226,7 @@ typedef struct {
  *  S_pending [s_size]       scattered luminosity waiting for the next iteration
  *  S_next    [s_size]       work array of the pass (overwritten)
  *  tally     [n_lambda][8]  FP64, overwritten by each pass (DARTRAY_T_*)
- *  counters  [8]            uint64, overwritten when DARTRAY_FLAG_COUNTERS
+ *  counters  [16]           uint64 (DARTRAY_N_COUNT), overwritten when DARTRAY_FLAG_COUNTERS
  *  escape    [n_lambda][12 nside^2]  nullable; fixed rays only: luminosity of
  *                           the pass leaving the root block, by ray direction
  *                           (summed over sources; FP64 sums, FP32 output),

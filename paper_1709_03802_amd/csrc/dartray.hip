@@ -1069,6 +1069,7 @@ struct AdaptArgs {
     int32_t log2_nside0;
     int32_t max_depth;           // levels above nside0 a ray may reach
     double n_rays;               // N_rays of Eq. 2
+    double n_rays_max;           // N_rays^max of Eq. 3 (merging instances)
     double f_U;                  // < 0: 4 a_RT / N_s (Eq. 11)
     double a_RT;
     double c_light;
@@ -1077,6 +1078,23 @@ struct AdaptArgs {
     int64_t max_steps;
     int64_t hard_cap;
 };
+
+// a + b + c + d added in ascending order (the same sum for any order of the four)
+template <typename T>
+__device__ inline T sum4_sorted(T a, T b, T c, T d)
+{
+    T v[4] = {a, b, c, d};
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+#pragma unroll
+        for (int k = i; k > 0; --k)
+            if (v[k] < v[k - 1]) {
+                const T x = v[k];
+                v[k] = v[k - 1];
+                v[k - 1] = x;
+            }
+    return ((v[0] + v[1]) + v[2]) + v[3];
+}
 
 __device__ inline float readlane_f(float v, int j)
 {
@@ -1103,7 +1121,10 @@ __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlan
 #define DR_FETCH_MIN_SCATTER 32
 #endif
 
-template <int NL, int MODE>
+// MERGE: ray merging (Eq. 3).  A ray's luminosity is then carried
+// explicitly per wavelength (FP64 outside step 1), since a merged ray's is a
+// sum over four paths; each split level keeps its group's paused children.
+template <int NL, int MODE, bool MERGE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? DR_WAVES_STEP1 : DR_WAVES_SCATTER, 8)))
 void k_march_adaptive(const AdaptArgs A)
 {
@@ -1151,7 +1172,7 @@ void k_march_adaptive(const AdaptArgs A)
     float skp[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) skp[l] = 0.f;
-    uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_skip = 0, n_max = 0;
+    uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_skip = 0, n_max = 0, n_merge = 0;
 
     // ray state.  Step 1 carries the ray's luminosity in FP32 (its decisions
     // are geometric).  The passes that take per-wavelength significance
@@ -1177,6 +1198,26 @@ void k_march_adaptive(const AdaptArgs A)
     int32_t st_c[kMaxDepthAdaptive + 1];   // cell in which the level's parent split
     float st_L[STEP1 ? kMaxDepthAdaptive + 1 : 1][STEP1 ? NL : 1];
     double st_N[STEP1 ? 1 : kMaxDepthAdaptive + 1];
+    // merging state (MERGE only): the explicit FP64 luminosity outside step
+    // 1, what the children of each level start with, and per level the
+    // paused children (bitmask, distance, cell, luminosity), the plane they
+    // crossed (0 none yet, -1 not all the same) and whether the level is
+    // resuming them; bit d of can_low: the ray at depth d may pause
+    constexpr int KD = MERGE ? kMaxDepthAdaptive + 1 : 1;
+    constexpr bool XL = MERGE && !STEP1;
+    double Lx[XL ? NL : 1];
+    double st_Lx[XL ? KD : 1][XL ? NL : 1];
+    uint8_t g_low[KD], g_res[KD];
+    int32_t g_pl[KD];
+    double g_t[KD][4];
+    int32_t g_c[KD][4];
+    float g_Ls[MERGE && STEP1 ? KD : 1][4][MERGE && STEP1 ? NL : 1];
+    double g_Ld[XL ? KD : 1][4][XL ? NL : 1];
+    uint32_t can_low = 0;
+    int32_t entry_key = 0;         // plane through which the ray entered c: 1 + axis + 3 coordinate, 0 none
+    int32_t start_c = -1;          // a resumed child starts in its own cell
+#pragma unroll
+    for (int l = 0; l < (XL ? NL : 1); ++l) Lx[l] = 0.0;
     int64_t steps = 0;
     double omega_hp = 0.0;
 #pragma unroll
@@ -1186,11 +1227,81 @@ void k_march_adaptive(const AdaptArgs A)
     // luminosity the ray carries at its current position, wavelength l
     auto lum = [&](int l) -> double {
         if constexpr (STEP1) return (double)L[l];
+        else if constexpr (XL) return Lx[l];
         else return L0[l] * ldexp(1.0, -2 * depth) * exp(-(double)s_kap[l] * colN);
     };
 
     while (true) {
         // ---- lanes without a ray: next sibling from the stack
+        if constexpr (MERGE) {
+            if (!has_ray && !pending && has_item && depth > 0) {
+                // next sibling, or the end of a group: merge, resume, pop
+                for (;;) {
+                    const int k = pix & 3;
+                    if (!g_res[depth] && k < 3) {
+                        ++pix;
+                        t = st_t[depth];
+                        if constexpr (STEP1) {
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) L[l] = st_L[depth][l];
+                        } else {
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) Lx[l] = st_Lx[depth][l];
+                        }
+                        pending = true;
+                        break;
+                    }
+                    if (!g_res[depth]) {
+                        if (g_low[depth] == 15 && g_pl[depth] > 0) {
+                            // four paused siblings across one plane: the
+                            // parent carries on with their summed luminosity
+                            // from their mean distance (sums in ascending order)
+                            ++n_merge;
+                            t = 0.25 * sum4_sorted(g_t[depth][0], g_t[depth][1], g_t[depth][2], g_t[depth][3]);
+                            if constexpr (STEP1) {
+#pragma unroll
+                                for (int l = 0; l < NL; ++l)
+                                    L[l] = sum4_sorted(g_Ls[depth][0][l], g_Ls[depth][1][l], g_Ls[depth][2][l],
+                                                       g_Ls[depth][3][l]);
+                            } else {
+#pragma unroll
+                                for (int l = 0; l < NL; ++l)
+                                    Lx[l] = sum4_sorted(g_Ld[depth][0][l], g_Ld[depth][1][l], g_Ld[depth][2][l],
+                                                        g_Ld[depth][3][l]);
+                            }
+                            --depth;
+                            pix >>= 2;
+                            pending = true;
+                            break;
+                        }
+                        g_res[depth] = 1;
+                    }
+                    if (g_low[depth]) {
+                        // a paused sibling of a group that does not merge
+                        // continues from where it stopped, pausing no more
+                        const int kk = __builtin_ctz((unsigned)g_low[depth]);
+                        g_low[depth] &= (uint8_t)~(1u << kk);
+                        pix = (pix & ~3) | kk;
+                        t = g_t[depth][kk];
+                        start_c = g_c[depth][kk];
+                        if constexpr (STEP1) {
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) L[l] = g_Ls[depth][kk][l];
+                        } else {
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) Lx[l] = g_Ld[depth][kk][l];
+                        }
+                        can_low &= ~(1u << depth);
+                        pending = true;
+                        break;
+                    }
+                    g_res[depth] = 0;
+                    --depth;
+                    pix >>= 2;
+                    if (depth == 0) break;
+                }
+            }
+        }
         if (!has_ray && !pending && has_item) {
             while (depth > 0 && (pix & 3) == 3) {
                 --depth;
@@ -1300,11 +1411,17 @@ void k_march_adaptive(const AdaptArgs A)
                             lsum += v;
                         }
                         colN = 0.0;
+                        if constexpr (XL) {
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) Lx[l] = L0[l];
+                        }
                     }
+                    can_low = 0;
                     has_item = true;
                     depth = 0;
                     pix = r0;
                     t = 0.0;
+                    st_c[0] = own_c;   // a ray merged back to the launch level starts its search here
                     if (lsum > 0.0) {
                         ++n_rays;
                         pending = true;
@@ -1332,7 +1449,11 @@ void k_march_adaptive(const AdaptArgs A)
             }
             omega_hp = kPi / (3.0 * (double)N * (double)N);   // 4 pi / (12 N^2)
             steps = 0;
-            if (t == 0.0) {
+            entry_key = 0;
+            if (MERGE && start_c >= 0) {
+                c = start_c;
+                start_c = -1;
+            } else if (t == 0.0) {
                 c = own_c;
             } else {
                 // a child starts at its parent's entry distance: mostly inside
@@ -1436,6 +1557,9 @@ void k_march_adaptive(const AdaptArgs A)
                 } else if (c != own_c && omega_hp * (double)A.n_rays * d2 > side * side) {   // Eq. 2
                     if (sigm && depth < A.max_depth) action = 1;
                     else if (!sigm) action = 2;
+                } else if (MERGE && ((can_low >> depth) & 1u) && depth > 0 && c != own_c &&
+                           omega_hp * A.n_rays_max * d2 < side * side) {                      // Eq. 3
+                    action = 3;
                 }
                 if (action == 1) {
                     // split: child 0 starts next iteration, siblings wait on the stack
@@ -1449,13 +1573,42 @@ void k_march_adaptive(const AdaptArgs A)
                             L[l] *= 0.25f;
                             st_L[depth][l] = L[l];
                         }
+                    } else if constexpr (XL) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) {
+                            Lx[l] *= 0.25;
+                            st_Lx[depth][l] = Lx[l];
+                        }
                     } else {
                         st_N[depth] = colN;   // children restart with the column density of the split point
+                    }
+                    if constexpr (MERGE) {
+                        g_low[depth] = 0;
+                        g_res[depth] = 0;
+                        g_pl[depth] = 0;
+                        can_low |= 1u << depth;
                     }
                     pix = 4 * pix;
                     t = t_in;
                     has_ray = false;
                     pending = true;
+                } else if (MERGE && action == 3) {
+                    // paused before this crossing, nothing deposited: the
+                    // group decides at its end (merge, or carry on)
+                    const int k = pix & 3;
+                    g_t[depth][k] = t_in;
+                    g_c[depth][k] = c;
+                    if constexpr (STEP1) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) g_Ls[depth][k][l] = L[l];
+                    } else {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) g_Ld[depth][k][l] = Lx[l];
+                    }
+                    g_low[depth] |= (uint8_t)(1u << k);
+                    const int32_t key = entry_key > 0 ? entry_key : -1;
+                    g_pl[depth] = g_pl[depth] == 0 ? key : (g_pl[depth] == key ? key : -1);
+                    has_ray = false;
                 } else if (action == 2) {
                     ++n_cut;
 #pragma unroll
@@ -1499,6 +1652,11 @@ void k_march_adaptive(const AdaptArgs A)
                             }
                         }
                     }
+                    if constexpr (XL) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l)
+                            if (l < nl) Lx[l] *= exp(-((double)s_kap[l] * (double)rho_c) * (len * h));
+                    }
                     if constexpr (!STEP1) {
                         colN += (double)rho_c * (len * h);   // the crossing attenuates every wavelength
                         if (deposit)
@@ -1521,6 +1679,12 @@ void k_march_adaptive(const AdaptArgs A)
                     ++n_max;
                     has_ray = false;
                 } else {
+                    if constexpr (MERGE) {
+                        // the plane of the face the ray leaves c by
+                        const bool pos = axis == 0 ? R.n[0] > 0.0 : axis == 1 ? R.n[1] > 0.0 : R.n[2] > 0.0;
+                        const int lo_a = axis == 0 ? b.x : axis == 1 ? b.y : b.z;
+                        entry_key = 1 + axis + 3 * (pos ? lo_a + b.w : lo_a);
+                    }
                     c = nx;
                 }
             }
@@ -1614,10 +1778,11 @@ void k_march_adaptive(const AdaptArgs A)
         }
     }
     if (A.counters) {
-        const uint64_t v[8] = {wave_sum_u64(n_cross), wave_sum_u64(n_rays), wave_sum_u64(n_split), wave_sum_u64(n_cut),
-                               wave_sum_u64(n_esc), wave_sum_u64(n_dep), wave_sum_u64(n_skip), wave_sum_u64(n_max)};
+        const uint64_t v[9] = {wave_sum_u64(n_cross), wave_sum_u64(n_rays), wave_sum_u64(n_split), wave_sum_u64(n_cut),
+                               wave_sum_u64(n_esc), wave_sum_u64(n_dep), wave_sum_u64(n_skip), wave_sum_u64(n_max),
+                               MERGE ? wave_sum_u64(n_merge) : 0};
         if (lane == 0)
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < 9; ++i)
                 if (v[i]) atomicAdd((unsigned long long *)&A.counters[i], (unsigned long long)v[i]);
     }
     __syncthreads();
@@ -2846,6 +3011,8 @@ static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_
         if (!std::isfinite(o->f_U) || (!(o->f_U >= 0.0) && !(o->a_RT > 0.0 && std::isfinite(o->a_RT))))
             return fail(DARTRAY_E_INVALID, "f_U must be >= 0, or < 0 with a_RT > 0 (Eq. 11)");
         if (!std::isfinite(o->r_pre)) return fail(DARTRAY_E_INVALID, "r_pre must be finite");
+        if (!(o->n_rays_max == 0.0 || (o->n_rays_max >= 4.0 * o->n_rays_min && std::isfinite(o->n_rays_max))))
+            return fail(DARTRAY_E_INVALID, "n_rays_max must be 0 or >= 4 n_rays_min (Eq. 3)");
         if (g.n_lambda > 16) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays carry at most 16 wavelengths");
     }
     if (f->escape && o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "escape by direction covers fixed rays only");
@@ -3157,9 +3324,17 @@ static void launch_expand(const ExpandArgs &X, int nl, int slots, hipStream_t s,
 template <int NL>
 static void launch_adaptive(const AdaptArgs &A, int mode, hipStream_t s, unsigned blocks)
 {
-    if (mode == 0) hipLaunchKernelGGL((k_march_adaptive<NL, 0>), dim3(blocks), dim3(256), 0, s, A);
-    else if (mode == 1) hipLaunchKernelGGL((k_march_adaptive<NL, 1>), dim3(blocks), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_march_adaptive<NL, 2>), dim3(blocks), dim3(256), 0, s, A);
+    const bool merge = A.n_rays_max > 0.0;
+    if (mode == 0) {
+        if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 0, true>), dim3(blocks), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((k_march_adaptive<NL, 0, false>), dim3(blocks), dim3(256), 0, s, A);
+    } else if (mode == 1) {
+        if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 1, true>), dim3(blocks), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((k_march_adaptive<NL, 1, false>), dim3(blocks), dim3(256), 0, s, A);
+    } else {
+        if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 2, true>), dim3(blocks), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((k_march_adaptive<NL, 2, false>), dim3(blocks), dim3(256), 0, s, A);
+    }
 }
 
 static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_fields *f, bool scatter)
@@ -3217,6 +3392,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     while ((o->nside << depth) < o->nside_max) ++depth;
     A.max_depth = depth;
     A.n_rays = o->n_rays_min;
+    A.n_rays_max = o->n_rays_max;
     A.f_U = o->f_U;
     A.a_RT = o->a_RT;
     A.r_pre_fine64 = o->r_pre / g.h_fine;

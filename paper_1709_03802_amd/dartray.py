@@ -31,7 +31,8 @@ MODE_STEP1, MODE_DIRECT = 0, 1
 PROF_FIXED, PROF_STEP1, PROF_SCATTERING, PROF_ADJOINT, PROF_ALL = 1, 2, 4, 8, 15
 FLAG_COUNTERS, FLAG_CHECK, FLAG_CONTINUE, FLAG_2D = 1, 2, 4, 8
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
-C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP = range(8)
+C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, C_MERGES = range(9)
+N_COUNT = 16
 
 EXPORTS = [
     "dartray_grid_create", "dartray_grid_destroy", "dartray_grid_info", "dartray_nside_sca",
@@ -90,6 +91,7 @@ class TraceOpts(C.Structure):
         ("source_mask", C.c_void_p),
         ("flags", C.c_uint32),
         ("max_steps", C.c_int64),
+        ("n_rays_max", C.c_double),
     ]
 
 
@@ -377,7 +379,7 @@ class Fields:
         self.S_pending = torch.zeros(max(grid.s_size, 1), **f32)
         self.S_next = torch.zeros(max(grid.s_size, 1), **f32)
         self.tally = torch.zeros((grid.nl, 8), dtype=torch.float64, device=dev)
-        self.counters = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.counters = torch.zeros(N_COUNT, dtype=torch.int64, device=dev)
         self.escape = (torch.zeros((grid.nl, 12 * escape_nside ** 2), **f32) if escape_nside else None)
 
     def c(self) -> FieldsC:
@@ -448,6 +450,7 @@ def make_opts(policy, mode=MODE_DIRECT, frame=None, source_mask=None, counters=T
     o.flags = (FLAG_COUNTERS if counters else 0) | (FLAG_CHECK if check else 0) | \
         (FLAG_2D if getattr(policy, "mode_2d", False) else 0)
     o.max_steps = int(max_steps)
+    o.n_rays_max = float(getattr(policy, "n_rays_max", 0.0))
     return o
 
 

@@ -61,13 +61,15 @@ def check_counts(c_gpu, c_ref, dr, orc):
     for gi, oi, name in ((dr.C_SPLITS, orc.C_SPLITS, "splits"), (dr.C_CUTS, orc.C_CUTS, "cuts"),
                          (dr.C_CROSSINGS, orc.C_CROSS, "crossings"), (dr.C_RAYS, orc.C_RAYS, "rays"),
                          (dr.C_DEPOSITS, orc.C_DEPOSITS, "deposits"), (dr.C_SKIPS, orc.C_SKIPS, "skips"),
-                         (dr.C_ESCAPES, orc.C_ESCAPES, "escapes")):
+                         (dr.C_ESCAPES, orc.C_ESCAPES, "escapes"), (dr.C_MERGES, orc.C_MERGES, "merges")):
         a, b = int(c_gpu[gi]), int(c_ref[oi])
         print(f"  {name}: gpu {a} oracle {b}", flush=True)
         assert a == b, name
-    # every ray ends once: a split ends one ray and starts four
+    # every ray ends once: a split ends one ray and starts four, a merge ends
+    # four and starts one
     c = [int(v) for v in c_gpu]
-    assert c[dr.C_ESCAPES] + c[dr.C_CUTS] + c[dr.C_MAXSTEP] == c[dr.C_RAYS] + 3 * c[dr.C_SPLITS]
+    assert c[dr.C_ESCAPES] + c[dr.C_CUTS] + c[dr.C_MAXSTEP] == \
+        c[dr.C_RAYS] + 3 * c[dr.C_SPLITS] - 3 * c[dr.C_MERGES]
 
 
 def check_balance(t):
