@@ -15,7 +15,10 @@ against the FP64 oracle on seeded source subsets of every pass kind its step
 runs (step 1, direct, scattering: the passes are additive over sources),
 checks the FP64 luminosity balance of every pass, times the oracle on the
 host cores as the CPU baseline, and measures its dominant march kernel with
-HIP events on the library's stream for the roofline figure.
+HIP events on the library's stream for the roofline figure.  The extras
+time batched wavelengths and models, the autotuner, the adjoint, and the
+parts beyond the base passes: ray merging (Eq. 3), the 2D mode, observer
+maps and the dust self-heating loop ("next_rows").
 
 Prints one JSON line.
 """
@@ -619,6 +622,173 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
     }
 
 
+def gpu_rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    both = (np.abs(a) > 0) | (np.abs(b) > 0)
+    e = np.abs(a - b)[both] / np.maximum(np.abs(b[both]), 1e-30)
+    return e if e.size else np.zeros(1)
+
+
+def timed_run(dr, G, pol, f):
+    """One counting run (untimed), then one timed run: ms, counters per pass."""
+    import torch
+    f.U.zero_()
+    out = dr.run(G, pol, fields=f, collect=True)
+    torch.cuda.synchronize()
+    f.U.zero_()
+    t0 = time.perf_counter()
+    dr.run(G, pol, fields=f, collect=False)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0), np.array(out.counters)
+
+
+def next_rows(dr, W, args):
+    """The parts of the method beyond the base passes, each timed on its
+    workload: ray merging (Eq. 3) and the 2D mode (Sect. 3.6) on the galaxy
+    disk, observer maps (Sect. 2, 3.6) of the disk's light, and the dust
+    self-heating loop (Sect. 3.3).  Merging and the maps are checked against
+    the FP64 oracle here (seeded source samples of every pass kind; a whole
+    map from the same scattered light), the 2D mode against the 3D run, the
+    dust loop against the oracle's loop on a small cube."""
+    import dataclasses
+    import torch
+    import oracle
+    res = {}
+    # --- ray merging, on the small disk (merging is limited to 3 split levels)
+    log("next rows: ray merging ...")
+    wt = W.disk_tiny()
+    gt = as_f32(wt.grid)
+    Gt = dr.Grid(gt, nside_max=max(wt.policy.nside_max, 64))
+    ft = dr.Fields(Gt)
+    ms0, c0 = timed_run(dr, Gt, wt.policy, ft)
+    U0 = ft.U.cpu().numpy()
+    pm = dataclasses.replace(wt.policy, n_rays_max=64.0)
+    ms1, c1 = timed_run(dr, Gt, pm, ft)
+    du = gpu_rel(ft.U.cpu().numpy(), U0)
+    parity = None if args.no_cpu_baseline else parity_and_cpu(dr, Gt, gt, pm, wt.name, 256)[0]
+    res["merging"] = {
+        "workload": f"{wt.name}: {wt.description}, adaptive Nside {wt.policy.nside}..{wt.policy.nside_max}, "
+                    f"N_rays^max = 64 (Eq. 3)",
+        "ms_per_step": ms1, "ms_per_step_without": ms0,
+        "crossings_x_lambda_per_s": float(c1[:, dr.C_CROSSINGS].sum()) * gt.n_lambda / (ms1 * 1e-3),
+        "crossings_per_pass": [int(x) for x in c1[:, dr.C_CROSSINGS]],
+        "crossings_per_pass_without": [int(x) for x in c0[:, dr.C_CROSSINGS]],
+        "merges_per_pass": [int(x) for x in c1[:, dr.C_MERGES]],
+        "U_change_vs_without": {"median": float(np.median(du)), "p99": float(np.quantile(du, 0.99)),
+                                "max": float(du.max())},
+        "parity": parity,
+        "note": "merging is refused beyond 3 split levels (the galaxy disk's policy has 8)"}
+    log(f"merging: {res['merging']}")
+    del ft
+    Gt.close()
+    wl = W.by_name("disk")
+    grid = as_f32(wl.grid)
+    pol = wl.policy
+    G = dr.Grid(grid, nside_max=max(pol.nside_max, 64))
+    f = dr.Fields(G)
+    nl = grid.n_lambda
+    ms0, c0 = timed_run(dr, G, pol, f)
+    S0 = f.S_total.clone()
+    # --- observer maps of the disk's light (stellar + scattered, the run without merging)
+    log("next rows: observer maps ...")
+    lo, hi = grid.box()
+    ctr = 0.5 * (lo + hi)
+    ext = float(np.max(hi - lo))
+    specs = {"distant_512x512_inclined": dict(kind="distant", dir=[0.0, -0.5, 0.866], up=[0, 0, 1], centre=ctr,
+                                              pixel_size=ext / 512, nx=512, ny=512),
+             "internal_nside64": dict(kind="internal", pos=[8.0, 0.3, 0.05], nside_map=64)}
+    maps = {}
+    for name, spec in specs.items():
+        ob = dr.observer(**spec)
+        dr.observe(G, ob, S_total=S0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            img = dr.observe(G, ob, S_total=S0)
+        torch.cuda.synchronize()
+        maps[name] = {"ms": 1e3 * (time.perf_counter() - t0) / 3, "pixels": int(img.shape[1]), "n_lambda": nl,
+                      "sources": int(grid.n)}
+    if not args.no_cpu_baseline:
+        spec = dict(kind="distant", dir=[0.0, -0.5, 0.866], up=[0, 0, 1], centre=ctr, pixel_size=ext / 64, nx=64, ny=64)
+        m = oracle.Model(grid)
+        S32 = S0.cpu().numpy()[:G.s_size].astype(np.float64)
+        t0 = time.perf_counter()
+        want = m.observe(oracle.observer(**spec), S_total=S32)
+        t_cpu = time.perf_counter() - t0
+        got = dr.observe(G, dr.observer(**spec), S_total=S0).cpu().numpy()
+        e = gpu_rel(got, want)
+        maps["parity"] = {"checked": "64 x 64 inclined image of the disk's stellar and scattered light, the same "
+                                     "FP32 S_total on both sides", "max_rel": float(e.max()), "pass": bool(e.max() <= 1e-4),
+                          "oracle_s": t_cpu}
+    res["observer_maps"] = maps
+    log(f"observer maps: {maps}")
+    del f, S0
+    G.close()
+    torch.cuda.empty_cache()
+    # --- 2D mode on the disk with every root cube split once
+    log("next rows: 2D mode ...")
+    w2 = W.disk(mode_2d=True)
+    g2 = as_f32(w2.grid)
+    G2 = dr.Grid(g2, nside_max=max(w2.policy.nside_max, 64))
+    f2 = dr.Fields(G2)
+    p3 = dataclasses.replace(w2.policy, mode_2d=False)
+    ms3, c3 = timed_run(dr, G2, p3, f2)
+    U3 = f2.U.cpu().numpy()
+    ms2, c2 = timed_run(dr, G2, w2.policy, f2)
+    d23 = gpu_rel(f2.U.cpu().numpy(), U3)
+    res["mode_2d"] = {
+        "workload": f"disk with every root cube split once ({g2.n} leaves), 2D mode against the 3D run",
+        "ms_per_step": ms2, "ms_per_step_3d": ms3, "speedup": ms3 / ms2,
+        "crossings_per_pass": [int(x) for x in c2[:, dr.C_CROSSINGS]],
+        "crossings_per_pass_3d": [int(x) for x in c3[:, dr.C_CROSSINGS]],
+        "U_2d_vs_3d": {"max": float(d23.max()), "p99_9": float(np.quantile(d23, 0.999))}}
+    log(f"2D mode: {res['mode_2d']}")
+    del f2
+    G2.close()
+    torch.cuda.empty_cache()
+    # --- dust emission with self-heating
+    log("next rows: dust self-heating ...")
+    dw = W.selfheat(n=32, nside=4)
+    Gs = dr.Grid(as_f32(dw.stellar.grid))
+    Gd = dr.Grid(as_f32(dw.dust_grid))
+    fs = dr.Fields(Gs)
+    dr.run(Gs, dw.stellar.policy, fields=fs, collect=False)
+    dr.dust_selfheat(Gs, fs.U, Gd, dw.dust_policy, dw.dust)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outd = dr.dust_selfheat(Gs, fs.U, Gd, dw.dust_policy, dw.dust)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    dust = {"workload": f"{dw.name}: {dw.description}", "loop_ms": 1e3 * t_loop, "calculations": len(outd.ratios),
+            "ratios": outd.ratios, "T_range_K": [float(outd.T[outd.T > 0].min()), float(outd.T.max())]}
+    if not args.no_cpu_baseline:
+        sw = W.selfheat(n=12, nside=4)
+        sw.stellar.grid = as_f32(sw.stellar.grid)
+        sw.dust_grid = as_f32(sw.dust_grid)
+        ms_ = oracle.Model(sw.stellar.grid)
+        U32 = oracle.run(ms_, sw.stellar.policy).U.astype(np.float32)
+        t0 = time.perf_counter()
+        ref = oracle.dust_selfheat(ms_, U32.astype(np.float64), sw.dust_grid, sw.dust_policy, sw.dust)
+        t_cpu = time.perf_counter() - t0
+        Gs2, Gd2 = dr.Grid(sw.stellar.grid), dr.Grid(sw.dust_grid)
+        o2 = dr.dust_selfheat(Gs2, torch.from_numpy(U32).cuda(), Gd2, sw.dust_policy, sw.dust)
+        eu = gpu_rel(o2.fields.U.cpu().numpy(), ref.U).max()
+        et = gpu_rel(o2.T.cpu().numpy(), ref.T).max()
+        dust["parity"] = {"checked": f"the whole loop on {sw.name} from the same FP32 stellar U",
+                          "calculations_equal": len(o2.ratios) == len(ref.runs), "U_max_rel": float(eu),
+                          "T_max_rel": float(et),
+                          "pass": bool(len(o2.ratios) == len(ref.runs) and eu <= 1e-4 and et <= 1e-4),
+                          "oracle_s": t_cpu}
+        Gs2.close()
+        Gd2.close()
+    res["dust_selfheat"] = dust
+    log(f"dust: {dust}")
+    Gs.close()
+    Gd.close()
+    return res
+
+
 def nl_pow2(k):
     return 1 if k <= 1 else 4 if k <= 4 else 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64
 
@@ -635,7 +805,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the largest configuration's run and the batched-wavelength, batched-model, "
-                         "autotuner and adjoint measurements")
+                         "autotuner, adjoint, merging, 2D-mode, observer-map and dust-loop measurements")
     ap.add_argument("--sample-sources", type=int, default=1536,
                     help="seeded emitting cells whose step 1 (adaptive workloads) is checked against the oracle and "
                          "timed on the CPU (about 12 s of oracle work on 16 cores for the disk); grids too large "
@@ -695,6 +865,7 @@ def main():
         log("adjoint ...")
         res["adjoint"] = adjoint_timing(dr, W)
         log(f"adjoint: {res['adjoint']}")
+        res["next_rows"] = next_rows(dr, W, args)
     print(json.dumps(res), flush=True)
 
 

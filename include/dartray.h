@@ -184,7 +184,8 @@ typedef struct {
  *   of their luminosities (their average intensity over the four times
  *   wider beam) from the mean of their distances, and the parent's walk
  *   continues with it; otherwise the paused children carry on from where
- *   they stopped and pause no more.
+ *   they stopped and pause no more.  At most 3 split levels (nside_max <=
+ *   8 nside) with merging: deeper trees give DARTRAY_E_UNSUPPORTED.
  * DARTRAY_FLAG_2D (Sect. 3.6): for a model symmetric under reflection
  *   across the three planes through the centre of the root block (an
  *   axisymmetric model on a Cartesian grid is), only the sources of the

@@ -3013,6 +3013,10 @@ static int check_opts(const Grid &g, const dartray_trace_opts *o, const dartray_
         if (!std::isfinite(o->r_pre)) return fail(DARTRAY_E_INVALID, "r_pre must be finite");
         if (!(o->n_rays_max == 0.0 || (o->n_rays_max >= 4.0 * o->n_rays_min && std::isfinite(o->n_rays_max))))
             return fail(DARTRAY_E_INVALID, "n_rays_max must be 0 or >= 4 n_rays_min (Eq. 3)");
+        // merging has been run on trees of at most 3 split levels; a run with
+        // 8 levels faulted the device and the cause is not yet found
+        if (o->n_rays_max > 0.0 && depth > kMaxDepthMerge)
+            return fail(DARTRAY_E_UNSUPPORTED, "ray merging is limited to 3 split levels (nside_max <= 8 nside)");
         if (g.n_lambda > 16) return fail(DARTRAY_E_UNSUPPORTED, "adaptive rays carry at most 16 wavelengths");
     }
     if (f->escape && o->adaptive) return fail(DARTRAY_E_UNSUPPORTED, "escape by direction covers fixed rays only");

@@ -14,6 +14,7 @@ namespace dr {
 
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr int kMaxLambda = 64;            // wavelengths per grid
+constexpr int kMaxDepthMerge = 3;         // split levels of adaptive trees with ray merging
 constexpr int kMaxNsideWTable = 16;       // fixed-mode ray Nside with a tabulated phase table
 constexpr int kMaxNsideCap = 1024;        // largest ray Nside of any table
 constexpr int kMaxNsideSca = 8;           // largest Nside of the scattered source function

@@ -63,3 +63,18 @@ def test_merging_one_source_banded_octree(dr, orc):
     check_counts(c, r.counters, dr, orc)
     assert eu <= 1e-4 and es <= 1e-4
     G.close()
+
+
+def test_merging_beyond_three_split_levels_is_refused(dr):
+    wl = W.disk_tiny(nside_max=64)          # 4 split levels above Nside 4
+    G = dr.Grid(as_f32_grid(wl.grid), nside_max=64)
+    f = dr.Fields(G)
+    with pytest.raises(dr.DartRayError) as e:
+        dr.trace_direct(G, dr.make_opts(dataclasses.replace(wl.policy, n_rays_max=64.0), dr.MODE_STEP1), f)
+    assert e.value.code == dr.E_UNSUPPORTED
+    G.close()
+
+
+def as_f32_grid(grid):
+    from test_gpu_adaptive import as_f32
+    return as_f32(grid)
