@@ -23,7 +23,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "dartray_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# DARTRAY_ORACLE_LIB names a prebuilt oracle library to load instead (the
+# sanitizer run of sanitize.sh); it is then not rebuilt here
+LIB_OVERRIDE = os.environ.get("DARTRAY_ORACLE_LIB")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "liboracle.so")
 
 STEP1, DIRECT, SCATTER = 0, 1, 2
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
@@ -34,6 +37,8 @@ def build(force: bool = False) -> str:
     """Compile the oracle (plain C, FP64, OpenMP).  No contraction into fused
     multiply-adds: each FP64 step rounds on its own, which is the rule that
     decides a value lying on a pixel or cell edge."""
+    if LIB_OVERRIDE:
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",

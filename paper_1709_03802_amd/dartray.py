@@ -24,7 +24,9 @@ from typing import Optional
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libdartray.so")
+# DARTRAY_LIB names another build of the library to load (the host-sanitizer
+# run of sanitize_host.sh)
+LIB_PATH = os.environ.get("DARTRAY_LIB") or os.path.join(PKG, "libdartray.so")
 
 OK, E_INVALID, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 MODE_STEP1, MODE_DIRECT = 0, 1
