@@ -52,9 +52,16 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # kernel sources hashed here (null traffic once the sources change)
 PMC_TRAFFIC = {
     "disk": {
-        "bytes_per_launch": 2.6299e+13 + 1.9904e+13,
-        "sources_sha256": "608cac3514d632f4c5c1d8321b02dd29be5e62db23aefc70b98a06407b3bc601",
+        # k_march_adaptive<8, 0, false>, per launch: 1.2806e10 KiB fetched x2, 1.9438e10 KiB written x1
+        "bytes_per_launch": 2.6227e+13 + 1.9904e+13,
+        "sources_sha256": "83205a9a9b0563976faecc08479ddb7a7a3236e134c3925cb9348e0837cbd1c6",
         "profile": "profiles/k_march_adaptive_step1_disk.md",
+    },
+    "clumpy128": {
+        # k_march_fixed<16>, per launch (average of the run's 5): 2.5945e9 KiB fetched x2, 6.7823e9 KiB written x1
+        "bytes_per_launch": 5.3136e+12 + 6.9451e+12,
+        "sources_sha256": "83205a9a9b0563976faecc08479ddb7a7a3236e134c3925cb9348e0837cbd1c6",
+        "profile": "profiles/k_march_fixed_clumpy128.md",
     },
 }
 # the same for the adjoint march of the 64^3 clumpy grid at 4 wavelengths, per
@@ -568,7 +575,7 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
     value = cross_lambda / (dt / steps_done)
     if pol.adaptive:
         kern_cross = per_pass[0]
-        kernel = f"k_march_adaptive<{nl_pow2(grid.n_lambda)}, 0> (step 1)"
+        kernel = f"k_march_adaptive<{nl_pow2(grid.n_lambda)}, 0, false> (step 1)"
         impl_bytes = 64 + 2 * 8 * grid.n_lambda
     else:
         kern_cross = crossings
