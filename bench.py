@@ -574,11 +574,15 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
     ms_per_step = 1e3 * dt / steps_done
     value = cross_lambda / (dt / steps_done)
     if pol.adaptive:
+        # step 1: the crossings of sibling rays into one cell in the same
+        # step share one energy-density row
         kern_cross = per_pass[0]
-        kernel = f"k_march_adaptive<{nl_pow2(grid.n_lambda)}, 0, false> (step 1)"
-        impl_bytes = 64 + 2 * 8 * grid.n_lambda
+        rows_per_cross = int(counters[0, dr.C_U_ROWS]) / max(kern_cross, 1)
+        kernel = f"k_step1_quad<{nl_pow2(grid.n_lambda)}> (step 1)"
+        impl_bytes = 64 + 2 * 8 * grid.n_lambda * rows_per_cross
     else:
         kern_cross = crossings
+        rows_per_cross = 1.0
         kernel = f"k_march_fixed<{nl_pow2(grid.n_lambda)}>"
         impl_bytes = 64 + 2 * 4 * grid.n_lambda
     per_cross = algorithmic_bytes(pol, grid)
@@ -586,13 +590,14 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
     avg_ms = kern_ms / max(launches, 1)
     cross_per_launch = kern_cross / launches_per_step
     achieved = cross_per_launch * per_cross / (avg_ms * 1e-3) / 1e9
-    # 64-byte atomic requests per crossing: one row of n_lambda FP64
-    # (adaptive) or FP32 (fixed) values; a row narrower than 64 bytes shares
-    # its segment with neighbouring cells' rows and has no matching ceiling
+    # 64-byte atomic requests per crossing: a row of n_lambda FP64
+    # (adaptive) or FP32 (fixed) values per row written; a row narrower than
+    # 64 bytes shares its segment with neighbouring cells' rows and has no
+    # matching ceiling
     row_bytes = (8 if pol.adaptive else 4) * grid.n_lambda
     atomic_peak = ATOMIC_PEAK_ROWS_F64 if pol.adaptive else ATOMIC_PEAK_ROWS_F32
     if row_bytes >= 64:
-        rpc = row_bytes / 64.0
+        rpc = row_bytes / 64.0 * rows_per_cross
         req_rate = rpc * cross_per_launch / (avg_ms * 1e-3)
         atomic_roof = {"achieved": req_rate, "peak": atomic_peak, "unit": "64-byte atomic rows/s",
                        "frac": req_rate / atomic_peak, "requests_per_crossing": rpc}
@@ -620,9 +625,9 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
                                                 "written) per wavelength",
                      "implementation_bytes_per_crossing": impl_bytes,
                      "crossings_per_launch": cross_per_launch},
-        # the deposits are one 64-byte atomic request per crossing at 8 FP64
-        # or 16 FP32 wavelengths: the request rate against the measured
-        # ceiling of that access pattern
+        # the deposits are one 64-byte atomic request per row at 8 FP64 or
+        # 16 FP32 wavelengths: the request rate against the measured ceiling
+        # of that access pattern
         "atomic_roofline": atomic_roof,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -1117,6 +1117,11 @@ __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlan
 #ifndef DR_FETCH_MIN_STEP1
 #define DR_FETCH_MIN_STEP1 4
 #endif
+// step 1 without merging by teams of four lanes (k_step1_quad); 0 keeps
+// the lane-per-item march for it
+#ifndef DR_STEP1_QUAD
+#define DR_STEP1_QUAD 1
+#endif
 #ifndef DR_FETCH_MIN_SCATTER
 #define DR_FETCH_MIN_SCATTER 32
 #endif
@@ -1791,6 +1796,400 @@ void k_march_adaptive(const AdaptArgs A)
         if (s_esc[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], s_esc[l]);
         if (s_cut[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_CUT], s_cut[l]);
         if (s_skp[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_SKIPPED], s_skp[l]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 by teams of four lanes (step-1 rays of Sect. 3.2, split by Eq. 2).
+//
+// The four children of a split start at one point with nearly parallel
+// directions and cross many cells together, so the four lanes of a quad
+// march them side by side, one crossing each per iteration, and the
+// crossings of an iteration that deposit into the same cell add their rows
+// inside the quad (DPP moves) before one atomic row goes out.  A quad's work
+// item is one source and four nested launch pixels 4m .. 4m+3, which also
+// start together, at the source.  The quad walks the item's ray tree group
+// by group, depth first: a ray that splits leaves its children's start
+// (entry distance, split cell, quarter luminosity, parent pixel) in its
+// lane's slot of the next level and stops; once all four lanes have stopped,
+// the quad starts the children of the deepest level holding a slot (lowest
+// lane first), or takes a new item.  A lane holds at most one slot per
+// level: the slots of a level all come from the single group running one
+// level above, and deeper levels are emptied before another group of that
+// level starts.  Same rays, crossings and counters as the lane-per-item
+// march; only the order of the FP64 atomic adds and the FP32 pre-sums of
+// equal-cell rows differ.
+// ---------------------------------------------------------------------------
+
+// v of lane (k + R) & 3 of this lane's quad (k its place in the quad)
+template <int R>
+__device__ inline int quad_rot(int v)
+{
+    constexpr int ctrl = ((0 + R) & 3) | (((1 + R) & 3) << 2) | (((2 + R) & 3) << 4) | (((3 + R) & 3) << 6);
+    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+}
+
+template <int R>
+__device__ inline float quad_rot_f(float v)
+{
+    return __int_as_float(quad_rot<R>(__float_as_int(v)));
+}
+
+template <int NL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DR_WAVES_STEP1, 8)))
+void k_step1_quad(const AdaptArgs A)
+{
+    constexpr int kBlock = 256;
+    constexpr int KD = kMaxDepthAdaptive + 1;
+    __shared__ float s_kap[NL];
+    __shared__ double s_esc[NL], s_cut[NL];
+    __shared__ float s_du[NL][kBlock];
+    __shared__ int32_t s_cell[kBlock];
+    // a starting group's slot, one per quad
+    __shared__ double g_t[kBlock / 4];
+    __shared__ int32_t g_c[kBlock / 4], g_p[kBlock / 4];
+    __shared__ float g_L[NL][kBlock / 4];
+    const LambdaTable *lt = A.lt;
+    const int nl = lt->n_lambda;
+    if (threadIdx.x < NL) {
+        const int l = threadIdx.x;
+        s_kap[l] = l < nl ? lt->kappa[l] : 0.f;
+        s_esc[l] = 0.0;
+        s_cut[l] = 0.0;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+    const int qbase = lane & ~3;          // first lane of this lane's quad
+    const int qk = lane & 3;              // place in the quad: the child index within a group
+    const int qi = threadIdx.x >> 2;      // the quad's slot in the block
+    const int nsrc = *A.n_src;
+    const uint64_t nitems = (uint64_t)nsrc * (uint64_t)(3 * A.nside0 * A.nside0);
+    uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_max = 0, n_rows = 0;
+
+    bool has_ray = false, pending = false, done = false;
+    int32_t s = 0;
+    int32_t own_c = -1;
+    double o[3] = {0.0, 0.0, 0.0};
+    int depth = 0;
+    int pix = 0;
+    double t = 0.0;
+    int32_t c = -1;
+    int32_t hint_c = -1;              // the cell the parent split in (children start there mostly)
+    RayT<double> R;
+    float L[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) L[l] = 0.f;
+    double omega_hp = 0.0;
+    int64_t steps = 0;
+    // this lane's waiting children group per level
+    double w_t[KD];
+    int32_t w_c[KD], w_p[KD];
+    float w_L[KD][NL];
+    uint32_t w_mask = 0;
+    // the row this lane holds for one more step: cell (-1 none), values
+    int32_t h_cell = -1;
+    float h_du[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) h_du[l] = 0.f;
+    // the wave's rows go out as atomic requests of NL FP64 values: lanes q of
+    // an instruction take value q % NL of the (q / NL)-th row
+    auto emit_rows = [&](bool has, int32_t cell, const float *vals) {
+        const uint64_t om = __ballot(has);
+        if (has) {
+            const int slot = wbase + __popcll(om & ((1ull << lane) - 1ull));
+            s_cell[slot] = cell;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) s_du[l][slot] = vals[l];
+        }
+        wave_sync_lds();
+        const int cnt = __popcll(om);
+        constexpr int PER = 64 / NL;
+        for (int k0 = 0; k0 < cnt; k0 += PER) {
+            const int q = k0 + lane / NL;
+            const int l = lane % NL;
+            if (q < cnt && l < nl) {
+                const float v = s_du[l][wbase + q];
+                // 32-bit row offsets: n * n_lambda < 2^32 is checked at grid creation
+                const uint32_t off = (uint32_t)s_cell[wbase + q] * (uint32_t)nl + (uint32_t)l;
+                atomic_add_f64(A.U_k + off, (double)v);
+            }
+        }
+        wave_sync_lds();
+    };
+
+    while (true) {
+        // ---- quads whose four lanes have stopped: the deepest waiting group
+        const uint64_t busy = __ballot(has_ray || pending);
+        const bool q_idle = ((busy >> qbase) & 0xFull) == 0 && !done;
+        uint32_t qm = q_idle ? w_mask : 0u;
+        qm |= (uint32_t)quad_rot<1>((int)qm);
+        qm |= (uint32_t)quad_rot<2>((int)qm);
+        if (__ballot(qm != 0u)) {
+            const int D = qm ? 31 - __clz(qm) : 0;
+            const bool has_D = qm != 0u && ((w_mask >> D) & 1u);
+            const uint32_t nib = (uint32_t)(__ballot(has_D) >> qbase) & 0xFu;
+            if (has_D && qk == __builtin_ctz(nib | 16u)) {
+                g_t[qi] = w_t[D];
+                g_c[qi] = w_c[D];
+                g_p[qi] = w_p[D];
+#pragma unroll
+                for (int l = 0; l < NL; ++l) g_L[l][qi] = w_L[D][l];
+                w_mask &= ~(1u << D);
+            }
+            wave_sync_lds();
+            if (qm != 0u) {
+                depth = D;
+                pix = 4 * g_p[qi] + qk;
+                t = g_t[qi];
+                hint_c = g_c[qi];
+#pragma unroll
+                for (int l = 0; l < NL; ++l) L[l] = g_L[l][qi];
+                pending = true;
+            }
+            wave_sync_lds();
+        }
+        // ---- ... or a new item (source, launch pixels 4m .. 4m+3)
+        const bool q_new = q_idle && qm == 0u;
+        const uint64_t need = __ballot(q_new && qk == 0);
+        if (need) {
+            const int leader = __ffsll((unsigned long long)need) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(A.queue, (unsigned long long)__popcll(need));
+            base = __shfl(base, leader, 64);
+            if (q_new) {
+                const uint64_t it = base + __popcll(need & ((1ull << qbase) - 1ull));
+                if (it >= nitems) {
+                    done = true;
+                } else {
+                    const int m = (int)(it / (uint64_t)nsrc);
+                    s = A.src_list[it - (uint64_t)m * nsrc];
+                    if (s < A.n) {
+                        const int4 sb = A.geo.rec[s].box;
+                        const double half = 0.5 * (double)sb.w;
+                        o[0] = (double)sb.x + half;
+                        o[1] = (double)sb.y + half;
+                        o[2] = (double)sb.z + half;
+                        own_c = s;
+                    } else {
+                        const double4 pp = A.ps_pos[s - A.n];
+                        o[0] = pp.x;
+                        o[1] = pp.y;
+                        o[2] = pp.z;
+                        own_c = A.ps_cell[s - A.n];
+                    }
+                    const int32_t kp = s - (int32_t)A.n;
+                    const float inv_nray0 = 1.f / (float)(12 * A.nside0 * A.nside0);
+                    double lsum = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        L[l] = l >= nl ? 0.f
+                               : s < A.n ? A.emis_lum[(int64_t)l * A.n + s] * inv_nray0
+                                         : A.ps_lum[(int64_t)l * A.n_point + kp] * inv_nray0;
+                        lsum += (double)L[l];
+                    }
+                    depth = 0;
+                    pix = 4 * m + qk;
+                    t = 0.0;
+                    hint_c = own_c;
+                    if (lsum > 0.0) {
+                        ++n_rays;
+                        pending = true;
+                    }
+                }
+            }
+        }
+        // ---- start the rays of new groups: direction, first cell
+        if (pending) {
+            pending = false;
+            const int64_t N = (int64_t)A.nside0 << depth;
+            const double4 nd = A.dirs64[entry_of(N, pix)];
+            R.n[0] = nd.x;
+            R.n[1] = nd.y;
+            R.n[2] = nd.z;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R.o[a] = o[a];
+                R.inv[a] = 1.0 / R.n[a];
+            }
+            omega_hp = kPi / (3.0 * (double)N * (double)N);   // 4 pi / (12 N^2)
+            steps = 0;
+            if (t == 0.0) {
+                c = own_c;
+            } else {
+                const int fx = fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0], A.geo.fine[0]);
+                const int fy = fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1], A.geo.fine[1]);
+                const int fz = fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2], A.geo.fine[2]);
+                const int4 pb = A.geo.rec[hint_c].box;
+                const bool inside = fx >= pb.x && fx < pb.x + pb.w && fy >= pb.y && fy < pb.y + pb.w &&
+                                    fz >= pb.z && fz < pb.z + pb.w;
+                c = inside ? hint_c : locate_fine(A.geo, fx, fy, fz);
+            }
+            if (c >= 0) {
+                has_ray = true;
+            } else {
+#pragma unroll
+                for (int l = 0; l < NL; ++l)
+                    if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
+                ++n_esc;
+            }
+        }
+        if (__ballot(!done) == 0) break;
+
+        // ---- one crossing per lane with a ray
+        bool udep = false;
+        int32_t dcell = -1;
+        float du[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) du[l] = 0.f;
+        if (has_ray) {
+            const LeafRec &rc = A.geo.rec[c];
+            const int4 b = rc.box;
+            const float rho_c = rc.rho;
+            int32_t nbc[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+            int axis;
+            double te = exit_t<double>(R, b, axis);
+            if (fabs(te - A.r_pre_fine64) <= 1e-9 * A.r_pre_fine64) {
+                // a face exactly at the step-1 extent (rational HEALPix z
+                // components, faces on an integer lattice): the correctly
+                // rounded quotient, exact when the distance is representable
+                const double face = (R.n[axis] > 0.0) ? (double)((axis == 0 ? b.x : axis == 1 ? b.y : b.z) + b.w)
+                                                       : (double)(axis == 0 ? b.x : axis == 1 ? b.y : b.z);
+                te = (face - R.o[axis]) / R.n[axis];
+            }
+            const double len = te - t;
+            int action = 0;   // 0 continue, 1 split, 2 cut
+            if (!is_graze(len, te)) {
+                const double t_in = t;
+                const double dx = ((double)b.x + 0.5 * (double)b.w - o[0]);
+                const double dy = ((double)b.y + 0.5 * (double)b.w - o[1]);
+                const double dz = ((double)b.z + 0.5 * (double)b.w - o[2]);
+                const double h = A.h_fine64;
+                const double d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
+                const double side = (double)b.w * h;
+                const float lp = (float)(len * h);
+                if (t_in >= A.r_pre_fine64) {
+                    action = 2;
+                } else if (c != own_c && omega_hp * (double)A.n_rays * d2 > side * side) {   // Eq. 2
+                    if (nl > 0 && depth < A.max_depth) action = 1;
+                    else if (nl == 0) action = 2;
+                }
+                if (action == 1) {
+                    // split: the children's start waits in this lane's slot of the next level
+                    ++n_split;
+                    const int d1 = depth + 1;
+                    w_t[d1] = t_in;
+                    w_c[d1] = c;
+                    w_p[d1] = pix;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) w_L[d1][l] = 0.25f * L[l];
+                    w_mask |= 1u << d1;
+                    has_ray = false;
+                } else if (action == 2) {
+                    ++n_cut;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l)
+                        if (l < nl) atomicAdd(&s_cut[l], (double)L[l]);
+                    has_ray = false;
+                } else {
+                    const float ivc = rc.ivc;
+                    ++n_cross;
+                    udep = true;
+                    dcell = c;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        if (l < nl) {
+                            const float alpha = s_kap[l] * rho_c;
+                            const float tau = alpha * lp;
+                            bool thick;
+                            float tr;
+                            const float em1 = fast_em1(tau, thick, tr);
+                            const float ext = -L[l] * em1;
+                            du[l] = alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
+                            ++n_dep;
+                            L[l] = tau < 0.5f ? fmaf(L[l], em1, L[l]) : L[l] * tr;
+                        }
+                    }
+                    t = te;
+                }
+            }
+            if (has_ray && action == 0) {
+                const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
+                ++steps;
+                if (nx < 0) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l)
+                        if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
+                    ++n_esc;
+                    has_ray = false;
+                } else if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
+                    ++n_max;
+                    has_ray = false;
+                } else {
+                    c = nx;
+                }
+            }
+        }
+
+        // ---- energy-density rows.  A row stays with its quad for one more
+        // step: a sibling one crossing behind (it cut a corner its siblings
+        // missed) still adds to it.  Then (1) the quad's deposits into cells
+        // whose rows are held join them; (2) of the other deposits, the
+        // lowest lane of each cell takes the row of that cell; (3) the held
+        // rows go out; (4) the new rows are held.
+        const int32_t c1 = quad_rot<1>(dcell), c2 = quad_rot<2>(dcell), c3 = quad_rot<3>(dcell);
+        const int32_t h1 = quad_rot<1>(h_cell), h2 = quad_rot<2>(h_cell), h3 = quad_rot<3>(h_cell);
+        const bool joined = udep && (dcell == h_cell || dcell == h1 || dcell == h2 || dcell == h3);
+        const bool held = h_cell >= 0;
+        // lane (k + r) & 3 deposits into this lane's held cell
+        const bool p0 = held && dcell == h_cell, p1 = held && c1 == h_cell, p2 = held && c2 == h_cell,
+                   p3 = held && c3 == h_cell;
+        // cells equal to a fresh deposit's are fresh deposits too (held cells
+        // are distinct within the quad)
+        const bool fresh = udep && !joined;
+        const bool e1 = fresh && c1 == dcell, e2 = fresh && c2 == dcell, e3 = fresh && c3 == dcell;
+        // lane (k + r) & 3 lies below this one when k + r >= 4
+        const bool owner = fresh && !(e1 && qk >= 3) && !(e2 && qk >= 2) && !(e3 && qk >= 1);
+        const bool a1 = owner && e1 && qk < 3, a2 = owner && e2 && qk < 2, a3 = owner && e3 && qk < 1;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const float v1 = quad_rot_f<1>(du[l]), v2 = quad_rot_f<2>(du[l]), v3 = quad_rot_f<3>(du[l]);
+            float hv = h_du[l];
+            if (p0) hv += du[l];
+            if (p1) hv += v1;
+            if (p2) hv += v2;
+            if (p3) hv += v3;
+            h_du[l] = hv;
+            float v = du[l];
+            if (a1) v += v1;
+            if (a2) v += v2;
+            if (a3) v += v3;
+            du[l] = v;
+        }
+        emit_rows(held, h_cell, h_du);
+        if (owner) ++n_rows;
+        h_cell = owner ? dcell : -1;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) h_du[l] = du[l];
+    }
+    emit_rows(h_cell >= 0, h_cell, h_du);
+
+    if (A.counters) {
+        const uint64_t v[10] = {wave_sum_u64(n_cross), wave_sum_u64(n_rays), wave_sum_u64(n_split), wave_sum_u64(n_cut),
+                                wave_sum_u64(n_esc), wave_sum_u64(n_dep), 0, wave_sum_u64(n_max), 0,
+                                wave_sum_u64(n_rows)};
+        if (lane == 0)
+            for (int i = 0; i < 10; ++i)
+                if (v[i]) atomicAdd((unsigned long long *)&A.counters[i], (unsigned long long)v[i]);
+    }
+    __syncthreads();
+    if (threadIdx.x < NL && threadIdx.x < nl) {
+        const int l = threadIdx.x;
+        if (s_esc[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_ESCAPED], s_esc[l]);
+        if (s_cut[l] != 0.0) atomic_add_f64(&A.tally[l * DARTRAY_N_TALLY + DARTRAY_T_CUT], s_cut[l]);
     }
 }
 
@@ -3331,7 +3730,11 @@ static void launch_adaptive(const AdaptArgs &A, int mode, hipStream_t s, unsigne
     const bool merge = A.n_rays_max > 0.0;
     if (mode == 0) {
         if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 0, true>), dim3(blocks), dim3(256), 0, s, A);
+#if DR_STEP1_QUAD
+        else hipLaunchKernelGGL((k_step1_quad<NL>), dim3(blocks), dim3(256), 0, s, A);
+#else
         else hipLaunchKernelGGL((k_march_adaptive<NL, 0, false>), dim3(blocks), dim3(256), 0, s, A);
+#endif
     } else if (mode == 1) {
         if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 1, true>), dim3(blocks), dim3(256), 0, s, A);
         else hipLaunchKernelGGL((k_march_adaptive<NL, 1, false>), dim3(blocks), dim3(256), 0, s, A);

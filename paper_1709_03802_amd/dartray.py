@@ -33,7 +33,7 @@ MODE_STEP1, MODE_DIRECT = 0, 1
 PROF_FIXED, PROF_STEP1, PROF_SCATTERING, PROF_ADJOINT, PROF_ALL = 1, 2, 4, 8, 15
 FLAG_COUNTERS, FLAG_CHECK, FLAG_CONTINUE, FLAG_2D = 1, 2, 4, 8
 T_EMITTED, T_ABSORBED, T_SCATTERED, T_ESCAPED, T_CUT, T_SKIPPED = range(6)
-C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, C_MERGES = range(9)
+C_CROSSINGS, C_RAYS, C_SPLITS, C_CUTS, C_ESCAPES, C_DEPOSITS, C_SKIPS, C_MAXSTEP, C_MERGES, C_U_ROWS = range(10)
 N_COUNT = 16
 
 EXPORTS = [

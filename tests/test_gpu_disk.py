@@ -92,11 +92,18 @@ def test_full_disk_sampled_step1_and_direct_pass(dr, orc, disk, step1):
     torch.cuda.synchronize()
     e1 = rel(f.U_LL.cpu().numpy(), r1.U)
     c1 = f.counters.cpu().numpy()
+    rows = int(c1[dr.C_U_ROWS])
     print(f"disk step 1, 48 sources: U_LL max rel {e1.max():.3g}; crossings {c1[dr.C_CROSSINGS]} "
-          f"(oracle {r1.counters[orc.C_CROSS]})", flush=True)
+          f"(oracle {r1.counters[orc.C_CROSS]}); energy-density rows {rows} "
+          f"({rows / max(int(c1[dr.C_CROSSINGS]), 1):.3f} per crossing)", flush=True)
     assert e1.max() <= TOL
-    for k_gpu, k_orc in ((dr.C_CROSSINGS, orc.C_CROSS), (dr.C_SPLITS, orc.C_SPLITS), (dr.C_CUTS, orc.C_CUTS)):
+    for k_gpu, k_orc in ((dr.C_CROSSINGS, orc.C_CROSS), (dr.C_SPLITS, orc.C_SPLITS), (dr.C_CUTS, orc.C_CUTS),
+                         (dr.C_RAYS, orc.C_RAYS), (dr.C_ESCAPES, orc.C_ESCAPES), (dr.C_DEPOSITS, orc.C_DEPOSITS)):
         assert c1[k_gpu] == r1.counters[k_orc]
+    # sibling rays share rows of the cells they cross together: at least one
+    # row per four crossings, and fewer rows than crossings (the four launch
+    # rays of an item all start in the source's own cell)
+    assert int(c1[dr.C_CROSSINGS]) / 4 <= rows < int(c1[dr.C_CROSSINGS])
     # direct pass with the same FP32 U_LL on both sides
     ull = f32(r1.U)
     r2 = m.run_pass(orc.DIRECT, pol, U_LL=ull, source_mask=mask, n_threads=16)
