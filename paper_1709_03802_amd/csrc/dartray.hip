@@ -386,6 +386,31 @@ __device__ inline float fast_em1(float tau, bool &thick, float &tr)
     return tr - 1.f;
 }
 
+// g = (1 - e^{-tau}) / tau for tau >= 0: below 0.5 the Taylor series
+// sum_k (-tau)^k / (k + 1)! through k = 7 (truncation under 1.4e-8
+// relative), above it (1 - e^{-tau}) / tau from one hardware base-2
+// exponential.  Sets thick when the second branch was taken, in which case
+// tr holds e^{-tau} (the transmitted fraction, where 1 - tau g would cancel).
+__device__ inline float fast_g(float tau, bool &thick, float &tr)
+{
+    thick = tau >= 0.5f;
+    if (!thick) {
+        const float x = -tau;
+        float p = 1.f / 40320.f;
+        p = fmaf(p, x, 1.f / 5040.f);
+        p = fmaf(p, x, 1.f / 720.f);
+        p = fmaf(p, x, 1.f / 120.f);
+        p = fmaf(p, x, 1.f / 24.f);
+        p = fmaf(p, x, 1.f / 6.f);
+        p = fmaf(p, x, 0.5f);
+        p = fmaf(p, x, 1.f);
+        tr = 0.f;
+        return p;
+    }
+    tr = __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
+    return (1.f - tr) * __builtin_amdgcn_rcpf(tau);
+}
+
 // fine-level cell coordinate of position p along an axis with direction
 // component d and F fine cells: on a face, the side d points to; a ray lying
 // in the face plane (d == 0) takes the side away from the block's central
@@ -1882,6 +1907,8 @@ void k_step1_quad(const AdaptArgs A)
 #pragma unroll
     for (int l = 0; l < NL; ++l) L[l] = 0.f;
     double omega_hp = 0.0;
+    // solid angle of a launch pixel; a power of two smaller per level
+    const double omega_hp0 = kPi / (3.0 * (double)A.nside0 * (double)A.nside0);
     int64_t steps = 0;
     // this lane's waiting children group per level
     double w_t[KD];
@@ -2013,7 +2040,7 @@ void k_step1_quad(const AdaptArgs A)
                 R.o[a] = o[a];
                 R.inv[a] = 1.0 / R.n[a];
             }
-            omega_hp = kPi / (3.0 * (double)N * (double)N);   // 4 pi / (12 N^2)
+            omega_hp = ldexp(omega_hp0, -2 * depth);   // 4 pi / (12 N^2), exactly
             steps = 0;
             if (t == 0.0) {
                 c = own_c;
@@ -2055,10 +2082,14 @@ void k_step1_quad(const AdaptArgs A)
             if (fabs(te - A.r_pre_fine64) <= 1e-9 * A.r_pre_fine64) {
                 // a face exactly at the step-1 extent (rational HEALPix z
                 // components, faces on an integer lattice): the correctly
-                // rounded quotient, exact when the distance is representable
-                const double face = (R.n[axis] > 0.0) ? (double)((axis == 0 ? b.x : axis == 1 ? b.y : b.z) + b.w)
-                                                       : (double)(axis == 0 ? b.x : axis == 1 ? b.y : b.z);
-                te = (face - R.o[axis]) / R.n[axis];
+                // rounded quotient, exact when the distance is representable.
+                // (Selects, not a runtime index into the ray, which would keep
+                // the ray in scratch memory.)
+                const double na = axis == 0 ? R.n[0] : axis == 1 ? R.n[1] : R.n[2];
+                const double oa = axis == 0 ? R.o[0] : axis == 1 ? R.o[1] : R.o[2];
+                const int la = axis == 0 ? b.x : axis == 1 ? b.y : b.z;
+                const double face = (double)(na > 0.0 ? la + b.w : la);
+                te = (face - oa) / na;
             }
             const double len = te - t;
             int action = 0;   // 0 continue, 1 split, 2 cut
@@ -2095,22 +2126,23 @@ void k_step1_quad(const AdaptArgs A)
                         if (l < nl) atomicAdd(&s_cut[l], (double)L[l]);
                     has_ray = false;
                 } else {
-                    const float ivc = rc.ivc;
+                    const float lpv = lp * rc.ivc;
                     ++n_cross;
                     udep = true;
                     dcell = c;
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
                         if (l < nl) {
-                            const float alpha = s_kap[l] * rho_c;
-                            const float tau = alpha * lp;
+                            // extinguished luminosity L tau g, energy density L g l / (V c)
+                            // with g = (1 - e^{-tau}) / tau (1 when the cell is empty)
+                            const float tau = s_kap[l] * rho_c * lp;
                             bool thick;
                             float tr;
-                            const float em1 = fast_em1(tau, thick, tr);
-                            const float ext = -L[l] * em1;
-                            du[l] = alpha > 0.f ? ext * ivc * __builtin_amdgcn_rcpf(alpha) : L[l] * lp * ivc;
+                            const float g = fast_g(tau, thick, tr);
+                            const float Lg = L[l] * g;
+                            du[l] = Lg * lpv;
                             ++n_dep;
-                            L[l] = tau < 0.5f ? fmaf(L[l], em1, L[l]) : L[l] * tr;
+                            L[l] = thick ? L[l] * tr : fmaf(-tau, Lg, L[l]);
                         }
                     }
                     t = te;
