@@ -391,21 +391,25 @@ __device__ inline float fast_em1(float tau, bool &thick, float &tr)
 // relative), above it (1 - e^{-tau}) / tau from one hardware base-2
 // exponential.  Sets thick when the second branch was taken, in which case
 // tr holds e^{-tau} (the transmitted fraction, where 1 - tau g would cancel).
+__device__ inline float g_series(float tau)
+{
+    const float x = -tau;
+    float p = 1.f / 40320.f;
+    p = fmaf(p, x, 1.f / 5040.f);
+    p = fmaf(p, x, 1.f / 720.f);
+    p = fmaf(p, x, 1.f / 120.f);
+    p = fmaf(p, x, 1.f / 24.f);
+    p = fmaf(p, x, 1.f / 6.f);
+    p = fmaf(p, x, 0.5f);
+    return fmaf(p, x, 1.f);
+}
+
 __device__ inline float fast_g(float tau, bool &thick, float &tr)
 {
     thick = tau >= 0.5f;
     if (!thick) {
-        const float x = -tau;
-        float p = 1.f / 40320.f;
-        p = fmaf(p, x, 1.f / 5040.f);
-        p = fmaf(p, x, 1.f / 720.f);
-        p = fmaf(p, x, 1.f / 120.f);
-        p = fmaf(p, x, 1.f / 24.f);
-        p = fmaf(p, x, 1.f / 6.f);
-        p = fmaf(p, x, 0.5f);
-        p = fmaf(p, x, 1.f);
         tr = 0.f;
-        return p;
+        return g_series(tau);
     }
     tr = __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
     return (1.f - tr) * __builtin_amdgcn_rcpf(tau);
@@ -2128,21 +2132,36 @@ void k_step1_quad(const AdaptArgs A)
                 } else {
                     const float lpv = lp * rc.ivc;
                     ++n_cross;
+                    n_dep += (uint32_t)nl;
                     udep = true;
                     dcell = c;
+                    // optical depths (zero beyond n_lambda, where L is zero too)
+                    float tau[NL];
+                    float tmax = 0.f;
 #pragma unroll
                     for (int l = 0; l < NL; ++l) {
-                        if (l < nl) {
-                            // extinguished luminosity L tau g, energy density L g l / (V c)
-                            // with g = (1 - e^{-tau}) / tau (1 when the cell is empty)
-                            const float tau = s_kap[l] * rho_c * lp;
+                        tau[l] = s_kap[l] * rho_c * lp;
+                        tmax = fmaxf(tmax, tau[l]);
+                    }
+                    // extinguished luminosity L tau g, energy density L g l / (V c)
+                    // with g = (1 - e^{-tau}) / tau (1 when the cell is empty);
+                    // when every crossing of the wave is optically thin the
+                    // series serves all wavelengths without a branch
+                    if (__ballot(tmax >= 0.5f) == 0) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) {
+                            const float Lg = L[l] * g_series(tau[l]);
+                            du[l] = Lg * lpv;
+                            L[l] = fmaf(-tau[l], Lg, L[l]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) {
                             bool thick;
                             float tr;
-                            const float g = fast_g(tau, thick, tr);
-                            const float Lg = L[l] * g;
+                            const float Lg = L[l] * fast_g(tau[l], thick, tr);
                             du[l] = Lg * lpv;
-                            ++n_dep;
-                            L[l] = thick ? L[l] * tr : fmaf(-tau, Lg, L[l]);
+                            L[l] = thick ? L[l] * tr : fmaf(-tau[l], Lg, L[l]);
                         }
                     }
                     t = te;
