@@ -457,15 +457,15 @@ __device__ inline T exit_t(const RayT<T> &R, const int4 b, int &axis)
     const int lo[3] = {b.x, b.y, b.z};
     T best = INF;
     axis = 0;
+    // selects rather than branches: the face the direction points to, no
+    // exit across an axis the ray runs parallel to
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        T t = INF;
-        if (R.n[a] > T(0)) t = ((T)(lo[a] + b.w) - R.o[a]) * R.inv[a];
-        else if (R.n[a] < T(0)) t = ((T)lo[a] - R.o[a]) * R.inv[a];
-        if (t < best) {
-            best = t;
-            axis = a;
-        }
+        const int face = R.n[a] > T(0) ? lo[a] + b.w : lo[a];
+        const T ta = ((T)face - R.o[a]) * R.inv[a];
+        const T t = R.n[a] != T(0) ? ta : INF;
+        axis = t < best ? a : axis;
+        best = t < best ? t : best;
     }
     return best;
 }
