@@ -39,7 +39,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # random 64-byte atomic rows per second, measured on MI355X with
-# paper_1709_03802_amd/ceilings.py (profiles/k_march_adaptive_step1_disk.md):
+# paper_1709_03802_amd/ceilings.py (profiles/k_step1_quad_disk.md):
 # rows of 8 FP64 values (the adaptive marches' energy-density rows, footprints
 # up to 128 MiB) and rows of 16 FP32 values (the fixed march's direction bins)
 ATOMIC_PEAK_ROWS_F64 = 2.35e10
@@ -52,15 +52,15 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # kernel sources hashed here (null traffic once the sources change)
 PMC_TRAFFIC = {
     "disk": {
-        # k_march_adaptive<8, 0, false>, per launch: 1.2806e10 KiB fetched x2, 1.9438e10 KiB written x1
-        "bytes_per_launch": 2.6227e+13 + 1.9904e+13,
-        "sources_sha256": "83205a9a9b0563976faecc08479ddb7a7a3236e134c3925cb9348e0837cbd1c6",
-        "profile": "profiles/k_march_adaptive_step1_disk.md",
+        # k_step1_quad<8>, per launch: 4.4318e9 KiB fetched x2, 7.3911e9 KiB written x1
+        "bytes_per_launch": 9.0763e+12 + 7.5685e+12,
+        "sources_sha256": "377c4189ac147913a8243def880441b22d6fd07169475e8e9de56ab953062d7c",
+        "profile": "profiles/k_step1_quad_disk.md",
     },
     "clumpy128": {
-        # k_march_fixed<16>, per launch (average of the run's 5): 2.5945e9 KiB fetched x2, 6.7823e9 KiB written x1
-        "bytes_per_launch": 5.3136e+12 + 6.9451e+12,
-        "sources_sha256": "83205a9a9b0563976faecc08479ddb7a7a3236e134c3925cb9348e0837cbd1c6",
+        # k_march_fixed<16>, per launch (average of the run's 5): 2.5943e9 KiB fetched x2, 6.7823e9 KiB written x1
+        "bytes_per_launch": 5.3131e+12 + 6.9451e+12,
+        "sources_sha256": "377c4189ac147913a8243def880441b22d6fd07169475e8e9de56ab953062d7c",
         "profile": "profiles/k_march_fixed_clumpy128.md",
     },
 }
@@ -555,13 +555,17 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
             f.U.zero_()
             dr.run(G, pol, fields=f, collect=False)
 
-        for _ in range(warmup):
+        for k in range(warmup):
             step()
+            log(f"warm-up step {k + 1} of {warmup} issued")
         torch.cuda.synchronize()
         G.profile(kinds)
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for k in range(steps):
             step()
+            # one line per step: a long run stays visibly alive (the passes
+            # synchronise with the host inside dr.run, so this costs nothing)
+            log(f"timed step {k + 1} of {steps} issued")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         steps_done = steps
