@@ -1895,25 +1895,39 @@ void k_step1_quad(const AdaptArgs A)
     const int qi = threadIdx.x >> 2;      // the quad's slot in the block
     const int nsrc = *A.n_src;
     const uint64_t nitems = (uint64_t)nsrc * (uint64_t)(3 * A.nside0 * A.nside0);
-    uint32_t n_cross = 0, n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_dep = 0, n_max = 0, n_rows = 0;
+    // event counts of the wave (uniform: ballots of per-lane events)
+    uint64_t n_cross = 0, n_rows = 0;
+    uint32_t n_rays = 0, n_split = 0, n_cut = 0, n_esc = 0, n_max = 0;
 
     bool has_ray = false, pending = false, done = false;
     int32_t s = 0;
     int32_t own_c = -1;
-    double o[3] = {0.0, 0.0, 0.0};
     int depth = 0;
     int pix = 0;
     double t = 0.0;
     int32_t c = -1;
     int32_t hint_c = -1;              // the cell the parent split in (children start there mostly)
-    RayT<double> R;
-    float L[NL];
+    RayT<double> R;              // origin set per item (all its rays start at the source)
 #pragma unroll
-    for (int l = 0; l < NL; ++l) L[l] = 0.f;
+    for (int a = 0; a < 3; ++a) R.o[a] = R.n[a] = R.inv[a] = 0.0;
+    float L[NL];
+    // luminosity of this lane's cut rays within the current item (FP32, a
+    // few hundred rays), folded into the block's FP64 sums between items
+    float cut_acc[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) L[l] = cut_acc[l] = 0.f;
+    auto flush_cuts = [&]() {
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+            if (l < nl && cut_acc[l] != 0.f) {
+                atomicAdd(&s_cut[l], (double)cut_acc[l]);
+                cut_acc[l] = 0.f;
+            }
+    };
     double omega_hp = 0.0;
     // solid angle of a launch pixel; a power of two smaller per level
     const double omega_hp0 = kPi / (3.0 * (double)A.nside0 * (double)A.nside0);
-    int64_t steps = 0;
+    int32_t steps = 0;
     // this lane's waiting children group per level
     double w_t[KD];
     int32_t w_c[KD], w_p[KD];
@@ -1981,6 +1995,8 @@ void k_step1_quad(const AdaptArgs A)
             }
             wave_sync_lds();
         }
+        // events of this step, counted per wave below
+        bool ev_launch = false, ev_esc = false, ev_split = false, ev_cut = false, ev_max = false;
         // ---- ... or a new item (source, launch pixels 4m .. 4m+3)
         const bool q_new = q_idle && qm == 0u;
         const uint64_t need = __ballot(q_new && qk == 0);
@@ -1990,6 +2006,7 @@ void k_step1_quad(const AdaptArgs A)
             if (lane == leader) base = atomicAdd(A.queue, (unsigned long long)__popcll(need));
             base = __shfl(base, leader, 64);
             if (q_new) {
+                flush_cuts();
                 const uint64_t it = base + __popcll(need & ((1ull << qbase) - 1ull));
                 if (it >= nitems) {
                     done = true;
@@ -1999,15 +2016,15 @@ void k_step1_quad(const AdaptArgs A)
                     if (s < A.n) {
                         const int4 sb = A.geo.rec[s].box;
                         const double half = 0.5 * (double)sb.w;
-                        o[0] = (double)sb.x + half;
-                        o[1] = (double)sb.y + half;
-                        o[2] = (double)sb.z + half;
+                        R.o[0] = (double)sb.x + half;
+                        R.o[1] = (double)sb.y + half;
+                        R.o[2] = (double)sb.z + half;
                         own_c = s;
                     } else {
                         const double4 pp = A.ps_pos[s - A.n];
-                        o[0] = pp.x;
-                        o[1] = pp.y;
-                        o[2] = pp.z;
+                        R.o[0] = pp.x;
+                        R.o[1] = pp.y;
+                        R.o[2] = pp.z;
                         own_c = A.ps_cell[s - A.n];
                     }
                     const int32_t kp = s - (int32_t)A.n;
@@ -2024,10 +2041,8 @@ void k_step1_quad(const AdaptArgs A)
                     pix = 4 * m + qk;
                     t = 0.0;
                     hint_c = own_c;
-                    if (lsum > 0.0) {
-                        ++n_rays;
-                        pending = true;
-                    }
+                    pending = lsum > 0.0;
+                    ev_launch = pending;
                 }
             }
         }
@@ -2040,18 +2055,15 @@ void k_step1_quad(const AdaptArgs A)
             R.n[1] = nd.y;
             R.n[2] = nd.z;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                R.o[a] = o[a];
-                R.inv[a] = 1.0 / R.n[a];
-            }
+            for (int a = 0; a < 3; ++a) R.inv[a] = 1.0 / R.n[a];
             omega_hp = ldexp(omega_hp0, -2 * depth);   // 4 pi / (12 N^2), exactly
             steps = 0;
             if (t == 0.0) {
                 c = own_c;
             } else {
-                const int fx = fine_coord<double>(fma(t, R.n[0], o[0]), R.n[0], A.geo.fine[0]);
-                const int fy = fine_coord<double>(fma(t, R.n[1], o[1]), R.n[1], A.geo.fine[1]);
-                const int fz = fine_coord<double>(fma(t, R.n[2], o[2]), R.n[2], A.geo.fine[2]);
+                const int fx = fine_coord<double>(fma(t, R.n[0], R.o[0]), R.n[0], A.geo.fine[0]);
+                const int fy = fine_coord<double>(fma(t, R.n[1], R.o[1]), R.n[1], A.geo.fine[1]);
+                const int fz = fine_coord<double>(fma(t, R.n[2], R.o[2]), R.n[2], A.geo.fine[2]);
                 const int4 pb = A.geo.rec[hint_c].box;
                 const bool inside = fx >= pb.x && fx < pb.x + pb.w && fy >= pb.y && fy < pb.y + pb.w &&
                                     fz >= pb.z && fz < pb.z + pb.w;
@@ -2063,7 +2075,7 @@ void k_step1_quad(const AdaptArgs A)
 #pragma unroll
                 for (int l = 0; l < NL; ++l)
                     if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
-                ++n_esc;
+                ev_esc = true;
             }
         }
         if (__ballot(!done) == 0) break;
@@ -2099,9 +2111,9 @@ void k_step1_quad(const AdaptArgs A)
             int action = 0;   // 0 continue, 1 split, 2 cut
             if (!is_graze(len, te)) {
                 const double t_in = t;
-                const double dx = ((double)b.x + 0.5 * (double)b.w - o[0]);
-                const double dy = ((double)b.y + 0.5 * (double)b.w - o[1]);
-                const double dz = ((double)b.z + 0.5 * (double)b.w - o[2]);
+                const double dx = ((double)b.x + 0.5 * (double)b.w - R.o[0]);
+                const double dy = ((double)b.y + 0.5 * (double)b.w - R.o[1]);
+                const double dz = ((double)b.z + 0.5 * (double)b.w - R.o[2]);
                 const double h = A.h_fine64;
                 const double d2 = (dx * dx + dy * dy + dz * dz) * (h * h);
                 const double side = (double)b.w * h;
@@ -2114,7 +2126,7 @@ void k_step1_quad(const AdaptArgs A)
                 }
                 if (action == 1) {
                     // split: the children's start waits in this lane's slot of the next level
-                    ++n_split;
+                    ev_split = true;
                     const int d1 = depth + 1;
                     w_t[d1] = t_in;
                     w_c[d1] = c;
@@ -2124,15 +2136,12 @@ void k_step1_quad(const AdaptArgs A)
                     w_mask |= 1u << d1;
                     has_ray = false;
                 } else if (action == 2) {
-                    ++n_cut;
+                    ev_cut = true;
 #pragma unroll
-                    for (int l = 0; l < NL; ++l)
-                        if (l < nl) atomicAdd(&s_cut[l], (double)L[l]);
+                    for (int l = 0; l < NL; ++l) cut_acc[l] += L[l];
                     has_ray = false;
                 } else {
                     const float lpv = lp * rc.ivc;
-                    ++n_cross;
-                    n_dep += (uint32_t)nl;
                     udep = true;
                     dcell = c;
                     // optical depths (zero beyond n_lambda, where L is zero too)
@@ -2174,16 +2183,23 @@ void k_step1_quad(const AdaptArgs A)
 #pragma unroll
                     for (int l = 0; l < NL; ++l)
                         if (l < nl) atomicAdd(&s_esc[l], (double)L[l]);
-                    ++n_esc;
+                    ev_esc = true;
                     has_ray = false;
                 } else if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
-                    ++n_max;
+                    ev_max = true;
                     has_ray = false;
                 } else {
                     c = nx;
                 }
             }
         }
+
+        n_cross += (uint64_t)__popcll(__ballot(udep));
+        n_rays += (uint32_t)__popcll(__ballot(ev_launch));
+        n_esc += (uint32_t)__popcll(__ballot(ev_esc));
+        n_split += (uint32_t)__popcll(__ballot(ev_split));
+        n_cut += (uint32_t)__popcll(__ballot(ev_cut));
+        n_max += (uint32_t)__popcll(__ballot(ev_max));
 
         // ---- energy-density rows.  A row stays with its quad for one more
         // step: a sibling one crossing behind (it cut a corner its siblings
@@ -2221,17 +2237,17 @@ void k_step1_quad(const AdaptArgs A)
             du[l] = v;
         }
         emit_rows(held, h_cell, h_du);
-        if (owner) ++n_rows;
+        n_rows += (uint64_t)__popcll(__ballot(owner));
         h_cell = owner ? dcell : -1;
 #pragma unroll
         for (int l = 0; l < NL; ++l) h_du[l] = du[l];
     }
     emit_rows(h_cell >= 0, h_cell, h_du);
+    flush_cuts();
 
     if (A.counters) {
-        const uint64_t v[10] = {wave_sum_u64(n_cross), wave_sum_u64(n_rays), wave_sum_u64(n_split), wave_sum_u64(n_cut),
-                                wave_sum_u64(n_esc), wave_sum_u64(n_dep), 0, wave_sum_u64(n_max), 0,
-                                wave_sum_u64(n_rows)};
+        // every deposit of step 1 covers all wavelengths
+        const uint64_t v[10] = {n_cross, n_rays, n_split, n_cut, n_esc, n_cross * (uint64_t)nl, 0, n_max, 0, n_rows};
         if (lane == 0)
             for (int i = 0; i < 10; ++i)
                 if (v[i]) atomicAdd((unsigned long long *)&A.counters[i], (unsigned long long)v[i]);
