@@ -176,8 +176,11 @@ typedef struct {
  *   emitted tally counts the selected sources only).  The passes are
  *   additive over sources (Sect. 3.4), so complementary masks add up to the
  *   unmasked pass when the other inputs (U_LL, S_pending) are the same.
- * max_steps: per-ray crossing limit (0 = unlimited); rays hitting it stop and
- *   are counted in DARTRAY_C_MAXSTEP.
+ * max_steps: per-ray crossing limit (0 = unlimited).  It counts crossings of
+ *   positive length (a zero-length graze of an edge or corner is none); a
+ *   ray that has made max_steps of them and has a next cell stops there, is
+ *   counted in DARTRAY_C_MAXSTEP and its remaining luminosity enters no
+ *   tally (it is neither escaped nor cut).
  * n_rays_max > 0 (adaptive rays; >= 4 n_rays_min, so that a merged beam is
  *   not at once too large): ray merging (Eq. 3).  A ray above the launch
  *   Nside, outside its source's cell, whose beam is smaller than the crossed

@@ -186,7 +186,7 @@ typedef struct {
     double r_pre;           /* step-1 extent */
     double frame[9];        /* rotation applied to every HEALPix direction */
     const uint8_t *source_mask; /* [n] or NULL */
-    int64_t max_steps;      /* per ray; <= 0 means unlimited */
+    int64_t max_steps;      /* per ray, crossings of positive length; <= 0 means unlimited */
     int32_t n_threads;
     double a_RT;            /* accuracy parameter of Eq. 11, used when f_U < 0 */
     int32_t mode_2d;        /* 2D mode (Sect. 3.6): first-octant sources, deposits mirrored */
@@ -851,8 +851,9 @@ static int orc_follow(const orc_model *m, const orc_pass_opts *o, const double *
     int entry_axis = -1;      /* the grid plane crossed to enter cell c */
     double entry_plane = 0.0;
     while (c >= 0) {
+        /* the per-ray limit counts crossings of positive length: a ray that has
+         * made max_steps of them stops before its next cell */
         if (o->max_steps > 0 && steps >= o->max_steps) { th->count[C_MAXSTEP]++; return 0; }
-        ++steps;
         double te;
         int axis;
         int64_t next = orc_step_axis(m, c, xs, n, &te, &axis);
@@ -922,6 +923,7 @@ static int orc_follow(const orc_model *m, const orc_pass_opts *o, const double *
                 }
             }
             th->count[C_CROSS]++;
+            ++steps;
             for (int l = 0; l < nl; ++l) {
                 double alpha = d->kappa[l] * d->rho[c];
                 if (sig[l]) {

@@ -719,21 +719,22 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                 st.cell[threadIdx.x] = c;
                 dep = true;
                 ++acc.ncross;
+                ++steps;   // the per-ray limit counts crossings of positive length
                 t = te;
             }
             const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
+            bool escaped = false;
             if (nx < 0) {
                 active = false;
+                escaped = true;
+            } else if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
+                // stopped before its next cell: its light is not escaped light
+                ++acc.nmax;
+                active = false;
             } else {
-                ++steps;
-                if ((A.max_steps > 0 && steps >= A.max_steps) || steps >= A.hard_cap) {
-                    ++acc.nmax;
-                    active = false;
-                } else {
-                    c = nx;
-                }
+                c = nx;
             }
-            if (!active) {
+            if (escaped) {
 #pragma unroll
                 for (int l = 0; l < NL; ++l)
                     if (l < nlc && L[l] != 0.f) {
@@ -1652,6 +1653,7 @@ void k_march_adaptive(const AdaptArgs A)
                 } else {
                     const float ivc = rc.ivc;
                     ++n_cross;
+                    ++steps;   // the per-ray limit counts crossings of positive length
                     udep = true;
                     // the lanes depositing in this step fill the staging in lane order
                     dslot = wbase + __popcll(__ballot(true) & ((1ull << lane) - 1ull));
@@ -1702,7 +1704,6 @@ void k_march_adaptive(const AdaptArgs A)
             }
             if (has_ray && action == 0) {
                 const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
-                ++steps;
                 if (nx < 0) {
 #pragma unroll
                     for (int l = 0; l < NL; ++l)
@@ -2142,6 +2143,7 @@ void k_step1_quad(const AdaptArgs A)
                     has_ray = false;
                 } else {
                     const float lpv = lp * rc.ivc;
+                    ++steps;   // the per-ray limit counts crossings of positive length
                     udep = true;
                     dcell = c;
                     // optical depths (zero beyond n_lambda, where L is zero too)
@@ -2178,7 +2180,6 @@ void k_step1_quad(const AdaptArgs A)
             }
             if (has_ray && action == 0) {
                 const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
-                ++steps;
                 if (nx < 0) {
 #pragma unroll
                     for (int l = 0; l < NL; ++l)

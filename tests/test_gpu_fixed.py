@@ -200,6 +200,37 @@ def test_max_steps_guard(dr):
     assert c[dr.C_MAXSTEP] + c[dr.C_ESCAPES] == c[dr.C_RAYS]
 
 
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_max_steps_matches_the_oracle(dr, orc, k):
+    """The step limit counts crossings of positive length on both sides
+    (Nside 1 and 2 directions from cell centres of a uniform grid run through
+    cell edges): the same crossings, step-limited rays and escapes, U within
+    1e-4, and the escaped luminosity (step-limited rays' light is not escaped
+    light) within 1e-6 of the emitted."""
+    import torch
+    wl = W.plain16(n=8, nside=2, lambdas=np.array([0.3, 1.0]), n_scatter=0)
+    g = wl.grid.copy()
+    for name in ("rho", "emis", "kappa", "albedo", "g"):
+        setattr(g, name, getattr(g, name).astype(np.float32).astype(np.float64))
+    ref = orc.Model(g).run_pass(orc.DIRECT, wl.policy, max_steps=k)
+    G = dr.Grid(g)
+    f = dr.Fields(G)
+    dr.trace_direct(G, dr.make_opts(wl.policy, max_steps=k), f)
+    torch.cuda.synchronize()
+    c = f.counters.cpu().numpy()
+    for a, b in ((dr.C_CROSSINGS, orc.C_CROSS), (dr.C_MAXSTEP, orc.C_MAXSTEP), (dr.C_ESCAPES, orc.C_ESCAPES),
+                 (dr.C_RAYS, orc.C_RAYS)):
+        assert int(c[a]) == int(ref.counters[b]), a
+    assert int(c[dr.C_MAXSTEP]) > 0
+    U = f.U.cpu().numpy()              # the first pass of fresh fields: U = U_k
+    both = (np.abs(U) > 0) | (np.abs(ref.U) > 0)
+    assert (np.abs(U - ref.U)[both] / np.maximum(np.abs(ref.U[both]), 1e-30)).max() <= 1e-4
+    t = f.tally.cpu().numpy()
+    em = ref.tally[:, dr.T_EMITTED]
+    assert np.all(np.abs(t[:, dr.T_ESCAPED] - ref.tally[:, dr.T_ESCAPED]) <= 1e-6 * em)
+    G.close()
+
+
 TUNINGS = [
     {},
     {"lambda_tile": 1},

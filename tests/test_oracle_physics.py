@@ -315,3 +315,35 @@ def test_step1_deposits_stop_at_r_pre(orc):
     assert np.all(U[dmin >= r_pre] == 0.0)
     assert np.count_nonzero(dmin >= r_pre) > 0
     assert np.mean(U[dmin < 0.5 * r_pre] > 0) > 0.9
+
+
+def test_step_limit_counts_crossings_of_positive_length(orc):
+    """The per-ray step limit counts crossings of positive length: with a limit
+    of k, every ray makes min(k, its crossings) crossings, however many
+    zero-length grazes of edges and corners lie between them.  From the
+    centre of a cell of a uniform grid, the Nside 1 directions at longitude
+    pi/4 run through cell edges, so the walks hold grazes; the per-ray
+    crossings come from the plain walk (orc_crossings), independently of the
+    pass's loop."""
+    wl = W.plain16(n=8, nside=1, n_scatter=0)
+    g = wl.grid
+    m = orc.Model(g)
+    s = int(np.argmin(np.linalg.norm(g.centres() - np.array([0.5625, 0.4375, 0.5625]), axis=1)))
+    o = g.centres()[s]
+    full, grazes = [], 0
+    for p in range(12):
+        d = orc.healpix_vec(1, p)
+        full.append(len(m.crossings(o, d)[0]))
+        grazes += len(m.trace_cells(o, d)[0]) - full[-1]
+    assert grazes > 0
+    mask = np.zeros(g.n, np.uint8)
+    mask[s] = 1
+    pol = W.RayPolicy(adaptive=False, nside=1, nside_max=1, n_scatter=0)
+    for k in (1, 2, 3, 5):
+        r = m.run_pass(orc.DIRECT, pol, source_mask=mask, max_steps=k)
+        c = r.counters
+        assert c[orc.C_CROSS] == sum(min(k, n) for n in full), k
+        assert c[orc.C_MAXSTEP] + c[orc.C_ESCAPES] == c[orc.C_RAYS] == 12
+        assert c[orc.C_MAXSTEP] >= sum(1 for n in full if n > k)
+    r = m.run_pass(orc.DIRECT, pol, source_mask=mask, max_steps=max(full))
+    assert r.counters[orc.C_CROSS] == sum(full)
