@@ -1087,8 +1087,8 @@ struct AdaptArgs {
     uint64_t *counters;
     unsigned long long *queue;
     // deposit log (0 capacity: deposit with atomics)
-    uint32_t *log_key;
-    uint32_t *log_dir;
+    uint64_t *log_key;           // (cell << log_dir_bits) | direction entry
+    int32_t log_dir_bits;
     float *log_du;
     unsigned long long *log_count;
     int64_t log_cap;
@@ -1740,8 +1740,7 @@ void k_march_adaptive(const AdaptArgs A)
                 if (udep) {
                     const unsigned long long slot = base + __popcll(lm & ((1ull << lane) - 1ull));
                     if (slot < (unsigned long long)A.log_cap) {
-                        A.log_key[slot] = (uint32_t)s_cell[dslot];
-                        A.log_dir[slot] = (uint32_t)e;
+                        A.log_key[slot] = ((uint64_t)(uint32_t)s_cell[dslot] << A.log_dir_bits) | (uint64_t)e;
 #pragma unroll
                         for (int l = 0; l < NL; ++l)
                             if (l < nl) A.log_du[(int64_t)l * A.log_cap + slot] = s_du[l][dslot];
@@ -2264,10 +2263,13 @@ void k_step1_quad(const AdaptArgs A)
 // ---------------------------------------------------------------------------
 // Expansion of the sorted deposit log.  Thread slots cover every
 // (wavelength, j_sca pixel) pair, and the first n_lambda threads also sum the
-// energy density; a block walks a contiguous range of cell-sorted tuples,
-// accumulates each cell's contributions in compensated (Kahan) registers and
-// adds them to S_next / U_k when the cell changes.  The scattered luminosity of a tuple is
-// albedo c alpha V du w(p|n) (the deposit du = ext / (alpha V c)).
+// energy density; a block walks a contiguous range of tuples sorted by
+// (cell, direction), accumulates each cell's contributions in compensated
+// (Kahan) registers and adds them to S_next / U_k when the cell changes.
+// Tuples of one cell and one direction (rays of different sources in the
+// same pixel) are summed first and their phase function evaluated once.
+// The scattered luminosity of a tuple is albedo c alpha V du w(p|n) (the
+// deposit du = ext / (alpha V c)).
 // ---------------------------------------------------------------------------
 
 constexpr int kExpandSlots = 8;        // pixel slots per thread: up to 2048 per block
@@ -2280,9 +2282,8 @@ __global__ void k_iota(uint32_t *p, int64_t n)
 }
 
 struct ExpandArgs {
-    const uint32_t *key;       // sorted cells
+    const uint64_t *key;       // sorted keys (cell << dir_bits) | direction entry
     const uint32_t *idx;       // tuple index of each sorted entry
-    const uint32_t *dir;       // direction entry per tuple
     const float *du;           // [nl][cap]
     const float4 *dirs;
     const float *invz;
@@ -2294,6 +2295,7 @@ struct ExpandArgs {
     int64_t cap;
     int64_t chunk;
     int32_t w_row;
+    int32_t dir_bits;
 };
 
 #ifndef DR_WAVES_EXPAND
@@ -2309,6 +2311,9 @@ void k_expand(const ExpandArgs X)
     __shared__ float4 t_n[kExpandBatch];
     __shared__ float t_a[NL + 1][kExpandBatch];   // du / Z per wavelength; row NL stays zero
     __shared__ float t_du[NL][kExpandBatch];
+    __shared__ uint8_t t_same[kExpandBatch];     // same (cell, direction) as the tuple before
+    __shared__ uint8_t t_head[kExpandBatch];     // the first tuple of each run, in order
+    __shared__ int t_nhead;
     const LambdaTable *lt = X.lt;
     const int nl = lt->n_lambda;
     for (int i = threadIdx.x; i < kScaDirs; i += blockDim.x) sca[i] = X.dirs[i];
@@ -2396,8 +2401,10 @@ void k_expand(const ExpandArgs X)
         if (threadIdx.x < nb) {
             const int64_t j = i + threadIdx.x;
             const uint32_t orig = X.idx[j];
-            const uint32_t e = X.dir[orig];
-            t_cell[threadIdx.x] = (int32_t)X.key[j];
+            const uint64_t key = X.key[j];
+            const uint32_t e = (uint32_t)(key & ((1ull << X.dir_bits) - 1ull));
+            t_cell[threadIdx.x] = (int32_t)(key >> X.dir_bits);
+            t_same[threadIdx.x] = threadIdx.x > 0 && X.key[j - 1] == key;
             t_n[threadIdx.x] = X.dirs[e];
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
@@ -2409,7 +2416,26 @@ void k_expand(const ExpandArgs X)
             }
         }
         __syncthreads();
-        for (int jj = 0; jj < nb; ++jj) {
+        // each run of one (cell, direction) is summed into its first tuple
+        // (thread l: wavelength l), and wave 0 lists the runs' first tuples
+        if (threadIdx.x < NL && threadIdx.x < nl) {
+            const int l = threadIdx.x;
+            for (int jj = nb - 1; jj > 0; --jj)
+                if (t_same[jj]) {
+                    t_a[l][jj - 1] += t_a[l][jj];
+                    t_du[l][jj - 1] += t_du[l][jj];
+                }
+        }
+        if (threadIdx.x < 64) {
+            const bool h = (int)threadIdx.x < nb && !t_same[threadIdx.x];
+            const uint64_t hm = __ballot(h);
+            if (h) t_head[__popcll(hm & ((1ull << threadIdx.x) - 1ull))] = (uint8_t)threadIdx.x;
+            if (threadIdx.x == 0) t_nhead = __popcll(hm);
+        }
+        __syncthreads();
+        const int nh = t_nhead;
+        for (int q = 0; q < nh; ++q) {
+            const int jj = t_head[q];
             const int32_t cell = t_cell[jj];
             if (cell != cur) {
                 flush();
@@ -2884,7 +2910,7 @@ static void free_grid(Grid &g)
     g.ev_pool.clear();
     void *ptrs[] = {g.mir, g.first, g.reps, g.pmir, g.esc_tmp, g.dust_word, g.ps_pos, g.ps_xyz, g.ps_cell, g.ps_lum, g.ps_lum64, g.rec, g.ull_t, g.rho_bar, g.own.esc64, g.sbar[0], g.sbar[1], g.leaf_box, g.rho, g.inv_vc, g.emis_lum, g.lum64, g.own.n_all, g.own.err_word, g.root_tab, g.nodes, g.morton, g.by_level, g.d_lt, g.own.U_k,
                     g.own.flags, g.cell_flag, g.own.src_list, g.own.scan_blocks, g.own.n_src, g.own.dsum, g.s1_sum, g.own.ubar, g.dir_all, g.dir64, g.invz, g.sca64, g.wtab, g.queue, g.log_key, g.log_key2,
-                    g.log_idx, g.log_idx2, g.log_dir, g.log_du, g.log_count, g.sort_tmp};
+                    g.log_idx, g.log_idx2, g.log_du, g.log_count, g.sort_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -3213,19 +3239,22 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
         // most 16 GiB): fewer log-full restarts of the march per pass
         size_t fr = 0, tt = 0;
         if (hipMemGetInfo(&fr, &tt) != hipSuccess || fr == 0) fr = (size_t)16 << 30;
-        const int64_t per_tuple = 20 + 4 * (int64_t)nl;
+        const int64_t per_tuple = 24 + 4 * (int64_t)nl;
         const int64_t by_mem = (int64_t)(std::min<size_t>(fr / 8, (size_t)16 << 30) / (size_t)per_tuple);
         const int64_t lcap = std::max<int64_t>((int64_t)1 << 16,
                                                std::min<int64_t>(std::min<int64_t>((int64_t)1 << 28, 1024 * n), by_mem));
         int rl[] = {dalloc(g, &g.log_key, (size_t)lcap), dalloc(g, &g.log_key2, (size_t)lcap),
                     dalloc(g, &g.log_idx, (size_t)lcap), dalloc(g, &g.log_idx2, (size_t)lcap),
-                    dalloc(g, &g.log_dir, (size_t)lcap), dalloc(g, &g.log_du, (size_t)lcap * nl),
-                    dalloc(g, &g.log_count, 1)};
+                    dalloc(g, &g.log_du, (size_t)lcap * nl), dalloc(g, &g.log_count, 1)};
         int bad = 0;
         for (int r : rl) bad |= r;
-        while ((1ll << g.key_bits) < n) ++g.key_bits;
+        int cell_bits = 1;
+        while ((1ll << cell_bits) < n) ++cell_bits;
+        while ((1ll << g.dir_bits) < g.ndir_all) ++g.dir_bits;
+        g.key_bits = cell_bits + g.dir_bits;
         if (!bad) {
-            hipcub::DoubleBuffer<uint32_t> kb(g.log_key, g.log_key2), vb(g.log_idx, g.log_idx2);
+            hipcub::DoubleBuffer<uint64_t> kb(g.log_key, g.log_key2);
+            hipcub::DoubleBuffer<uint32_t> vb(g.log_idx, g.log_idx2);
             size_t tb = 0;
             hipError_t qe = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, kb, vb, (int)lcap, 0, g.key_bits, g.stream);
             if (qe != hipSuccess) bad = 1;
@@ -3342,7 +3371,7 @@ int dartray_workspace_bytes(const dartray_grid *grid, const dartray_trace_opts *
     } else if (!step1) {
         b += n * nl * sizeof(float) + (size_t)g.ndir_all * nl * sizeof(float);   // U_LL copy, phase normalisation
         if (g.log_cap > 0)
-            b += (size_t)g.log_cap * (5 * sizeof(uint32_t) + nl * sizeof(float)) + g.sort_tmp_bytes;
+            b += (size_t)g.log_cap * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t) + nl * sizeof(float)) + g.sort_tmp_bytes;
     }
     *bytes = b;
     return DARTRAY_OK;
@@ -3880,7 +3909,7 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
     const bool use_log = !step1 && g.log_cap > 0;
     g.prof_kind = step1 ? DARTRAY_PROF_STEP1 : DARTRAY_PROF_SCATTERING;
     A.log_key = g.log_key;
-    A.log_dir = g.log_dir;
+    A.log_dir_bits = g.dir_bits;
     A.log_du = g.log_du;
     A.log_count = g.log_count;
     A.log_cap = use_log ? g.log_cap : 0;
@@ -3912,13 +3941,14 @@ static int run_adaptive_pass(Grid &g, const dartray_trace_opts *o, dartray_field
             hipLaunchKernelGGL(k_iota, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 8192)), dim3(256), 0,
                                g.stream, g.log_idx, cnt);
             DR_LAUNCH_CHECK("k_iota");
-            hipcub::DoubleBuffer<uint32_t> kb(g.log_key, g.log_key2), vb(g.log_idx, g.log_idx2);
+            hipcub::DoubleBuffer<uint64_t> kb(g.log_key, g.log_key2);
+            hipcub::DoubleBuffer<uint32_t> vb(g.log_idx, g.log_idx2);
             size_t tb = g.sort_tmp_bytes;
             DR_HIP(hipcub::DeviceRadixSort::SortPairs(g.sort_tmp, tb, kb, vb, (int)cnt, 0, g.key_bits, g.stream));
             ExpandArgs X{};
             X.key = kb.Current();
             X.idx = vb.Current();
-            X.dir = g.log_dir;
+            X.dir_bits = g.dir_bits;
             X.du = g.log_du;
             X.dirs = g.dir_all;
             X.invz = g.invz;

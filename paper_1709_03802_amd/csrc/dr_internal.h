@@ -140,17 +140,18 @@ struct Grid {
     double *esc_tmp = nullptr;            // [nl][12 * 16^2] escape by direction before folding
 
     // deposit log of the adaptive passes that scatter light: one tuple
-    // (cell, direction entry, per-wavelength energy-density deposit) per
-    // depositing crossing, radix-sorted by cell and expanded per cell
+    // (cell and direction entry as one key, per-wavelength energy-density
+    // deposit) per depositing crossing, radix-sorted by (cell, direction) and
+    // expanded per cell, once per run of one direction
     int64_t log_cap = 0;
-    uint32_t *log_key = nullptr, *log_key2 = nullptr;
+    uint64_t *log_key = nullptr, *log_key2 = nullptr;   // (cell << dir_bits) | direction entry
     uint32_t *log_idx = nullptr, *log_idx2 = nullptr;
-    uint32_t *log_dir = nullptr;
     float *log_du = nullptr;              // [nl][log_cap]
     unsigned long long *log_count = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
-    int32_t key_bits = 1;
+    int32_t key_bits = 1;                 // bits of the sort key
+    int32_t dir_bits = 1;                 // bits of a direction entry
     int64_t log_chunks = 0;               // launches of the last adaptive pass
 
 
