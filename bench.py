@@ -52,15 +52,15 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # kernel sources hashed here (null traffic once the sources change)
 PMC_TRAFFIC = {
     "disk": {
-        # k_step1_quad<8>, per launch: 4.4318e9 KiB fetched x2, 7.3911e9 KiB written x1
-        "bytes_per_launch": 9.0763e+12 + 7.5685e+12,
-        "sources_sha256": "377c4189ac147913a8243def880441b22d6fd07169475e8e9de56ab953062d7c",
+        # k_step1_quad<8>, per launch: 4.4318e9 KiB fetched x2, 7.3879e9 KiB written x1
+        "bytes_per_launch": 9.0764e+12 + 7.5652e+12,
+        "sources_sha256": "cd6dbba7582dad2dd4d5b5b3b887f817134603992de1fea216050719ccb8b602",
         "profile": "profiles/k_step1_quad_disk.md",
     },
     "clumpy128": {
-        # k_march_fixed<16>, per launch (average of the run's 5): 2.5943e9 KiB fetched x2, 6.7823e9 KiB written x1
-        "bytes_per_launch": 5.3131e+12 + 6.9451e+12,
-        "sources_sha256": "377c4189ac147913a8243def880441b22d6fd07169475e8e9de56ab953062d7c",
+        # k_march_fixed<16>, per launch (average of the run's 5): 2.5948e9 KiB fetched x2, 6.7823e9 KiB written x1
+        "bytes_per_launch": 5.3142e+12 + 6.9451e+12,
+        "sources_sha256": "cd6dbba7582dad2dd4d5b5b3b887f817134603992de1fea216050719ccb8b602",
         "profile": "profiles/k_march_fixed_clumpy128.md",
     },
 }
