@@ -404,6 +404,27 @@ __device__ inline float g_series(float tau)
     return fmaf(p, x, 1.f);
 }
 
+// g = (1 - e^{-tau}) / tau in FP64 for 0 <= tau < 0.5: the Taylor series
+// sum_k (-tau)^k / (k + 1)! through k = 13 (truncation under 5e-17 relative)
+__device__ inline double g_series64(double tau)
+{
+    const double x = -tau;
+    double p = 1.0 / 87178291200.0;           // 1 / 14!
+    p = fma(p, x, 1.0 / 6227020800.0);
+    p = fma(p, x, 1.0 / 479001600.0);
+    p = fma(p, x, 1.0 / 39916800.0);
+    p = fma(p, x, 1.0 / 3628800.0);
+    p = fma(p, x, 1.0 / 362880.0);
+    p = fma(p, x, 1.0 / 40320.0);
+    p = fma(p, x, 1.0 / 5040.0);
+    p = fma(p, x, 1.0 / 720.0);
+    p = fma(p, x, 1.0 / 120.0);
+    p = fma(p, x, 1.0 / 24.0);
+    p = fma(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    return fma(p, x, 1.0);
+}
+
 __device__ inline float fast_g(float tau, bool &thick, float &tr)
 {
     thick = tau >= 0.5f;
@@ -1211,11 +1232,9 @@ void k_march_adaptive(const AdaptArgs A)
 
     // ray state.  Step 1 carries the ray's luminosity in FP32 (its decisions
     // are geometric).  The passes that take per-wavelength significance
-    // decisions (Eq. 1 / Eq. 8) carry the item's FP64 launch luminosity L0
-    // and the column density N = sum rho l from the source to the ray's
-    // position: the luminosity at any point is L0 4^-depth e^{-kappa N}, in
-    // FP64 as in the oracle, so no decision rests on FP32 rounding or
-    // underflow.
+    // decisions (Eq. 1 / Eq. 8) carry it in FP64 per wavelength, attenuated
+    // crossing by crossing as in the oracle, so no decision rests on FP32
+    // rounding or underflow.
     bool has_ray = false, has_item = false, pending = false, done = false;
     int32_t s = 0;
     int32_t own_c = -1;            // the source's own cell (no split or block test there)
@@ -1228,26 +1247,25 @@ void k_march_adaptive(const AdaptArgs A)
     RayT<double> R;
     float L[STEP1 ? NL : 1];
     double L0[STEP1 ? 1 : NL];
-    double colN = 0.0;             // column density, physical length units
     double st_t[kMaxDepthAdaptive + 1];
     int32_t st_c[kMaxDepthAdaptive + 1];   // cell in which the level's parent split
     float st_L[STEP1 ? kMaxDepthAdaptive + 1 : 1][STEP1 ? NL : 1];
-    double st_N[STEP1 ? 1 : kMaxDepthAdaptive + 1];
-    // merging state (MERGE only): the explicit FP64 luminosity outside step
-    // 1, what the children of each level start with, and per level the
-    // paused children (bitmask, distance, cell, luminosity), the plane they
-    // crossed (0 none yet, -1 not all the same) and whether the level is
-    // resuming them; bit d of can_low: the ray at depth d may pause
-    constexpr int KD = MERGE ? kMaxDepthAdaptive + 1 : 1;
-    constexpr bool XL = MERGE && !STEP1;
+    // the FP64 luminosity outside step 1 and what the children of each
+    // level start with
+    constexpr bool XL = !STEP1;
     double Lx[XL ? NL : 1];
-    double st_Lx[XL ? KD : 1][XL ? NL : 1];
+    double st_Lx[XL ? kMaxDepthAdaptive + 1 : 1][XL ? NL : 1];
+    // merging state (MERGE only): per level the paused children (bitmask,
+    // distance, cell, luminosity), the plane they crossed (0 none yet, -1 not
+    // all the same) and whether the level is resuming them; bit d of
+    // can_low: the ray at depth d may pause
+    constexpr int KD = MERGE ? kMaxDepthAdaptive + 1 : 1;
     uint8_t g_low[KD], g_res[KD];
     int32_t g_pl[KD];
     double g_t[KD][4];
     int32_t g_c[KD][4];
     float g_Ls[MERGE && STEP1 ? KD : 1][4][MERGE && STEP1 ? NL : 1];
-    double g_Ld[XL ? KD : 1][4][XL ? NL : 1];
+    double g_Ld[MERGE && XL ? KD : 1][4][MERGE && XL ? NL : 1];
     uint32_t can_low = 0;
     int32_t entry_key = 0;         // plane through which the ray entered c: 1 + axis + 3 coordinate, 0 none
     int32_t start_c = -1;          // a resumed child starts in its own cell
@@ -1262,8 +1280,7 @@ void k_march_adaptive(const AdaptArgs A)
     // luminosity the ray carries at its current position, wavelength l
     auto lum = [&](int l) -> double {
         if constexpr (STEP1) return (double)L[l];
-        else if constexpr (XL) return Lx[l];
-        else return L0[l] * ldexp(1.0, -2 * depth) * exp(-(double)s_kap[l] * colN);
+        else return Lx[l];
     };
 
     while (true) {
@@ -1349,7 +1366,8 @@ void k_march_adaptive(const AdaptArgs A)
 #pragma unroll
                     for (int l = 0; l < NL; ++l) L[l] = st_L[depth][l];
                 } else {
-                    colN = st_N[depth];
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) Lx[l] = st_Lx[depth][l];
                 }
                 pending = true;
             } else {
@@ -1445,7 +1463,6 @@ void k_march_adaptive(const AdaptArgs A)
                             L0[l] = v;
                             lsum += v;
                         }
-                        colN = 0.0;
                         if constexpr (XL) {
 #pragma unroll
                             for (int l = 0; l < NL; ++l) Lx[l] = L0[l];
@@ -1551,15 +1568,16 @@ void k_march_adaptive(const AdaptArgs A)
                 const double side = (double)b.w * h;
                 const float lp = (float)(len * h);
                 // step 1: e^{-tau} - 1 per wavelength (FP32); other passes: the
-                // energy-density deposit and the extinguished luminosity of the
-                // crossing, computed in FP64 and rounded once
+                // mean luminosity over the crossing <L> = L (1 - e^{-tau}) / tau
+                // in FP64, from which the deposit, the extinguished luminosity
+                // and the transmission follow
                 float em1[STEP1 ? NL : 1];
-                float du32[STEP1 ? 1 : NL], ext32[STEP1 ? 1 : NL];
+                double lavg64[STEP1 ? 1 : NL];
                 uint32_t sigm = 0;
                 const float *ull = A.ull_t + (int64_t)c * nl;
+                if constexpr (STEP1) {
 #pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    if constexpr (STEP1) {
+                    for (int l = 0; l < NL; ++l) {
                         em1[l] = 0.f;
                         if (l < nl) {
                             const float tau = s_kap[l] * rho_c * lp;
@@ -1568,23 +1586,27 @@ void k_march_adaptive(const AdaptArgs A)
                             em1[l] = fast_em1(tau, thick, tr);
                             sigm |= 1u << l;
                         }
-                    } else {
-                        du32[l] = 0.f;
-                        ext32[l] = 0.f;
-                        if (l < nl) {
-                            // Eq. 8 estimate <L> / (Omega_HP d^2 c) against f_U U_LL (Eq. 1), in FP64
-                            const double lenp = len * h;
-                            const double alpha = (double)s_kap[l] * (double)rho_c;
-                            const double tau = alpha * lenp;
-                            const double Lin = lum(l);
-                            const double ext = Lin * -expm1(-tau);
-                            const double lavg = tau > 0.0 ? ext / tau : Lin;
-                            const bool sg = lavg > 0.0 &&
-                                            (c == own_c || lavg / (omega_hp * d2 * A.c_light) >= f_U * (double)ull[l]);
-                            sigm |= (uint32_t)sg << l;
-                            ext32[l] = (float)ext;
-                            du32[l] = (float)((alpha > 0.0 ? ext / alpha : Lin * lenp) * (double)rc.ivc);
-                        }
+                    }
+                } else {
+                    // Eq. 8 estimate <L> / (Omega_HP d^2 c) against f_U U_LL (Eq. 1), in FP64
+                    const double lenp = len * h;
+                    const double inv_den = 1.0 / (omega_hp * d2 * A.c_light);
+                    double tau[NL];
+                    double tmax = 0.0;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        tau[l] = (double)s_kap[l] * (double)rho_c * lenp;   // zero beyond n_lambda
+                        tmax = fmax(tmax, tau[l]);
+                    }
+                    const bool thin = __ballot(tmax >= 0.5) == 0;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        const double g = thin || tau[l] < 0.5 ? g_series64(tau[l]) : -expm1(-tau[l]) / tau[l];
+                        const double lavg = lum(l) * g;
+                        const bool sg = l < nl && lavg > 0.0 &&
+                                        (c == own_c || lavg * inv_den >= f_U * (double)ull[l < nl ? l : 0]);
+                        sigm |= (uint32_t)sg << l;
+                        lavg64[l] = lavg;
                     }
                 }
                 if (STEP1 && t_in >= A.r_pre_fine64) {
@@ -1608,14 +1630,12 @@ void k_march_adaptive(const AdaptArgs A)
                             L[l] *= 0.25f;
                             st_L[depth][l] = L[l];
                         }
-                    } else if constexpr (XL) {
+                    } else {
 #pragma unroll
                         for (int l = 0; l < NL; ++l) {
                             Lx[l] *= 0.25;
                             st_Lx[depth][l] = Lx[l];
                         }
-                    } else {
-                        st_N[depth] = colN;   // children restart with the column density of the split point
                     }
                     if constexpr (MERGE) {
                         g_low[depth] = 0;
@@ -1672,29 +1692,31 @@ void k_march_adaptive(const AdaptArgs A)
                                 L[l] = tau < 0.5f ? fmaf(L[l], em1[l], L[l])
                                                   : L[l] * __builtin_amdgcn_exp2f(-tau * 1.44269504088896341f);
                             } else {
+                                // extinguished luminosity <L> tau, deposit <L> l / (V c)
+                                const double lenp = len * h;
+                                const double tau = (double)s_kap[l] * (double)rho_c * lenp;
+                                const double ext = lavg64[l] * tau;
+                                const float ext32 = (float)ext;
                                 float Fl = 0.f;
                                 float du = 0.f;
                                 if ((sigm >> l) & 1u) {
-                                    du = du32[l];
+                                    du = (float)(lavg64[l] * lenp * (double)ivc);
                                     ++n_dep;
-                                    Fl = s_alb[l] * ext32[l] * izr[l] * s_hgA[l];
+                                    Fl = s_alb[l] * ext32 * izr[l] * s_hgA[l];
                                 } else {
-                                    skp[l] += ext32[l];
+                                    skp[l] += ext32;
                                     ++n_skip;
                                 }
+                                // transmission: L - <L> tau = L e^{-tau} below tau 0.5, where
+                                // it keeps extinguished + transmitted equal to the input
+                                Lx[l] = tau < 0.5 ? Lx[l] - ext : Lx[l] * exp(-tau);
                                 s_F[l][threadIdx.x] = Fl;
                                 deposit |= Fl != 0.f;
                                 s_du[l][dslot] = du;
                             }
                         }
                     }
-                    if constexpr (XL) {
-#pragma unroll
-                        for (int l = 0; l < NL; ++l)
-                            if (l < nl) Lx[l] *= exp(-((double)s_kap[l] * (double)rho_c) * (len * h));
-                    }
                     if constexpr (!STEP1) {
-                        colN += (double)rho_c * (len * h);   // the crossing attenuates every wavelength
                         if (deposit)
                             s_dep[threadIdx.x] =
                                 make_float4((float)R.n[0], (float)R.n[1], (float)R.n[2], __int_as_float(c));
