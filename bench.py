@@ -52,15 +52,15 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # kernel sources hashed here (null traffic once the sources change)
 PMC_TRAFFIC = {
     "disk": {
-        # k_step1_quad<8>, per launch: 4.4318e9 KiB fetched x2, 7.3879e9 KiB written x1
-        "bytes_per_launch": 9.0764e+12 + 7.5652e+12,
-        "sources_sha256": "cd6dbba7582dad2dd4d5b5b3b887f817134603992de1fea216050719ccb8b602",
+        # k_step1_quad<8>, per launch: 4.4315e9 KiB fetched x2, 7.3875e9 KiB written x1
+        "bytes_per_launch": 9.0757e+12 + 7.5648e+12,
+        "sources_sha256": "6d4951fa921b78ce502d3ef42931125b717454d870c1bb6197d9e9b23657b7c1",
         "profile": "profiles/k_step1_quad_disk.md",
     },
     "clumpy128": {
-        # k_march_fixed<16>, per launch (average of the run's 5): 2.5948e9 KiB fetched x2, 6.7823e9 KiB written x1
-        "bytes_per_launch": 5.3142e+12 + 6.9451e+12,
-        "sources_sha256": "cd6dbba7582dad2dd4d5b5b3b887f817134603992de1fea216050719ccb8b602",
+        # k_march_fixed<16>, per launch (average of the run's 5): 2.5954e9 KiB fetched x2, 6.7823e9 KiB written x1
+        "bytes_per_launch": 5.3154e+12 + 6.9451e+12,
+        "sources_sha256": "6d4951fa921b78ce502d3ef42931125b717454d870c1bb6197d9e9b23657b7c1",
         "profile": "profiles/k_march_fixed_clumpy128.md",
     },
 }
