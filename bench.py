@@ -69,9 +69,9 @@ PMC_TRAFFIC = {
 # rocprofv3 TCC_ATOMIC (lanes whose cells share a 64-byte segment share one)
 PMC_ADJOINT = {
     "workload": "clumpy64",
-    "bytes_per_step": 2.0580e+12 + 2.8701e+11,
-    "atomic_requests_per_step": 7.4174e+09,
-    "sources_sha256": "608cac3514d632f4c5c1d8321b02dd29be5e62db23aefc70b98a06407b3bc601",
+    "bytes_per_step": 2.0422e+12 + 2.8701e+11,
+    "atomic_requests_per_step": 7.4175e+09,
+    "sources_sha256": "6d4951fa921b78ce502d3ef42931125b717454d870c1bb6197d9e9b23657b7c1",
     "profile": "profiles/k_march_adjoint_clumpy64_l4.md",
 }
 

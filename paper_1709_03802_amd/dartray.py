@@ -510,6 +510,11 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, rho, grid, policy, frame=None):
+            # outputs the loss does not use get no gradient (None, not a
+            # zero tensor), so the adjoint skips their terms: an all-zero
+            # dJ/dS_total would still gather the scattered-light gradient
+            # for the last scattering pass
+            ctx.set_materialize_grads(False)
             grid.set_rho(rho.detach().contiguous())
             f = Fields(grid, escape_nside=policy.nside)
             opts = make_opts(policy, MODE_DIRECT, frame, counters=False)
