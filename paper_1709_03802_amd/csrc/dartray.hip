@@ -1066,7 +1066,9 @@ __global__ __launch_bounds__(256) void k_flush_fixed_multi(const FlushArgs *mode
 }
 
 // ---------------------------------------------------------------------------
-// Adaptive march (ray splitting and blocking, Sect. 3.1.1 / 3.2 / 3.5).
+// Adaptive march (ray splitting and blocking, Sect. 3.1.1 / 3.2 / 3.5): the
+// direct and scattering passes, and step 1 with ray merging (step 1 without
+// merging runs k_step1_quad, below).
 //
 // A persistent kernel: each lane takes work items (top-level pixel r0,
 // source) from a device counter, 64 at a time per wave, items ordered so that
@@ -1078,10 +1080,11 @@ __global__ __launch_bounds__(256) void k_flush_fixed_multi(const FlushArgs *mode
 // the next sibling is pix + 1 and the parent is pix >> 2.
 //
 // Every loop iteration advances each lane with a ray by one crossing; the
-// energy density is deposited lane by lane, the scattered luminosity
-// cooperatively: for each depositing lane the whole wave adds that crossing's
-// phase-weighted luminosity to the cell's HEALPix row, 64 pixels per
-// instruction.
+// energy density is deposited lane by lane, the scattered luminosity through
+// the deposit log (expanded per cell after the launch) or, for what the log
+// cannot take, cooperatively: for each depositing lane the whole wave adds
+// that crossing's phase-weighted luminosity to the cell's HEALPix row, 64
+// pixels per instruction.
 // ---------------------------------------------------------------------------
 
 struct AdaptArgs {
@@ -1167,11 +1170,6 @@ __device__ inline int readlane_i(int v, int j) { return __builtin_amdgcn_readlan
 #endif
 #ifndef DR_FETCH_MIN_STEP1
 #define DR_FETCH_MIN_STEP1 4
-#endif
-// step 1 without merging by teams of four lanes (k_step1_quad); 0 keeps
-// the lane-per-item march for it
-#ifndef DR_STEP1_QUAD
-#define DR_STEP1_QUAD 1
 #endif
 #ifndef DR_FETCH_MIN_SCATTER
 #define DR_FETCH_MIN_SCATTER 32
@@ -3849,11 +3847,7 @@ static void launch_adaptive(const AdaptArgs &A, int mode, hipStream_t s, unsigne
     const bool merge = A.n_rays_max > 0.0;
     if (mode == 0) {
         if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 0, true>), dim3(blocks), dim3(256), 0, s, A);
-#if DR_STEP1_QUAD
         else hipLaunchKernelGGL((k_step1_quad<NL>), dim3(blocks), dim3(256), 0, s, A);
-#else
-        else hipLaunchKernelGGL((k_march_adaptive<NL, 0, false>), dim3(blocks), dim3(256), 0, s, A);
-#endif
     } else if (mode == 1) {
         if (merge) hipLaunchKernelGGL((k_march_adaptive<NL, 1, true>), dim3(blocks), dim3(256), 0, s, A);
         else hipLaunchKernelGGL((k_march_adaptive<NL, 1, false>), dim3(blocks), dim3(256), 0, s, A);
