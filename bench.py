@@ -585,10 +585,11 @@ def measure(dr, W, name, steps, warmup, args, timed_counting=False):
         kernel = f"k_step1_quad<{nl_pow2(grid.n_lambda)}> (step 1)"
         impl_bytes = 64 + 2 * 8 * grid.n_lambda * rows_per_cross
     else:
+        # the crossings of a quad's parallel rays into one cell share a row
         kern_cross = crossings
-        rows_per_cross = 1.0
+        rows_per_cross = int(counters[:, dr.C_U_ROWS].sum()) / max(kern_cross, 1)
         kernel = f"k_march_fixed<{nl_pow2(grid.n_lambda)}>"
-        impl_bytes = 64 + 2 * 4 * grid.n_lambda
+        impl_bytes = 64 + 2 * 4 * grid.n_lambda * rows_per_cross
     per_cross = algorithmic_bytes(pol, grid)
     launches_per_step = launches / steps_done
     avg_ms = kern_ms / max(launches, 1)

@@ -89,9 +89,10 @@ extern "C" {
 #define DARTRAY_C_SKIPS 6           /* crossing x wavelength skipped (Sect. 3.2) */
 #define DARTRAY_C_MAXSTEP 7         /* rays stopped by max_steps */
 #define DARTRAY_C_MERGES 8          /* groups of 4 rays merged into 1 (Eq. 3) */
-#define DARTRAY_C_U_ROWS 9          /* step 1 without merging: energy-density rows written, one atomic
-                                       request of n_lambda FP64 values each (the crossings of sibling
-                                       rays into one cell in the same step share a row); 0 otherwise */
+#define DARTRAY_C_U_ROWS 9          /* rows of per-wavelength deposits written, one atomic row each:
+                                       step 1 without merging (FP64 energy density) and fixed rays
+                                       (FP32 direction bins), where the crossings of a quad's rays
+                                       into one cell share a row; 0 in the other passes */
 #define DARTRAY_N_COUNT 16          /* slots of the counters buffer (10 .. 15 stay zero) */
 
 typedef struct dartray_grid dartray_grid;   /* opaque handle */

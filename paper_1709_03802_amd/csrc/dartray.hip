@@ -616,19 +616,35 @@ __device__ inline float fixed_launch(const FixedArgs &A, const LambdaTable *lt, 
     return v;
 }
 
+// v of lane (k + R) & 3 of this lane's quad (k its place in the quad)
+template <int R>
+__device__ inline int quad_rot(int v)
+{
+    constexpr int ctrl = ((0 + R) & 3) | (((1 + R) & 3) << 2) | (((2 + R) & 3) << 4) | (((3 + R) & 3) << 6);
+    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+}
+
+template <int R>
+__device__ inline float quad_rot_f(float v)
+{
+    return __int_as_float(quad_rot<R>(__float_as_int(v)));
+}
+
 // per-lane counters
 template <int NL>
 struct FixedAcc {
-    uint32_t ncross, nrays, nmax;
-    __device__ void clear() { ncross = nrays = nmax = 0; }
+    uint32_t ncross, nrays, nmax, nrows;
+    __device__ void clear() { ncross = nrays = nmax = nrows = 0; }
 };
 
 // LDS of the march (256-thread workgroups at most): each wave's deposit
 // staging, its wavelengths' opacities and its FP64 escaped-luminosity sums
 template <int NL>
 struct FixedStage {
-    float du[NL][256];
+    float du[NL][256];           // each lane's deposit row of the step
     int32_t cell[256];
+    float ed[NL][256];           // rows going out, at compacted slots
+    int32_t ecell[256];
     uint8_t list[256];
     float kap[4][NL];
     double esc[4][NL];
@@ -646,7 +662,13 @@ __device__ inline void wave_sync_lds()
 // wave's lanes walk their rays in lock step, one cell per iteration, and the
 // iteration's deposits go out wave-cooperatively: the wavelength values of a
 // crossing are one contiguous row of the bin array, and one atomic
-// instruction carries 64 / NL crossings.
+// instruction carries 64 / NL crossings.  A tile of a dense source list is a
+// 4 x 4 x 4 block of cells (Morton order); each quad of lanes takes four of
+// them on a line along the direction's dominant axis, so the quad's parallel
+// rays, less than a cell apart sideways near that axis, cross many cells a
+// step or two apart.  As in the step-1 team march, a row stays with its quad
+// for one more step and the quad's deposits into its cell join it; rows of
+// one cell in one step are summed by the lowest lane.
 template <int NL>
 __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, FixedStage<NL> &st, FixedAcc<NL> &acc)
 {
@@ -657,7 +679,22 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     const int wbase = threadIdx.x & ~63;
     const int w = threadIdx.x >> 6;
     const int r = A.r0 + rl;
-    const int64_t si = tile * 64 + lane;
+    const double4 nd = A.dirs[r];
+    // lane (q, k) of a quad -> source m of the tile: the Morton bits of the
+    // dominant axis (x, y, z are bits 0-2 and 3-5) take k, the others q
+    int ax = 0;
+    {
+        const double ax0 = fabs(nd.x), ax1 = fabs(nd.y), ax2 = fabs(nd.z);
+        ax = ax1 > ax0 ? (ax2 > ax1 ? 2 : 1) : (ax2 > ax0 ? 2 : 0);
+    }
+    const int qk = lane & 3, qq = lane >> 2;
+    int m = ((qk & 1) << ax) | ((qk >> 1) << (ax + 3));
+    for (int b = 0, j = 0; b < 6; ++b) {
+        if (b == ax || b == ax + 3) continue;
+        m |= ((qq >> j) & 1) << b;
+        ++j;
+    }
+    const int64_t si = tile * 64 + m;
     bool active = si < nsrc;
     int32_t c = 0;
     // FP64 geometry: distances along a ray reach hundreds of cells, where FP32
@@ -670,7 +707,6 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     wave_sync_lds();
     if (active) {
         const int32_t s = A.src_list[si];
-        const double4 nd = A.dirs[r];
         R.n[0] = nd.x;
         R.n[1] = nd.y;
         R.n[2] = nd.z;
@@ -708,6 +744,30 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     double t = 0.0;
     int64_t steps = 0;
     float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
+    // the row this lane holds for one more step: cell (-1 none), values
+    int32_t h_cell = -1;
+    float h_du[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) h_du[l] = 0.f;
+    // rows go out as atomic instructions over 64 / NL rows each
+    auto emit_rows = [&](bool has) {
+        const uint64_t om = __ballot(has);
+        if (has) {
+            const int slot = wbase + __popcll(om & ((1ull << lane) - 1ull));
+            st.ecell[slot] = h_cell;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) st.ed[l][slot] = h_du[l];
+        }
+        wave_sync_lds();
+        const int cnt = __popcll(om);
+        constexpr int PER = 64 / NL;
+        for (int k0 = 0; k0 < cnt; k0 += PER) {
+            const int q = k0 + lane / NL;
+            const int l = lane % NL;
+            if (q < cnt && l < nlc) atomic_add_f32(ubase + (size_t)st.ecell[wbase + q] * nl + l, st.ed[l][wbase + q]);
+        }
+        wave_sync_lds();
+    };
     while (__ballot(active)) {
         bool dep = false;
         if (active) {
@@ -764,25 +824,49 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                     }
             }
         }
-        // lanes q of an instruction add value q % NL of the (q / NL)-th
-        // depositing lane
-        const uint64_t dm = __ballot(dep);
-        if (dm) {
-            if (dep) st.list[wbase + __popcll(dm & ((1ull << lane) - 1ull))] = (uint8_t)lane;
-            wave_sync_lds();
-            const int cnt = __popcll(dm);
-            constexpr int PER = 64 / NL;
-            for (int k0 = 0; k0 < cnt; k0 += PER) {
-                const int q = k0 + lane / NL;
-                const int l = lane % NL;
-                if (q < cnt && l < nlc) {
-                    const int j = st.list[wbase + q];
-                    atomic_add_f32(ubase + (size_t)st.cell[wbase + j] * nl + l, st.du[l][wbase + j]);
+        // ---- rows: (1) the quad's deposits into cells whose rows are held
+        // join them; (2) of the other deposits, the lowest lane of each cell
+        // takes the row; (3) the held rows go out; (4) the new rows are held
+        wave_sync_lds();
+        const int32_t dcell = dep ? st.cell[threadIdx.x] : -1;
+        const int32_t c1 = quad_rot<1>(dcell), c2 = quad_rot<2>(dcell), c3 = quad_rot<3>(dcell);
+        const int32_t h1 = quad_rot<1>(h_cell), h2 = quad_rot<2>(h_cell), h3 = quad_rot<3>(h_cell);
+        const bool joined = dep && (dcell == h_cell || dcell == h1 || dcell == h2 || dcell == h3);
+        const bool held = h_cell >= 0;
+        const bool fresh = dep && !joined;
+        const bool e1 = fresh && c1 == dcell, e2 = fresh && c2 == dcell, e3 = fresh && c3 == dcell;
+        const bool owner = fresh && !(e1 && qk >= 3) && !(e2 && qk >= 2) && !(e3 && qk >= 1);
+        if (held) {
+            // the deposits of this lane (k) and of lane (k + r) & 3 into the held cell
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int32_t cr = r == 0 ? dcell : r == 1 ? c1 : r == 2 ? c2 : c3;
+                if (cr == h_cell) {
+                    const int src = wbase + (lane & ~3) + ((qk + r) & 3);
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) h_du[l] += st.du[l][src];
                 }
             }
-            wave_sync_lds();
         }
+        if (owner) {
+            // the lanes above this one depositing into its cell add to its row
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const bool er = r == 1 ? e1 : r == 2 ? e2 : e3;
+                if (er && qk + r < 4) {
+                    const int src = wbase + (lane & ~3) + qk + r;
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) st.du[l][threadIdx.x] += st.du[l][src];
+                }
+            }
+        }
+        emit_rows(held);
+        acc.nrows += owner ? 1u : 0u;
+        h_cell = owner ? dcell : -1;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) h_du[l] = owner ? st.du[l][threadIdx.x] : 0.f;
     }
+    emit_rows(h_cell >= 0);
     if (A.esc_dir) {
         // all rays of the item share direction r: one FP64 add per wavelength
         wave_sync_lds();
@@ -811,8 +895,10 @@ __device__ void fixed_commit(const FixedArgs &A, FixedStage<NL> &st, FixedAcc<NL
     }
     wave_sync_lds();
     if (A.counters) {
-        const uint64_t wc = wave_sum_u64(acc.ncross), wr = wave_sum_u64(acc.nrays), wm = wave_sum_u64(acc.nmax);
+        const uint64_t wc = wave_sum_u64(acc.ncross), wr = wave_sum_u64(acc.nrays), wm = wave_sum_u64(acc.nmax),
+                       wu = wave_sum_u64(acc.nrows);
         if (lane == 0) {
+            if (wu) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_U_ROWS], (unsigned long long)wu);
             if (wc) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_CROSSINGS], (unsigned long long)wc);
             if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_RAYS], (unsigned long long)wr);
             if (wr) atomicAdd((unsigned long long *)&A.counters[DARTRAY_C_ESCAPES], (unsigned long long)(wr - wm));
@@ -1869,20 +1955,6 @@ void k_march_adaptive(const AdaptArgs A)
 // march; only the order of the FP64 atomic adds and the FP32 pre-sums of
 // equal-cell rows differ.
 // ---------------------------------------------------------------------------
-
-// v of lane (k + R) & 3 of this lane's quad (k its place in the quad)
-template <int R>
-__device__ inline int quad_rot(int v)
-{
-    constexpr int ctrl = ((0 + R) & 3) | (((1 + R) & 3) << 2) | (((2 + R) & 3) << 4) | (((3 + R) & 3) << 6);
-    return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
-}
-
-template <int R>
-__device__ inline float quad_rot_f(float v)
-{
-    return __int_as_float(quad_rot<R>(__float_as_int(v)));
-}
 
 template <int NL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DR_WAVES_STEP1, 8)))
