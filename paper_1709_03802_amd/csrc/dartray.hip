@@ -666,9 +666,10 @@ __device__ inline void wave_sync_lds()
 // 4 x 4 x 4 block of cells (Morton order); each quad of lanes takes four of
 // them on a line along the direction's dominant axis, so the quad's parallel
 // rays, less than a cell apart sideways near that axis, cross many cells a
-// step or two apart.  As in the step-1 team march, a row stays with its quad
-// for one more step and the quad's deposits into its cell join it; rows of
-// one cell in one step are summed by the lowest lane.
+// step or two apart.  Rows of one cell in one step are summed by the lowest
+// lane, and a row stays open while the quad keeps depositing into its cell
+// (it moves to the lowest lane depositing there); it goes out at the first
+// step in which no lane of the quad deposits into that cell.
 template <int NL>
 __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, FixedStage<NL> &st, FixedAcc<NL> &acc)
 {
@@ -744,20 +745,25 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     double t = 0.0;
     int64_t steps = 0;
     float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
-    // the row this lane holds for one more step: cell (-1 none), values
+    // the row this lane holds: cell (-1 none), values
     int32_t h_cell = -1;
     float h_du[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) h_du[l] = 0.f;
-    // rows go out as atomic instructions over 64 / NL rows each
-    auto emit_rows = [&](bool has) {
-        const uint64_t om = __ballot(has);
-        if (has) {
-            const int slot = wbase + __popcll(om & ((1ull << lane) - 1ull));
+    // staging of the held rows in the wave's 64 slots of st.ed: the rows that
+    // go out compacted from the bottom, the rows that stay open compacted from
+    // the top; then the outgoing rows as atomic instructions over 64 / NL rows
+    // each
+    auto stage_rows = [&](bool out, bool keep) {
+        const uint64_t om = __ballot(out), km = __ballot(keep);
+        if (out || keep) {
+            const uint64_t below = (1ull << lane) - 1ull;
+            const int slot = out ? wbase + __popcll(om & below) : wbase + 63 - __popcll(km & below);
             st.ecell[slot] = h_cell;
 #pragma unroll
             for (int l = 0; l < NL; ++l) st.ed[l][slot] = h_du[l];
         }
+        acc.nrows += out ? 1u : 0u;
         wave_sync_lds();
         const int cnt = __popcll(om);
         constexpr int PER = 64 / NL;
@@ -766,7 +772,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
             const int l = lane % NL;
             if (q < cnt && l < nlc) atomic_add_f32(ubase + (size_t)st.ecell[wbase + q] * nl + l, st.ed[l][wbase + q]);
         }
-        wave_sync_lds();
+        return km;
     };
     while (__ballot(active)) {
         bool dep = false;
@@ -824,49 +830,50 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                     }
             }
         }
-        // ---- rows: (1) the quad's deposits into cells whose rows are held
-        // join them; (2) of the other deposits, the lowest lane of each cell
-        // takes the row; (3) the held rows go out; (4) the new rows are held
+        // ---- rows: a held row stays open while the quad keeps depositing
+        // into its cell and moves to the lowest lane depositing there; the
+        // lowest lane of each other cell opens a row; the rest go out
         wave_sync_lds();
         const int32_t dcell = dep ? st.cell[threadIdx.x] : -1;
         const int32_t c1 = quad_rot<1>(dcell), c2 = quad_rot<2>(dcell), c3 = quad_rot<3>(dcell);
         const int32_t h1 = quad_rot<1>(h_cell), h2 = quad_rot<2>(h_cell), h3 = quad_rot<3>(h_cell);
-        const bool joined = dep && (dcell == h_cell || dcell == h1 || dcell == h2 || dcell == h3);
         const bool held = h_cell >= 0;
-        const bool fresh = dep && !joined;
-        const bool e1 = fresh && c1 == dcell, e2 = fresh && c2 == dcell, e3 = fresh && c3 == dcell;
-        const bool owner = fresh && !(e1 && qk >= 3) && !(e2 && qk >= 2) && !(e3 && qk >= 1);
-        if (held) {
-            // the deposits of this lane (k) and of lane (k + r) & 3 into the held cell
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int32_t cr = r == 0 ? dcell : r == 1 ? c1 : r == 2 ? c2 : c3;
-                if (cr == h_cell) {
-                    const int src = wbase + (lane & ~3) + ((qk + r) & 3);
-#pragma unroll
-                    for (int l = 0; l < NL; ++l) h_du[l] += st.du[l][src];
-                }
-            }
-        }
+        const bool keep = held && (h_cell == dcell || h_cell == c1 || h_cell == c2 || h_cell == c3);
+        // the quad place of the lane holding this lane's cell (-1 none)
+        const int hr = !dep ? -1 : dcell == h_cell ? 0 : dcell == h1 ? 1 : dcell == h2 ? 2 : dcell == h3 ? 3 : -1;
+        const bool e1 = dep && c1 == dcell, e2 = dep && c2 == dcell, e3 = dep && c3 == dcell;
+        const bool owner = dep && !(e1 && qk >= 3) && !(e2 && qk >= 2) && !(e3 && qk >= 1);
+        const uint64_t km = stage_rows(held && !keep, keep);
         if (owner) {
-            // the lanes above this one depositing into its cell add to its row
+            // this lane's deposit, the deposits of the lanes above it into
+            // its cell, and the open row of that cell
+#pragma unroll
+            for (int l = 0; l < NL; ++l) h_du[l] = st.du[l][threadIdx.x];
 #pragma unroll
             for (int r = 1; r < 4; ++r) {
                 const bool er = r == 1 ? e1 : r == 2 ? e2 : e3;
                 if (er && qk + r < 4) {
                     const int src = wbase + (lane & ~3) + qk + r;
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) st.du[l][threadIdx.x] += st.du[l][src];
+                    for (int l = 0; l < NL; ++l) h_du[l] += st.du[l][src];
                 }
             }
-        }
-        emit_rows(held);
-        acc.nrows += owner ? 1u : 0u;
-        h_cell = owner ? dcell : -1;
+            if (hr >= 0) {
+                const int hl = (lane & ~3) + ((qk + hr) & 3);
+                const int src = wbase + 63 - __popcll(km & ((1ull << hl) - 1ull));
 #pragma unroll
-        for (int l = 0; l < NL; ++l) h_du[l] = owner ? st.du[l][threadIdx.x] : 0.f;
+                for (int l = 0; l < NL; ++l) h_du[l] += st.ed[l][src];
+            }
+        }
+        h_cell = owner ? dcell : -1;
+        if (!owner) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) h_du[l] = 0.f;
+        }
+        wave_sync_lds();
     }
-    emit_rows(h_cell >= 0);
+    stage_rows(h_cell >= 0, false);
+    wave_sync_lds();
     if (A.esc_dir) {
         // all rays of the item share direction r: one FP64 add per wavelength
         wave_sync_lds();
