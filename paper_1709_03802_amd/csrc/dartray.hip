@@ -640,9 +640,10 @@ struct FixedAcc {
 // LDS of the march (256-thread workgroups at most): each wave's deposit
 // staging, its wavelengths' opacities and its FP64 escaped-luminosity sums
 template <int NL>
-struct FixedStage {
+struct alignas(16) FixedStage {
     float du[NL][256];           // each lane's deposit row of the step
-    int32_t cell[256];
+    alignas(16) int32_t cell[256];    // each lane's deposit cell of the step (-1 none)
+    alignas(16) int32_t hcell[256];   // the cell of each lane's open row (-1 none)
     float ed[NL][256];           // rows going out, at compacted slots
     int32_t ecell[256];
     uint8_t list[256];
@@ -666,10 +667,12 @@ __device__ inline void wave_sync_lds()
 // 4 x 4 x 4 block of cells (Morton order); each quad of lanes takes four of
 // them on a line along the direction's dominant axis, so the quad's parallel
 // rays, less than a cell apart sideways near that axis, cross many cells a
-// step or two apart.  Rows of one cell in one step are summed by the lowest
-// lane, and a row stays open while the quad keeps depositing into its cell
-// (it moves to the lowest lane depositing there); it goes out at the first
-// step in which no lane of the quad deposits into that cell.
+// step or two apart.  Groups of eight lanes pair two such quads, side by side
+// along the axis of the next-largest direction component.  Rows of one cell
+// in one step are summed by the group's lowest lane depositing there, and a
+// row stays open while the group keeps depositing into its cell (it moves to
+// that lowest lane); it goes out at the first step in which no lane of the
+// group deposits into that cell.
 template <int NL>
 __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, FixedStage<NL> &st, FixedAcc<NL> &acc)
 {
@@ -681,18 +684,19 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     const int w = threadIdx.x >> 6;
     const int r = A.r0 + rl;
     const double4 nd = A.dirs[r];
-    // lane (q, k) of a quad -> source m of the tile: the Morton bits of the
-    // dominant axis (x, y, z are bits 0-2 and 3-5) take k, the others q
-    int ax = 0;
-    {
-        const double ax0 = fabs(nd.x), ax1 = fabs(nd.y), ax2 = fabs(nd.z);
-        ax = ax1 > ax0 ? (ax2 > ax1 ? 2 : 1) : (ax2 > ax0 ? 2 : 0);
-    }
-    const int qk = lane & 3, qq = lane >> 2;
-    int m = ((qk & 1) << ax) | ((qk >> 1) << (ax + 3));
+    // lane -> source m of the tile (x, y, z are Morton bits 0-2 and 3-5):
+    // lane bits 0-1 take the two bits of the dominant axis, lane bit 2 the
+    // low bit of the axis of the next-largest direction component, lane bits
+    // 3-5 the other three
+    const double a0 = fabs(nd.x), a1 = fabs(nd.y), a2 = fabs(nd.z);
+    const int ax = a1 > a0 ? (a2 > a1 ? 2 : 1) : (a2 > a0 ? 2 : 0);
+    const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+    const int mid = (o2 == 1 ? a1 : a2) > (o1 == 0 ? a0 : a1) ? o2 : o1;
+    const int go = lane & 7, gq = lane >> 3;
+    int m = ((go & 1) << ax) | (((go >> 1) & 1) << (ax + 3)) | (((go >> 2) & 1) << mid);
     for (int b = 0, j = 0; b < 6; ++b) {
-        if (b == ax || b == ax + 3) continue;
-        m |= ((qq >> j) & 1) << b;
+        if (b == ax || b == ax + 3 || b == mid) continue;
+        m |= ((gq >> j) & 1) << b;
         ++j;
     }
     const int64_t si = tile * 64 + m;
@@ -776,6 +780,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
     };
     while (__ballot(active)) {
         bool dep = false;
+        int32_t dcell = -1;
         if (active) {
             const LeafRec &rc = A.geo.rec[c];
             const int4 b = rc.box;
@@ -803,7 +808,7 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                         L[l] = thick ? L[l] * tr : fmaf(L[l], em1, L[l]);   // transmission, fused
                     }
                 }
-                st.cell[threadIdx.x] = c;
+                dcell = c;
                 dep = true;
                 ++acc.ncross;
                 ++steps;   // the per-ray limit counts crossings of positive length
@@ -830,19 +835,29 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                     }
             }
         }
-        // ---- rows: a held row stays open while the quad keeps depositing
+        // ---- rows: a held row stays open while its group keeps depositing
         // into its cell and moves to the lowest lane depositing there; the
         // lowest lane of each other cell opens a row; the rest go out
+        st.cell[threadIdx.x] = dcell;
+        st.hcell[threadIdx.x] = h_cell;
         wave_sync_lds();
-        const int32_t dcell = dep ? st.cell[threadIdx.x] : -1;
-        const int32_t c1 = quad_rot<1>(dcell), c2 = quad_rot<2>(dcell), c3 = quad_rot<3>(dcell);
-        const int32_t h1 = quad_rot<1>(h_cell), h2 = quad_rot<2>(h_cell), h3 = quad_rot<3>(h_cell);
+        const int gb = wbase + (lane & ~7);
+        const int4 ca = *reinterpret_cast<const int4 *>(&st.cell[gb]);
+        const int4 cb = *reinterpret_cast<const int4 *>(&st.cell[gb + 4]);
+        const int4 ha = *reinterpret_cast<const int4 *>(&st.hcell[gb]);
+        const int4 hb = *reinterpret_cast<const int4 *>(&st.hcell[gb + 4]);
+        const int32_t C[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+        const int32_t H[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
         const bool held = h_cell >= 0;
-        const bool keep = held && (h_cell == dcell || h_cell == c1 || h_cell == c2 || h_cell == c3);
-        // the quad place of the lane holding this lane's cell (-1 none)
-        const int hr = !dep ? -1 : dcell == h_cell ? 0 : dcell == h1 ? 1 : dcell == h2 ? 2 : dcell == h3 ? 3 : -1;
-        const bool e1 = dep && c1 == dcell, e2 = dep && c2 == dcell, e3 = dep && c3 == dcell;
-        const bool owner = dep && !(e1 && qk >= 3) && !(e2 && qk >= 2) && !(e3 && qk >= 1);
+        bool keep = false, below = false;
+        int hr = -1;   // the group place of the lane holding this lane's cell
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            keep = keep || (held && C[j] == h_cell);
+            below = below || (j < go && C[j] == dcell);
+            hr = dep && H[j] == dcell ? j : hr;
+        }
+        const bool owner = dep && !below;
         const uint64_t km = stage_rows(held && !keep, keep);
         if (owner) {
             // this lane's deposit, the deposits of the lanes above it into
@@ -850,16 +865,14 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
 #pragma unroll
             for (int l = 0; l < NL; ++l) h_du[l] = st.du[l][threadIdx.x];
 #pragma unroll
-            for (int r = 1; r < 4; ++r) {
-                const bool er = r == 1 ? e1 : r == 2 ? e2 : e3;
-                if (er && qk + r < 4) {
-                    const int src = wbase + (lane & ~3) + qk + r;
+            for (int j = 1; j < 8; ++j) {
+                if (j > go && C[j] == dcell) {
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) h_du[l] += st.du[l][src];
+                    for (int l = 0; l < NL; ++l) h_du[l] += st.du[l][gb + j];
                 }
             }
             if (hr >= 0) {
-                const int hl = (lane & ~3) + ((qk + hr) & 3);
+                const int hl = (lane & ~7) + hr;
                 const int src = wbase + 63 - __popcll(km & ((1ull << hl) - 1ull));
 #pragma unroll
                 for (int l = 0; l < NL; ++l) h_du[l] += st.ed[l][src];
