@@ -52,15 +52,15 @@ ATOMIC_PEAK_SINGLE = 2.11e10
 # kernel sources hashed here (null traffic once the sources change)
 PMC_TRAFFIC = {
     "disk": {
-        # k_step1_quad<8>, per launch: 4.4315e9 KiB fetched x2, 7.3879e9 KiB written x1
-        "bytes_per_launch": 9.0757e+12 + 7.5652e+12,
-        "sources_sha256": "fe0b3aaa52df9ec5e06f597f77ea3bc8b67ea49ed85460d6520ffb256469fb03",
+        # k_step1_quad<8>, per launch: 4.4312e9 KiB fetched x2, 7.3879e9 KiB written x1
+        "bytes_per_launch": 9.0752e+12 + 7.5652e+12,
+        "sources_sha256": "40028a05e3d8650f9c4c429febe0bd2142643f22cefe9501cf1d533531f78029",
         "profile": "profiles/k_step1_quad_disk.md",
     },
     "clumpy128": {
-        # k_march_fixed<16>, per launch (average of the run's 5): 2.3298e9 KiB fetched x2, 4.5496e9 KiB written x1
-        "bytes_per_launch": 4.7714e+12 + 4.6588e+12,
-        "sources_sha256": "fe0b3aaa52df9ec5e06f597f77ea3bc8b67ea49ed85460d6520ffb256469fb03",
+        # k_march_fixed<16>, per launch (average of the run's 5): 2.6233e9 KiB fetched x2, 2.9999e9 KiB written x1
+        "bytes_per_launch": 5.3725e+12 + 3.0719e+12,
+        "sources_sha256": "40028a05e3d8650f9c4c429febe0bd2142643f22cefe9501cf1d533531f78029",
         "profile": "profiles/k_march_fixed_clumpy128.md",
     },
 }
@@ -69,9 +69,9 @@ PMC_TRAFFIC = {
 # rocprofv3 TCC_ATOMIC (lanes whose cells share a 64-byte segment share one)
 PMC_ADJOINT = {
     "workload": "clumpy64",
-    "bytes_per_step": 2.0424e+12 + 2.8701e+11,
+    "bytes_per_step": 2.0404e+12 + 2.8701e+11,
     "atomic_requests_per_step": 7.4174e+09,
-    "sources_sha256": "fe0b3aaa52df9ec5e06f597f77ea3bc8b67ea49ed85460d6520ffb256469fb03",
+    "sources_sha256": "40028a05e3d8650f9c4c429febe0bd2142643f22cefe9501cf1d533531f78029",
     "profile": "profiles/k_march_adjoint_clumpy64_l4.md",
 }
 
