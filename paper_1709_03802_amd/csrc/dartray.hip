@@ -596,6 +596,7 @@ struct FixedArgs {
     double h_fine;
     int64_t max_steps;           // caller's per-ray limit (0 = none)
     int64_t hard_cap;            // bound no straight ray can exceed; ends any loop
+    int32_t linear;              // uniform grid, leaf i at root position i (x fastest)
 };
 
 // Launch luminosity of source s along ray r at wavelength l: the direct pass
@@ -673,7 +674,13 @@ __device__ inline void wave_sync_lds()
 // row stays open while the group keeps depositing into its cell (it moves to
 // that lowest lane); it goes out at the first step in which no lane of the
 // group deposits into that cell.
-template <int NL>
+//
+// LIN (a linearly numbered uniform grid): a cell's box and the cell across its
+// exit face follow from the cell's integer position, so the walk needs no
+// record load to find the next cell, and the next cell's density is loaded
+// one step ahead; the exit distances are those of the same exit_t, so the
+// cells and segments are those of the record walk.
+template <int NL, bool LIN>
 __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, FixedStage<NL> &st, FixedAcc<NL> &acc)
 {
     const LambdaTable *lt = A.lt;
@@ -746,6 +753,17 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
         c = s < A.n ? s : A.ps_cell[s - A.n];
         if (active) ++acc.nrays;
     }
+    // LIN: the cell's position, and its density and 1/(V c)
+    int32_t cx = 0, cy = 0, cz = 0;
+    float rho_c = 0.f, ivc_c = 0.f;
+    if (LIN && active) {
+        const LeafRec &r0c = A.geo.rec[c];
+        cx = r0c.box.x;
+        cy = r0c.box.y;
+        cz = r0c.box.z;
+        rho_c = r0c.rho;
+        ivc_c = r0c.ivc;
+    }
     double t = 0.0;
     int64_t steps = 0;
     float *ubase = A.ubar + (size_t)rl * (size_t)A.n * nl + l0;
@@ -782,13 +800,21 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
         bool dep = false;
         int32_t dcell = -1;
         if (active) {
-            const LeafRec &rc = A.geo.rec[c];
-            const int4 b = rc.box;
-            const float rho = rc.rho;
-            const float ivc = rc.ivc;
+            int4 b;
+            float rho, ivc;
             int32_t nbc[6];
+            if (LIN) {
+                b = make_int4(cx, cy, cz, 1);
+                rho = rho_c;
+                ivc = ivc_c;
+            } else {
+                const LeafRec &rc = A.geo.rec[c];
+                b = rc.box;
+                rho = rc.rho;
+                ivc = rc.ivc;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+                for (int q = 0; q < 6; ++q) nbc[q] = rc.nb[q];
+            }
             int axis;
             const double te = exit_t(R, b, axis);
             const double len = te - t;
@@ -814,7 +840,25 @@ __device__ void fixed_item(const FixedArgs &A, int64_t tile, int rl, int nsrc, F
                 ++steps;   // the per-ray limit counts crossings of positive length
                 t = te;
             }
-            const int32_t nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
+            int32_t nx;
+            if (LIN) {
+                // one cell along the exit axis, in the direction of travel
+                bool pos = false;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pos = a == axis ? R.n[a] > 0.0 : pos;
+                const int d = pos ? 1 : -1;
+                cx += axis == 0 ? d : 0;
+                cy += axis == 1 ? d : 0;
+                cz += axis == 2 ? d : 0;
+                const bool inside = (unsigned)cx < (unsigned)A.geo.nroot[0] &&
+                                    (unsigned)cy < (unsigned)A.geo.nroot[1] &&
+                                    (unsigned)cz < (unsigned)A.geo.nroot[2];
+                const int32_t stride = axis == 0 ? 1 : axis == 1 ? A.geo.nroot[0] : A.geo.nroot[0] * A.geo.nroot[1];
+                nx = inside ? c + d * stride : -1;
+                if (nx >= 0) rho_c = A.geo.rec[nx].rho;    // for the next step
+            } else {
+                nx = next_leaf<double>(A.geo, R, b, nbc, axis, te);
+            }
             bool escaped = false;
             if (nx < 0) {
                 active = false;
@@ -948,7 +992,7 @@ __device__ inline void fixed_item_index(const FixedArgs &A, int64_t it, int64_t 
 // its LDS staging allows 2 anyway.
 #define DR_FIXED_WAVES(NL) ((NL) <= 16 ? 4 : 1)
 
-template <int NL>
+template <int NL, bool LIN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DR_FIXED_WAVES(NL), 8)))
 void k_march_fixed(const FixedArgs A)
 {
@@ -968,7 +1012,7 @@ void k_march_fixed(const FixedArgs A)
         int64_t tile;
         int rl;
         fixed_item_index(A, it, ntiles, tile, rl);
-        fixed_item<NL>(A, tile, rl, nsrc, st, acc);
+        fixed_item<NL, LIN>(A, tile, rl, nsrc, st, acc);
     }
     fixed_commit<NL>(A, st, acc);
 }
@@ -1022,7 +1066,7 @@ void k_march_fixed_multi(const BatchMarch B)
         int64_t tile;
         int rl;
         fixed_item_index(A, it - B.item_off[m], ntiles, tile, rl);
-        fixed_item<NL>(A, tile, rl, nsrc, st, acc);
+        fixed_item<NL, false>(A, tile, rl, nsrc, st, acc);
     }
     if (mcur >= 0) fixed_commit<NL>(A, st, acc);
 }
@@ -3306,6 +3350,10 @@ int dartray_grid_create(const dartray_grid_desc *d, void *stream, dartray_grid *
     g.h_fine = d->root_size / (double)((int64_t)1 << lmax);
     g.c_light = d->c_light;
     g.uniform = (lmax == 0);
+    // leaf i at root position i, x fastest: the fixed march then finds a
+    // cell's neighbours by index arithmetic
+    g.linear = g.uniform && n == nroot;
+    for (int64_t i = 0; g.linear && i < nroot; ++i) g.linear = root_tab[(size_t)i] == (int32_t)(-i - 1);
     g.n_internal = (int64_t)(nodes.size() / 8);
     g.lt = lt;
     g.s_size = lt.s_off[nl];
@@ -3752,14 +3800,20 @@ static int nl_template(int k) { return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : k 
 
 static void launch_fixed(const FixedArgs &A, int nlt, hipStream_t s, unsigned blocks, unsigned threads)
 {
+#define DR_LAUNCH_FIXED(N)                                                                           \
+    do {                                                                                             \
+        if (A.linear) hipLaunchKernelGGL((k_march_fixed<N, true>), dim3(blocks), dim3(threads), 0, s, A);  \
+        else hipLaunchKernelGGL((k_march_fixed<N, false>), dim3(blocks), dim3(threads), 0, s, A);          \
+    } while (0)
     switch (nlt) {
-    case 1: hipLaunchKernelGGL((k_march_fixed<1>), dim3(blocks), dim3(threads), 0, s, A); break;
-    case 4: hipLaunchKernelGGL((k_march_fixed<4>), dim3(blocks), dim3(threads), 0, s, A); break;
-    case 8: hipLaunchKernelGGL((k_march_fixed<8>), dim3(blocks), dim3(threads), 0, s, A); break;
-    case 16: hipLaunchKernelGGL((k_march_fixed<16>), dim3(blocks), dim3(threads), 0, s, A); break;
-    case 32: hipLaunchKernelGGL((k_march_fixed<32>), dim3(blocks), dim3(threads), 0, s, A); break;
-    default: hipLaunchKernelGGL((k_march_fixed<64>), dim3(blocks), dim3(threads), 0, s, A); break;
+    case 1: DR_LAUNCH_FIXED(1); break;
+    case 4: DR_LAUNCH_FIXED(4); break;
+    case 8: DR_LAUNCH_FIXED(8); break;
+    case 16: DR_LAUNCH_FIXED(16); break;
+    case 32: DR_LAUNCH_FIXED(32); break;
+    default: DR_LAUNCH_FIXED(64); break;
     }
+#undef DR_LAUNCH_FIXED
 }
 
 // wavelengths per march launch under the grid's tuning
@@ -3786,6 +3840,7 @@ static FixedArgs fixed_args(Grid &g, const dartray_trace_opts *o, dartray_fields
     FixedArgs A{};
     A.geo = Geo{g.rec, g.root_tab, g.nodes, {g.fine[0], g.fine[1], g.fine[2]}, {g.nroot[0], g.nroot[1], g.nroot[2]},
                 g.max_level};
+    A.linear = g.linear ? 1 : 0;
     A.src_list = g.w.src_list;
     A.n_src = g.w.n_src;
     A.dirs = g.dir64 + entry_of(o->nside, 0);

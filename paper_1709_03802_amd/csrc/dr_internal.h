@@ -77,6 +77,7 @@ struct Grid {
     double h_fine = 0;                    // physical edge of a finest-level cell
     double c_light = 1;
     bool uniform = true;                  // no refinement anywhere
+    bool linear = false;                  // uniform, leaf i at root position i (x fastest)
     int64_t n_internal = 0;
     LambdaTable lt{};
     int64_t s_size = 0;
